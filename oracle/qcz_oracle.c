@@ -1,0 +1,781 @@
+/*
+ * qcz_oracle.c -- plain CPU oracle for the compressed state-vector simulator
+ * of Wu et al., "Full-State Quantum Circuit Simulation by Using Data
+ * Compression" (SC'19).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product (the HIP library under
+ * paper_1911_04034_amd/) includes, links or calls this file; only the tests,
+ * the smoke check and the CPU-baseline leg of the benchmark load it.  It shares
+ * no code with the GPU path: every routine here is written out a second time,
+ * slowly and directly, so that the two can be compared byte for byte.
+ *
+ * What it computes, in the paper's terms:
+ *   - gates on a 2^n complex128 state (Sec. 2.1, Eq. (5); Sec. 3.1, Eqs. (6)
+ *     and (7)); qubit k is bit k of the amplitude index;
+ *   - Solution C of Sec. 4.2: bit-plane truncation to Sig_Bit_Count bits
+ *     (Eq. (12)) and the XOR leading-byte reduction with a two-bit code per
+ *     value, followed by a lossless stage (the paper's Zstd role, here the
+ *     project's own chunk modes CONST2 / PACK / SPARSE);
+ *   - the blockwise loop of Sec. 3.1/3.3: decompress at most two units,
+ *     update the amplitude pairs, recompress, move on; control bits that fall
+ *     on unit-index bits skip whole units (Sec. 3.3);
+ *   - the variable error bound of Sec. 3.7 (start lossless, relax through
+ *     1e-5 .. 1e-1 whenever the compressed state does not fit the budget) and
+ *     the fidelity lower bound prod(1 - delta_i) of Sec. 3.8, Eq. (11).
+ *
+ * Readings where the paper is silent (all listed in the design notes):
+ *   - the unit of compression is a "chunk" of C interleaved doubles
+ *     (C = min(2048, 2b)); a "block" of b amplitudes groups chunks and carries
+ *     the error level;
+ *   - truncation is toward zero by masking (Sec. 3.7 range (|D(1-d)|, |D|]);
+ *     the relative bound applies to each real and imaginary double;
+ *   - XOR is taken against the previous *truncated* value; the two-bit code is
+ *     the number (0..3) of identical leading bytes, most significant first;
+ *   - a chunk holding a subnormal double is stored lossless;
+ *   - the lossless stage is the project-defined chunk format described at
+ *     oq_encode_chunk (Zstd is not reproducible bit-exactly on a GPU).
+ *
+ * Gate arithmetic uses an explicit, fixed fused-multiply-add order (see lin2
+ * and dmul) so that its results are reproducible to the bit; it must be
+ * compiled with -ffp-contract=off.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Error levels, Sec. 3.7: lossless, then 1e-5, 1e-4, 1e-3, 1e-2, 1e-1.       */
+/* ------------------------------------------------------------------------- */
+#define OQ_NLEVELS 6
+static const double oq_delta_tab[OQ_NLEVELS] = {0.0, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1};
+
+double oq_level_delta(int level)
+{
+    if (level < 0 || level >= OQ_NLEVELS) return -1.0;
+    return oq_delta_tab[level];
+}
+
+/* EXP(eps) of Eq. (12): the IEEE-754 exponent of eps, eps = 1.f * 2^EXP. */
+int oq_exp_of(double eps)
+{
+    int e;
+    frexp(eps, &e);          /* eps = m * 2^e with m in [0.5, 1) */
+    return e - 1;
+}
+
+/* Sig_Bit_Count of Eq. (12) for binary64: 12 sign+exponent bits - EXP(eps).
+ * Level 0 (lossless) keeps all 64 bits. */
+int oq_sig_bits(int level)
+{
+    if (level <= 0) return 64;
+    return 12 - oq_exp_of(oq_delta_tab[level]);
+}
+
+static uint64_t dbits(double x) { uint64_t b; memcpy(&b, &x, 8); return b; }
+static double bitsd(uint64_t b) { double x; memcpy(&x, &b, 8); return x; }
+
+/* Bit-plane truncation: keep the K most significant bits, zero the rest. */
+uint64_t oq_truncate_bits(uint64_t b, int K)
+{
+    if (K >= 64) return b;
+    return b & ~((UINT64_C(1) << (64 - K)) - 1);
+}
+
+double oq_truncate(double x, int level)
+{
+    return bitsd(oq_truncate_bits(dbits(x), oq_sig_bits(level)));
+}
+
+static int is_subnormal(uint64_t b)
+{
+    return ((b >> 52) & 0x7FF) == 0 && (b & ((UINT64_C(1) << 52) - 1)) != 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Bit streams: bit p of a stream lives in byte p/8 at bit p%8 (LSB first);  */
+/* a field of r bits is stored least significant bit first.                   */
+/* ------------------------------------------------------------------------- */
+static void put_bits(uint8_t *buf, uint64_t *pos, uint64_t v, int nbits)
+{
+    for (int k = 0; k < nbits; ++k) {
+        uint64_t p = *pos + (uint64_t)k;
+        if ((v >> k) & 1u) buf[p >> 3] |= (uint8_t)(1u << (p & 7));
+    }
+    *pos += (uint64_t)nbits;
+}
+
+static uint64_t get_bits(const uint8_t *buf, uint64_t pos, int nbits)
+{
+    uint64_t v = 0;
+    for (int k = 0; k < nbits; ++k) {
+        uint64_t p = pos + (uint64_t)k;
+        if ((buf[p >> 3] >> (p & 7)) & 1u) v |= UINT64_C(1) << k;
+    }
+    return v;
+}
+
+static void put_u32(uint8_t *p, uint32_t v) { for (int k = 0; k < 4; ++k) p[k] = (uint8_t)(v >> (8 * k)); }
+static void put_u64(uint8_t *p, uint64_t v) { for (int k = 0; k < 8; ++k) p[k] = (uint8_t)(v >> (8 * k)); }
+static uint32_t get_u32(const uint8_t *p) { uint32_t v = 0; for (int k = 0; k < 4; ++k) v |= (uint32_t)p[k] << (8 * k); return v; }
+static uint64_t get_u64(const uint8_t *p) { uint64_t v = 0; for (int k = 0; k < 8; ++k) v |= (uint64_t)p[k] << (8 * k); return v; }
+
+/* ------------------------------------------------------------------------- */
+/* Solution C, step "XOR leading-zero data reduction" (Sec. 4.2).            */
+/* ------------------------------------------------------------------------- */
+
+/* Number of identical leading bytes (most significant first) of two values,
+ * capped at 3 so that it fits the two-bit code. */
+static int lead_bytes(uint64_t cur, uint64_t prev)
+{
+    uint64_t d = cur ^ prev;
+    int L = 0;
+    while (L < 3 && ((d >> (56 - 8 * L)) & 0xFFu) == 0) ++L;
+    return L;
+}
+
+/* Residual bits of a value whose first L bytes repeat the previous value:
+ * the significant bits that remain after those bytes. */
+static int resid_bits(int K, int L)
+{
+    int r = K - 8 * L;
+    return r > 0 ? r : 0;
+}
+
+static uint64_t top_mask(int nbits)
+{
+    if (nbits <= 0) return 0;
+    if (nbits >= 64) return ~UINT64_C(0);
+    return ~UINT64_C(0) << (64 - nbits);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Chunk format.                                                              */
+/*                                                                            */
+/* A chunk holds C doubles v_0..v_{C-1} = re a_0, im a_0, re a_1, ... of C/2   */
+/* consecutive amplitudes.  Bytes, little-endian:                             */
+/*   u32 header: bits 0-1 mode, bits 2-4 level index (0 lossless, 1..5),     */
+/*               bits 5-31 zero.                                              */
+/*   mode CONST2 (1): t_0 (u64), t_1 (u64).  Used when every even value      */
+/*               equals t_0 and every odd value equals t_1.                   */
+/*   mode PACK (0): codes area of 4*ceil(C/16) bytes (value i's two-bit code  */
+/*               L_i at bit 2i), then the residual stream: for each value in */
+/*               order, r_i = max(0, K - 8 L_i) bits holding the low r_i bits */
+/*               of its K-bit significant prefix; zero-padded to a byte.      */
+/*   mode SPARSE (2): bitmap of 4*ceil(C/32) bytes (bit i set when t_i has   */
+/*               any bit set), then a PACK body (codes area of               */
+/*               4*ceil(nnz/16) bytes and residual stream) over the          */
+/*               subsequence of nonzero values, XOR-chained among themselves. */
+/* The chain starts from t_{-1} = 0.  The encoder picks CONST2 when it        */
+/* applies, otherwise the smaller of PACK and SPARSE (PACK on a tie).         */
+/* ------------------------------------------------------------------------- */
+#define OQ_MODE_PACK 0
+#define OQ_MODE_CONST2 1
+#define OQ_MODE_SPARSE 2
+
+size_t oq_chunk_cap(int C)
+{
+    return 4 + 4 * (size_t)((C + 15) / 16) + 8 * (size_t)C;
+}
+
+/* Size in bytes of a PACK body (codes + residual) over the sequence s[0..N). */
+static size_t pack_body_size(const uint64_t *s, int N, int K)
+{
+    uint64_t bits = 0, prev = 0;
+    for (int i = 0; i < N; ++i) {
+        bits += (uint64_t)resid_bits(K, lead_bytes(s[i], prev));
+        prev = s[i];
+    }
+    return 4 * (size_t)((N + 15) / 16) + (size_t)((bits + 7) / 8);
+}
+
+/* Write a PACK body over s[0..N) at out; returns its size. */
+static size_t pack_body_write(const uint64_t *s, int N, int K, uint8_t *out)
+{
+    size_t codes_bytes = 4 * (size_t)((N + 15) / 16);
+    uint8_t *res = out + codes_bytes;
+    uint64_t cpos = 0, rpos = 0, prev = 0;
+    for (int i = 0; i < N; ++i) {
+        int L = lead_bytes(s[i], prev);
+        int r = resid_bits(K, L);
+        put_bits(out, &cpos, (uint64_t)L, 2);
+        if (r > 0) {
+            uint64_t sig = (K >= 64) ? s[i] : (s[i] >> (64 - K));
+            uint64_t R = (r >= 64) ? sig : (sig & ((UINT64_C(1) << r) - 1));
+            put_bits(res, &rpos, R, r);
+        }
+        prev = s[i];
+    }
+    return codes_bytes + (size_t)((rpos + 7) / 8);
+}
+
+/* Read a PACK body of N values; returns bytes consumed or 0 on error. */
+static size_t pack_body_read(const uint8_t *in, size_t avail, int N, int K, uint64_t *s)
+{
+    size_t codes_bytes = 4 * (size_t)((N + 15) / 16);
+    if (codes_bytes > avail) return 0;
+    const uint8_t *res = in + codes_bytes;
+    size_t res_avail = avail - codes_bytes;
+    uint64_t rpos = 0, prev = 0;
+    for (int i = 0; i < N; ++i) {
+        int L = (int)get_bits(in, 2 * (uint64_t)i, 2);
+        int r = resid_bits(K, L);
+        if ((rpos + (uint64_t)r + 7) / 8 > res_avail) return 0;
+        uint64_t R = get_bits(res, rpos, r);
+        rpos += (uint64_t)r;
+        uint64_t low = (K >= 64) ? R : (R << (64 - K));
+        s[i] = (prev & top_mask(8 * L)) | low;
+        prev = s[i];
+    }
+    return codes_bytes + (size_t)((rpos + 7) / 8);
+}
+
+/* Encode one chunk of C doubles at error level `level`; returns its size.
+ * `out` must hold oq_chunk_cap(C) bytes. */
+size_t oq_encode_chunk(const double *x, int C, int level, uint8_t *out)
+{
+    if (C < 4 || (C & (C - 1)) != 0 || level < 0 || level >= OQ_NLEVELS) return 0;
+    int lev = level;
+    for (int i = 0; i < C; ++i)
+        if (is_subnormal(dbits(x[i]))) lev = 0;
+    int K = oq_sig_bits(lev);
+
+    uint64_t *t = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)C);
+    uint64_t *nz = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)C);
+    for (int i = 0; i < C; ++i) t[i] = oq_truncate_bits(dbits(x[i]), K);
+
+    memset(out, 0, oq_chunk_cap(C));
+    size_t size;
+    int const2 = 1;
+    for (int i = 0; i < C; ++i)
+        if (t[i] != t[i & 1]) const2 = 0;
+    if (const2) {
+        put_u32(out, (uint32_t)(OQ_MODE_CONST2 | (lev << 2)));
+        put_u64(out + 4, t[0]);
+        put_u64(out + 12, t[1]);
+        size = 20;
+    } else {
+        int nnz = 0;
+        for (int i = 0; i < C; ++i)
+            if (t[i] != 0) nz[nnz++] = t[i];
+        size_t bitmap_bytes = 4 * (size_t)((C + 31) / 32);
+        size_t pack_size = 4 + pack_body_size(t, C, K);
+        size_t sparse_size = 4 + bitmap_bytes + pack_body_size(nz, nnz, K);
+        if (sparse_size < pack_size) {
+            put_u32(out, (uint32_t)(OQ_MODE_SPARSE | (lev << 2)));
+            uint64_t bpos = 0;
+            for (int i = 0; i < C; ++i) put_bits(out + 4, &bpos, t[i] != 0, 1);
+            size = 4 + bitmap_bytes + pack_body_write(nz, nnz, K, out + 4 + bitmap_bytes);
+        } else {
+            put_u32(out, (uint32_t)(OQ_MODE_PACK | (lev << 2)));
+            size = 4 + pack_body_write(t, C, K, out + 4);
+        }
+    }
+    free(t);
+    free(nz);
+    return size;
+}
+
+/* Decode one chunk; returns 0 on success, -1 on a malformed stream. */
+int oq_decode_chunk(const uint8_t *in, size_t len, int C, double *x)
+{
+    if (C < 4 || (C & (C - 1)) != 0 || len < 4) return -1;
+    uint32_t hdr = get_u32(in);
+    int mode = (int)(hdr & 3u), lev = (int)((hdr >> 2) & 7u);
+    if ((hdr >> 5) != 0 || lev >= OQ_NLEVELS) return -1;
+    int K = oq_sig_bits(lev);
+    if (mode == OQ_MODE_CONST2) {
+        if (len != 20) return -1;
+        uint64_t t0 = get_u64(in + 4), t1 = get_u64(in + 12);
+        for (int i = 0; i < C; ++i) x[i] = bitsd((i & 1) ? t1 : t0);
+        return 0;
+    }
+    uint64_t *s = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)C);
+    int rc = 0;
+    if (mode == OQ_MODE_PACK) {
+        size_t used = pack_body_read(in + 4, len - 4, C, K, s);
+        if (used == 0 || used != len - 4) rc = -1;
+        else for (int i = 0; i < C; ++i) x[i] = bitsd(s[i]);
+    } else if (mode == OQ_MODE_SPARSE) {
+        size_t bitmap_bytes = 4 * (size_t)((C + 31) / 32);
+        if (len < 4 + bitmap_bytes) { free(s); return -1; }
+        int nnz = 0;
+        for (int i = 0; i < C; ++i) nnz += (int)get_bits(in + 4, (uint64_t)i, 1);
+        size_t used = pack_body_read(in + 4 + bitmap_bytes, len - 4 - bitmap_bytes, nnz, K, s);
+        if (used == 0 || used != len - 4 - bitmap_bytes) rc = -1;
+        else {
+            int k = 0;
+            for (int i = 0; i < C; ++i)
+                x[i] = get_bits(in + 4, (uint64_t)i, 1) ? bitsd(s[k++]) : 0.0;
+        }
+    } else {
+        rc = -1;
+    }
+    free(s);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Gates (Sec. 2.1 Eq. (5); Sec. 3.1 Eqs. (6), (7)).                          */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t kind;          /* OQ_U1 .. OQ_MCZ */
+    uint32_t target;        /* q (for DIAG2: first qubit) */
+    uint32_t target2;       /* DIAG2: second qubit */
+    uint32_t reserved;
+    uint64_t control_mask;  /* qubits that must all be 1 */
+    double m[8];            /* U1: u00,u01,u10,u11 as (re,im); DIAG1: d0,d1; DIAG2: p0..p3 */
+} oq_gate;
+
+enum { OQ_U1 = 0, OQ_DIAG1 = 1, OQ_DIAG2 = 2, OQ_X = 3, OQ_MCZ = 4 };
+
+size_t oq_gate_size(void) { return sizeof(oq_gate); }
+
+/* y = u*a + v*b in a fixed fused-multiply-add order. */
+static void lin2(double ur, double ui, double vr, double vi,
+                 double ar, double ai, double br, double bi,
+                 double *yr, double *yi)
+{
+    *yr = fma(vr, br, fma(-vi, bi, fma(ur, ar, -(ui * ai))));
+    *yi = fma(vr, bi, fma(vi, br, fma(ur, ai, ui * ar)));
+}
+
+/* y = d*a. */
+static void dmul(double dr, double di, double ar, double ai, double *yr, double *yi)
+{
+    *yr = fma(dr, ar, -(di * ai));
+    *yi = fma(dr, ai, di * ar);
+}
+
+/* 0 when the gate record is well formed for an n-qubit state. */
+int oq_gate_check(const oq_gate *g, int n)
+{
+    uint64_t all = (n >= 64) ? ~UINT64_C(0) : ((UINT64_C(1) << n) - 1);
+    if (g->control_mask & ~all) return -1;
+    for (int k = 0; k < 8; ++k)
+        if (!isfinite(g->m[k])) return -1;
+    switch (g->kind) {
+    case OQ_U1:
+    case OQ_DIAG1:
+    case OQ_X:
+        if ((int)g->target >= n) return -1;
+        if (g->control_mask & (UINT64_C(1) << g->target)) return -1;
+        return 0;
+    case OQ_DIAG2:
+        if ((int)g->target >= n || (int)g->target2 >= n || g->target == g->target2) return -1;
+        if (g->control_mask & ((UINT64_C(1) << g->target) | (UINT64_C(1) << g->target2))) return -1;
+        return 0;
+    case OQ_MCZ:
+        return g->control_mask ? 0 : -1;
+    default:
+        return -1;
+    }
+}
+
+/* Phase a diagonal gate gives the amplitude with global index i. */
+static void diag_phase(const oq_gate *g, uint64_t i, double *pr, double *pi)
+{
+    int idx;
+    if (g->kind == OQ_DIAG1) idx = (int)((i >> g->target) & 1u);
+    else idx = (int)(((i >> g->target2) & 1u) * 2 + ((i >> g->target) & 1u));
+    *pr = g->m[2 * idx];
+    *pi = g->m[2 * idx + 1];
+}
+
+/* Apply a gate to a set of amplitudes psi[2*l], psi[2*l+1], l < nloc, whose
+ * global indices are glob(l).  Pairs (Eq. (6)) are formed by flipping the
+ * target bit; `partner(l)` gives the local index of that amplitude. */
+typedef struct {
+    uint64_t base0, base1;  /* global index of local 0 and of local half */
+    uint64_t half;          /* nloc/2 when two units are held, else nloc */
+    int pair_units;         /* 1: target flips between the two units */
+} oq_layout;
+
+static uint64_t glob_index(const oq_layout *lay, uint64_t l)
+{
+    if (lay->pair_units) return (l < lay->half) ? lay->base0 + l : lay->base1 + (l - lay->half);
+    return lay->base0 + l;
+}
+
+static void apply_local(const oq_gate *g, double *psi, uint64_t nloc, const oq_layout *lay)
+{
+    uint64_t cm = g->control_mask;
+    for (uint64_t l = 0; l < nloc; ++l) {
+        uint64_t i = glob_index(lay, l);
+        if ((i & cm) != cm) continue;
+        if (g->kind == OQ_U1 || g->kind == OQ_X) {
+            if ((i >> g->target) & 1u) continue;                 /* visit each pair from its 0 side */
+            uint64_t lj = lay->pair_units ? l + lay->half : l + (UINT64_C(1) << g->target);
+            double ar = psi[2 * l], ai = psi[2 * l + 1], br = psi[2 * lj], bi = psi[2 * lj + 1];
+            if (g->kind == OQ_X) {
+                psi[2 * l] = br; psi[2 * l + 1] = bi; psi[2 * lj] = ar; psi[2 * lj + 1] = ai;
+            } else {
+                const double *u = g->m;
+                double yr, yi, zr, zi;
+                lin2(u[0], u[1], u[2], u[3], ar, ai, br, bi, &yr, &yi);
+                lin2(u[4], u[5], u[6], u[7], ar, ai, br, bi, &zr, &zi);
+                psi[2 * l] = yr; psi[2 * l + 1] = yi; psi[2 * lj] = zr; psi[2 * lj + 1] = zi;
+            }
+        } else if (g->kind == OQ_DIAG1 || g->kind == OQ_DIAG2) {
+            double pr, pi, yr, yi;
+            diag_phase(g, i, &pr, &pi);
+            dmul(pr, pi, psi[2 * l], psi[2 * l + 1], &yr, &yi);
+            psi[2 * l] = yr; psi[2 * l + 1] = yi;
+        } else if (g->kind == OQ_MCZ) {
+            psi[2 * l] = -psi[2 * l];
+            psi[2 * l + 1] = -psi[2 * l + 1];
+        }
+    }
+}
+
+/* Uncompressed reference: apply one gate to the full state psi (2*2^n doubles). */
+int oq_apply_gate_dense(double *psi, int n, const oq_gate *g)
+{
+    if (oq_gate_check(g, n) != 0) return -1;
+    oq_layout lay = {0, 0, UINT64_C(1) << n, 0};
+    apply_local(g, psi, UINT64_C(1) << n, &lay);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Which chunks a gate touches (Sec. 3.3 index segments and control rules).  */
+/* ------------------------------------------------------------------------- */
+enum { OQ_JOB_NONE = 0, OQ_JOB_SINGLE = 1, OQ_JOB_PAIR_LO = 2, OQ_JOB_PAIR_HI = 3, OQ_JOB_PERMUTE_LO = 4, OQ_JOB_PERMUTE_HI = 5 };
+
+static int is_unit(double re, double im) { return re == 1.0 && im == 0.0; }
+
+/* Role of chunk c (global amplitudes c*2^cb ...) under gate g. */
+int oq_chunk_role(const oq_gate *g, int cb, uint64_t c)
+{
+    uint64_t cm = g->control_mask;
+    uint64_t cm_hi = cm >> cb;                       /* controls on chunk-index bits */
+    uint64_t cm_lo = cm & ((UINT64_C(1) << cb) - 1); /* controls inside the chunk */
+    if ((c & cm_hi) != cm_hi) return OQ_JOB_NONE;    /* a control bit is 0: chunk left unmodified */
+    switch (g->kind) {
+    case OQ_U1:
+    case OQ_X:
+        if ((int)g->target >= cb) {
+            int hi = (int)((c >> (g->target - cb)) & 1u);
+            if (g->kind == OQ_X && cm_lo == 0) return hi ? OQ_JOB_PERMUTE_HI : OQ_JOB_PERMUTE_LO;
+            return hi ? OQ_JOB_PAIR_HI : OQ_JOB_PAIR_LO;
+        }
+        return OQ_JOB_SINGLE;
+    case OQ_MCZ:
+        return OQ_JOB_SINGLE;
+    case OQ_DIAG1:
+    case OQ_DIAG2: {
+        /* touched unless every phase that can occur inside this chunk is 1 */
+        int all_unit = 1;
+        for (int idx = 0; idx < 4; ++idx) {
+            if (g->kind == OQ_DIAG1 && idx >= 2) break;
+            int b1 = idx & 1, b2 = idx >> 1;
+            if ((int)g->target >= cb && (int)((c >> (g->target - cb)) & 1u) != b1) continue;
+            if (g->kind == OQ_DIAG2 && (int)g->target2 >= cb && (int)((c >> (g->target2 - cb)) & 1u) != b2) continue;
+            if (!is_unit(g->m[2 * idx], g->m[2 * idx + 1])) all_unit = 0;
+        }
+        return all_unit ? OQ_JOB_NONE : OQ_JOB_SINGLE;
+    }
+    default:
+        return OQ_JOB_NONE;
+    }
+}
+
+/* One unit of the blockwise loop: decompress chunk c0 (and c1 for a pair
+ * job), update its amplitudes, recompress each at its own level.  For a
+ * single-chunk job pass in1 = NULL.  Returns 0 or -1. */
+int oq_gate_job(const oq_gate *g, int cb, int C,
+                uint64_t c0, const uint8_t *in0, size_t len0, int level0, uint8_t *out0, size_t *olen0,
+                uint64_t c1, const uint8_t *in1, size_t len1, int level1, uint8_t *out1, size_t *olen1)
+{
+    uint64_t ca = (uint64_t)C / 2;
+    int two = in1 != NULL;
+    double *psi = (double *)malloc(sizeof(double) * (size_t)C * (two ? 2 : 1));
+    int rc = oq_decode_chunk(in0, len0, C, psi);
+    if (rc == 0 && two) rc = oq_decode_chunk(in1, len1, C, psi + C);
+    if (rc == 0) {
+        oq_layout lay;
+        lay.base0 = c0 << cb;
+        lay.base1 = two ? (c1 << cb) : 0;
+        lay.half = ca;
+        lay.pair_units = two;
+        apply_local(g, psi, two ? 2 * ca : ca, &lay);
+        *olen0 = oq_encode_chunk(psi, C, level0, out0);
+        if (two) *olen1 = oq_encode_chunk(psi + C, C, level1, out1);
+    }
+    free(psi);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Compressed simulator (Sec. 3.1, 3.3, 3.7, 3.8).                           */
+/* ------------------------------------------------------------------------- */
+enum { OQ_MODE_LOSSLESS = 0, OQ_MODE_FIXED = 1, OQ_MODE_ADAPTIVE = 2, OQ_MODE_PERBLOCK = 3 };
+
+typedef struct {
+    int n, cb, bl, C;
+    uint64_t nchunks, nblocks;
+    uint8_t **chunk;
+    uint32_t *len;
+    int mode, level;
+    uint64_t budget;
+    uint8_t *block_level;     /* used in per-block mode */
+    double flb;               /* fidelity lower bound, Eq. (11) */
+    double flb_weighted;      /* per-block mode: prod(1 - sum_b w_b d_b) */
+    uint64_t gates_applied, lossy_steps;
+    uint64_t min_compressed, max_compressed;
+    uint8_t *scratch_out[2];
+} oq_sim;
+
+static size_t pad4(size_t x) { return (x + 3) & ~(size_t)3; }
+
+uint64_t oq_sim_compressed_bytes(const oq_sim *s)
+{
+    uint64_t tot = 0;
+    for (uint64_t c = 0; c < s->nchunks; ++c) tot += pad4(s->len[c]);
+    return tot;
+}
+
+/* State |0...0> stored in compressed form (Sec. 3.3: the state vectors are
+ * created in blocks and compressed). */
+oq_sim *oq_sim_create(int n, int block_log2, int mode, int fixed_level, uint64_t budget)
+{
+    if (n < 2 || n > 40 || block_log2 < 1 || block_log2 > n) return NULL;
+    if (fixed_level < 0 || fixed_level >= OQ_NLEVELS) return NULL;
+    oq_sim *s = (oq_sim *)calloc(1, sizeof(oq_sim));
+    s->n = n;
+    s->bl = block_log2;
+    s->cb = block_log2 < 10 ? block_log2 : 10;
+    s->C = 2 << s->cb;
+    s->nchunks = UINT64_C(1) << (n - s->cb);
+    s->nblocks = UINT64_C(1) << (n - s->bl);
+    s->chunk = (uint8_t **)calloc(s->nchunks, sizeof(uint8_t *));
+    s->len = (uint32_t *)calloc(s->nchunks, sizeof(uint32_t));
+    s->mode = mode;
+    s->level = (mode == OQ_MODE_FIXED) ? fixed_level : 0;
+    s->budget = budget;
+    s->block_level = (uint8_t *)calloc(s->nblocks, 1);
+    if (mode == OQ_MODE_PERBLOCK) memset(s->block_level, fixed_level, s->nblocks);
+    s->flb = 1.0;
+    s->flb_weighted = 1.0;
+    size_t cap = oq_chunk_cap(s->C);
+    s->scratch_out[0] = (uint8_t *)malloc(cap);
+    s->scratch_out[1] = (uint8_t *)malloc(cap);
+    double *zero = (double *)calloc((size_t)s->C, sizeof(double));
+    for (uint64_t c = 0; c < s->nchunks; ++c) {
+        if (c == 0) zero[0] = 1.0;
+        size_t L = oq_encode_chunk(zero, s->C, 0, s->scratch_out[0]);
+        s->chunk[c] = (uint8_t *)malloc(L);
+        memcpy(s->chunk[c], s->scratch_out[0], L);
+        s->len[c] = (uint32_t)L;
+        zero[0] = 0.0;
+    }
+    free(zero);
+    s->min_compressed = s->max_compressed = oq_sim_compressed_bytes(s);
+    return s;
+}
+
+void oq_sim_destroy(oq_sim *s)
+{
+    if (!s) return;
+    for (uint64_t c = 0; c < s->nchunks; ++c) free(s->chunk[c]);
+    free(s->chunk); free(s->len); free(s->block_level);
+    free(s->scratch_out[0]); free(s->scratch_out[1]);
+    free(s);
+}
+
+static int chunk_level(const oq_sim *s, uint64_t c)
+{
+    if (s->mode == OQ_MODE_PERBLOCK) return s->block_level[c >> (s->bl - s->cb)];
+    return s->level;
+}
+
+/* Replacement record kept until the gate commits (so it can be undone). */
+typedef struct { uint64_t c; uint8_t *old; uint32_t old_len; } oq_undo;
+
+/* Apply gate g to the compressed state.  Old chunk versions are returned in
+ * undo[] (count in *nundo) so the caller can commit or roll back.  Sets
+ * *reencoded to the number of chunks recompressed. */
+static int sim_gate(oq_sim *s, const oq_gate *g, oq_undo *undo, uint64_t *nundo, uint64_t *reencoded)
+{
+    *nundo = 0;
+    *reencoded = 0;
+    for (uint64_t c = 0; c < s->nchunks; ++c) {
+        int role = oq_chunk_role(g, s->cb, c);
+        if (role == OQ_JOB_NONE || role == OQ_JOB_PAIR_HI || role == OQ_JOB_PERMUTE_HI) continue;
+        if (role == OQ_JOB_PERMUTE_LO) {
+            /* X on chunk-index bits with no in-chunk control: exchange the
+             * two compressed chunks without recompressing (exact). */
+            uint64_t c1 = c | (UINT64_C(1) << (g->target - s->cb));
+            uint8_t *tp = s->chunk[c]; s->chunk[c] = s->chunk[c1]; s->chunk[c1] = tp;
+            uint32_t tl = s->len[c]; s->len[c] = s->len[c1]; s->len[c1] = tl;
+            undo[(*nundo)++] = (oq_undo){c, NULL, 0};   /* NULL marks a swap record */
+            continue;
+        }
+        size_t o0 = 0, o1 = 0;
+        if (role == OQ_JOB_SINGLE) {
+            if (oq_gate_job(g, s->cb, s->C, c, s->chunk[c], s->len[c], chunk_level(s, c), s->scratch_out[0], &o0,
+                            0, NULL, 0, 0, NULL, NULL) != 0) return -1;
+            undo[(*nundo)++] = (oq_undo){c, s->chunk[c], s->len[c]};
+            s->chunk[c] = (uint8_t *)malloc(o0);
+            memcpy(s->chunk[c], s->scratch_out[0], o0);
+            s->len[c] = (uint32_t)o0;
+            *reencoded += 1;
+        } else { /* OQ_JOB_PAIR_LO */
+            uint64_t c1 = c | (UINT64_C(1) << (g->target - s->cb));
+            if (oq_gate_job(g, s->cb, s->C, c, s->chunk[c], s->len[c], chunk_level(s, c), s->scratch_out[0], &o0,
+                            c1, s->chunk[c1], s->len[c1], chunk_level(s, c1), s->scratch_out[1], &o1) != 0) return -1;
+            undo[(*nundo)++] = (oq_undo){c, s->chunk[c], s->len[c]};
+            undo[(*nundo)++] = (oq_undo){c1, s->chunk[c1], s->len[c1]};
+            s->chunk[c] = (uint8_t *)malloc(o0);
+            memcpy(s->chunk[c], s->scratch_out[0], o0);
+            s->len[c] = (uint32_t)o0;
+            s->chunk[c1] = (uint8_t *)malloc(o1);
+            memcpy(s->chunk[c1], s->scratch_out[1], o1);
+            s->len[c1] = (uint32_t)o1;
+            *reencoded += 2;
+        }
+    }
+    return 0;
+}
+
+static void sim_commit(oq_undo *undo, uint64_t nundo)
+{
+    for (uint64_t k = 0; k < nundo; ++k) free(undo[k].old);
+}
+
+static void sim_rollback(oq_sim *s, const oq_gate *g, oq_undo *undo, uint64_t nundo)
+{
+    for (uint64_t k = nundo; k-- > 0;) {
+        uint64_t c = undo[k].c;
+        if (undo[k].old == NULL) {
+            uint64_t c1 = c | (UINT64_C(1) << (g->target - s->cb));
+            uint8_t *tp = s->chunk[c]; s->chunk[c] = s->chunk[c1]; s->chunk[c1] = tp;
+            uint32_t tl = s->len[c]; s->len[c] = s->len[c1]; s->len[c1] = tl;
+        } else {
+            free(s->chunk[c]);
+            s->chunk[c] = undo[k].old;
+            s->len[c] = undo[k].old_len;
+        }
+    }
+}
+
+/* Sum over blocks of w_b * delta_b with w_b = sum of |a|^2 in block b, for
+ * the per-block ledger (the paper's Eq. (10) argument with a pointwise
+ * bound that varies by block). */
+static double weighted_delta(const oq_sim *s)
+{
+    double *psi = (double *)malloc(sizeof(double) * (size_t)s->C);
+    double acc = 0.0;
+    uint64_t cpb = UINT64_C(1) << (s->bl - s->cb);
+    for (uint64_t b = 0; b < s->nblocks; ++b) {
+        double w = 0.0;
+        for (uint64_t k = 0; k < cpb; ++k) {
+            uint64_t c = b * cpb + k;
+            oq_decode_chunk(s->chunk[c], s->len[c], s->C, psi);
+            for (int i = 0; i < s->C; ++i) w += psi[i] * psi[i];
+        }
+        acc += w * oq_delta_tab[s->block_level[b]];
+    }
+    free(psi);
+    return acc;
+}
+
+/* Apply a gate list.  Returns the number of gates applied (all of them on
+ * success); a negative value -(k+1) reports that gate k could not be fitted
+ * into the budget even at the loosest level (-2 - k: malformed gate k). */
+long oq_sim_apply(oq_sim *s, const oq_gate *gates, size_t ngates)
+{
+    uint64_t max_undo = s->nchunks;
+    oq_undo *undo = (oq_undo *)malloc(sizeof(oq_undo) * (size_t)max_undo);
+    for (size_t k = 0; k < ngates; ++k) {
+        const oq_gate *g = &gates[k];
+        if (oq_gate_check(g, s->n) != 0) { free(undo); return -2 - (long)k; }
+        uint64_t nundo = 0, reenc = 0;
+        for (;;) {
+            if (sim_gate(s, g, undo, &nundo, &reenc) != 0) { free(undo); return -2 - (long)k; }
+            uint64_t cbytes = oq_sim_compressed_bytes(s);
+            if (s->mode != OQ_MODE_ADAPTIVE || s->budget == 0 || cbytes <= s->budget) {
+                sim_commit(undo, nundo);
+                break;
+            }
+            /* Sec. 3.7: the compressed state does not fit -> relax the bound
+             * to the next level and redo the gate from its input. */
+            sim_rollback(s, g, undo, nundo);
+            if (s->level >= OQ_NLEVELS - 1) { free(undo); return -1 - (long)k; }
+            s->level += 1;
+        }
+        if (reenc > 0) {
+            if (s->mode == OQ_MODE_PERBLOCK) {
+                double wd = weighted_delta(s);
+                if (wd > 0.0) { s->flb_weighted *= (1.0 - wd); s->lossy_steps += 1; }
+            } else if (s->level > 0) {
+                s->flb *= (1.0 - oq_delta_tab[s->level]);   /* Eq. (11) */
+                s->lossy_steps += 1;
+            }
+        }
+        s->gates_applied += 1;
+        uint64_t cb = oq_sim_compressed_bytes(s);
+        if (cb < s->min_compressed) s->min_compressed = cb;
+        if (cb > s->max_compressed) s->max_compressed = cb;
+    }
+    free(undo);
+    return (long)ngates;
+}
+
+/* Decode the whole state into psi (2*2^n doubles). */
+int oq_sim_read_all(const oq_sim *s, double *psi)
+{
+    for (uint64_t c = 0; c < s->nchunks; ++c)
+        if (oq_decode_chunk(s->chunk[c], s->len[c], s->C, psi + c * (uint64_t)s->C) != 0) return -1;
+    return 0;
+}
+
+/* Copy chunk c's bytes into out (capacity cap); returns its length or 0. */
+size_t oq_sim_chunk(const oq_sim *s, uint64_t c, uint8_t *out, size_t cap)
+{
+    if (c >= s->nchunks || s->len[c] > cap) return 0;
+    memcpy(out, s->chunk[c], s->len[c]);
+    return s->len[c];
+}
+
+/* Replace chunk c by the given bytes (checkpoint reload / test setup). */
+int oq_sim_set_chunk(oq_sim *s, uint64_t c, const uint8_t *in, size_t len)
+{
+    if (c >= s->nchunks || len > oq_chunk_cap(s->C)) return -1;
+    double *psi = (double *)malloc(sizeof(double) * (size_t)s->C);
+    int rc = oq_decode_chunk(in, len, s->C, psi);
+    free(psi);
+    if (rc != 0) return -1;
+    free(s->chunk[c]);
+    s->chunk[c] = (uint8_t *)malloc(len);
+    memcpy(s->chunk[c], in, len);
+    s->len[c] = (uint32_t)len;
+    return 0;
+}
+
+int oq_sim_set_block_level(oq_sim *s, uint64_t b, int level)
+{
+    if (b >= s->nblocks || level < 0 || level >= OQ_NLEVELS) return -1;
+    s->block_level[b] = (uint8_t)level;
+    return 0;
+}
+
+/* Footprint summary: out[0] compressed bytes (sum of 4-byte padded chunk
+ * sizes), out[1] number of chunks, out[2] current level, out[3] gates
+ * applied, out[4] lossy steps, out[5] min compressed bytes, out[6] max
+ * compressed bytes; fout[0] fidelity lower bound (Eq. (11)), fout[1] the
+ * per-block weighted bound. */
+void oq_sim_footprint(const oq_sim *s, uint64_t *out, double *fout)
+{
+    out[0] = oq_sim_compressed_bytes(s);
+    out[1] = s->nchunks;
+    out[2] = (uint64_t)s->level;
+    out[3] = s->gates_applied;
+    out[4] = s->lossy_steps;
+    out[5] = s->min_compressed;
+    out[6] = s->max_compressed;
+    fout[0] = s->flb;
+    fout[1] = s->flb_weighted;
+}
+
+int oq_sim_chunk_log2(const oq_sim *s) { return s->cb; }
