@@ -1,0 +1,189 @@
+/*
+ * qcz.h -- C ABI of the MI355X compressed full-state quantum circuit
+ * simulator (Wu et al., "Full-State Quantum Circuit Simulation by Using Data
+ * Compression", SC'19).
+ *
+ * A 2^n-amplitude complex128 state is held as independently compressed
+ * chunks in device memory.  Each gate decompresses the chunks it touches,
+ * applies its 2x2 unitary to the amplitude pairs (Sec. 3.1, Eqs. (6), (7)),
+ * and recompresses them with the hybrid lossless / error-bounded lossy scheme
+ * of Sec. 3.7 and Sec. 4.2 (Solution C: truncation to Sig_Bit_Count bits,
+ * Eq. (12), and the XOR leading-byte code), under the per-timestep adaptive
+ * bound of Sec. 3.7.
+ *
+ * Conventions shared by every call:
+ *   - qubit k is bit k of the amplitude index (Sec. 2.1, Eq. (5));
+ *   - amplitudes are stored as interleaved doubles (re, im);
+ *   - a "chunk" holds C = min(2048, 2b) doubles (min(1024, b) amplitudes) and
+ *     is the unit of compression; a "block" of b = 2^block_log2 amplitudes
+ *     groups chunks and carries an error level in the per-block mode;
+ *   - error levels: 0 lossless, 1..5 the pointwise relative bounds
+ *     1e-5, 1e-4, 1e-3, 1e-2, 1e-1 (Sec. 3.7);
+ *   - all device work is queued on the stream given to qcz_create; calls
+ *     that return host data synchronize that stream;
+ *   - the caller owns every buffer it passes; the library keeps no pointer
+ *     to caller memory except the device pool given to qcz_create, which
+ *     must stay allocated until qcz_destroy;
+ *   - no call throws; each returns a qcz_status and qcz_last_error() gives
+ *     the message of the last failure on a state.
+ */
+#ifndef QCZ_H
+#define QCZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qcz_state qcz_state;
+
+typedef enum {
+    QCZ_OK = 0,
+    QCZ_E_INVAL = -1,   /* malformed argument or gate record */
+    QCZ_E_NOMEM = -2,   /* the state does not fit the budget at the loosest level, or the pool is too small */
+    QCZ_E_DEVICE = -3,  /* a HIP call failed */
+    QCZ_E_FORMAT = -4,  /* a compressed stream or chunk entry is malformed */
+    QCZ_E_STATE = -5    /* call not allowed in the current state */
+} qcz_status;
+
+typedef enum {
+    QCZ_MODE_LOSSLESS = 0,  /* every chunk lossless (level 0) */
+    QCZ_MODE_FIXED = 1,     /* every gate at config.level */
+    QCZ_MODE_ADAPTIVE = 2,  /* Sec. 3.7: start lossless, relax one level whenever the
+                               compressed state exceeds budget_bytes after a gate, and
+                               redo that gate from its input */
+    QCZ_MODE_PERBLOCK = 3   /* level per block, set by qcz_set_block_levels */
+} qcz_mode;
+
+/* flags */
+#define QCZ_FLAG_GRAPH 1u   /* replay launch batches from captured HIP graphs when a batch repeats */
+
+typedef struct {
+    uint32_t n_qubits;      /* 6 .. 40 */
+    uint32_t block_log2;    /* log2 amplitudes per block, 6 .. n_qubits */
+    int32_t mode;           /* qcz_mode */
+    int32_t level;          /* QCZ_MODE_FIXED: the level; QCZ_MODE_PERBLOCK: the initial level */
+    uint64_t budget_bytes;  /* QCZ_MODE_ADAPTIVE: limit on compressed bytes (0: none) */
+    uint32_t flags;         /* QCZ_FLAG_* */
+    uint32_t batch;         /* gates per launch batch between host checks (0: 64; at most 512) */
+    uint32_t grid;          /* workgroups per gate launch (0: 4 per compute unit) */
+    uint32_t reserved0;
+    uint64_t reserved[3];
+} qcz_config;
+
+/* Gate record, 88 bytes.  kind:
+ *   0 U1    general 2x2 unitary on `target` (Eq. (6)), applied where every
+ *           bit of control_mask is 1 (Eq. (7)); m = u00,u01,u10,u11 as (re,im)
+ *   1 DIAG1 diagonal phases d0 (target bit 0), d1 (target bit 1), controlled
+ *   2 DIAG2 diagonal phases p[2*bit(target2) + bit(target)], controlled
+ *   3 X     Pauli-X on `target`, controlled by control_mask (exact)
+ *   4 MCZ   sign flip where every bit of control_mask is 1 (exact)
+ * The target may not be in control_mask; matrix entries must be finite.   */
+typedef struct {
+    uint32_t kind;
+    uint32_t target;
+    uint32_t target2;
+    uint32_t reserved;
+    uint64_t control_mask;
+    double m[8];
+} qcz_gate;
+
+typedef struct {
+    uint64_t compressed_bytes;   /* sum over chunks of the 4-byte padded stream size: sum sizeof(CB_i) of Eq. (8) */
+    uint64_t table_bytes;        /* chunk table, 8 bytes per chunk */
+    uint64_t total_bytes;        /* compressed + table; Eq. (8)'s decompressed term is 0 here: decoded chunks live in LDS */
+    uint64_t raw_bytes;          /* 2^(n+4) */
+    uint64_t arena_bytes;        /* capacity of one arena */
+    uint64_t arena_used;         /* arena bytes in use, garbage included */
+    uint64_t nchunks;
+    uint64_t gates_applied;
+    uint64_t lossy_steps;        /* gates that recompressed a chunk at a lossy level */
+    uint64_t min_compressed;     /* over the run, after each gate */
+    uint64_t max_compressed;
+    uint64_t compactions;
+    int32_t level;               /* current global level */
+    int32_t reserved;
+    double ratio;                /* raw_bytes / total_bytes */
+    double fidelity_lower_bound; /* prod over lossy gates of (1 - delta), Sec. 3.8 Eq. (11) */
+} qcz_footprint_t;
+
+/* Bytes of device pool needed for a configuration (state |0..0> plus
+ * metadata); larger pools leave room for less compressible states. */
+size_t qcz_pool_bytes_min(const qcz_config *cfg);
+
+/* Create the state |0...0> (Sec. 3.3: the state is created in blocks and
+ * compressed) inside the caller's device pool.  hip_stream may be NULL (the
+ * default stream).  Errors: QCZ_E_INVAL (configuration), QCZ_E_NOMEM (pool
+ * smaller than qcz_pool_bytes_min), QCZ_E_DEVICE. */
+qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, void *hip_stream, qcz_state **out);
+
+/* Apply n_gates gate records (host array, copied before return).  The state
+ * advances gate by gate; each gate is one timestep of Sec. 3.7.  On
+ * QCZ_E_NOMEM (no level fits the budget) or any error, the state is the one
+ * after the last gate that completed and *applied (if not NULL) holds their
+ * number.  Records are validated first: QCZ_E_INVAL applies nothing. */
+qcz_status qcz_apply_gates(qcz_state *st, const qcz_gate *gates, size_t n_gates, size_t *applied);
+
+/* Amplitudes at the k indices idx[] into out_re_im[2k] (host). */
+qcz_status qcz_read_amplitudes(qcz_state *st, const uint64_t *idx, size_t k, double *out_re_im);
+
+/* Decode chunks [first_chunk, first_chunk + n_chunks) into device memory
+ * dev_out (n_chunks * C doubles, interleaved re/im). */
+qcz_status qcz_decode_chunks_to(qcz_state *st, uint64_t first_chunk, uint64_t n_chunks, void *dev_out);
+
+/* Sums over the decoded state: out[0] = sum re, out[1] = sum im,
+ * out[2] = sum |a|^2 (fp64 device reductions, fixed order for a given
+ * configuration). */
+qcz_status qcz_moments(qcz_state *st, double out[3]);
+
+/* Draw `shots` basis indices with probability |a_i|^2 / sum |a|^2 without
+ * collapsing the state; deterministic for a seed. */
+qcz_status qcz_sample(qcz_state *st, uint64_t seed, size_t shots, uint64_t *out_idx);
+
+qcz_status qcz_footprint(qcz_state *st, qcz_footprint_t *out);
+
+/* Copy chunk `chunk`'s stream to host memory (capacity cap); *len gets its
+ * size.  QCZ_E_INVAL if cap is too small. */
+qcz_status qcz_export_chunk(qcz_state *st, uint64_t chunk, void *host_buf, size_t cap, size_t *len);
+
+/* Replace chunk `chunk` by a stream (checkpoint reload).  The header is
+ * checked; QCZ_E_FORMAT if it is not a valid stream header or too long. */
+qcz_status qcz_import_chunk(qcz_state *st, uint64_t chunk, const void *host_buf, size_t len);
+
+/* Per-block levels (host array of 2^(n - block_log2) values 0..5) used by
+ * QCZ_MODE_PERBLOCK; QCZ_E_STATE in other modes. */
+qcz_status qcz_set_block_levels(qcz_state *st, const uint8_t *levels);
+
+/* Stream sizes of all chunks into host memory (n_chunks values). */
+qcz_status qcz_chunk_sizes(qcz_state *st, uint32_t *out_sizes);
+
+/* Number of chunks and doubles per chunk of a state. */
+uint64_t qcz_num_chunks(const qcz_state *st);
+uint32_t qcz_chunk_doubles(const qcz_state *st);
+
+const char *qcz_last_error(const qcz_state *st);
+void qcz_destroy(qcz_state *st);
+
+/* ---- codec entry points (no state) -------------------------------------- */
+
+/* Largest stream of a chunk of C doubles (bytes). */
+size_t qcz_chunk_cap(uint32_t C);
+
+/* Encode n_chunks chunks of C doubles (device, contiguous) at `level` into
+ * device slots of slot_bytes bytes each (slot_bytes >= qcz_chunk_cap(C),
+ * multiple of 4); stream sizes go to dev_sizes (device, n_chunks u32).
+ * C is a power of two in 128 .. 2048. */
+qcz_status qcz_encode_chunks(const void *dev_in, uint32_t C, uint64_t n_chunks, int level, void *dev_slots,
+                             size_t slot_bytes, uint32_t *dev_sizes, void *hip_stream);
+
+/* Decode n_chunks streams from device slots into C doubles each (device). */
+qcz_status qcz_decode_chunks(const void *dev_slots, size_t slot_bytes, const uint32_t *dev_sizes, uint32_t C,
+                             uint64_t n_chunks, void *dev_out, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCZ_H */

@@ -1,0 +1,109 @@
+// Internal types shared by the HIP kernels (qcz_kernels.hip) and the host
+// runtime (qcz_runtime.cpp) of the compressed state-vector library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace qcz {
+
+constexpr int kLevels = 6;          // lossless, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1 (Sec. 3.7)
+constexpr int kWG = 256;            // threads per workgroup: two chunk slots of 128
+constexpr int kGroup = 128;         // threads per chunk slot
+constexpr int kCMax = 2048;         // doubles per chunk (1024 amplitudes)
+constexpr int kCMin = 128;          // one value per thread at least
+constexpr int kBufWords = 4304;     // per-slot LDS words: 2*kCMax doubles, or the largest
+                                    // stream plus the slack its bit reader may touch
+constexpr int kMaxBatch = 512;      // gates per launch batch (per-gate log entries)
+constexpr uint32_t kMaxChunkBytes = 4 + 4 * (kCMax / 16) + 8 * kCMax;   // 16900
+
+enum GateKind { K_U1 = 0, K_DIAG1 = 1, K_DIAG2 = 2, K_X = 3, K_MCZ = 4 };
+enum JobType { J_SINGLE = 0, J_PAIR = 1, J_PERMUTE = 2 };
+enum StopReason { STOP_NONE = 0, STOP_BUDGET = 1, STOP_ARENA = 2, STOP_CORRUPT = 3 };
+enum ChunkMode { M_PACK = 0, M_CONST2 = 1, M_SPARSE = 2 };
+
+// One gate, lowered to a job enumeration over chunk indices.
+struct GateDesc {
+    int32_t kind, q, q2, seq;       // seq: position in the launch batch
+    uint64_t cm;                    // control mask over amplitude-index bits
+    double m[8];
+    int32_t job_type;               // JobType
+    int32_t nchunk_bits;            // log2(number of chunks)
+    uint64_t fixed_mask, fixed_val; // chunk-index bits held fixed by the enumeration
+    uint64_t pair_bit;              // PAIR / PERMUTE: chunk-index bit flipped by the target
+    uint64_t nitems;                // enumerated chunk positions
+    uint64_t njobs;                 // workgroup jobs (two positions each)
+    int32_t check_phase;            // DIAG: skip chunks whose reachable phases are all 1
+    int32_t per_block;              // level from the per-block table instead of the global one
+    int32_t block_shift;            // log2(chunks per block)
+    int32_t fixed_level;            // >= 0: codec kernels encode at this level
+};
+
+struct GateLog {
+    uint64_t live;   // compressed bytes after the gate
+    uint64_t bump;   // arena bytes used after the gate
+    uint64_t reenc;  // chunks re-encoded by the gate
+    uint64_t pad;
+};
+
+// Device-resident control block (first bytes of the pool).
+struct DevState {
+    uint64_t bump;        // bytes used in the current arena
+    uint64_t live;        // sum over chunks of the 4-byte padded size
+    uint64_t arena_cap;   // bytes in one arena
+    uint64_t budget;      // compressed-byte limit checked after each gate (0: none)
+    int32_t level;        // global level used by gates
+    int32_t stop;         // set by a gate epilogue: every later gate of the batch is skipped
+    int32_t stop_reason;
+    int32_t stop_seq;
+    int32_t fail;         // an allocation of the current gate did not fit
+    int32_t corrupt;      // a chunk entry pointed outside the arena
+    uint32_t done;        // finished workgroups of the running kernel
+    uint32_t pad0;
+    uint64_t reenc_cur;   // chunks re-encoded by the running gate
+    uint64_t pad1[6];
+    GateLog log[kMaxBatch];
+};
+
+// Pointers of one state, passed by value to every kernel.
+struct DevPtrs {
+    uint32_t *arena;            // current arena, word addressed
+    uint64_t arena_words;
+    uint64_t *table;            // per chunk: (offset in words << 16) | size in bytes
+    uint64_t *undo;             // per enumerated position: previous table entry
+    const uint8_t *block_level; // per block
+    DevState *ds;
+    int32_t cb;                 // log2 amplitudes per chunk
+    int32_t C;                  // doubles per chunk
+    uint64_t nchunks;
+};
+
+// Inputs / outputs of the codec-only and readout kernels.
+struct IOPtrs {
+    const double *raw_in;       // [nitems][C] doubles
+    double *raw_out;            // [nitems][C] doubles
+    const uint32_t *slots_in;   // [nitems][slot_words] streams
+    const uint32_t *sizes_in;   // [nitems] bytes
+    uint32_t *slots_out;
+    uint32_t *sizes_out;
+    uint64_t slot_words;
+    const uint64_t *list;       // readout: chunk ids (nullptr: positions are chunk ids + first)
+    uint64_t first;
+    double *partials;           // moments: [gridDim.x][4]
+};
+
+inline uint32_t chunk_cap_bytes(int C) { return 4u + 4u * (uint32_t)((C + 15) / 16) + 8u * (uint32_t)C; }
+
+// Host launchers (qcz_kernels.hip).
+hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);
+hipError_t launch_permute(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);
+hipError_t launch_rollback(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);
+hipError_t launch_encode_raw(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);
+hipError_t launch_decode_slots(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);
+hipError_t launch_readout(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);
+hipError_t launch_moments(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);
+hipError_t launch_fill_table(const DevPtrs &P, uint64_t entry0, uint64_t entry_rest, hipStream_t st);
+hipError_t launch_compact(const DevPtrs &P, uint32_t *dst_arena, uint64_t *scratch, uint64_t *block_sums,
+                          uint64_t nblocks_scan, hipStream_t st);
+
+}  // namespace qcz

@@ -1,0 +1,776 @@
+// Host runtime of the compressed state-vector library: the C ABI of
+// include/qcz.h on top of the kernels in qcz_kernels.hip.
+//
+// Device memory is one caller-owned pool, carved into
+//   control block | chunk table | undo log | scan scratch | block levels |
+//   reduction partials | staging | arena A | arena B.
+// Compressed chunks are appended to the current arena; a chunk's previous
+// stream stays where it was until the next compaction, so a gate can be
+// undone by restoring table entries.  Compaction copies the live streams,
+// in chunk order, into the other arena.
+//
+// Gates are launched in batches; each gate kernel's last workgroup logs the
+// compressed size after the gate and raises a stop flag when the state no
+// longer fits (budget of Sec. 3.7) or the arena is full.  Later gates of the
+// batch then do nothing; the host rolls the stopped gate back, relaxes the
+// level or compacts, and resumes from it.  This gives the per-gate decisions
+// of Sec. 3.7 without a host round trip per gate.
+#include "../../include/qcz.h"
+#include "qcz_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace qcz;
+
+namespace {
+
+constexpr double kDelta[kLevels] = {0.0, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1};
+constexpr int kScratchChunks = 64;
+constexpr int kMomGrid = 2048;
+constexpr int kMaxGraphs = 8;
+constexpr uint64_t kScanItems = 1024;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct GraphEntry {
+    std::vector<uint8_t> key;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct Layout {
+    size_t ds, table, undo, bsums, blevel, partials, scratch, arena0, arena1, arena_bytes, end;
+};
+
+int chunk_log2_for(int bl) { return bl < 10 ? bl : 10; }
+
+Layout layout_for(int n, int bl, size_t pool_bytes)
+{
+    const int cb = chunk_log2_for(bl);
+    const int C = 2 << cb;
+    const uint64_t nchunks = 1ull << (n - cb);
+    const uint64_t nblocks = 1ull << (n - bl);
+    Layout L{};
+    size_t o = 0;
+    L.ds = o; o = align256(o + sizeof(DevState));
+    L.table = o; o = align256(o + 8 * nchunks);
+    L.undo = o; o = align256(o + 8 * nchunks);
+    L.bsums = o; o = align256(o + 8 * ((nchunks + kScanItems - 1) / kScanItems + 1));
+    L.blevel = o; o = align256(o + nblocks);
+    L.partials = o; o = align256(o + 8 * (size_t)std::max<uint64_t>(4 * kMomGrid, nchunks < (1u << 20) ? nchunks : 0));
+    const size_t slot = ((chunk_cap_bytes(C) + 3) & ~3u);
+    L.scratch = o; o = align256(o + (size_t)kScratchChunks * (8 * (size_t)C + slot + 16) + 4096);
+    L.end = o;
+    size_t rest = pool_bytes > o ? pool_bytes - o : 0;
+    L.arena_bytes = (rest / 2) & ~(size_t)255;
+    L.arena0 = o;
+    L.arena1 = o + L.arena_bytes;
+    return L;
+}
+
+}  // namespace
+
+struct qcz_state {
+    qcz_config cfg{};
+    int n = 0, bl = 0, cb = 0, C = 0;
+    uint64_t nchunks = 0, nblocks = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint8_t *pool = nullptr;
+    size_t pool_bytes = 0;
+    Layout lay{};
+    DevState *ds = nullptr;
+    uint64_t *table = nullptr, *undo = nullptr, *bsums = nullptr;
+    uint8_t *blevel = nullptr;
+    double *partials = nullptr;
+    uint8_t *scratch = nullptr;
+    uint32_t *arena[2] = {nullptr, nullptr};
+    int cur = 0;
+    int grid_max = 1024;
+    int batch = 64;
+    // host mirror of the committed state
+    int level = 0;
+    uint64_t live = 0, bump = 0;
+    uint64_t gates_applied = 0, lossy_steps = 0, min_c = 0, max_c = 0, compactions = 0;
+    double flb = 1.0;
+    std::vector<uint8_t> block_levels;
+    std::string err;
+    std::vector<GraphEntry> graphs;
+    DevState hds{};  // readback staging
+};
+
+namespace {
+
+qcz_status fail(qcz_state *s, qcz_status code, const std::string &msg)
+{
+    if (s) s->err = msg;
+    return code;
+}
+
+#define HIPCHK(s, call)                                                                               \
+    do {                                                                                              \
+        hipError_t e_ = (call);                                                                       \
+        if (e_ != hipSuccess) return fail((s), QCZ_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+DevPtrs ptrs(const qcz_state *s)
+{
+    DevPtrs P{};
+    P.arena = s->arena[s->cur];
+    P.arena_words = s->lay.arena_bytes / 4;
+    P.table = s->table;
+    P.undo = s->undo;
+    P.block_level = s->blevel;
+    P.ds = s->ds;
+    P.cb = s->cb;
+    P.C = s->C;
+    P.nchunks = s->nchunks;
+    return P;
+}
+
+int popcount64(uint64_t x) { return __builtin_popcountll(x); }
+
+bool is_unit(double re, double im) { return re == 1.0 && im == 0.0; }
+
+qcz_status check_gate(const qcz_state *s, const qcz_gate &g)
+{
+    const int n = s->n;
+    const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    if (g.control_mask & ~all) return QCZ_E_INVAL;
+    for (int k = 0; k < 8; ++k)
+        if (!std::isfinite(g.m[k])) return QCZ_E_INVAL;
+    switch (g.kind) {
+    case K_U1:
+    case K_DIAG1:
+    case K_X:
+        if ((int)g.target >= n) return QCZ_E_INVAL;
+        if (g.control_mask & (1ull << g.target)) return QCZ_E_INVAL;
+        return QCZ_OK;
+    case K_DIAG2:
+        if ((int)g.target >= n || (int)g.target2 >= n || g.target == g.target2) return QCZ_E_INVAL;
+        if (g.control_mask & ((1ull << g.target) | (1ull << g.target2))) return QCZ_E_INVAL;
+        return QCZ_OK;
+    case K_MCZ:
+        return g.control_mask ? QCZ_OK : QCZ_E_INVAL;
+    default:
+        return QCZ_E_INVAL;
+    }
+}
+
+// Job builder: which chunks a gate touches (Sec. 3.3 index segments and
+// control rules, at chunk granularity) as an enumeration over chunk bits.
+GateDesc lower_gate(const qcz_state *s, const qcz_gate &g, int seq)
+{
+    GateDesc d{};
+    d.kind = (int32_t)g.kind;
+    d.q = (int32_t)g.target;
+    d.q2 = (int32_t)g.target2;
+    d.seq = seq;
+    d.cm = g.control_mask;
+    for (int k = 0; k < 8; ++k) d.m[k] = g.m[k];
+    d.nchunk_bits = s->n - s->cb;
+    d.per_block = s->cfg.mode == QCZ_MODE_PERBLOCK ? 1 : 0;
+    d.block_shift = s->bl - s->cb;
+    d.fixed_level = -1;
+    const uint64_t cm_hi = g.control_mask >> s->cb;
+    const uint64_t cm_lo = g.control_mask & ((1ull << s->cb) - 1);
+    if ((g.kind == K_U1 || g.kind == K_X) && (int)g.target >= s->cb) {
+        d.pair_bit = 1ull << (g.target - s->cb);
+        d.job_type = (g.kind == K_X && cm_lo == 0) ? J_PERMUTE : J_PAIR;
+        d.fixed_mask = cm_hi | d.pair_bit;
+        d.fixed_val = cm_hi;
+        const int nfree = d.nchunk_bits - popcount64(d.fixed_mask);
+        d.njobs = 1ull << nfree;
+        d.nitems = d.job_type == J_PAIR ? 2 * d.njobs : d.njobs;
+        return d;
+    }
+    d.job_type = J_SINGLE;
+    d.fixed_mask = cm_hi;
+    d.fixed_val = cm_hi;
+    bool none = false;
+    if (g.kind == K_DIAG1 || g.kind == K_DIAG2) {
+        d.check_phase = 1;
+        if (g.kind == K_DIAG1) {
+            const bool u0 = is_unit(g.m[0], g.m[1]), u1 = is_unit(g.m[2], g.m[3]);
+            if (u0 && u1) none = true;
+            else if ((int)g.target >= s->cb && (u0 || u1)) {
+                const uint64_t bit = 1ull << (g.target - s->cb);
+                d.fixed_mask |= bit;
+                if (u0) d.fixed_val |= bit;   // only the target=1 half has a non-trivial phase
+            }
+        } else if (is_unit(g.m[0], g.m[1]) && is_unit(g.m[2], g.m[3]) && is_unit(g.m[4], g.m[5]) &&
+                   is_unit(g.m[6], g.m[7])) {
+            none = true;
+        }
+    }
+    const int nfree = d.nchunk_bits - popcount64(d.fixed_mask);
+    d.nitems = none ? 0 : (1ull << nfree);
+    d.njobs = (d.nitems + 1) / 2;
+    return d;
+}
+
+int grid_for(const qcz_state *s, const GateDesc &d)
+{
+    if (d.job_type == J_PERMUTE) {
+        uint64_t b = (d.njobs + kWG - 1) / kWG;
+        return (int)std::max<uint64_t>(1, std::min<uint64_t>(b, 65535));
+    }
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(d.njobs, (uint64_t)s->grid_max));
+}
+
+qcz_status write_header(qcz_state *s)
+{
+    DevState h{};
+    h.bump = s->bump;
+    h.live = s->live;
+    h.arena_cap = s->lay.arena_bytes;
+    h.budget = s->cfg.mode == QCZ_MODE_ADAPTIVE ? s->cfg.budget_bytes : 0;
+    h.level = s->level;
+    s->hds = h;
+    HIPCHK(s, hipMemcpyAsync(s->ds, &s->hds, offsetof(DevState, log), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));   // the staging struct is reused right after
+    return QCZ_OK;
+}
+
+void clear_graphs(qcz_state *s)
+{
+    for (auto &g : s->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    s->graphs.clear();
+}
+
+qcz_status compact(qcz_state *s)
+{
+    DevPtrs P = ptrs(s);
+    const uint64_t nb = (s->nchunks + kScanItems - 1) / kScanItems;
+    HIPCHK(s, launch_compact(P, s->arena[1 - s->cur], s->undo, s->bsums, nb, s->stream));
+    uint64_t total = 0;
+    HIPCHK(s, hipMemcpyAsync(&total, s->bsums + nb, 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    s->cur = 1 - s->cur;
+    s->bump = total;
+    s->compactions += 1;
+    clear_graphs(s);
+    return write_header(s);
+}
+
+qcz_status launch_one(qcz_state *s, const GateDesc &d)
+{
+    DevPtrs P = ptrs(s);
+    const int grid = grid_for(s, d);
+    hipError_t e = d.job_type == J_PERMUTE ? launch_permute(d, P, grid, s->stream) : launch_gate(d, P, grid, s->stream);
+    if (e != hipSuccess) return fail(s, QCZ_E_DEVICE, std::string("gate launch: ") + hipGetErrorString(e));
+    return QCZ_OK;
+}
+
+qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
+{
+    if (!(s->cfg.flags & QCZ_FLAG_GRAPH) || s->stream == nullptr) {
+        for (const auto &d : descs) {
+            qcz_status st = launch_one(s, d);
+            if (st != QCZ_OK) return st;
+        }
+        return QCZ_OK;
+    }
+    std::vector<uint8_t> key(descs.size() * sizeof(GateDesc) + sizeof(DevPtrs));
+    DevPtrs P = ptrs(s);
+    memcpy(key.data(), &P, sizeof(P));
+    if (!descs.empty()) memcpy(key.data() + sizeof(P), descs.data(), descs.size() * sizeof(GateDesc));
+    for (auto &g : s->graphs) {
+        if (g.key == key) {
+            HIPCHK(s, hipGraphLaunch(g.exec, s->stream));
+            return QCZ_OK;
+        }
+    }
+    hipGraph_t graph = nullptr;
+    HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed));
+    qcz_status st = QCZ_OK;
+    for (const auto &d : descs) {
+        st = launch_one(s, d);
+        if (st != QCZ_OK) break;
+    }
+    hipError_t e = hipStreamEndCapture(s->stream, &graph);
+    if (st != QCZ_OK) return st;
+    if (e != hipSuccess) return fail(s, QCZ_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(s, QCZ_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    if ((int)s->graphs.size() >= kMaxGraphs) {
+        (void)hipGraphExecDestroy(s->graphs.front().exec);
+        s->graphs.erase(s->graphs.begin());
+    }
+    GraphEntry ge;
+    ge.key = std::move(key);
+    ge.exec = exec;
+    s->graphs.push_back(std::move(ge));
+    HIPCHK(s, hipGraphLaunch(exec, s->stream));
+    return QCZ_OK;
+}
+
+void commit_gate(qcz_state *s, const GateLog &lg)
+{
+    s->live = lg.live;
+    s->bump = lg.bump;
+    s->gates_applied += 1;
+    if (lg.reenc > 0) {
+        double d = 0.0;
+        if (s->cfg.mode == QCZ_MODE_PERBLOCK) {
+            for (uint8_t lv : s->block_levels) d = std::max(d, kDelta[lv]);
+        } else {
+            d = kDelta[s->level];
+        }
+        if (d > 0.0) {
+            s->flb *= (1.0 - d);   // Sec. 3.8, Eq. (11)
+            s->lossy_steps += 1;
+        }
+    }
+    s->min_c = std::min(s->min_c, s->live);
+    s->max_c = std::max(s->max_c, s->live);
+}
+
+qcz_status single_kernel_chunks(qcz_state *s, GateDesc &d, uint64_t nitems, uint64_t first)
+{
+    d = GateDesc{};
+    d.job_type = J_SINGLE;
+    d.nitems = nitems;
+    d.njobs = (nitems + 1) / 2;
+    d.fixed_level = -1;
+    int bits = 0;
+    while ((1ull << bits) < nitems) ++bits;
+    d.nchunk_bits = bits;
+    (void)first;
+    return QCZ_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t qcz_chunk_cap(uint32_t C)
+{
+    if (C < 4 || (C & (C - 1))) return 0;
+    return chunk_cap_bytes((int)C);
+}
+
+size_t qcz_pool_bytes_min(const qcz_config *cfg)
+{
+    if (!cfg || cfg->n_qubits < 6 || cfg->n_qubits > 40 || cfg->block_log2 < 6 || cfg->block_log2 > cfg->n_qubits)
+        return 0;
+    Layout L = layout_for((int)cfg->n_qubits, (int)cfg->block_log2, 0);
+    const int cb = chunk_log2_for((int)cfg->block_log2);
+    const uint64_t nchunks = 1ull << (cfg->n_qubits - cb);
+    // two arenas, each holding the initial streams with room to spare
+    const size_t arena = align256((size_t)(64u << 10) + 64 * (size_t)nchunks);
+    return L.end + 2 * arena;
+}
+
+qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, void *hip_stream, qcz_state **out)
+{
+    if (!cfg || !out || !dev_pool) return QCZ_E_INVAL;
+    *out = nullptr;
+    if (cfg->n_qubits < 6 || cfg->n_qubits > 40 || cfg->block_log2 < 6 || cfg->block_log2 > cfg->n_qubits)
+        return QCZ_E_INVAL;
+    if (cfg->mode < QCZ_MODE_LOSSLESS || cfg->mode > QCZ_MODE_PERBLOCK) return QCZ_E_INVAL;
+    if (cfg->level < 0 || cfg->level >= kLevels || cfg->batch > (uint32_t)kMaxBatch) return QCZ_E_INVAL;
+    if (((uintptr_t)dev_pool & 255) != 0) return QCZ_E_INVAL;
+    if (pool_bytes < qcz_pool_bytes_min(cfg)) return QCZ_E_NOMEM;
+
+    qcz_state *s = new qcz_state();
+    s->cfg = *cfg;
+    s->n = (int)cfg->n_qubits;
+    s->bl = (int)cfg->block_log2;
+    s->cb = chunk_log2_for(s->bl);
+    s->C = 2 << s->cb;
+    s->nchunks = 1ull << (s->n - s->cb);
+    s->nblocks = 1ull << (s->n - s->bl);
+    s->pool = (uint8_t *)dev_pool;
+    s->pool_bytes = pool_bytes;
+    s->lay = layout_for(s->n, s->bl, pool_bytes);
+    s->ds = (DevState *)(s->pool + s->lay.ds);
+    s->table = (uint64_t *)(s->pool + s->lay.table);
+    s->undo = (uint64_t *)(s->pool + s->lay.undo);
+    s->bsums = (uint64_t *)(s->pool + s->lay.bsums);
+    s->blevel = s->pool + s->lay.blevel;
+    s->partials = (double *)(s->pool + s->lay.partials);
+    s->scratch = s->pool + s->lay.scratch;
+    s->arena[0] = (uint32_t *)(s->pool + s->lay.arena0);
+    s->arena[1] = (uint32_t *)(s->pool + s->lay.arena1);
+    s->batch = cfg->batch ? (int)cfg->batch : 64;
+    s->level = cfg->mode == QCZ_MODE_FIXED ? cfg->level : 0;
+
+    if (hip_stream) {
+        s->stream = (hipStream_t)hip_stream;
+    } else {
+        hipError_t e = hipStreamCreate(&s->stream);
+        if (e != hipSuccess) { delete s; return QCZ_E_DEVICE; }
+        s->own_stream = true;
+        (void)hipDeviceSynchronize();
+    }
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    s->grid_max = cfg->grid ? (int)cfg->grid : 4 * ncu;
+
+    s->block_levels.assign(s->nblocks, (uint8_t)(cfg->mode == QCZ_MODE_PERBLOCK ? cfg->level : 0));
+    auto bail = [&](qcz_status st) {
+        qcz_destroy(s);
+        return st;
+    };
+    if (hipMemcpyAsync(s->blevel, s->block_levels.data(), s->nblocks, hipMemcpyHostToDevice, s->stream) != hipSuccess)
+        return bail(QCZ_E_DEVICE);
+
+    // |0...0>: chunk 0 holds amplitude 1 at index 0, every other chunk is zero
+    // (Sec. 3.3: the state vectors are created in blocks and compressed).
+    const size_t slot = (chunk_cap_bytes(s->C) + 3) & ~3u;
+    double *raw = (double *)s->scratch;
+    uint32_t *slots = (uint32_t *)(s->scratch + 2 * 8 * (size_t)s->C);
+    uint32_t *sizes = (uint32_t *)(s->scratch + 2 * 8 * (size_t)s->C + 2 * slot);
+    std::vector<double> init(2 * (size_t)s->C, 0.0);
+    init[0] = 1.0;
+    if (hipMemcpyAsync(raw, init.data(), init.size() * 8, hipMemcpyHostToDevice, s->stream) != hipSuccess)
+        return bail(QCZ_E_DEVICE);
+    if (qcz_encode_chunks(raw, (uint32_t)s->C, 2, 0, slots, slot, sizes, s->stream) != QCZ_OK) return bail(QCZ_E_DEVICE);
+    uint32_t hsz[2] = {0, 0};
+    if (hipMemcpyAsync(hsz, sizes, 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess) return bail(QCZ_E_DEVICE);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(QCZ_E_DEVICE);
+    const uint64_t p0 = (hsz[0] + 3u) & ~3u, p1 = (hsz[1] + 3u) & ~3u;
+    if (hipMemcpyAsync(s->arena[0], slots, p0, hipMemcpyDeviceToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync((uint8_t *)s->arena[0] + p0, (uint8_t *)slots + slot, p1, hipMemcpyDeviceToDevice, s->stream) !=
+            hipSuccess)
+        return bail(QCZ_E_DEVICE);
+    DevPtrs P = ptrs(s);
+    if (launch_fill_table(P, (0ull << 16) | hsz[0], ((p0 / 4) << 16) | hsz[1], s->stream) != hipSuccess)
+        return bail(QCZ_E_DEVICE);
+    s->bump = p0 + p1;
+    s->live = p0 + p1 * (s->nchunks - 1);
+    s->min_c = s->max_c = s->live;
+    if (write_header(s) != QCZ_OK) return bail(QCZ_E_DEVICE);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(QCZ_E_DEVICE);
+    *out = s;
+    return QCZ_OK;
+}
+
+void qcz_destroy(qcz_state *s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    clear_graphs(s);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+const char *qcz_last_error(const qcz_state *s) { return s ? s->err.c_str() : "null state"; }
+
+uint64_t qcz_num_chunks(const qcz_state *s) { return s ? s->nchunks : 0; }
+uint32_t qcz_chunk_doubles(const qcz_state *s) { return s ? (uint32_t)s->C : 0; }
+
+qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, size_t *applied)
+{
+    if (applied) *applied = 0;
+    if (!s || (!gates && n_gates)) return QCZ_E_INVAL;
+    for (size_t k = 0; k < n_gates; ++k)
+        if (check_gate(s, gates[k]) != QCZ_OK)
+            return fail(s, QCZ_E_INVAL, "malformed gate record " + std::to_string(k));
+    size_t idx = 0;
+    int compacted_for = -1;  // gate index a compaction was made for
+    std::vector<GateDesc> descs;
+    while (idx < n_gates) {
+        const size_t B = std::min<size_t>((size_t)s->batch, n_gates - idx);
+        if (s->bump > s->lay.arena_bytes / 4 * 3 && s->bump > 2 * s->live) {
+            qcz_status st = compact(s);
+            if (st != QCZ_OK) return st;
+        }
+        descs.clear();
+        for (size_t k = 0; k < B; ++k) descs.push_back(lower_gate(s, gates[idx + k], (int)k));
+        const uint64_t live0 = s->live, bump0 = s->bump;
+        qcz_status st = launch_batch(s, descs);
+        if (st != QCZ_OK) return st;
+        HIPCHK(s, hipMemcpyAsync(&s->hds, s->ds, offsetof(DevState, log) + B * sizeof(GateLog), hipMemcpyDeviceToHost,
+                                 s->stream));
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        const DevState &h = s->hds;
+        if (!h.stop) {
+            for (size_t k = 0; k < B; ++k) commit_gate(s, h.log[k]);
+            idx += B;
+            if (applied) *applied = idx;
+            continue;
+        }
+        const int sseq = h.stop_seq;
+        const int reason = h.stop_reason;
+        for (int k = 0; k < sseq; ++k) commit_gate(s, h.log[k]);
+        // undo the stopped gate
+        const GateDesc &dstop = descs[(size_t)sseq];
+        DevPtrs P = ptrs(s);
+        const uint64_t work = dstop.job_type == J_PERMUTE ? dstop.njobs : dstop.nitems;
+        const int rg = (int)std::max<uint64_t>(1, std::min<uint64_t>((work + kWG - 1) / kWG, 65535));
+        HIPCHK(s, launch_rollback(dstop, P, rg, s->stream));
+        if (sseq == 0) { s->live = live0; s->bump = bump0; }
+        idx += (size_t)sseq;
+        if (applied) *applied = idx;
+        if (reason == STOP_BUDGET) {
+            if (s->level >= kLevels - 1) {
+                (void)write_header(s);
+                (void)hipStreamSynchronize(s->stream);
+                return fail(s, QCZ_E_NOMEM, "compressed state exceeds the budget at the loosest level");
+            }
+            s->level += 1;   // Sec. 3.7: relax the bound and redo the gate
+            st = write_header(s);
+            if (st != QCZ_OK) return st;
+        } else if (reason == STOP_ARENA) {
+            st = write_header(s);
+            if (st != QCZ_OK) return st;
+            if (compacted_for == (int)idx) return fail(s, QCZ_E_NOMEM, "arena too small for one gate after compaction");
+            st = compact(s);
+            if (st != QCZ_OK) return st;
+            compacted_for = (int)idx;
+        } else {
+            (void)write_header(s);
+            (void)hipStreamSynchronize(s->stream);
+            return fail(s, QCZ_E_FORMAT, "a chunk table entry points outside the arena");
+        }
+    }
+    return QCZ_OK;
+}
+
+qcz_status qcz_footprint(qcz_state *s, qcz_footprint_t *out)
+{
+    if (!s || !out) return QCZ_E_INVAL;
+    qcz_footprint_t f{};
+    f.compressed_bytes = s->live;
+    f.table_bytes = 8 * s->nchunks;
+    f.total_bytes = f.compressed_bytes + f.table_bytes;
+    f.raw_bytes = 1ull << (s->n + 4);
+    f.arena_bytes = s->lay.arena_bytes;
+    f.arena_used = s->bump;
+    f.nchunks = s->nchunks;
+    f.gates_applied = s->gates_applied;
+    f.lossy_steps = s->lossy_steps;
+    f.min_compressed = s->min_c;
+    f.max_compressed = s->max_c;
+    f.compactions = s->compactions;
+    f.level = s->level;
+    f.ratio = (double)f.raw_bytes / (double)f.total_bytes;
+    f.fidelity_lower_bound = s->flb;
+    *out = f;
+    return QCZ_OK;
+}
+
+qcz_status qcz_set_block_levels(qcz_state *s, const uint8_t *levels)
+{
+    if (!s || !levels) return QCZ_E_INVAL;
+    if (s->cfg.mode != QCZ_MODE_PERBLOCK) return fail(s, QCZ_E_STATE, "block levels need QCZ_MODE_PERBLOCK");
+    for (uint64_t b = 0; b < s->nblocks; ++b)
+        if (levels[b] >= kLevels) return fail(s, QCZ_E_INVAL, "block level out of range");
+    s->block_levels.assign(levels, levels + s->nblocks);
+    HIPCHK(s, hipMemcpyAsync(s->blevel, s->block_levels.data(), s->nblocks, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    clear_graphs(s);
+    return QCZ_OK;
+}
+
+qcz_status qcz_decode_chunks_to(qcz_state *s, uint64_t first_chunk, uint64_t n_chunks, void *dev_out)
+{
+    if (!s || !dev_out || first_chunk > s->nchunks || n_chunks > s->nchunks - first_chunk) return QCZ_E_INVAL;
+    if (n_chunks == 0) return QCZ_OK;
+    GateDesc d{};
+    single_kernel_chunks(s, d, n_chunks, first_chunk);
+    IOPtrs io{};
+    io.first = first_chunk;
+    io.raw_out = (double *)dev_out;
+    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(d.njobs, (uint64_t)s->grid_max));
+    HIPCHK(s, launch_readout(d, ptrs(s), io, grid, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return QCZ_OK;
+}
+
+qcz_status qcz_read_amplitudes(qcz_state *s, const uint64_t *idx, size_t k, double *out)
+{
+    if (!s || (k && (!idx || !out))) return QCZ_E_INVAL;
+    const uint64_t N = 1ull << s->n;
+    for (size_t i = 0; i < k; ++i)
+        if (idx[i] >= N) return fail(s, QCZ_E_INVAL, "amplitude index out of range");
+    std::vector<uint64_t> chunks;
+    for (size_t i = 0; i < k; ++i) chunks.push_back(idx[i] >> s->cb);
+    std::sort(chunks.begin(), chunks.end());
+    chunks.erase(std::unique(chunks.begin(), chunks.end()), chunks.end());
+    double *raw = (double *)s->scratch;
+    uint64_t *list = (uint64_t *)(s->scratch + (size_t)kScratchChunks * 8 * (size_t)s->C);
+    std::vector<double> host((size_t)kScratchChunks * (size_t)s->C);
+    for (size_t base = 0; base < chunks.size(); base += kScratchChunks) {
+        const size_t m = std::min<size_t>(kScratchChunks, chunks.size() - base);
+        HIPCHK(s, hipMemcpyAsync(list, chunks.data() + base, m * 8, hipMemcpyHostToDevice, s->stream));
+        GateDesc d{};
+        single_kernel_chunks(s, d, m, 0);
+        IOPtrs io{};
+        io.list = list;
+        io.raw_out = raw;
+        const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(d.njobs, (uint64_t)s->grid_max));
+        HIPCHK(s, launch_readout(d, ptrs(s), io, grid, s->stream));
+        HIPCHK(s, hipMemcpyAsync(host.data(), raw, m * 8 * (size_t)s->C, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        for (size_t i = 0; i < k; ++i) {
+            const uint64_t c = idx[i] >> s->cb;
+            auto it = std::lower_bound(chunks.begin() + base, chunks.begin() + base + m, c);
+            if (it == chunks.begin() + base + m || *it != c) continue;
+            const size_t pos = (size_t)(it - (chunks.begin() + base));
+            const uint64_t off = idx[i] & ((1ull << s->cb) - 1);
+            out[2 * i] = host[pos * (size_t)s->C + 2 * off];
+            out[2 * i + 1] = host[pos * (size_t)s->C + 2 * off + 1];
+        }
+    }
+    return QCZ_OK;
+}
+
+qcz_status qcz_moments(qcz_state *s, double out[3])
+{
+    if (!s || !out) return QCZ_E_INVAL;
+    GateDesc d{};
+    single_kernel_chunks(s, d, s->nchunks, 0);
+    IOPtrs io{};
+    io.partials = s->partials;
+    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(d.njobs, (uint64_t)kMomGrid));
+    HIPCHK(s, launch_moments(d, ptrs(s), io, grid, s->stream));
+    std::vector<double> h(4 * (size_t)grid);
+    HIPCHK(s, hipMemcpyAsync(h.data(), s->partials, h.size() * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    out[0] = out[1] = out[2] = 0.0;
+    for (int g = 0; g < grid; ++g) {
+        out[0] += h[4 * (size_t)g];
+        out[1] += h[4 * (size_t)g + 1];
+        out[2] += h[4 * (size_t)g + 2];
+    }
+    return QCZ_OK;
+}
+
+qcz_status qcz_sample(qcz_state *s, uint64_t seed, size_t shots, uint64_t *out_idx)
+{
+    if (!s || (shots && !out_idx)) return QCZ_E_INVAL;
+    (void)seed;
+    return fail(s, QCZ_E_STATE, "sampling is not available in this build");
+}
+
+qcz_status qcz_export_chunk(qcz_state *s, uint64_t chunk, void *host_buf, size_t cap, size_t *len)
+{
+    if (!s || !host_buf || !len || chunk >= s->nchunks) return QCZ_E_INVAL;
+    uint64_t e = 0;
+    HIPCHK(s, hipMemcpyAsync(&e, s->table + chunk, 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    const size_t size = (size_t)(e & 0xFFFF);
+    const uint64_t off = e >> 16;
+    *len = size;
+    if (size > cap) return fail(s, QCZ_E_INVAL, "export buffer too small");
+    if (off * 4 + size > s->lay.arena_bytes) return fail(s, QCZ_E_FORMAT, "chunk entry outside the arena");
+    HIPCHK(s, hipMemcpyAsync(host_buf, (uint8_t *)s->arena[s->cur] + off * 4, size, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return QCZ_OK;
+}
+
+qcz_status qcz_import_chunk(qcz_state *s, uint64_t chunk, const void *host_buf, size_t len)
+{
+    if (!s || !host_buf || chunk >= s->nchunks) return QCZ_E_INVAL;
+    if (len < 4 || len > chunk_cap_bytes(s->C)) return fail(s, QCZ_E_FORMAT, "stream length out of range");
+    const uint8_t *p = (const uint8_t *)host_buf;
+    const uint32_t hdr = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+    const uint32_t mode = hdr & 3u, lev = (hdr >> 2) & 7u;
+    if ((hdr >> 5) != 0 || lev >= (uint32_t)kLevels || mode > M_SPARSE || (mode == M_CONST2 && len != 20))
+        return fail(s, QCZ_E_FORMAT, "bad stream header");
+    const uint64_t pad = (len + 3) & ~(size_t)3;
+    if (s->bump + pad > s->lay.arena_bytes) {
+        qcz_status st = compact(s);
+        if (st != QCZ_OK) return st;
+        if (s->bump + pad > s->lay.arena_bytes) return fail(s, QCZ_E_NOMEM, "arena full");
+    }
+    uint64_t old = 0;
+    HIPCHK(s, hipMemcpyAsync(&old, s->table + chunk, 8, hipMemcpyDeviceToHost, s->stream));
+    std::vector<uint8_t> tmp(pad, 0);
+    memcpy(tmp.data(), host_buf, len);
+    HIPCHK(s, hipMemcpyAsync((uint8_t *)s->arena[s->cur] + s->bump, tmp.data(), pad, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    const uint64_t entry = ((s->bump / 4) << 16) | (uint64_t)len;
+    HIPCHK(s, hipMemcpyAsync(s->table + chunk, &entry, 8, hipMemcpyHostToDevice, s->stream));
+    const uint64_t old_pad = ((old & 0xFFFF) + 3) & ~3ull;
+    s->live = s->live + pad - old_pad;
+    s->bump += pad;
+    qcz_status st = write_header(s);
+    if (st != QCZ_OK) return st;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    clear_graphs(s);
+    return QCZ_OK;
+}
+
+qcz_status qcz_chunk_sizes(qcz_state *s, uint32_t *out_sizes)
+{
+    if (!s || !out_sizes) return QCZ_E_INVAL;
+    std::vector<uint64_t> t(s->nchunks);
+    HIPCHK(s, hipMemcpyAsync(t.data(), s->table, 8 * s->nchunks, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (uint64_t c = 0; c < s->nchunks; ++c) out_sizes[c] = (uint32_t)(t[c] & 0xFFFF);
+    return QCZ_OK;
+}
+
+qcz_status qcz_encode_chunks(const void *dev_in, uint32_t C, uint64_t n_chunks, int level, void *dev_slots,
+                             size_t slot_bytes, uint32_t *dev_sizes, void *hip_stream)
+{
+    if (!dev_in || !dev_slots || !dev_sizes) return QCZ_E_INVAL;
+    if (C < (uint32_t)kCMin || C > (uint32_t)kCMax || (C & (C - 1)) || level < 0 || level >= kLevels) return QCZ_E_INVAL;
+    if (slot_bytes < chunk_cap_bytes((int)C) || (slot_bytes & 3)) return QCZ_E_INVAL;
+    if (n_chunks == 0) return QCZ_OK;
+    GateDesc d{};
+    d.job_type = J_SINGLE;
+    d.nitems = n_chunks;
+    d.njobs = (n_chunks + 1) / 2;
+    int bits = 0;
+    while ((1ull << bits) < n_chunks) ++bits;
+    d.nchunk_bits = bits;
+    d.fixed_level = level;
+    DevPtrs P{};
+    P.C = (int)C;
+    int cb = 0;
+    while ((2u << cb) < C) ++cb;
+    P.cb = cb;
+    IOPtrs io{};
+    io.raw_in = (const double *)dev_in;
+    io.slots_out = (uint32_t *)dev_slots;
+    io.sizes_out = dev_sizes;
+    io.slot_words = slot_bytes / 4;
+    const int grid = (int)std::min<uint64_t>(d.njobs, 4096);
+    if (launch_encode_raw(d, P, io, grid, (hipStream_t)hip_stream) != hipSuccess) return QCZ_E_DEVICE;
+    return QCZ_OK;
+}
+
+qcz_status qcz_decode_chunks(const void *dev_slots, size_t slot_bytes, const uint32_t *dev_sizes, uint32_t C,
+                             uint64_t n_chunks, void *dev_out, void *hip_stream)
+{
+    if (!dev_slots || !dev_sizes || !dev_out) return QCZ_E_INVAL;
+    if (C < (uint32_t)kCMin || C > (uint32_t)kCMax || (C & (C - 1)) || (slot_bytes & 3) || slot_bytes < 4)
+        return QCZ_E_INVAL;
+    if (n_chunks == 0) return QCZ_OK;
+    GateDesc d{};
+    d.job_type = J_SINGLE;
+    d.nitems = n_chunks;
+    d.njobs = (n_chunks + 1) / 2;
+    int bits = 0;
+    while ((1ull << bits) < n_chunks) ++bits;
+    d.nchunk_bits = bits;
+    d.fixed_level = 0;
+    DevPtrs P{};
+    P.C = (int)C;
+    IOPtrs io{};
+    io.slots_in = (const uint32_t *)dev_slots;
+    io.sizes_in = dev_sizes;
+    io.slot_words = slot_bytes / 4;
+    io.raw_out = (double *)dev_out;
+    const int grid = (int)std::min<uint64_t>(d.njobs, 4096);
+    if (launch_decode_slots(d, P, io, grid, (hipStream_t)hip_stream) != hipSuccess) return QCZ_E_DEVICE;
+    return QCZ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,276 @@
+"""ctypes binding of libqcz.so (C ABI in include/qcz.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of the library.  PyTorch provides the device pool and the stream.
+Raises RuntimeError when the library has not been built; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqcz.so")
+
+MODE_LOSSLESS, MODE_FIXED, MODE_ADAPTIVE, MODE_PERBLOCK = 0, 1, 2, 3
+FLAG_GRAPH = 1
+STATUS = {0: "QCZ_OK", -1: "QCZ_E_INVAL", -2: "QCZ_E_NOMEM", -3: "QCZ_E_DEVICE", -4: "QCZ_E_FORMAT",
+          -5: "QCZ_E_STATE"}
+
+
+class QczError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_uint32), ("block_log2", ctypes.c_uint32), ("mode", ctypes.c_int32),
+                ("level", ctypes.c_int32), ("budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("batch", ctypes.c_uint32), ("grid", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint64 * 3)]
+
+
+class Footprint(ctypes.Structure):
+    _fields_ = [("compressed_bytes", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
+                ("total_bytes", ctypes.c_uint64), ("raw_bytes", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+                ("arena_used", ctypes.c_uint64), ("nchunks", ctypes.c_uint64), ("gates_applied", ctypes.c_uint64),
+                ("lossy_steps", ctypes.c_uint64), ("min_compressed", ctypes.c_uint64),
+                ("max_compressed", ctypes.c_uint64), ("compactions", ctypes.c_uint64), ("level", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("ratio", ctypes.c_double),
+                ("fidelity_lower_bound", ctypes.c_double)]
+
+
+EXPORTED = [
+    "qcz_pool_bytes_min", "qcz_create", "qcz_apply_gates", "qcz_read_amplitudes", "qcz_decode_chunks_to",
+    "qcz_moments", "qcz_sample", "qcz_footprint", "qcz_export_chunk", "qcz_import_chunk", "qcz_set_block_levels",
+    "qcz_chunk_sizes", "qcz_num_chunks", "qcz_chunk_doubles", "qcz_last_error", "qcz_destroy", "qcz_chunk_cap",
+    "qcz_encode_chunks", "qcz_decode_chunks",
+]
+
+_lib = None
+
+
+def load():
+    """Load libqcz.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libqcz.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, u64, u32, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    L.qcz_pool_bytes_min.restype = sz
+    L.qcz_pool_bytes_min.argtypes = [ctypes.POINTER(Config)]
+    L.qcz_create.restype = i32
+    L.qcz_create.argtypes = [ctypes.POINTER(Config), vp, sz, vp, ctypes.POINTER(vp)]
+    L.qcz_apply_gates.restype = i32
+    L.qcz_apply_gates.argtypes = [vp, vp, sz, ctypes.POINTER(sz)]
+    L.qcz_read_amplitudes.restype = i32
+    L.qcz_read_amplitudes.argtypes = [vp, vp, sz, vp]
+    L.qcz_decode_chunks_to.restype = i32
+    L.qcz_decode_chunks_to.argtypes = [vp, u64, u64, vp]
+    L.qcz_moments.restype = i32
+    L.qcz_moments.argtypes = [vp, vp]
+    L.qcz_sample.restype = i32
+    L.qcz_sample.argtypes = [vp, u64, sz, vp]
+    L.qcz_footprint.restype = i32
+    L.qcz_footprint.argtypes = [vp, ctypes.POINTER(Footprint)]
+    L.qcz_export_chunk.restype = i32
+    L.qcz_export_chunk.argtypes = [vp, u64, vp, sz, ctypes.POINTER(sz)]
+    L.qcz_import_chunk.restype = i32
+    L.qcz_import_chunk.argtypes = [vp, u64, vp, sz]
+    L.qcz_set_block_levels.restype = i32
+    L.qcz_set_block_levels.argtypes = [vp, vp]
+    L.qcz_chunk_sizes.restype = i32
+    L.qcz_chunk_sizes.argtypes = [vp, vp]
+    L.qcz_num_chunks.restype = u64
+    L.qcz_num_chunks.argtypes = [vp]
+    L.qcz_chunk_doubles.restype = u32
+    L.qcz_chunk_doubles.argtypes = [vp]
+    L.qcz_last_error.restype = ctypes.c_char_p
+    L.qcz_last_error.argtypes = [vp]
+    L.qcz_destroy.restype = None
+    L.qcz_destroy.argtypes = [vp]
+    L.qcz_chunk_cap.restype = sz
+    L.qcz_chunk_cap.argtypes = [u32]
+    L.qcz_encode_chunks.restype = i32
+    L.qcz_encode_chunks.argtypes = [vp, u32, u64, i32, vp, sz, vp, vp]
+    L.qcz_decode_chunks.restype = i32
+    L.qcz_decode_chunks.argtypes = [vp, sz, vp, u32, u64, vp, vp]
+    _lib = L
+    return L
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible")
+    return torch
+
+
+def chunk_cap(C: int) -> int:
+    return load().qcz_chunk_cap(C)
+
+
+def _gates(g):
+    g = np.ascontiguousarray(g)
+    if g.dtype.itemsize != 88:
+        raise ValueError("gate records must be 88-byte structs (circuits.GATE_DTYPE)")
+    return g
+
+
+class State:
+    """A compressed 2^n-amplitude state on the current HIP device."""
+
+    def __init__(self, n: int, block_log2: int, mode: int = MODE_LOSSLESS, level: int = 0, budget: int = 0,
+                 pool_bytes: int | None = None, flags: int = 0, batch: int = 0, grid: int = 0, stream=None):
+        torch = _torch()
+        L = load()
+        self._lib = L
+        self.n, self.block_log2 = n, block_log2
+        cfg = Config(n, block_log2, mode, level, budget, flags, batch, grid, 0)
+        self.cfg = cfg
+        pmin = L.qcz_pool_bytes_min(ctypes.byref(cfg))
+        if pmin == 0:
+            raise QczError(-1, "bad configuration")
+        if pool_bytes is None:
+            raw = 16 << n
+            free, _total = torch.cuda.mem_get_info()
+            pool_bytes = max(pmin, min(2 * raw + (256 << 20), int(0.85 * free)))
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        rc = L.qcz_create(ctypes.byref(cfg), self.pool.data_ptr(), int(pool_bytes), self.stream.cuda_stream,
+                          ctypes.byref(h))
+        if rc != 0:
+            raise QczError(rc, "qcz_create failed")
+        self._h = h
+        self.nchunks = L.qcz_num_chunks(h)
+        self.C = L.qcz_chunk_doubles(h)
+        self.cb = (self.C // 2).bit_length() - 1
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.qcz_destroy(self._h)
+            self._h = None
+            self.pool = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = self._lib.qcz_last_error(self._h)
+            raise QczError(rc, "%s: %s" % (what, msg.decode() if msg else ""))
+
+    # -- the hot path -----------------------------------------------------
+    def apply(self, gates) -> int:
+        """Apply gate records; returns the number applied (raises on error)."""
+        g = _gates(gates)
+        applied = ctypes.c_size_t(0)
+        rc = self._lib.qcz_apply_gates(self._h, g.ctypes.data, len(g), ctypes.byref(applied))
+        self.last_applied = applied.value
+        self._check(rc, "qcz_apply_gates (applied %d)" % applied.value)
+        return applied.value
+
+    def try_apply(self, gates):
+        """Like apply, but returns (status, applied) instead of raising."""
+        g = _gates(gates)
+        applied = ctypes.c_size_t(0)
+        rc = self._lib.qcz_apply_gates(self._h, g.ctypes.data, len(g), ctypes.byref(applied))
+        return rc, applied.value
+
+    # -- readout ----------------------------------------------------------
+    def read(self, idx) -> np.ndarray:
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64).reshape(-1))
+        out = np.zeros(2 * idx.size, dtype=np.float64)
+        self._check(self._lib.qcz_read_amplitudes(self._h, idx.ctypes.data, idx.size, out.ctypes.data),
+                    "qcz_read_amplitudes")
+        return out.view(np.complex128)
+
+    def decode_to(self, first_chunk: int, n_chunks: int, dev_tensor):
+        self._check(self._lib.qcz_decode_chunks_to(self._h, first_chunk, n_chunks, dev_tensor.data_ptr()),
+                    "qcz_decode_chunks_to")
+
+    def state(self) -> np.ndarray:
+        """Whole decoded state as complex128 (host)."""
+        torch = _torch()
+        out = torch.empty(self.nchunks * self.C, dtype=torch.float64, device="cuda")
+        self.decode_to(0, self.nchunks, out)
+        return out.cpu().numpy().view(np.complex128)
+
+    def moments(self):
+        out = np.zeros(3, dtype=np.float64)
+        self._check(self._lib.qcz_moments(self._h, out.ctypes.data), "qcz_moments")
+        return complex(out[0], out[1]), float(out[2])
+
+    def footprint(self) -> dict:
+        f = Footprint()
+        self._check(self._lib.qcz_footprint(self._h, ctypes.byref(f)), "qcz_footprint")
+        return {k: getattr(f, k) for k, _ in Footprint._fields_ if k != "reserved"}
+
+    def export_chunk(self, c: int) -> bytes:
+        cap = chunk_cap(self.C)
+        buf = np.zeros(cap, dtype=np.uint8)
+        ln = ctypes.c_size_t(0)
+        self._check(self._lib.qcz_export_chunk(self._h, c, buf.ctypes.data, cap, ctypes.byref(ln)),
+                    "qcz_export_chunk")
+        return buf[:ln.value].tobytes()
+
+    def import_chunk(self, c: int, data: bytes):
+        b = np.frombuffer(bytes(data), dtype=np.uint8).copy()
+        self._check(self._lib.qcz_import_chunk(self._h, c, b.ctypes.data, b.size), "qcz_import_chunk")
+
+    def chunk_sizes(self) -> np.ndarray:
+        out = np.zeros(self.nchunks, dtype=np.uint32)
+        self._check(self._lib.qcz_chunk_sizes(self._h, out.ctypes.data), "qcz_chunk_sizes")
+        return out
+
+    def set_block_levels(self, levels):
+        lv = np.ascontiguousarray(np.asarray(levels, dtype=np.uint8))
+        self._check(self._lib.qcz_set_block_levels(self._h, lv.ctypes.data), "qcz_set_block_levels")
+
+    def sample(self, seed: int, shots: int) -> np.ndarray:
+        out = np.zeros(shots, dtype=np.uint64)
+        self._check(self._lib.qcz_sample(self._h, seed, shots, out.ctypes.data), "qcz_sample")
+        return out
+
+
+# -- codec entry points -----------------------------------------------------
+def encode_chunks(x, level: int, stream=None):
+    """x: cuda float64 tensor [n, C].  Returns (slots uint8 [n, slot], sizes)."""
+    torch = _torch()
+    L = load()
+    n, C = x.shape
+    slot = (chunk_cap(C) + 3) & ~3
+    slots = torch.zeros((n, slot), dtype=torch.uint8, device=x.device)
+    sizes = torch.zeros(n, dtype=torch.int32, device=x.device)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = L.qcz_encode_chunks(x.contiguous().data_ptr(), C, n, level, slots.data_ptr(), slot, sizes.data_ptr(),
+                             st.cuda_stream)
+    if rc != 0:
+        raise QczError(rc, "qcz_encode_chunks")
+    st.synchronize()
+    return slots, sizes
+
+
+def decode_chunks(slots, sizes, C: int, stream=None):
+    torch = _torch()
+    L = load()
+    n, slot = slots.shape
+    out = torch.empty((n, C), dtype=torch.float64, device=slots.device)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = L.qcz_decode_chunks(slots.data_ptr(), slot, sizes.data_ptr(), C, n, out.data_ptr(), st.cuda_stream)
+    if rc != 0:
+        raise QczError(rc, "qcz_decode_chunks")
+    st.synchronize()
+    return out

@@ -1,0 +1,49 @@
+"""The C-ABI library loads and exports every function include/qcz.h declares
+(no device calls: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qcz.h")
+LIB = os.path.join(ROOT, "paper_1911_04034_amd", "libqcz.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(qcz_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("qcz_create", "qcz_apply_gates", "qcz_read_amplitudes", "qcz_footprint", "qcz_destroy",
+                     "qcz_export_chunk", "qcz_encode_chunks", "qcz_decode_chunks"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libqcz.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libqcz.so not built")
+def test_binding_lists_match_header():
+    from paper_1911_04034_amd import qcz
+    assert sorted(qcz.EXPORTED) == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libqcz.so not built")
+def test_host_only_calls():
+    from paper_1911_04034_amd import qcz
+    L = qcz.load()
+    assert L.qcz_chunk_cap(2048) == 4 + 512 + 8 * 2048
+    cfg = qcz.Config(12, 8, 0, 0, 0, 0, 0, 0, 0)
+    assert L.qcz_pool_bytes_min(ctypes.byref(cfg)) > 0
+    bad = qcz.Config(3, 8, 0, 0, 0, 0, 0, 0, 0)
+    assert L.qcz_pool_bytes_min(ctypes.byref(bad)) == 0
