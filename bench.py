@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused compressed gate-apply path on one MI355X.
+
+Workload (default "grover24+qft24"): a 24-qubit Grover search with a seeded
+marked index and floor(pi/4 * 2^12) = 3216 iterations, and a 24-qubit QFT of
+a seeded basis state; complex128 amplitudes, 2^16-amplitude blocks (chunks of
+1024 amplitudes), error bound 1e-5 on every gate.  Synthetic circuits from
+paper_1911_04034_amd.circuits; inputs are created in HBM before timing.
+
+One step = one pass of the whole workload: the full QFT-24 circuit on a fresh
+state plus --grover-iters Grover iterations continuing the Grover state
+(--grover-iters 0 spreads the full 3216-iteration search over the passes).
+
+Prints one JSON line:
+  value      = amplitudes through the fused kernel (touched chunks) per second
+               of the timed region, in GAmp/s;
+  roofline   = the fused kernel's algorithmic bytes (compressed streams read +
+               written + 24 table/undo bytes per chunk) over its event-timed
+               average duration, against 8 TB/s;
+  cpu_baseline = the CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "fused compressed gate-apply GAmp/s + compression ratio at fidelity ≥0.99"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def grover_fidelity(st, n, w, iters):
+    """|<ideal|sim>| with ideal = closed form; uses sum of amplitudes and the
+    marked amplitude (no full readout)."""
+    theta = math.asin(2.0 ** (-n / 2))
+    sign = (-1) ** iters
+    beta = sign * math.sin((2 * iters + 1) * theta)
+    alpha = sign * math.cos((2 * iters + 1) * theta) / math.sqrt((1 << n) - 1)
+    total, norm2 = st.moments()
+    aw = st.read([w])[0]
+    ov = alpha * (total - aw) + beta * aw
+    return abs(ov), math.sqrt(norm2), abs(aw)
+
+
+def qft_fidelity(st, n, x_in):
+    import torch
+    N = 1 << n
+    psi = torch.empty(st.nchunks * st.C, dtype=torch.float64, device="cuda")
+    st.decode_to(0, st.nchunks, psi)
+    psi = torch.view_as_complex(psi.view(-1, 2))
+    y = torch.arange(N, device="cuda", dtype=torch.int64)
+    rev = torch.zeros_like(y)
+    for b in range(n):
+        rev |= ((y >> b) & 1) << (n - 1 - b)
+    ph = (2 * math.pi / N) * ((x_in * rev) % N).to(torch.float64)
+    ideal = torch.polar(torch.full_like(ph, 1.0 / math.sqrt(N)), ph)
+    ov = torch.sum(torch.conj(ideal) * psi).item()
+    nrm = torch.linalg.vector_norm(psi).item()
+    return abs(ov), nrm
+
+
+def cpu_baseline(budget_s: float):
+    """The C oracle on a bounded sample: QFT-24 from its input state, gate by
+    gate, until the time budget is spent; returns amplitude-gates per second
+    over the touched chunks."""
+    from oracle import qcz_oracle as oq
+    from paper_1911_04034_amd import circuits as cc
+    n, bl, level = 24, 16, 1
+    gates = cc.qft(n, cc.qft_input(n, 2))
+    sim = oq.Sim(n, bl, oq.MODE_FIXED, level)
+    cb = sim.cb
+    ca = 1 << cb
+    # skip ahead cheaply over the X prefix and into the dense part of the circuit:
+    # the sample is the first gates whose chunks are no longer almost all zero
+    t_all = 0.0
+    amps = 0
+    k = 0
+    used = 0
+    while k < len(gates) and t_all < budget_s:
+        g = gates[k:k + 1]
+        touched = sum(1 for c in range(0, sim.nchunks) if oq.chunk_role(g, cb, c) in (1, 2, 3))
+        t0 = time.perf_counter()
+        sim.apply(g)
+        dt = time.perf_counter() - t0
+        t_all += dt
+        amps += touched * ca
+        used += 1
+        k += 1
+    return {"value": amps / t_all / 1e9 if t_all > 0 else 0.0, "unit": "GAmp/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d gates of QFT-24 (2^16-amplitude blocks, bound 1e-5) through the single-threaded "
+                      "C oracle, %.1f s" % (used, t_all)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="grover24+qft24", choices=["grover24+qft24", "grover24", "qft24"])
+    ap.add_argument("--grover-iters", type=int, default=32,
+                    help="Grover iterations per step (0: spread the full 3216 over warmup+steps)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--chunk-waves", type=int, default=0, help="wavefronts per chunk in the fused kernel (2, 4, 8)")
+    ap.add_argument("--no-timing", action="store_true", help="launch from graphs instead of timing each kernel")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the compressed gate-apply path here has no multi-GPU exchange; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1911_04034_amd import circuits as cc
+    from paper_1911_04034_amd import qcz
+
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        nb = args.calibrate_copy << 20
+        a = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": nb}), flush=True)
+        return
+    n, bl, level = 24, 16, 1
+    do_grover = "grover" in args.workload
+    do_qft = "qft" in args.workload
+    total_iters = cc.grover_optimal_iterations(n)
+    passes = args.warmup + args.steps
+    g_iters = args.grover_iters or (-(-total_iters // passes))
+    flags = qcz.FLAG_GRAPH if args.no_timing else qcz.FLAG_TIMING
+    stream = torch.cuda.Stream()
+
+    # --- inputs resident in HBM before timing -------------------------------
+    grover = qft_states = None
+    w = cc.grover_marked(n, 2)
+    it = cc.grover_iteration(n, w)
+    if do_grover:
+        grover = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=level, pool_bytes=4 << 30, flags=flags,
+                           batch=len(it), grid=args.grid, stream=stream, chunk_waves=args.chunk_waves)
+        grover.apply(cc.grover_prefix(n))
+    x_in = cc.qft_input(n, 2)
+    qft_gates = cc.qft(n, x_in)
+    if do_qft:
+        qft_states = [qcz.State(n, bl, mode=qcz.MODE_FIXED, level=level, pool_bytes=2 << 30, flags=flags,
+                                batch=256, grid=args.grid, stream=stream, chunk_waves=args.chunk_waves)
+                      for _ in range(passes)]
+    log("inputs ready: grover=%s qft=%s passes=%d grover_iters/step=%d" % (do_grover, do_qft, passes, g_iters))
+
+    iters_done = 0
+    min_ratio = float("inf")
+
+    def one_pass(p):
+        nonlocal iters_done, min_ratio
+        if do_qft:
+            qft_states[p].apply(qft_gates)
+        if do_grover:
+            k = min(g_iters, total_iters - iters_done) if total_iters > iters_done else g_iters
+            for _ in range(k):
+                grover.apply(it)
+            iters_done += k
+
+    def all_states():
+        return ([grover] if grover else []) + (qft_states or [])
+
+    for p in range(args.warmup):
+        one_pass(p)
+        log("warmup pass %d done" % p)
+    for s in all_states():
+        s.reset_stats()
+    torch.cuda.synchronize()
+    stream.synchronize()
+    t0 = time.perf_counter()
+    for p in range(args.warmup, passes):
+        one_pass(p)
+        log("timed pass %d done" % (p - args.warmup))
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+
+    # --- results ---------------------------------------------------------
+    stats = [s.stats() for s in all_states()]
+    amps = sum(x["amps_touched"] for x in stats)
+    launches = sum(x["gate_launches"] for x in stats)
+    gates_total = sum(x["gate_launches"] + x["permute_launches"] for x in stats)
+    rd = sum(x["bytes_read"] for x in stats)
+    wr = sum(x["bytes_written"] for x in stats)
+    tb = sum(x["table_bytes"] for x in stats)
+    timed = sum(x["timed_launches"] for x in stats)
+    kms = sum(x["gate_kernel_ms"] for x in stats)
+    value = amps / wall / 1e9
+
+    out_extra = {}
+    fids = []
+    if grover:
+        fp = grover.footprint()
+        f_raw, nrm, aw = grover_fidelity(grover, n, w, iters_done)
+        fids.append(f_raw / nrm if nrm > 0 else 0.0)
+        min_ratio = min(min_ratio, fp["raw_bytes"] / (fp["max_compressed"] + fp["table_bytes"]))
+        out_extra["grover24"] = {"iterations": iters_done, "marked_probability": aw ** 2, "fidelity_raw": f_raw,
+                                 "fidelity_norm": f_raw / nrm, "fidelity_lower_bound": fp["fidelity_lower_bound"],
+                                 "ratio_final": fp["ratio"],
+                                 "ratio_min": fp["raw_bytes"] / (fp["max_compressed"] + fp["table_bytes"])}
+    if qft_states:
+        s = qft_states[-1]
+        fp = s.footprint()
+        f_raw, nrm = qft_fidelity(s, n, x_in)
+        fids.append(f_raw / nrm)
+        r_min = fp["raw_bytes"] / (fp["max_compressed"] + fp["table_bytes"])
+        min_ratio = min(min_ratio, r_min)
+        out_extra["qft24"] = {"gates": len(qft_gates), "fidelity_raw": f_raw, "fidelity_norm": f_raw / nrm,
+                              "fidelity_lower_bound": fp["fidelity_lower_bound"], "ratio_final": fp["ratio"],
+                              "ratio_min": r_min}
+
+    roofline = None
+    if timed > 0:
+        avg_ms = kms / timed
+        bytes_per_launch = (rd + wr + tb) / launches if launches else 0.0
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+                    "kernel": "job_kernel<16, ARENA, ARENA, gate> (fused decode-gate-encode)",
+                    "avg_launch_us": round(avg_ms * 1e3, 3), "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
+                    "launches": timed}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_seconds)
+
+    line = {
+        "metric": METRIC, "value": round(value, 4), "unit": "GAmp/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "qubits": n, "block_amplitudes": 1 << bl, "bound": 1e-5,
+                   "grover_iterations_total": iters_done, "gates_per_step": gates_total / max(1, args.steps),
+                   "parallelism": "single GPU"},
+        "compression_ratio_min": round(min_ratio, 3),
+        "fidelity_min": round(min(fids), 6) if fids else None,
+        "logical_gamp_s": round(gates_total * (1 << n) / wall / 1e9, 3),
+        "fused_kernel_gamp_s": round(amps / (kms * 1e-3) / 1e9, 3) if kms > 0 else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "workloads": out_extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

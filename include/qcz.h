@@ -59,6 +59,8 @@ typedef enum {
 
 /* flags */
 #define QCZ_FLAG_GRAPH 1u   /* replay launch batches from captured HIP graphs when a batch repeats */
+#define QCZ_FLAG_TIMING 2u  /* time every fused gate kernel with HIP events on the state's stream
+                               (launches directly, so it takes precedence over QCZ_FLAG_GRAPH) */
 
 typedef struct {
     uint32_t n_qubits;      /* 6 .. 40 */
@@ -69,7 +71,7 @@ typedef struct {
     uint32_t flags;         /* QCZ_FLAG_* */
     uint32_t batch;         /* gates per launch batch between host checks (0: 64; at most 512) */
     uint32_t grid;          /* workgroups per gate launch (0: 4 per compute unit) */
-    uint32_t reserved0;
+    uint32_t chunk_waves;   /* wavefronts working on one chunk in the gate kernel: 2, 4 or 8 (0: 2) */
     uint64_t reserved[3];
 } qcz_config;
 
@@ -109,6 +111,21 @@ typedef struct {
     double fidelity_lower_bound; /* prod over lossy gates of (1 - delta), Sec. 3.8 Eq. (11) */
 } qcz_footprint_t;
 
+/* Work counters over the committed gates since creation or the last
+ * qcz_reset_stats (what the fused kernels moved and, with QCZ_FLAG_TIMING,
+ * how long they ran). */
+typedef struct {
+    uint64_t gate_launches;     /* fused decompress-gate-recompress kernels */
+    uint64_t permute_launches;  /* chunk-table permutations (X on chunk-index qubits) */
+    uint64_t chunks_reencoded;
+    uint64_t amps_touched;      /* chunks_reencoded * amplitudes per chunk */
+    uint64_t bytes_read;        /* compressed stream bytes read (4-byte padded) */
+    uint64_t bytes_written;     /* compressed stream bytes written (4-byte padded) */
+    uint64_t table_bytes;       /* chunk-table and undo-log bytes: 24 per re-encoded chunk */
+    uint64_t timed_launches;    /* fused kernels timed with events */
+    double gate_kernel_ms;      /* their summed event time */
+} qcz_stats_t;
+
 /* Bytes of device pool needed for a configuration (state |0..0> plus
  * metadata); larger pools leave room for less compressible states. */
 size_t qcz_pool_bytes_min(const qcz_config *cfg);
@@ -143,6 +160,9 @@ qcz_status qcz_moments(qcz_state *st, double out[3]);
 qcz_status qcz_sample(qcz_state *st, uint64_t seed, size_t shots, uint64_t *out_idx);
 
 qcz_status qcz_footprint(qcz_state *st, qcz_footprint_t *out);
+
+qcz_status qcz_get_stats(qcz_state *st, qcz_stats_t *out);
+qcz_status qcz_reset_stats(qcz_state *st);
 
 /* Copy chunk `chunk`'s stream to host memory (capacity cap); *len gets its
  * size.  QCZ_E_INVAL if cap is too small. */

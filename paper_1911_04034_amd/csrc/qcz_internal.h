@@ -15,6 +15,8 @@ constexpr int kCMin = 128;          // one value per thread at least
 constexpr int kBufWords = 4304;     // per-slot LDS words: 2*kCMax doubles, or the largest
                                     // stream plus the slack its bit reader may touch
 constexpr int kMaxBatch = 512;      // gates per launch batch (per-gate log entries)
+constexpr int kStripes = 32;        // independent arena allocators (one cache line each)
+constexpr int kMaxGrid = 8192;      // workgroups per gate launch
 constexpr uint32_t kMaxChunkBytes = 4 + 4 * (kCMax / 16) + 8 * kCMax;   // 16900
 
 enum GateKind { K_U1 = 0, K_DIAG1 = 1, K_DIAG2 = 2, K_X = 3, K_MCZ = 4 };
@@ -43,12 +45,19 @@ struct GateLog {
     uint64_t live;   // compressed bytes after the gate
     uint64_t bump;   // arena bytes used after the gate
     uint64_t reenc;  // chunks re-encoded by the gate
-    uint64_t pad;
+    uint64_t rd;     // padded stream bytes read by those jobs
+    uint64_t wr;     // padded stream bytes written
+    uint64_t pad[3];
 };
 
-// Device-resident control block (first bytes of the pool).
+// Device-resident control block (first bytes of the pool).  The arena is
+// [0, base) compacted streams, then kStripes stripes of stripe_size bytes,
+// each filled by its own bump counter so that concurrent allocations from
+// different workgroups do not contend for one address.
 struct DevState {
-    uint64_t bump;        // bytes used in the current arena
+    uint64_t base;        // start of the stripes
+    uint64_t stripe_size; // bytes per stripe
+    uint64_t nstripes;    // stripes in use (1 .. kStripes)
     uint64_t live;        // sum over chunks of the 4-byte padded size
     uint64_t arena_cap;   // bytes in one arena
     uint64_t budget;      // compressed-byte limit checked after each gate (0: none)
@@ -60,9 +69,15 @@ struct DevState {
     int32_t corrupt;      // a chunk entry pointed outside the arena
     uint32_t done;        // finished workgroups of the running kernel
     uint32_t pad0;
-    uint64_t reenc_cur;   // chunks re-encoded by the running gate
-    uint64_t pad1[6];
+    uint64_t pad1[7];
+    // -- below: not rewritten by the host header update --
+    uint64_t stripe[kStripes][16];   // bytes used per stripe (first word of a 128-byte line)
     GateLog log[kMaxBatch];
+};
+
+// per-workgroup partial sums of a gate launch (no same-address atomics)
+struct WgPart {
+    uint64_t delta, reenc, rd, wr;
 };
 
 // Pointers of one state, passed by value to every kernel.
@@ -73,6 +88,7 @@ struct DevPtrs {
     uint64_t *undo;             // per enumerated position: previous table entry
     const uint8_t *block_level; // per block
     DevState *ds;
+    WgPart *wgp;                // [kMaxGrid]
     int32_t cb;                 // log2 amplitudes per chunk
     int32_t C;                  // doubles per chunk
     uint64_t nchunks;
@@ -95,7 +111,7 @@ struct IOPtrs {
 inline uint32_t chunk_cap_bytes(int C) { return 4u + 4u * (uint32_t)((C + 15) / 16) + 8u * (uint32_t)C; }
 
 // Host launchers (qcz_kernels.hip).
-hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);
+hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st, int wpg);
 hipError_t launch_permute(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);
 hipError_t launch_rollback(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);
 hipError_t launch_encode_raw(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);

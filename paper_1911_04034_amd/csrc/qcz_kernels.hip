@@ -31,220 +31,303 @@ enum { SRC_ARENA = 0, SRC_RAW = 1, SRC_SLOTS = 2 };
 enum { DST_ARENA = 0, DST_RAW = 1, DST_SLOTS = 2, DST_MOMENTS = 3 };
 
 // ---------------------------------------------------------------------------
-// bit helpers
+// bit helpers.  A value is handled as its two 32-bit words (hi, lo).  At every
+// lossy level Sig_Bit_Count <= 29, so a truncated value lives entirely in its
+// high word; the leading-byte code looks at the top three bytes only, which
+// are high-word bits as well.  Only lossless chunks carry low words.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t d2u(double x) { return (uint64_t)__double_as_longlong(x); }
 __device__ __forceinline__ double u2d(uint64_t b) { return __longlong_as_double((long long)b); }
 
-__device__ __forceinline__ uint64_t trunc_bits(uint64_t b, int K)
+__device__ __forceinline__ uint32_t lead_bytes(uint32_t cur_hi, uint32_t prev_hi)
 {
-    return K >= 64 ? b : (b & ~((1ull << (64 - K)) - 1ull));
+    const uint32_t L = (uint32_t)__clz((int)(cur_hi ^ prev_hi)) >> 3;  // 32 leading zeros -> 4
+    return L < 3u ? L : 3u;
 }
 
-// identical leading bytes of two values, most significant first, capped at 3
-__device__ __forceinline__ int lead_bytes(uint64_t cur, uint64_t prev)
+__device__ __forceinline__ uint32_t resid_bits(int K, uint32_t L)
 {
-    uint64_t d = cur ^ prev;
-    if (d == 0) return 3;
-    int L = __clzll((long long)d) >> 3;
-    return L < 3 ? L : 3;
+    const int r = K - 8 * (int)L;
+    return r > 0 ? (uint32_t)r : 0u;
 }
 
-__device__ __forceinline__ int resid_bits(int K, int L)
-{
-    int r = K - 8 * L;
-    return r > 0 ? r : 0;
-}
+__device__ __forceinline__ uint32_t top_mask32(uint32_t L) { return L ? (~0u << (32u - 8u * L)) : 0u; }
+__device__ __forceinline__ uint32_t low_mask32(uint32_t r) { return r >= 32u ? ~0u : ((1u << r) - 1u); }
+__device__ __forceinline__ uint32_t sig_mask_hi(int K) { return K >= 32 ? ~0u : ~((1u << (32 - K)) - 1u); }
 
-__device__ __forceinline__ uint64_t top_mask(int nbits)  // 0 <= nbits <= 24
+__device__ __forceinline__ bool subnormal(uint32_t h, uint32_t l)
 {
-    return nbits <= 0 ? 0ull : (~0ull << (64 - nbits));
-}
-
-__device__ __forceinline__ bool subnormal(uint64_t b)
-{
-    return ((b >> 52) & 0x7FFull) == 0 && (b & 0xFFFFFFFFFFFFFull) != 0;
+    return ((h >> 20) & 0x7FFu) == 0 && ((h & 0xFFFFFu) | l) != 0;
 }
 
 __device__ __forceinline__ int clampw(int i) { return i < kBufWords - 1 ? i : kBufWords - 1; }
 
-// r bits (r <= 64) at bit offset o of the word stream starting at b[base]
-__device__ __forceinline__ uint64_t read_bits(const uint32_t *b, int base, uint32_t o, int r)
+// bits [sh, sh+32) of the 64-bit word pair (hi:lo)
+__device__ __forceinline__ uint32_t fshr(uint32_t hi, uint32_t lo, uint32_t sh)
 {
-    if (r == 0) return 0;
-    int wi = base + (int)(o >> 5);
-    int sh = (int)(o & 31);
-    uint64_t w0 = b[clampw(wi)], w1 = b[clampw(wi + 1)], w2 = b[clampw(wi + 2)];
-    uint64_t v = (w0 | (w1 << 32)) >> sh;
-    if (sh) v |= w2 << (64 - sh);
-    return r >= 64 ? v : (v & ((1ull << r) - 1ull));
+    return __builtin_amdgcn_alignbit(hi, lo, sh);
 }
 
-// ---------------------------------------------------------------------------
-// group scans: a group is the 128 threads (two wavefronts) of one chunk slot
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void wave_scan3(uint32_t &a, uint32_t &b, uint32_t &c)
+// Workgroup barrier that orders LDS only: pending global stores and loads
+// are not waited for (no thread of the workgroup reads them back).
+__device__ __forceinline__ void lds_barrier()
 {
-    const int lane = threadIdx.x & 63;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Copy `words` words from global memory into LDS with eight loads in flight
+// per thread (one HBM round trip per 1024 words).
+template <int G>
+__device__ __forceinline__ void stage_words(uint32_t *dst, const uint32_t *src, uint32_t words, int lt)
+{
+    for (uint32_t base = (uint32_t)lt; base < words; base += 8u * G) {
+        uint32_t v[8];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t ya = __shfl_up(a, d, 64), yb = __shfl_up(b, d, 64), yc = __shfl_up(c, d, 64);
-        if (lane >= d) { a += ya; b += yb; c += yc; }
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t w = base + (uint32_t)u * G;
+            v[u] = (w < words) ? __builtin_nontemporal_load(src + w) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t w = base + (uint32_t)u * G;
+            if (w < words) dst[w] = v[u];
+        }
     }
 }
 
-// exclusive sums of (v0, v1, v2) over the group; totals in tot
-__device__ void group_scan3(uint32_t v0, uint32_t v1, uint32_t v2, uint32_t *sh, uint32_t ex[3], uint32_t tot[3])
+// ---------------------------------------------------------------------------
+// scans.  A group is the 128 threads (two wavefronts) of one chunk slot.
+// Wavefront scans use DPP row shifts (1, 2, 4, 8) and row broadcasts (15,
+// 31); the two wavefronts of a group meet through LDS with one barrier.
+// Each call site owns its LDS slot, so no second barrier is needed before the
+// slot is reused (the next use is a job later, many barriers away).
+// ---------------------------------------------------------------------------
+template <int CTRL, int RMASK>
+__device__ __forceinline__ uint32_t dpp0(uint32_t x)
 {
-    uint32_t a = v0, b = v1, c = v2;
-    wave_scan3(a, b, c);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 63) { sh[4 * w] = a; sh[4 * w + 1] = b; sh[4 * w + 2] = c; }
-    __syncthreads();
-    const int w0 = w & ~1;
-    const bool odd = (w & 1) != 0;
-    uint32_t p0 = sh[4 * w0], p1 = sh[4 * w0 + 1], p2 = sh[4 * w0 + 2];
-    uint32_t q0 = sh[4 * w0 + 4], q1 = sh[4 * w0 + 5], q2 = sh[4 * w0 + 6];
-    ex[0] = (odd ? p0 : 0) + a - v0;
-    ex[1] = (odd ? p1 : 0) + b - v1;
-    ex[2] = (odd ? p2 : 0) + c - v2;
-    tot[0] = p0 + q0;
-    tot[1] = p1 + q1;
-    tot[2] = p2 + q2;
-    __syncthreads();
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, RMASK, 0xF, false);
 }
 
-// "last writer" combine of per-byte carries: bits 24..26 flag bytes 0..2,
-// bits 8j..8j+7 hold byte j; the later operand wins where it is defined.
+__device__ __forceinline__ uint32_t wave_incl_add(uint32_t x)
+{
+    x += dpp0<0x111, 0xF>(x);
+    x += dpp0<0x112, 0xF>(x);
+    x += dpp0<0x114, 0xF>(x);
+    x += dpp0<0x118, 0xF>(x);
+    x += dpp0<0x142, 0xA>(x);
+    x += dpp0<0x143, 0xC>(x);
+    return x;
+}
+
+// exclusive sum over the group (WPG wavefronts), and the group total
+template <int WPG>
+__device__ __forceinline__ void gscan_add(uint32_t v, uint32_t *slot, uint32_t &ex, uint32_t &tot)
+{
+    const uint32_t x = wave_incl_add(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) slot[w] = x;
+    lds_barrier();
+    const int g0 = w - (w % WPG);
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < WPG; ++i) {
+        const uint32_t t = slot[g0 + i];
+        before += (g0 + i < w) ? t : 0u;
+        all += t;
+    }
+    ex = before + x - v;
+    tot = all;
+}
+
+// Per-byte carry of the leading bytes: bits 31..8 hold bytes 0..2 of a high
+// word (most significant first), bits 0..2 flag which of them are defined.
+// carry_op(a, b): b is later and wins where it is defined.
 __device__ __forceinline__ uint32_t carry_op(uint32_t a, uint32_t b)
 {
-    uint32_t bm = (b >> 24) & 7u;
-    uint32_t sel = ((bm & 1u) ? 0xFFu : 0u) | ((bm & 2u) ? 0xFF00u : 0u) | ((bm & 4u) ? 0xFF0000u : 0u);
-    return ((a | b) & 0x07000000u) | (b & sel) | (a & ~sel & 0xFFFFFFu);
+    const uint32_t sel = ((b & 1u) ? 0xFF000000u : 0u) | ((b & 2u) ? 0x00FF0000u : 0u) | ((b & 4u) ? 0x0000FF00u : 0u);
+    return (b & sel) | (a & ~sel & 0xFFFFFF00u) | ((a | b) & 7u);
 }
 
 // exclusive carry scan over the group (identity 0)
-__device__ uint32_t group_scan_carry(uint32_t v, uint32_t *sh)
+template <int WPG>
+__device__ __forceinline__ uint32_t gscan_carry(uint32_t v, uint32_t *slot)
 {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint32_t x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t y = __shfl_up(x, d, 64);
-        if (lane >= d) x = carry_op(y, x);
-    }
-    uint32_t e = __shfl_up(x, 1, 64);
+    x = carry_op(dpp0<0x111, 0xF>(x), x);
+    x = carry_op(dpp0<0x112, 0xF>(x), x);
+    x = carry_op(dpp0<0x114, 0xF>(x), x);
+    x = carry_op(dpp0<0x118, 0xF>(x), x);
+    x = carry_op(dpp0<0x142, 0xA>(x), x);
+    x = carry_op(dpp0<0x143, 0xC>(x), x);
+    uint32_t e = (uint32_t)__shfl_up((int)x, 1, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) e = 0;
-    if (lane == 63) sh[4 * w + 3] = x;
-    __syncthreads();
-    if (w & 1) e = carry_op(sh[4 * (w - 1) + 3], e);
-    __syncthreads();
-    return e;
+    if (lane == 63) slot[w] = x;
+    lds_barrier();
+    const int g0 = w - (w % WPG);
+    uint32_t in = 0;
+#pragma unroll
+    for (int i = 0; i < WPG - 1; ++i)
+        if (g0 + i < w) in = carry_op(in, slot[g0 + i]);
+    return carry_op(in, e);
 }
 
-// exclusive "last value with flag" scan over the group
-__device__ void group_scan_last(bool has, uint64_t val, uint32_t *sh, bool &ehas, uint64_t &eval)
+// Encoder scan: exclusive sums of (rp, cnt), totals of (bad, rp, cnt), and
+// the last nonzero high word before this thread (flag f, value v).
+template <int WPG>
+__device__ __forceinline__ void gscan_enc(uint32_t bad, uint32_t rp, uint32_t cnt, uint32_t f, uint32_t v,
+                                          uint32_t *slot, uint32_t &ex_rp, uint32_t &ex_cnt, uint32_t tot[3],
+                                          uint32_t &in_f, uint32_t &in_v)
 {
+    uint32_t a = bad, b = rp, c = cnt;
+#define QCZ_ENC_STEP(CTRL, RM)                                                   \
+    {                                                                            \
+        a += dpp0<CTRL, RM>(a);                                                  \
+        b += dpp0<CTRL, RM>(b);                                                  \
+        c += dpp0<CTRL, RM>(c);                                                  \
+        const uint32_t yf = dpp0<CTRL, RM>(f), yv = dpp0<CTRL, RM>(v);           \
+        v = f ? v : yv;                                                          \
+        f |= yf;                                                                 \
+    }
+    QCZ_ENC_STEP(0x111, 0xF)
+    QCZ_ENC_STEP(0x112, 0xF)
+    QCZ_ENC_STEP(0x114, 0xF)
+    QCZ_ENC_STEP(0x118, 0xF)
+    QCZ_ENC_STEP(0x142, 0xA)
+    QCZ_ENC_STEP(0x143, 0xC)
+#undef QCZ_ENC_STEP
+    uint32_t ef = (uint32_t)__shfl_up((int)f, 1, 64), ev = (uint32_t)__shfl_up((int)v, 1, 64);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint32_t h = has ? 1u : 0u, lo = (uint32_t)val, hi = (uint32_t)(val >> 32);
+    if (lane == 0) ef = 0;
+    if (lane == 63) {
+        slot[8 * w] = a;
+        slot[8 * w + 1] = b;
+        slot[8 * w + 2] = c;
+        slot[8 * w + 3] = f;
+        slot[8 * w + 4] = v;
+    }
+    lds_barrier();
+    const int g0 = w - (w % WPG);
+    uint32_t t0 = 0, t1 = 0, t2 = 0, b1 = 0, b2 = 0, pf = 0, pv = 0;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t yh = __shfl_up(h, d, 64), ylo = __shfl_up(lo, d, 64), yhi = __shfl_up(hi, d, 64);
-        if (lane >= d && !h) { h = yh; lo = ylo; hi = yhi; }
+    for (int i = 0; i < WPG; ++i) {
+        const uint32_t *q = slot + 8 * (g0 + i);
+        const bool earlier = g0 + i < w;
+        t0 += q[0];
+        t1 += q[1];
+        t2 += q[2];
+        b1 += earlier ? q[1] : 0u;
+        b2 += earlier ? q[2] : 0u;
+        pv = (earlier && q[3]) ? q[4] : pv;
+        pf |= earlier ? q[3] : 0u;
     }
-    uint32_t eh = __shfl_up(h, 1, 64), elo = __shfl_up(lo, 1, 64), ehi = __shfl_up(hi, 1, 64);
-    if (lane == 0) eh = 0;
-    if (lane == 63) { sh[16 + 4 * w] = h; sh[16 + 4 * w + 1] = lo; sh[16 + 4 * w + 2] = hi; }
-    __syncthreads();
-    if ((w & 1) && !eh) {
-        eh = sh[16 + 4 * (w - 1)];
-        elo = sh[16 + 4 * (w - 1) + 1];
-        ehi = sh[16 + 4 * (w - 1) + 2];
-    }
-    __syncthreads();
-    ehas = eh != 0;
-    eval = ((uint64_t)ehi << 32) | elo;
+    tot[0] = t0;
+    tot[1] = t1;
+    tot[2] = t2;
+    ex_rp = b1 + b - rp;
+    ex_cnt = b2 + c - cnt;
+    in_f = ef ? ef : pf;
+    in_v = ef ? ev : pv;
 }
 
 // ---------------------------------------------------------------------------
 // decode: the chunk staged in b[] -> the V values this thread owns
 // ---------------------------------------------------------------------------
-template <int V>
-__device__ void decode_group(const uint32_t *b, bool active, int C, int lt, uint32_t *sh, uint64_t (&t)[V])
+__device__ __forceinline__ int codes_word0(int mode, int C) { return mode == M_SPARSE ? 1 + ((C + 31) >> 5) : 1; }
+
+// `hdr` is the stream header (an inactive slot passes a CONST2 header and
+// active = false); `any_sparse` is workgroup-uniform.
+template <int V, int WPG>
+__device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool any_sparse, int C, int lt,
+                             uint32_t *slotA, uint32_t *slotB, uint32_t *slotC, uint32_t (&th)[V], uint32_t (&tl)[V])
 {
-    const uint32_t hdr = active ? b[0] : (uint32_t)M_CONST2;
     const int mode = (int)(hdr & 3u);
     int lev = (int)((hdr >> 2) & 7u);
     if (lev >= kLevels) lev = 0;
     const int K = kSig[lev];
     const int first = lt * V;
-    const uint32_t vmask = (V >= 32) ? 0xFFFFFFFFu : ((1u << V) - 1u);
+    const uint32_t vmask = (V >= 32) ? ~0u : ((1u << V) - 1u);
     uint32_t stored = 0;
     if (mode == M_PACK) stored = vmask;
     else if (mode == M_SPARSE) stored = (b[clampw(1 + (first >> 5))] >> (first & 31)) & vmask;
-    const uint32_t cnt = __popc(stored);
-
-    uint32_t ex[3], tot[3];
-    group_scan3(cnt, 0, 0, sh, ex, tot);
-    const uint32_t rank0 = ex[0], nnz = tot[0];
-    const int codes_w0 = (mode == M_SPARSE) ? 1 + ((C + 31) >> 5) : 1;
-    const int res_w0 = codes_w0 + (int)((nnz + 15) >> 4);
-
-    uint64_t cw = 0;
-    if (cnt) {
-        uint32_t bit = 2 * rank0;
-        int wi = codes_w0 + (int)(bit >> 5);
-        uint64_t lo = b[clampw(wi)], hi = b[clampw(wi + 1)];
-        cw = ((hi << 32) | lo) >> (bit & 31);
+    uint32_t rank0 = (uint32_t)first, nnz = (uint32_t)C;
+    if (any_sparse) {
+        uint32_t ex, tot;
+        gscan_add<WPG>(__popc(stored), slotA, ex, tot);
+        if (mode == M_SPARSE) { rank0 = ex; nnz = tot; }
     }
-    int Lk[V];
-    uint32_t rsum = 0;
+    const int cw0 = codes_word0(mode, C);
+    const int res_w0 = cw0 + (int)((nnz + 15u) >> 4);
+    const uint32_t cbit = 2u * rank0;
+    const uint32_t cw = fshr(b[clampw(cw0 + (int)(cbit >> 5) + 1)], b[clampw(cw0 + (int)(cbit >> 5))], cbit & 31u);
+
+    // codes by position
+    uint32_t Lpos = 0, rsum = 0;
 #pragma unroll
     for (int k = 0; k < V; ++k) {
-        uint32_t lr = __popc(stored & ((1u << k) - 1u));
-        Lk[k] = (int)((cw >> (2 * lr)) & 3u);
-        if ((stored >> k) & 1u) rsum += (uint32_t)resid_bits(K, Lk[k]);
+        const uint32_t st = (stored >> k) & 1u;
+        const uint32_t L = (cw >> (2u * __popc(stored & ((1u << k) - 1u)))) & 3u;
+        Lpos |= (st ? L : 0u) << (2 * k);
+        rsum += st ? resid_bits(K, L) : 0u;
     }
-    group_scan3(rsum, 0, 0, sh, ex, tot);
-    uint32_t o = ex[0];
+    uint32_t o, rtot;
+    gscan_add<WPG>(rsum, slotB, o, rtot);
 
     uint32_t carry = 0;
+    if (K < 64) {
+        const uint32_t up = (uint32_t)(32 - K);
 #pragma unroll
-    for (int k = 0; k < V; ++k) {
-        uint64_t p = 0;
-        if ((stored >> k) & 1u) {
-            int r = resid_bits(K, Lk[k]);
-            uint64_t R = read_bits(b, res_w0, o, r);
-            o += (uint32_t)r;
-            p = (K >= 64) ? R : (R << (64 - K));
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                if (Lk[k] <= j) {
-                    carry = (carry & ~(0xFFu << (8 * j))) | ((uint32_t)((p >> (56 - 8 * j)) & 0xFFu) << (8 * j));
-                    carry |= 1u << (24 + j);
-                }
-            }
+        for (int k = 0; k < V; ++k) {
+            const uint32_t st = (stored >> k) & 1u;
+            const uint32_t L = (Lpos >> (2 * k)) & 3u;
+            const uint32_t r = st ? resid_bits(K, L) : 0u;
+            const int wi = res_w0 + (int)(o >> 5);
+            const uint32_t R = fshr(b[clampw(wi + 1)], b[clampw(wi)], o & 31u) & low_mask32(r);
+            const uint32_t p = R << up;
+            o += r;
+            th[k] = p;
+            tl[k] = 0u;
+            const uint32_t def = st ? ((7u << L) & 7u) : 0u;
+            carry = carry_op(carry, (p & 0xFFFFFF00u) | def);
         }
-        t[k] = p;
-    }
-    uint32_t inc = carry_op(0x07000000u, group_scan_carry(carry, sh));
-    uint64_t prev = ((uint64_t)(inc & 0xFFu) << 56) | ((uint64_t)((inc >> 8) & 0xFFu) << 48) |
-                    ((uint64_t)((inc >> 16) & 0xFFu) << 40);
-    if (mode == M_CONST2) {
-        uint64_t t0 = active ? ((uint64_t)b[1] | ((uint64_t)b[2] << 32)) : 0ull;
-        uint64_t t1 = active ? ((uint64_t)b[3] | ((uint64_t)b[4] << 32)) : 0ull;
-#pragma unroll
-        for (int k = 0; k < V; ++k) t[k] = ((first + k) & 1) ? t1 : t0;
     } else {
 #pragma unroll
         for (int k = 0; k < V; ++k) {
-            if ((stored >> k) & 1u) {
-                uint64_t v = (prev & top_mask(8 * Lk[k])) | t[k];
-                t[k] = v;
-                prev = v;
-            } else {
-                t[k] = 0;
-            }
+            const uint32_t st = (stored >> k) & 1u;
+            const uint32_t L = (Lpos >> (2 * k)) & 3u;
+            const uint32_t r = st ? 64u - 8u * L : 0u;
+            const int wi = res_w0 + (int)(o >> 5);
+            const uint32_t w0 = b[clampw(wi)], w1 = b[clampw(wi + 1)], w2 = b[clampw(wi + 2)];
+            const uint32_t Rl = r ? fshr(w1, w0, o & 31u) : 0u;
+            const uint32_t Rh = fshr(w2, w1, o & 31u) & (r ? low_mask32(r - 32u) : 0u);
+            o += r;
+            th[k] = Rh;
+            tl[k] = Rl;
+            const uint32_t def = st ? ((7u << L) & 7u) : 0u;
+            carry = carry_op(carry, (Rh & 0xFFFFFF00u) | def);
+        }
+    }
+    // the value before the chunk is 0: every leading byte defined as zero
+    uint32_t prev = carry_op(7u, gscan_carry<WPG>(carry, slotC)) & 0xFFFFFF00u;
+    if (mode == M_CONST2) {
+        const uint32_t c0l = active ? b[1] : 0u, c0h = active ? b[2] : 0u;
+        const uint32_t c1l = active ? b[3] : 0u, c1h = active ? b[4] : 0u;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const bool odd = ((first + k) & 1) != 0;
+            th[k] = odd ? c1h : c0h;
+            tl[k] = odd ? c1l : c0l;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const uint32_t st = (stored >> k) & 1u;
+            const uint32_t v = (prev & top_mask32((Lpos >> (2 * k)) & 3u)) | th[k];
+            th[k] = st ? v : 0u;
+            tl[k] = st ? tl[k] : 0u;
+            prev = st ? v : prev;
         }
     }
 }
@@ -254,124 +337,146 @@ __device__ void decode_group(const uint32_t *b, bool active, int C, int lt, uint
 // ---------------------------------------------------------------------------
 template <int V>
 struct EncPlan {
-    uint64_t t[V];      // truncated values
-    uint32_t codes;     // PACK codes of my positions (2 bits each)
-    uint32_t scodes;    // SPARSE codes of my nonzero positions, in rank order
-    uint32_t nzm;       // my nonzero positions
-    uint32_t pack_off;  // bit offset of my PACK residuals
-    uint32_t sp_off;    // bit offset of my SPARSE residuals
-    uint32_t rank0;     // rank of my first nonzero
+    uint32_t th[V], tl[V];  // truncated values
+    uint32_t codes;         // PACK codes by position (2 bits each)
+    uint32_t scodes;        // SPARSE codes of my nonzero values, rank order
+    uint32_t nzm;           // my nonzero positions
+    uint32_t pack_off;      // bit offset of my PACK residuals
+    uint32_t sp_off;        // bit offset of my SPARSE residuals
+    uint32_t rank0;         // rank of my first nonzero value
     uint32_t nnz;
-    uint64_t c0, c1;    // CONST2 values (truncated values 0 and 1)
+    uint32_t c0h, c0l, c1h, c1l;  // values 0 and 1 (CONST2)
     int mode, lev, K;
     uint32_t size;
 };
 
-template <int V>
-__device__ void encode_plan(const uint64_t (&x)[V], uint64_t xprev, uint64_t x0, uint64_t x1, int lev_req,
-                            bool active, int C, int lt, uint32_t *sh, EncPlan<V> &e)
+// Plan the stream of one chunk.  x: my values (hi, lo); xprev_hi: high word of
+// the value before mine; x0/x1: values 0 and 1 of the chunk.  `sub` is the
+// group's subnormal flag.  Contains barriers: every thread calls it.
+template <int V, int WPG>
+__device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], uint32_t xprev_hi, uint64_t x0,
+                            uint64_t x1, int lev_req, bool active, bool sub, int C, int lt, uint32_t *slotB,
+                            uint32_t *slotC, EncPlan<V> &e)
 {
     const int first = lt * V;
-    uint32_t sub = 0;
-#pragma unroll
-    for (int k = 0; k < V; ++k) sub |= (active && subnormal(x[k])) ? 1u : 0u;
-    uint32_t ex[3], tot[3];
-    group_scan3(sub, 0, 0, sh, ex, tot);
-    const int lev = (tot[0] != 0) ? 0 : lev_req;       // a chunk with a subnormal is kept lossless
+    const int lev = sub ? 0 : lev_req;  // a chunk with a subnormal is kept lossless
     const int K = kSig[lev];
-    const uint64_t tp = trunc_bits(xprev, K), t0 = trunc_bits(x0, K), t1 = trunc_bits(x1, K);
+    const uint32_t mh = sig_mask_hi(K);
+    const bool lossless = K >= 64;
+    e.c0h = (uint32_t)(x0 >> 32) & mh;
+    e.c0l = lossless ? (uint32_t)x0 : 0u;
+    e.c1h = (uint32_t)(x1 >> 32) & mh;
+    e.c1l = lossless ? (uint32_t)x1 : 0u;
 
-    uint32_t bad2 = 0, rp = 0, nzm = 0, codes = 0;
-    uint64_t prev = tp, lastnz = 0;
+    uint32_t bad = 0, rp = 0, nzm = 0, codes = 0, lf = 0, lv = 0;
+    uint32_t prev = xprev_hi & mh;
 #pragma unroll
     for (int k = 0; k < V; ++k) {
-        uint64_t tk = active ? trunc_bits(x[k], K) : 0ull;
-        e.t[k] = tk;
-        bad2 += (tk != (((first + k) & 1) ? t1 : t0)) ? 1u : 0u;
-        int L = lead_bytes(tk, prev);
-        codes |= (uint32_t)L << (2 * k);
-        rp += (uint32_t)resid_bits(K, L);
-        prev = tk;
-        if (tk != 0) { nzm |= 1u << k; lastnz = tk; }
+        const uint32_t h = active ? (xh[k] & mh) : 0u;
+        const uint32_t l = (active && lossless) ? xl[k] : 0u;
+        e.th[k] = h;
+        e.tl[k] = l;
+        const bool odd = ((first + k) & 1) != 0;
+        bad += (h != (odd ? e.c1h : e.c0h) || l != (odd ? e.c1l : e.c0l)) ? 1u : 0u;
+        const uint32_t L = lead_bytes(h, prev);
+        codes |= L << (2 * k);
+        rp += resid_bits(K, L);
+        prev = h;
+        const bool nz = (h | l) != 0;
+        nzm |= nz ? (1u << k) : 0u;
+        lv = nz ? h : lv;
+        lf |= nz ? 1u : 0u;
     }
     const uint32_t cnt = __popc(nzm);
-    group_scan3(bad2, rp, cnt, sh, ex, tot);
+    uint32_t tot[3], in_f, in_v;
+    gscan_enc<WPG>(bad, rp, cnt, lf, lv, slotB, e.pack_off, e.rank0, tot, in_f, in_v);
     const bool const2 = tot[0] == 0;
     const uint32_t RP = tot[1], NNZ = tot[2];
-    e.pack_off = ex[1];
-    e.rank0 = ex[2];
     e.nnz = NNZ;
-    bool ph;
-    uint64_t pv;
-    group_scan_last(cnt != 0, lastnz, sh, ph, pv);
-    uint64_t sprev = ph ? pv : 0ull;
-    uint32_t rs = 0, scodes = 0, j = 0;
+    // SPARSE can only win when the chunk has zeros; with none its body equals
+    // PACK's plus the bitmap.  The decision must be uniform over the workgroup.
+    const int w = threadIdx.x >> 6;
+    const int og0 = (w < WPG) ? WPG : 0;   // first wavefront of the other slot's group
+    uint32_t other_bad = 0, other_nnz = 0;
 #pragma unroll
-    for (int k = 0; k < V; ++k) {
-        if ((nzm >> k) & 1u) {
-            int L = lead_bytes(e.t[k], sprev);
-            scodes |= (uint32_t)L << (2 * j);
-            ++j;
-            rs += (uint32_t)resid_bits(K, L);
-            sprev = e.t[k];
-        }
+    for (int i = 0; i < WPG; ++i) {
+        other_bad += slotB[8 * (og0 + i)];
+        other_nnz += slotB[8 * (og0 + i) + 2];
     }
-    group_scan3(rs, 0, 0, sh, ex, tot);
-    e.sp_off = ex[0];
-    const uint32_t RS = tot[0];
+    const bool need_me = !const2 && NNZ < (uint32_t)C;
+    const bool need_other = other_bad != 0 && other_nnz < (uint32_t)C;
+    uint32_t RS = 0;
+    e.scodes = 0;
+    e.sp_off = 0;
+    if (need_me || need_other) {
+        uint32_t sprev = in_f ? in_v : 0u;
+        uint32_t rs = 0, scodes = 0, j = 0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const bool nz = ((nzm >> k) & 1u) != 0;
+            const uint32_t L = lead_bytes(e.th[k], sprev);
+            scodes |= nz ? (L << (2 * j)) : 0u;
+            j += nz ? 1u : 0u;
+            rs += nz ? resid_bits(K, L) : 0u;
+            sprev = nz ? e.th[k] : sprev;
+        }
+        e.scodes = scodes;
+        gscan_add<WPG>(rs, slotC, e.sp_off, RS);
+    }
     const uint32_t pack_size = 4u + 4u * (uint32_t)((C + 15) / 16) + (RP + 7u) / 8u;
     const uint32_t sparse_size = 4u + 4u * (uint32_t)((C + 31) / 32) + 4u * ((NNZ + 15u) / 16u) + (RS + 7u) / 8u;
-    e.c0 = t0;
-    e.c1 = t1;
     e.codes = codes;
-    e.scodes = scodes;
     e.nzm = nzm;
     e.lev = lev;
     e.K = K;
     if (const2) { e.mode = M_CONST2; e.size = 20; }
-    else if (sparse_size < pack_size) { e.mode = M_SPARSE; e.size = sparse_size; }
+    else if (need_me && sparse_size < pack_size) { e.mode = M_SPARSE; e.size = sparse_size; }
     else { e.mode = M_PACK; e.size = pack_size; }
 }
 
-// Bit writer into LDS words: the first and the last word a thread touches
-// may be shared with its neighbours (atomic OR); words in between are its own.
-struct BitOut {
-    uint32_t *w;
-    int wi;
-    int nb;
-    uint64_t acc;
-    bool first;
-    __device__ void init(uint32_t *base, uint32_t bitoff) { w = base; wi = (int)(bitoff >> 5); nb = (int)(bitoff & 31); acc = 0; first = true; }
-    __device__ __forceinline__ void put32(uint64_t v, int n)  // n <= 32, nb < 32 on entry
-    {
-        if (n == 0) return;
-        acc |= v << nb;
-        nb += n;
-        if (nb >= 32) {
-            int idx = clampw(wi);
-            if (first) atomicOr(&w[idx], (uint32_t)acc);
-            else w[idx] = (uint32_t)acc;
-            first = false;
-            ++wi;
-            acc >>= 32;
-            nb -= 32;
+// OR an r-bit field (r <= 32) into the word stream at bit offset o
+__device__ __forceinline__ void or_bits32(uint32_t *b, int base, uint32_t o, uint32_t R, uint32_t r)
+{
+    if (r == 0) return;
+    const uint64_t x = (uint64_t)R << (o & 31u);
+    const int wi = base + (int)(o >> 5);
+    atomicOr(&b[clampw(wi)], (uint32_t)x);
+    if ((uint32_t)(x >> 32)) atomicOr(&b[clampw(wi + 1)], (uint32_t)(x >> 32));
+}
+
+// OR a 64-bit field (Rh:Rl, r bits, 32 < r <= 64) into the stream
+__device__ __forceinline__ void or_bits64(uint32_t *b, int base, uint32_t o, uint32_t Rh, uint32_t Rl)
+{
+    const uint32_t sh = o & 31u;
+    const uint64_t xl = (uint64_t)Rl << sh, xh = (uint64_t)Rh << sh;
+    const int wi = base + (int)(o >> 5);
+    atomicOr(&b[clampw(wi)], (uint32_t)xl);
+    atomicOr(&b[clampw(wi + 1)], (uint32_t)(xl >> 32) | (uint32_t)xh);
+    if ((uint32_t)(xh >> 32)) atomicOr(&b[clampw(wi + 2)], (uint32_t)(xh >> 32));
+}
+
+// residual field of a value: the low r bits of its K-bit significant prefix
+template <int V>
+__device__ __forceinline__ void emit_residuals(uint32_t *b, int base, uint32_t o, const EncPlan<V> &e,
+                                               uint32_t mask, uint32_t codes, bool sparse)
+{
+    const int K = e.K;
+    uint32_t j = 0;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const bool on = ((mask >> k) & 1u) != 0;
+        const uint32_t L = ((sparse ? (codes >> (2 * j)) : (codes >> (2 * k))) & 3u);
+        j += on ? 1u : 0u;
+        if (K < 64) {
+            const uint32_t r = on ? resid_bits(K, L) : 0u;
+            or_bits32(b, base, o, (e.th[k] >> (32 - K)) & low_mask32(r), r);
+            o += r;
+        } else if (on) {
+            const uint32_t r = 64u - 8u * L;
+            or_bits64(b, base, o, e.th[k] & (~0u >> (8u * L)), e.tl[k]);
+            o += r;
         }
     }
-    __device__ __forceinline__ void put(uint64_t v, int n)
-    {
-        if (n > 32) { put32(v & 0xFFFFFFFFull, 32); put32(v >> 32, n - 32); }
-        else put32(v, n);
-    }
-    __device__ __forceinline__ void flush()
-    {
-        if (nb > 0) atomicOr(&w[clampw(wi)], (uint32_t)acc);
-    }
-};
-
-__device__ __forceinline__ uint64_t residual_of(uint64_t t, int K, int r)
-{
-    uint64_t sig = (K >= 64) ? t : (t >> (64 - K));
-    return r >= 64 ? sig : (sig & ((1ull << r) - 1ull));
 }
 
 // write the planned stream into b[] (already zeroed); no barriers inside
@@ -382,49 +487,29 @@ __device__ void encode_emit(uint32_t *b, const EncPlan<V> &e, int C, int lt)
     if (lt == 0) b[0] = (uint32_t)e.mode | ((uint32_t)e.lev << 2);
     if (e.mode == M_CONST2) {
         if (lt == 0) {
-            b[1] = (uint32_t)e.c0; b[2] = (uint32_t)(e.c0 >> 32);
-            b[3] = (uint32_t)e.c1; b[4] = (uint32_t)(e.c1 >> 32);
+            b[1] = e.c0l; b[2] = e.c0h;
+            b[3] = e.c1l; b[4] = e.c1h;
         }
         return;
     }
-    const int K = e.K;
+    const uint32_t vmask = (V >= 32) ? ~0u : ((1u << V) - 1u);
     if (e.mode == M_PACK) {
         const uint32_t bit = 2u * (uint32_t)first;
         if (V == 16) b[1 + (bit >> 5)] = e.codes;
         else atomicOr(&b[1 + (bit >> 5)], e.codes << (bit & 31));
-        BitOut bo;
-        bo.init(b + 1 + C / 16, e.pack_off);
-#pragma unroll
-        for (int k = 0; k < V; ++k) {
-            int L = (int)((e.codes >> (2 * k)) & 3u);
-            int r = resid_bits(K, L);
-            bo.put(residual_of(e.t[k], K, r), r);
-        }
-        bo.flush();
+        emit_residuals<V>(b, 1 + C / 16, e.pack_off, e, vmask, e.codes, false);
     } else {  // M_SPARSE
         if (e.nzm) atomicOr(&b[1 + (first >> 5)], e.nzm << (first & 31));
-        const int codes_w0 = 1 + ((C + 31) >> 5);
+        const int cw0 = 1 + ((C + 31) >> 5);
         const uint32_t cnt = __popc(e.nzm);
         if (cnt) {
-            uint32_t bit = 2u * e.rank0;
-            uint64_t v = (uint64_t)e.scodes << (bit & 31);
-            int wi = codes_w0 + (int)(bit >> 5);
+            const uint32_t bit = 2u * e.rank0;
+            const uint64_t v = (uint64_t)e.scodes << (bit & 31);
+            const int wi = cw0 + (int)(bit >> 5);
             if ((uint32_t)v) atomicOr(&b[clampw(wi)], (uint32_t)v);
             if ((uint32_t)(v >> 32)) atomicOr(&b[clampw(wi + 1)], (uint32_t)(v >> 32));
         }
-        BitOut bo;
-        bo.init(b + codes_w0 + (int)((e.nnz + 15u) >> 4), e.sp_off);
-        uint32_t j = 0;
-#pragma unroll
-        for (int k = 0; k < V; ++k) {
-            if ((e.nzm >> k) & 1u) {
-                int L = (int)((e.scodes >> (2 * j)) & 3u);
-                ++j;
-                int r = resid_bits(K, L);
-                bo.put(residual_of(e.t[k], K, r), r);
-            }
-        }
-        bo.flush();
+        emit_residuals<V>(b, cw0 + (int)((e.nnz + 15u) >> 4), e.sp_off, e, e.nzm, e.scodes, true);
     }
 }
 
@@ -483,7 +568,7 @@ __device__ __forceinline__ uint64_t item_chunk(const GateDesc &gd, uint64_t item
 }
 
 __device__ void apply_gate(const GateDesc &gd, double *v0, double *v1, uint64_t c0, uint64_t c1, bool a0, bool a1,
-                           int cb)
+                           int cb, int nthreads)
 {
     const int tid = threadIdx.x;
     const int ca = 1 << cb;
@@ -491,7 +576,7 @@ __device__ void apply_gate(const GateDesc &gd, double *v0, double *v1, uint64_t 
     const double *m = gd.m;
     if (gd.job_type == J_PAIR) {
         if (!(a0 && a1)) return;
-        for (int k = tid; k < ca; k += kWG) {
+        for (int k = tid; k < ca; k += nthreads) {
             uint64_t i = (c0 << cb) | (uint64_t)k;
             if ((i & cm) != cm) continue;
             double ar = v0[2 * k], ai = v0[2 * k + 1], br = v1[2 * k], bi = v1[2 * k + 1];
@@ -508,7 +593,7 @@ __device__ void apply_gate(const GateDesc &gd, double *v0, double *v1, uint64_t 
     }
     const bool pairwise = gd.kind == K_U1 || gd.kind == K_X;
     const int units = pairwise ? ca / 2 : ca;
-    for (int w = tid; w < 2 * units; w += kWG) {
+    for (int w = tid; w < 2 * units; w += nthreads) {
         const int s = w >= units ? 1 : 0;
         const int u = w - s * units;
         if (!(s ? a1 : a0)) continue;
@@ -549,27 +634,33 @@ __device__ void apply_gate(const GateDesc &gd, double *v0, double *v1, uint64_t 
 // ---------------------------------------------------------------------------
 // the job kernel
 // ---------------------------------------------------------------------------
-template <int V, int SRC, int DST, bool GATE>
-__global__ __launch_bounds__(kWG) void job_kernel(GateDesc gd, DevPtrs P, IOPtrs io)
+template <int V, int WPG, int SRC, int DST, bool GATE>
+__global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, IOPtrs io)
 {
+    constexpr int G = 64 * WPG;   // threads per chunk slot
+    constexpr int WGS = 2 * G;    // threads per workgroup
     __shared__ uint32_t buf[2][kBufWords];
-    __shared__ uint32_t sh[32];
+    __shared__ uint32_t sh[256];
     __shared__ uint64_t sh_off[2];
     __shared__ int sh_ok[2];
     __shared__ int sh_src_ok[2];
-    __shared__ uint64_t sh_acc[4];
-    __shared__ double sh_mom[kWG / 64][4];
+    __shared__ uint64_t sh_acc[8];
+    __shared__ double sh_mom[WGS / 64][4];
 
     DevState *ds = P.ds;
     if (DST == DST_ARENA && ds->stop) return;
 
-    const int tid = threadIdx.x, s = tid >> 7, lt = tid & (kGroup - 1);
+    const int tid = threadIdx.x, s = tid / G, lt = tid % G;
     const int C = P.C;
     uint32_t *b = buf[s];
     double *vals = reinterpret_cast<double *>(b);
     const int first = lt * V;
+    // LDS slots of the scans (per call site)
+    uint32_t *slA = sh, *slB = sh + 16, *slC = sh + 32, *slE = sh + 48, *slF = sh + 176, *slS = sh + 192;
+    const int glevel = (DST == DST_ARENA || DST == DST_SLOTS) && gd.fixed_level < 0 && !gd.per_block ? ds->level : 0;
+    const uint64_t ds_nstripes = DST == DST_ARENA ? ds->nstripes : 1;
 
-    uint64_t acc_reenc = 0;
+    uint64_t acc_reenc = 0, acc_rd = 0, acc_wr = 0;
     int64_t acc_delta = 0;
     double mom_re = 0.0, mom_im = 0.0, mom_n2 = 0.0;
 
@@ -603,46 +694,48 @@ __global__ __launch_bounds__(kWG) void job_kernel(GateDesc gd, DevPtrs P, IOPtrs
             const uint64_t off = old_entry >> 16;
             const uint32_t words = (size + 3u) >> 2;
             ok_src = words <= (uint32_t)(kBufWords - 8) && off + words <= P.arena_words && size >= 4;
-            if (act && ok_src)
-                for (uint32_t w = lt; w < words; w += kGroup) b[w] = P.arena[off + w];
+            if (act && ok_src) stage_words<G>(b, P.arena + off, words, lt);
             if (act && !ok_src && lt == 0 && ds) atomicExch(&ds->corrupt, 1);
         } else if (SRC == SRC_SLOTS) {
             const uint32_t size = valid ? io.sizes_in[item] : 0u;
             const uint32_t words = (size + 3u) >> 2;
             ok_src = words <= (uint32_t)(kBufWords - 8) && words <= io.slot_words && size >= 4;
-            if (act && ok_src)
-                for (uint32_t w = lt; w < words; w += kGroup) b[w] = io.slots_in[item * io.slot_words + w];
+            if (act && ok_src) stage_words<G>(b, io.slots_in + item * io.slot_words, words, lt);
         } else {  // SRC_RAW
             if (act)
-                for (int w = lt; w < C; w += kGroup) vals[w] = io.raw_in[item * (uint64_t)C + w];
+                for (int w = lt; w < C; w += G) vals[w] = io.raw_in[item * (uint64_t)C + w];
         }
         if (lt == 0) sh_src_ok[s] = ok_src ? 1 : 0;
-        __syncthreads();
-        const bool src_ok0 = sh_src_ok[0] != 0, src_ok1 = sh_src_ok[1] != 0;
+        lds_barrier();
+        const bool use0 = act0 && sh_src_ok[0] != 0, use1 = act1 && sh_src_ok[1] != 0;
+        const bool use = s ? use1 : use0;
 
         // 2. decode
         if (SRC != SRC_RAW) {
-            uint64_t t[V];
-            decode_group<V>(b, act && ok_src, C, lt, sh, t);
-            __syncthreads();
+            const uint32_t hdr0 = use0 ? buf[0][0] : (uint32_t)M_CONST2;
+            const uint32_t hdr1 = use1 ? buf[1][0] : (uint32_t)M_CONST2;
+            const bool any_sparse = (hdr0 & 3u) == M_SPARSE || (hdr1 & 3u) == M_SPARSE;
+            uint32_t th[V], tl[V];
+            decode_group<V, WPG>(b, s ? hdr1 : hdr0, use, any_sparse, C, lt, slA, slB, slC, th, tl);
+            lds_barrier();
 #pragma unroll
-            for (int k = 0; k < V; ++k) vals[first + k] = u2d(t[k]);
-            __syncthreads();
+            for (int k = 0; k < V; ++k) vals[first + k] = u2d(((uint64_t)th[k] << 32) | tl[k]);
+            lds_barrier();
         }
 
         // 3. gate
         if (GATE) {
-            apply_gate(gd, reinterpret_cast<double *>(buf[0]), reinterpret_cast<double *>(buf[1]), cc0, cc1,
-                       act0 && src_ok0, act1 && src_ok1, P.cb);
-            __syncthreads();
+            apply_gate(gd, reinterpret_cast<double *>(buf[0]), reinterpret_cast<double *>(buf[1]), cc0, cc1, use0,
+                       use1, P.cb, WGS);
+            lds_barrier();
         }
 
         // 4. sink
         if (DST == DST_RAW) {
-            if (act)
-                for (int w = lt; w < C; w += kGroup) io.raw_out[item * (uint64_t)C + w] = vals[w];
+            if (use)
+                for (int w = lt; w < C; w += G) io.raw_out[item * (uint64_t)C + w] = vals[w];
         } else if (DST == DST_MOMENTS) {
-            if (act) {
+            if (use) {
 #pragma unroll
                 for (int k = 0; k < V; k += 2) {
                     double re = vals[first + k], im = (k + 1 < V) ? vals[first + k + 1] : 0.0;
@@ -654,53 +747,70 @@ __global__ __launch_bounds__(kWG) void job_kernel(GateDesc gd, DevPtrs P, IOPtrs
                     double v = vals[first];
                     mom_re -= (lt & 1) ? v : 0.0;
                     mom_im += (lt & 1) ? v : 0.0;
-                    mom_n2 += 0.0;
                 }
             }
         } else {
             // encode at the chunk's level
-            uint64_t x[V];
+            uint32_t xh[V], xl[V];
+            bool sub = false;
 #pragma unroll
-            for (int k = 0; k < V; ++k) x[k] = d2u(vals[first + k]);
-            const uint64_t xprev = lt ? d2u(vals[first - 1]) : 0ull;
+            for (int k = 0; k < V; ++k) {
+                const uint64_t x = d2u(vals[first + k]);
+                xh[k] = (uint32_t)(x >> 32);
+                xl[k] = (uint32_t)x;
+                sub = sub || subnormal(xh[k], xl[k]);
+            }
+            const uint32_t xprev_hi = lt ? (uint32_t)(d2u(vals[first - 1]) >> 32) : 0u;
             const uint64_t x0 = d2u(vals[0]), x1 = d2u(vals[1]);
             int lev_req;
             if (gd.fixed_level >= 0) lev_req = gd.fixed_level;
             else if (gd.per_block) lev_req = P.block_level[c >> gd.block_shift];
-            else lev_req = ds->level;
-            const bool enc = act && ok_src;
+            else lev_req = glevel;
+            const bool enc = use;
+            // subnormal flag of the group (wave ballots meet in LDS)
+            const bool wsub = __any(enc && sub);
+            if ((tid & 63) == 0) slS[tid >> 6] = wsub ? 1u : 0u;
+            lds_barrier();
+            uint32_t gs = 0;
+#pragma unroll
+            for (int i = 0; i < WPG; ++i) gs |= slS[s * WPG + i];
+            const bool gsub = gs != 0;
             EncPlan<V> e;
-            encode_plan<V>(x, xprev, x0, x1, lev_req, enc, C, lt, sh, e);
+            encode_plan<V, WPG>(xh, xl, xprev_hi, x0, x1, lev_req, enc, gsub, C, lt, slE, slF, e);
+            // claim arena space now; the returned offset is first needed after
+            // the stream has been assembled in LDS, which hides the atomic
+            uint64_t my_off = 0;
+            const int stripe = (int)(blockIdx.x % (uint32_t)ds_nstripes);
+            if (lt == 0 && enc && DST == DST_ARENA)
+                my_off = atomicAdd((unsigned long long *)&ds->stripe[stripe][0], (unsigned long long)((e.size + 3u) & ~3u));
+            lds_barrier();
+            const uint32_t words = (e.size + 3u) >> 2;
+            if (enc)
+                for (uint32_t w = lt; w < words; w += G) b[w] = 0u;
+            lds_barrier();
+            if (enc) encode_emit<V>(b, e, C, lt);
             if (lt == 0) {
-                uint64_t off = 0;
                 int ok = 0;
                 if (enc) {
                     if (DST == DST_ARENA) {
-                        const uint64_t pad = (e.size + 3u) & ~3u;
-                        off = atomicAdd((unsigned long long *)&ds->bump, (unsigned long long)pad);
-                        ok = (off + pad <= ds->arena_cap) ? 1 : 0;
+                        ok = (my_off + ((e.size + 3u) & ~3u) <= ds->stripe_size) ? 1 : 0;
+                        my_off += ds->base + (uint64_t)stripe * ds->stripe_size;
                         if (!ok) atomicExch(&ds->fail, 1);
                     } else {
                         ok = 1;
                     }
                 }
-                sh_off[s] = off;
+                sh_off[s] = my_off;
                 sh_ok[s] = ok;
             }
-            __syncthreads();
-            const uint32_t words = (e.size + 3u) >> 2;
-            if (enc)
-                for (uint32_t w = lt; w < words; w += kGroup) b[w] = 0u;
-            __syncthreads();
-            if (enc) encode_emit<V>(b, e, C, lt);
-            __syncthreads();
+            lds_barrier();
             const int ok = sh_ok[s];
             if (ok) {
                 if (DST == DST_ARENA) {
                     const uint64_t offw = sh_off[s] >> 2;
-                    for (uint32_t w = lt; w < words; w += kGroup) P.arena[offw + w] = b[w];
+                    for (uint32_t w = lt; w < words; w += G) P.arena[offw + w] = b[w];
                 } else {
-                    for (uint32_t w = lt; w < words; w += kGroup) io.slots_out[item * io.slot_words + w] = b[w];
+                    for (uint32_t w = lt; w < words; w += G) io.slots_out[item * io.slot_words + w] = b[w];
                 }
             }
             if (lt == 0 && valid) {
@@ -709,15 +819,18 @@ __global__ __launch_bounds__(kWG) void job_kernel(GateDesc gd, DevPtrs P, IOPtrs
                     if (ok) {
                         P.table[c] = ((sh_off[s] >> 2) << 16) | (uint64_t)e.size;
                         const uint64_t old_pad = ((old_entry & 0xFFFFull) + 3ull) & ~3ull;
-                        acc_delta += (int64_t)(((uint64_t)e.size + 3ull) & ~3ull) - (int64_t)old_pad;
+                        const uint64_t new_pad = ((uint64_t)e.size + 3ull) & ~3ull;
+                        acc_delta += (int64_t)new_pad - (int64_t)old_pad;
                         acc_reenc += 1;
+                        acc_rd += old_pad;
+                        acc_wr += new_pad;
                     }
                 } else {
                     io.sizes_out[item] = ok ? e.size : 0u;
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 
     if (DST == DST_MOMENTS) {
@@ -729,10 +842,10 @@ __global__ __launch_bounds__(kWG) void job_kernel(GateDesc gd, DevPtrs P, IOPtrs
             cc += __shfl_down(cc, d, 64);
         }
         if ((tid & 63) == 0) { sh_mom[tid >> 6][0] = a; sh_mom[tid >> 6][1] = bb; sh_mom[tid >> 6][2] = cc; }
-        __syncthreads();
+        lds_barrier();
         if (tid == 0) {
             double A = 0, B = 0, Cc = 0;
-            for (int w = 0; w < kWG / 64; ++w) { A += sh_mom[w][0]; B += sh_mom[w][1]; Cc += sh_mom[w][2]; }
+            for (int w = 0; w < WGS / 64; ++w) { A += sh_mom[w][0]; B += sh_mom[w][1]; Cc += sh_mom[w][2]; }
             io.partials[4 * blockIdx.x] = A;
             io.partials[4 * blockIdx.x + 1] = B;
             io.partials[4 * blockIdx.x + 2] = Cc;
@@ -742,28 +855,73 @@ __global__ __launch_bounds__(kWG) void job_kernel(GateDesc gd, DevPtrs P, IOPtrs
 
     if (DST == DST_ARENA) {
         // per-workgroup totals, then the last workgroup closes the gate
-        if (lt == 0) { sh_acc[2 * s] = (uint64_t)acc_delta; sh_acc[2 * s + 1] = acc_reenc; }
-        __syncthreads();
+        if (lt == 0) {
+            sh_acc[4 * s] = (uint64_t)acc_delta;
+            sh_acc[4 * s + 1] = acc_reenc;
+            sh_acc[4 * s + 2] = acc_rd;
+            sh_acc[4 * s + 3] = acc_wr;
+        }
+        lds_barrier();
         if (tid == 0) {
-            const uint64_t d = sh_acc[0] + sh_acc[2];
-            const uint64_t r = sh_acc[1] + sh_acc[3];
-            if (d) atomicAdd((unsigned long long *)&ds->live, (unsigned long long)d);
-            if (r) atomicAdd((unsigned long long *)&ds->reenc_cur, (unsigned long long)r);
+            WgPart wp;
+            wp.delta = sh_acc[0] + sh_acc[4];
+            wp.reenc = sh_acc[1] + sh_acc[5];
+            wp.rd = sh_acc[2] + sh_acc[6];
+            wp.wr = sh_acc[3] + sh_acc[7];
+            P.wgp[blockIdx.x] = wp;
             __threadfence();
             const uint32_t prev = atomicAdd(&ds->done, 1u);
             sh_ok[0] = (prev == gridDim.x - 1) ? 1 : 0;
         }
-        __syncthreads();
-        if (tid == 0 && sh_ok[0]) {
+        lds_barrier();
+        if (sh_ok[0]) {
+            // the last workgroup: sum the partials of all workgroups
             __threadfence();
-            const uint64_t live = atomicAdd((unsigned long long *)&ds->live, 0ull);
-            const uint64_t bump = atomicAdd((unsigned long long *)&ds->bump, 0ull);
-            const uint64_t reenc = atomicExch((unsigned long long *)&ds->reenc_cur, 0ull);
+            uint64_t d = 0, r = 0, rd = 0, wr = 0, used = 0;
+            for (uint32_t g = (uint32_t)tid; g < gridDim.x; g += WGS) {
+                const WgPart wp = P.wgp[g];
+                d += wp.delta;
+                r += wp.reenc;
+                rd += wp.rd;
+                wr += wp.wr;
+            }
+            if (tid < kStripes) used = atomicAdd((unsigned long long *)&ds->stripe[tid][0], 0ull);
+            for (int off = 32; off >= 1; off >>= 1) {
+                d += __shfl_down(d, off, 64);
+                r += __shfl_down(r, off, 64);
+                rd += __shfl_down(rd, off, 64);
+                wr += __shfl_down(wr, off, 64);
+                used += __shfl_down(used, off, 64);
+            }
+            uint64_t *red = reinterpret_cast<uint64_t *>(buf[0]);
+            if ((tid & 63) == 0) {
+                red[5 * (tid >> 6)] = d;
+                red[5 * (tid >> 6) + 1] = r;
+                red[5 * (tid >> 6) + 2] = rd;
+                red[5 * (tid >> 6) + 3] = wr;
+                red[5 * (tid >> 6) + 4] = used;
+            }
+        }
+        lds_barrier();
+        if (tid == 0 && sh_ok[0]) {
+            const uint64_t *red = reinterpret_cast<const uint64_t *>(buf[0]);
+            uint64_t d = 0, r = 0, rd = 0, wr = 0, used = 0;
+            for (int w = 0; w < WGS / 64; ++w) {
+                d += red[5 * w];
+                r += red[5 * w + 1];
+                rd += red[5 * w + 2];
+                wr += red[5 * w + 3];
+                used += red[5 * w + 4];
+            }
+            const uint64_t live = ds->live + d;
+            ds->live = live;
             GateLog lg;
             lg.live = live;
-            lg.bump = bump;
-            lg.reenc = reenc;
-            lg.pad = 0;
+            lg.bump = ds->base + used;
+            lg.reenc = r;
+            lg.rd = rd;
+            lg.wr = wr;
+            lg.pad[0] = lg.pad[1] = lg.pad[2] = 0;
             ds->log[gd.seq] = lg;
             const int fail = atomicExch(&ds->fail, 0);
             const int corrupt = atomicExch(&ds->corrupt, 0);
@@ -806,10 +964,13 @@ __global__ __launch_bounds__(kWG) void permute_kernel(GateDesc gd, DevPtrs P)
     if (threadIdx.x == 0 && last) {
         __threadfence();
         GateLog lg;
-        lg.live = atomicAdd((unsigned long long *)&ds->live, 0ull);
-        lg.bump = atomicAdd((unsigned long long *)&ds->bump, 0ull);
+        lg.live = ds->live;
+        uint64_t used = 0;
+        for (int k = 0; k < kStripes; ++k) used += atomicAdd((unsigned long long *)&ds->stripe[k][0], 0ull);
+        lg.bump = ds->base + used;
         lg.reenc = 0;
-        lg.pad = 0;
+        lg.rd = lg.wr = 0;
+        lg.pad[0] = lg.pad[1] = lg.pad[2] = 0;
         ds->log[gd.seq] = lg;
         atomicExch(&ds->done, 0u);
     }
@@ -920,26 +1081,49 @@ __global__ __launch_bounds__(kWG) void compact_copy_kernel(DevPtrs P, uint32_t *
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-template <int SRC, int DST, bool GATE>
-static hipError_t launch_job(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st)
+template <int V, int WPG, int SRC, int DST, bool GATE>
+static void launch_vw(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st)
 {
-    const int V = P.C / kGroup;
-    dim3 g(grid), blk(kWG);
-    switch (V) {
-    case 1: hipLaunchKernelGGL((job_kernel<1, SRC, DST, GATE>), g, blk, 0, st, gd, P, io); break;
-    case 2: hipLaunchKernelGGL((job_kernel<2, SRC, DST, GATE>), g, blk, 0, st, gd, P, io); break;
-    case 4: hipLaunchKernelGGL((job_kernel<4, SRC, DST, GATE>), g, blk, 0, st, gd, P, io); break;
-    case 8: hipLaunchKernelGGL((job_kernel<8, SRC, DST, GATE>), g, blk, 0, st, gd, P, io); break;
-    case 16: hipLaunchKernelGGL((job_kernel<16, SRC, DST, GATE>), g, blk, 0, st, gd, P, io); break;
-    default: return hipErrorInvalidValue;
+    hipLaunchKernelGGL((job_kernel<V, WPG, SRC, DST, GATE>), dim3(grid), dim3(128 * WPG), 0, st, gd, P, io);
+}
+
+// V values per thread and WPG wavefronts per chunk slot: C = V * 64 * WPG.
+// Gate kernels exist for 2, 4 and 8 wavefronts per slot (a tuning choice);
+// the codec and readout kernels use 2.
+template <int SRC, int DST, bool GATE>
+static hipError_t launch_job(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st,
+                             int wpg = 2)
+{
+    const int threads = 64 * wpg;
+    if (P.C % threads) return hipErrorInvalidValue;
+    const int V = P.C / threads;
+    const int key = wpg * 100 + V;
+    switch (key) {
+    case 201: launch_vw<1, 2, SRC, DST, GATE>(gd, P, io, grid, st); break;
+    case 202: launch_vw<2, 2, SRC, DST, GATE>(gd, P, io, grid, st); break;
+    case 204: launch_vw<4, 2, SRC, DST, GATE>(gd, P, io, grid, st); break;
+    case 208: launch_vw<8, 2, SRC, DST, GATE>(gd, P, io, grid, st); break;
+    case 216: launch_vw<16, 2, SRC, DST, GATE>(gd, P, io, grid, st); break;
+    default:
+        if (!GATE) return hipErrorInvalidValue;
+        switch (key) {
+        case 401: launch_vw<1, 4, SRC, DST, GATE>(gd, P, io, grid, st); break;
+        case 402: launch_vw<2, 4, SRC, DST, GATE>(gd, P, io, grid, st); break;
+        case 404: launch_vw<4, 4, SRC, DST, GATE>(gd, P, io, grid, st); break;
+        case 408: launch_vw<8, 4, SRC, DST, GATE>(gd, P, io, grid, st); break;
+        case 801: launch_vw<1, 8, SRC, DST, GATE>(gd, P, io, grid, st); break;
+        case 802: launch_vw<2, 8, SRC, DST, GATE>(gd, P, io, grid, st); break;
+        case 804: launch_vw<4, 8, SRC, DST, GATE>(gd, P, io, grid, st); break;
+        default: return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }
 
-hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st)
+hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st, int wpg)
 {
     IOPtrs io = {};
-    return launch_job<SRC_ARENA, DST_ARENA, true>(gd, P, io, grid, st);
+    return launch_job<SRC_ARENA, DST_ARENA, true>(gd, P, io, grid, st, wpg);
 }
 
 hipError_t launch_permute(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st)

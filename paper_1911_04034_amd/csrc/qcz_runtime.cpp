@@ -43,7 +43,7 @@ struct GraphEntry {
 };
 
 struct Layout {
-    size_t ds, table, undo, bsums, blevel, partials, scratch, arena0, arena1, arena_bytes, end;
+    size_t ds, table, undo, bsums, blevel, partials, wgp, scratch, arena0, arena1, arena_bytes, end;
 };
 
 int chunk_log2_for(int bl) { return bl < 10 ? bl : 10; }
@@ -62,6 +62,7 @@ Layout layout_for(int n, int bl, size_t pool_bytes)
     L.bsums = o; o = align256(o + 8 * ((nchunks + kScanItems - 1) / kScanItems + 1));
     L.blevel = o; o = align256(o + nblocks);
     L.partials = o; o = align256(o + 8 * (size_t)std::max<uint64_t>(4 * kMomGrid, nchunks < (1u << 20) ? nchunks : 0));
+    L.wgp = o; o = align256(o + sizeof(WgPart) * (size_t)kMaxGrid);
     const size_t slot = ((chunk_cap_bytes(C) + 3) & ~3u);
     L.scratch = o; o = align256(o + (size_t)kScratchChunks * (8 * (size_t)C + slot + 16) + 4096);
     L.end = o;
@@ -85,6 +86,7 @@ struct qcz_state {
     Layout lay{};
     DevState *ds = nullptr;
     uint64_t *table = nullptr, *undo = nullptr, *bsums = nullptr;
+    WgPart *wgp = nullptr;
     uint8_t *blevel = nullptr;
     double *partials = nullptr;
     uint8_t *scratch = nullptr;
@@ -92,15 +94,22 @@ struct qcz_state {
     int cur = 0;
     int grid_max = 1024;
     int batch = 64;
+    int chunk_waves = 4;
     // host mirror of the committed state
     int level = 0;
-    uint64_t live = 0, bump = 0;
+    uint64_t live = 0, bump = 0;          // bump: arena bytes in use (base + stripe fills)
+    uint64_t base = 0, stripe_size = 0;   // arena stripes (see DevState)
+    int nstripes = 1;
+    uint64_t stripe_fill[kStripes] = {};
     uint64_t gates_applied = 0, lossy_steps = 0, min_c = 0, max_c = 0, compactions = 0;
     double flb = 1.0;
     std::vector<uint8_t> block_levels;
     std::string err;
     std::vector<GraphEntry> graphs;
     DevState hds{};  // readback staging
+    qcz_stats_t stats{};
+    std::vector<hipEvent_t> events;   // QCZ_FLAG_TIMING: start/stop per gate of a batch
+    std::vector<int> timed;           // per gate of the batch: 1 if its fused kernel was timed
 };
 
 namespace {
@@ -126,6 +135,7 @@ DevPtrs ptrs(const qcz_state *s)
     P.undo = s->undo;
     P.block_level = s->blevel;
     P.ds = s->ds;
+    P.wgp = s->wgp;
     P.cb = s->cb;
     P.C = s->C;
     P.nchunks = s->nchunks;
@@ -225,15 +235,41 @@ int grid_for(const qcz_state *s, const GateDesc &d)
 qcz_status write_header(qcz_state *s)
 {
     DevState h{};
-    h.bump = s->bump;
+    h.base = s->base;
+    h.stripe_size = s->stripe_size;
+    h.nstripes = (uint64_t)s->nstripes;
     h.live = s->live;
     h.arena_cap = s->lay.arena_bytes;
     h.budget = s->cfg.mode == QCZ_MODE_ADAPTIVE ? s->cfg.budget_bytes : 0;
     h.level = s->level;
     s->hds = h;
-    HIPCHK(s, hipMemcpyAsync(s->ds, &s->hds, offsetof(DevState, log), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->ds, &s->hds, offsetof(DevState, stripe), hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));   // the staging struct is reused right after
     return QCZ_OK;
+}
+
+// Start fresh stripes right after the first `used` arena bytes.
+qcz_status reset_stripes(qcz_state *s, uint64_t used)
+{
+    s->base = align256(used);
+    const uint64_t cap = s->lay.arena_bytes;
+    const uint64_t room = cap > s->base ? cap - s->base : 0;
+    // as many stripes as leave room for 64 of the largest streams each
+    uint64_t ns = room / (64ull * chunk_cap_bytes(s->C));
+    s->nstripes = (int)std::max<uint64_t>(1, std::min<uint64_t>(ns, kStripes));
+    s->stripe_size = (room / (uint64_t)s->nstripes) & ~(uint64_t)255;
+    for (int k = 0; k < kStripes; ++k) s->stripe_fill[k] = 0;
+    s->bump = s->base;
+    for (int k = 0; k < kStripes; ++k) s->hds.stripe[k][0] = 0;
+    HIPCHK(s, hipMemcpyAsync(&s->ds->stripe, &s->hds.stripe, sizeof(s->hds.stripe), hipMemcpyHostToDevice, s->stream));
+    return write_header(s);
+}
+
+uint64_t max_stripe_fill(const qcz_state *s)
+{
+    uint64_t m = 0;
+    for (int k = 0; k < s->nstripes; ++k) m = std::max(m, s->stripe_fill[k]);
+    return m;
 }
 
 void clear_graphs(qcz_state *s)
@@ -252,26 +288,39 @@ qcz_status compact(qcz_state *s)
     HIPCHK(s, hipMemcpyAsync(&total, s->bsums + nb, 8, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     s->cur = 1 - s->cur;
-    s->bump = total;
     s->compactions += 1;
     clear_graphs(s);
-    return write_header(s);
+    return reset_stripes(s, total);
 }
 
-qcz_status launch_one(qcz_state *s, const GateDesc &d)
+qcz_status launch_one(qcz_state *s, const GateDesc &d, bool timing)
 {
     DevPtrs P = ptrs(s);
     const int grid = grid_for(s, d);
-    hipError_t e = d.job_type == J_PERMUTE ? launch_permute(d, P, grid, s->stream) : launch_gate(d, P, grid, s->stream);
+    const bool t = timing && d.job_type != J_PERMUTE;
+    if (t) HIPCHK(s, hipEventRecord(s->events[2 * d.seq], s->stream));
+    hipError_t e = d.job_type == J_PERMUTE ? launch_permute(d, P, grid, s->stream)
+                                           : launch_gate(d, P, grid, s->stream, s->chunk_waves);
     if (e != hipSuccess) return fail(s, QCZ_E_DEVICE, std::string("gate launch: ") + hipGetErrorString(e));
+    if (t) HIPCHK(s, hipEventRecord(s->events[2 * d.seq + 1], s->stream));
+    if (timing) s->timed[(size_t)d.seq] = t ? 1 : 0;
     return QCZ_OK;
 }
 
 qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
 {
-    if (!(s->cfg.flags & QCZ_FLAG_GRAPH) || s->stream == nullptr) {
+    const bool timing = (s->cfg.flags & QCZ_FLAG_TIMING) != 0;
+    if (timing) {
+        while (s->events.size() < 2 * descs.size()) {
+            hipEvent_t ev;
+            HIPCHK(s, hipEventCreate(&ev));
+            s->events.push_back(ev);
+        }
+        s->timed.assign(descs.size(), 0);
+    }
+    if (timing || !(s->cfg.flags & QCZ_FLAG_GRAPH) || s->stream == nullptr) {
         for (const auto &d : descs) {
-            qcz_status st = launch_one(s, d);
+            qcz_status st = launch_one(s, d, timing);
             if (st != QCZ_OK) return st;
         }
         return QCZ_OK;
@@ -290,7 +339,7 @@ qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
     HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed));
     qcz_status st = QCZ_OK;
     for (const auto &d : descs) {
-        st = launch_one(s, d);
+        st = launch_one(s, d, false);
         if (st != QCZ_OK) break;
     }
     hipError_t e = hipStreamEndCapture(s->stream, &graph);
@@ -312,11 +361,29 @@ qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
     return QCZ_OK;
 }
 
-void commit_gate(qcz_state *s, const GateLog &lg)
+void commit_gate(qcz_state *s, const GateLog &lg, const GateDesc &d, int k)
 {
     s->live = lg.live;
     s->bump = lg.bump;
     s->gates_applied += 1;
+    qcz_stats_t &S = s->stats;
+    if (d.job_type == J_PERMUTE) {
+        S.permute_launches += 1;
+    } else {
+        S.gate_launches += 1;
+        S.chunks_reencoded += lg.reenc;
+        S.amps_touched += lg.reenc * (uint64_t)(s->C / 2);
+        S.bytes_read += lg.rd;
+        S.bytes_written += lg.wr;
+        S.table_bytes += 24 * lg.reenc;
+        if ((s->cfg.flags & QCZ_FLAG_TIMING) && k < (int)s->timed.size() && s->timed[(size_t)k]) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, s->events[2 * (size_t)k], s->events[2 * (size_t)k + 1]) == hipSuccess) {
+                S.timed_launches += 1;
+                S.gate_kernel_ms += ms;
+            }
+        }
+    }
     if (lg.reenc > 0) {
         double d = 0.0;
         if (s->cfg.mode == QCZ_MODE_PERBLOCK) {
@@ -380,6 +447,8 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
         return QCZ_E_INVAL;
     if (cfg->mode < QCZ_MODE_LOSSLESS || cfg->mode > QCZ_MODE_PERBLOCK) return QCZ_E_INVAL;
     if (cfg->level < 0 || cfg->level >= kLevels || cfg->batch > (uint32_t)kMaxBatch) return QCZ_E_INVAL;
+    if (cfg->chunk_waves != 0 && cfg->chunk_waves != 2 && cfg->chunk_waves != 4 && cfg->chunk_waves != 8)
+        return QCZ_E_INVAL;
     if (((uintptr_t)dev_pool & 255) != 0) return QCZ_E_INVAL;
     if (pool_bytes < qcz_pool_bytes_min(cfg)) return QCZ_E_NOMEM;
 
@@ -400,10 +469,13 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
     s->bsums = (uint64_t *)(s->pool + s->lay.bsums);
     s->blevel = s->pool + s->lay.blevel;
     s->partials = (double *)(s->pool + s->lay.partials);
+    s->wgp = (WgPart *)(s->pool + s->lay.wgp);
     s->scratch = s->pool + s->lay.scratch;
     s->arena[0] = (uint32_t *)(s->pool + s->lay.arena0);
     s->arena[1] = (uint32_t *)(s->pool + s->lay.arena1);
     s->batch = cfg->batch ? (int)cfg->batch : 64;
+    s->chunk_waves = cfg->chunk_waves ? (int)cfg->chunk_waves : 2;
+    while (s->chunk_waves > 2 && s->C < 64 * s->chunk_waves) s->chunk_waves /= 2;   // at least one value per thread
     s->level = cfg->mode == QCZ_MODE_FIXED ? cfg->level : 0;
 
     if (hip_stream) {
@@ -418,6 +490,7 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     s->grid_max = cfg->grid ? (int)cfg->grid : 4 * ncu;
+    if (s->grid_max > kMaxGrid) s->grid_max = kMaxGrid;
 
     s->block_levels.assign(s->nblocks, (uint8_t)(cfg->mode == QCZ_MODE_PERBLOCK ? cfg->level : 0));
     auto bail = [&](qcz_status st) {
@@ -449,10 +522,9 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
     DevPtrs P = ptrs(s);
     if (launch_fill_table(P, (0ull << 16) | hsz[0], ((p0 / 4) << 16) | hsz[1], s->stream) != hipSuccess)
         return bail(QCZ_E_DEVICE);
-    s->bump = p0 + p1;
     s->live = p0 + p1 * (s->nchunks - 1);
     s->min_c = s->max_c = s->live;
-    if (write_header(s) != QCZ_OK) return bail(QCZ_E_DEVICE);
+    if (reset_stripes(s, p0 + p1) != QCZ_OK) return bail(QCZ_E_DEVICE);
     if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(QCZ_E_DEVICE);
     *out = s;
     return QCZ_OK;
@@ -463,6 +535,7 @@ void qcz_destroy(qcz_state *s)
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     clear_graphs(s);
+    for (hipEvent_t ev : s->events) (void)hipEventDestroy(ev);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -484,7 +557,7 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
     std::vector<GateDesc> descs;
     while (idx < n_gates) {
         const size_t B = std::min<size_t>((size_t)s->batch, n_gates - idx);
-        if (s->bump > s->lay.arena_bytes / 4 * 3 && s->bump > 2 * s->live) {
+        if (max_stripe_fill(s) > s->stripe_size / 2) {
             qcz_status st = compact(s);
             if (st != QCZ_OK) return st;
         }
@@ -497,15 +570,16 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
                                  s->stream));
         HIPCHK(s, hipStreamSynchronize(s->stream));
         const DevState &h = s->hds;
+        for (int k = 0; k < kStripes; ++k) s->stripe_fill[k] = h.stripe[k][0];
         if (!h.stop) {
-            for (size_t k = 0; k < B; ++k) commit_gate(s, h.log[k]);
+            for (size_t k = 0; k < B; ++k) commit_gate(s, h.log[k], descs[k], (int)k);
             idx += B;
             if (applied) *applied = idx;
             continue;
         }
         const int sseq = h.stop_seq;
         const int reason = h.stop_reason;
-        for (int k = 0; k < sseq; ++k) commit_gate(s, h.log[k]);
+        for (int k = 0; k < sseq; ++k) commit_gate(s, h.log[k], descs[(size_t)k], k);
         // undo the stopped gate
         const GateDesc &dstop = descs[(size_t)sseq];
         DevPtrs P = ptrs(s);
@@ -560,6 +634,20 @@ qcz_status qcz_footprint(qcz_state *s, qcz_footprint_t *out)
     f.ratio = (double)f.raw_bytes / (double)f.total_bytes;
     f.fidelity_lower_bound = s->flb;
     *out = f;
+    return QCZ_OK;
+}
+
+qcz_status qcz_get_stats(qcz_state *s, qcz_stats_t *out)
+{
+    if (!s || !out) return QCZ_E_INVAL;
+    *out = s->stats;
+    return QCZ_OK;
+}
+
+qcz_status qcz_reset_stats(qcz_state *s)
+{
+    if (!s) return QCZ_E_INVAL;
+    s->stats = qcz_stats_t{};
     return QCZ_OK;
 }
 
@@ -683,22 +771,34 @@ qcz_status qcz_import_chunk(qcz_state *s, uint64_t chunk, const void *host_buf, 
     if ((hdr >> 5) != 0 || lev >= (uint32_t)kLevels || mode > M_SPARSE || (mode == M_CONST2 && len != 20))
         return fail(s, QCZ_E_FORMAT, "bad stream header");
     const uint64_t pad = (len + 3) & ~(size_t)3;
-    if (s->bump + pad > s->lay.arena_bytes) {
+    auto emptiest = [&]() {
+        int best = 0;
+        for (int k = 1; k < s->nstripes; ++k)
+            if (s->stripe_fill[k] < s->stripe_fill[best]) best = k;
+        return best;
+    };
+    int sk = emptiest();
+    if (s->stripe_fill[sk] + pad > s->stripe_size) {
         qcz_status st = compact(s);
         if (st != QCZ_OK) return st;
-        if (s->bump + pad > s->lay.arena_bytes) return fail(s, QCZ_E_NOMEM, "arena full");
+        sk = emptiest();
+        if (s->stripe_fill[sk] + pad > s->stripe_size) return fail(s, QCZ_E_NOMEM, "arena full");
     }
+    const uint64_t where = s->base + (uint64_t)sk * s->stripe_size + s->stripe_fill[sk];
     uint64_t old = 0;
     HIPCHK(s, hipMemcpyAsync(&old, s->table + chunk, 8, hipMemcpyDeviceToHost, s->stream));
     std::vector<uint8_t> tmp(pad, 0);
     memcpy(tmp.data(), host_buf, len);
-    HIPCHK(s, hipMemcpyAsync((uint8_t *)s->arena[s->cur] + s->bump, tmp.data(), pad, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync((uint8_t *)s->arena[s->cur] + where, tmp.data(), pad, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    const uint64_t entry = ((s->bump / 4) << 16) | (uint64_t)len;
+    const uint64_t entry = ((where / 4) << 16) | (uint64_t)len;
     HIPCHK(s, hipMemcpyAsync(s->table + chunk, &entry, 8, hipMemcpyHostToDevice, s->stream));
     const uint64_t old_pad = ((old & 0xFFFF) + 3) & ~3ull;
     s->live = s->live + pad - old_pad;
+    s->stripe_fill[sk] += pad;
     s->bump += pad;
+    s->hds.stripe[sk][0] = s->stripe_fill[sk];
+    HIPCHK(s, hipMemcpyAsync(&s->ds->stripe[sk][0], &s->hds.stripe[sk][0], 8, hipMemcpyHostToDevice, s->stream));
     qcz_status st = write_header(s);
     if (st != QCZ_OK) return st;
     HIPCHK(s, hipStreamSynchronize(s->stream));

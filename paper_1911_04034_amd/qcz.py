@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libqcz.so")
 
 MODE_LOSSLESS, MODE_FIXED, MODE_ADAPTIVE, MODE_PERBLOCK = 0, 1, 2, 3
 FLAG_GRAPH = 1
+FLAG_TIMING = 2
 STATUS = {0: "QCZ_OK", -1: "QCZ_E_INVAL", -2: "QCZ_E_NOMEM", -3: "QCZ_E_DEVICE", -4: "QCZ_E_FORMAT",
           -5: "QCZ_E_STATE"}
 
@@ -30,7 +31,7 @@ class QczError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_uint32), ("block_log2", ctypes.c_uint32), ("mode", ctypes.c_int32),
                 ("level", ctypes.c_int32), ("budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("batch", ctypes.c_uint32), ("grid", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+                ("batch", ctypes.c_uint32), ("grid", ctypes.c_uint32), ("chunk_waves", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint64 * 3)]
 
 
@@ -44,11 +45,19 @@ class Footprint(ctypes.Structure):
                 ("fidelity_lower_bound", ctypes.c_double)]
 
 
+class Stats(ctypes.Structure):
+    _fields_ = [("gate_launches", ctypes.c_uint64), ("permute_launches", ctypes.c_uint64),
+                ("chunks_reencoded", ctypes.c_uint64), ("amps_touched", ctypes.c_uint64),
+                ("bytes_read", ctypes.c_uint64), ("bytes_written", ctypes.c_uint64),
+                ("table_bytes", ctypes.c_uint64), ("timed_launches", ctypes.c_uint64),
+                ("gate_kernel_ms", ctypes.c_double)]
+
+
 EXPORTED = [
     "qcz_pool_bytes_min", "qcz_create", "qcz_apply_gates", "qcz_read_amplitudes", "qcz_decode_chunks_to",
     "qcz_moments", "qcz_sample", "qcz_footprint", "qcz_export_chunk", "qcz_import_chunk", "qcz_set_block_levels",
     "qcz_chunk_sizes", "qcz_num_chunks", "qcz_chunk_doubles", "qcz_last_error", "qcz_destroy", "qcz_chunk_cap",
-    "qcz_encode_chunks", "qcz_decode_chunks",
+    "qcz_encode_chunks", "qcz_decode_chunks", "qcz_get_stats", "qcz_reset_stats",
 ]
 
 _lib = None
@@ -101,6 +110,10 @@ def load():
     L.qcz_encode_chunks.argtypes = [vp, u32, u64, i32, vp, sz, vp, vp]
     L.qcz_decode_chunks.restype = i32
     L.qcz_decode_chunks.argtypes = [vp, sz, vp, u32, u64, vp, vp]
+    L.qcz_get_stats.restype = i32
+    L.qcz_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.qcz_reset_stats.restype = i32
+    L.qcz_reset_stats.argtypes = [vp]
     _lib = L
     return L
 
@@ -127,12 +140,13 @@ class State:
     """A compressed 2^n-amplitude state on the current HIP device."""
 
     def __init__(self, n: int, block_log2: int, mode: int = MODE_LOSSLESS, level: int = 0, budget: int = 0,
-                 pool_bytes: int | None = None, flags: int = 0, batch: int = 0, grid: int = 0, stream=None):
+                 pool_bytes: int | None = None, flags: int = 0, batch: int = 0, grid: int = 0, stream=None,
+                 chunk_waves: int = 0):
         torch = _torch()
         L = load()
         self._lib = L
         self.n, self.block_log2 = n, block_log2
-        cfg = Config(n, block_log2, mode, level, budget, flags, batch, grid, 0)
+        cfg = Config(n, block_log2, mode, level, budget, flags, batch, grid, chunk_waves)
         self.cfg = cfg
         pmin = L.qcz_pool_bytes_min(ctypes.byref(cfg))
         if pmin == 0:
@@ -217,6 +231,14 @@ class State:
         f = Footprint()
         self._check(self._lib.qcz_footprint(self._h, ctypes.byref(f)), "qcz_footprint")
         return {k: getattr(f, k) for k, _ in Footprint._fields_ if k != "reserved"}
+
+    def stats(self) -> dict:
+        st = Stats()
+        self._check(self._lib.qcz_get_stats(self._h, ctypes.byref(st)), "qcz_get_stats")
+        return {k: getattr(st, k) for k, _ in Stats._fields_}
+
+    def reset_stats(self):
+        self._check(self._lib.qcz_reset_stats(self._h), "qcz_reset_stats")
 
     def export_chunk(self, c: int) -> bytes:
         cap = chunk_cap(self.C)

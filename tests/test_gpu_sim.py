@@ -49,11 +49,12 @@ def test_random12_gate_by_gate(level):
     assert same_bits(g.state(), o.state())
 
 
+@pytest.mark.parametrize("waves", [2, 4, 8])
 @pytest.mark.parametrize("n,bl,level,seed", [(12, 8, 2, 5), (13, 10, 4, 6), (14, 12, 1, 7), (11, 11, 5, 8)])
-def test_all_gate_kinds_batched(n, bl, level, seed):
+def test_all_gate_kinds_batched(n, bl, level, seed, waves):
     gates = cc.concat([cc.grover_prefix(n), cc.random_unitary_gates(n, 120, seed)])
-    g, o = make(n, bl, oq.MODE_FIXED, level, batch=16)
-    say("all kinds n=%d bl=%d level=%d" % (n, bl, level))
+    g, o = make(n, bl, oq.MODE_FIXED, level, batch=16, chunk_waves=waves)
+    say("all kinds n=%d bl=%d level=%d waves=%d" % (n, bl, level, waves))
     assert g.apply(gates) == len(gates)
     assert o.apply(gates) == len(gates)
     assert_same_chunks(g, o, "after %d gates" % len(gates))
