@@ -153,13 +153,13 @@ def main():
     w = cc.grover_marked(n, 2)
     it = cc.grover_iteration(n, w)
     if do_grover:
-        grover = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=level, pool_bytes=4 << 30, flags=flags,
+        grover = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=level, pool_bytes=8 << 30, flags=flags,
                            batch=len(it), grid=args.grid, stream=stream, chunk_waves=args.chunk_waves)
         grover.apply(cc.grover_prefix(n))
     x_in = cc.qft_input(n, 2)
     qft_gates = cc.qft(n, x_in)
     if do_qft:
-        qft_states = [qcz.State(n, bl, mode=qcz.MODE_FIXED, level=level, pool_bytes=2 << 30, flags=flags,
+        qft_states = [qcz.State(n, bl, mode=qcz.MODE_FIXED, level=level, pool_bytes=4 << 30, flags=flags,
                                 batch=256, grid=args.grid, stream=stream, chunk_waves=args.chunk_waves)
                       for _ in range(passes)]
     log("inputs ready: grover=%s qft=%s passes=%d grover_iters/step=%d" % (do_grover, do_qft, passes, g_iters))
@@ -207,6 +207,8 @@ def main():
     timed = sum(x["timed_launches"] for x in stats)
     kms = sum(x["gate_kernel_ms"] for x in stats)
     value = amps / wall / 1e9
+    stops = sum(x["stops"] for x in stats)
+    compactions = sum(s.footprint()["compactions"] for s in all_states())
 
     out_extra = {}
     fids = []
@@ -231,12 +233,18 @@ def main():
                               "ratio_min": r_min}
 
     roofline = None
+    traffic = None
+    if args.workload == "grover24+qft24":
+        from paper_1911_04034_amd import profile_summary as ps
+        t_bytes, t_hash = ps.read_traffic(os.path.join(ROOT, "profiles", "traffic_fused_kernel_grover24_qft24.txt"))
+        if t_bytes is not None and t_hash == ps.kernel_hash():
+            traffic = round(t_bytes, 1)
     if timed > 0:
         avg_ms = kms / timed
         bytes_per_launch = (rd + wr + tb) / launches if launches else 0.0
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
                     "kernel": "job_kernel<16, ARENA, ARENA, gate> (fused decode-gate-encode)",
                     "avg_launch_us": round(avg_ms * 1e3, 3), "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
                     "launches": timed}
@@ -258,6 +266,8 @@ def main():
         "fused_kernel_gamp_s": round(amps / (kms * 1e-3) / 1e9, 3) if kms > 0 else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "device_stops": stops,
+        "compactions": compactions,
         "workloads": out_extra,
     }
     print(json.dumps(line), flush=True)

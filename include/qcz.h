@@ -61,6 +61,9 @@ typedef enum {
 #define QCZ_FLAG_GRAPH 1u   /* replay launch batches from captured HIP graphs when a batch repeats */
 #define QCZ_FLAG_TIMING 2u  /* time every fused gate kernel with HIP events on the state's stream
                                (launches directly, so it takes precedence over QCZ_FLAG_GRAPH) */
+#define QCZ_FLAG_AUTOTUNE 4u /* over the first launch batches, rotate the fused kernel's launch shape
+                                (wavefronts per chunk x workgroups per CU), time each shape with events and
+                                keep the fastest per recompressed chunk; results do not depend on the shape */
 
 typedef struct {
     uint32_t n_qubits;      /* 6 .. 40 */
@@ -124,6 +127,10 @@ typedef struct {
     uint64_t table_bytes;       /* chunk-table and undo-log bytes: 24 per re-encoded chunk */
     uint64_t timed_launches;    /* fused kernels timed with events */
     double gate_kernel_ms;      /* their summed event time */
+    uint32_t chunk_waves;       /* launch shape in use: wavefronts per chunk */
+    uint32_t grid;              /* launch shape in use: workgroups per fused launch */
+    uint32_t tuning;            /* 1 while the autotuner is still measuring */
+    uint32_t stops;             /* batches stopped on the device (budget or arena full) and rolled back */
 } qcz_stats_t;
 
 /* Bytes of device pool needed for a configuration (state |0..0> plus
@@ -163,6 +170,11 @@ qcz_status qcz_footprint(qcz_state *st, qcz_footprint_t *out);
 
 qcz_status qcz_get_stats(qcz_state *st, qcz_stats_t *out);
 qcz_status qcz_reset_stats(qcz_state *st);
+
+/* Set the fused kernel's launch shape: chunk_waves in {2, 4, 8} (0 keeps the
+ * current one), grid = workgroups per launch (0 keeps it). QCZ_E_INVAL for
+ * an unsupported shape. Does not change any result. */
+qcz_status qcz_set_launch(qcz_state *st, uint32_t chunk_waves, uint32_t grid);
 
 /* Copy chunk `chunk`'s stream to host memory (capacity cap); *len gets its
  * size.  QCZ_E_INVAL if cap is too small. */

@@ -111,7 +111,8 @@ struct IOPtrs {
 inline uint32_t chunk_cap_bytes(int C) { return 4u + 4u * (uint32_t)((C + 15) / 16) + 8u * (uint32_t)C; }
 
 // Host launchers (qcz_kernels.hip).
-hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st, int wpg);
+hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st, int wpg,
+                       hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_permute(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);
 hipError_t launch_rollback(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);
 hipError_t launch_encode_raw(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);

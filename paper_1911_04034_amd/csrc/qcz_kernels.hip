@@ -21,6 +21,8 @@
 // flow around barriers.
 #include "qcz_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace qcz {
 
 // Sig_Bit_Count of Eq. (12) for binary64 (12 sign/exponent bits minus the
@@ -1082,9 +1084,15 @@ __global__ __launch_bounds__(kWG) void compact_copy_kernel(DevPtrs P, uint32_t *
 // host launchers
 // ---------------------------------------------------------------------------
 template <int V, int WPG, int SRC, int DST, bool GATE>
-static void launch_vw(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st)
+static void launch_vw(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st,
+                      hipEvent_t t0, hipEvent_t t1)
 {
-    hipLaunchKernelGGL((job_kernel<V, WPG, SRC, DST, GATE>), dim3(grid), dim3(128 * WPG), 0, st, gd, P, io);
+    if (t0) {  // events attached to the dispatch itself: they time exactly this kernel
+        hipExtLaunchKernelGGL((job_kernel<V, WPG, SRC, DST, GATE>), dim3(grid), dim3(128 * WPG), 0, st, t0, t1, 0, gd,
+                              P, io);
+    } else {
+        hipLaunchKernelGGL((job_kernel<V, WPG, SRC, DST, GATE>), dim3(grid), dim3(128 * WPG), 0, st, gd, P, io);
+    }
 }
 
 // V values per thread and WPG wavefronts per chunk slot: C = V * 64 * WPG.
@@ -1092,38 +1100,39 @@ static void launch_vw(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, in
 // the codec and readout kernels use 2.
 template <int SRC, int DST, bool GATE>
 static hipError_t launch_job(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st,
-                             int wpg = 2)
+                             int wpg = 2, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr)
 {
     const int threads = 64 * wpg;
     if (P.C % threads) return hipErrorInvalidValue;
     const int V = P.C / threads;
     const int key = wpg * 100 + V;
     switch (key) {
-    case 201: launch_vw<1, 2, SRC, DST, GATE>(gd, P, io, grid, st); break;
-    case 202: launch_vw<2, 2, SRC, DST, GATE>(gd, P, io, grid, st); break;
-    case 204: launch_vw<4, 2, SRC, DST, GATE>(gd, P, io, grid, st); break;
-    case 208: launch_vw<8, 2, SRC, DST, GATE>(gd, P, io, grid, st); break;
-    case 216: launch_vw<16, 2, SRC, DST, GATE>(gd, P, io, grid, st); break;
+    case 201: launch_vw<1, 2, SRC, DST, GATE>(gd, P, io, grid, st, t0, t1); break;
+    case 202: launch_vw<2, 2, SRC, DST, GATE>(gd, P, io, grid, st, t0, t1); break;
+    case 204: launch_vw<4, 2, SRC, DST, GATE>(gd, P, io, grid, st, t0, t1); break;
+    case 208: launch_vw<8, 2, SRC, DST, GATE>(gd, P, io, grid, st, t0, t1); break;
+    case 216: launch_vw<16, 2, SRC, DST, GATE>(gd, P, io, grid, st, t0, t1); break;
     default:
         if (!GATE) return hipErrorInvalidValue;
         switch (key) {
-        case 401: launch_vw<1, 4, SRC, DST, GATE>(gd, P, io, grid, st); break;
-        case 402: launch_vw<2, 4, SRC, DST, GATE>(gd, P, io, grid, st); break;
-        case 404: launch_vw<4, 4, SRC, DST, GATE>(gd, P, io, grid, st); break;
-        case 408: launch_vw<8, 4, SRC, DST, GATE>(gd, P, io, grid, st); break;
-        case 801: launch_vw<1, 8, SRC, DST, GATE>(gd, P, io, grid, st); break;
-        case 802: launch_vw<2, 8, SRC, DST, GATE>(gd, P, io, grid, st); break;
-        case 804: launch_vw<4, 8, SRC, DST, GATE>(gd, P, io, grid, st); break;
+        case 401: launch_vw<1, 4, SRC, DST, GATE>(gd, P, io, grid, st, t0, t1); break;
+        case 402: launch_vw<2, 4, SRC, DST, GATE>(gd, P, io, grid, st, t0, t1); break;
+        case 404: launch_vw<4, 4, SRC, DST, GATE>(gd, P, io, grid, st, t0, t1); break;
+        case 408: launch_vw<8, 4, SRC, DST, GATE>(gd, P, io, grid, st, t0, t1); break;
+        case 801: launch_vw<1, 8, SRC, DST, GATE>(gd, P, io, grid, st, t0, t1); break;
+        case 802: launch_vw<2, 8, SRC, DST, GATE>(gd, P, io, grid, st, t0, t1); break;
+        case 804: launch_vw<4, 8, SRC, DST, GATE>(gd, P, io, grid, st, t0, t1); break;
         default: return hipErrorInvalidValue;
         }
     }
     return hipGetLastError();
 }
 
-hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st, int wpg)
+hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st, int wpg, hipEvent_t t0,
+                       hipEvent_t t1)
 {
     IOPtrs io = {};
-    return launch_job<SRC_ARENA, DST_ARENA, true>(gd, P, io, grid, st, wpg);
+    return launch_job<SRC_ARENA, DST_ARENA, true>(gd, P, io, grid, st, wpg, t0, t1);
 }
 
 hipError_t launch_permute(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st)

@@ -108,6 +108,12 @@ struct qcz_state {
     std::vector<GraphEntry> graphs;
     DevState hds{};  // readback staging
     qcz_stats_t stats{};
+    // launch-shape autotuner: candidate (waves, grid) shapes, measured round robin
+    struct Cand { int waves, grid; double ms; uint64_t chunks; };
+    std::vector<Cand> cands;
+    int tune_next = 0;
+    int tune_rounds = 0;
+    bool tuning = false;
     std::vector<hipEvent_t> events;   // QCZ_FLAG_TIMING: start/stop per gate of a batch
     std::vector<int> timed;           // per gate of the batch: 1 if its fused kernel was timed
 };
@@ -289,8 +295,38 @@ qcz_status compact(qcz_state *s)
     HIPCHK(s, hipStreamSynchronize(s->stream));
     s->cur = 1 - s->cur;
     s->compactions += 1;
-    clear_graphs(s);
+    // captured batches stay valid: they are keyed by the arena pointer and
+    // read the stripe bases from the device header
     return reset_stripes(s, total);
+}
+
+// Expected bytes one stripe receives from gate `d`: every touched chunk gets a
+// fresh stream, sized here at twice the current mean stream (plus slack) and
+// never more than the largest stream; work-group w allocates in stripe
+// w mod nstripes, so the fullest stripe serves ceil(grid / nstripes) groups.
+uint64_t stripe_share(const qcz_state *s, const GateDesc &d)
+{
+    if (d.job_type == J_PERMUTE || d.nitems == 0) return 0;
+    const uint64_t mean = s->live / std::max<uint64_t>(1, s->nchunks);
+    const uint64_t per = std::min<uint64_t>(2 * mean + 64, (uint64_t)chunk_cap_bytes(s->C) + 4);
+    const uint64_t g = (uint64_t)grid_for(s, d);
+    const uint64_t groups = (g + (uint64_t)s->nstripes - 1) / (uint64_t)s->nstripes;
+    return (d.nitems * per * groups + g - 1) / g;
+}
+
+// Number of leading gates of `descs` whose expected allocations fit in the
+// room the fullest stripe has left.
+size_t gates_that_fit(const qcz_state *s, const std::vector<GateDesc> &descs)
+{
+    const uint64_t fill = max_stripe_fill(s);
+    const uint64_t room = s->stripe_size > fill ? s->stripe_size - fill : 0;
+    uint64_t acc = 0;
+    size_t k = 0;
+    for (; k < descs.size(); ++k) {
+        acc += stripe_share(s, descs[k]);
+        if (acc > room) break;
+    }
+    return k;
 }
 
 qcz_status launch_one(qcz_state *s, const GateDesc &d, bool timing)
@@ -298,18 +334,17 @@ qcz_status launch_one(qcz_state *s, const GateDesc &d, bool timing)
     DevPtrs P = ptrs(s);
     const int grid = grid_for(s, d);
     const bool t = timing && d.job_type != J_PERMUTE;
-    if (t) HIPCHK(s, hipEventRecord(s->events[2 * d.seq], s->stream));
+    hipEvent_t t0 = t ? s->events[2 * d.seq] : nullptr, t1 = t ? s->events[2 * d.seq + 1] : nullptr;
     hipError_t e = d.job_type == J_PERMUTE ? launch_permute(d, P, grid, s->stream)
-                                           : launch_gate(d, P, grid, s->stream, s->chunk_waves);
+                                           : launch_gate(d, P, grid, s->stream, s->chunk_waves, t0, t1);
     if (e != hipSuccess) return fail(s, QCZ_E_DEVICE, std::string("gate launch: ") + hipGetErrorString(e));
-    if (t) HIPCHK(s, hipEventRecord(s->events[2 * d.seq + 1], s->stream));
     if (timing) s->timed[(size_t)d.seq] = t ? 1 : 0;
     return QCZ_OK;
 }
 
 qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
 {
-    const bool timing = (s->cfg.flags & QCZ_FLAG_TIMING) != 0;
+    const bool timing = (s->cfg.flags & QCZ_FLAG_TIMING) != 0 || s->tuning;
     if (timing) {
         while (s->events.size() < 2 * descs.size()) {
             hipEvent_t ev;
@@ -376,11 +411,18 @@ void commit_gate(qcz_state *s, const GateLog &lg, const GateDesc &d, int k)
         S.bytes_read += lg.rd;
         S.bytes_written += lg.wr;
         S.table_bytes += 24 * lg.reenc;
-        if ((s->cfg.flags & QCZ_FLAG_TIMING) && k < (int)s->timed.size() && s->timed[(size_t)k]) {
+        if (k < (int)s->timed.size() && s->timed[(size_t)k]) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, s->events[2 * (size_t)k], s->events[2 * (size_t)k + 1]) == hipSuccess) {
-                S.timed_launches += 1;
-                S.gate_kernel_ms += ms;
+                if (s->cfg.flags & QCZ_FLAG_TIMING) {
+                    S.timed_launches += 1;
+                    S.gate_kernel_ms += ms;
+                }
+                if (s->tuning) {
+                    auto &c = s->cands[(size_t)s->tune_next];
+                    c.ms += ms;
+                    c.chunks += lg.reenc;
+                }
             }
         }
     }
@@ -398,6 +440,34 @@ void commit_gate(qcz_state *s, const GateLog &lg, const GateDesc &d, int k)
     }
     s->min_c = std::min(s->min_c, s->live);
     s->max_c = std::max(s->max_c, s->live);
+}
+
+// Move the autotuner to its next candidate; after kTuneRounds passes over
+// the candidates keep the one with the least kernel time per chunk.
+constexpr int kTuneRounds = 2;
+
+void tune_step(qcz_state *s)
+{
+    if (!s->tuning) return;
+    s->tune_next += 1;
+    if (s->tune_next < (int)s->cands.size()) return;
+    s->tune_next = 0;
+    s->tune_rounds += 1;
+    if (s->tune_rounds < kTuneRounds) return;
+    int best = -1;
+    double best_cost = 0.0;
+    for (size_t i = 0; i < s->cands.size(); ++i) {
+        const auto &c = s->cands[i];
+        if (c.chunks == 0) continue;
+        const double cost = c.ms / (double)c.chunks;
+        if (best < 0 || cost < best_cost) { best = (int)i; best_cost = cost; }
+    }
+    if (best >= 0) {
+        s->chunk_waves = s->cands[(size_t)best].waves;
+        s->grid_max = s->cands[(size_t)best].grid;
+    }
+    s->tuning = false;
+    clear_graphs(s);
 }
 
 qcz_status single_kernel_chunks(qcz_state *s, GateDesc &d, uint64_t nitems, uint64_t first)
@@ -491,6 +561,16 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     s->grid_max = cfg->grid ? (int)cfg->grid : 4 * ncu;
     if (s->grid_max > kMaxGrid) s->grid_max = kMaxGrid;
+    if (cfg->flags & QCZ_FLAG_AUTOTUNE) {
+        for (int w : {2, 4, 8}) {
+            if (s->C % (64 * w) != 0 || s->C / (64 * w) < 1) continue;
+            for (int per_cu : {2, 4, 8}) {
+                const int g = std::min(per_cu * ncu, kMaxGrid);
+                s->cands.push_back({w, g, 0.0, 0});
+            }
+        }
+        s->tuning = !s->cands.empty();
+    }
 
     s->block_levels.assign(s->nblocks, (uint8_t)(cfg->mode == QCZ_MODE_PERBLOCK ? cfg->level : 0));
     auto bail = [&](qcz_status st) {
@@ -556,13 +636,27 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
     int compacted_for = -1;  // gate index a compaction was made for
     std::vector<GateDesc> descs;
     while (idx < n_gates) {
-        const size_t B = std::min<size_t>((size_t)s->batch, n_gates - idx);
-        if (max_stripe_fill(s) > s->stripe_size / 2) {
-            qcz_status st = compact(s);
-            if (st != QCZ_OK) return st;
+        size_t B = std::min<size_t>((size_t)s->batch, n_gates - idx);
+        if (s->tuning) {
+            const auto &c = s->cands[(size_t)s->tune_next];
+            s->chunk_waves = c.waves;
+            s->grid_max = c.grid;
         }
         descs.clear();
         for (size_t k = 0; k < B; ++k) descs.push_back(lower_gate(s, gates[idx + k], (int)k));
+        // Compact before a batch that is not expected to fit, so that a full
+        // stripe seldom stops a batch midway (a stop costs a rollback and the
+        // relaunch of the rest); if it still does not fit, launch the part
+        // that does (at least one gate: the device-side check stays exact).
+        if (gates_that_fit(s, descs) < B && s->bump > s->base) {
+            qcz_status st = compact(s);
+            if (st != QCZ_OK) return st;
+        }
+        const size_t fit = gates_that_fit(s, descs);
+        if (fit < B) {
+            B = std::max<size_t>(1, fit);
+            descs.resize(B);
+        }
         const uint64_t live0 = s->live, bump0 = s->bump;
         qcz_status st = launch_batch(s, descs);
         if (st != QCZ_OK) return st;
@@ -575,10 +669,12 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
             for (size_t k = 0; k < B; ++k) commit_gate(s, h.log[k], descs[k], (int)k);
             idx += B;
             if (applied) *applied = idx;
+            tune_step(s);
             continue;
         }
         const int sseq = h.stop_seq;
         const int reason = h.stop_reason;
+        s->stats.stops += 1;
         for (int k = 0; k < sseq; ++k) commit_gate(s, h.log[k], descs[(size_t)k], k);
         // undo the stopped gate
         const GateDesc &dstop = descs[(size_t)sseq];
@@ -641,6 +737,26 @@ qcz_status qcz_get_stats(qcz_state *s, qcz_stats_t *out)
 {
     if (!s || !out) return QCZ_E_INVAL;
     *out = s->stats;
+    out->chunk_waves = (uint32_t)s->chunk_waves;
+    out->grid = (uint32_t)s->grid_max;
+    out->tuning = s->tuning ? 1u : 0u;
+    return QCZ_OK;
+}
+
+qcz_status qcz_set_launch(qcz_state *s, uint32_t chunk_waves, uint32_t grid)
+{
+    if (!s) return QCZ_E_INVAL;
+    if (chunk_waves) {
+        if ((chunk_waves != 2 && chunk_waves != 4 && chunk_waves != 8) || s->C % (64 * (int)chunk_waves) != 0)
+            return fail(s, QCZ_E_INVAL, "unsupported chunk_waves");
+        s->chunk_waves = (int)chunk_waves;
+    }
+    if (grid) {
+        if (grid > (uint32_t)kMaxGrid) return fail(s, QCZ_E_INVAL, "grid too large");
+        s->grid_max = (int)grid;
+    }
+    s->tuning = false;
+    clear_graphs(s);
     return QCZ_OK;
 }
 

@@ -1,0 +1,119 @@
+"""Summarise rocprofv3 CSV output for the fused gate kernel.
+
+Usage:
+  python -m paper_1911_04034_amd.profile_summary stats  <kernel_stats.csv> <command> > profiles/X.txt
+  python -m paper_1911_04034_amd.profile_summary traffic <fetch_dir> <write_dir> <copy_fetch_dir> \
+         <copy_write_dir> <copy_bytes> <last_n_dispatches> <command> > profiles/Y.txt
+
+The traffic summary scales the per-dispatch FETCH_SIZE / WRITE_SIZE of the
+fused kernel by the ratio (known bytes / counter) that the same counters read
+for a plain device copy, and records a hash of the kernel source so readers
+can tell whether the counters still describe the current kernel.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import os
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(HERE, "csrc", "qcz_kernels.hip")
+FUSED = "job_kernel<16, 2, 0, 0, true>"
+
+
+def kernel_hash() -> str:
+    """Hash of the device code (the file up to its host launchers)."""
+    src = open(KERNEL_SRC, "rb").read()
+    cut = src.find(b"// host launchers")
+    return hashlib.sha256(src[:cut] if cut > 0 else src).hexdigest()[:16]
+
+
+def _counter_rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    rows = []
+    for f in files:
+        rows += list(csv.DictReader(open(f)))
+    return rows
+
+
+def per_dispatch(d, counter, name_part, last=0):
+    """Mean over dispatches of `counter` (summed over its dimensions) for kernels matching name_part;
+    with last > 0 only the last `last` dispatches (the benchmark's timed region) count."""
+    acc = {}
+    for r in _counter_rows(d):
+        if r["Counter_Name"] != counter or name_part not in r["Kernel_Name"]:
+            continue
+        key = int(r["Dispatch_Id"])
+        acc.setdefault(key, 0.0)
+        acc[key] += float(r["Counter_Value"])
+    vals = [acc[k] for k in sorted(acc)]
+    if last > 0:
+        vals = vals[-last:]
+    return (statistics.mean(vals) if vals else float("nan")), len(vals)
+
+
+def stats(path, command, trace=None, last=0):
+    rows = list(csv.DictReader(open(path)))
+    if trace:
+        tr = [r for r in csv.DictReader(open(trace)) if FUSED in r["Kernel_Name"]]
+        tr.sort(key=lambda r: int(r["Start_Timestamp"]))
+        d = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in tr][-int(last):]
+        print("# fused kernel, last %d dispatches (the timed region): mean %.1f ns" % (len(d), statistics.mean(d)))
+    print("# rocprofv3 --kernel-trace --stats summary")
+    print("# command: %s" % command)
+    print("# kernel source sha256[:16]: %s" % kernel_hash())
+    print("%-70s %8s %14s %12s %8s" % ("kernel", "calls", "total_ns", "avg_ns", "pct"))
+    for r in rows[:15]:
+        print("%-70s %8s %14s %12.1f %8.2f" % (r["Name"][:70], r["Calls"], r["TotalDurationNs"],
+                                              float(r["AverageNs"]), float(r["Percentage"])))
+
+
+def traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, last, command):
+    copy_bytes = float(copy_bytes)
+    last = int(last)
+    cf, _ = per_dispatch(cfetch_dir, "FETCH_SIZE", "copyBuffer")
+    cw, _ = per_dispatch(cwrite_dir, "WRITE_SIZE", "copyBuffer")
+    f, nf = per_dispatch(fetch_dir, "FETCH_SIZE", FUSED, last)
+    w, nw = per_dispatch(write_dir, "WRITE_SIZE", FUSED, last)
+    kf = copy_bytes / cf if cf else float("nan")
+    kw = copy_bytes / cw if cw else float("nan")
+    print("# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, fused gate kernel %s" % FUSED)
+    print("# command: %s" % command)
+    print("kernel_source_sha256_16: %s" % kernel_hash())
+    print("copy_bytes: %d" % copy_bytes)
+    print("copy_fetch_counter: %.4f" % cf)
+    print("copy_write_counter: %.4f" % cw)
+    print("fetch_scale_bytes_per_unit: %.4f" % kf)
+    print("write_scale_bytes_per_unit: %.4f" % kw)
+    print("dispatches_fetch: %d" % nf)
+    print("dispatches_write: %d" % nw)
+    print("fetch_counter_per_dispatch: %.4f" % f)
+    print("write_counter_per_dispatch: %.4f" % w)
+    print("traffic_bytes_per_dispatch: %.1f" % (f * kf + w * kw))
+
+
+def read_traffic(path):
+    """(bytes per dispatch, kernel hash) from a traffic summary, or (None, None)."""
+    if not os.path.exists(path):
+        return None, None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    try:
+        return float(vals["traffic_bytes_per_dispatch"]), vals["kernel_source_sha256_16"]
+    except (KeyError, ValueError):
+        return None, None
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], *(sys.argv[4:6]))
+    elif sys.argv[1] == "traffic":
+        traffic(*sys.argv[2:9])
+    else:
+        raise SystemExit(__doc__)

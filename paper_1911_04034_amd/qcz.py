@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libqcz.so")
 MODE_LOSSLESS, MODE_FIXED, MODE_ADAPTIVE, MODE_PERBLOCK = 0, 1, 2, 3
 FLAG_GRAPH = 1
 FLAG_TIMING = 2
+FLAG_AUTOTUNE = 4
 STATUS = {0: "QCZ_OK", -1: "QCZ_E_INVAL", -2: "QCZ_E_NOMEM", -3: "QCZ_E_DEVICE", -4: "QCZ_E_FORMAT",
           -5: "QCZ_E_STATE"}
 
@@ -50,14 +51,15 @@ class Stats(ctypes.Structure):
                 ("chunks_reencoded", ctypes.c_uint64), ("amps_touched", ctypes.c_uint64),
                 ("bytes_read", ctypes.c_uint64), ("bytes_written", ctypes.c_uint64),
                 ("table_bytes", ctypes.c_uint64), ("timed_launches", ctypes.c_uint64),
-                ("gate_kernel_ms", ctypes.c_double)]
+                ("gate_kernel_ms", ctypes.c_double), ("chunk_waves", ctypes.c_uint32), ("grid", ctypes.c_uint32),
+                ("tuning", ctypes.c_uint32), ("stops", ctypes.c_uint32)]
 
 
 EXPORTED = [
     "qcz_pool_bytes_min", "qcz_create", "qcz_apply_gates", "qcz_read_amplitudes", "qcz_decode_chunks_to",
     "qcz_moments", "qcz_sample", "qcz_footprint", "qcz_export_chunk", "qcz_import_chunk", "qcz_set_block_levels",
     "qcz_chunk_sizes", "qcz_num_chunks", "qcz_chunk_doubles", "qcz_last_error", "qcz_destroy", "qcz_chunk_cap",
-    "qcz_encode_chunks", "qcz_decode_chunks", "qcz_get_stats", "qcz_reset_stats",
+    "qcz_encode_chunks", "qcz_decode_chunks", "qcz_get_stats", "qcz_reset_stats", "qcz_set_launch",
 ]
 
 _lib = None
@@ -114,6 +116,8 @@ def load():
     L.qcz_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.qcz_reset_stats.restype = i32
     L.qcz_reset_stats.argtypes = [vp]
+    L.qcz_set_launch.restype = i32
+    L.qcz_set_launch.argtypes = [vp, u32, u32]
     _lib = L
     return L
 
@@ -239,6 +243,9 @@ class State:
 
     def reset_stats(self):
         self._check(self._lib.qcz_reset_stats(self._h), "qcz_reset_stats")
+
+    def set_launch(self, chunk_waves: int = 0, grid: int = 0):
+        self._check(self._lib.qcz_set_launch(self._h, chunk_waves, grid), "qcz_set_launch")
 
     def export_chunk(self, c: int) -> bytes:
         cap = chunk_cap(self.C)

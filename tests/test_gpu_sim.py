@@ -169,6 +169,42 @@ def test_compaction_keeps_bytes():
     assert_same_chunks(g, o, "after compactions")
 
 
+def test_arena_exhausted_keeps_last_committed_state():
+    """A pool whose arena cannot hold the lossless state: the gate that
+    overflows it stops on the device, is rolled back, compacted for and
+    retried once; the call then fails with NOMEM and the state is the
+    oracle's after the gates that completed."""
+    n, bl = 13, 8
+    from paper_1911_04034_amd import qcz
+    gates = cc.random_circuit_small(n, depth=12, seed=31)
+    pmin = qcz.load().qcz_pool_bytes_min(__import__("ctypes").byref(qcz.Config(n, bl, 0, 0, 0, 0, 0, 0, 0)))
+    g, o = make(n, bl, oq.MODE_LOSSLESS, 0, pool_bytes=pmin, batch=16)
+    say("arena exhaustion run")
+    rc, applied = g.try_apply(gates)
+    assert rc == -2 and 0 < applied < len(gates)
+    assert g.stats()["stops"] >= 1
+    o.apply(gates[:applied])
+    assert_same_chunks(g, o, "after arena NOMEM")
+
+
+def test_autotune_keeps_bytes_and_settles():
+    """The launch-shape autotuner only changes how kernels are launched:
+    bytes stay the oracle's while it measures and after it has chosen."""
+    n, bl = 14, 10
+    from paper_1911_04034_amd import qcz
+    gates = cc.random_circuit_small(n, depth=40, seed=12)
+    g, o = make(n, bl, oq.MODE_FIXED, 2, flags=qcz.FLAG_AUTOTUNE, batch=4)
+    assert g.stats()["tuning"] == 1
+    say("autotune run")
+    for k in range(0, len(gates), 4):
+        g.apply(gates[k:k + 4])
+        o.apply(gates[k:k + 4])
+    st = g.stats()
+    assert st["tuning"] == 0
+    assert st["chunk_waves"] in (2, 4, 8) and st["grid"] > 0
+    assert_same_chunks(g, o, "after autotuning")
+
+
 def test_sampled_gates_full_size_grover24():
     """At the benchmark shape (24 qubits, 2^16-amplitude blocks) compare
     sampled gates: the oracle re-runs one unit of the blockwise loop on the
