@@ -480,12 +480,23 @@ int oq_chunk_role(const oq_gate *g, int cb, uint64_t c)
     }
 }
 
+/* Sum of squares of C doubles, in index order. */
+static double sum_sq(const double *x, int C)
+{
+    double a = 0.0;
+    for (int i = 0; i < C; ++i) a += x[i] * x[i];
+    return a;
+}
+
 /* One unit of the blockwise loop: decompress chunk c0 (and c1 for a pair
  * job), update its amplitudes, recompress each at its own level.  For a
- * single-chunk job pass in1 = NULL.  Returns 0 or -1. */
-int oq_gate_job(const oq_gate *g, int cb, int C,
-                uint64_t c0, const uint8_t *in0, size_t len0, int level0, uint8_t *out0, size_t *olen0,
-                uint64_t c1, const uint8_t *in1, size_t len1, int level1, uint8_t *out1, size_t *olen1)
+ * single-chunk job pass in1 = NULL.  If n2 is not NULL, n2[k] receives the
+ * squared norm of output chunk k after the update and before truncation, and
+ * n2[2 + k] that of the values its new stream holds.  Returns 0 or -1. */
+static int gate_job_n2(const oq_gate *g, int cb, int C,
+                       uint64_t c0, const uint8_t *in0, size_t len0, int level0, uint8_t *out0, size_t *olen0,
+                       uint64_t c1, const uint8_t *in1, size_t len1, int level1, uint8_t *out1, size_t *olen1,
+                       double *n2)
 {
     uint64_t ca = (uint64_t)C / 2;
     int two = in1 != NULL;
@@ -499,11 +510,28 @@ int oq_gate_job(const oq_gate *g, int cb, int C,
         lay.half = ca;
         lay.pair_units = two;
         apply_local(g, psi, two ? 2 * ca : ca, &lay);
+        if (n2) {
+            n2[0] = sum_sq(psi, C);
+            n2[1] = two ? sum_sq(psi + C, C) : 0.0;
+        }
         *olen0 = oq_encode_chunk(psi, C, level0, out0);
         if (two) *olen1 = oq_encode_chunk(psi + C, C, level1, out1);
+        if (n2) {
+            rc = oq_decode_chunk(out0, *olen0, C, psi);
+            if (rc == 0 && two) rc = oq_decode_chunk(out1, *olen1, C, psi + C);
+            n2[2] = sum_sq(psi, C);
+            n2[3] = two ? sum_sq(psi + C, C) : 0.0;
+        }
     }
     free(psi);
     return rc;
+}
+
+int oq_gate_job(const oq_gate *g, int cb, int C,
+                uint64_t c0, const uint8_t *in0, size_t len0, int level0, uint8_t *out0, size_t *olen0,
+                uint64_t c1, const uint8_t *in1, size_t len1, int level1, uint8_t *out1, size_t *olen1)
+{
+    return gate_job_n2(g, cb, C, c0, in0, len0, level0, out0, olen0, c1, in1, len1, level1, out1, olen1, NULL);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -520,7 +548,8 @@ typedef struct {
     uint64_t budget;
     uint8_t *block_level;     /* used in per-block mode */
     double flb;               /* fidelity lower bound, Eq. (11) */
-    double flb_weighted;      /* per-block mode: prod(1 - sum_b w_b d_b) */
+    double flb_weighted;      /* per-block mode: prod over gates of (1 - wd / nlb) */
+    double norm2;             /* per-block mode: squared norm of the stored state */
     uint64_t gates_applied, lossy_steps;
     uint64_t min_compressed, max_compressed;
     uint8_t *scratch_out[2];
@@ -557,6 +586,7 @@ oq_sim *oq_sim_create(int n, int block_log2, int mode, int fixed_level, uint64_t
     if (mode == OQ_MODE_PERBLOCK) memset(s->block_level, fixed_level, s->nblocks);
     s->flb = 1.0;
     s->flb_weighted = 1.0;
+    s->norm2 = 1.0;
     size_t cap = oq_chunk_cap(s->C);
     s->scratch_out[0] = (uint8_t *)malloc(cap);
     s->scratch_out[1] = (uint8_t *)malloc(cap);
@@ -594,11 +624,17 @@ typedef struct { uint64_t c; uint8_t *old; uint32_t old_len; } oq_undo;
 
 /* Apply gate g to the compressed state.  Old chunk versions are returned in
  * undo[] (count in *nundo) so the caller can commit or roll back.  Sets
- * *reencoded to the number of chunks recompressed. */
-static int sim_gate(oq_sim *s, const oq_gate *g, oq_undo *undo, uint64_t *nundo, uint64_t *reencoded)
+ * *reencoded to the number of chunks recompressed, *wd to the sum over them
+ * of delta(level of the chunk) * (squared norm of the chunk after the update,
+ * before truncation) and *lost to the squared norm the truncation removed. */
+static int sim_gate(oq_sim *s, const oq_gate *g, oq_undo *undo, uint64_t *nundo, uint64_t *reencoded, double *wd,
+                    double *lost)
 {
     *nundo = 0;
     *reencoded = 0;
+    *wd = 0.0;
+    *lost = 0.0;
+    double n2[4];
     for (uint64_t c = 0; c < s->nchunks; ++c) {
         int role = oq_chunk_role(g, s->cb, c);
         if (role == OQ_JOB_NONE || role == OQ_JOB_PAIR_HI || role == OQ_JOB_PERMUTE_HI) continue;
@@ -613,8 +649,10 @@ static int sim_gate(oq_sim *s, const oq_gate *g, oq_undo *undo, uint64_t *nundo,
         }
         size_t o0 = 0, o1 = 0;
         if (role == OQ_JOB_SINGLE) {
-            if (oq_gate_job(g, s->cb, s->C, c, s->chunk[c], s->len[c], chunk_level(s, c), s->scratch_out[0], &o0,
-                            0, NULL, 0, 0, NULL, NULL) != 0) return -1;
+            if (gate_job_n2(g, s->cb, s->C, c, s->chunk[c], s->len[c], chunk_level(s, c), s->scratch_out[0], &o0,
+                            0, NULL, 0, 0, NULL, NULL, n2) != 0) return -1;
+            *wd += oq_delta_tab[chunk_level(s, c)] * n2[0];
+            *lost += n2[0] - n2[2];
             undo[(*nundo)++] = (oq_undo){c, s->chunk[c], s->len[c]};
             s->chunk[c] = (uint8_t *)malloc(o0);
             memcpy(s->chunk[c], s->scratch_out[0], o0);
@@ -622,8 +660,12 @@ static int sim_gate(oq_sim *s, const oq_gate *g, oq_undo *undo, uint64_t *nundo,
             *reencoded += 1;
         } else { /* OQ_JOB_PAIR_LO */
             uint64_t c1 = c | (UINT64_C(1) << (g->target - s->cb));
-            if (oq_gate_job(g, s->cb, s->C, c, s->chunk[c], s->len[c], chunk_level(s, c), s->scratch_out[0], &o0,
-                            c1, s->chunk[c1], s->len[c1], chunk_level(s, c1), s->scratch_out[1], &o1) != 0) return -1;
+            if (gate_job_n2(g, s->cb, s->C, c, s->chunk[c], s->len[c], chunk_level(s, c), s->scratch_out[0], &o0,
+                            c1, s->chunk[c1], s->len[c1], chunk_level(s, c1), s->scratch_out[1], &o1, n2) != 0)
+                return -1;
+            *wd += oq_delta_tab[chunk_level(s, c)] * n2[0];
+            *wd += oq_delta_tab[chunk_level(s, c1)] * n2[1];
+            *lost += (n2[0] - n2[2]) + (n2[1] - n2[3]);
             undo[(*nundo)++] = (oq_undo){c, s->chunk[c], s->len[c]};
             undo[(*nundo)++] = (oq_undo){c1, s->chunk[c1], s->len[c1]};
             s->chunk[c] = (uint8_t *)malloc(o0);
@@ -659,27 +701,6 @@ static void sim_rollback(oq_sim *s, const oq_gate *g, oq_undo *undo, uint64_t nu
     }
 }
 
-/* Sum over blocks of w_b * delta_b with w_b = sum of |a|^2 in block b, for
- * the per-block ledger (the paper's Eq. (10) argument with a pointwise
- * bound that varies by block). */
-static double weighted_delta(const oq_sim *s)
-{
-    double *psi = (double *)malloc(sizeof(double) * (size_t)s->C);
-    double acc = 0.0;
-    uint64_t cpb = UINT64_C(1) << (s->bl - s->cb);
-    for (uint64_t b = 0; b < s->nblocks; ++b) {
-        double w = 0.0;
-        for (uint64_t k = 0; k < cpb; ++k) {
-            uint64_t c = b * cpb + k;
-            oq_decode_chunk(s->chunk[c], s->len[c], s->C, psi);
-            for (int i = 0; i < s->C; ++i) w += psi[i] * psi[i];
-        }
-        acc += w * oq_delta_tab[s->block_level[b]];
-    }
-    free(psi);
-    return acc;
-}
-
 /* Apply a gate list.  Returns the number of gates applied (all of them on
  * success); a negative value -(k+1) reports that gate k could not be fitted
  * into the budget even at the loosest level (-2 - k: malformed gate k). */
@@ -691,8 +712,9 @@ long oq_sim_apply(oq_sim *s, const oq_gate *gates, size_t ngates)
         const oq_gate *g = &gates[k];
         if (oq_gate_check(g, s->n) != 0) { free(undo); return -2 - (long)k; }
         uint64_t nundo = 0, reenc = 0;
+        double wd = 0.0, lost = 0.0;
         for (;;) {
-            if (sim_gate(s, g, undo, &nundo, &reenc) != 0) { free(undo); return -2 - (long)k; }
+            if (sim_gate(s, g, undo, &nundo, &reenc, &wd, &lost) != 0) { free(undo); return -2 - (long)k; }
             uint64_t cbytes = oq_sim_compressed_bytes(s);
             if (s->mode != OQ_MODE_ADAPTIVE || s->budget == 0 || cbytes <= s->budget) {
                 sim_commit(undo, nundo);
@@ -706,8 +728,15 @@ long oq_sim_apply(oq_sim *s, const oq_gate *gates, size_t ngates)
         }
         if (reenc > 0) {
             if (s->mode == OQ_MODE_PERBLOCK) {
-                double wd = weighted_delta(s);
-                if (wd > 0.0) { s->flb_weighted *= (1.0 - wd); s->lossy_steps += 1; }
+                /* Sec. 3.8 with a bound that varies by chunk: truncating v at
+                 * relative error delta_c per value keeps <v|T(v)> at least
+                 * |v|^2 - wd, so the step fidelity is at least 1 - wd/|v|^2,
+                 * and |v|^2 is the norm before the gate (unitary update). */
+                if (wd > 0.0) {
+                    s->flb_weighted *= (1.0 - wd / s->norm2);
+                    s->lossy_steps += 1;
+                }
+                s->norm2 -= lost;
             } else if (s->level > 0) {
                 s->flb *= (1.0 - oq_delta_tab[s->level]);   /* Eq. (11) */
                 s->lossy_steps += 1;
