@@ -198,6 +198,83 @@ uint32_t qcz_chunk_doubles(const qcz_state *st);
 const char *qcz_last_error(const qcz_state *st);
 void qcz_destroy(qcz_state *st);
 
+/* ---- per-block level selection ------------------------------------------
+ * Sec. 3.7 relaxes one error bound for the whole state when memory runs
+ * short; these calls choose one bound per block instead.  The Sec. 3.8
+ * argument carries over when each block b is truncated at relative error
+ * delta_b per value: one step keeps the fidelity at least
+ * 1 - sum_b w_b delta_b, w_b = the block's share of the squared norm.  A
+ * per-step budget beta on that sum gives the Eq. (11) product of a uniform
+ * bound beta.  In QCZ_MODE_PERBLOCK the state's ledger
+ * (fidelity_lower_bound) multiplies, per gate, 1 - (sum over re-encoded
+ * chunks of delta(level) * |chunk before truncation|^2) / |state|^2. */
+
+/* 16 float features per block (device, n_blocks x 16, row major) and the
+ * squared norm of each block (device, n_blocks doubles; may be NULL), from
+ * the stored values: f0 log2(max(n2_b * n_blocks, 2^-60))/64; f1 zero
+ * fraction; f2 (mean biased exponent of nonzero values - 1023)/64; f3
+ * exponent range/64; f4..f6 fraction of values whose top 8/16/24 bits equal
+ * the previous value's (a chunk's first value is compared with +0.0); f7
+ * fraction of sign changes; f8 fraction of chunks stored as two constants;
+ * f9 stream bytes / raw bytes of the block; f10 block level/5; f11 (largest
+ * biased exponent - 1023)/64 (-17 for an all-zero block); f12
+ * max(log10(beta), -20)/5 (-4 for beta = 0); f13 log2(raw / stream bytes of
+ * the state)/16; f14 log2(n_blocks)/16; f15 block_log2/32.  QCZ_E_INVAL for
+ * beta < 0 or blocks of more than 65536 chunks. */
+qcz_status qcz_block_stats(qcz_state *st, double beta, float *dev_features, double *dev_norms);
+
+/* Padded stream bytes of every block re-encoded at each level: device
+ * n_blocks x 6 u64 (block major), overwritten. */
+qcz_status qcz_block_level_sizes(qcz_state *st, uint64_t *dev_sizes);
+
+/* Host call, no device work.  Training labels: for sizes s[b][l] (host,
+ * n_blocks x 6) and weights w (host, >= 0), the level of each block that
+ * minimises s[b][l] + lambda * w_b * delta_l (ties: the tighter level), for
+ * the smallest lambda among 0 and the values where some block's choice
+ * changes whose choice satisfies sum_b w_b delta_b <= beta * (1 + 2^-20)
+ * (sum in block order).  Output: levels (host, n_blocks). */
+qcz_status qcz_label_levels(const uint64_t *sizes, const double *w, uint64_t n_blocks, double beta,
+                            uint8_t *levels);
+
+/* Host call.  Budget projection: while sum_b w_b delta(levels[b]) exceeds
+ * beta * (1 + 2^-20), lower by one the level of the block with the largest
+ * w_b delta(levels[b]) (lowest index on ties).  levels: host, in/out. */
+qcz_status qcz_project_levels(const double *w, uint64_t n_blocks, double beta, uint8_t *levels);
+
+/* Selector network 16 -> 64 -> 64 -> 6: ReLU hidden layers, softmax over
+ * the six levels.  Parameters: 5638 floats on the device, packed W1 (64x16,
+ * row major), b1, W2 (64x64), b2, W3 (6x64), b3.  Forward pass over
+ * n_samples rows of 16 features (device): probabilities (device,
+ * n_samples x 6; may be NULL) and the most probable level (device, u8;
+ * may be NULL; lowest level on ties).  Asynchronous on hip_stream. */
+qcz_status qcz_mlp_forward(const float *dev_params, const float *dev_x, uint64_t n_samples, float *dev_probs,
+                           uint8_t *dev_levels, void *hip_stream);
+
+/* Device workspace bytes that qcz_mlp_train_step needs for n_samples. */
+size_t qcz_mlp_workspace_bytes(uint64_t n_samples);
+
+/* One full-batch training step on the device: loss = mean cross-entropy of
+ * labels (device u8 in 0..5); dev_grad (5638 floats, may be NULL) receives
+ * its gradient; dev_loss (1 float, may be NULL) the loss before the step.
+ * step >= 1 then applies Adam step number `step` (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias corrected) to dev_params with moments dev_m / dev_v (5638
+ * floats each, zero before step 1); step 0 computes only loss and gradient.
+ * dev_work: caller-owned device memory of qcz_mlp_workspace_bytes. */
+qcz_status qcz_mlp_train_step(float *dev_params, float *dev_m, float *dev_v, const float *dev_x,
+                              const uint8_t *dev_labels, uint64_t n_samples, float lr, uint32_t step,
+                              float *dev_grad, float *dev_loss, void *dev_work, size_t work_bytes,
+                              void *hip_stream);
+
+/* QCZ_MODE_PERBLOCK: block features -> network -> most probable level per
+ * block -> budget projection with w_b = n2_b / sum n2 -> block levels of the
+ * state.  out_levels (host, n_blocks; may be NULL) receives them. */
+qcz_status qcz_select_levels(qcz_state *st, const float *dev_params, double beta, uint8_t *out_levels);
+
+/* QCZ_MODE_PERBLOCK: make qcz_apply_gates call qcz_select_levels before the
+ * first gate and again every `period` gates.  dev_params must stay valid
+ * while attached; NULL detaches. */
+qcz_status qcz_set_selector(qcz_state *st, const float *dev_params, double beta, uint32_t period);
+
 /* ---- codec entry points (no state) -------------------------------------- */
 
 /* Largest stream of a chunk of C doubles (bytes). */

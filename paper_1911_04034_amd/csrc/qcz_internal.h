@@ -47,7 +47,9 @@ struct GateLog {
     uint64_t reenc;  // chunks re-encoded by the gate
     uint64_t rd;     // padded stream bytes read by those jobs
     uint64_t wr;     // padded stream bytes written
-    uint64_t pad[3];
+    double wd;       // per-block levels: sum over re-encoded chunks of delta(level) * |chunk before truncation|^2
+    double lost;     // per-block levels: squared norm removed by the truncation
+    uint64_t pad;
 };
 
 // Device-resident control block (first bytes of the pool).  The arena is
@@ -78,6 +80,7 @@ struct DevState {
 // per-workgroup partial sums of a gate launch (no same-address atomics)
 struct WgPart {
     uint64_t delta, reenc, rd, wr;
+    double wd, lost;
 };
 
 // Pointers of one state, passed by value to every kernel.
@@ -106,7 +109,20 @@ struct IOPtrs {
     const uint64_t *list;       // readout: chunk ids (nullptr: positions are chunk ids + first)
     uint64_t first;
     double *partials;           // moments: [gridDim.x][4]
+    double *cstats;             // chunk statistics: [chunk][kChunkStats]
+    uint64_t *lsizes;           // per-level sizes: [block][kLevels] padded bytes (accumulated)
 };
+
+// Per-chunk statistics record (doubles): sum of squares, nonzero values, sum /
+// max / min of their biased exponents, values whose top 8 / 16 / 24 bits equal
+// the previous value's, sign changes, stored as two constants, padded bytes.
+constexpr int kChunkStats = 12;
+enum { CS_N2 = 0, CS_NZ, CS_ESUM, CS_EMAX, CS_EMIN, CS_EQ8, CS_EQ16, CS_EQ24, CS_SGN, CS_CONST2, CS_BYTES };
+
+// Selector network 16 -> 64 -> 64 -> 6 (float parameters, packed W1 b1 W2 b2 W3 b3).
+constexpr int kNIn = 16, kNH = 64, kNOut = 6;
+constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kNH * kNIn, kOffW2 = kOffB1 + kNH, kOffB2 = kOffW2 + kNH * kNH,
+              kOffW3 = kOffB2 + kNH, kOffB3 = kOffW3 + kNOut * kNH, kNParams = kOffB3 + kNOut;   // 5638
 
 inline uint32_t chunk_cap_bytes(int C) { return 4u + 4u * (uint32_t)((C + 15) / 16) + 8u * (uint32_t)C; }
 
@@ -119,6 +135,24 @@ hipError_t launch_encode_raw(const GateDesc &gd, const DevPtrs &P, const IOPtrs 
 hipError_t launch_decode_slots(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);
 hipError_t launch_readout(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);
 hipError_t launch_moments(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);
+hipError_t launch_chunk_stats(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);
+hipError_t launch_level_sizes(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);
+hipError_t launch_zero_u64(uint64_t *p, uint64_t n, hipStream_t st);
+
+// Selector kernels (qcz_select.hip).
+struct FeatCtx {
+    double f12, f13, f14, f15;   // context features shared by all blocks
+    int32_t cpb;                 // chunks per block
+    int32_t block_log2;
+    uint64_t nblocks;
+};
+hipError_t launch_block_features(const double *cstats, const uint8_t *block_level, const FeatCtx &ctx, uint64_t nb,
+                                 float *X, double *n2, hipStream_t st);
+hipError_t launch_mlp_forward(const float *params, const float *X, uint64_t N, float *probs, uint8_t *argmax,
+                              hipStream_t st);
+size_t mlp_workspace_bytes(uint64_t N);
+hipError_t launch_mlp_train(float *params, float *m, float *v, const float *X, const uint8_t *labels, uint64_t N,
+                            float lr, uint32_t step, float *grad_out, float *loss_out, void *work, hipStream_t st);
 hipError_t launch_fill_table(const DevPtrs &P, uint64_t entry0, uint64_t entry_rest, hipStream_t st);
 hipError_t launch_compact(const DevPtrs &P, uint32_t *dst_arena, uint64_t *scratch, uint64_t *block_sums,
                           uint64_t nblocks_scan, hipStream_t st);

@@ -30,7 +30,10 @@ namespace qcz {
 __constant__ int kSig[kLevels] = {64, 29, 26, 22, 19, 16};
 
 enum { SRC_ARENA = 0, SRC_RAW = 1, SRC_SLOTS = 2 };
-enum { DST_ARENA = 0, DST_RAW = 1, DST_SLOTS = 2, DST_MOMENTS = 3 };
+enum { DST_ARENA = 0, DST_RAW = 1, DST_SLOTS = 2, DST_MOMENTS = 3, DST_CSTATS = 4, DST_LSIZES = 5 };
+
+// delta of each level (0 for lossless): the per-value relative bound of Sec. 3.7
+__constant__ double kDeltaDev[kLevels] = {0.0, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1};
 
 // ---------------------------------------------------------------------------
 // bit helpers.  A value is handled as its two 32-bit words (hi, lo).  At every
@@ -648,6 +651,7 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
     __shared__ int sh_src_ok[2];
     __shared__ uint64_t sh_acc[8];
     __shared__ double sh_mom[WGS / 64][4];
+    __shared__ double sh_cs[DST == DST_CSTATS ? WGS / 64 : 1][9];
 
     DevState *ds = P.ds;
     if (DST == DST_ARENA && ds->stop) return;
@@ -664,6 +668,7 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
 
     uint64_t acc_reenc = 0, acc_rd = 0, acc_wr = 0;
     int64_t acc_delta = 0;
+    double acc_wd = 0.0, acc_lost = 0.0;   // per-block fidelity ledger terms
     double mom_re = 0.0, mom_im = 0.0, mom_n2 = 0.0;
 
     for (uint64_t job = blockIdx.x; job < gd.njobs; job += gridDim.x) {
@@ -713,9 +718,11 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
         const bool use = s ? use1 : use0;
 
         // 2. decode
+        uint32_t my_hdr = 0;
         if (SRC != SRC_RAW) {
             const uint32_t hdr0 = use0 ? buf[0][0] : (uint32_t)M_CONST2;
             const uint32_t hdr1 = use1 ? buf[1][0] : (uint32_t)M_CONST2;
+            my_hdr = s ? hdr1 : hdr0;
             const bool any_sparse = (hdr0 & 3u) == M_SPARSE || (hdr1 & 3u) == M_SPARSE;
             uint32_t th[V], tl[V];
             decode_group<V, WPG>(b, s ? hdr1 : hdr0, use, any_sparse, C, lt, slA, slB, slC, th, tl);
@@ -751,6 +758,88 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
                     mom_im += (lt & 1) ? v : 0.0;
                 }
             }
+        } else if (DST == DST_CSTATS) {
+            // 4a. statistics of the stored values of the chunk
+            double n2 = 0.0;
+            uint32_t nz = 0, esum = 0, eq8 = 0, eq16 = 0, eq24 = 0, sgn = 0;
+            int emax = -1, emin = 4096;
+            uint64_t prev = lt ? d2u(vals[first - 1]) : 0ull;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const double x = vals[first + k];
+                const uint64_t u = d2u(x);
+                n2 += x * x;
+                const bool isnz = x != 0.0;
+                const int e = (int)((u >> 52) & 0x7FFull);
+                nz += isnz ? 1u : 0u;
+                esum += isnz ? (uint32_t)e : 0u;
+                emax = isnz ? max(emax, e) : emax;
+                emin = isnz ? min(emin, e) : emin;
+                eq8 += (u >> 56) == (prev >> 56) ? 1u : 0u;
+                eq16 += (u >> 48) == (prev >> 48) ? 1u : 0u;
+                eq24 += (u >> 40) == (prev >> 40) ? 1u : 0u;
+                sgn += (u >> 63) != (prev >> 63) ? 1u : 0u;
+                prev = u;
+            }
+            for (int d = 32; d >= 1; d >>= 1) {
+                n2 += __shfl_down(n2, d, 64);
+                nz += __shfl_down(nz, d, 64);
+                esum += __shfl_down(esum, d, 64);
+                emax = max(emax, __shfl_down(emax, d, 64));
+                emin = min(emin, __shfl_down(emin, d, 64));
+                eq8 += __shfl_down(eq8, d, 64);
+                eq16 += __shfl_down(eq16, d, 64);
+                eq24 += __shfl_down(eq24, d, 64);
+                sgn += __shfl_down(sgn, d, 64);
+            }
+            double *red = sh_cs[tid >> 6];
+            if ((tid & 63) == 0) {
+                red[0] = n2; red[1] = nz; red[2] = esum; red[3] = emax; red[4] = emin;
+                red[5] = eq8; red[6] = eq16; red[7] = eq24; red[8] = sgn;
+            }
+            lds_barrier();
+            if (lt == 0 && use) {
+                double r[9];
+                for (int j = 0; j < 9; ++j) r[j] = sh_cs[s * WPG][j];
+                for (int w = 1; w < WPG; ++w) {
+                    const double *o = sh_cs[s * WPG + w];
+                    r[0] += o[0]; r[1] += o[1]; r[2] += o[2];
+                    r[3] = fmax(r[3], o[3]); r[4] = fmin(r[4], o[4]);
+                    r[5] += o[5]; r[6] += o[6]; r[7] += o[7]; r[8] += o[8];
+                }
+                double *out = io.cstats + (c - io.first) * kChunkStats;
+                for (int j = 0; j < 9; ++j) out[j] = r[j];
+                out[CS_CONST2] = (my_hdr & 3u) == (uint32_t)M_CONST2 ? 1.0 : 0.0;
+                out[CS_BYTES] = (double)(((old_entry & 0xFFFFull) + 3ull) & ~3ull);
+                out[11] = 0.0;
+            }
+        } else if (DST == DST_LSIZES) {
+            // 4b. padded size of the chunk re-encoded at every level
+            uint32_t xh[V], xl[V];
+            bool sub = false;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const uint64_t x = d2u(vals[first + k]);
+                xh[k] = (uint32_t)(x >> 32);
+                xl[k] = (uint32_t)x;
+                sub = sub || subnormal(xh[k], xl[k]);
+            }
+            const uint32_t xprev_hi = lt ? (uint32_t)(d2u(vals[first - 1]) >> 32) : 0u;
+            const uint64_t x0 = d2u(vals[0]), x1 = d2u(vals[1]);
+            const bool wsub = __any(use && sub);
+            if ((tid & 63) == 0) slS[tid >> 6] = wsub ? 1u : 0u;
+            lds_barrier();
+            uint32_t gs = 0;
+#pragma unroll
+            for (int i = 0; i < WPG; ++i) gs |= slS[s * WPG + i];
+            for (int lev = 0; lev < kLevels; ++lev) {
+                EncPlan<V> e;
+                encode_plan<V, WPG>(xh, xl, xprev_hi, x0, x1, lev, use, gs != 0, C, lt, slE, slF, e);
+                if (lt == 0 && use)
+                    atomicAdd((unsigned long long *)&io.lsizes[(c >> gd.block_shift) * kLevels + lev],
+                              (unsigned long long)((e.size + 3u) & ~3u));
+                lds_barrier();
+            }
         } else {
             // encode at the chunk's level
             uint32_t xh[V], xl[V];
@@ -777,8 +866,28 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
 #pragma unroll
             for (int i = 0; i < WPG; ++i) gs |= slS[s * WPG + i];
             const bool gsub = gs != 0;
+            // Sec. 3.8 per chunk (per-block levels): delta(level) * |v|^2 before
+            // truncation, and the squared norm the truncation removes
+            double pre = 0.0;
+            if (DST == DST_ARENA && gd.per_block) {
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const double x = vals[first + k];
+                    pre += x * x;
+                }
+            }
             EncPlan<V> e;
             encode_plan<V, WPG>(xh, xl, xprev_hi, x0, x1, lev_req, enc, gsub, C, lt, slE, slF, e);
+            if (DST == DST_ARENA && gd.per_block && enc) {
+                double post = 0.0;
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const double t = u2d(((uint64_t)e.th[k] << 32) | e.tl[k]);
+                    post += t * t;
+                }
+                acc_wd += kDeltaDev[lev_req] * pre;
+                acc_lost += pre - post;
+            }
             // claim arena space now; the returned offset is first needed after
             // the stream has been assembled in LDS, which hides the atomic
             uint64_t my_off = 0;
@@ -863,6 +972,14 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
             sh_acc[4 * s + 2] = acc_rd;
             sh_acc[4 * s + 3] = acc_wr;
         }
+        if (gd.per_block) {
+            double a = acc_wd, l = acc_lost;
+            for (int d = 32; d >= 1; d >>= 1) {
+                a += __shfl_down(a, d, 64);
+                l += __shfl_down(l, d, 64);
+            }
+            if ((tid & 63) == 0) { sh_mom[tid >> 6][0] = a; sh_mom[tid >> 6][1] = l; }
+        }
         lds_barrier();
         if (tid == 0) {
             WgPart wp;
@@ -870,6 +987,10 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
             wp.reenc = sh_acc[1] + sh_acc[5];
             wp.rd = sh_acc[2] + sh_acc[6];
             wp.wr = sh_acc[3] + sh_acc[7];
+            wp.wd = 0.0;
+            wp.lost = 0.0;
+            if (gd.per_block)
+                for (int w = 0; w < WGS / 64; ++w) { wp.wd += sh_mom[w][0]; wp.lost += sh_mom[w][1]; }
             P.wgp[blockIdx.x] = wp;
             __threadfence();
             const uint32_t prev = atomicAdd(&ds->done, 1u);
@@ -880,12 +1001,15 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
             // the last workgroup: sum the partials of all workgroups
             __threadfence();
             uint64_t d = 0, r = 0, rd = 0, wr = 0, used = 0;
+            double fw = 0.0, fl = 0.0;
             for (uint32_t g = (uint32_t)tid; g < gridDim.x; g += WGS) {
                 const WgPart wp = P.wgp[g];
                 d += wp.delta;
                 r += wp.reenc;
                 rd += wp.rd;
                 wr += wp.wr;
+                fw += wp.wd;
+                fl += wp.lost;
             }
             if (tid < kStripes) used = atomicAdd((unsigned long long *)&ds->stripe[tid][0], 0ull);
             for (int off = 32; off >= 1; off >>= 1) {
@@ -894,7 +1018,10 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
                 rd += __shfl_down(rd, off, 64);
                 wr += __shfl_down(wr, off, 64);
                 used += __shfl_down(used, off, 64);
+                fw += __shfl_down(fw, off, 64);
+                fl += __shfl_down(fl, off, 64);
             }
+            if ((tid & 63) == 0) { sh_mom[tid >> 6][2] = fw; sh_mom[tid >> 6][3] = fl; }
             uint64_t *red = reinterpret_cast<uint64_t *>(buf[0]);
             if ((tid & 63) == 0) {
                 red[5 * (tid >> 6)] = d;
@@ -923,7 +1050,10 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
             lg.reenc = r;
             lg.rd = rd;
             lg.wr = wr;
-            lg.pad[0] = lg.pad[1] = lg.pad[2] = 0;
+            lg.wd = 0.0;
+            lg.lost = 0.0;
+            for (int w = 0; w < WGS / 64; ++w) { lg.wd += sh_mom[w][2]; lg.lost += sh_mom[w][3]; }
+            lg.pad = 0;
             ds->log[gd.seq] = lg;
             const int fail = atomicExch(&ds->fail, 0);
             const int corrupt = atomicExch(&ds->corrupt, 0);
@@ -972,7 +1102,8 @@ __global__ __launch_bounds__(kWG) void permute_kernel(GateDesc gd, DevPtrs P)
         lg.bump = ds->base + used;
         lg.reenc = 0;
         lg.rd = lg.wr = 0;
-        lg.pad[0] = lg.pad[1] = lg.pad[2] = 0;
+        lg.wd = lg.lost = 0.0;
+        lg.pad = 0;
         ds->log[gd.seq] = lg;
         atomicExch(&ds->done, 0u);
     }
@@ -1165,6 +1296,29 @@ hipError_t launch_readout(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io
 hipError_t launch_moments(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st)
 {
     return launch_job<SRC_ARENA, DST_MOMENTS, false>(gd, P, io, grid, st);
+}
+
+hipError_t launch_chunk_stats(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st)
+{
+    return launch_job<SRC_ARENA, DST_CSTATS, false>(gd, P, io, grid, st);
+}
+
+hipError_t launch_level_sizes(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st)
+{
+    return launch_job<SRC_ARENA, DST_LSIZES, false>(gd, P, io, grid, st);
+}
+
+__global__ __launch_bounds__(kWG) void zero_u64_kernel(uint64_t *p, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kWG) p[i] = 0ull;
+}
+
+hipError_t launch_zero_u64(uint64_t *p, uint64_t n, hipStream_t st)
+{
+    const uint64_t blocks = (n + kWG - 1) / kWG;
+    const int grid = (int)(blocks < 4096 ? (blocks ? blocks : 1) : 4096);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(grid), dim3(kWG), 0, st, p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_table(const DevPtrs &P, uint64_t entry0, uint64_t entry_rest, hipStream_t st)

@@ -43,8 +43,12 @@ struct GraphEntry {
 };
 
 struct Layout {
-    size_t ds, table, undo, bsums, blevel, partials, wgp, scratch, arena0, arena1, arena_bytes, end;
+    size_t ds, table, undo, bsums, blevel, partials, wgp, scratch, cstats, feat, fn2, fsel, arena0, arena1,
+        arena_bytes, end;
 };
+
+// chunk statistics records held at once (blocks are processed in batches)
+constexpr uint64_t kStatChunks = 65536;
 
 int chunk_log2_for(int bl) { return bl < 10 ? bl : 10; }
 
@@ -65,6 +69,10 @@ Layout layout_for(int n, int bl, size_t pool_bytes)
     L.wgp = o; o = align256(o + sizeof(WgPart) * (size_t)kMaxGrid);
     const size_t slot = ((chunk_cap_bytes(C) + 3) & ~3u);
     L.scratch = o; o = align256(o + (size_t)kScratchChunks * (8 * (size_t)C + slot + 16) + 4096);
+    L.cstats = o; o = align256(o + 8 * kChunkStats * (size_t)std::min<uint64_t>(nchunks, kStatChunks));
+    L.feat = o; o = align256(o + 4 * kNIn * (size_t)nblocks);
+    L.fn2 = o; o = align256(o + 8 * (size_t)nblocks);
+    L.fsel = o; o = align256(o + (size_t)nblocks);
     L.end = o;
     size_t rest = pool_bytes > o ? pool_bytes - o : 0;
     L.arena_bytes = (rest / 2) & ~(size_t)255;
@@ -103,7 +111,13 @@ struct qcz_state {
     uint64_t stripe_fill[kStripes] = {};
     uint64_t gates_applied = 0, lossy_steps = 0, min_c = 0, max_c = 0, compactions = 0;
     double flb = 1.0;
+    double norm2 = 1.0;                   // squared norm of the stored state (per-block ledger)
     std::vector<uint8_t> block_levels;
+    // learned per-block level selection, re-run every sel_period gates
+    const float *sel_params = nullptr;
+    double sel_beta = 0.0;
+    uint64_t sel_period = 0, sel_since = 0;
+    bool sel_fresh = false;
     std::string err;
     std::vector<GraphEntry> graphs;
     DevState hds{};  // readback staging
@@ -426,17 +440,18 @@ void commit_gate(qcz_state *s, const GateLog &lg, const GateDesc &d, int k)
             }
         }
     }
-    if (lg.reenc > 0) {
-        double d = 0.0;
-        if (s->cfg.mode == QCZ_MODE_PERBLOCK) {
-            for (uint8_t lv : s->block_levels) d = std::max(d, kDelta[lv]);
-        } else {
-            d = kDelta[s->level];
-        }
-        if (d > 0.0) {
-            s->flb *= (1.0 - d);   // Sec. 3.8, Eq. (11)
+    if (s->cfg.mode == QCZ_MODE_PERBLOCK) {
+        // Sec. 3.8 with a bound that varies by chunk: the step keeps the
+        // fidelity at least 1 - wd / |state|^2, wd = sum over re-encoded
+        // chunks of delta(level) * |chunk before truncation|^2
+        if (lg.wd > 0.0) {
+            s->flb *= (1.0 - lg.wd / s->norm2);
             s->lossy_steps += 1;
         }
+        s->norm2 -= lg.lost;
+    } else if (lg.reenc > 0 && kDelta[s->level] > 0.0) {
+        s->flb *= (1.0 - kDelta[s->level]);   // Sec. 3.8, Eq. (11)
+        s->lossy_steps += 1;
     }
     s->min_c = std::min(s->min_c, s->live);
     s->max_c = std::max(s->max_c, s->live);
@@ -481,6 +496,101 @@ qcz_status single_kernel_chunks(qcz_state *s, GateDesc &d, uint64_t nitems, uint
     while ((1ull << bits) < nitems) ++bits;
     d.nchunk_bits = bits;
     (void)first;
+    return QCZ_OK;
+}
+
+// Statistics of every block: 16 float features into X (device, nblocks x 16)
+// and the squared norm of each block into n2 (device, may be null).
+qcz_status block_stats(qcz_state *s, double beta, float *X, double *n2)
+{
+    const int shift = s->bl - s->cb;
+    const uint64_t cpb = 1ull << shift;
+    if (cpb > kStatChunks) return fail(s, QCZ_E_INVAL, "blocks of more than 65536 chunks");
+    FeatCtx ctx{};
+    ctx.f12 = beta > 0.0 ? std::max(std::log10(beta), -20.0) / 5.0 : -4.0;
+    ctx.f13 = std::log2(std::ldexp(1.0, s->n + 4) / (double)s->live) / 16.0;
+    ctx.f14 = std::log2((double)s->nblocks) / 16.0;
+    ctx.f15 = (double)s->bl / 32.0;
+    ctx.cpb = (int32_t)cpb;
+    ctx.block_log2 = s->bl;
+    ctx.nblocks = s->nblocks;
+    double *cs = (double *)(s->pool + s->lay.cstats);
+    const uint64_t per = std::max<uint64_t>(1, kStatChunks / cpb);   // blocks per batch
+    for (uint64_t b0 = 0; b0 < s->nblocks; b0 += per) {
+        const uint64_t nb = std::min<uint64_t>(per, s->nblocks - b0);
+        GateDesc d{};
+        single_kernel_chunks(s, d, nb << shift, 0);
+        d.block_shift = shift;
+        IOPtrs io{};
+        io.first = b0 << shift;
+        io.cstats = cs;
+        const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(d.njobs, (uint64_t)s->grid_max));
+        HIPCHK(s, launch_chunk_stats(d, ptrs(s), io, grid, s->stream));
+        HIPCHK(s, launch_block_features(cs, s->blevel + b0, ctx, nb, X + b0 * kNIn, n2 ? n2 + b0 : nullptr,
+                                        s->stream));
+    }
+    return QCZ_OK;
+}
+
+// Tighten, one level at a time, the block with the largest w_b * delta_b
+// (lowest index on ties) until sum_b w_b delta_b <= beta * (1 + 2^-20).  The
+// running sum is confirmed by an in-order sum whenever it is near the limit,
+// so the stopping point is that of the in-order sum.
+void project(const double *w, uint64_t nb, double beta, uint8_t *L)
+{
+    const double lim = beta * (1.0 + std::ldexp(1.0, -20));
+    auto exact = [&]() {
+        double t = 0.0;
+        for (uint64_t b = 0; b < nb; ++b) t += w[b] * kDelta[L[b]];
+        return t;
+    };
+    double run = exact();
+    if (run <= lim) return;
+    // max-heap on (w_b * delta_b, -b)
+    std::vector<std::pair<double, int64_t>> heap;
+    heap.reserve(nb);
+    for (uint64_t b = 0; b < nb; ++b)
+        if (L[b] > 0 && w[b] * kDelta[L[b]] > 0.0) heap.push_back({w[b] * kDelta[L[b]], -(int64_t)b});
+    std::make_heap(heap.begin(), heap.end());
+    while (!heap.empty()) {
+        std::pop_heap(heap.begin(), heap.end());
+        const auto top = heap.back();
+        heap.pop_back();
+        const uint64_t b = (uint64_t)(-top.second);
+        run -= top.first;
+        L[b] -= 1;
+        const double v = w[b] * kDelta[L[b]];
+        run += v;
+        if (L[b] > 0 && v > 0.0) {
+            heap.push_back({v, -(int64_t)b});
+            std::push_heap(heap.begin(), heap.end());
+        }
+        if (run <= lim * (1.0 + 1e-9) && exact() <= lim) return;
+    }
+}
+
+qcz_status select_levels(qcz_state *s, const float *params, double beta, uint8_t *out_levels)
+{
+    if (s->cfg.mode != QCZ_MODE_PERBLOCK) return fail(s, QCZ_E_STATE, "level selection needs QCZ_MODE_PERBLOCK");
+    float *X = (float *)(s->pool + s->lay.feat);
+    double *n2 = (double *)(s->pool + s->lay.fn2);
+    uint8_t *sel = s->pool + s->lay.fsel;
+    qcz_status st = block_stats(s, beta, X, n2);
+    if (st != QCZ_OK) return st;
+    HIPCHK(s, launch_mlp_forward(params, X, s->nblocks, nullptr, sel, s->stream));
+    std::vector<uint8_t> L(s->nblocks);
+    std::vector<double> w(s->nblocks);
+    HIPCHK(s, hipMemcpyAsync(L.data(), sel, s->nblocks, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(w.data(), n2, 8 * s->nblocks, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    double tot = 0.0;
+    for (double x : w) tot += x;
+    for (double &x : w) x = tot > 0.0 ? x / tot : 0.0;
+    project(w.data(), s->nblocks, beta, L.data());
+    s->block_levels = L;
+    HIPCHK(s, hipMemcpyAsync(s->blevel, s->block_levels.data(), s->nblocks, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    if (out_levels) memcpy(out_levels, L.data(), s->nblocks);
     return QCZ_OK;
 }
 
@@ -637,6 +747,16 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
     std::vector<GateDesc> descs;
     while (idx < n_gates) {
         size_t B = std::min<size_t>((size_t)s->batch, n_gates - idx);
+        if (s->sel_params) {
+            // learned per-block levels: re-select every sel_period gates
+            if (!s->sel_fresh || s->sel_since >= s->sel_period) {
+                qcz_status st = select_levels(s, s->sel_params, s->sel_beta, nullptr);
+                if (st != QCZ_OK) return st;
+                s->sel_fresh = true;
+                s->sel_since = 0;
+            }
+            B = std::min<size_t>(B, (size_t)(s->sel_period - s->sel_since));
+        }
         if (s->tuning) {
             const auto &c = s->cands[(size_t)s->tune_next];
             s->chunk_waves = c.waves;
@@ -668,6 +788,7 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
         if (!h.stop) {
             for (size_t k = 0; k < B; ++k) commit_gate(s, h.log[k], descs[k], (int)k);
             idx += B;
+            s->sel_since += B;
             if (applied) *applied = idx;
             tune_step(s);
             continue;
@@ -676,6 +797,7 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
         const int reason = h.stop_reason;
         s->stats.stops += 1;
         for (int k = 0; k < sseq; ++k) commit_gate(s, h.log[k], descs[(size_t)k], k);
+        s->sel_since += (uint64_t)sseq;
         // undo the stopped gate
         const GateDesc &dstop = descs[(size_t)sseq];
         DevPtrs P = ptrs(s);
@@ -986,6 +1108,135 @@ qcz_status qcz_decode_chunks(const void *dev_slots, size_t slot_bytes, const uin
     io.raw_out = (double *)dev_out;
     const int grid = (int)std::min<uint64_t>(d.njobs, 4096);
     if (launch_decode_slots(d, P, io, grid, (hipStream_t)hip_stream) != hipSuccess) return QCZ_E_DEVICE;
+    return QCZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-block level selection
+// ---------------------------------------------------------------------------
+qcz_status qcz_block_stats(qcz_state *s, double beta, float *dev_features, double *dev_norms)
+{
+    if (!s || !dev_features || !(beta >= 0.0)) return QCZ_E_INVAL;
+    qcz_status st = block_stats(s, beta, dev_features, dev_norms);
+    if (st != QCZ_OK) return st;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return QCZ_OK;
+}
+
+qcz_status qcz_block_level_sizes(qcz_state *s, uint64_t *dev_sizes)
+{
+    if (!s || !dev_sizes) return QCZ_E_INVAL;
+    HIPCHK(s, launch_zero_u64(dev_sizes, (uint64_t)kLevels * s->nblocks, s->stream));
+    GateDesc d{};
+    single_kernel_chunks(s, d, s->nchunks, 0);
+    d.block_shift = s->bl - s->cb;
+    IOPtrs io{};
+    io.lsizes = dev_sizes;
+    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(d.njobs, (uint64_t)s->grid_max));
+    HIPCHK(s, launch_level_sizes(d, ptrs(s), io, grid, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return QCZ_OK;
+}
+
+qcz_status qcz_label_levels(const uint64_t *sizes, const double *w, uint64_t nblocks, double beta, uint8_t *levels)
+{
+    if ((nblocks && (!sizes || !w || !levels)) || !(beta >= 0.0)) return QCZ_E_INVAL;
+    for (uint64_t b = 0; b < nblocks; ++b)
+        if (!(w[b] >= 0.0)) return QCZ_E_INVAL;
+    const double lim = beta * (1.0 + std::ldexp(1.0, -20));
+    auto choose = [&](double lam) {
+        for (uint64_t b = 0; b < nblocks; ++b) {
+            int best = 0;
+            double bc = 0.0;
+            for (int l = 0; l < kLevels; ++l) {
+                const double c = (double)sizes[b * kLevels + l] + lam * (w[b] * kDelta[l]);
+                if (l == 0 || c < bc) { best = l; bc = c; }
+            }
+            levels[b] = (uint8_t)best;
+        }
+        double t = 0.0;
+        for (uint64_t b = 0; b < nblocks; ++b) t += w[b] * kDelta[levels[b]];
+        return t <= lim;
+    };
+    // candidate multipliers: 0 and every breakpoint where a block's choice can change
+    std::vector<double> lam{0.0};
+    for (uint64_t b = 0; b < nblocks; ++b) {
+        if (w[b] <= 0.0) continue;
+        for (int lo = 0; lo < kLevels; ++lo)
+            for (int hi = lo + 1; hi < kLevels; ++hi) {
+                const double ds = (double)sizes[b * kLevels + lo] - (double)sizes[b * kLevels + hi];
+                if (ds > 0.0) lam.push_back(ds / (w[b] * (kDelta[hi] - kDelta[lo])));
+            }
+    }
+    std::sort(lam.begin(), lam.end());
+    lam.erase(std::unique(lam.begin(), lam.end()), lam.end());
+    // the budget use falls as the multiplier grows: smallest feasible candidate by bisection
+    size_t lo = 0, hi = lam.size();   // answer in [lo, hi]; hi = none feasible
+    while (lo < hi) {
+        const size_t mid = lo + (hi - lo) / 2;
+        if (choose(lam[mid])) hi = mid;
+        else lo = mid + 1;
+    }
+    if (lo < lam.size()) {
+        choose(lam[lo]);
+    } else {
+        for (uint64_t b = 0; b < nblocks; ++b) levels[b] = 0;
+    }
+    return QCZ_OK;
+}
+
+qcz_status qcz_project_levels(const double *w, uint64_t nblocks, double beta, uint8_t *levels)
+{
+    if ((nblocks && (!w || !levels)) || !(beta >= 0.0)) return QCZ_E_INVAL;
+    for (uint64_t b = 0; b < nblocks; ++b)
+        if (!(w[b] >= 0.0) || levels[b] >= kLevels) return QCZ_E_INVAL;
+    project(w, nblocks, beta, levels);
+    return QCZ_OK;
+}
+
+size_t qcz_mlp_workspace_bytes(uint64_t n_samples) { return n_samples ? mlp_workspace_bytes(n_samples) : 0; }
+
+qcz_status qcz_mlp_forward(const float *dev_params, const float *dev_x, uint64_t n_samples, float *dev_probs,
+                           uint8_t *dev_levels, void *hip_stream)
+{
+    if (!dev_params || (n_samples && !dev_x)) return QCZ_E_INVAL;
+    if (launch_mlp_forward(dev_params, dev_x, n_samples, dev_probs, dev_levels, (hipStream_t)hip_stream) !=
+        hipSuccess)
+        return QCZ_E_DEVICE;
+    return QCZ_OK;
+}
+
+qcz_status qcz_mlp_train_step(float *dev_params, float *dev_m, float *dev_v, const float *dev_x,
+                              const uint8_t *dev_labels, uint64_t n_samples, float lr, uint32_t step,
+                              float *dev_grad, float *dev_loss, void *dev_work, size_t work_bytes, void *hip_stream)
+{
+    if (!dev_params || !dev_x || !dev_labels || !dev_work || n_samples == 0) return QCZ_E_INVAL;
+    if (step > 0 && (!dev_m || !dev_v)) return QCZ_E_INVAL;
+    if (work_bytes < mlp_workspace_bytes(n_samples)) return QCZ_E_INVAL;
+    if (launch_mlp_train(dev_params, dev_m, dev_v, dev_x, dev_labels, n_samples, lr, step, dev_grad, dev_loss,
+                         dev_work, (hipStream_t)hip_stream) != hipSuccess)
+        return QCZ_E_DEVICE;
+    return QCZ_OK;
+}
+
+qcz_status qcz_select_levels(qcz_state *s, const float *dev_params, double beta, uint8_t *out_levels)
+{
+    if (!s || !dev_params || !(beta >= 0.0)) return QCZ_E_INVAL;
+    qcz_status st = select_levels(s, dev_params, beta, out_levels);
+    if (st == QCZ_OK) clear_graphs(s);
+    return st;
+}
+
+qcz_status qcz_set_selector(qcz_state *s, const float *dev_params, double beta, uint32_t period)
+{
+    if (!s || (dev_params && (!(beta >= 0.0) || period == 0))) return QCZ_E_INVAL;
+    if (dev_params && s->cfg.mode != QCZ_MODE_PERBLOCK)
+        return fail(s, QCZ_E_STATE, "level selection needs QCZ_MODE_PERBLOCK");
+    s->sel_params = dev_params;
+    s->sel_beta = beta;
+    s->sel_period = period;
+    s->sel_since = 0;
+    s->sel_fresh = false;
     return QCZ_OK;
 }
 

@@ -60,7 +60,11 @@ EXPORTED = [
     "qcz_moments", "qcz_sample", "qcz_footprint", "qcz_export_chunk", "qcz_import_chunk", "qcz_set_block_levels",
     "qcz_chunk_sizes", "qcz_num_chunks", "qcz_chunk_doubles", "qcz_last_error", "qcz_destroy", "qcz_chunk_cap",
     "qcz_encode_chunks", "qcz_decode_chunks", "qcz_get_stats", "qcz_reset_stats", "qcz_set_launch",
+    "qcz_block_stats", "qcz_block_level_sizes", "qcz_label_levels", "qcz_project_levels", "qcz_mlp_forward",
+    "qcz_mlp_workspace_bytes", "qcz_mlp_train_step", "qcz_select_levels", "qcz_set_selector",
 ]
+MLP_PARAMS = 5638
+N_FEATURES = 16
 
 _lib = None
 
@@ -118,6 +122,25 @@ def load():
     L.qcz_reset_stats.argtypes = [vp]
     L.qcz_set_launch.restype = i32
     L.qcz_set_launch.argtypes = [vp, u32, u32]
+    dbl, flt = ctypes.c_double, ctypes.c_float
+    L.qcz_block_stats.restype = i32
+    L.qcz_block_stats.argtypes = [vp, dbl, vp, vp]
+    L.qcz_block_level_sizes.restype = i32
+    L.qcz_block_level_sizes.argtypes = [vp, vp]
+    L.qcz_label_levels.restype = i32
+    L.qcz_label_levels.argtypes = [vp, vp, u64, dbl, vp]
+    L.qcz_project_levels.restype = i32
+    L.qcz_project_levels.argtypes = [vp, u64, dbl, vp]
+    L.qcz_mlp_forward.restype = i32
+    L.qcz_mlp_forward.argtypes = [vp, vp, u64, vp, vp, vp]
+    L.qcz_mlp_workspace_bytes.restype = sz
+    L.qcz_mlp_workspace_bytes.argtypes = [u64]
+    L.qcz_mlp_train_step.restype = i32
+    L.qcz_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, u64, flt, u32, vp, vp, vp, sz, vp]
+    L.qcz_select_levels.restype = i32
+    L.qcz_select_levels.argtypes = [vp, vp, dbl, vp]
+    L.qcz_set_selector.restype = i32
+    L.qcz_set_selector.argtypes = [vp, vp, dbl, u32]
     _lib = L
     return L
 
@@ -268,6 +291,37 @@ class State:
         lv = np.ascontiguousarray(np.asarray(levels, dtype=np.uint8))
         self._check(self._lib.qcz_set_block_levels(self._h, lv.ctypes.data), "qcz_set_block_levels")
 
+    # -- per-block level selection -------------------------------------------
+    def block_stats(self, beta: float):
+        """(features float32 [nblocks, 16], squared norms float64 [nblocks]) on the device."""
+        torch = _torch()
+        nb = 1 << (self.n - self.block_log2)
+        X = torch.empty((nb, N_FEATURES), dtype=torch.float32, device="cuda")
+        n2 = torch.empty(nb, dtype=torch.float64, device="cuda")
+        self._check(self._lib.qcz_block_stats(self._h, float(beta), X.data_ptr(), n2.data_ptr()), "qcz_block_stats")
+        return X, n2
+
+    def block_level_sizes(self):
+        """Padded bytes of every block at each level: int64 [nblocks, 6] on the device."""
+        torch = _torch()
+        nb = 1 << (self.n - self.block_log2)
+        S = torch.empty((nb, 6), dtype=torch.int64, device="cuda")
+        self._check(self._lib.qcz_block_level_sizes(self._h, S.data_ptr()), "qcz_block_level_sizes")
+        return S
+
+    def select_levels(self, params, beta: float) -> np.ndarray:
+        nb = 1 << (self.n - self.block_log2)
+        out = np.zeros(nb, dtype=np.uint8)
+        self._check(self._lib.qcz_select_levels(self._h, params.data_ptr(), float(beta), out.ctypes.data),
+                    "qcz_select_levels")
+        return out
+
+    def set_selector(self, params, beta: float = 0.0, period: int = 1):
+        """Attach (params: cuda float32 [5638], kept alive here) or detach (None)."""
+        self._sel_params = params
+        ptr = params.data_ptr() if params is not None else None
+        self._check(self._lib.qcz_set_selector(self._h, ptr, float(beta), int(period)), "qcz_set_selector")
+
     def sample(self, seed: int, shots: int) -> np.ndarray:
         out = np.zeros(shots, dtype=np.uint64)
         self._check(self._lib.qcz_sample(self._h, seed, shots, out.ctypes.data), "qcz_sample")
@@ -303,3 +357,72 @@ def decode_chunks(slots, sizes, C: int, stream=None):
         raise QczError(rc, "qcz_decode_chunks")
     st.synchronize()
     return out
+
+
+# -- selector entry points ----------------------------------------------------
+def label_levels(sizes, w, beta: float) -> np.ndarray:
+    """Host call: Lagrangian level labels (sizes [nblocks, 6] u64, w [nblocks])."""
+    S = np.ascontiguousarray(np.asarray(sizes, dtype=np.uint64))
+    W = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    out = np.zeros(W.size, dtype=np.uint8)
+    rc = load().qcz_label_levels(S.ctypes.data, W.ctypes.data, W.size, float(beta), out.ctypes.data)
+    if rc != 0:
+        raise QczError(rc, "qcz_label_levels")
+    return out
+
+
+def project_levels(levels, w, beta: float) -> np.ndarray:
+    """Host call: budget projection of per-block levels."""
+    L = np.ascontiguousarray(np.asarray(levels, dtype=np.uint8)).copy()
+    W = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    rc = load().qcz_project_levels(W.ctypes.data, W.size, float(beta), L.ctypes.data)
+    if rc != 0:
+        raise QczError(rc, "qcz_project_levels")
+    return L
+
+
+def mlp_forward(params, X, stream=None):
+    """(probabilities float32 [N, 6], levels uint8 [N]) for features X (cuda float32 [N, 16])."""
+    torch = _torch()
+    N = X.shape[0]
+    probs = torch.empty((N, 6), dtype=torch.float32, device=X.device)
+    lev = torch.empty(N, dtype=torch.uint8, device=X.device)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = load().qcz_mlp_forward(params.data_ptr(), X.contiguous().data_ptr(), N, probs.data_ptr(), lev.data_ptr(),
+                                st.cuda_stream)
+    if rc != 0:
+        raise QczError(rc, "qcz_mlp_forward")
+    st.synchronize()
+    return probs, lev
+
+
+class MLPTrainer:
+    """Device-resident parameters, Adam moments and workspace of the selector."""
+
+    def __init__(self, params, n_samples: int, stream=None):
+        torch = _torch()
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.grad = torch.zeros_like(params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+        self.n = int(n_samples)
+        self.work = torch.empty(load().qcz_mlp_workspace_bytes(self.n), dtype=torch.uint8, device=params.device)
+        self.t = 0
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+
+    def step(self, X, labels, lr: float, update: bool = True, sync: bool = True):
+        """One full-batch step (update=False: loss and gradient only)."""
+        assert X.shape[0] == self.n and labels.shape[0] == self.n
+        if update:
+            self.t += 1
+        rc = load().qcz_mlp_train_step(self.params.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), X.data_ptr(),
+                                       labels.data_ptr(), self.n, float(lr), self.t if update else 0,
+                                       self.grad.data_ptr(), self.loss.data_ptr(), self.work.data_ptr(),
+                                       self.work.numel(), self.stream.cuda_stream)
+        if rc != 0:
+            raise QczError(rc, "qcz_mlp_train_step")
+        if sync:
+            self.stream.synchronize()
+            return float(self.loss.item())
+        return None
