@@ -203,9 +203,14 @@ void qcz_destroy(qcz_state *st);
  * short; these calls choose one bound per block instead.  The Sec. 3.8
  * argument carries over when each block b is truncated at relative error
  * delta_b per value: one step keeps the fidelity at least
- * 1 - sum_b w_b delta_b, w_b = the block's share of the squared norm.  A
- * per-step budget beta on that sum gives the Eq. (11) product of a uniform
- * bound beta.  In QCZ_MODE_PERBLOCK the state's ledger
+ * 1 - sum_b w_b delta_b, w_b = the block's share of the squared norm.
+ * Levels are chosen for a window of gates; gates whose target is a
+ * block-index qubit move weight between blocks, but only inside the cosets
+ * {b' : b' & ~mix_mask == b & ~mix_mask} of the block-index bits they flip
+ * (mix_mask), whose total weight W_c the window conserves.  The per-step
+ * budget sum over cosets of W_c * delta(max level in the coset) <= beta
+ * therefore holds at every gate of the window and gives at least the
+ * Eq. (11) product of a uniform bound beta.  In QCZ_MODE_PERBLOCK the state's ledger
  * (fidelity_lower_bound) multiplies, per gate, 1 - (sum over re-encoded
  * chunks of delta(level) * |chunk before truncation|^2) / |state|^2. */
 
@@ -219,27 +224,33 @@ void qcz_destroy(qcz_state *st);
  * f9 stream bytes / raw bytes of the block; f10 block level/5; f11 (largest
  * biased exponent - 1023)/64 (-17 for an all-zero block); f12
  * max(log10(beta), -20)/5 (-4 for beta = 0); f13 log2(raw / stream bytes of
- * the state)/16; f14 log2(n_blocks)/16; f15 block_log2/32.  QCZ_E_INVAL for
- * beta < 0 or blocks of more than 65536 chunks. */
-qcz_status qcz_block_stats(qcz_state *st, double beta, float *dev_features, double *dev_norms);
+ * the state)/16; f14 log2(n_blocks)/16; f15 popcount(mix_mask)/16.
+ * QCZ_E_INVAL for beta < 0, a mask bit beyond the block index, or blocks of
+ * more than 65536 chunks. */
+qcz_status qcz_block_stats(qcz_state *st, double beta, uint64_t mix_mask, float *dev_features, double *dev_norms);
 
 /* Padded stream bytes of every block re-encoded at each level: device
  * n_blocks x 6 u64 (block major), overwritten. */
 qcz_status qcz_block_level_sizes(qcz_state *st, uint64_t *dev_sizes);
 
-/* Host call, no device work.  Training labels: for sizes s[b][l] (host,
- * n_blocks x 6) and weights w (host, >= 0), the level of each block that
- * minimises s[b][l] + lambda * w_b * delta_l (ties: the tighter level), for
- * the smallest lambda among 0 and the values where some block's choice
- * changes whose choice satisfies sum_b w_b delta_b <= beta * (1 + 2^-20)
- * (sum in block order).  Output: levels (host, n_blocks). */
+/* Host call, no device work.  Training labels for sizes s[b][l] (host,
+ * n_blocks x 6, n_blocks a power of two) and weights w (host, >= 0): each
+ * coset c (above; cosets in increasing id b & ~mix_mask, sums in block
+ * order) takes the cap level minimising (bytes of its blocks, each at its
+ * smallest level <= cap, lowest on ties) + lambda * W_c * delta(cap), lowest
+ * cap on ties, for the smallest lambda among 0 and the values where some
+ * coset's choice changes whose caps satisfy
+ * sum_c W_c delta(cap_c) <= beta * (1 + 2^-20); each block then takes its
+ * smallest level under its coset's cap.  Output: levels (host, n_blocks). */
 qcz_status qcz_label_levels(const uint64_t *sizes, const double *w, uint64_t n_blocks, double beta,
-                            uint8_t *levels);
+                            uint64_t mix_mask, uint8_t *levels);
 
-/* Host call.  Budget projection: while sum_b w_b delta(levels[b]) exceeds
- * beta * (1 + 2^-20), lower by one the level of the block with the largest
- * w_b delta(levels[b]) (lowest index on ties).  levels: host, in/out. */
-qcz_status qcz_project_levels(const double *w, uint64_t n_blocks, double beta, uint8_t *levels);
+/* Host call.  Budget projection: while sum_c W_c delta(max level in c)
+ * exceeds beta * (1 + 2^-20), lower by one every block at the max level of
+ * the coset with the largest W_c delta(max level) (lowest id on ties).
+ * levels: host, in/out. */
+qcz_status qcz_project_levels(const double *w, uint64_t n_blocks, double beta, uint64_t mix_mask,
+                              uint8_t *levels);
 
 /* Selector network 16 -> 64 -> 64 -> 6: ReLU hidden layers, softmax over
  * the six levels.  Parameters: 5638 floats on the device, packed W1 (64x16,
@@ -266,14 +277,28 @@ qcz_status qcz_mlp_train_step(float *dev_params, float *dev_m, float *dev_v, con
                               void *hip_stream);
 
 /* QCZ_MODE_PERBLOCK: block features -> network -> most probable level per
- * block -> budget projection with w_b = n2_b / sum n2 -> block levels of the
- * state.  out_levels (host, n_blocks; may be NULL) receives them. */
-qcz_status qcz_select_levels(qcz_state *st, const float *dev_params, double beta, uint8_t *out_levels);
+ * block -> budget projection with w_b = n2_b / sum n2 and the window's
+ * mix_mask -> block levels of the state.  out_levels (host, n_blocks; may be
+ * NULL) receives them. */
+qcz_status qcz_select_levels(qcz_state *st, const float *dev_params, double beta, uint64_t mix_mask,
+                             uint8_t *out_levels);
 
 /* QCZ_MODE_PERBLOCK: make qcz_apply_gates call qcz_select_levels before the
- * first gate and again every `period` gates.  dev_params must stay valid
- * while attached; NULL detaches. */
+ * first gate and again every `period` gates, each time with the mixing mask
+ * of the next `period` gates (targets of U1 and X gates on block-index
+ * qubits).  dev_params must stay valid while attached; NULL detaches. */
 qcz_status qcz_set_selector(qcz_state *st, const float *dev_params, double beta, uint32_t period);
+
+/* Block-index bits flipped by the gates (targets of U1 and X gates on
+ * block-index qubits): the mix_mask of a window of gates. */
+uint64_t qcz_mixing_mask(const qcz_state *st, const qcz_gate *gates, size_t n_gates);
+
+/* Make dst hold the same state as src (streams, chunk table, levels, global
+ * level, ledger and counters of the footprint).  src is compacted first (its
+ * streams move, its state does not change), then its streams and table are
+ * copied device to device on dst's stream.  Same n_qubits, block_log2 and
+ * mode; QCZ_E_NOMEM if src's streams exceed dst's arena. */
+qcz_status qcz_copy_state(qcz_state *dst, qcz_state *src);
 
 /* ---- codec entry points (no state) -------------------------------------- */
 

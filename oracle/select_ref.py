@@ -8,8 +8,13 @@ The selector generalises the variable error bound of Sec. 3.7 from one level
 for the whole state to one level per block, and keeps the Sec. 3.8 argument:
 if block b is truncated at relative error delta_b per value, one step keeps
 the fidelity at least 1 - sum_b w_b delta_b with w_b the block's share of the
-squared norm.  A per-step budget beta on sum_b w_b delta_b therefore gives the
-same Eq. (11) product as a uniform bound beta.
+squared norm.  Levels are chosen for a window of gates, during which weight
+moves between blocks: gates whose target is a block-index qubit (mask M of
+such bits) only move it inside the cosets {b' : b' & ~M == b & ~M}, whose
+total weight W_c the window's unitary gates conserve.  The per-step budget is
+therefore sum over cosets of W_c * max_{b in c} delta_b <= beta, which holds
+at every gate of the window and gives at least the Eq. (11) product of a
+uniform bound beta.
 
 Block features (16 per block; M = 2^(block_log2+1) stored doubles of block b
 in interleaved re/im order, C doubles per chunk, previous value of a chunk's
@@ -30,7 +35,7 @@ value):
    f12 max(log10(beta), -20) / 5
    f13 log2(2^(n+4) / padded stream bytes of the state) / 16
    f14 log2(nblocks) / 16
-   f15 block_log2 / 32
+   f15 (number of block-index bits in the window's mixing mask) / 16
 """
 from __future__ import annotations
 
@@ -48,7 +53,7 @@ def _pad4(n):
     return (n + 3) & ~3
 
 
-def block_features(sim, levels, beta):
+def block_features(sim, levels, beta, mask=0):
     """Features (nblocks x 16, float64) and n2_b (nblocks) of an oracle Sim."""
     n, bl, cb, C = sim.n, sim.block_log2, sim.cb, sim.C
     nblocks = 1 << (n - bl)
@@ -101,7 +106,7 @@ def block_features(sim, levels, beta):
         f[12] = max(math.log10(beta), -20.0) / 5.0 if beta > 0 else -4.0
         f[13] = math.log2((2.0 ** (n + 4)) / live) / 16.0
         f[14] = math.log2(nblocks) / 16.0
-        f[15] = bl / 32.0
+        f[15] = bin(mask).count("1") / 16.0
     return F, n2
 
 
@@ -118,61 +123,100 @@ def block_level_sizes(sim):
     return S
 
 
-def _weighted(levels, w):
-    tot = 0.0
+def cosets(nblocks, mask):
+    """Coset id of every block (b & ~mask) and the sorted distinct ids."""
+    ids = np.arange(nblocks, dtype=np.int64) & ~np.int64(mask)
+    return ids, sorted(set(int(x) for x in ids))
+
+
+def coset_weights(w, mask):
+    ids, order = cosets(len(w), mask)
+    W = {c: 0.0 for c in order}
     for b in range(len(w)):
-        tot += float(w[b]) * DELTA[int(levels[b])]
+        W[int(ids[b])] += float(w[b])
+    return ids, order, W
+
+
+def _weighted(levels, w, mask=0):
+    """sum over cosets (increasing id) of W_c * delta(max level in c)."""
+    ids, order, W = coset_weights(w, mask)
+    top = {c: 0 for c in order}
+    for b in range(len(w)):
+        top[int(ids[b])] = max(top[int(ids[b])], int(levels[b]))
+    tot = 0.0
+    for c in order:
+        tot += W[c] * DELTA[top[c]]
     return tot
 
 
-def _argmin_levels(S, w, lam):
-    L = np.zeros(len(w), dtype=np.uint8)
-    for b in range(len(w)):
-        best, bestc = 0, None
-        for lev in range(6):
-            c = float(S[b, lev]) + lam * (float(w[b]) * DELTA[lev])
-            if bestc is None or c < bestc:
-                best, bestc = lev, c
-        L[b] = best
-    return L
+def _capped(S, b, cap):
+    """Level <= cap with the fewest bytes for block b (lowest on ties)."""
+    best = 0
+    for lev in range(1, cap + 1):
+        if S[b, lev] < S[b, best]:
+            best = lev
+    return best
 
 
-def breakpoints(S, w):
-    """Every lambda at which some block's Lagrangian choice can change."""
-    out = set()
-    for b in range(len(w)):
-        if w[b] <= 0.0:
+def label_levels(S, w, beta, mask=0):
+    """Per coset c a cap level minimising (bytes of its blocks, each at its
+    smallest level <= cap) + lambda * W_c * delta(cap), lowest cap on ties,
+    for the smallest lambda among 0 and the values where some coset's choice
+    changes whose caps satisfy sum_c W_c delta(cap_c) <= beta * SLACK; each
+    block then takes its smallest level under its coset's cap."""
+    nb = len(w)
+    ids, order, W = coset_weights(w, mask)
+    members = {c: [b for b in range(nb) if int(ids[b]) == c] for c in order}
+    cost = {c: [float(sum(int(S[b, _capped(S, b, cap)]) for b in members[c])) for cap in range(6)] for c in order}
+    lim = beta * SLACK
+    cands = set()
+    for c in order:
+        if W[c] <= 0.0:
             continue
         for lo in range(6):
             for hi in range(lo + 1, 6):
-                ds = float(S[b, lo]) - float(S[b, hi])
-                if ds > 0.0:
-                    out.add(ds / (float(w[b]) * (DELTA[hi] - DELTA[lo])))
-    return sorted(out)
+                d = cost[c][lo] - cost[c][hi]
+                if d > 0.0:
+                    cands.add(d / (W[c] * (DELTA[hi] - DELTA[lo])))
+    caps = None
+    for lam in [0.0] + sorted(cands):
+        cp = {}
+        for c in order:
+            best, bc = 0, None
+            for cap in range(6):
+                v = cost[c][cap] + lam * (W[c] * DELTA[cap])
+                if bc is None or v < bc:
+                    best, bc = cap, v
+            cp[c] = best
+        tot = 0.0
+        for c in order:
+            tot += W[c] * DELTA[cp[c]]
+        if tot <= lim:
+            caps = cp
+            break
+    L = np.zeros(nb, dtype=np.uint8)
+    if caps is None:
+        return L
+    for b in range(nb):
+        L[b] = _capped(S, b, caps[int(ids[b])])
+    return L
 
 
-def label_levels(S, w, beta):
-    """Per-block level minimising size + lambda * w_b * delta, with the
-    smallest lambda among {0} and the breakpoints whose choice meets the
-    budget; ties between levels go to the tighter one."""
-    lim = beta * SLACK
-    for lam in [0.0] + breakpoints(S, w):
-        L = _argmin_levels(S, w, lam)
-        if _weighted(L, w) <= lim:
-            return L
-    return np.zeros(len(w), dtype=np.uint8)
-
-
-def project_levels(levels, w, beta):
-    """Tighten one level at a time the block with the largest w_b delta_b
-    (lowest index on ties) until sum_b w_b delta_b <= beta * SLACK."""
+def project_levels(levels, w, beta, mask=0):
+    """While the coset budget is exceeded, take the coset with the largest
+    W_c * delta(max level) (lowest id on ties) and lower by one every block
+    of it at that max level."""
     L = np.array(levels, dtype=np.uint8).copy()
+    ids, order, W = coset_weights(w, mask)
     lim = beta * SLACK
-    while _weighted(L, w) > lim:
-        best, bv = -1, -1.0
-        for b in range(len(w)):
-            v = float(w[b]) * DELTA[int(L[b])]
+    while _weighted(L, w, mask) > lim:
+        best, bv, btop = -1, -1.0, 0
+        for c in order:
+            top = max(int(L[b]) for b in range(len(w)) if int(ids[b]) == c)
+            v = W[c] * DELTA[top]
             if v > bv:
-                best, bv = b, v
-        L[best] -= 1
+                best, bv, btop = c, v, top
+        for b in range(len(w)):
+            if int(ids[b]) == best and int(L[b]) == btop:
+                L[b] -= 1
     return L

@@ -111,6 +111,11 @@ def rx(q, beta):
     return u1(q, [[c, -1j * s], [-1j * s, c]])
 
 
+def ry(q, theta):
+    c, s = math.cos(theta / 2), math.sin(theta / 2)
+    return u1(q, [[c, -s], [s, c]])
+
+
 def cphase(control, target, phi):
     return diag1(target, 1.0, complex(math.cos(phi), math.sin(phi)), controls=(control,))
 
@@ -323,3 +328,23 @@ WORKLOADS = {
     "qaoa34": dict(n=34, block_log2=20, level=2,
                    doc="34-qubit QAOA on a seeded 3-regular graph, p=4"),
 }
+
+
+def biased_local(n=16, block_log2=8, depth=12, seed=41):
+    """A state whose block weights are uneven and stay so: Ry(theta) with
+    theta ~ U[0.12 pi, 0.3 pi] on every block-index qubit (weight of a block =
+    product of cos^2 / sin^2 factors), then `depth` layers of the
+    random_circuit_small pattern on the in-block qubits, Rz on every
+    block-index qubit and CZ on a seeded pair of them (diagonal there: no
+    weight moves between blocks)."""
+    rng = np.random.default_rng(seed)
+    hi = list(range(block_log2, n))
+    out = [ry(q, float(rng.uniform(0.12 * math.pi, 0.3 * math.pi))) for q in hi]
+    for layer in range(depth):
+        local = random_circuit_small(block_log2, 1, int(rng.integers(1 << 30)))
+        out.append(local)
+        out += [rz(q, float(rng.uniform(0.0, 2 * math.pi))) for q in hi]
+        if len(hi) >= 2:
+            a, b = rng.choice(len(hi), size=2, replace=False)
+            out.append(cz(hi[int(a)], hi[int(b)]))
+    return concat(out)

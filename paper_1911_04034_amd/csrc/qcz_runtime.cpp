@@ -501,7 +501,7 @@ qcz_status single_kernel_chunks(qcz_state *s, GateDesc &d, uint64_t nitems, uint
 
 // Statistics of every block: 16 float features into X (device, nblocks x 16)
 // and the squared norm of each block into n2 (device, may be null).
-qcz_status block_stats(qcz_state *s, double beta, float *X, double *n2)
+qcz_status block_stats(qcz_state *s, double beta, uint64_t mask, float *X, double *n2)
 {
     const int shift = s->bl - s->cb;
     const uint64_t cpb = 1ull << shift;
@@ -510,7 +510,7 @@ qcz_status block_stats(qcz_state *s, double beta, float *X, double *n2)
     ctx.f12 = beta > 0.0 ? std::max(std::log10(beta), -20.0) / 5.0 : -4.0;
     ctx.f13 = std::log2(std::ldexp(1.0, s->n + 4) / (double)s->live) / 16.0;
     ctx.f14 = std::log2((double)s->nblocks) / 16.0;
-    ctx.f15 = (double)s->bl / 32.0;
+    ctx.f15 = (double)__builtin_popcountll(mask) / 16.0;
     ctx.cpb = (int32_t)cpb;
     ctx.block_log2 = s->bl;
     ctx.nblocks = s->nblocks;
@@ -532,50 +532,103 @@ qcz_status block_stats(qcz_state *s, double beta, float *X, double *n2)
     return QCZ_OK;
 }
 
-// Tighten, one level at a time, the block with the largest w_b * delta_b
-// (lowest index on ties) until sum_b w_b delta_b <= beta * (1 + 2^-20).  The
+// Blocks grouped by coset id b & ~mask: cosets in increasing id, members in
+// block order, and the weight of each coset summed in block order.
+struct Cosets {
+    std::vector<uint64_t> ids;      // distinct coset ids, increasing
+    std::vector<double> W;          // per coset
+    std::vector<uint64_t> start;    // members of coset k: mem[start[k] .. start[k+1])
+    std::vector<uint64_t> mem;
+};
+
+Cosets make_cosets(const double *w, uint64_t nb, uint64_t mask)
+{
+    Cosets c;
+    std::vector<int64_t> slot(nb, -1);
+    for (uint64_t b = 0; b < nb; ++b) {
+        const uint64_t id = b & ~mask;
+        if (slot[id] < 0) slot[id] = 0;
+    }
+    for (uint64_t id = 0; id < nb; ++id)
+        if (slot[id] >= 0) { slot[id] = (int64_t)c.ids.size(); c.ids.push_back(id); }
+    const size_t nc = c.ids.size();
+    c.W.assign(nc, 0.0);
+    std::vector<uint64_t> cnt(nc + 1, 0);
+    for (uint64_t b = 0; b < nb; ++b) {
+        const size_t k = (size_t)slot[b & ~mask];
+        c.W[k] += w[b];
+        cnt[k + 1] += 1;
+    }
+    c.start.assign(nc + 1, 0);
+    for (size_t k = 0; k < nc; ++k) c.start[k + 1] = c.start[k] + cnt[k + 1];
+    c.mem.assign(nb, 0);
+    std::vector<uint64_t> fill(c.start.begin(), c.start.end() - 1);
+    for (uint64_t b = 0; b < nb; ++b) c.mem[fill[(size_t)slot[b & ~mask]]++] = b;
+    return c;
+}
+
+// While sum over cosets of W_c * delta(max level in c) exceeds
+// beta * (1 + 2^-20), lower by one every block at the max level of the coset
+// with the largest W_c * delta(max level) (lowest coset id on ties).  The
 // running sum is confirmed by an in-order sum whenever it is near the limit,
 // so the stopping point is that of the in-order sum.
-void project(const double *w, uint64_t nb, double beta, uint8_t *L)
+void project(const double *w, uint64_t nb, double beta, uint64_t mask, uint8_t *L)
 {
     const double lim = beta * (1.0 + std::ldexp(1.0, -20));
+    const Cosets cs = make_cosets(w, nb, mask);
+    const size_t nc = cs.ids.size();
+    std::vector<int> top(nc, 0);
+    for (size_t k = 0; k < nc; ++k)
+        for (uint64_t i = cs.start[k]; i < cs.start[k + 1]; ++i) top[k] = std::max(top[k], (int)L[cs.mem[i]]);
     auto exact = [&]() {
         double t = 0.0;
-        for (uint64_t b = 0; b < nb; ++b) t += w[b] * kDelta[L[b]];
+        for (size_t k = 0; k < nc; ++k) t += cs.W[k] * kDelta[top[k]];
         return t;
     };
     double run = exact();
     if (run <= lim) return;
-    // max-heap on (w_b * delta_b, -b)
+    // max-heap on (W_c * delta(top_c), -k)
     std::vector<std::pair<double, int64_t>> heap;
-    heap.reserve(nb);
-    for (uint64_t b = 0; b < nb; ++b)
-        if (L[b] > 0 && w[b] * kDelta[L[b]] > 0.0) heap.push_back({w[b] * kDelta[L[b]], -(int64_t)b});
+    for (size_t k = 0; k < nc; ++k)
+        if (top[k] > 0 && cs.W[k] * kDelta[top[k]] > 0.0) heap.push_back({cs.W[k] * kDelta[top[k]], -(int64_t)k});
     std::make_heap(heap.begin(), heap.end());
     while (!heap.empty()) {
         std::pop_heap(heap.begin(), heap.end());
-        const auto top = heap.back();
+        const auto h = heap.back();
         heap.pop_back();
-        const uint64_t b = (uint64_t)(-top.second);
-        run -= top.first;
-        L[b] -= 1;
-        const double v = w[b] * kDelta[L[b]];
+        const size_t k = (size_t)(-h.second);
+        for (uint64_t i = cs.start[k]; i < cs.start[k + 1]; ++i)
+            if (L[cs.mem[i]] == top[k]) L[cs.mem[i]] -= 1;
+        run -= h.first;
+        top[k] -= 1;
+        const double v = cs.W[k] * kDelta[top[k]];
         run += v;
-        if (L[b] > 0 && v > 0.0) {
-            heap.push_back({v, -(int64_t)b});
+        if (top[k] > 0 && v > 0.0) {
+            heap.push_back({v, -(int64_t)k});
             std::push_heap(heap.begin(), heap.end());
         }
         if (run <= lim * (1.0 + 1e-9) && exact() <= lim) return;
     }
 }
 
-qcz_status select_levels(qcz_state *s, const float *params, double beta, uint8_t *out_levels)
+// Block-index bits that the gates may flip: targets of U1 / X gates on
+// block-index qubits.  Weight only moves inside cosets of these bits.
+uint64_t mixing_mask(const qcz_state *s, const qcz_gate *g, size_t n)
+{
+    uint64_t m = 0;
+    for (size_t k = 0; k < n; ++k)
+        if ((g[k].kind == (uint32_t)K_U1 || g[k].kind == (uint32_t)K_X) && (int)g[k].target >= s->bl)
+            m |= 1ull << (g[k].target - (uint32_t)s->bl);
+    return m;
+}
+
+qcz_status select_levels(qcz_state *s, const float *params, double beta, uint64_t mask, uint8_t *out_levels)
 {
     if (s->cfg.mode != QCZ_MODE_PERBLOCK) return fail(s, QCZ_E_STATE, "level selection needs QCZ_MODE_PERBLOCK");
     float *X = (float *)(s->pool + s->lay.feat);
     double *n2 = (double *)(s->pool + s->lay.fn2);
     uint8_t *sel = s->pool + s->lay.fsel;
-    qcz_status st = block_stats(s, beta, X, n2);
+    qcz_status st = block_stats(s, beta, mask, X, n2);
     if (st != QCZ_OK) return st;
     HIPCHK(s, launch_mlp_forward(params, X, s->nblocks, nullptr, sel, s->stream));
     std::vector<uint8_t> L(s->nblocks);
@@ -586,7 +639,7 @@ qcz_status select_levels(qcz_state *s, const float *params, double beta, uint8_t
     double tot = 0.0;
     for (double x : w) tot += x;
     for (double &x : w) x = tot > 0.0 ? x / tot : 0.0;
-    project(w.data(), s->nblocks, beta, L.data());
+    project(w.data(), s->nblocks, beta, mask, L.data());
     s->block_levels = L;
     HIPCHK(s, hipMemcpyAsync(s->blevel, s->block_levels.data(), s->nblocks, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -750,7 +803,8 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
         if (s->sel_params) {
             // learned per-block levels: re-select every sel_period gates
             if (!s->sel_fresh || s->sel_since >= s->sel_period) {
-                qcz_status st = select_levels(s, s->sel_params, s->sel_beta, nullptr);
+                const size_t win = std::min<size_t>((size_t)s->sel_period, n_gates - idx);
+                qcz_status st = select_levels(s, s->sel_params, s->sel_beta, mixing_mask(s, gates + idx, win), nullptr);
                 if (st != QCZ_OK) return st;
                 s->sel_fresh = true;
                 s->sel_since = 0;
@@ -1114,10 +1168,10 @@ qcz_status qcz_decode_chunks(const void *dev_slots, size_t slot_bytes, const uin
 // ---------------------------------------------------------------------------
 // per-block level selection
 // ---------------------------------------------------------------------------
-qcz_status qcz_block_stats(qcz_state *s, double beta, float *dev_features, double *dev_norms)
+qcz_status qcz_block_stats(qcz_state *s, double beta, uint64_t mix_mask, float *dev_features, double *dev_norms)
 {
-    if (!s || !dev_features || !(beta >= 0.0)) return QCZ_E_INVAL;
-    qcz_status st = block_stats(s, beta, dev_features, dev_norms);
+    if (!s || !dev_features || !(beta >= 0.0) || (mix_mask >> (s->n - s->bl))) return QCZ_E_INVAL;
+    qcz_status st = block_stats(s, beta, mix_mask, dev_features, dev_norms);
     if (st != QCZ_OK) return st;
     HIPCHK(s, hipStreamSynchronize(s->stream));
     return QCZ_OK;
@@ -1138,59 +1192,87 @@ qcz_status qcz_block_level_sizes(qcz_state *s, uint64_t *dev_sizes)
     return QCZ_OK;
 }
 
-qcz_status qcz_label_levels(const uint64_t *sizes, const double *w, uint64_t nblocks, double beta, uint8_t *levels)
+qcz_status qcz_label_levels(const uint64_t *sizes, const double *w, uint64_t nblocks, double beta, uint64_t mix_mask,
+                            uint8_t *levels)
 {
-    if ((nblocks && (!sizes || !w || !levels)) || !(beta >= 0.0)) return QCZ_E_INVAL;
+    if ((nblocks && (!sizes || !w || !levels)) || !(beta >= 0.0) || (mix_mask & ~(nblocks - 1)) ||
+        (nblocks & (nblocks - 1)))
+        return QCZ_E_INVAL;
     for (uint64_t b = 0; b < nblocks; ++b)
         if (!(w[b] >= 0.0)) return QCZ_E_INVAL;
+    if (nblocks == 0) return QCZ_OK;
     const double lim = beta * (1.0 + std::ldexp(1.0, -20));
+    const Cosets cs = make_cosets(w, nblocks, mix_mask);
+    const size_t nc = cs.ids.size();
+    // smallest level <= cap of each block (lowest on ties) and the coset's bytes under each cap
+    auto capped = [&](uint64_t b, int cap) {
+        int best = 0;
+        for (int l = 1; l <= cap; ++l)
+            if (sizes[b * kLevels + l] < sizes[b * kLevels + best]) best = l;
+        return best;
+    };
+    std::vector<double> cost(nc * kLevels, 0.0);
+    for (size_t k = 0; k < nc; ++k)
+        for (int cap = 0; cap < kLevels; ++cap) {
+            double t = 0.0;
+            for (uint64_t i = cs.start[k]; i < cs.start[k + 1]; ++i) {
+                const uint64_t b = cs.mem[i];
+                t += (double)sizes[b * kLevels + capped(b, cap)];
+            }
+            cost[k * kLevels + cap] = t;
+        }
+    std::vector<int> caps(nc, 0);
     auto choose = [&](double lam) {
-        for (uint64_t b = 0; b < nblocks; ++b) {
+        double t = 0.0;
+        for (size_t k = 0; k < nc; ++k) {
             int best = 0;
             double bc = 0.0;
-            for (int l = 0; l < kLevels; ++l) {
-                const double c = (double)sizes[b * kLevels + l] + lam * (w[b] * kDelta[l]);
-                if (l == 0 || c < bc) { best = l; bc = c; }
+            for (int cap = 0; cap < kLevels; ++cap) {
+                const double v = cost[k * kLevels + cap] + lam * (cs.W[k] * kDelta[cap]);
+                if (cap == 0 || v < bc) { best = cap; bc = v; }
             }
-            levels[b] = (uint8_t)best;
+            caps[k] = best;
         }
-        double t = 0.0;
-        for (uint64_t b = 0; b < nblocks; ++b) t += w[b] * kDelta[levels[b]];
+        for (size_t k = 0; k < nc; ++k) t += cs.W[k] * kDelta[caps[k]];
         return t <= lim;
     };
-    // candidate multipliers: 0 and every breakpoint where a block's choice can change
+    // candidate multipliers: 0 and every value where a coset's choice can change
     std::vector<double> lam{0.0};
-    for (uint64_t b = 0; b < nblocks; ++b) {
-        if (w[b] <= 0.0) continue;
+    for (size_t k = 0; k < nc; ++k) {
+        if (cs.W[k] <= 0.0) continue;
         for (int lo = 0; lo < kLevels; ++lo)
             for (int hi = lo + 1; hi < kLevels; ++hi) {
-                const double ds = (double)sizes[b * kLevels + lo] - (double)sizes[b * kLevels + hi];
-                if (ds > 0.0) lam.push_back(ds / (w[b] * (kDelta[hi] - kDelta[lo])));
+                const double d = cost[k * kLevels + lo] - cost[k * kLevels + hi];
+                if (d > 0.0) lam.push_back(d / (cs.W[k] * (kDelta[hi] - kDelta[lo])));
             }
     }
     std::sort(lam.begin(), lam.end());
     lam.erase(std::unique(lam.begin(), lam.end()), lam.end());
     // the budget use falls as the multiplier grows: smallest feasible candidate by bisection
-    size_t lo = 0, hi = lam.size();   // answer in [lo, hi]; hi = none feasible
+    size_t lo = 0, hi = lam.size();
     while (lo < hi) {
         const size_t mid = lo + (hi - lo) / 2;
         if (choose(lam[mid])) hi = mid;
         else lo = mid + 1;
     }
-    if (lo < lam.size()) {
-        choose(lam[lo]);
-    } else {
+    if (lo == lam.size()) {
         for (uint64_t b = 0; b < nblocks; ++b) levels[b] = 0;
+        return QCZ_OK;
     }
+    choose(lam[lo]);
+    for (size_t k = 0; k < nc; ++k)
+        for (uint64_t i = cs.start[k]; i < cs.start[k + 1]; ++i) levels[cs.mem[i]] = (uint8_t)capped(cs.mem[i], caps[k]);
     return QCZ_OK;
 }
 
-qcz_status qcz_project_levels(const double *w, uint64_t nblocks, double beta, uint8_t *levels)
+qcz_status qcz_project_levels(const double *w, uint64_t nblocks, double beta, uint64_t mix_mask, uint8_t *levels)
 {
-    if ((nblocks && (!w || !levels)) || !(beta >= 0.0)) return QCZ_E_INVAL;
+    if ((nblocks && (!w || !levels)) || !(beta >= 0.0) || (mix_mask & ~(nblocks - 1)) || (nblocks & (nblocks - 1)))
+        return QCZ_E_INVAL;
     for (uint64_t b = 0; b < nblocks; ++b)
         if (!(w[b] >= 0.0) || levels[b] >= kLevels) return QCZ_E_INVAL;
-    project(w, nblocks, beta, levels);
+    if (nblocks == 0) return QCZ_OK;
+    project(w, nblocks, beta, mix_mask, levels);
     return QCZ_OK;
 }
 
@@ -1219,10 +1301,11 @@ qcz_status qcz_mlp_train_step(float *dev_params, float *dev_m, float *dev_v, con
     return QCZ_OK;
 }
 
-qcz_status qcz_select_levels(qcz_state *s, const float *dev_params, double beta, uint8_t *out_levels)
+qcz_status qcz_select_levels(qcz_state *s, const float *dev_params, double beta, uint64_t mix_mask,
+                             uint8_t *out_levels)
 {
-    if (!s || !dev_params || !(beta >= 0.0)) return QCZ_E_INVAL;
-    qcz_status st = select_levels(s, dev_params, beta, out_levels);
+    if (!s || !dev_params || !(beta >= 0.0) || (mix_mask >> (s->n - s->bl))) return QCZ_E_INVAL;
+    qcz_status st = select_levels(s, dev_params, beta, mix_mask, out_levels);
     if (st == QCZ_OK) clear_graphs(s);
     return st;
 }
@@ -1238,6 +1321,46 @@ qcz_status qcz_set_selector(qcz_state *s, const float *dev_params, double beta, 
     s->sel_since = 0;
     s->sel_fresh = false;
     return QCZ_OK;
+}
+
+qcz_status qcz_copy_state(qcz_state *dst, qcz_state *src)
+{
+    if (!dst || !src || dst == src || dst->n != src->n || dst->bl != src->bl || dst->cfg.mode != src->cfg.mode)
+        return QCZ_E_INVAL;
+    // compact the source first: its live streams then fill [0, base) of its arena
+    // (streams appended since the last compaction sit in stripes spread over the arena)
+    if (src->bump > src->base) {
+        qcz_status st = compact(src);
+        if (st != QCZ_OK) return fail(dst, st, "compacting the source: " + src->err);
+    }
+    const uint64_t used = src->base;
+    if (used > dst->lay.arena_bytes) return fail(dst, QCZ_E_NOMEM, "destination arena smaller than the source's streams");
+    HIPCHK(dst, hipStreamSynchronize(src->stream));
+    HIPCHK(dst, hipMemcpyAsync(dst->table, src->table, 8 * src->nchunks, hipMemcpyDeviceToDevice, dst->stream));
+    if (used)
+        HIPCHK(dst, hipMemcpyAsync(dst->arena[dst->cur], src->arena[src->cur], used, hipMemcpyDeviceToDevice,
+                                   dst->stream));
+    dst->level = src->level;
+    dst->live = src->live;
+    dst->block_levels = src->block_levels;
+    dst->flb = src->flb;
+    dst->norm2 = src->norm2;
+    dst->gates_applied = src->gates_applied;
+    dst->lossy_steps = src->lossy_steps;
+    dst->min_c = src->min_c;
+    dst->max_c = src->max_c;
+    HIPCHK(dst, hipMemcpyAsync(dst->blevel, dst->block_levels.data(), dst->nblocks, hipMemcpyHostToDevice,
+                               dst->stream));
+    qcz_status st = reset_stripes(dst, used);
+    if (st != QCZ_OK) return st;
+    HIPCHK(dst, hipStreamSynchronize(dst->stream));
+    return QCZ_OK;
+}
+
+uint64_t qcz_mixing_mask(const qcz_state *s, const qcz_gate *gates, size_t n_gates)
+{
+    if (!s || (n_gates && !gates)) return 0;
+    return mixing_mask(s, gates, n_gates);
 }
 
 }  // extern "C"

@@ -61,7 +61,8 @@ EXPORTED = [
     "qcz_chunk_sizes", "qcz_num_chunks", "qcz_chunk_doubles", "qcz_last_error", "qcz_destroy", "qcz_chunk_cap",
     "qcz_encode_chunks", "qcz_decode_chunks", "qcz_get_stats", "qcz_reset_stats", "qcz_set_launch",
     "qcz_block_stats", "qcz_block_level_sizes", "qcz_label_levels", "qcz_project_levels", "qcz_mlp_forward",
-    "qcz_mlp_workspace_bytes", "qcz_mlp_train_step", "qcz_select_levels", "qcz_set_selector",
+    "qcz_mlp_workspace_bytes", "qcz_mlp_train_step", "qcz_select_levels", "qcz_set_selector", "qcz_copy_state",
+    "qcz_mixing_mask",
 ]
 MLP_PARAMS = 5638
 N_FEATURES = 16
@@ -124,13 +125,13 @@ def load():
     L.qcz_set_launch.argtypes = [vp, u32, u32]
     dbl, flt = ctypes.c_double, ctypes.c_float
     L.qcz_block_stats.restype = i32
-    L.qcz_block_stats.argtypes = [vp, dbl, vp, vp]
+    L.qcz_block_stats.argtypes = [vp, dbl, u64, vp, vp]
     L.qcz_block_level_sizes.restype = i32
     L.qcz_block_level_sizes.argtypes = [vp, vp]
     L.qcz_label_levels.restype = i32
-    L.qcz_label_levels.argtypes = [vp, vp, u64, dbl, vp]
+    L.qcz_label_levels.argtypes = [vp, vp, u64, dbl, u64, vp]
     L.qcz_project_levels.restype = i32
-    L.qcz_project_levels.argtypes = [vp, u64, dbl, vp]
+    L.qcz_project_levels.argtypes = [vp, u64, dbl, u64, vp]
     L.qcz_mlp_forward.restype = i32
     L.qcz_mlp_forward.argtypes = [vp, vp, u64, vp, vp, vp]
     L.qcz_mlp_workspace_bytes.restype = sz
@@ -138,9 +139,13 @@ def load():
     L.qcz_mlp_train_step.restype = i32
     L.qcz_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, u64, flt, u32, vp, vp, vp, sz, vp]
     L.qcz_select_levels.restype = i32
-    L.qcz_select_levels.argtypes = [vp, vp, dbl, vp]
+    L.qcz_select_levels.argtypes = [vp, vp, dbl, u64, vp]
     L.qcz_set_selector.restype = i32
     L.qcz_set_selector.argtypes = [vp, vp, dbl, u32]
+    L.qcz_copy_state.restype = i32
+    L.qcz_copy_state.argtypes = [vp, vp]
+    L.qcz_mixing_mask.restype = u64
+    L.qcz_mixing_mask.argtypes = [vp, vp, sz]
     _lib = L
     return L
 
@@ -292,13 +297,14 @@ class State:
         self._check(self._lib.qcz_set_block_levels(self._h, lv.ctypes.data), "qcz_set_block_levels")
 
     # -- per-block level selection -------------------------------------------
-    def block_stats(self, beta: float):
+    def block_stats(self, beta: float, mask: int = 0):
         """(features float32 [nblocks, 16], squared norms float64 [nblocks]) on the device."""
         torch = _torch()
         nb = 1 << (self.n - self.block_log2)
         X = torch.empty((nb, N_FEATURES), dtype=torch.float32, device="cuda")
         n2 = torch.empty(nb, dtype=torch.float64, device="cuda")
-        self._check(self._lib.qcz_block_stats(self._h, float(beta), X.data_ptr(), n2.data_ptr()), "qcz_block_stats")
+        self._check(self._lib.qcz_block_stats(self._h, float(beta), int(mask), X.data_ptr(), n2.data_ptr()),
+                    "qcz_block_stats")
         return X, n2
 
     def block_level_sizes(self):
@@ -309,10 +315,10 @@ class State:
         self._check(self._lib.qcz_block_level_sizes(self._h, S.data_ptr()), "qcz_block_level_sizes")
         return S
 
-    def select_levels(self, params, beta: float) -> np.ndarray:
+    def select_levels(self, params, beta: float, mask: int = 0) -> np.ndarray:
         nb = 1 << (self.n - self.block_log2)
         out = np.zeros(nb, dtype=np.uint8)
-        self._check(self._lib.qcz_select_levels(self._h, params.data_ptr(), float(beta), out.ctypes.data),
+        self._check(self._lib.qcz_select_levels(self._h, params.data_ptr(), float(beta), int(mask), out.ctypes.data),
                     "qcz_select_levels")
         return out
 
@@ -321,6 +327,14 @@ class State:
         self._sel_params = params
         ptr = params.data_ptr() if params is not None else None
         self._check(self._lib.qcz_set_selector(self._h, ptr, float(beta), int(period)), "qcz_set_selector")
+
+    def copy_from(self, src: "State"):
+        """Make this state equal to src (same n, block size and mode)."""
+        self._check(self._lib.qcz_copy_state(self._h, src._h), "qcz_copy_state")
+
+    def mixing_mask(self, gates) -> int:
+        g = _gates(gates)
+        return int(self._lib.qcz_mixing_mask(self._h, g.ctypes.data, len(g)))
 
     def sample(self, seed: int, shots: int) -> np.ndarray:
         out = np.zeros(shots, dtype=np.uint64)
@@ -360,22 +374,22 @@ def decode_chunks(slots, sizes, C: int, stream=None):
 
 
 # -- selector entry points ----------------------------------------------------
-def label_levels(sizes, w, beta: float) -> np.ndarray:
+def label_levels(sizes, w, beta: float, mask: int = 0) -> np.ndarray:
     """Host call: Lagrangian level labels (sizes [nblocks, 6] u64, w [nblocks])."""
     S = np.ascontiguousarray(np.asarray(sizes, dtype=np.uint64))
     W = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
     out = np.zeros(W.size, dtype=np.uint8)
-    rc = load().qcz_label_levels(S.ctypes.data, W.ctypes.data, W.size, float(beta), out.ctypes.data)
+    rc = load().qcz_label_levels(S.ctypes.data, W.ctypes.data, W.size, float(beta), int(mask), out.ctypes.data)
     if rc != 0:
         raise QczError(rc, "qcz_label_levels")
     return out
 
 
-def project_levels(levels, w, beta: float) -> np.ndarray:
+def project_levels(levels, w, beta: float, mask: int = 0) -> np.ndarray:
     """Host call: budget projection of per-block levels."""
     L = np.ascontiguousarray(np.asarray(levels, dtype=np.uint8)).copy()
     W = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
-    rc = load().qcz_project_levels(W.ctypes.data, W.size, float(beta), L.ctypes.data)
+    rc = load().qcz_project_levels(W.ctypes.data, W.size, float(beta), int(mask), L.ctypes.data)
     if rc != 0:
         raise QczError(rc, "qcz_project_levels")
     return L

@@ -41,9 +41,9 @@ def test_block_features_match_oracle(n, bl, level, seed):
     say("features n=%d bl=%d" % (n, bl))
     g, o = pair(n, bl, oq.MODE_PERBLOCK, level, gates, levels)
     assert_same_chunks(g, o, "before statistics")
-    for beta in (1e-4, 0.0):
-        X, n2 = g.block_stats(beta)
-        F, n2o = sr.block_features(o, levels, beta)
+    for beta, mask in ((1e-4, 0), (0.0, nb - 1)):
+        X, n2 = g.block_stats(beta, mask)
+        F, n2o = sr.block_features(o, levels, beta, mask)
         Xg = X.cpu().numpy()
         assert np.allclose(n2.cpu().numpy(), n2o, rtol=1e-12, atol=1e-300)
         Fo = F.astype(np.float32)
@@ -141,16 +141,16 @@ def test_select_levels_projects_the_network_choice():
     gates = cc.concat([cc.grover_prefix(n), cc.random_circuit_small(n, depth=4, seed=5)])
     g, _ = pair(n, bl, oq.MODE_PERBLOCK, 2, gates)
     params = torch.tensor(_params(5, scale=1.0), dtype=torch.float32, device="cuda")
-    for beta in (1e-5, 1e-3, 0.0):
-        say("select beta=%g" % beta)
-        X, n2 = g.block_stats(beta)
+    for beta, mask in ((1e-5, 0), (1e-3, 0b1010), (1e-3, 0b1), (0.0, 0)):
+        say("select beta=%g mask=%d" % (beta, mask))
+        X, n2 = g.block_stats(beta, mask)
         _, lev = qcz.mlp_forward(params, X)
         w = n2.cpu().numpy()
         w = w / w.sum()
-        want = sr.project_levels(lev.cpu().numpy(), w, beta)
-        got = g.select_levels(params, beta)
+        want = sr.project_levels(lev.cpu().numpy(), w, beta, mask)
+        got = g.select_levels(params, beta, mask)
         assert np.array_equal(got, want)
-        assert sr._weighted(got, w) <= beta * sr.SLACK
+        assert sr._weighted(got, w, mask) <= beta * sr.SLACK
 
 
 def test_attached_selector_equals_manual_selection():
@@ -164,8 +164,13 @@ def test_attached_selector_equals_manual_selection():
     say("attached selector")
     assert a.apply(gates) == len(gates)
     for k in range(0, len(gates), K):
-        b.select_levels(params, beta)
-        b.apply(gates[k:k + K])
+        win = gates[k:k + K]
+        mask = 0
+        for gt in win:
+            if gt["kind"] in (0, 3) and gt["target"] >= bl:
+                mask |= 1 << (int(gt["target"]) - bl)
+        b.select_levels(params, beta, mask)
+        b.apply(win)
     for c in range(a.nchunks):
         assert a.export_chunk(c) == b.export_chunk(c)
     assert a.footprint()["fidelity_lower_bound"] == pytest.approx(b.footprint()["fidelity_lower_bound"], rel=1e-14)

@@ -1,0 +1,78 @@
+"""The learned per-block level selector against the plain rule (one bound
+for every block) on held-out circuits, at the same per-step error budget:
+trained on device from teacher traces of small circuits, it must never end
+with a lower fidelity bound than the rule, and it must need fewer bytes on
+a circuit whose block weights are uneven.  The gain is measured, not pinned
+to a value from the paper (the paper has no per-block selector)."""
+import numpy as np
+import pytest
+
+from oracle import qcz_oracle as oq
+from paper_1911_04034_amd import circuits as cc
+from tests.gpu_util import assert_same_chunks, say
+
+pytestmark = pytest.mark.gpu
+
+PERIOD = 16
+BETA = 1e-4
+
+
+def test_copy_state_then_diverge():
+    from paper_1911_04034_amd import qcz
+    n, bl = 12, 8
+    a_gates = cc.random_circuit_small(n, depth=6, seed=3)
+    b_gates = cc.random_unitary_gates(n, 40, 4)
+    src = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=2, pool_bytes=64 << 20)
+    dst = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=2, pool_bytes=64 << 20)
+    o = oq.Sim(n, bl, oq.MODE_FIXED, 2)
+    say("copy state")
+    src.apply(a_gates)
+    dst.apply(b_gates[:5])          # different contents before the copy
+    dst.copy_from(src)
+    o.apply(a_gates)
+    assert_same_chunks(dst, o, "after copy")
+    fa, fb = dst.footprint(), src.footprint()
+    for k in ("compressed_bytes", "level", "gates_applied", "lossy_steps", "fidelity_lower_bound", "ratio"):
+        assert fa[k] == fb[k], k
+    src.apply(b_gates)
+    dst.apply(b_gates)
+    o.apply(b_gates)
+    assert_same_chunks(dst, o, "copy then gates")
+    assert_same_chunks(src, o, "source then gates")
+
+
+def test_mixing_mask():
+    from paper_1911_04034_amd import qcz
+    n, bl = 12, 8
+    st = qcz.State(n, bl, pool_bytes=32 << 20)
+    g = cc.concat([cc.h(9), cc.t(11), cc.x(10, controls=(2,)), cc.cz(8, 11), cc.rzz(8, 9, 0.3), cc.h(3)])
+    assert st.mixing_mask(g) == 0b0110
+    assert st.mixing_mask(cc.concat([cc.t(9), cc.h(2)])) == 0
+
+
+def test_selector_gain_on_held_out_circuits():
+    from paper_1911_04034_amd import selector as sel
+    train = [(cc.biased_local(12, 6, 8, 1), 12, 6), (cc.biased_local(13, 7, 8, 2), 13, 7),
+             (cc.biased_local(13, 6, 8, 3), 13, 6), (cc.grover(12, 12, 11)[0], 12, 6),
+             (cc.random_circuit_small(12, 12, 13), 12, 6), (cc.qft(12, cc.qft_input(12, 14)), 12, 6),
+             (cc.qaoa(12, 3, 3, 15)[0], 12, 6)]
+    say("teacher traces")
+    X, y = sel.training_set(train, (1e-5, 1e-4, 1e-3), PERIOD)
+    say("training on %d samples" % X.shape[0])
+    params, losses = sel.train(X, y, steps=1500, lr=3e-3, seed=0)
+    acc = sel.accuracy(params, X, y)
+    say("loss %.4f -> %.4f, accuracy %.3f" % (losses[0], losses[-1], acc))
+    assert losses[-1] < 0.5 * losses[0] and acc > 0.85
+    held_out = {"biased14": (cc.biased_local(14, 7, 10, 21), 14, 7),
+                "qaoa14": (cc.qaoa(14, 4, 3, 22)[0], 14, 7),
+                "grover14": (cc.grover(14, 10, 21)[0], 14, 7),
+                "rand14": (cc.random_circuit_small(14, 10, 23), 14, 7)}
+    gains = {}
+    for name, (gates, n, bl) in held_out.items():
+        r, fr = sel.run_rule(gates, n, bl, BETA, PERIOD)
+        s, fs = sel.run_selector(gates, n, bl, BETA, PERIOD, params)
+        gains[name] = r.mean() / s.mean()
+        say("%s: rule mean %.0f B F_lb %.6f | selector mean %.0f B F_lb %.6f | gain %.3f"
+            % (name, r.mean(), fr, s.mean(), fs, gains[name]))
+        assert fs >= fr - 1e-12
+    assert gains["biased14"] > 1.08

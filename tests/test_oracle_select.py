@@ -108,6 +108,33 @@ def test_labels_extremes():
     assert sr.label_levels(S, w0, 0.0)[2] == 5
 
 
+@pytest.mark.parametrize("seed,mask", [(0, 0b01), (1, 0b10), (2, 0b11), (3, 0b101)])
+def test_coset_labels_are_optimal_for_their_own_budget(seed, mask):
+    """With a mixing mask the budget counts each coset's weight at its
+    loosest level; brute force over 6^B choices."""
+    B = 8 if mask == 0b101 else 4
+    S, w = _tiny(10 + seed, B)
+    beta = [1e-4, 2e-5, 3e-3, 1e-2][seed]
+    L = sr.label_levels(S, w, beta, mask)
+    used = sr._weighted(L, w, mask)
+    assert used <= beta * sr.SLACK
+    if B == 4:
+        best = min(_cost(S, c) for c in itertools.product(range(6), repeat=B) if sr._weighted(c, w, mask) <= used)
+        assert _cost(S, L) == best
+
+
+def test_coset_weights_and_budget_hand_example():
+    w = np.array([0.4, 0.1, 0.3, 0.2])
+    ids, order, W = sr.coset_weights(w, 0b01)
+    assert order == [0, 2] and W[0] == 0.5 and abs(W[2] - 0.5) < 1e-16
+    # coset {0,1} at max level 3 (1e-3), coset {2,3} at max level 1 (1e-5)
+    assert abs(sr._weighted([3, 0, 1, 1], w, 0b01) - (0.5 * 1e-3 + 0.5 * 1e-5)) < 1e-18
+    # full mixing: one coset, the loosest block sets the bound for all the weight
+    assert abs(sr._weighted([0, 0, 5, 0], w, 0b11) - 0.1) < 1e-16
+    assert list(sr.project_levels([5, 0, 2, 5], w, 1e-2, 0b11)) == [4, 0, 2, 4]
+    assert list(sr.project_levels([5, 0, 2, 5], w, 1e-3, 0b11)) == [3, 0, 2, 3]
+
+
 def test_projection_hand_example():
     w = np.array([0.5, 0.3, 0.2])
     assert list(sr.project_levels([5, 5, 5], w, 0.01)) == [4, 4, 4]
@@ -130,7 +157,9 @@ def test_features_of_basis_state():
         assert f[0] == -60 / 64 and f[1] == 1 and f[11] == -17
         assert f[4] == f[5] == f[6] == 1 and f[7] == 0 and f[8] == 1
         assert f[9] == 20 / (16 * 1024)
-    assert np.allclose(F[:, 12], -1.0, rtol=1e-15) and np.all(F[:, 14] == 2 / 16) and np.all(F[:, 15] == 10 / 32)
+    assert np.allclose(F[:, 12], -1.0, rtol=1e-15) and np.all(F[:, 14] == 2 / 16) and np.all(F[:, 15] == 0)
+    F2, _ = sr.block_features(s, [0] * 4, 1e-5, mask=0b11)
+    assert np.all(F2[:, 15] == 2 / 16) and np.array_equal(F2[:, :15], F[:, :15])
 
 
 def test_features_of_uniform_state():
