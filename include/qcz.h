@@ -162,9 +162,19 @@ qcz_status qcz_decode_chunks_to(qcz_state *st, uint64_t first_chunk, uint64_t n_
  * configuration). */
 qcz_status qcz_moments(qcz_state *st, double out[3]);
 
-/* Draw `shots` basis indices with probability |a_i|^2 / sum |a|^2 without
- * collapsing the state; deterministic for a seed. */
+/* Draw `shots` basis indices (host out_idx) with probability
+ * |a_i|^2 / sum |a|^2 without collapsing the state.  Shot k uses
+ * u_k = (SplitMix64 output k for state `seed`) >> 11, times 2^-53, and
+ * t = u_k * (sum over chunks of their squared norms, in chunk order): the
+ * chunk is the first whose running norm exceeds t, the amplitude the first
+ * in it whose running |a|^2 (index order) exceeds the rest of t (the last
+ * nonzero one if rounding runs past the end).  QCZ_E_STATE for a zero state. */
 qcz_status qcz_sample(qcz_state *st, uint64_t seed, size_t shots, uint64_t *out_idx);
+
+/* <a|b> = sum_i conj(a_i) b_i over the decoded states (host outputs); a and
+ * b have the same qubit count and chunk size.  Work runs on a's stream after
+ * b's stream is drained; a's and b's scratch areas are used. */
+qcz_status qcz_overlap(qcz_state *a, qcz_state *b, double *out_re, double *out_im);
 
 qcz_status qcz_footprint(qcz_state *st, qcz_footprint_t *out);
 

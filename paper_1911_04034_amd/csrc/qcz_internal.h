@@ -138,6 +138,7 @@ hipError_t launch_moments(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io
 hipError_t launch_chunk_stats(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);
 hipError_t launch_level_sizes(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);
 hipError_t launch_zero_u64(uint64_t *p, uint64_t n, hipStream_t st);
+hipError_t launch_dot(const double *a, const double *b, uint64_t npairs, double *partials, int grid, hipStream_t st);
 
 // Selector kernels (qcz_select.hip).
 struct FeatCtx {

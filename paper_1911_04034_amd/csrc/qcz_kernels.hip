@@ -1308,6 +1308,36 @@ hipError_t launch_level_sizes(const GateDesc &gd, const DevPtrs &P, const IOPtrs
     return launch_job<SRC_ARENA, DST_LSIZES, false>(gd, P, io, grid, st);
 }
 
+// partial sums of conj(a) . b over interleaved complex values, one pair per workgroup
+__global__ __launch_bounds__(kWG) void dot_kernel(const double *a, const double *b, uint64_t npairs, double *partials)
+{
+    __shared__ double red[kWG / 64][2];
+    double re = 0.0, im = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < npairs; i += (uint64_t)gridDim.x * kWG) {
+        const double ar = a[2 * i], ai = a[2 * i + 1], br = b[2 * i], bi = b[2 * i + 1];
+        re += ar * br + ai * bi;
+        im += ar * bi - ai * br;
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        re += __shfl_down(re, d, 64);
+        im += __shfl_down(im, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6][0] = re; red[threadIdx.x >> 6][1] = im; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0, m = 0.0;
+        for (int w = 0; w < kWG / 64; ++w) { r += red[w][0]; m += red[w][1]; }
+        partials[2 * blockIdx.x] = r;
+        partials[2 * blockIdx.x + 1] = m;
+    }
+}
+
+hipError_t launch_dot(const double *a, const double *b, uint64_t npairs, double *partials, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(dot_kernel, dim3(grid), dim3(kWG), 0, st, a, b, npairs, partials);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kWG) void zero_u64_kernel(uint64_t *p, uint64_t n)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kWG) p[i] = 0ull;

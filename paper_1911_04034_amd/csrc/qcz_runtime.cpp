@@ -1030,11 +1030,129 @@ qcz_status qcz_moments(qcz_state *s, double out[3])
     return QCZ_OK;
 }
 
+// SplitMix64 (Steele, Lea and Flood, 2014): output k of the generator whose
+// state starts at `seed`.
+static uint64_t splitmix64_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 qcz_status qcz_sample(qcz_state *s, uint64_t seed, size_t shots, uint64_t *out_idx)
 {
     if (!s || (shots && !out_idx)) return QCZ_E_INVAL;
-    (void)seed;
-    return fail(s, QCZ_E_STATE, "sampling is not available in this build");
+    if (shots == 0) return QCZ_OK;
+    // squared norm of every chunk (device), prefix sums in chunk order (host)
+    std::vector<double> cdf(s->nchunks);
+    {
+        double *cs = (double *)(s->pool + s->lay.cstats);
+        const uint64_t per = std::min<uint64_t>(s->nchunks, kStatChunks);
+        std::vector<double> rec((size_t)per * kChunkStats);
+        for (uint64_t c0 = 0; c0 < s->nchunks; c0 += per) {
+            const uint64_t m = std::min<uint64_t>(per, s->nchunks - c0);
+            GateDesc d{};
+            single_kernel_chunks(s, d, m, 0);
+            d.block_shift = s->bl - s->cb;
+            IOPtrs io{};
+            io.first = c0;
+            io.cstats = cs;
+            const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(d.njobs, (uint64_t)s->grid_max));
+            HIPCHK(s, launch_chunk_stats(d, ptrs(s), io, grid, s->stream));
+            HIPCHK(s, hipMemcpyAsync(rec.data(), cs, 8 * kChunkStats * m, hipMemcpyDeviceToHost, s->stream));
+            HIPCHK(s, hipStreamSynchronize(s->stream));
+            for (uint64_t k = 0; k < m; ++k) cdf[c0 + k] = rec[k * kChunkStats + CS_N2];
+        }
+    }
+    double run = 0.0;
+    uint64_t last_nz = 0;
+    for (uint64_t c = 0; c < s->nchunks; ++c) {
+        if (cdf[c] > 0.0) last_nz = c;
+        run += cdf[c];
+        cdf[c] = run;
+    }
+    const double total = run;
+    if (!(total > 0.0)) return fail(s, QCZ_E_STATE, "the state has zero norm");
+    // chunk of every shot
+    std::vector<double> target(shots);
+    std::vector<uint64_t> chunk_of(shots);
+    for (size_t k = 0; k < shots; ++k) {
+        const double u = (double)(splitmix64_at(seed, k) >> 11) * 0x1.0p-53;
+        const double t = u * total;
+        uint64_t c = (uint64_t)(std::upper_bound(cdf.begin(), cdf.end(), t) - cdf.begin());
+        if (c >= s->nchunks) c = last_nz;
+        chunk_of[k] = c;
+        target[k] = t - (c ? cdf[c - 1] : 0.0);
+    }
+    std::vector<uint64_t> chunks(chunk_of);
+    std::sort(chunks.begin(), chunks.end());
+    chunks.erase(std::unique(chunks.begin(), chunks.end()), chunks.end());
+    double *raw = (double *)s->scratch;
+    uint64_t *list = (uint64_t *)(s->scratch + (size_t)kScratchChunks * 8 * (size_t)s->C);
+    std::vector<double> host((size_t)kScratchChunks * (size_t)s->C);
+    const uint64_t amps = (uint64_t)s->C / 2;
+    for (size_t base = 0; base < chunks.size(); base += kScratchChunks) {
+        const size_t m = std::min<size_t>(kScratchChunks, chunks.size() - base);
+        HIPCHK(s, hipMemcpyAsync(list, chunks.data() + base, m * 8, hipMemcpyHostToDevice, s->stream));
+        GateDesc d{};
+        single_kernel_chunks(s, d, m, 0);
+        IOPtrs io{};
+        io.list = list;
+        io.raw_out = raw;
+        const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(d.njobs, (uint64_t)s->grid_max));
+        HIPCHK(s, launch_readout(d, ptrs(s), io, grid, s->stream));
+        HIPCHK(s, hipMemcpyAsync(host.data(), raw, m * 8 * (size_t)s->C, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        for (size_t k = 0; k < shots; ++k) {
+            auto it = std::lower_bound(chunks.begin() + base, chunks.begin() + base + m, chunk_of[k]);
+            if (it == chunks.begin() + base + m || *it != chunk_of[k]) continue;
+            const double *a = host.data() + (size_t)(it - (chunks.begin() + base)) * (size_t)s->C;
+            // first amplitude whose running |a|^2 passes the target (last nonzero one if rounding runs past)
+            double acc = 0.0;
+            uint64_t pick = amps, nz = 0;
+            for (uint64_t i = 0; i < amps; ++i) {
+                const double p = a[2 * i] * a[2 * i] + a[2 * i + 1] * a[2 * i + 1];
+                if (p > 0.0) nz = i;
+                acc += p;
+                if (acc > target[k]) { pick = i; break; }
+            }
+            if (pick == amps) pick = nz;
+            out_idx[k] = chunk_of[k] * amps + pick;
+        }
+    }
+    return QCZ_OK;
+}
+
+qcz_status qcz_overlap(qcz_state *a, qcz_state *b, double *out_re, double *out_im)
+{
+    if (!a || !b || !out_re || !out_im) return QCZ_E_INVAL;
+    if (a->n != b->n || a->C != b->C) return fail(a, QCZ_E_INVAL, "overlap needs the same qubits and chunk size");
+    HIPCHK(a, hipStreamSynchronize(b->stream));
+    double re = 0.0, im = 0.0;
+    double *ra = (double *)a->scratch, *rb = (double *)b->scratch;
+    std::vector<double> part(512);
+    for (uint64_t c0 = 0; c0 < a->nchunks; c0 += kScratchChunks) {
+        const uint64_t m = std::min<uint64_t>(kScratchChunks, a->nchunks - c0);
+        GateDesc d{};
+        single_kernel_chunks(a, d, m, 0);
+        IOPtrs io{};
+        io.first = c0;
+        io.raw_out = ra;
+        const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(d.njobs, (uint64_t)a->grid_max));
+        HIPCHK(a, launch_readout(d, ptrs(a), io, grid, a->stream));
+        io.raw_out = rb;
+        HIPCHK(a, launch_readout(d, ptrs(b), io, grid, a->stream));
+        const uint64_t npairs = m * (uint64_t)a->C / 2;
+        const int dg = (int)std::min<uint64_t>(256, (npairs + kWG - 1) / kWG);
+        HIPCHK(a, launch_dot(ra, rb, npairs, a->partials, dg, a->stream));
+        HIPCHK(a, hipMemcpyAsync(part.data(), a->partials, 16 * (size_t)dg, hipMemcpyDeviceToHost, a->stream));
+        HIPCHK(a, hipStreamSynchronize(a->stream));
+        for (int g = 0; g < dg; ++g) { re += part[2 * (size_t)g]; im += part[2 * (size_t)g + 1]; }
+    }
+    *out_re = re;
+    *out_im = im;
+    return QCZ_OK;
 }
 
 qcz_status qcz_export_chunk(qcz_state *s, uint64_t chunk, void *host_buf, size_t cap, size_t *len)

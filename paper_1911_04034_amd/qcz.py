@@ -62,7 +62,7 @@ EXPORTED = [
     "qcz_encode_chunks", "qcz_decode_chunks", "qcz_get_stats", "qcz_reset_stats", "qcz_set_launch",
     "qcz_block_stats", "qcz_block_level_sizes", "qcz_label_levels", "qcz_project_levels", "qcz_mlp_forward",
     "qcz_mlp_workspace_bytes", "qcz_mlp_train_step", "qcz_select_levels", "qcz_set_selector", "qcz_copy_state",
-    "qcz_mixing_mask",
+    "qcz_mixing_mask", "qcz_overlap",
 ]
 MLP_PARAMS = 5638
 N_FEATURES = 16
@@ -146,6 +146,8 @@ def load():
     L.qcz_copy_state.argtypes = [vp, vp]
     L.qcz_mixing_mask.restype = u64
     L.qcz_mixing_mask.argtypes = [vp, vp, sz]
+    L.qcz_overlap.restype = i32
+    L.qcz_overlap.argtypes = [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     _lib = L
     return L
 
@@ -335,6 +337,12 @@ class State:
     def mixing_mask(self, gates) -> int:
         g = _gates(gates)
         return int(self._lib.qcz_mixing_mask(self._h, g.ctypes.data, len(g)))
+
+    def overlap(self, other: "State") -> complex:
+        """<self|other> over the decoded states."""
+        re, im = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        self._check(self._lib.qcz_overlap(self._h, other._h, ctypes.byref(re), ctypes.byref(im)), "qcz_overlap")
+        return complex(re.value, im.value)
 
     def sample(self, seed: int, shots: int) -> np.ndarray:
         out = np.zeros(shots, dtype=np.uint64)
