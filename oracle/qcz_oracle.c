@@ -166,20 +166,12 @@ static uint64_t top_mask(int nbits)
 /*               any bit set), then a PACK body (codes area of               */
 /*               4*ceil(nnz/16) bytes and residual stream) over the          */
 /*               subsequence of nonzero values, XOR-chained among themselves. */
-/*   mode PALETTE (3): header bits 5-6 hold P - 1 (P = 1..4 distinct values); */
-/*               then the P distinct values in order of first appearance     */
-/*               (u64 each), then an index area of 4*ceil(C/16) bytes (value */
-/*               i's two-bit palette index at bit 2i).                        */
-/* Header bits 7-31 are zero, and bits 5-6 too except in PALETTE.             */
 /* The chain starts from t_{-1} = 0.  The encoder picks CONST2 when it        */
-/* applies, otherwise the smaller of PACK and SPARSE (PACK on a tie), and    */
-/* PALETTE instead when the chunk has at most four distinct values and the   */
-/* palette stream is strictly smaller than that choice.                      */
+/* applies, otherwise the smaller of PACK and SPARSE (PACK on a tie).         */
 /* ------------------------------------------------------------------------- */
 #define OQ_MODE_PACK 0
 #define OQ_MODE_CONST2 1
 #define OQ_MODE_SPARSE 2
-#define OQ_MODE_PALETTE 3
 
 size_t oq_chunk_cap(int C)
 {
@@ -269,28 +261,7 @@ size_t oq_encode_chunk(const double *x, int C, int level, uint8_t *out)
         size_t bitmap_bytes = 4 * (size_t)((C + 31) / 32);
         size_t pack_size = 4 + pack_body_size(t, C, K);
         size_t sparse_size = 4 + bitmap_bytes + pack_body_size(nz, nnz, K);
-        /* distinct values in order of first appearance (up to five) */
-        uint64_t pal[5];
-        int P = 0;
-        for (int i = 0; i < C && P <= 4; ++i) {
-            int seen = 0;
-            for (int j = 0; j < P; ++j)
-                if (pal[j] == t[i]) seen = 1;
-            if (!seen) pal[P++] = t[i];
-        }
-        size_t best = sparse_size < pack_size ? sparse_size : pack_size;
-        size_t pal_size = 4 + 8 * (size_t)P + 4 * (size_t)((C + 15) / 16);
-        if (P <= 4 && pal_size < best) {
-            put_u32(out, (uint32_t)(OQ_MODE_PALETTE | (lev << 2) | ((P - 1) << 5)));
-            for (int j = 0; j < P; ++j) put_u64(out + 4 + 8 * j, pal[j]);
-            uint64_t ipos = 0;
-            for (int i = 0; i < C; ++i) {
-                int idx = 0;
-                while (pal[idx] != t[i]) ++idx;
-                put_bits(out + 4 + 8 * P, &ipos, (uint64_t)idx, 2);
-            }
-            size = pal_size;
-        } else if (sparse_size < pack_size) {
+        if (sparse_size < pack_size) {
             put_u32(out, (uint32_t)(OQ_MODE_SPARSE | (lev << 2)));
             uint64_t bpos = 0;
             for (int i = 0; i < C; ++i) put_bits(out + 4, &bpos, t[i] != 0, 1);
@@ -311,19 +282,8 @@ int oq_decode_chunk(const uint8_t *in, size_t len, int C, double *x)
     if (C < 4 || (C & (C - 1)) != 0 || len < 4) return -1;
     uint32_t hdr = get_u32(in);
     int mode = (int)(hdr & 3u), lev = (int)((hdr >> 2) & 7u);
-    if ((hdr >> 7) != 0 || lev >= OQ_NLEVELS) return -1;
-    if (mode != OQ_MODE_PALETTE && ((hdr >> 5) & 3u) != 0) return -1;
+    if ((hdr >> 5) != 0 || lev >= OQ_NLEVELS) return -1;
     int K = oq_sig_bits(lev);
-    if (mode == OQ_MODE_PALETTE) {
-        int P = (int)((hdr >> 5) & 3u) + 1;
-        if (len != 4 + 8 * (size_t)P + 4 * (size_t)((C + 15) / 16)) return -1;
-        for (int i = 0; i < C; ++i) {
-            int idx = (int)get_bits(in + 4 + 8 * P, 2 * (uint64_t)i, 2);
-            if (idx >= P) return -1;
-            x[i] = bitsd(get_u64(in + 4 + 8 * idx));
-        }
-        return 0;
-    }
     if (mode == OQ_MODE_CONST2) {
         if (len != 20) return -1;
         uint64_t t0 = get_u64(in + 4), t1 = get_u64(in + 12);
