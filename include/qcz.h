@@ -131,6 +131,8 @@ typedef struct {
     uint32_t grid;              /* launch shape in use: workgroups per fused launch */
     uint32_t tuning;            /* 1 while the autotuner is still measuring */
     uint32_t stops;             /* batches stopped on the device (budget or arena full) and rolled back */
+    uint64_t range_gates;       /* gates run in job ranges because their new streams did not fit at once
+                                   (not event-timed) */
 } qcz_stats_t;
 
 /* Bytes of device pool needed for a configuration (state |0..0> plus

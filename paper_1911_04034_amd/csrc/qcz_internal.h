@@ -39,7 +39,12 @@ struct GateDesc {
     int32_t per_block;              // level from the per-block table instead of the global one
     int32_t block_shift;            // log2(chunks per block)
     int32_t fixed_level;            // >= 0: codec kernels encode at this level
+    uint64_t job0, job_end;         // jobs [job0, job_end) of this launch (job_end 0: all njobs)
 };
+
+// the jobs one launch of a gate runs
+__host__ __device__ inline uint64_t job_begin(const GateDesc &d) { return d.job_end ? d.job0 : 0; }
+__host__ __device__ inline uint64_t job_stop(const GateDesc &d) { return d.job_end ? d.job_end : d.njobs; }
 
 struct GateLog {
     uint64_t live;   // compressed bytes after the gate

@@ -671,7 +671,8 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
     double acc_wd = 0.0, acc_lost = 0.0;   // per-block fidelity ledger terms
     double mom_re = 0.0, mom_im = 0.0, mom_n2 = 0.0;
 
-    for (uint64_t job = blockIdx.x; job < gd.njobs; job += gridDim.x) {
+    const uint64_t jstop = job_stop(gd);
+    for (uint64_t job = job_begin(gd) + blockIdx.x; job < jstop; job += gridDim.x) {
         const uint64_t item0 = 2 * job, item1 = 2 * job + 1;
         const bool valid0 = item0 < gd.nitems, valid1 = item1 < gd.nitems;
         uint64_t cc0 = 0, cc1 = 0;
@@ -1122,7 +1123,10 @@ __global__ __launch_bounds__(kWG) void rollback_kernel(GateDesc gd, DevPtrs P)
         }
         return;
     }
-    for (uint64_t it = (uint64_t)blockIdx.x * kWG + threadIdx.x; it < gd.nitems; it += stride)
+    // the items of jobs [job_begin, job_stop): 2 job .. 2 job + 1
+    const uint64_t it0 = 2 * job_begin(gd);
+    const uint64_t it1 = 2 * job_stop(gd) < gd.nitems ? 2 * job_stop(gd) : gd.nitems;
+    for (uint64_t it = it0 + (uint64_t)blockIdx.x * kWG + threadIdx.x; it < it1; it += stride)
         P.table[item_chunk(gd, it)] = P.undo[it];
 }
 

@@ -249,7 +249,14 @@ int grid_for(const qcz_state *s, const GateDesc &d)
         uint64_t b = (d.njobs + kWG - 1) / kWG;
         return (int)std::max<uint64_t>(1, std::min<uint64_t>(b, 65535));
     }
-    return (int)std::max<uint64_t>(1, std::min<uint64_t>(d.njobs, (uint64_t)s->grid_max));
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(job_stop(d) - job_begin(d), (uint64_t)s->grid_max));
+}
+
+// enumerated chunk positions a launch covers (two per job)
+uint64_t launch_items(const GateDesc &d)
+{
+    const uint64_t i0 = 2 * job_begin(d), i1 = std::min<uint64_t>(2 * job_stop(d), d.nitems);
+    return i1 > i0 ? i1 - i0 : 0;
 }
 
 qcz_status write_header(qcz_state *s)
@@ -320,12 +327,13 @@ qcz_status compact(qcz_state *s)
 // w mod nstripes, so the fullest stripe serves ceil(grid / nstripes) groups.
 uint64_t stripe_share(const qcz_state *s, const GateDesc &d)
 {
-    if (d.job_type == J_PERMUTE || d.nitems == 0) return 0;
+    const uint64_t items = launch_items(d);
+    if (d.job_type == J_PERMUTE || items == 0) return 0;
     const uint64_t mean = s->live / std::max<uint64_t>(1, s->nchunks);
     const uint64_t per = std::min<uint64_t>(2 * mean + 64, (uint64_t)chunk_cap_bytes(s->C) + 4);
     const uint64_t g = (uint64_t)grid_for(s, d);
     const uint64_t groups = (g + (uint64_t)s->nstripes - 1) / (uint64_t)s->nstripes;
-    return (d.nitems * per * groups + g - 1) / g;
+    return (items * per * groups + g - 1) / g;
 }
 
 // Number of leading gates of `descs` whose expected allocations fit in the
@@ -529,6 +537,86 @@ qcz_status block_stats(qcz_state *s, double beta, uint64_t mask, float *X, doubl
         HIPCHK(s, launch_block_features(cs, s->blevel + b0, ctx, nb, X + b0 * kNIn, n2 ? n2 + b0 : nullptr,
                                         s->stream));
     }
+    return QCZ_OK;
+}
+
+// Run one gate whose new streams do not fit next to the live ones: launch
+// its jobs in ranges that fit, each committed before the next (the streams a
+// range replaced become garbage that compaction reclaims).  A range stopped
+// by a full arena is undone, the arena compacted and the range retried, halved
+// on a second stop.  Only for modes without a compressed-size budget: a
+// budget overflow must undo the whole gate, which needs all of its old
+// streams.  The gate counts once in the ledger and the statistics; its
+// launches are not event-timed.
+qcz_status apply_in_ranges(qcz_state *s, const GateDesc &d)
+{
+    const uint64_t nj = d.njobs;
+    uint64_t j = 0, L = nj;
+    bool retried = false;
+    GateLog tot{};
+    auto room = [&]() {
+        const uint64_t fill = max_stripe_fill(s);
+        return s->stripe_size > fill ? s->stripe_size - fill : 0;
+    };
+    while (j < nj) {
+        GateDesc r = d;
+        r.seq = 0;
+        r.job0 = j;
+        r.job_end = std::min<uint64_t>(nj, j + L);
+        if (stripe_share(s, r) > room() && s->bump > s->base) {
+            qcz_status st = compact(s);
+            if (st != QCZ_OK) return st;
+        }
+        while (L > 1 && stripe_share(s, r) > room()) {
+            L = (L + 1) / 2;
+            r.job_end = std::min<uint64_t>(nj, j + L);
+        }
+        const uint64_t live0 = s->live, bump0 = s->bump;
+        qcz_status st = launch_one(s, r, false);
+        if (st != QCZ_OK) return st;
+        HIPCHK(s, hipMemcpyAsync(&s->hds, s->ds, offsetof(DevState, log) + sizeof(GateLog), hipMemcpyDeviceToHost,
+                                 s->stream));
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        const DevState &h = s->hds;
+        for (int k = 0; k < kStripes; ++k) s->stripe_fill[k] = h.stripe[k][0];
+        if (!h.stop) {
+            const GateLog &lg = h.log[0];
+            s->live = lg.live;
+            s->bump = lg.bump;
+            tot.reenc += lg.reenc;
+            tot.rd += lg.rd;
+            tot.wr += lg.wr;
+            tot.wd += lg.wd;
+            tot.lost += lg.lost;
+            j = r.job_end;
+            retried = false;
+            continue;
+        }
+        const int reason = h.stop_reason;
+        s->stats.stops += 1;
+        DevPtrs P = ptrs(s);
+        const int rg = (int)std::max<uint64_t>(1, std::min<uint64_t>((launch_items(r) + kWG - 1) / kWG, 65535));
+        HIPCHK(s, launch_rollback(r, P, rg, s->stream));
+        s->live = live0;
+        s->bump = bump0;
+        st = write_header(s);
+        if (st != QCZ_OK) return st;
+        if (reason != STOP_ARENA) {
+            (void)hipStreamSynchronize(s->stream);
+            return fail(s, QCZ_E_FORMAT, "a chunk table entry points outside the arena");
+        }
+        if (retried) {
+            if (L == 1) return fail(s, QCZ_E_NOMEM, "arena too small for one job of a gate");
+            L = (L + 1) / 2;
+        }
+        st = compact(s);
+        if (st != QCZ_OK) return st;
+        retried = true;
+    }
+    tot.live = s->live;
+    tot.bump = s->bump;
+    s->stats.range_gates += 1;
+    commit_gate(s, tot, d, (int)s->timed.size());
     return QCZ_OK;
 }
 
@@ -827,6 +915,15 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
             if (st != QCZ_OK) return st;
         }
         const size_t fit = gates_that_fit(s, descs);
+        if (fit == 0 && s->cfg.mode != QCZ_MODE_ADAPTIVE && descs[0].job_type != J_PERMUTE && descs[0].njobs > 1) {
+            // one gate needs more arena room than is free: run it in job ranges
+            qcz_status st = apply_in_ranges(s, descs[0]);
+            if (st != QCZ_OK) return st;
+            idx += 1;
+            s->sel_since += 1;
+            if (applied) *applied = idx;
+            continue;
+        }
         if (fit < B) {
             B = std::max<size_t>(1, fit);
             descs.resize(B);
@@ -855,7 +952,7 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
         // undo the stopped gate
         const GateDesc &dstop = descs[(size_t)sseq];
         DevPtrs P = ptrs(s);
-        const uint64_t work = dstop.job_type == J_PERMUTE ? dstop.njobs : dstop.nitems;
+        const uint64_t work = dstop.job_type == J_PERMUTE ? dstop.njobs : launch_items(dstop);
         const int rg = (int)std::max<uint64_t>(1, std::min<uint64_t>((work + kWG - 1) / kWG, 65535));
         HIPCHK(s, launch_rollback(dstop, P, rg, s->stream));
         if (sseq == 0) { s->live = live0; s->bump = bump0; }

@@ -52,7 +52,8 @@ class Stats(ctypes.Structure):
                 ("bytes_read", ctypes.c_uint64), ("bytes_written", ctypes.c_uint64),
                 ("table_bytes", ctypes.c_uint64), ("timed_launches", ctypes.c_uint64),
                 ("gate_kernel_ms", ctypes.c_double), ("chunk_waves", ctypes.c_uint32), ("grid", ctypes.c_uint32),
-                ("tuning", ctypes.c_uint32), ("stops", ctypes.c_uint32)]
+                ("tuning", ctypes.c_uint32), ("stops", ctypes.c_uint32),
+                ("range_gates", ctypes.c_uint64)]
 
 
 EXPORTED = [

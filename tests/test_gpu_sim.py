@@ -242,3 +242,27 @@ def test_sampled_gates_full_size_grover24():
                 assert g.export_chunk(c) == r0 and g.export_chunk(c1) == r1
     theta = math.asin(2.0 ** (-n / 2))
     assert abs(abs(g.read([w])[0]) - abs(math.sin(5 * theta))) < 1e-4
+
+
+def test_gates_split_into_job_ranges_when_arena_is_short():
+    """An arena of about 1.5x the largest state cannot hold a full-state gate's
+    new streams next to the old ones; such gates run in job ranges with
+    compaction between them, and the bytes stay the oracle's."""
+    import ctypes
+    from paper_1911_04034_amd import qcz
+    n, bl = 14, 8
+    gates = cc.random_circuit_small(n, depth=10, seed=41)
+    o = oq.Sim(n, bl, oq.MODE_LOSSLESS)
+    o.apply(gates)
+    peak = o.footprint()["max_compressed"]
+    cfg = qcz.Config(n, bl, 0, 0, 0, 0, 0, 0, 0)
+    pmin = qcz.load().qcz_pool_bytes_min(ctypes.byref(cfg))
+    nchunks = 1 << (n - 8)
+    arena = int(1.5 * peak) + (64 << 10)
+    pool = pmin + 2 * (arena - (64 << 10) - 64 * nchunks)
+    g = qcz.State(n, bl, mode=qcz.MODE_LOSSLESS, pool_bytes=pool, batch=16)
+    say("job ranges: peak %d arena %d" % (peak, arena))
+    assert g.apply(gates) == len(gates)
+    assert g.stats()["range_gates"] > 0
+    assert_same_chunks(g, o, "after ranged gates")
+    assert g.footprint()["compressed_bytes"] == o.footprint()["compressed_bytes"]
