@@ -107,7 +107,8 @@ LARGE = {
     # name: (qubits, block_log2, description)
     "grid30": (30, 20, "30-qubit 5x6-grid random circuit, depth 20, {sqrtX, sqrtY, T} + CZ patterns, bound 1e-4"),
     "grover34": (34, 20, "34-qubit Grover, 8 iterations, bound 1e-5 (256 GiB uncompressed)"),
-    "qaoa34": (34, 20, "34-qubit QAOA, p=4 on a seeded 3-regular graph, adaptive bound with a memory budget "
+    "qaoa34": (34, 20, "34-qubit QAOA, p=4 on a seeded 3-regular graph, bound 1e-4 for every block (the rule); "
+                       "with --selector also the learned per-block levels at the same per-step budget "
                        "(256 GiB uncompressed)"),
 }
 
@@ -124,24 +125,25 @@ def large_config(args, torch, cc, qcz):
     elif args.workload == "grover34":
         w = cc.grover_marked(n, 4)
         gates = cc.concat([cc.grover_prefix(n)] + [cc.grover_iteration(n, w)] * 8)
-        level, mode, pool = 1, qcz.MODE_FIXED, min(160 << 30, free - (16 << 30))
+        level, mode, pool = 1, qcz.MODE_FIXED, min(250 << 30, free - (12 << 30))
     else:
         gates = cc.qaoa(n, 4, 3, 5)[0]
-        level, mode = 0, qcz.MODE_ADAPTIVE
+        level, mode = 2, qcz.MODE_FIXED
         pool = min(250 << 30, free - (12 << 30))
-        budget = pool // 2 - (8 << 30)
     flags = qcz.FLAG_TIMING
-    slice_len = 64
-    walls, stats, st = [], [], None
+    slice_len = 16 if args.workload == "qaoa34" else 64
+    walls, stats, st, trace = [], [], None, []
     for p in range(args.warmup + args.steps):
         st = None
         torch.cuda.empty_cache()
         st = qcz.State(n, bl, mode=mode, level=level, budget=budget, pool_bytes=pool, flags=flags, batch=128)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        trace = []
         for k in range(0, len(gates), slice_len):
             st.apply(gates[k:k + slice_len])
             fp = st.footprint()
+            trace.append(fp["compressed_bytes"])
             log("%s pass %d: %d/%d gates, level %d, compressed %.2f GB" % (
                 args.workload, p, min(k + slice_len, len(gates)), len(gates), fp["level"],
                 fp["compressed_bytes"] / 1e9))
@@ -150,6 +152,40 @@ def large_config(args, torch, cc, qcz):
             walls.append(time.perf_counter() - t0)
             stats.append(st.stats())
     fp = st.footprint()
+    selector = None
+    if args.workload == "qaoa34" and args.selector:
+        # the learned per-block levels at the rule's per-step budget (1e-4), trained on
+        # the device from teacher traces of small circuits (12-13 qubits)
+        from paper_1911_04034_amd import selector as sel
+        train = [(cc.biased_local(12, 6, 8, 1), 12, 6), (cc.biased_local(13, 7, 8, 2), 13, 7),
+                 (cc.biased_local(13, 6, 8, 3), 13, 6), (cc.grover(12, 12, 11)[0], 12, 6),
+                 (cc.random_circuit_small(12, 12, 13), 12, 6), (cc.qft(12, cc.qft_input(12, 14)), 12, 6),
+                 (cc.qaoa(12, 3, 3, 15)[0], 12, 6)]
+        log("selector: teacher traces and training")
+        X, y = sel.training_set(train, (1e-5, 1e-4, 1e-3), 16)
+        params, losses = sel.train(X, y, steps=1500, lr=3e-3, seed=0)
+        acc = sel.accuracy(params, X, y)
+        st = None
+        torch.cuda.empty_cache()
+        st2 = qcz.State(n, bl, mode=qcz.MODE_PERBLOCK, level=0, pool_bytes=pool, batch=128)
+        st2.set_selector(params, 1e-4, 16)
+        t0 = time.perf_counter()
+        strace = []
+        for k in range(0, len(gates), 16):
+            st2.apply(gates[k:k + 16])
+            f2 = st2.footprint()
+            strace.append(f2["compressed_bytes"])
+            log("qaoa34 selector: %d/%d gates, compressed %.2f GB" % (min(k + 16, len(gates)), len(gates),
+                                                                      f2["compressed_bytes"] / 1e9))
+        torch.cuda.synchronize()
+        f2 = st2.footprint()
+        selector = {"train_samples": int(X.shape[0]), "train_loss": [round(losses[0], 4), round(losses[-1], 4)],
+                    "train_accuracy": round(acc, 4), "wall_s": round(time.perf_counter() - t0, 2),
+                    "mean_compressed_bytes": float(np.mean(strace)), "peak_compressed_bytes": f2["max_compressed"],
+                    "fidelity_lower_bound": f2["fidelity_lower_bound"],
+                    "rule_mean_compressed_bytes": float(np.mean(trace)),
+                    "gain_mean_bytes": round(float(np.mean(trace)) / float(np.mean(strace)), 4)}
+        st = st2
     amps = sum(x["amps_touched"] for x in stats)
     kms = sum(x["gate_kernel_ms"] for x in stats)
     timed = sum(x["timed_launches"] for x in stats)
@@ -181,6 +217,8 @@ def large_config(args, torch, cc, qcz):
         "compression_ratio_final": round(fp["ratio"], 3),
         "peak_compressed_bytes": fp["max_compressed"],
         "fidelity": fid,
+        "mean_compressed_bytes": float(np.mean(trace)) if trace else None,
+        "selector": selector,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
                      "kernel": "job_kernel<16, ARENA, ARENA, gate> (fused decode-gate-encode)",
@@ -207,6 +245,7 @@ def main():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--chunk-waves", type=int, default=0, help="wavefronts per chunk in the fused kernel (2, 4, 8)")
     ap.add_argument("--no-timing", action="store_true", help="launch from graphs instead of timing each kernel")
+    ap.add_argument("--selector", action="store_true", help="qaoa34: also run the learned per-block selector")
     args = ap.parse_args()
 
     if args.gpus != 1:

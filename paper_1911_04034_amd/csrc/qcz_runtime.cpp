@@ -541,36 +541,52 @@ qcz_status block_stats(qcz_state *s, double beta, uint64_t mask, float *X, doubl
 }
 
 // Run one gate whose new streams do not fit next to the live ones: launch
-// its jobs in ranges that fit, each committed before the next (the streams a
-// range replaced become garbage that compaction reclaims).  A range stopped
-// by a full arena is undone, the arena compacted and the range retried, halved
-// on a second stop.  Only for modes without a compressed-size budget: a
+// its jobs in ranges, each committed before the next (the streams a range
+// replaced become garbage that compaction reclaims).  Each range takes as
+// many jobs as the free room of the fullest stripe holds at the current
+// bytes-per-chunk estimate (twice the mean stream at first, then 1.25 times
+// what the previous range wrote per chunk, the largest stream after a stop);
+// the arena is compacted when the room holds less than a sixteenth of the
+// gate.  A range stopped by a full arena is undone, the arena compacted and
+// the range retried at half the size per repeated stop (a single job that
+// still does not fit is QCZ_E_NOMEM).  Only for modes without a compressed-size budget: a
 // budget overflow must undo the whole gate, which needs all of its old
 // streams.  The gate counts once in the ledger and the statistics; its
 // launches are not event-timed.
 qcz_status apply_in_ranges(qcz_state *s, const GateDesc &d)
 {
     const uint64_t nj = d.njobs;
-    uint64_t j = 0, L = nj;
-    bool retried = false;
+    const uint64_t cap = (uint64_t)chunk_cap_bytes(s->C) + 4;
+    uint64_t per = std::min<uint64_t>(2 * (s->live / std::max<uint64_t>(1, s->nchunks)) + 64, cap);
+    uint64_t j = 0;
+    int stops_here = 0;
     GateLog tot{};
     auto room = [&]() {
         const uint64_t fill = max_stripe_fill(s);
         return s->stripe_size > fill ? s->stripe_size - fill : 0;
     };
+    // jobs (two chunks each) whose new streams fit in `r` bytes of the fullest stripe
+    auto jobs_fitting = [&](uint64_t r) {
+        const uint64_t gm = (uint64_t)std::max(1, s->grid_max), ns = (uint64_t)std::max(1, s->nstripes);
+        const uint64_t groups = (gm + ns - 1) / ns;
+        const uint64_t big = r * gm / (2 * per * groups);
+        if (big >= gm) return big;
+        return std::min<uint64_t>(gm - 1, ns * (r / (2 * per)));
+    };
     while (j < nj) {
+        const uint64_t left = nj - j;
+        uint64_t L = std::min<uint64_t>(left, jobs_fitting(room()));
+        if (L < std::min<uint64_t>(left, std::max<uint64_t>(1, nj / 16)) && s->bump > s->base) {
+            qcz_status st = compact(s);
+            if (st != QCZ_OK) return st;
+            L = std::min<uint64_t>(left, jobs_fitting(room()));
+        }
+        L >>= std::min(stops_here, 40);   // repeated stops: smaller ranges
+        if (L == 0) L = 1;                 // the device check decides
         GateDesc r = d;
         r.seq = 0;
         r.job0 = j;
-        r.job_end = std::min<uint64_t>(nj, j + L);
-        if (stripe_share(s, r) > room() && s->bump > s->base) {
-            qcz_status st = compact(s);
-            if (st != QCZ_OK) return st;
-        }
-        while (L > 1 && stripe_share(s, r) > room()) {
-            L = (L + 1) / 2;
-            r.job_end = std::min<uint64_t>(nj, j + L);
-        }
+        r.job_end = j + L;
         const uint64_t live0 = s->live, bump0 = s->bump;
         qcz_status st = launch_one(s, r, false);
         if (st != QCZ_OK) return st;
@@ -588,8 +604,9 @@ qcz_status apply_in_ranges(qcz_state *s, const GateDesc &d)
             tot.wr += lg.wr;
             tot.wd += lg.wd;
             tot.lost += lg.lost;
+            if (lg.reenc) per = std::min<uint64_t>(cap, std::max<uint64_t>(64, lg.wr / lg.reenc * 5 / 4));
             j = r.job_end;
-            retried = false;
+            stops_here = 0;
             continue;
         }
         const int reason = h.stop_reason;
@@ -605,13 +622,11 @@ qcz_status apply_in_ranges(qcz_state *s, const GateDesc &d)
             (void)hipStreamSynchronize(s->stream);
             return fail(s, QCZ_E_FORMAT, "a chunk table entry points outside the arena");
         }
-        if (retried) {
-            if (L == 1) return fail(s, QCZ_E_NOMEM, "arena too small for one job of a gate");
-            L = (L + 1) / 2;
-        }
+        if (L == 1 && stops_here > 0) return fail(s, QCZ_E_NOMEM, "arena too small for one job of a gate");
+        per = cap;                       // size the next attempt for the largest streams
+        stops_here += 1;
         st = compact(s);
         if (st != QCZ_OK) return st;
-        retried = true;
     }
     tot.live = s->live;
     tot.bump = s->bump;
@@ -970,7 +985,17 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
         } else if (reason == STOP_ARENA) {
             st = write_header(s);
             if (st != QCZ_OK) return st;
-            if (compacted_for == (int)idx) return fail(s, QCZ_E_NOMEM, "arena too small for one gate after compaction");
+            if (compacted_for == (int)idx) {
+                // the gate's new streams do not fit beside the live ones even after compaction
+                if (s->cfg.mode == QCZ_MODE_ADAPTIVE || dstop.job_type == J_PERMUTE || dstop.njobs < 2)
+                    return fail(s, QCZ_E_NOMEM, "arena too small for one gate after compaction");
+                st = apply_in_ranges(s, dstop);
+                if (st != QCZ_OK) return st;
+                idx += 1;
+                s->sel_since += 1;
+                if (applied) *applied = idx;
+                continue;
+            }
             st = compact(s);
             if (st != QCZ_OK) return st;
             compacted_for = (int)idx;

@@ -266,3 +266,27 @@ def test_gates_split_into_job_ranges_when_arena_is_short():
     assert g.stats()["range_gates"] > 0
     assert_same_chunks(g, o, "after ranged gates")
     assert g.footprint()["compressed_bytes"] == o.footprint()["compressed_bytes"]
+
+
+def test_underestimated_gate_falls_back_to_job_ranges():
+    """From a state of two-constant chunks one gate makes every chunk dense:
+    the planner's estimate is far too low, the whole gate stops twice on a
+    full arena, and the gate then runs in job ranges; bytes stay the oracle's."""
+    import ctypes
+    from paper_1911_04034_amd import qcz
+    n, bl = 14, 8
+    gates = cc.concat([cc.grover_prefix(n), cc.random_circuit_small(n, depth=4, seed=43)])
+    o = oq.Sim(n, bl, oq.MODE_LOSSLESS)
+    o.apply(gates)
+    peak = o.footprint()["max_compressed"]
+    cfg = qcz.Config(n, bl, 0, 0, 0, 0, 0, 0, 0)
+    pmin = qcz.load().qcz_pool_bytes_min(ctypes.byref(cfg))
+    nchunks = 1 << (n - 8)
+    arena = int(1.5 * peak) + (64 << 10)
+    pool = pmin + 2 * (arena - (64 << 10) - 64 * nchunks)
+    g = qcz.State(n, bl, mode=qcz.MODE_LOSSLESS, pool_bytes=pool, batch=64)
+    say("range fallback: peak %d arena %d" % (peak, arena))
+    assert g.apply(gates) == len(gates)
+    st = g.stats()
+    assert st["range_gates"] > 0
+    assert_same_chunks(g, o, "after the fallback")
