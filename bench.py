@@ -130,7 +130,7 @@ def large_config(args, torch, cc, qcz):
         gates = cc.qaoa(n, 4, 3, 5)[0]
         level, mode = 2, qcz.MODE_FIXED
         pool = min(250 << 30, free - (12 << 30))
-    flags = qcz.FLAG_TIMING
+    flags = qcz.FLAG_TIMING | qcz.FLAG_RANGES
     slice_len = 16 if args.workload == "qaoa34" else 64
     walls, stats, st, trace = [], [], None, []
     for p in range(args.warmup + args.steps):
@@ -167,7 +167,7 @@ def large_config(args, torch, cc, qcz):
         acc = sel.accuracy(params, X, y)
         st = None
         torch.cuda.empty_cache()
-        st2 = qcz.State(n, bl, mode=qcz.MODE_PERBLOCK, level=0, pool_bytes=pool, batch=128)
+        st2 = qcz.State(n, bl, mode=qcz.MODE_PERBLOCK, level=0, pool_bytes=pool, batch=128, flags=qcz.FLAG_RANGES)
         st2.set_selector(params, 1e-4, 16)
         t0 = time.perf_counter()
         strace = []

@@ -64,6 +64,13 @@ typedef enum {
 #define QCZ_FLAG_AUTOTUNE 4u /* over the first launch batches, rotate the fused kernel's launch shape
                                 (wavefronts per chunk x workgroups per CU), time each shape with events and
                                 keep the fastest per recompressed chunk; results do not depend on the shape */
+#define QCZ_FLAG_RANGES 8u  /* modes without a size budget: a gate whose new streams do not fit beside the
+                               live ones even after compaction runs in job ranges, each committed before the
+                               next, so the arena only needs the live state plus one range.  The price: a
+                               gate that still runs out of arena midway cannot be undone (its replaced
+                               streams are gone); the call returns QCZ_E_NOMEM and the state is invalid
+                               (later qcz_apply_gates calls return QCZ_E_STATE).  Without the flag such a
+                               gate fails with QCZ_E_NOMEM and the state stays at the previous gate. */
 
 typedef struct {
     uint32_t n_qubits;      /* 6 .. 40 */

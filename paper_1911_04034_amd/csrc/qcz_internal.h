@@ -12,8 +12,9 @@ constexpr int kWG = 256;            // threads per workgroup: two chunk slots of
 constexpr int kGroup = 128;         // threads per chunk slot
 constexpr int kCMax = 2048;         // doubles per chunk (1024 amplitudes)
 constexpr int kCMin = 128;          // one value per thread at least
-constexpr int kBufWords = 4304;     // per-slot LDS words: 2*kCMax doubles, or the largest
-                                    // stream plus the slack its bit reader may touch
+constexpr int kBufWords = 4352;     // per-slot LDS words: kCMax doubles at padded positions
+                                    // (one pad double per 16), or the largest stream plus the
+                                    // slack its bit reader may touch
 constexpr int kMaxBatch = 512;      // gates per launch batch (per-gate log entries)
 constexpr int kStripes = 32;        // independent arena allocators (one cache line each)
 constexpr int kMaxGrid = 8192;      // workgroups per gate launch

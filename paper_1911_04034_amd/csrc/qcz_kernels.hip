@@ -67,6 +67,12 @@ __device__ __forceinline__ bool subnormal(uint32_t h, uint32_t l)
 
 __device__ __forceinline__ int clampw(int i) { return i < kBufWords - 1 ? i : kBufWords - 1; }
 
+// LDS position of value i of a decoded chunk: one pad double after every 16
+// values, so that threads owning 16 consecutive values each start in
+// different banks (unpadded, a wavefront's accesses to its values all fall
+// into the same bank)
+__device__ __forceinline__ int vpos(int i) { return i + (i >> 4); }
+
 // bits [sh, sh+32) of the 64-bit word pair (hi:lo)
 __device__ __forceinline__ uint32_t fshr(uint32_t hi, uint32_t lo, uint32_t sh)
 {
@@ -584,14 +590,15 @@ __device__ void apply_gate(const GateDesc &gd, double *v0, double *v1, uint64_t 
         for (int k = tid; k < ca; k += nthreads) {
             uint64_t i = (c0 << cb) | (uint64_t)k;
             if ((i & cm) != cm) continue;
-            double ar = v0[2 * k], ai = v0[2 * k + 1], br = v1[2 * k], bi = v1[2 * k + 1];
+            const int p = vpos(2 * k);
+            double ar = v0[p], ai = v0[p + 1], br = v1[p], bi = v1[p + 1];
             if (gd.kind == K_X) {
-                v0[2 * k] = br; v0[2 * k + 1] = bi; v1[2 * k] = ar; v1[2 * k + 1] = ai;
+                v0[p] = br; v0[p + 1] = bi; v1[p] = ar; v1[p + 1] = ai;
             } else {
                 double yr, yi, zr, zi;
                 lin2(m[0], m[1], m[2], m[3], ar, ai, br, bi, yr, yi);
                 lin2(m[4], m[5], m[6], m[7], ar, ai, br, bi, zr, zi);
-                v0[2 * k] = yr; v0[2 * k + 1] = yi; v1[2 * k] = zr; v1[2 * k + 1] = zi;
+                v0[p] = yr; v0[p + 1] = yi; v1[p] = zr; v1[p + 1] = zi;
             }
         }
         return;
@@ -610,27 +617,30 @@ __device__ void apply_gate(const GateDesc &gd, double *v0, double *v1, uint64_t 
             const int k1 = k0 | (1 << q);
             const uint64_t i = base | (uint64_t)k0;
             if ((i & cm) != cm) continue;
-            double ar = v[2 * k0], ai = v[2 * k0 + 1], br = v[2 * k1], bi = v[2 * k1 + 1];
+            const int p0 = vpos(2 * k0), p1 = vpos(2 * k1);
+            double ar = v[p0], ai = v[p0 + 1], br = v[p1], bi = v[p1 + 1];
             if (gd.kind == K_X) {
-                v[2 * k0] = br; v[2 * k0 + 1] = bi; v[2 * k1] = ar; v[2 * k1 + 1] = ai;
+                v[p0] = br; v[p0 + 1] = bi; v[p1] = ar; v[p1 + 1] = ai;
             } else {
                 double yr, yi, zr, zi;
                 lin2(m[0], m[1], m[2], m[3], ar, ai, br, bi, yr, yi);
                 lin2(m[4], m[5], m[6], m[7], ar, ai, br, bi, zr, zi);
-                v[2 * k0] = yr; v[2 * k0 + 1] = yi; v[2 * k1] = zr; v[2 * k1 + 1] = zi;
+                v[p0] = yr; v[p0 + 1] = yi; v[p1] = zr; v[p1 + 1] = zi;
             }
         } else {
             const uint64_t i = base | (uint64_t)u;
             if ((i & cm) != cm) continue;
             if (gd.kind == K_MCZ) {
-                v[2 * u] = -v[2 * u];
-                v[2 * u + 1] = -v[2 * u + 1];
+                const int p = vpos(2 * u);
+                v[p] = -v[p];
+                v[p + 1] = -v[p + 1];
             } else {
                 int idx = (int)((i >> gd.q) & 1ull);
                 if (gd.kind == K_DIAG2) idx += 2 * (int)((i >> gd.q2) & 1ull);
                 double yr, yi;
-                dmul(m[2 * idx], m[2 * idx + 1], v[2 * u], v[2 * u + 1], yr, yi);
-                v[2 * u] = yr; v[2 * u + 1] = yi;
+                const int p = vpos(2 * u);
+                dmul(m[2 * idx], m[2 * idx + 1], v[p], v[p + 1], yr, yi);
+                v[p] = yr; v[p + 1] = yi;
             }
         }
     }
@@ -711,7 +721,7 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
             if (act && ok_src) stage_words<G>(b, io.slots_in + item * io.slot_words, words, lt);
         } else {  // SRC_RAW
             if (act)
-                for (int w = lt; w < C; w += G) vals[w] = io.raw_in[item * (uint64_t)C + w];
+                for (int w = lt; w < C; w += G) vals[vpos(w)] = io.raw_in[item * (uint64_t)C + w];
         }
         if (lt == 0) sh_src_ok[s] = ok_src ? 1 : 0;
         lds_barrier();
@@ -729,7 +739,7 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
             decode_group<V, WPG>(b, s ? hdr1 : hdr0, use, any_sparse, C, lt, slA, slB, slC, th, tl);
             lds_barrier();
 #pragma unroll
-            for (int k = 0; k < V; ++k) vals[first + k] = u2d(((uint64_t)th[k] << 32) | tl[k]);
+            for (int k = 0; k < V; ++k) vals[vpos(first + k)] = u2d(((uint64_t)th[k] << 32) | tl[k]);
             lds_barrier();
         }
 
@@ -743,18 +753,18 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
         // 4. sink
         if (DST == DST_RAW) {
             if (use)
-                for (int w = lt; w < C; w += G) io.raw_out[item * (uint64_t)C + w] = vals[w];
+                for (int w = lt; w < C; w += G) io.raw_out[item * (uint64_t)C + w] = vals[vpos(w)];
         } else if (DST == DST_MOMENTS) {
             if (use) {
 #pragma unroll
                 for (int k = 0; k < V; k += 2) {
-                    double re = vals[first + k], im = (k + 1 < V) ? vals[first + k + 1] : 0.0;
+                    double re = vals[vpos(first + k)], im = (k + 1 < V) ? vals[vpos(first + k + 1)] : 0.0;
                     mom_re += re;
                     mom_im += im;
                     mom_n2 += re * re + im * im;
                 }
                 if (V == 1) {  // one value per thread: odd threads hold the imaginary parts
-                    double v = vals[first];
+                    double v = vals[vpos(first)];
                     mom_re -= (lt & 1) ? v : 0.0;
                     mom_im += (lt & 1) ? v : 0.0;
                 }
@@ -764,10 +774,10 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
             double n2 = 0.0;
             uint32_t nz = 0, esum = 0, eq8 = 0, eq16 = 0, eq24 = 0, sgn = 0;
             int emax = -1, emin = 4096;
-            uint64_t prev = lt ? d2u(vals[first - 1]) : 0ull;
+            uint64_t prev = lt ? d2u(vals[vpos(first - 1)]) : 0ull;
 #pragma unroll
             for (int k = 0; k < V; ++k) {
-                const double x = vals[first + k];
+                const double x = vals[vpos(first + k)];
                 const uint64_t u = d2u(x);
                 n2 += x * x;
                 const bool isnz = x != 0.0;
@@ -820,12 +830,12 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
             bool sub = false;
 #pragma unroll
             for (int k = 0; k < V; ++k) {
-                const uint64_t x = d2u(vals[first + k]);
+                const uint64_t x = d2u(vals[vpos(first + k)]);
                 xh[k] = (uint32_t)(x >> 32);
                 xl[k] = (uint32_t)x;
                 sub = sub || subnormal(xh[k], xl[k]);
             }
-            const uint32_t xprev_hi = lt ? (uint32_t)(d2u(vals[first - 1]) >> 32) : 0u;
+            const uint32_t xprev_hi = lt ? (uint32_t)(d2u(vals[vpos(first - 1)]) >> 32) : 0u;
             const uint64_t x0 = d2u(vals[0]), x1 = d2u(vals[1]);
             const bool wsub = __any(use && sub);
             if ((tid & 63) == 0) slS[tid >> 6] = wsub ? 1u : 0u;
@@ -847,12 +857,12 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
             bool sub = false;
 #pragma unroll
             for (int k = 0; k < V; ++k) {
-                const uint64_t x = d2u(vals[first + k]);
+                const uint64_t x = d2u(vals[vpos(first + k)]);
                 xh[k] = (uint32_t)(x >> 32);
                 xl[k] = (uint32_t)x;
                 sub = sub || subnormal(xh[k], xl[k]);
             }
-            const uint32_t xprev_hi = lt ? (uint32_t)(d2u(vals[first - 1]) >> 32) : 0u;
+            const uint32_t xprev_hi = lt ? (uint32_t)(d2u(vals[vpos(first - 1)]) >> 32) : 0u;
             const uint64_t x0 = d2u(vals[0]), x1 = d2u(vals[1]);
             int lev_req;
             if (gd.fixed_level >= 0) lev_req = gd.fixed_level;
@@ -873,7 +883,7 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
             if (DST == DST_ARENA && gd.per_block) {
 #pragma unroll
                 for (int k = 0; k < V; ++k) {
-                    const double x = vals[first + k];
+                    const double x = vals[vpos(first + k)];
                     pre += x * x;
                 }
             }

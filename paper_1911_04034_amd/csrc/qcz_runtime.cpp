@@ -118,6 +118,7 @@ struct qcz_state {
     double sel_beta = 0.0;
     uint64_t sel_period = 0, sel_since = 0;
     bool sel_fresh = false;
+    bool broken = false;   // a gate run in ranges failed midway
     std::string err;
     std::vector<GraphEntry> graphs;
     DevState hds{};  // readback staging
@@ -553,6 +554,11 @@ qcz_status block_stats(qcz_state *s, double beta, uint64_t mask, float *X, doubl
 // budget overflow must undo the whole gate, which needs all of its old
 // streams.  The gate counts once in the ledger and the statistics; its
 // launches are not event-timed.
+bool ranges_allowed(const qcz_state *s)
+{
+    return (s->cfg.flags & QCZ_FLAG_RANGES) && s->cfg.mode != QCZ_MODE_ADAPTIVE;
+}
+
 qcz_status apply_in_ranges(qcz_state *s, const GateDesc &d)
 {
     const uint64_t nj = d.njobs;
@@ -622,7 +628,11 @@ qcz_status apply_in_ranges(qcz_state *s, const GateDesc &d)
             (void)hipStreamSynchronize(s->stream);
             return fail(s, QCZ_E_FORMAT, "a chunk table entry points outside the arena");
         }
-        if (L == 1 && stops_here > 0) return fail(s, QCZ_E_NOMEM, "arena too small for one job of a gate");
+        if (L == 1 && stops_here > 0) {
+            if (j == 0) return fail(s, QCZ_E_NOMEM, "arena too small for one job of a gate");
+            s->broken = true;   // earlier ranges of this gate are committed and cannot be undone
+            return fail(s, QCZ_E_NOMEM, "arena ran out midway through a gate run in ranges: the state is invalid");
+        }
         per = cap;                       // size the next attempt for the largest streams
         stops_here += 1;
         st = compact(s);
@@ -895,6 +905,7 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
 {
     if (applied) *applied = 0;
     if (!s || (!gates && n_gates)) return QCZ_E_INVAL;
+    if (s->broken) return fail(s, QCZ_E_STATE, "the state is invalid after a gate failed midway in ranges");
     for (size_t k = 0; k < n_gates; ++k)
         if (check_gate(s, gates[k]) != QCZ_OK)
             return fail(s, QCZ_E_INVAL, "malformed gate record " + std::to_string(k));
@@ -930,7 +941,7 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
             if (st != QCZ_OK) return st;
         }
         const size_t fit = gates_that_fit(s, descs);
-        if (fit == 0 && s->cfg.mode != QCZ_MODE_ADAPTIVE && descs[0].job_type != J_PERMUTE && descs[0].njobs > 1) {
+        if (fit == 0 && ranges_allowed(s) && descs[0].job_type != J_PERMUTE && descs[0].njobs > 1) {
             // one gate needs more arena room than is free: run it in job ranges
             qcz_status st = apply_in_ranges(s, descs[0]);
             if (st != QCZ_OK) return st;
@@ -987,7 +998,7 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
             if (st != QCZ_OK) return st;
             if (compacted_for == (int)idx) {
                 // the gate's new streams do not fit beside the live ones even after compaction
-                if (s->cfg.mode == QCZ_MODE_ADAPTIVE || dstop.job_type == J_PERMUTE || dstop.njobs < 2)
+                if (!ranges_allowed(s) || dstop.job_type == J_PERMUTE || dstop.njobs < 2)
                     return fail(s, QCZ_E_NOMEM, "arena too small for one gate after compaction");
                 st = apply_in_ranges(s, dstop);
                 if (st != QCZ_OK) return st;

@@ -19,6 +19,7 @@ MODE_LOSSLESS, MODE_FIXED, MODE_ADAPTIVE, MODE_PERBLOCK = 0, 1, 2, 3
 FLAG_GRAPH = 1
 FLAG_TIMING = 2
 FLAG_AUTOTUNE = 4
+FLAG_RANGES = 8
 STATUS = {0: "QCZ_OK", -1: "QCZ_E_INVAL", -2: "QCZ_E_NOMEM", -3: "QCZ_E_DEVICE", -4: "QCZ_E_FORMAT",
           -5: "QCZ_E_STATE"}
 

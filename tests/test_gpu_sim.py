@@ -260,7 +260,7 @@ def test_gates_split_into_job_ranges_when_arena_is_short():
     nchunks = 1 << (n - 8)
     arena = int(1.5 * peak) + (64 << 10)
     pool = pmin + 2 * (arena - (64 << 10) - 64 * nchunks)
-    g = qcz.State(n, bl, mode=qcz.MODE_LOSSLESS, pool_bytes=pool, batch=16)
+    g = qcz.State(n, bl, mode=qcz.MODE_LOSSLESS, pool_bytes=pool, batch=16, flags=qcz.FLAG_RANGES)
     say("job ranges: peak %d arena %d" % (peak, arena))
     assert g.apply(gates) == len(gates)
     assert g.stats()["range_gates"] > 0
@@ -284,7 +284,7 @@ def test_underestimated_gate_falls_back_to_job_ranges():
     nchunks = 1 << (n - 8)
     arena = int(1.5 * peak) + (64 << 10)
     pool = pmin + 2 * (arena - (64 << 10) - 64 * nchunks)
-    g = qcz.State(n, bl, mode=qcz.MODE_LOSSLESS, pool_bytes=pool, batch=64)
+    g = qcz.State(n, bl, mode=qcz.MODE_LOSSLESS, pool_bytes=pool, batch=64, flags=qcz.FLAG_RANGES)
     say("range fallback: peak %d arena %d" % (peak, arena))
     assert g.apply(gates) == len(gates)
     st = g.stats()
