@@ -274,14 +274,20 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
     const uint32_t cbit = 2u * rank0;
     const uint32_t cw = fshr(b[clampw(cw0 + (int)(cbit >> 5) + 1)], b[clampw(cw0 + (int)(cbit >> 5))], cbit & 31u);
 
-    // codes by position
+    // codes by position (a SPARSE chunk's codes are in rank order; wave-uniform branch)
     uint32_t Lpos = 0, rsum = 0;
+    if (mode == M_SPARSE) {
 #pragma unroll
-    for (int k = 0; k < V; ++k) {
-        const uint32_t st = (stored >> k) & 1u;
-        const uint32_t L = (cw >> (2u * __popc(stored & ((1u << k) - 1u)))) & 3u;
-        Lpos |= (st ? L : 0u) << (2 * k);
-        rsum += st ? resid_bits(K, L) : 0u;
+        for (int k = 0; k < V; ++k) {
+            const uint32_t st = (stored >> k) & 1u;
+            const uint32_t L = (cw >> (2u * __popc(stored & ((1u << k) - 1u)))) & 3u;
+            Lpos |= (st ? L : 0u) << (2 * k);
+            rsum += st ? resid_bits(K, L) : 0u;
+        }
+    } else if (stored) {
+        Lpos = (V >= 16) ? cw : (cw & ((1u << (2 * V)) - 1u));
+#pragma unroll
+        for (int k = 0; k < V; ++k) rsum += resid_bits(K, (Lpos >> (2 * k)) & 3u);
     }
     uint32_t o, rtot;
     gscan_add<WPG>(rsum, slotB, o, rtot);
@@ -473,16 +479,41 @@ __device__ __forceinline__ void emit_residuals(uint32_t *b, int base, uint32_t o
 {
     const int K = e.K;
     uint32_t j = 0;
+    if (K < 64) {
+        // a thread's fields are contiguous: assemble them in a 64-bit
+        // accumulator and write whole words; only the first word (shared with
+        // the thread before) and the last partial one (shared with the thread
+        // after) need an atomic OR
+        uint64_t acc = 0;
+        uint32_t nb = o & 31u;
+        int wi = base + (int)(o >> 5);
+        bool first = true;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const bool on = ((mask >> k) & 1u) != 0;
+            const uint32_t L = ((sparse ? (codes >> (2 * j)) : (codes >> (2 * k))) & 3u);
+            j += on ? 1u : 0u;
+            const uint32_t r = on ? resid_bits(K, L) : 0u;
+            acc |= (uint64_t)((e.th[k] >> (32 - K)) & low_mask32(r)) << nb;
+            nb += r;
+            if (nb >= 32u) {
+                if (first) atomicOr(&b[clampw(wi)], (uint32_t)acc);
+                else b[clampw(wi)] = (uint32_t)acc;
+                first = false;
+                ++wi;
+                acc >>= 32;
+                nb -= 32u;
+            }
+        }
+        if (nb > 0u) atomicOr(&b[clampw(wi)], (uint32_t)acc);
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < V; ++k) {
         const bool on = ((mask >> k) & 1u) != 0;
         const uint32_t L = ((sparse ? (codes >> (2 * j)) : (codes >> (2 * k))) & 3u);
         j += on ? 1u : 0u;
-        if (K < 64) {
-            const uint32_t r = on ? resid_bits(K, L) : 0u;
-            or_bits32(b, base, o, (e.th[k] >> (32 - K)) & low_mask32(r), r);
-            o += r;
-        } else if (on) {
+        if (on) {
             const uint32_t r = 64u - 8u * L;
             or_bits64(b, base, o, e.th[k] & (~0u >> (8u * L)), e.tl[k]);
             o += r;
