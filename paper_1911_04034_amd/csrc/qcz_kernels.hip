@@ -677,6 +677,66 @@ __device__ void apply_gate(const GateDesc &gd, double *v0, double *v1, uint64_t 
     }
 }
 
+// A single-chunk gate that each thread can apply to its own V values: diagonal
+// phases, multi-controlled Z, and U1 / X whose target pairs lie inside a
+// thread's V/2 amplitudes (2^(q+1) <= V/2).  Same arithmetic as apply_gate.
+template <int V>
+__device__ __forceinline__ bool gate_in_registers(const GateDesc &gd)
+{
+    if (gd.job_type != J_SINGLE || (V & 1)) return false;
+    if (gd.kind == K_DIAG1 || gd.kind == K_DIAG2 || gd.kind == K_MCZ) return true;
+    return (gd.kind == K_U1 || gd.kind == K_X) && (2 << gd.q) <= V / 2;
+}
+
+template <int V, int Q>
+__device__ __forceinline__ void pairs_in_registers(const GateDesc &gd, double (&x)[V], uint64_t base)
+{
+    const double *m = gd.m;
+#pragma unroll
+    for (int a = 0; a < V / 2; ++a) {
+        if (a & (1 << Q)) continue;
+        const int a1 = a | (1 << Q);
+        if (((base | (uint64_t)a) & gd.cm) != gd.cm) continue;
+        const double ar = x[2 * a], ai = x[2 * a + 1], br = x[2 * a1], bi = x[2 * a1 + 1];
+        if (gd.kind == K_X) {
+            x[2 * a] = br; x[2 * a + 1] = bi; x[2 * a1] = ar; x[2 * a1 + 1] = ai;
+        } else {
+            double yr, yi, zr, zi;
+            lin2(m[0], m[1], m[2], m[3], ar, ai, br, bi, yr, yi);
+            lin2(m[4], m[5], m[6], m[7], ar, ai, br, bi, zr, zi);
+            x[2 * a] = yr; x[2 * a + 1] = yi; x[2 * a1] = zr; x[2 * a1 + 1] = zi;
+        }
+    }
+}
+
+// x: my V values (amplitudes base .. base + V/2 - 1 of the state)
+template <int V>
+__device__ __forceinline__ void apply_gate_registers(const GateDesc &gd, double (&x)[V], uint64_t base)
+{
+    const double *m = gd.m;
+    if (gd.kind == K_U1 || gd.kind == K_X) {
+        if (gd.q == 0) pairs_in_registers<V, 0>(gd, x, base);
+        else if (gd.q == 1 && V >= 8) pairs_in_registers<V, (V >= 8 ? 1 : 0)>(gd, x, base);
+        else if (gd.q == 2 && V >= 16) pairs_in_registers<V, (V >= 16 ? 2 : 0)>(gd, x, base);
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < V / 2; ++a) {
+        const uint64_t i = base | (uint64_t)a;
+        if ((i & gd.cm) != gd.cm) continue;
+        if (gd.kind == K_MCZ) {
+            x[2 * a] = -x[2 * a];
+            x[2 * a + 1] = -x[2 * a + 1];
+        } else {
+            int idx = (int)((i >> gd.q) & 1ull);
+            if (gd.kind == K_DIAG2) idx += 2 * (int)((i >> gd.q2) & 1ull);
+            double yr, yi;
+            dmul(m[2 * idx], m[2 * idx + 1], x[2 * a], x[2 * a + 1], yr, yi);
+            x[2 * a] = yr; x[2 * a + 1] = yi;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // the job kernel
 // ---------------------------------------------------------------------------
@@ -769,13 +829,19 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
             uint32_t th[V], tl[V];
             decode_group<V, WPG>(b, s ? hdr1 : hdr0, use, any_sparse, C, lt, slA, slB, slC, th, tl);
             lds_barrier();
+            double x[V];
 #pragma unroll
-            for (int k = 0; k < V; ++k) vals[vpos(first + k)] = u2d(((uint64_t)th[k] << 32) | tl[k]);
+            for (int k = 0; k < V; ++k) x[k] = u2d(((uint64_t)th[k] << 32) | tl[k]);
+            // 3a. a gate each thread applies to its own values (no LDS pass)
+            if (GATE && gate_in_registers<V>(gd) && use)
+                apply_gate_registers<V>(gd, x, (c << P.cb) | (uint64_t)(first / 2));
+#pragma unroll
+            for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
             lds_barrier();
         }
 
-        // 3. gate
-        if (GATE) {
+        // 3. gate (pairs across threads or slots, in LDS)
+        if (GATE && !gate_in_registers<V>(gd)) {
             apply_gate(gd, reinterpret_cast<double *>(buf[0]), reinterpret_cast<double *>(buf[1]), cc0, cc1, use0,
                        use1, P.cb, WGS);
             lds_barrier();
