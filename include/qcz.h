@@ -80,7 +80,7 @@ typedef struct {
     uint64_t budget_bytes;  /* QCZ_MODE_ADAPTIVE: limit on compressed bytes (0: none) */
     uint32_t flags;         /* QCZ_FLAG_* */
     uint32_t batch;         /* gates per launch batch between host checks (0: 64; at most 512) */
-    uint32_t grid;          /* workgroups per gate launch (0: 4 per compute unit) */
+    uint32_t grid;          /* workgroups per gate launch (0: 3 per compute unit) */
     uint32_t chunk_waves;   /* wavefronts working on one chunk in the gate kernel: 2, 4 or 8 (0: 2) */
     uint64_t reserved[3];
 } qcz_config;

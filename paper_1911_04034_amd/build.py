@@ -20,6 +20,9 @@ HIP_FLAGS = [
     "-fPIC",
     "-shared",
     "-ffp-contract=off",
+    # every atomic in the kernels is issued by one lane; the wave-level atomic
+    # combiner would only add a scan and wait for the returned value at once
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     # keep hipcc from forming packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",

@@ -27,13 +27,21 @@ namespace qcz {
 
 // Sig_Bit_Count of Eq. (12) for binary64 (12 sign/exponent bits minus the
 // exponent of the bound) per level: lossless, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1.
-__constant__ int kSig[kLevels] = {64, 29, 26, 22, 19, 16};
+// Selected in registers: the level is a per-lane value, and a table in
+// memory would cost a load and a wait for every outstanding memory access.
+__device__ __forceinline__ int sig_bits(int lev)
+{
+    return lev == 1 ? 29 : lev == 2 ? 26 : lev == 3 ? 22 : lev == 4 ? 19 : lev == 5 ? 16 : 64;
+}
 
 enum { SRC_ARENA = 0, SRC_RAW = 1, SRC_SLOTS = 2 };
 enum { DST_ARENA = 0, DST_RAW = 1, DST_SLOTS = 2, DST_MOMENTS = 3, DST_CSTATS = 4, DST_LSIZES = 5 };
 
 // delta of each level (0 for lossless): the per-value relative bound of Sec. 3.7
-__constant__ double kDeltaDev[kLevels] = {0.0, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1};
+__device__ __forceinline__ double level_delta(int lev)
+{
+    return lev == 1 ? 1e-5 : lev == 2 ? 1e-4 : lev == 3 ? 1e-3 : lev == 4 ? 1e-2 : lev == 5 ? 1e-1 : 0.0;
+}
 
 // ---------------------------------------------------------------------------
 // bit helpers.  A value is handled as its two 32-bit words (hi, lo).  At every
@@ -66,6 +74,7 @@ __device__ __forceinline__ bool subnormal(uint32_t h, uint32_t l)
 }
 
 __device__ __forceinline__ int clampw(int i) { return i < kBufWords - 1 ? i : kBufWords - 1; }
+static_assert(kBufWords % 4 == 0, "stream buffers are cleared in 16-byte units");
 
 // LDS position of value i of a decoded chunk: one pad double after every 16
 // values, so that threads owning 16 consecutive values each start in
@@ -257,7 +266,7 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
     const int mode = (int)(hdr & 3u);
     int lev = (int)((hdr >> 2) & 7u);
     if (lev >= kLevels) lev = 0;
-    const int K = kSig[lev];
+    const int K = sig_bits(lev);
     const int first = lt * V;
     const uint32_t vmask = (V >= 32) ? ~0u : ((1u << V) - 1u);
     uint32_t stored = 0;
@@ -377,7 +386,7 @@ __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], ui
 {
     const int first = lt * V;
     const int lev = sub ? 0 : lev_req;  // a chunk with a subnormal is kept lossless
-    const int K = kSig[lev];
+    const int K = sig_bits(lev);
     const uint32_t mh = sig_mask_hi(K);
     const bool lossless = K >= 64;
     e.c0h = (uint32_t)(x0 >> 32) & mh;
@@ -574,11 +583,30 @@ __device__ __forceinline__ void dmul(double dr, double di, double ar, double ai,
 
 __device__ __forceinline__ bool unit_phase(double re, double im) { return re == 1.0 && im == 0.0; }
 
+// phase idx (0..3) of a diagonal gate, picked in registers: an indexed read
+// of the gate's parameters (or a select between two of them, which the
+// compiler turns into one load from a selected address) would be a memory
+// load per value.  The bit patterns are masked and OR-ed instead.
+__device__ __forceinline__ double pick4(int idx, double a, double b, double c, double d)
+{
+    const uint64_t r = (idx == 0 ? d2u(a) : 0ull) | (idx == 1 ? d2u(b) : 0ull) | (idx == 2 ? d2u(c) : 0ull) |
+                       (idx == 3 ? d2u(d) : 0ull);
+    return u2d(r);
+}
+
+__device__ __forceinline__ void phase_of(const double *m, int idx, double &pr, double &pi)
+{
+    pr = pick4(idx, m[0], m[2], m[4], m[6]);
+    pi = pick4(idx, m[1], m[3], m[5], m[7]);
+}
+
 // a diagonal gate leaves chunk c alone when every phase reachable in it is 1
 __device__ bool diag_touches(const GateDesc &gd, uint64_t c, int cb)
 {
     const int nidx = gd.kind == K_DIAG1 ? 2 : 4;
-    for (int idx = 0; idx < nidx; ++idx) {
+#pragma unroll
+    for (int idx = 0; idx < 4; ++idx) {
+        if (idx >= nidx) break;
         int b1 = idx & 1, b2 = idx >> 1;
         if (gd.q >= cb && (int)((c >> (gd.q - cb)) & 1ull) != b1) continue;
         if (gd.kind == K_DIAG2 && gd.q2 >= cb && (int)((c >> (gd.q2 - cb)) & 1ull) != b2) continue;
@@ -607,6 +635,25 @@ __device__ __forceinline__ uint64_t item_chunk(const GateDesc &gd, uint64_t item
         return (item & 1ull) ? (c | gd.pair_bit) : c;
     }
     return deposit(gd, item);
+}
+
+// chunk id of position `item` of a job (0 when the position is past the end)
+// and whether the job re-encodes it
+template <int SRC, bool GATE>
+__device__ __forceinline__ bool job_slot(const GateDesc &gd, const IOPtrs &io, int cb, uint64_t item, uint64_t &c)
+{
+    const bool valid = item < gd.nitems;
+    if (SRC == SRC_ARENA && !GATE && io.list) c = valid ? io.list[item] : 0;
+    else c = valid ? item_chunk(gd, item) + io.first : 0;
+    return valid && !(GATE && gd.check_phase && !diag_touches(gd, c, cb));
+}
+
+// validity of a table entry's stream: in the arena, within a staging buffer
+__device__ __forceinline__ bool entry_ok(uint64_t entry, uint64_t arena_words)
+{
+    const uint32_t size = (uint32_t)(entry & 0xFFFFull);
+    const uint32_t words = (size + 3u) >> 2;
+    return words <= (uint32_t)(kBufWords - 8) && (entry >> 16) + words <= arena_words && size >= 4;
 }
 
 __device__ void apply_gate(const GateDesc &gd, double *v0, double *v1, uint64_t c0, uint64_t c1, bool a0, bool a1,
@@ -668,9 +715,10 @@ __device__ void apply_gate(const GateDesc &gd, double *v0, double *v1, uint64_t 
             } else {
                 int idx = (int)((i >> gd.q) & 1ull);
                 if (gd.kind == K_DIAG2) idx += 2 * (int)((i >> gd.q2) & 1ull);
-                double yr, yi;
+                double yr, yi, pr, pi;
                 const int p = vpos(2 * u);
-                dmul(m[2 * idx], m[2 * idx + 1], v[p], v[p + 1], yr, yi);
+                phase_of(m, idx, pr, pi);
+                dmul(pr, pi, v[p], v[p + 1], yr, yi);
                 v[p] = yr; v[p + 1] = yi;
             }
         }
@@ -730,8 +778,9 @@ __device__ __forceinline__ void apply_gate_registers(const GateDesc &gd, double 
         } else {
             int idx = (int)((i >> gd.q) & 1ull);
             if (gd.kind == K_DIAG2) idx += 2 * (int)((i >> gd.q2) & 1ull);
-            double yr, yi;
-            dmul(m[2 * idx], m[2 * idx + 1], x[2 * a], x[2 * a + 1], yr, yi);
+            double yr, yi, pr, pi;
+            phase_of(m, idx, pr, pi);
+            dmul(pr, pi, x[2 * a], x[2 * a + 1], yr, yi);
             x[2 * a] = yr; x[2 * a + 1] = yi;
         }
     }
@@ -740,12 +789,15 @@ __device__ __forceinline__ void apply_gate_registers(const GateDesc &gd, double 
 // ---------------------------------------------------------------------------
 // the job kernel
 // ---------------------------------------------------------------------------
+// Two-wavefront groups run three workgroups per CU (three waves per SIMD):
+// the phases of a job wait on HBM, the arena atomic and barriers, and a third
+// workgroup keeps the SIMDs busy meanwhile; that caps a thread at 168 VGPRs.
 template <int V, int WPG, int SRC, int DST, bool GATE>
-__global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, IOPtrs io)
+__global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDesc gd, DevPtrs P, IOPtrs io)
 {
     constexpr int G = 64 * WPG;   // threads per chunk slot
     constexpr int WGS = 2 * G;    // threads per workgroup
-    __shared__ uint32_t buf[2][kBufWords];
+    __shared__ __align__(16) uint32_t buf[2][kBufWords];
     __shared__ uint32_t sh[256];
     __shared__ uint64_t sh_off[2];
     __shared__ int sh_ok[2];
@@ -766,6 +818,8 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
     uint32_t *slA = sh, *slB = sh + 16, *slC = sh + 32, *slE = sh + 48, *slF = sh + 176, *slS = sh + 192;
     const int glevel = (DST == DST_ARENA || DST == DST_SLOTS) && gd.fixed_level < 0 && !gd.per_block ? ds->level : 0;
     const uint64_t ds_nstripes = DST == DST_ARENA ? ds->nstripes : 1;
+    const uint64_t ds_base = DST == DST_ARENA ? ds->base : 0;           // fixed while a gate runs
+    const uint64_t ds_ssize = DST == DST_ARENA ? ds->stripe_size : 0;
 
     uint64_t acc_reenc = 0, acc_rd = 0, acc_wr = 0;
     int64_t acc_delta = 0;
@@ -777,18 +831,8 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
         const uint64_t item0 = 2 * job, item1 = 2 * job + 1;
         const bool valid0 = item0 < gd.nitems, valid1 = item1 < gd.nitems;
         uint64_t cc0 = 0, cc1 = 0;
-        if (SRC == SRC_ARENA && !GATE && io.list) {
-            cc0 = valid0 ? io.list[item0] : 0;
-            cc1 = valid1 ? io.list[item1] : 0;
-        } else {
-            cc0 = valid0 ? item_chunk(gd, item0) + io.first : 0;
-            cc1 = valid1 ? item_chunk(gd, item1) + io.first : 0;
-        }
-        bool act0 = valid0, act1 = valid1;
-        if (GATE && gd.check_phase) {
-            act0 = act0 && diag_touches(gd, cc0, P.cb);
-            act1 = act1 && diag_touches(gd, cc1, P.cb);
-        }
+        const bool act0 = job_slot<SRC, GATE>(gd, io, P.cb, item0, cc0);
+        const bool act1 = job_slot<SRC, GATE>(gd, io, P.cb, item1, cc1);
         const uint64_t item = s ? item1 : item0;
         const uint64_t c = s ? cc1 : cc0;
         const bool valid = s ? valid1 : valid0;
@@ -802,7 +846,7 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
             const uint32_t size = (uint32_t)(old_entry & 0xFFFFull);
             const uint64_t off = old_entry >> 16;
             const uint32_t words = (size + 3u) >> 2;
-            ok_src = words <= (uint32_t)(kBufWords - 8) && off + words <= P.arena_words && size >= 4;
+            ok_src = entry_ok(old_entry, P.arena_words);
             if (act && ok_src) stage_words<G>(b, P.arena + off, words, lt);
             if (act && !ok_src && lt == 0 && ds) atomicExch(&ds->corrupt, 1);
         } else if (SRC == SRC_SLOTS) {
@@ -993,7 +1037,7 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
                     const double t = u2d(((uint64_t)e.th[k] << 32) | e.tl[k]);
                     post += t * t;
                 }
-                acc_wd += kDeltaDev[lev_req] * pre;
+                acc_wd += level_delta(lev_req) * pre;
                 acc_lost += pre - post;
             }
             // claim arena space now; the returned offset is first needed after
@@ -1004,16 +1048,18 @@ __global__ __launch_bounds__(128 * WPG) void job_kernel(GateDesc gd, DevPtrs P, 
                 my_off = atomicAdd((unsigned long long *)&ds->stripe[stripe][0], (unsigned long long)((e.size + 3u) & ~3u));
             lds_barrier();
             const uint32_t words = (e.size + 3u) >> 2;
-            if (enc)
-                for (uint32_t w = lt; w < words; w += G) b[w] = 0u;
+            if (enc) {
+                uint4 *b4 = reinterpret_cast<uint4 *>(b);   // 16-byte aligned; kBufWords % 4 == 0
+                for (uint32_t w = lt; w < (words + 3u) >> 2; w += G) b4[w] = make_uint4(0u, 0u, 0u, 0u);
+            }
             lds_barrier();
             if (enc) encode_emit<V>(b, e, C, lt);
             if (lt == 0) {
                 int ok = 0;
                 if (enc) {
                     if (DST == DST_ARENA) {
-                        ok = (my_off + ((e.size + 3u) & ~3u) <= ds->stripe_size) ? 1 : 0;
-                        my_off += ds->base + (uint64_t)stripe * ds->stripe_size;
+                        ok = (my_off + ((e.size + 3u) & ~3u) <= ds_ssize) ? 1 : 0;
+                        my_off += ds_base + (uint64_t)stripe * ds_ssize;
                         if (!ok) atomicExch(&ds->fail, 1);
                     } else {
                         ok = 1;

@@ -835,12 +835,13 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
     int dev = 0, ncu = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    s->grid_max = cfg->grid ? (int)cfg->grid : 4 * ncu;
+    // one round of resident workgroups (three per CU for two-wavefront groups)
+    s->grid_max = cfg->grid ? (int)cfg->grid : 3 * ncu;
     if (s->grid_max > kMaxGrid) s->grid_max = kMaxGrid;
     if (cfg->flags & QCZ_FLAG_AUTOTUNE) {
         for (int w : {2, 4, 8}) {
             if (s->C % (64 * w) != 0 || s->C / (64 * w) < 1) continue;
-            for (int per_cu : {2, 4, 8}) {
+            for (int per_cu : {2, 3, 4, 6}) {
                 const int g = std::min(per_cu * ncu, kMaxGrid);
                 s->cands.push_back({w, g, 0.0, 0});
             }
