@@ -74,6 +74,9 @@ __device__ __forceinline__ bool subnormal(uint32_t h, uint32_t l)
 }
 
 __device__ __forceinline__ int clampw(int i) { return i < kBufWords - 1 ? i : kBufWords - 1; }
+// first of N consecutive words read together (one ds_read2 for N = 2)
+template <int N>
+__device__ __forceinline__ int clampn(int i) { return i < kBufWords - N ? i : kBufWords - N; }
 static_assert(kBufWords % 4 == 0, "stream buffers are cleared in 16-byte units");
 
 // LDS position of value i of a decoded chunk: one pad double after every 16
@@ -281,7 +284,8 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
     const int cw0 = codes_word0(mode, C);
     const int res_w0 = cw0 + (int)((nnz + 15u) >> 4);
     const uint32_t cbit = 2u * rank0;
-    const uint32_t cw = fshr(b[clampw(cw0 + (int)(cbit >> 5) + 1)], b[clampw(cw0 + (int)(cbit >> 5))], cbit & 31u);
+    const int cwi = clampn<2>(cw0 + (int)(cbit >> 5));
+    const uint32_t cw = fshr(b[cwi + 1], b[cwi], cbit & 31u);
 
     // codes by position (a SPARSE chunk's codes are in rank order; wave-uniform branch)
     uint32_t Lpos = 0, rsum = 0;
@@ -304,19 +308,36 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
     uint32_t carry = 0;
     if (K < 64) {
         const uint32_t up = (uint32_t)(32 - K);
+        // four values at a time: their word pairs are read before any is used,
+        // so one LDS round trip serves four values
+        constexpr int U = V < 4 ? V : 4;
 #pragma unroll
-        for (int k = 0; k < V; ++k) {
-            const uint32_t st = (stored >> k) & 1u;
-            const uint32_t L = (Lpos >> (2 * k)) & 3u;
-            const uint32_t r = st ? resid_bits(K, L) : 0u;
-            const int wi = res_w0 + (int)(o >> 5);
-            const uint32_t R = fshr(b[clampw(wi + 1)], b[clampw(wi)], o & 31u) & low_mask32(r);
-            const uint32_t p = R << up;
-            o += r;
-            th[k] = p;
-            tl[k] = 0u;
-            const uint32_t def = st ? ((7u << L) & 7u) : 0u;
-            carry = carry_op(carry, (p & 0xFFFFFF00u) | def);
+        for (int k0 = 0; k0 < V; k0 += U) {
+            uint32_t lo[U], hi[U], sh[U], rr[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int k = k0 + j;
+                const uint32_t st = (stored >> k) & 1u;
+                const uint32_t L = (Lpos >> (2 * k)) & 3u;
+                rr[j] = st ? resid_bits(K, L) : 0u;
+                const int wi = clampn<2>(res_w0 + (int)(o >> 5));
+                lo[j] = b[wi];
+                hi[j] = b[wi + 1];
+                sh[j] = o & 31u;
+                o += rr[j];
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int k = k0 + j;
+                const uint32_t st = (stored >> k) & 1u;
+                const uint32_t L = (Lpos >> (2 * k)) & 3u;
+                // lossy levels keep at most 29 bits, so rr < 32
+                const uint32_t p = (fshr(hi[j], lo[j], sh[j]) & ((1u << rr[j]) - 1u)) << up;
+                th[k] = p;
+                tl[k] = 0u;
+                const uint32_t def = st ? ((7u << L) & 7u) : 0u;
+                carry = carry_op(carry, (p & 0xFFFFFF00u) | def);
+            }
         }
     } else {
 #pragma unroll
@@ -324,8 +345,8 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
             const uint32_t st = (stored >> k) & 1u;
             const uint32_t L = (Lpos >> (2 * k)) & 3u;
             const uint32_t r = st ? 64u - 8u * L : 0u;
-            const int wi = res_w0 + (int)(o >> 5);
-            const uint32_t w0 = b[clampw(wi)], w1 = b[clampw(wi + 1)], w2 = b[clampw(wi + 2)];
+            const int wi = clampn<3>(res_w0 + (int)(o >> 5));
+            const uint32_t w0 = b[wi], w1 = b[wi + 1], w2 = b[wi + 2];
             const uint32_t Rl = r ? fshr(w1, w0, o & 31u) : 0u;
             const uint32_t Rh = fshr(w2, w1, o & 31u) & (r ? low_mask32(r - 32u) : 0u);
             o += r;
@@ -821,8 +842,10 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     const uint64_t ds_base = DST == DST_ARENA ? ds->base : 0;           // fixed while a gate runs
     const uint64_t ds_ssize = DST == DST_ARENA ? ds->stripe_size : 0;
 
-    uint64_t acc_reenc = 0, acc_rd = 0, acc_wr = 0;
-    int64_t acc_delta = 0;
+    // per-slot totals (size change, re-encoded chunks, bytes read, bytes
+    // written) live in LDS: only thread 0 of a slot updates them
+    if (DST == DST_ARENA && lt == 0)
+        for (int k = 0; k < 4; ++k) sh_acc[4 * s + k] = 0;
     double acc_wd = 0.0, acc_lost = 0.0;   // per-block fidelity ledger terms
     double mom_re = 0.0, mom_im = 0.0, mom_n2 = 0.0;
 
@@ -1085,10 +1108,10 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                         P.table[c] = ((sh_off[s] >> 2) << 16) | (uint64_t)e.size;
                         const uint64_t old_pad = ((old_entry & 0xFFFFull) + 3ull) & ~3ull;
                         const uint64_t new_pad = ((uint64_t)e.size + 3ull) & ~3ull;
-                        acc_delta += (int64_t)new_pad - (int64_t)old_pad;
-                        acc_reenc += 1;
-                        acc_rd += old_pad;
-                        acc_wr += new_pad;
+                        sh_acc[4 * s] += new_pad - old_pad;   // two's complement: the sum is a signed delta
+                        sh_acc[4 * s + 1] += 1;
+                        sh_acc[4 * s + 2] += old_pad;
+                        sh_acc[4 * s + 3] += new_pad;
                     }
                 } else {
                     io.sizes_out[item] = ok ? e.size : 0u;
@@ -1120,12 +1143,6 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
 
     if (DST == DST_ARENA) {
         // per-workgroup totals, then the last workgroup closes the gate
-        if (lt == 0) {
-            sh_acc[4 * s] = (uint64_t)acc_delta;
-            sh_acc[4 * s + 1] = acc_reenc;
-            sh_acc[4 * s + 2] = acc_rd;
-            sh_acc[4 * s + 3] = acc_wr;
-        }
         if (gd.per_block) {
             double a = acc_wd, l = acc_lost;
             for (int d = 32; d >= 1; d >>= 1) {
