@@ -64,7 +64,16 @@ __device__ __forceinline__ uint32_t resid_bits(int K, uint32_t L)
     return r > 0 ? (uint32_t)r : 0u;
 }
 
-__device__ __forceinline__ uint32_t top_mask32(uint32_t L) { return L ? (~0u << (32u - 8u * L)) : 0u; }
+// residual bits of n values whose two-bit codes are packed in `codes`
+// (positions past n hold code 0 and are not counted)
+__device__ __forceinline__ uint32_t resid_total(uint32_t codes, int K, uint32_t n)
+{
+    const uint32_t lo = codes & 0x55555555u, hi = (codes >> 1) & 0x55555555u;
+    const uint32_t n3 = __popc(lo & hi), n2 = __popc(hi & ~lo), n1 = __popc(lo & ~hi);
+    return (n - n1 - n2 - n3) * resid_bits(K, 0) + n1 * resid_bits(K, 1) + n2 * resid_bits(K, 2) +
+           n3 * resid_bits(K, 3);
+}
+
 __device__ __forceinline__ uint32_t low_mask32(uint32_t r) { return r >= 32u ? ~0u : ((1u << r) - 1u); }
 __device__ __forceinline__ uint32_t sig_mask_hi(int K) { return K >= 32 ? ~0u : ~((1u << (32 - K)) - 1u); }
 
@@ -299,13 +308,15 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
         }
     } else if (stored) {
         Lpos = (V >= 16) ? cw : (cw & ((1u << (2 * V)) - 1u));
-#pragma unroll
-        for (int k = 0; k < V; ++k) rsum += resid_bits(K, (Lpos >> (2 * k)) & 3u);
+        rsum = resid_total(Lpos, K, (uint32_t)V);
     }
     uint32_t o, rtot;
     gscan_add<WPG>(rsum, slotB, o, rtot);
 
-    uint32_t carry = 0;
+    // carry-out of my values for the leading-byte scan: the top three bytes
+    // as last defined by one of my stored values (a value with L shared
+    // leading bytes defines the 3 - L after them) and the smallest such L
+    uint32_t cbytes = 0, cmin = 3;
     if (K < 64) {
         const uint32_t up = (uint32_t)(32 - K);
         // four values at a time: their word pairs are read before any is used,
@@ -335,8 +346,10 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
                 const uint32_t p = (fshr(hi[j], lo[j], sh[j]) & ((1u << rr[j]) - 1u)) << up;
                 th[k] = p;
                 tl[k] = 0u;
-                const uint32_t def = st ? ((7u << L) & 7u) : 0u;
-                carry = carry_op(carry, (p & 0xFFFFFF00u) | def);
+                const uint32_t Ls = st ? L : 3u;
+                const uint32_t own = (~0u >> (8u * Ls)) & 0xFFFFFF00u;
+                cbytes = (own & p) | (~own & cbytes);
+                cmin = Ls < cmin ? Ls : cmin;
             }
         }
     } else {
@@ -352,10 +365,14 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
             o += r;
             th[k] = Rh;
             tl[k] = Rl;
-            const uint32_t def = st ? ((7u << L) & 7u) : 0u;
-            carry = carry_op(carry, (Rh & 0xFFFFFF00u) | def);
+            const uint32_t Ls = st ? L : 3u;
+            const uint32_t own = (~0u >> (8u * Ls)) & 0xFFFFFF00u;
+            cbytes = (own & Rh) | (~own & cbytes);
+            cmin = Ls < cmin ? Ls : cmin;
         }
     }
+    // (low three bits: which of the three bytes are defined, top byte first)
+    const uint32_t carry = cbytes | ((7u << cmin) & 7u);
     // the value before the chunk is 0: every leading byte defined as zero
     uint32_t prev = carry_op(7u, gscan_carry<WPG>(carry, slotC)) & 0xFFFFFF00u;
     if (mode == M_CONST2) {
@@ -371,7 +388,9 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             const uint32_t st = (stored >> k) & 1u;
-            const uint32_t v = (prev & top_mask32((Lpos >> (2 * k)) & 3u)) | th[k];
+            // the L leading bytes shared with the previous value, the rest mine
+            const uint32_t mine = ~0u >> (8u * ((Lpos >> (2 * k)) & 3u));
+            const uint32_t v = (mine & th[k]) | (~mine & prev);
             th[k] = st ? v : 0u;
             tl[k] = st ? tl[k] : 0u;
             prev = st ? v : prev;
@@ -415,7 +434,7 @@ __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], ui
     e.c1h = (uint32_t)(x1 >> 32) & mh;
     e.c1l = lossless ? (uint32_t)x1 : 0u;
 
-    uint32_t bad = 0, rp = 0, nzm = 0, codes = 0, lf = 0, lv = 0;
+    uint32_t badbits = 0, nzm = 0, codes = 0, lf = 0, lv = 0;
     uint32_t prev = xprev_hi & mh;
 #pragma unroll
     for (int k = 0; k < V; ++k) {
@@ -424,10 +443,9 @@ __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], ui
         e.th[k] = h;
         e.tl[k] = l;
         const bool odd = ((first + k) & 1) != 0;
-        bad += (h != (odd ? e.c1h : e.c0h) || l != (odd ? e.c1l : e.c0l)) ? 1u : 0u;
+        badbits |= (h ^ (odd ? e.c1h : e.c0h)) | (l ^ (odd ? e.c1l : e.c0l));   // differs from value 0 / 1
         const uint32_t L = lead_bytes(h, prev);
         codes |= L << (2 * k);
-        rp += resid_bits(K, L);
         prev = h;
         const bool nz = (h | l) != 0;
         nzm |= nz ? (1u << k) : 0u;
@@ -435,6 +453,8 @@ __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], ui
         lf |= nz ? 1u : 0u;
     }
     const uint32_t cnt = __popc(nzm);
+    const uint32_t bad = badbits ? 1u : 0u;
+    const uint32_t rp = resid_total(codes, K, (uint32_t)V);
     uint32_t tot[3], in_f, in_v;
     gscan_enc<WPG>(bad, rp, cnt, lf, lv, slotB, e.pack_off, e.rank0, tot, in_f, in_v);
     const bool const2 = tot[0] == 0;
@@ -523,8 +543,8 @@ __device__ __forceinline__ void emit_residuals(uint32_t *b, int base, uint32_t o
             const bool on = ((mask >> k) & 1u) != 0;
             const uint32_t L = ((sparse ? (codes >> (2 * j)) : (codes >> (2 * k))) & 3u);
             j += on ? 1u : 0u;
-            const uint32_t r = on ? resid_bits(K, L) : 0u;
-            acc |= (uint64_t)((e.th[k] >> (32 - K)) & low_mask32(r)) << nb;
+            const uint32_t r = on ? resid_bits(K, L) : 0u;   // < 32 at every lossy level
+            acc |= (uint64_t)((e.th[k] >> (32 - K)) & ((1u << r) - 1u)) << nb;
             nb += r;
             if (nb >= 32u) {
                 if (first) atomicOr(&b[clampw(wi)], (uint32_t)acc);
