@@ -777,15 +777,33 @@ __device__ __forceinline__ bool gate_in_registers(const GateDesc &gd)
     return (gd.kind == K_U1 || gd.kind == K_X) && (2 << gd.q) <= V / 2;
 }
 
+// A thread holds amplitudes base .. base + V/2 - 1 with base a multiple of
+// V/2: an amplitude index splits into the thread's fixed high bits and the
+// low bits a (a compile-time loop index).  Control tests and phase indices
+// are split the same way, so the per-amplitude part is uniform over the wave.
+template <int V>
+struct RegSplit {
+    static constexpr int A = V / 2;                                // amplitudes per thread
+    static constexpr int LB = A >= 8 ? 3 : A >= 4 ? 2 : A >= 2 ? 1 : 0;   // log2(A)
+    bool mine;       // my high bits satisfy the high controls
+    uint32_t cm_lo;  // controls among the low bits
+    __device__ __forceinline__ RegSplit(const GateDesc &gd, uint64_t base)
+    {
+        const uint64_t hi_mask = ~(uint64_t)(A - 1);
+        mine = (base & gd.cm & hi_mask) == (gd.cm & hi_mask);
+        cm_lo = (uint32_t)(gd.cm & (uint64_t)(A - 1));
+    }
+};
+
 template <int V, int Q>
-__device__ __forceinline__ void pairs_in_registers(const GateDesc &gd, double (&x)[V], uint64_t base)
+__device__ __forceinline__ void pairs_in_registers(const GateDesc &gd, double (&x)[V], const RegSplit<V> &sp)
 {
     const double *m = gd.m;
 #pragma unroll
     for (int a = 0; a < V / 2; ++a) {
         if (a & (1 << Q)) continue;
         const int a1 = a | (1 << Q);
-        if (((base | (uint64_t)a) & gd.cm) != gd.cm) continue;
+        if (((uint32_t)a & sp.cm_lo) != sp.cm_lo) continue;
         const double ar = x[2 * a], ai = x[2 * a + 1], br = x[2 * a1], bi = x[2 * a1 + 1];
         if (gd.kind == K_X) {
             x[2 * a] = br; x[2 * a + 1] = bi; x[2 * a1] = ar; x[2 * a1 + 1] = ai;
@@ -802,28 +820,51 @@ __device__ __forceinline__ void pairs_in_registers(const GateDesc &gd, double (&
 template <int V>
 __device__ __forceinline__ void apply_gate_registers(const GateDesc &gd, double (&x)[V], uint64_t base)
 {
-    const double *m = gd.m;
+    const RegSplit<V> sp(gd, base);
+    if (!sp.mine) return;
+    constexpr int LB = RegSplit<V>::LB;
     if (gd.kind == K_U1 || gd.kind == K_X) {
-        if (gd.q == 0) pairs_in_registers<V, 0>(gd, x, base);
-        else if (gd.q == 1 && V >= 8) pairs_in_registers<V, (V >= 8 ? 1 : 0)>(gd, x, base);
-        else if (gd.q == 2 && V >= 16) pairs_in_registers<V, (V >= 16 ? 2 : 0)>(gd, x, base);
+        if (gd.q == 0) pairs_in_registers<V, 0>(gd, x, sp);
+        else if (gd.q == 1 && V >= 8) pairs_in_registers<V, (V >= 8 ? 1 : 0)>(gd, x, sp);
+        else if (gd.q == 2 && V >= 16) pairs_in_registers<V, (V >= 16 ? 2 : 0)>(gd, x, sp);
+        return;
+    }
+    if (gd.kind == K_MCZ) {
+#pragma unroll
+        for (int a = 0; a < V / 2; ++a) {
+            if (((uint32_t)a & sp.cm_lo) != sp.cm_lo) continue;
+            x[2 * a] = -x[2 * a];
+            x[2 * a + 1] = -x[2 * a + 1];
+        }
+        return;
+    }
+    // diagonal: phase index bit 0 from qubit q, bit 1 from qubit q2 (DIAG2)
+    const int q = gd.q, q2 = gd.kind == K_DIAG2 ? gd.q2 : -1;
+    const bool q_lo = q < LB, q2_lo = q2 >= 0 && q2 < LB;
+    uint32_t ihi = 0;
+    if (!q_lo) ihi |= (uint32_t)(base >> q) & 1u;
+    if (q2 >= 0 && !q2_lo) ihi |= ((uint32_t)(base >> q2) & 1u) << 1;
+    if (!q_lo && !q2_lo) {
+        // one phase for all my amplitudes
+        double pr, pi;
+        phase_of(gd.m, (int)ihi, pr, pi);
+#pragma unroll
+        for (int a = 0; a < V / 2; ++a) {
+            if (((uint32_t)a & sp.cm_lo) != sp.cm_lo) continue;
+            double yr, yi;
+            dmul(pr, pi, x[2 * a], x[2 * a + 1], yr, yi);
+            x[2 * a] = yr; x[2 * a + 1] = yi;
+        }
         return;
     }
 #pragma unroll
     for (int a = 0; a < V / 2; ++a) {
-        const uint64_t i = base | (uint64_t)a;
-        if ((i & gd.cm) != gd.cm) continue;
-        if (gd.kind == K_MCZ) {
-            x[2 * a] = -x[2 * a];
-            x[2 * a + 1] = -x[2 * a + 1];
-        } else {
-            int idx = (int)((i >> gd.q) & 1ull);
-            if (gd.kind == K_DIAG2) idx += 2 * (int)((i >> gd.q2) & 1ull);
-            double yr, yi, pr, pi;
-            phase_of(m, idx, pr, pi);
-            dmul(pr, pi, x[2 * a], x[2 * a + 1], yr, yi);
-            x[2 * a] = yr; x[2 * a + 1] = yi;
-        }
+        if (((uint32_t)a & sp.cm_lo) != sp.cm_lo) continue;
+        const uint32_t idx = ihi | (q_lo ? ((uint32_t)a >> q) & 1u : 0u) | (q2_lo ? (((uint32_t)a >> q2) & 1u) << 1 : 0u);
+        double yr, yi, pr, pi;
+        phase_of(gd.m, (int)idx, pr, pi);
+        dmul(pr, pi, x[2 * a], x[2 * a + 1], yr, yi);
+        x[2 * a] = yr; x[2 * a + 1] = yi;
     }
 }
 
