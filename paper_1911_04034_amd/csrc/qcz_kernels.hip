@@ -54,7 +54,8 @@ __device__ __forceinline__ double u2d(uint64_t b) { return __longlong_as_double(
 
 __device__ __forceinline__ uint32_t lead_bytes(uint32_t cur_hi, uint32_t prev_hi)
 {
-    const uint32_t L = (uint32_t)__clz((int)(cur_hi ^ prev_hi)) >> 3;  // 32 leading zeros -> 4
+    // (| 1: the count never sees zero, so no zero fix-up; equal words give 3)
+    const uint32_t L = (uint32_t)__clz((int)((cur_hi ^ prev_hi) | 1u)) >> 3;
     return L < 3u ? L : 3u;
 }
 
@@ -299,13 +300,16 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
     // codes by position (a SPARSE chunk's codes are in rank order; wave-uniform branch)
     uint32_t Lpos = 0, rsum = 0;
     if (mode == M_SPARSE) {
+        // spread the rank-ordered codes to the stored positions
+        uint32_t j2 = 0;   // two bits per code already taken
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             const uint32_t st = (stored >> k) & 1u;
-            const uint32_t L = (cw >> (2u * __popc(stored & ((1u << k) - 1u)))) & 3u;
+            const uint32_t L = __builtin_amdgcn_ubfe(cw, j2 & 31u, 2u);
             Lpos |= (st ? L : 0u) << (2 * k);
-            rsum += st ? resid_bits(K, L) : 0u;
+            j2 += 2u * st;
         }
+        rsum = resid_total(Lpos, K, (uint32_t)__popc(stored));   // zero codes at empty positions add nothing
     } else if (stored) {
         Lpos = (V >= 16) ? cw : (cw & ((1u << (2 * V)) - 1u));
         rsum = resid_total(Lpos, K, (uint32_t)V);
@@ -418,10 +422,11 @@ struct EncPlan {
 
 // Plan the stream of one chunk.  x: my values (hi, lo); xprev_hi: high word of
 // the value before mine; x0/x1: values 0 and 1 of the chunk.  `sub` is the
-// group's subnormal flag.  Contains barriers: every thread calls it.
+// group's subnormal flag.  Contains barriers: every thread calls it; the plan
+// of a group with no chunk (stale values) is computed and ignored.
 template <int V, int WPG>
 __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], uint32_t xprev_hi, uint64_t x0,
-                            uint64_t x1, int lev_req, bool active, bool sub, int C, int lt, uint32_t *slotB,
+                            uint64_t x1, int lev_req, bool sub, int C, int lt, uint32_t *slotB,
                             uint32_t *slotC, EncPlan<V> &e)
 {
     const int first = lt * V;
@@ -438,8 +443,8 @@ __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], ui
     uint32_t prev = xprev_hi & mh;
 #pragma unroll
     for (int k = 0; k < V; ++k) {
-        const uint32_t h = active ? (xh[k] & mh) : 0u;
-        const uint32_t l = (active && lossless) ? xl[k] : 0u;
+        const uint32_t h = xh[k] & mh;
+        const uint32_t l = lossless ? xl[k] : 0u;
         e.th[k] = h;
         e.tl[k] = l;
         const bool odd = ((first + k) & 1) != 0;
@@ -450,9 +455,9 @@ __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], ui
         const bool nz = (h | l) != 0;
         nzm |= nz ? (1u << k) : 0u;
         lv = nz ? h : lv;
-        lf |= nz ? 1u : 0u;
     }
     const uint32_t cnt = __popc(nzm);
+    lf = nzm ? 1u : 0u;
     const uint32_t bad = badbits ? 1u : 0u;
     const uint32_t rp = resid_total(codes, K, (uint32_t)V);
     uint32_t tot[3], in_f, in_v;
@@ -476,18 +481,22 @@ __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], ui
     e.scodes = 0;
     e.sp_off = 0;
     if (need_me || need_other) {
-        uint32_t sprev = in_f ? in_v : 0u;
-        uint32_t rs = 0, scodes = 0, j = 0;
+        // (the scan has a barrier: both slots take part when either needs it)
+        uint32_t rs = 0;
+        if (need_me) {
+            uint32_t sprev = in_f ? in_v : 0u;
+            uint32_t scodes = 0, j2 = 0;
 #pragma unroll
-        for (int k = 0; k < V; ++k) {
-            const bool nz = ((nzm >> k) & 1u) != 0;
-            const uint32_t L = lead_bytes(e.th[k], sprev);
-            scodes |= nz ? (L << (2 * j)) : 0u;
-            j += nz ? 1u : 0u;
-            rs += nz ? resid_bits(K, L) : 0u;
-            sprev = nz ? e.th[k] : sprev;
+            for (int k = 0; k < V; ++k) {
+                const bool nz = ((nzm >> k) & 1u) != 0;
+                const uint32_t L = lead_bytes(e.th[k], sprev);
+                scodes |= nz ? (L << (j2 & 31u)) : 0u;
+                j2 += nz ? 2u : 0u;
+                sprev = nz ? e.th[k] : sprev;
+            }
+            e.scodes = scodes;
+            rs = resid_total(scodes, K, cnt);
         }
-        e.scodes = scodes;
         gscan_add<WPG>(rs, slotC, e.sp_off, RS);
     }
     const uint32_t pack_size = 4u + 4u * (uint32_t)((C + 15) / 16) + (RP + 7u) / 8u;
@@ -544,7 +553,7 @@ __device__ __forceinline__ void emit_residuals(uint32_t *b, int base, uint32_t o
             const uint32_t L = ((sparse ? (codes >> (2 * j)) : (codes >> (2 * k))) & 3u);
             j += on ? 1u : 0u;
             const uint32_t r = on ? resid_bits(K, L) : 0u;   // < 32 at every lossy level
-            acc |= (uint64_t)((e.th[k] >> (32 - K)) & ((1u << r) - 1u)) << nb;
+            acc |= (uint64_t)__builtin_amdgcn_ubfe(e.th[k], (uint32_t)(32 - K), r) << nb;   // r bits from bit 32 - K
             nb += r;
             if (nb >= 32u) {
                 if (first) atomicOr(&b[clampw(wi)], (uint32_t)acc);
@@ -1070,7 +1079,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             for (int i = 0; i < WPG; ++i) gs |= slS[s * WPG + i];
             for (int lev = 0; lev < kLevels; ++lev) {
                 EncPlan<V> e;
-                encode_plan<V, WPG>(xh, xl, xprev_hi, x0, x1, lev, use, gs != 0, C, lt, slE, slF, e);
+                encode_plan<V, WPG>(xh, xl, xprev_hi, x0, x1, lev, gs != 0, C, lt, slE, slF, e);
                 if (lt == 0 && use)
                     atomicAdd((unsigned long long *)&io.lsizes[(c >> gd.block_shift) * kLevels + lev],
                               (unsigned long long)((e.size + 3u) & ~3u));
@@ -1113,7 +1122,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                 }
             }
             EncPlan<V> e;
-            encode_plan<V, WPG>(xh, xl, xprev_hi, x0, x1, lev_req, enc, gsub, C, lt, slE, slF, e);
+            encode_plan<V, WPG>(xh, xl, xprev_hi, x0, x1, lev_req, gsub, C, lt, slE, slF, e);
             if (DST == DST_ARENA && gd.per_block && enc) {
                 double post = 0.0;
 #pragma unroll
