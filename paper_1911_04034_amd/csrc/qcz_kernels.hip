@@ -323,6 +323,15 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
     uint32_t cbytes = 0, cmin = 3;
     if (K < 64) {
         const uint32_t up = (uint32_t)(32 - K);
+        // residual width of each code, one byte apiece
+        const uint32_t rtab = resid_bits(K, 0) | (resid_bits(K, 1) << 8) | (resid_bits(K, 2) << 16) |
+                              (resid_bits(K, 3) << 24);
+        // my fields lie in [o, o + rsum) past the first residual word; a valid
+        // stream keeps them inside the buffer, a corrupt one reads empty fields
+        const bool fits = res_w0 + (int)((o + rsum) >> 5) <= kBufWords - 2;
+        const uint32_t rd = fits ? stored : 0u;
+        uint32_t ob = fits ? o : 0u;
+        const uint32_t *bw = b + res_w0;
         // four values at a time: their word pairs are read before any is used,
         // so one LDS round trip serves four values
         constexpr int U = V < 4 ? V : 4;
@@ -332,14 +341,13 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 const int k = k0 + j;
-                const uint32_t st = (stored >> k) & 1u;
                 const uint32_t L = (Lpos >> (2 * k)) & 3u;
-                rr[j] = st ? resid_bits(K, L) : 0u;
-                const int wi = clampn<2>(res_w0 + (int)(o >> 5));
-                lo[j] = b[wi];
-                hi[j] = b[wi + 1];
-                sh[j] = o & 31u;
-                o += rr[j];
+                rr[j] = ((rd >> k) & 1u) ? __builtin_amdgcn_ubfe(rtab, 8u * L, 8u) : 0u;
+                const uint32_t wi = ob >> 5;
+                lo[j] = bw[wi];
+                hi[j] = bw[wi + 1];
+                sh[j] = ob & 31u;
+                ob += rr[j];
             }
 #pragma unroll
             for (int j = 0; j < U; ++j) {
@@ -393,10 +401,10 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
         for (int k = 0; k < V; ++k) {
             const uint32_t st = (stored >> k) & 1u;
             // the L leading bytes shared with the previous value, the rest mine
+            // (an empty position has code 0 and zero words, so it stays zero)
             const uint32_t mine = ~0u >> (8u * ((Lpos >> (2 * k)) & 3u));
             const uint32_t v = (mine & th[k]) | (~mine & prev);
-            th[k] = st ? v : 0u;
-            tl[k] = st ? tl[k] : 0u;
+            th[k] = v;
             prev = st ? v : prev;
         }
     }
