@@ -551,6 +551,9 @@ __device__ __forceinline__ void emit_residuals(uint32_t *b, int base, uint32_t o
         // accumulator and write whole words; only the first word (shared with
         // the thread before) and the last partial one (shared with the thread
         // after) need an atomic OR
+        // (the planned size bounds every word index: no clamping)
+        const uint32_t rtab = resid_bits(K, 0) | (resid_bits(K, 1) << 8) | (resid_bits(K, 2) << 16) |
+                              (resid_bits(K, 3) << 24);
         uint64_t acc = 0;
         uint32_t nb = o & 31u;
         int wi = base + (int)(o >> 5);
@@ -560,19 +563,19 @@ __device__ __forceinline__ void emit_residuals(uint32_t *b, int base, uint32_t o
             const bool on = ((mask >> k) & 1u) != 0;
             const uint32_t L = ((sparse ? (codes >> (2 * j)) : (codes >> (2 * k))) & 3u);
             j += on ? 1u : 0u;
-            const uint32_t r = on ? resid_bits(K, L) : 0u;   // < 32 at every lossy level
+            const uint32_t r = on ? __builtin_amdgcn_ubfe(rtab, 8u * L, 8u) : 0u;   // < 32 at every lossy level
             acc |= (uint64_t)__builtin_amdgcn_ubfe(e.th[k], (uint32_t)(32 - K), r) << nb;   // r bits from bit 32 - K
             nb += r;
             if (nb >= 32u) {
-                if (first) atomicOr(&b[clampw(wi)], (uint32_t)acc);
-                else b[clampw(wi)] = (uint32_t)acc;
+                if (first) atomicOr(&b[wi], (uint32_t)acc);
+                else b[wi] = (uint32_t)acc;
                 first = false;
                 ++wi;
                 acc >>= 32;
                 nb -= 32u;
             }
         }
-        if (nb > 0u) atomicOr(&b[clampw(wi)], (uint32_t)acc);
+        if (nb > 0u) atomicOr(&b[wi], (uint32_t)acc);
         return;
     }
 #pragma unroll
@@ -675,14 +678,17 @@ __device__ bool diag_touches(const GateDesc &gd, uint64_t c, int cb)
 
 __device__ __forceinline__ uint64_t deposit(const GateDesc &gd, uint64_t k)
 {
-    uint64_t c = gd.fixed_val;
-    for (int bpos = 0; bpos < gd.nchunk_bits; ++bpos) {
-        if (!((gd.fixed_mask >> bpos) & 1ull)) {
-            c |= (k & 1ull) << bpos;
-            k >>= 1;
-        }
+    // k's bits fill the chunk-index positions outside fixed_mask in order:
+    // open a hole at every fixed position, lowest first, then set the fixed
+    // values (a loop over the few fixed bits, not over all index bits)
+    uint64_t c = k;
+    uint64_t fm = gd.fixed_mask;
+    while (fm) {
+        const uint64_t low = (fm & (0ull - fm)) - 1ull;   // bits below the lowest fixed one
+        c = ((c & ~low) << 1) | (c & low);
+        fm &= fm - 1ull;
     }
-    return c;
+    return c | gd.fixed_val;
 }
 
 // chunk id of enumerated position `item`
