@@ -644,25 +644,18 @@ __device__ __forceinline__ void dmul(double dr, double di, double ar, double ai,
 
 __device__ __forceinline__ bool unit_phase(double re, double im) { return re == 1.0 && im == 0.0; }
 
-// phase idx (0..3) of a diagonal gate, picked in registers: an indexed read
-// of the gate's parameters (or a select between two of them, which the
-// compiler turns into one load from a selected address) would be a memory
-// load per value.  The bit patterns are masked and OR-ed instead.
-__device__ __forceinline__ double pick4(int idx, double a, double b, double c, double d)
-{
-    const uint64_t r = (idx == 0 ? d2u(a) : 0ull) | (idx == 1 ? d2u(b) : 0ull) | (idx == 2 ? d2u(c) : 0ull) |
-                       (idx == 3 ? d2u(d) : 0ull);
-    return u2d(r);
-}
-
+// phase idx (0..3) of a diagonal gate; m is the workgroup's LDS copy of the
+// gate parameters (an indexed read of the kernel arguments would be a memory
+// load, and its wait would cover every outstanding memory access)
 __device__ __forceinline__ void phase_of(const double *m, int idx, double &pr, double &pi)
 {
-    pr = pick4(idx, m[0], m[2], m[4], m[6]);
-    pi = pick4(idx, m[1], m[3], m[5], m[7]);
+    pr = m[2 * idx];
+    pi = m[2 * idx + 1];
 }
 
 // a diagonal gate leaves chunk c alone when every phase reachable in it is 1
-__device__ bool diag_touches(const GateDesc &gd, uint64_t c, int cb)
+// unit_mask: bit idx set when phase idx is 1 (computed once per launch)
+__device__ bool diag_touches(const GateDesc &gd, uint32_t unit_mask, uint64_t c, int cb)
 {
     const int nidx = gd.kind == K_DIAG1 ? 2 : 4;
 #pragma unroll
@@ -671,7 +664,7 @@ __device__ bool diag_touches(const GateDesc &gd, uint64_t c, int cb)
         int b1 = idx & 1, b2 = idx >> 1;
         if (gd.q >= cb && (int)((c >> (gd.q - cb)) & 1ull) != b1) continue;
         if (gd.kind == K_DIAG2 && gd.q2 >= cb && (int)((c >> (gd.q2 - cb)) & 1ull) != b2) continue;
-        if (!unit_phase(gd.m[2 * idx], gd.m[2 * idx + 1])) return true;
+        if (!((unit_mask >> idx) & 1u)) return true;
     }
     return false;
 }
@@ -704,12 +697,13 @@ __device__ __forceinline__ uint64_t item_chunk(const GateDesc &gd, uint64_t item
 // chunk id of position `item` of a job (0 when the position is past the end)
 // and whether the job re-encodes it
 template <int SRC, bool GATE>
-__device__ __forceinline__ bool job_slot(const GateDesc &gd, const IOPtrs &io, int cb, uint64_t item, uint64_t &c)
+__device__ __forceinline__ bool job_slot(const GateDesc &gd, uint32_t unit_mask, const IOPtrs &io, int cb, uint64_t item,
+                                         uint64_t &c)
 {
     const bool valid = item < gd.nitems;
     if (SRC == SRC_ARENA && !GATE && io.list) c = valid ? io.list[item] : 0;
     else c = valid ? item_chunk(gd, item) + io.first : 0;
-    return valid && !(GATE && gd.check_phase && !diag_touches(gd, c, cb));
+    return valid && !(GATE && gd.check_phase && !diag_touches(gd, unit_mask, c, cb));
 }
 
 // validity of a table entry's stream: in the arena, within a staging buffer
@@ -720,13 +714,12 @@ __device__ __forceinline__ bool entry_ok(uint64_t entry, uint64_t arena_words)
     return words <= (uint32_t)(kBufWords - 8) && (entry >> 16) + words <= arena_words && size >= 4;
 }
 
-__device__ void apply_gate(const GateDesc &gd, double *v0, double *v1, uint64_t c0, uint64_t c1, bool a0, bool a1,
-                           int cb, int nthreads)
+__device__ void apply_gate(const GateDesc &gd, const double *m, double *v0, double *v1, uint64_t c0, uint64_t c1,
+                           bool a0, bool a1, int cb, int nthreads)
 {
     const int tid = threadIdx.x;
     const int ca = 1 << cb;
     const uint64_t cm = gd.cm;
-    const double *m = gd.m;
     if (gd.job_type == J_PAIR) {
         if (!(a0 && a1)) return;
         for (int k = tid; k < ca; k += nthreads) {
@@ -819,9 +812,9 @@ struct RegSplit {
 };
 
 template <int V, int Q>
-__device__ __forceinline__ void pairs_in_registers(const GateDesc &gd, double (&x)[V], const RegSplit<V> &sp)
+__device__ __forceinline__ void pairs_in_registers(const GateDesc &gd, const double *m, double (&x)[V],
+                                                   const RegSplit<V> &sp)
 {
-    const double *m = gd.m;
 #pragma unroll
     for (int a = 0; a < V / 2; ++a) {
         if (a & (1 << Q)) continue;
@@ -841,15 +834,15 @@ __device__ __forceinline__ void pairs_in_registers(const GateDesc &gd, double (&
 
 // x: my V values (amplitudes base .. base + V/2 - 1 of the state)
 template <int V>
-__device__ __forceinline__ void apply_gate_registers(const GateDesc &gd, double (&x)[V], uint64_t base)
+__device__ __forceinline__ void apply_gate_registers(const GateDesc &gd, const double *m, double (&x)[V], uint64_t base)
 {
     const RegSplit<V> sp(gd, base);
     if (!sp.mine) return;
     constexpr int LB = RegSplit<V>::LB;
     if (gd.kind == K_U1 || gd.kind == K_X) {
-        if (gd.q == 0) pairs_in_registers<V, 0>(gd, x, sp);
-        else if (gd.q == 1 && V >= 8) pairs_in_registers<V, (V >= 8 ? 1 : 0)>(gd, x, sp);
-        else if (gd.q == 2 && V >= 16) pairs_in_registers<V, (V >= 16 ? 2 : 0)>(gd, x, sp);
+        if (gd.q == 0) pairs_in_registers<V, 0>(gd, m, x, sp);
+        else if (gd.q == 1 && V >= 8) pairs_in_registers<V, (V >= 8 ? 1 : 0)>(gd, m, x, sp);
+        else if (gd.q == 2 && V >= 16) pairs_in_registers<V, (V >= 16 ? 2 : 0)>(gd, m, x, sp);
         return;
     }
     if (gd.kind == K_MCZ) {
@@ -870,7 +863,7 @@ __device__ __forceinline__ void apply_gate_registers(const GateDesc &gd, double 
     if (!q_lo && !q2_lo) {
         // one phase for all my amplitudes
         double pr, pi;
-        phase_of(gd.m, (int)ihi, pr, pi);
+        phase_of(m, (int)ihi, pr, pi);
 #pragma unroll
         for (int a = 0; a < V / 2; ++a) {
             if (((uint32_t)a & sp.cm_lo) != sp.cm_lo) continue;
@@ -885,7 +878,7 @@ __device__ __forceinline__ void apply_gate_registers(const GateDesc &gd, double 
         if (((uint32_t)a & sp.cm_lo) != sp.cm_lo) continue;
         const uint32_t idx = ihi | (q_lo ? ((uint32_t)a >> q) & 1u : 0u) | (q2_lo ? (((uint32_t)a >> q2) & 1u) << 1 : 0u);
         double yr, yi, pr, pi;
-        phase_of(gd.m, (int)idx, pr, pi);
+        phase_of(m, (int)idx, pr, pi);
         dmul(pr, pi, x[2 * a], x[2 * a + 1], yr, yi);
         x[2 * a] = yr; x[2 * a + 1] = yi;
     }
@@ -910,11 +903,18 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     __shared__ uint64_t sh_acc[8];
     __shared__ double sh_mom[WGS / 64][4];
     __shared__ double sh_cs[DST == DST_CSTATS ? WGS / 64 : 1][9];
+    // the gate's parameters: read in the gate phase from LDS, so that the job
+    // loop does not hold them in scalar registers
+    __shared__ double sh_m[8];
 
     DevState *ds = P.ds;
     if (DST == DST_ARENA && ds->stop) return;
 
     const int tid = threadIdx.x, s = tid / G, lt = tid % G;
+    if (GATE && tid < 8) sh_m[tid] = gd.m[tid];   // first read after the first job's fetch barrier
+    uint32_t unit_mask = 0;                        // phases equal to 1 (diagonal gates)
+    if (GATE)
+        for (int i = 0; i < 4; ++i) unit_mask |= unit_phase(gd.m[2 * i], gd.m[2 * i + 1]) ? (1u << i) : 0u;
     const int C = P.C;
     uint32_t *b = buf[s];
     double *vals = reinterpret_cast<double *>(b);
@@ -938,8 +938,8 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
         const uint64_t item0 = 2 * job, item1 = 2 * job + 1;
         const bool valid0 = item0 < gd.nitems, valid1 = item1 < gd.nitems;
         uint64_t cc0 = 0, cc1 = 0;
-        const bool act0 = job_slot<SRC, GATE>(gd, io, P.cb, item0, cc0);
-        const bool act1 = job_slot<SRC, GATE>(gd, io, P.cb, item1, cc1);
+        const bool act0 = job_slot<SRC, GATE>(gd, unit_mask, io, P.cb, item0, cc0);
+        const bool act1 = job_slot<SRC, GATE>(gd, unit_mask, io, P.cb, item1, cc1);
         const uint64_t item = s ? item1 : item0;
         const uint64_t c = s ? cc1 : cc0;
         const bool valid = s ? valid1 : valid0;
@@ -985,7 +985,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             for (int k = 0; k < V; ++k) x[k] = u2d(((uint64_t)th[k] << 32) | tl[k]);
             // 3a. a gate each thread applies to its own values (no LDS pass)
             if (GATE && gate_in_registers<V>(gd) && use)
-                apply_gate_registers<V>(gd, x, (c << P.cb) | (uint64_t)(first / 2));
+                apply_gate_registers<V>(gd, sh_m, x, (c << P.cb) | (uint64_t)(first / 2));
 #pragma unroll
             for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
             lds_barrier();
@@ -993,7 +993,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
 
         // 3. gate (pairs across threads or slots, in LDS)
         if (GATE && !gate_in_registers<V>(gd)) {
-            apply_gate(gd, reinterpret_cast<double *>(buf[0]), reinterpret_cast<double *>(buf[1]), cc0, cc1, use0,
+            apply_gate(gd, sh_m, reinterpret_cast<double *>(buf[0]), reinterpret_cast<double *>(buf[1]), cc0, cc1, use0,
                        use1, P.cb, WGS);
             lds_barrier();
         }
