@@ -719,20 +719,26 @@ __device__ void apply_gate(const GateDesc &gd, const double *m, double *v0, doub
 {
     const int tid = threadIdx.x;
     const int ca = 1 << cb;
-    const uint64_t cm = gd.cm;
+    // the control test splits into the chunk's index bits (one test per
+    // chunk) and the in-chunk bits (one per amplitude)
+    const uint64_t cm_hi = gd.cm & ~(uint64_t)(ca - 1);
+    const uint32_t cm_lo = (uint32_t)(gd.cm & (uint64_t)(ca - 1));
+    const bool hi0 = ((c0 << cb) & cm_hi) == cm_hi, hi1 = ((c1 << cb) & cm_hi) == cm_hi;
+    // the matrix in registers (m is an LDS copy that the loops below would
+    // otherwise re-read after every store)
+    const double u0r = m[0], u0i = m[1], u1r = m[2], u1i = m[3], u2r = m[4], u2i = m[5], u3r = m[6], u3i = m[7];
     if (gd.job_type == J_PAIR) {
-        if (!(a0 && a1)) return;
+        if (!(a0 && a1 && hi0)) return;
         for (int k = tid; k < ca; k += nthreads) {
-            uint64_t i = (c0 << cb) | (uint64_t)k;
-            if ((i & cm) != cm) continue;
+            if (((uint32_t)k & cm_lo) != cm_lo) continue;
             const int p = vpos(2 * k);
             double ar = v0[p], ai = v0[p + 1], br = v1[p], bi = v1[p + 1];
             if (gd.kind == K_X) {
                 v0[p] = br; v0[p + 1] = bi; v1[p] = ar; v1[p + 1] = ai;
             } else {
                 double yr, yi, zr, zi;
-                lin2(m[0], m[1], m[2], m[3], ar, ai, br, bi, yr, yi);
-                lin2(m[4], m[5], m[6], m[7], ar, ai, br, bi, zr, zi);
+                lin2(u0r, u0i, u1r, u1i, ar, ai, br, bi, yr, yi);
+                lin2(u2r, u2i, u3r, u3i, ar, ai, br, bi, zr, zi);
                 v0[p] = yr; v0[p + 1] = yi; v1[p] = zr; v1[p + 1] = zi;
             }
         }
@@ -740,43 +746,40 @@ __device__ void apply_gate(const GateDesc &gd, const double *m, double *v0, doub
     }
     const bool pairwise = gd.kind == K_U1 || gd.kind == K_X;
     const int units = pairwise ? ca / 2 : ca;
-    for (int w = tid; w < 2 * units; w += nthreads) {
-        const int s = w >= units ? 1 : 0;
-        const int u = w - s * units;
-        if (!(s ? a1 : a0)) continue;
+    for (int s = 0; s < 2; ++s) {
+        if (!(s ? (a1 && hi1) : (a0 && hi0))) continue;
         double *v = s ? v1 : v0;
-        const uint64_t base = (s ? c1 : c0) << cb;
-        if (pairwise) {
-            const int q = gd.q;
-            const int k0 = ((u >> q) << (q + 1)) | (u & ((1 << q) - 1));
-            const int k1 = k0 | (1 << q);
-            const uint64_t i = base | (uint64_t)k0;
-            if ((i & cm) != cm) continue;
-            const int p0 = vpos(2 * k0), p1 = vpos(2 * k1);
-            double ar = v[p0], ai = v[p0 + 1], br = v[p1], bi = v[p1 + 1];
-            if (gd.kind == K_X) {
-                v[p0] = br; v[p0 + 1] = bi; v[p1] = ar; v[p1 + 1] = ai;
+        for (int u = tid; u < units; u += nthreads) {
+            if (pairwise) {
+                const int q = gd.q;
+                const int k0 = ((u >> q) << (q + 1)) | (u & ((1 << q) - 1));
+                const int k1 = k0 | (1 << q);
+                if (((uint32_t)k0 & cm_lo) != cm_lo) continue;
+                const int p0 = vpos(2 * k0), p1 = vpos(2 * k1);
+                double ar = v[p0], ai = v[p0 + 1], br = v[p1], bi = v[p1 + 1];
+                if (gd.kind == K_X) {
+                    v[p0] = br; v[p0 + 1] = bi; v[p1] = ar; v[p1 + 1] = ai;
+                } else {
+                    double yr, yi, zr, zi;
+                    lin2(u0r, u0i, u1r, u1i, ar, ai, br, bi, yr, yi);
+                    lin2(u2r, u2i, u3r, u3i, ar, ai, br, bi, zr, zi);
+                    v[p0] = yr; v[p0 + 1] = yi; v[p1] = zr; v[p1 + 1] = zi;
+                }
             } else {
-                double yr, yi, zr, zi;
-                lin2(m[0], m[1], m[2], m[3], ar, ai, br, bi, yr, yi);
-                lin2(m[4], m[5], m[6], m[7], ar, ai, br, bi, zr, zi);
-                v[p0] = yr; v[p0 + 1] = yi; v[p1] = zr; v[p1 + 1] = zi;
-            }
-        } else {
-            const uint64_t i = base | (uint64_t)u;
-            if ((i & cm) != cm) continue;
-            if (gd.kind == K_MCZ) {
+                if (((uint32_t)u & cm_lo) != cm_lo) continue;
                 const int p = vpos(2 * u);
-                v[p] = -v[p];
-                v[p + 1] = -v[p + 1];
-            } else {
-                int idx = (int)((i >> gd.q) & 1ull);
-                if (gd.kind == K_DIAG2) idx += 2 * (int)((i >> gd.q2) & 1ull);
-                double yr, yi, pr, pi;
-                const int p = vpos(2 * u);
-                phase_of(m, idx, pr, pi);
-                dmul(pr, pi, v[p], v[p + 1], yr, yi);
-                v[p] = yr; v[p + 1] = yi;
+                if (gd.kind == K_MCZ) {
+                    v[p] = -v[p];
+                    v[p + 1] = -v[p + 1];
+                } else {
+                    const uint64_t i = ((s ? c1 : c0) << cb) | (uint64_t)u;
+                    int idx = (int)((i >> gd.q) & 1ull);
+                    if (gd.kind == K_DIAG2) idx += 2 * (int)((i >> gd.q2) & 1ull);
+                    double yr, yi, pr, pi;
+                    phase_of(m, idx, pr, pi);
+                    dmul(pr, pi, v[p], v[p + 1], yr, yi);
+                    v[p] = yr; v[p + 1] = yi;
+                }
             }
         }
     }
