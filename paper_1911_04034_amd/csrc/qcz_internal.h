@@ -132,6 +132,11 @@ constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kNH * kNIn, kOffW2 = kOffB1 + kNH, k
 
 inline uint32_t chunk_cap_bytes(int C) { return 4u + 4u * (uint32_t)((C + 15) / 16) + 8u * (uint32_t)C; }
 
+// Arena bytes a stream of `size` bytes occupies: whole 16-byte units, so that
+// every stream starts 16-byte aligned and moves in 16-byte loads and stores
+// (the compressed-size ledger counts 4-byte padded sizes).
+__host__ __device__ inline uint32_t alloc_bytes(uint32_t size) { return (size + 15u) & ~15u; }
+
 // Host launchers (qcz_kernels.hip).
 hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st, int wpg,
                        hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);

@@ -101,6 +101,33 @@ __device__ __forceinline__ uint32_t fshr(uint32_t hi, uint32_t lo, uint32_t sh)
     return __builtin_amdgcn_alignbit(hi, lo, sh);
 }
 
+// Copy `words` words of a 16-byte aligned stream (its arena allocation is a
+// whole number of 16-byte units) into 16-byte aligned LDS, four 16-byte
+// loads in flight per thread; the last unit may carry up to three words past
+// the stream, which belong to its allocation.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int G>
+__device__ __forceinline__ void stage_units(uint32_t *dst, const uint32_t *src, uint32_t words, int lt)
+{
+    const uint32_t units = (words + 3u) >> 2;
+    const u32x4 *s4 = reinterpret_cast<const u32x4 *>(src);
+    u32x4 *d4 = reinterpret_cast<u32x4 *>(dst);
+    for (uint32_t base = (uint32_t)lt; base < units; base += 4u * G) {
+        u32x4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t w = base + (uint32_t)u * G;
+            v[u] = (w < units) ? __builtin_nontemporal_load(s4 + w) : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t w = base + (uint32_t)u * G;
+            if (w < units) d4[w] = v[u];
+        }
+    }
+}
+
 // Workgroup barrier that orders LDS only: pending global stores and loads
 // are not waited for (no thread of the workgroup reads them back).
 __device__ __forceinline__ void lds_barrier()
@@ -957,7 +984,10 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             const uint64_t off = old_entry >> 16;
             const uint32_t words = (size + 3u) >> 2;
             ok_src = entry_ok(old_entry, P.arena_words);
-            if (act && ok_src) stage_words<G>(b, P.arena + off, words, lt);
+            if (act && ok_src) {
+                if ((off & 3ull) == 0) stage_units<G>(b, P.arena + off, words, lt);
+                else stage_words<G>(b, P.arena + off, words, lt);
+            }
             if (act && !ok_src && lt == 0 && ds) atomicExch(&ds->corrupt, 1);
         } else if (SRC == SRC_SLOTS) {
             const uint32_t size = valid ? io.sizes_in[item] : 0u;
@@ -1155,7 +1185,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             uint64_t my_off = 0;
             const int stripe = (int)(blockIdx.x % (uint32_t)ds_nstripes);
             if (lt == 0 && enc && DST == DST_ARENA)
-                my_off = atomicAdd((unsigned long long *)&ds->stripe[stripe][0], (unsigned long long)((e.size + 3u) & ~3u));
+                my_off = atomicAdd((unsigned long long *)&ds->stripe[stripe][0], (unsigned long long)alloc_bytes(e.size));
             lds_barrier();
             const uint32_t words = (e.size + 3u) >> 2;
             if (enc) {
@@ -1168,7 +1198,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                 int ok = 0;
                 if (enc) {
                     if (DST == DST_ARENA) {
-                        ok = (my_off + ((e.size + 3u) & ~3u) <= ds_ssize) ? 1 : 0;
+                        ok = (my_off + alloc_bytes(e.size) <= ds_ssize) ? 1 : 0;
                         my_off += ds_base + (uint64_t)stripe * ds_ssize;
                         if (!ok) atomicExch(&ds->fail, 1);
                     } else {
@@ -1182,8 +1212,11 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             const int ok = sh_ok[s];
             if (ok) {
                 if (DST == DST_ARENA) {
+                    // whole 16-byte units: the allocation holds them and b[] is zero past the stream
                     const uint64_t offw = sh_off[s] >> 2;
-                    for (uint32_t w = lt; w < words; w += G) P.arena[offw + w] = b[w];
+                    u32x4 *dst4 = reinterpret_cast<u32x4 *>(P.arena + offw);
+                    const u32x4 *b4 = reinterpret_cast<const u32x4 *>(b);
+                    for (uint32_t w = lt; w < (words + 3u) >> 2; w += G) dst4[w] = b4[w];
                 } else {
                     for (uint32_t w = lt; w < words; w += G) io.slots_out[item * io.slot_words + w] = b[w];
                 }
@@ -1407,7 +1440,7 @@ __global__ __launch_bounds__(kWG) void scan_local_kernel(const uint64_t *table, 
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const uint64_t c = base + 4 * threadIdx.x + k;
-        v[k] = c < n ? (((table[c] & 0xFFFFull) + 3ull) & ~3ull) : 0ull;
+        v[k] = c < n ? (uint64_t)alloc_bytes((uint32_t)(table[c] & 0xFFFFull)) : 0ull;
         run += v[k];
     }
     part[threadIdx.x] = run;

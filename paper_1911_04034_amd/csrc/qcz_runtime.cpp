@@ -871,15 +871,16 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
     uint32_t hsz[2] = {0, 0};
     if (hipMemcpyAsync(hsz, sizes, 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess) return bail(QCZ_E_DEVICE);
     if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(QCZ_E_DEVICE);
-    const uint64_t p0 = (hsz[0] + 3u) & ~3u, p1 = (hsz[1] + 3u) & ~3u;
-    if (hipMemcpyAsync(s->arena[0], slots, p0, hipMemcpyDeviceToDevice, s->stream) != hipSuccess ||
-        hipMemcpyAsync((uint8_t *)s->arena[0] + p0, (uint8_t *)slots + slot, p1, hipMemcpyDeviceToDevice, s->stream) !=
-            hipSuccess)
+    // streams start 16-byte aligned in the arena; the ledger counts 4-byte padded sizes
+    const uint64_t p0 = alloc_bytes(hsz[0]), p1 = alloc_bytes(hsz[1]);
+    if (hipMemcpyAsync(s->arena[0], slots, (hsz[0] + 3u) & ~3u, hipMemcpyDeviceToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync((uint8_t *)s->arena[0] + p0, (uint8_t *)slots + slot, (hsz[1] + 3u) & ~3u,
+                       hipMemcpyDeviceToDevice, s->stream) != hipSuccess)
         return bail(QCZ_E_DEVICE);
     DevPtrs P = ptrs(s);
     if (launch_fill_table(P, (0ull << 16) | hsz[0], ((p0 / 4) << 16) | hsz[1], s->stream) != hipSuccess)
         return bail(QCZ_E_DEVICE);
-    s->live = p0 + p1 * (s->nchunks - 1);
+    s->live = ((hsz[0] + 3u) & ~3ull) + ((hsz[1] + 3u) & ~3ull) * (s->nchunks - 1);
     s->min_c = s->max_c = s->live;
     if (reset_stripes(s, p0 + p1) != QCZ_OK) return bail(QCZ_E_DEVICE);
     if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(QCZ_E_DEVICE);
@@ -1314,7 +1315,8 @@ qcz_status qcz_import_chunk(qcz_state *s, uint64_t chunk, const void *host_buf, 
     const uint32_t mode = hdr & 3u, lev = (hdr >> 2) & 7u;
     if ((hdr >> 5) != 0 || lev >= (uint32_t)kLevels || mode > M_SPARSE || (mode == M_CONST2 && len != 20))
         return fail(s, QCZ_E_FORMAT, "bad stream header");
-    const uint64_t pad = (len + 3) & ~(size_t)3;
+    const uint64_t pad = (len + 3) & ~(size_t)3;   // ledger size
+    const uint64_t room_needed = alloc_bytes((uint32_t)len);   // arena allocation (16-byte units)
     auto emptiest = [&]() {
         int best = 0;
         for (int k = 1; k < s->nstripes; ++k)
@@ -1322,11 +1324,11 @@ qcz_status qcz_import_chunk(qcz_state *s, uint64_t chunk, const void *host_buf, 
         return best;
     };
     int sk = emptiest();
-    if (s->stripe_fill[sk] + pad > s->stripe_size) {
+    if (s->stripe_fill[sk] + room_needed > s->stripe_size) {
         qcz_status st = compact(s);
         if (st != QCZ_OK) return st;
         sk = emptiest();
-        if (s->stripe_fill[sk] + pad > s->stripe_size) return fail(s, QCZ_E_NOMEM, "arena full");
+        if (s->stripe_fill[sk] + room_needed > s->stripe_size) return fail(s, QCZ_E_NOMEM, "arena full");
     }
     const uint64_t where = s->base + (uint64_t)sk * s->stripe_size + s->stripe_fill[sk];
     uint64_t old = 0;
@@ -1339,8 +1341,8 @@ qcz_status qcz_import_chunk(qcz_state *s, uint64_t chunk, const void *host_buf, 
     HIPCHK(s, hipMemcpyAsync(s->table + chunk, &entry, 8, hipMemcpyHostToDevice, s->stream));
     const uint64_t old_pad = ((old & 0xFFFF) + 3) & ~3ull;
     s->live = s->live + pad - old_pad;
-    s->stripe_fill[sk] += pad;
-    s->bump += pad;
+    s->stripe_fill[sk] += room_needed;
+    s->bump += room_needed;
     s->hds.stripe[sk][0] = s->stripe_fill[sk];
     HIPCHK(s, hipMemcpyAsync(&s->ds->stripe[sk][0], &s->hds.stripe[sk][0], 8, hipMemcpyHostToDevice, s->stream));
     qcz_status st = write_header(s);
