@@ -244,6 +244,44 @@ def test_sampled_gates_full_size_grover24():
     assert abs(abs(g.read([w])[0]) - abs(math.sin(5 * theta))) < 1e-4
 
 
+def test_sampled_gates_full_size_qft24():
+    """QFT-24 at the benchmark shape: controlled phases run as single-chunk
+    register gates, Hadamards as in-chunk or paired LDS gates; for sampled
+    gates the oracle re-runs one unit of the blockwise loop on the GPU's
+    exported input chunks and must produce the GPU's output bytes."""
+    n, bl = 24, 16
+    from paper_1911_04034_amd import qcz
+    gates = cc.qft(n, cc.qft_input(n, 2))
+    g = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=1, pool_bytes=2 << 30, batch=128)
+    rng = np.random.default_rng(7)
+    cb = g.cb
+    checked = 0
+    for k in range(len(gates)):
+        gate = gates[k:k + 1]
+        if k % 13 != 5:
+            g.apply(gate)
+            continue
+        touched = [c for c in range(g.nchunks) if oq.chunk_role(gate, cb, c) in (1, 2)]
+        sample = touched if len(touched) <= 4 else [int(c) for c in rng.choice(touched, size=4, replace=False)]
+        before = {}
+        for c in sample:
+            before[c] = g.export_chunk(c)
+            if oq.chunk_role(gate, cb, c) == 2:
+                c1 = c | (1 << (int(gate["target"][0]) - cb))
+                before[c1] = g.export_chunk(c1)
+        say("qft24 sampled gate %d kind=%d target=%d touched=%d" % (k, gate["kind"][0], gate["target"][0], len(touched)))
+        g.apply(gate)
+        for c in sample:
+            if oq.chunk_role(gate, cb, c) == 1:
+                assert g.export_chunk(c) == oq.gate_job(gate, cb, g.C, c, before[c], 1)
+            else:
+                c1 = c | (1 << (int(gate["target"][0]) - cb))
+                r0, r1 = oq.gate_job(gate, cb, g.C, c, before[c], 1, c1, before[c1], 1)
+                assert g.export_chunk(c) == r0 and g.export_chunk(c1) == r1
+            checked += 1
+    assert checked >= 20
+
+
 def test_gates_split_into_job_ranges_when_arena_is_short():
     """An arena of about 1.5x the largest state cannot hold a full-state gate's
     new streams next to the old ones; such gates run in job ranges with
