@@ -1186,7 +1186,8 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             const int stripe = (int)(blockIdx.x % (uint32_t)ds_nstripes);
             if (lt == 0 && enc && DST == DST_ARENA)
                 my_off = atomicAdd((unsigned long long *)&ds->stripe[stripe][0], (unsigned long long)alloc_bytes(e.size));
-            lds_barrier();
+            // no barrier before clearing b[]: every read of the decoded values
+            // (and of the other slot's buffer) precedes the plan's last barrier
             const uint32_t words = (e.size + 3u) >> 2;
             if (enc) {
                 uint4 *b4 = reinterpret_cast<uint4 *>(b);   // 16-byte aligned; kBufWords % 4 == 0
