@@ -296,9 +296,11 @@ qcz_status qcz_mlp_train_step(float *dev_params, float *dev_m, float *dev_v, con
                               void *hip_stream);
 
 /* QCZ_MODE_PERBLOCK: block features -> network -> most probable level per
- * block -> budget projection with w_b = n2_b / sum n2 and the window's
- * mix_mask -> block levels of the state.  out_levels (host, n_blocks; may be
- * NULL) receives them. */
+ * block, raised to at least the rule's level (the loosest level with delta
+ * <= beta: one bound for every block already meets the budget) -> budget
+ * projection with w_b = n2_b / sum n2 and the window's mix_mask -> block
+ * levels of the state.  out_levels (host, n_blocks; may be NULL) receives
+ * them. */
 qcz_status qcz_select_levels(qcz_state *st, const float *dev_params, double beta, uint64_t mix_mask,
                              uint8_t *out_levels);
 

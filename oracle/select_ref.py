@@ -220,3 +220,21 @@ def project_levels(levels, w, beta, mask=0):
             if int(ids[b]) == best and int(L[b]) == btop:
                 L[b] -= 1
     return L
+
+
+def rule_level(beta):
+    """The loosest level whose delta is at most beta (0 = lossless)."""
+    r = 0
+    for lev in range(1, 6):
+        if DELTA[lev] <= beta:
+            r = lev
+    return r
+
+
+def select_from_network(levels, w, beta, mask=0):
+    """The selector's levels from the network's per-block choice: each raised
+    to at least the rule's level (one bound for every block, delta <= beta,
+    already meets the budget), then projected onto the coset budget."""
+    floor = rule_level(beta)
+    L = np.maximum(np.asarray(levels, dtype=np.uint8), np.uint8(floor))
+    return project_levels(L, w, beta, mask)

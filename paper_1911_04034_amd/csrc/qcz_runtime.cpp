@@ -724,6 +724,15 @@ void project(const double *w, uint64_t nb, double beta, uint64_t mask, uint8_t *
     }
 }
 
+// The loosest level whose delta is at most beta (0, lossless, for beta < 1e-5).
+uint8_t rule_level(double beta)
+{
+    uint8_t r = 0;
+    for (int lev = 1; lev < kLevels; ++lev)
+        if (kDelta[lev] <= beta) r = (uint8_t)lev;
+    return r;
+}
+
 // Block-index bits that the gates may flip: targets of U1 / X gates on
 // block-index qubits.  Weight only moves inside cosets of these bits.
 uint64_t mixing_mask(const qcz_state *s, const qcz_gate *g, size_t n)
@@ -752,6 +761,11 @@ qcz_status select_levels(qcz_state *s, const float *params, double beta, uint64_
     double tot = 0.0;
     for (double x : w) tot += x;
     for (double &x : w) x = tot > 0.0 ? x / tot : 0.0;
+    // Floor at the rule's level (the loosest level with delta <= beta): one
+    // bound for every block already meets the budget, so a tighter level
+    // only costs bytes; the projection may still lower blocks below it.
+    const uint8_t rule = rule_level(beta);
+    for (auto &l : L) l = std::max(l, rule);
     project(w.data(), s->nblocks, beta, mask, L.data());
     s->block_levels = L;
     HIPCHK(s, hipMemcpyAsync(s->blevel, s->block_levels.data(), s->nblocks, hipMemcpyHostToDevice, s->stream));

@@ -16,8 +16,8 @@ together):
   traced runs, full-batch cross-entropy with Adam on the device
   (qcz_mlp_train_step);
 * use: qcz_set_selector attaches the trained parameters; every `period`
-  gates the state re-selects its block levels (features -> network ->
-  budget projection).
+  gates the state re-selects its block levels (features -> network -> at
+  least the rule's level -> budget projection).
 
 Inputs are synthetic circuits from ``circuits``.
 """

@@ -147,7 +147,7 @@ def test_select_levels_projects_the_network_choice():
         _, lev = qcz.mlp_forward(params, X)
         w = n2.cpu().numpy()
         w = w / w.sum()
-        want = sr.project_levels(lev.cpu().numpy(), w, beta, mask)
+        want = sr.select_from_network(lev.cpu().numpy(), w, beta, mask)
         got = g.select_levels(params, beta, mask)
         assert np.array_equal(got, want)
         assert sr._weighted(got, w, mask) <= beta * sr.SLACK

@@ -76,3 +76,5 @@ def test_selector_gain_on_held_out_circuits():
             % (name, r.mean(), fr, s.mean(), fs, gains[name]))
         assert fs >= fr - 1e-12
     assert gains["biased14"] > 1.08
+    # floored at the rule's level, the selector does not spend more bytes than the rule
+    assert min(gains.values()) >= 0.99

@@ -141,6 +141,39 @@ def test_projection_hand_example():
     assert list(sr.project_levels([5, 1, 0], w, 1.0)) == [5, 1, 0]
 
 
+def test_rule_level_and_floor_hand_example():
+    # the loosest level with delta <= beta
+    assert [sr.rule_level(b) for b in (0.0, 1e-6, 1e-5, 5e-5, 1e-4, 1e-3, 0.05, 1.0)] == [0, 0, 1, 1, 2, 3, 4, 5]
+    w = np.array([0.5, 0.3, 0.2])
+    # tighter choices are raised to the rule's level (here level 2 for 1e-4) ...
+    assert list(sr.select_from_network([0, 1, 4], w, 1e-4)) == [2, 2, 2]
+    # ... then the projection: [3, 5, 3] costs 0.98e-3 + 0.01 * 0.1 + 0.01e-3 > 1e-3; block 1
+    # (largest W * delta) drops to 4, still over; block 0 drops to 2: 0.98e-4 + 1e-4 + 1e-5
+    w = np.array([0.98, 0.01, 0.01])
+    assert list(sr.select_from_network([0, 5, 3], w, 1e-3)) == [2, 4, 3]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_floored_selection_meets_budget_and_rule(seed):
+    """Random instances: the floored projection meets the coset budget, and
+    a block below the rule's level only appears in a coset the projection
+    had to lower (its loosest block is then at most the rule's level)."""
+    rng = np.random.default_rng(seed)
+    nb = 16
+    w = rng.dirichlet(np.full(nb, 0.3))
+    beta = float(rng.choice([1e-5, 1e-4, 1e-3]))
+    mask = int(rng.integers(0, nb))
+    lev = rng.integers(0, 6, size=nb)
+    got = sr.select_from_network(lev, w, beta, mask)
+    assert sr._weighted(got, w, mask) <= beta * sr.SLACK
+    rule = sr.rule_level(beta)
+    ids, order, W = sr.coset_weights(w, mask)
+    for b in range(nb):
+        if got[b] < rule:
+            top = max(int(got[x]) for x in range(nb) if ids[x] == ids[b])
+            assert top <= rule
+
+
 # --------------------------------------------------------------- features --
 def test_features_of_basis_state():
     n, bl = 12, 10
