@@ -33,6 +33,9 @@ def families(rng, C):
     x = rng.normal(size=C)
     x[5] = 2.0 ** -1070                       # subnormal: chunk stays lossless
     out["subnormal"] = x
+    x = rng.normal(size=C)
+    x[C - 3] = -(2.0 ** -1060)                # only the last wavefront of the chunk sees it
+    out["subnormal_late"] = x
     x = np.zeros(C)
     x[-1] = -3.5
     out["last_only"] = x
