@@ -572,7 +572,7 @@ __device__ __forceinline__ void emit_residuals(uint32_t *b, int base, uint32_t o
                                                uint32_t mask, uint32_t codes, bool sparse)
 {
     const int K = e.K;
-    uint32_t j = 0;
+    uint32_t j2 = 0;   // two bits per code of the values emitted so far (SPARSE: rank order)
     if (K < 64) {
         // a thread's fields are contiguous: assemble them in a 64-bit
         // accumulator and write whole words; only the first word (shared with
@@ -588,8 +588,8 @@ __device__ __forceinline__ void emit_residuals(uint32_t *b, int base, uint32_t o
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             const bool on = ((mask >> k) & 1u) != 0;
-            const uint32_t L = ((sparse ? (codes >> (2 * j)) : (codes >> (2 * k))) & 3u);
-            j += on ? 1u : 0u;
+            const uint32_t L = __builtin_amdgcn_ubfe(codes, sparse ? (j2 & 31u) : 2u * k, 2u);
+            j2 += on ? 2u : 0u;
             const uint32_t r = on ? __builtin_amdgcn_ubfe(rtab, 8u * L, 8u) : 0u;   // < 32 at every lossy level
             acc |= (uint64_t)__builtin_amdgcn_ubfe(e.th[k], (uint32_t)(32 - K), r) << nb;   // r bits from bit 32 - K
             nb += r;
@@ -608,8 +608,8 @@ __device__ __forceinline__ void emit_residuals(uint32_t *b, int base, uint32_t o
 #pragma unroll
     for (int k = 0; k < V; ++k) {
         const bool on = ((mask >> k) & 1u) != 0;
-        const uint32_t L = ((sparse ? (codes >> (2 * j)) : (codes >> (2 * k))) & 3u);
-        j += on ? 1u : 0u;
+        const uint32_t L = __builtin_amdgcn_ubfe(codes, sparse ? (j2 & 31u) : 2u * k, 2u);
+        j2 += on ? 2u : 0u;
         if (on) {
             const uint32_t r = 64u - 8u * L;
             or_bits64(b, base, o, e.th[k] & (~0u >> (8u * L)), e.tl[k]);
