@@ -246,6 +246,9 @@ def main():
     ap.add_argument("--chunk-waves", type=int, default=0, help="wavefronts per chunk in the fused kernel (2, 4, 8)")
     ap.add_argument("--no-timing", action="store_true", help="launch from graphs instead of timing each kernel")
     ap.add_argument("--selector", action="store_true", help="qaoa34: also run the learned per-block selector")
+    ap.add_argument("--cache", action="store_true",
+                    help="grover24/qft24: run with the compressed block cache (a separate figure: each gate is "
+                         "then a planning kernel plus two job launches, timed together)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -277,6 +280,8 @@ def main():
     passes = args.warmup + args.steps
     g_iters = args.grover_iters or (-(-total_iters // passes))
     flags = qcz.FLAG_GRAPH if args.no_timing else qcz.FLAG_TIMING
+    if args.cache:
+        flags |= qcz.FLAG_CACHE
     stream = torch.cuda.Stream()
 
     # --- inputs resident in HBM before timing -------------------------------
@@ -365,7 +370,7 @@ def main():
 
     roofline = None
     traffic = None
-    if args.workload == "grover24+qft24":
+    if args.workload == "grover24+qft24" and not args.cache:
         from paper_1911_04034_amd import profile_summary as ps
         t_bytes, t_hash = ps.read_traffic(os.path.join(ROOT, "profiles", "traffic_fused_kernel_grover24_qft24.txt"))
         if t_bytes is not None and t_hash == ps.kernel_hash():
@@ -376,7 +381,8 @@ def main():
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
-                    "kernel": "job_kernel<16, ARENA, ARENA, gate> (fused decode-gate-encode)",
+                    "kernel": ("block cache: plan + leader and follower job_kernel launches, per gate"
+                               if args.cache else "job_kernel<16, ARENA, ARENA, gate> (fused decode-gate-encode)"),
                     "avg_launch_us": round(avg_ms * 1e3, 3), "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
                     "launches": timed}
 
@@ -401,6 +407,12 @@ def main():
         "compactions": compactions,
         "workloads": out_extra,
     }
+    if args.cache:
+        ch = sum(x["cache_hits"] for x in stats)
+        line["config"]["block_cache"] = True
+        line["block_cache"] = {"gates": sum(x["cache_gates"] for x in stats), "chunks_copied": ch,
+                               "chunks_reencoded": sum(x["chunks_reencoded"] for x in stats),
+                               "on_at_end": [x["cache_on"] for x in stats]}
     print(json.dumps(line), flush=True)
 
 

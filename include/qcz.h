@@ -71,6 +71,15 @@ typedef enum {
                                streams are gone); the call returns QCZ_E_NOMEM and the state is invalid
                                (later qcz_apply_gates calls return QCZ_E_STATE).  Without the flag such a
                                gate fails with QCZ_E_NOMEM and the state stays at the previous gate. */
+#define QCZ_FLAG_CACHE 16u  /* compressed block cache (Sec. 3.4), per gate: jobs whose input streams and
+                               gate action equal another job's (byte-exact comparison after a hash match)
+                               copy that job's new streams instead of decompressing, applying and
+                               recompressing.  Results are identical with or without it.  Gates over
+                               per-block levels (QCZ_MODE_PERBLOCK) and gates run in job ranges do not use
+                               it; after 32 cached gates in a row without a hit it switches itself off.
+                               Needs a larger pool (qcz_pool_bytes_min); not with QCZ_FLAG_AUTOTUNE. */
+#define QCZ_FLAG_CACHE_COLLIDE 32u /* test hook: keep 3 bits of the cache keys, so that different
+                                      streams share keys and only the byte comparison separates them */
 
 typedef struct {
     uint32_t n_qubits;      /* 6 .. 40 */
@@ -140,6 +149,11 @@ typedef struct {
     uint32_t stops;             /* batches stopped on the device (budget or arena full) and rolled back */
     uint64_t range_gates;       /* gates run in job ranges because their new streams did not fit at once
                                    (not event-timed) */
+    uint64_t cache_gates;       /* QCZ_FLAG_CACHE: gates run through the block cache (event timing, if on,
+                                   covers the cache's planning kernel and both job launches) */
+    uint64_t cache_hits;        /* chunks whose new stream was copied from an identical job's */
+    uint32_t cache_on;          /* 1 while the block cache is in use */
+    uint32_t reserved;
 } qcz_stats_t;
 
 /* Bytes of device pool needed for a configuration (state |0..0> plus

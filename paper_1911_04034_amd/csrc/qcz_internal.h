@@ -55,7 +55,7 @@ struct GateLog {
     uint64_t wr;     // padded stream bytes written
     double wd;       // per-block levels: sum over re-encoded chunks of delta(level) * |chunk before truncation|^2
     double lost;     // per-block levels: squared norm removed by the truncation
-    uint64_t pad;
+    uint64_t hits;   // block cache: chunks whose new stream was copied from an identical job's
 };
 
 // Device-resident control block (first bytes of the pool).  The arena is
@@ -87,6 +87,7 @@ struct DevState {
 struct WgPart {
     uint64_t delta, reenc, rd, wr;
     double wd, lost;
+    uint64_t hits;
 };
 
 // Pointers of one state, passed by value to every kernel.
@@ -117,6 +118,22 @@ struct IOPtrs {
     double *partials;           // moments: [gridDim.x][4]
     double *cstats;             // chunk statistics: [chunk][kChunkStats]
     uint64_t *lsizes;           // per-level sizes: [block][kLevels] padded bytes (accumulated)
+    const uint32_t *role;       // block cache, per job of the launch: 0 leader, else 1 + key slot
+    const uint32_t *owner;      // block cache, per key slot: the leader job
+};
+
+// Compressed block cache of one gate launch (Sec. 3.4, on the GPU): every job
+// is keyed by a hash of its input streams and of the chunk-index bits the gate
+// reads.  The first job to insert a key leads and is computed; the others
+// follow: after an exact comparison of their streams with the leader's they
+// copy its output, or compute when the bytes differ.
+constexpr uint64_t kEmptyKey = ~0ull;
+struct CachePtrs {
+    uint64_t *keys;       // [tsize], kEmptyKey when free
+    uint32_t *owner;      // [tsize]
+    uint32_t *role;       // [jobs of the launch]
+    uint64_t tsize;       // power of two, at least twice the jobs of the launch
+    uint64_t key_mask;    // bits of the key kept (all but in tests that force collisions)
 };
 
 // Per-chunk statistics record (doubles): sum of squares, nonzero values, sum /
@@ -140,6 +157,12 @@ __host__ __device__ inline uint32_t alloc_bytes(uint32_t size) { return (size + 
 // Host launchers (qcz_kernels.hip).
 hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st, int wpg,
                        hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+// block cache: key the jobs (clears the key table first), then run the
+// leaders (list 1, no gate epilogue) and the followers (list 2, closes the
+// gate); both launches with the same grid, at most kMaxGrid / 2
+hipError_t launch_cache_plan(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, hipStream_t st);
+hipError_t launch_gate_list(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, int list, int grid,
+                            hipStream_t st);
 hipError_t launch_permute(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);
 hipError_t launch_rollback(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);
 hipError_t launch_encode_raw(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);

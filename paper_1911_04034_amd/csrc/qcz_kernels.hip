@@ -920,7 +920,21 @@ __device__ __forceinline__ void apply_gate_registers(const GateDesc &gd, const d
 // Two-wavefront groups run three workgroups per CU (three waves per SIMD):
 // the phases of a job wait on HBM, the arena atomic and barriers, and a third
 // workgroup keeps the SIMDs busy meanwhile; that caps a thread at 168 VGPRs.
-template <int V, int WPG, int SRC, int DST, bool GATE>
+// block cache (Sec. 3.4): chunk-index bits whose values the gate reads
+// (controls, and diagonal targets above the chunk); two jobs whose chunks
+// agree on them get the same operation
+__device__ __forceinline__ uint64_t op_mask(const GateDesc &gd, int cb)
+{
+    uint64_t m = gd.cm >> cb;
+    if (gd.q >= cb) m |= 1ull << (gd.q - cb);
+    if (gd.kind == K_DIAG2 && gd.q2 >= cb) m |= 1ull << (gd.q2 - cb);
+    return m;
+}
+
+// LIST 0: every job of the launch.  With the block cache, LIST 1 runs the
+// leader jobs and leaves the gate open; LIST 2 runs the followers (copy on an
+// exact match, compute otherwise) and closes the gate over both launches.
+template <int V, int WPG, int SRC, int DST, bool GATE, int LIST = 0>
 __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDesc gd, DevPtrs P, IOPtrs io)
 {
     constexpr int G = 64 * WPG;   // threads per chunk slot
@@ -936,6 +950,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     // the gate's parameters: read in the gate phase from LDS, so that the job
     // loop does not hold them in scalar registers
     __shared__ double sh_m[8];
+    __shared__ uint64_t sh_hit[2];   // block cache: chunks copied, per slot
 
     DevState *ds = P.ds;
     if (DST == DST_ARENA && ds->stop) return;
@@ -960,11 +975,17 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     // written) live in LDS: only thread 0 of a slot updates them
     if (DST == DST_ARENA && lt == 0)
         for (int k = 0; k < 4; ++k) sh_acc[4 * s + k] = 0;
+    if (LIST == 2 && lt == 0) sh_hit[s] = 0;
+    const uint64_t opm = LIST == 2 ? op_mask(gd, P.cb) : 0ull;
     double acc_wd = 0.0, acc_lost = 0.0;   // per-block fidelity ledger terms
     double mom_re = 0.0, mom_im = 0.0, mom_n2 = 0.0;
 
     const uint64_t jstop = job_stop(gd);
     for (uint64_t job = job_begin(gd) + blockIdx.x; job < jstop; job += gridDim.x) {
+        if (LIST != 0) {
+            const uint32_t r = io.role[job - job_begin(gd)];
+            if (LIST == 1 ? r != 0u : r == 0u) continue;   // (uniform over the workgroup)
+        }
         const uint64_t item0 = 2 * job, item1 = 2 * job + 1;
         const bool valid0 = item0 < gd.nitems, valid1 = item1 < gd.nitems;
         uint64_t cc0 = 0, cc1 = 0;
@@ -974,6 +995,83 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
         const uint64_t c = s ? cc1 : cc0;
         const bool valid = s ? valid1 : valid0;
         const bool act = s ? act1 : act0;
+
+        // 0. block cache follower: when both positions hold the same streams
+        // as the leader job's inputs (compared byte by byte) and the gate
+        // reads the same index bits, the leader's new streams are the result
+        if (LIST == 2) {
+            const uint64_t lj = io.owner[io.role[job - job_begin(gd)] - 1u];
+            const uint64_t li = 2 * lj + (uint64_t)s;
+            uint64_t lc = 0;
+            const bool lact = job_slot<SRC, GATE>(gd, unit_mask, io, P.cb, li, lc);
+            const bool lvalid = li < gd.nitems;
+            const uint64_t mine = valid ? P.table[c] : 0ull;
+            const uint64_t lold = lvalid ? P.undo[li] : 0ull;   // written by the leaders' launch
+            bool same = valid == lvalid && act == lact && (c & opm) == (lc & opm);
+            if (same && act)
+                same = (mine & 0xFFFFull) == (lold & 0xFFFFull) && entry_ok(mine, P.arena_words) &&
+                       entry_ok(lold, P.arena_words);
+            if (same && act) {
+                const uint32_t words = (uint32_t)(((mine & 0xFFFFull) + 3ull) >> 2);
+                const uint32_t *pa = P.arena + (mine >> 16), *pb = P.arena + (lold >> 16);
+                uint32_t diff = 0;
+                for (uint32_t w = (uint32_t)lt; w < words; w += G) diff |= pa[w] ^ pb[w];
+                same = diff == 0u;
+            }
+            const bool wbad = __any(!same);
+            if ((tid & 63) == 0) slS[tid >> 6] = wbad ? 1u : 0u;
+            lds_barrier();
+            uint32_t bad = 0;
+#pragma unroll
+            for (int i = 0; i < WGS / 64; ++i) bad |= slS[i];
+            if (bad == 0u) {
+                const uint64_t lnew = act ? P.table[lc] : 0ull;
+                const uint32_t nsize = (uint32_t)(lnew & 0xFFFFull);
+                if (lt == 0) {
+                    uint64_t my_off = 0;
+                    int ok = 0;
+                    if (act) {
+                        const int stripe = (int)(blockIdx.x % (uint32_t)ds_nstripes);
+                        my_off = atomicAdd((unsigned long long *)&ds->stripe[stripe][0],
+                                           (unsigned long long)alloc_bytes(nsize));
+                        ok = (my_off + alloc_bytes(nsize) <= ds_ssize) ? 1 : 0;
+                        my_off += ds_base + (uint64_t)stripe * ds_ssize;
+                        if (!ok) atomicExch(&ds->fail, 1);
+                    }
+                    sh_off[s] = my_off;
+                    sh_ok[s] = ok;
+                }
+                lds_barrier();
+                const int ok = sh_ok[s];
+                if (ok) {
+                    const uint32_t words = (nsize + 3u) >> 2;
+                    const uint64_t srcw = lnew >> 16, dstw = sh_off[s] >> 2;
+                    if ((srcw & 3ull) == 0) {   // whole 16-byte units, zero past the leader's stream
+                        const u32x4 *s4 = reinterpret_cast<const u32x4 *>(P.arena + srcw);
+                        u32x4 *d4 = reinterpret_cast<u32x4 *>(P.arena + dstw);
+                        for (uint32_t w = lt; w < (words + 3u) >> 2; w += G) d4[w] = s4[w];
+                    } else {
+                        for (uint32_t w = lt; w < ((words + 3u) & ~3u); w += G)
+                            P.arena[dstw + w] = w < words ? P.arena[srcw + w] : 0u;
+                    }
+                }
+                if (lt == 0 && valid) {
+                    P.undo[item] = mine;
+                    if (ok) {
+                        P.table[c] = ((sh_off[s] >> 2) << 16) | (uint64_t)nsize;
+                        const uint64_t old_pad = ((mine & 0xFFFFull) + 3ull) & ~3ull;
+                        const uint64_t new_pad = ((uint64_t)nsize + 3ull) & ~3ull;
+                        sh_acc[4 * s] += new_pad - old_pad;
+                        sh_acc[4 * s + 1] += 1;
+                        sh_acc[4 * s + 2] += old_pad;
+                        sh_acc[4 * s + 3] += new_pad;
+                        sh_hit[s] += 1;
+                    }
+                }
+                lds_barrier();
+                continue;
+            }
+        }
 
         // 1. fetch
         uint64_t old_entry = 0;
@@ -1263,6 +1361,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     }
 
     if (DST == DST_ARENA) {
+        constexpr int NRED = LIST == 2 ? 6 : 5;   // per-wavefront sums in the closing reduction
         // per-workgroup totals, then the last workgroup closes the gate
         if (gd.per_block) {
             double a = acc_wd, l = acc_lost;
@@ -1283,16 +1382,22 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             wp.lost = 0.0;
             if (gd.per_block)
                 for (int w = 0; w < WGS / 64; ++w) { wp.wd += sh_mom[w][0]; wp.lost += sh_mom[w][1]; }
-            P.wgp[blockIdx.x] = wp;
-            __threadfence();
-            const uint32_t prev = atomicAdd(&ds->done, 1u);
-            sh_ok[0] = (prev == gridDim.x - 1) ? 1 : 0;
+            wp.hits = LIST == 2 ? sh_hit[0] + sh_hit[1] : 0;
+            if (LIST == 1) {
+                P.wgp[kMaxGrid / 2 + blockIdx.x] = wp;   // summed by the followers' launch
+            } else {
+                P.wgp[blockIdx.x] = wp;
+                __threadfence();
+                const uint32_t prev = atomicAdd(&ds->done, 1u);
+                sh_ok[0] = (prev == gridDim.x - 1) ? 1 : 0;
+            }
         }
+        if (LIST == 1) return;
         lds_barrier();
         if (sh_ok[0]) {
             // the last workgroup: sum the partials of all workgroups
             __threadfence();
-            uint64_t d = 0, r = 0, rd = 0, wr = 0, used = 0;
+            uint64_t d = 0, r = 0, rd = 0, wr = 0, used = 0, h = 0;
             double fw = 0.0, fl = 0.0;
             for (uint32_t g = (uint32_t)tid; g < gridDim.x; g += WGS) {
                 const WgPart wp = P.wgp[g];
@@ -1302,6 +1407,14 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                 wr += wp.wr;
                 fw += wp.wd;
                 fl += wp.lost;
+                if (LIST == 2) {   // the leaders' launch ran with the same grid
+                    const WgPart wq = P.wgp[kMaxGrid / 2 + g];
+                    d += wq.delta;
+                    r += wq.reenc;
+                    rd += wq.rd;
+                    wr += wq.wr;
+                    h += wp.hits;
+                }
             }
             if (tid < kStripes) used = atomicAdd((unsigned long long *)&ds->stripe[tid][0], 0ull);
             for (int off = 32; off >= 1; off >>= 1) {
@@ -1312,27 +1425,30 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                 used += __shfl_down(used, off, 64);
                 fw += __shfl_down(fw, off, 64);
                 fl += __shfl_down(fl, off, 64);
+                if (LIST == 2) h += __shfl_down(h, off, 64);
             }
             if ((tid & 63) == 0) { sh_mom[tid >> 6][2] = fw; sh_mom[tid >> 6][3] = fl; }
             uint64_t *red = reinterpret_cast<uint64_t *>(buf[0]);
             if ((tid & 63) == 0) {
-                red[5 * (tid >> 6)] = d;
-                red[5 * (tid >> 6) + 1] = r;
-                red[5 * (tid >> 6) + 2] = rd;
-                red[5 * (tid >> 6) + 3] = wr;
-                red[5 * (tid >> 6) + 4] = used;
+                red[NRED * (tid >> 6)] = d;
+                red[NRED * (tid >> 6) + 1] = r;
+                red[NRED * (tid >> 6) + 2] = rd;
+                red[NRED * (tid >> 6) + 3] = wr;
+                red[NRED * (tid >> 6) + 4] = used;
+                if (LIST == 2) red[NRED * (tid >> 6) + 5] = h;
             }
         }
         lds_barrier();
         if (tid == 0 && sh_ok[0]) {
             const uint64_t *red = reinterpret_cast<const uint64_t *>(buf[0]);
-            uint64_t d = 0, r = 0, rd = 0, wr = 0, used = 0;
+            uint64_t d = 0, r = 0, rd = 0, wr = 0, used = 0, h = 0;
             for (int w = 0; w < WGS / 64; ++w) {
-                d += red[5 * w];
-                r += red[5 * w + 1];
-                rd += red[5 * w + 2];
-                wr += red[5 * w + 3];
-                used += red[5 * w + 4];
+                d += red[NRED * w];
+                r += red[NRED * w + 1];
+                rd += red[NRED * w + 2];
+                wr += red[NRED * w + 3];
+                used += red[NRED * w + 4];
+                if (LIST == 2) h += red[NRED * w + 5];
             }
             const uint64_t live = ds->live + d;
             ds->live = live;
@@ -1345,7 +1461,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             lg.wd = 0.0;
             lg.lost = 0.0;
             for (int w = 0; w < WGS / 64; ++w) { lg.wd += sh_mom[w][2]; lg.lost += sh_mom[w][3]; }
-            lg.pad = 0;
+            lg.hits = h;
             ds->log[gd.seq] = lg;
             const int fail = atomicExch(&ds->fail, 0);
             const int corrupt = atomicExch(&ds->corrupt, 0);
@@ -1395,7 +1511,7 @@ __global__ __launch_bounds__(kWG) void permute_kernel(GateDesc gd, DevPtrs P)
         lg.reenc = 0;
         lg.rd = lg.wr = 0;
         lg.wd = lg.lost = 0.0;
-        lg.pad = 0;
+        lg.hits = 0;
         ds->log[gd.seq] = lg;
         atomicExch(&ds->done, 0u);
     }
@@ -1425,6 +1541,79 @@ __global__ __launch_bounds__(kWG) void fill_table_kernel(uint64_t *table, uint64
 {
     const uint64_t stride = (uint64_t)gridDim.x * kWG;
     for (uint64_t c = (uint64_t)blockIdx.x * kWG + threadIdx.x; c < n; c += stride) table[c] = c ? erest : e0;
+}
+
+// the finalizer of SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): a
+// bijective 64-bit mix
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Block cache (Sec. 3.4) of one gate launch: one wavefront per job hashes the
+// job's input streams (word values with their positions, and the size) and
+// the chunk-index bits the gate reads, then inserts the key into an
+// open-addressing table.  The job that inserts a key leads (role 0); a job
+// that finds its key follows the slot's owner (role 1 + slot).  Jobs with no
+// stream to re-encode, or with an entry outside the arena, lead.
+__global__ __launch_bounds__(kWG) void cache_plan_kernel(GateDesc gd, DevPtrs P, CachePtrs cp)
+{
+    uint32_t unit_mask = 0;
+    for (int i = 0; i < 4; ++i) unit_mask |= unit_phase(gd.m[2 * i], gd.m[2 * i + 1]) ? (1u << i) : 0u;
+    const IOPtrs io = {};
+    const uint64_t opm = op_mask(gd, P.cb);
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t nw = (uint64_t)gridDim.x * (kWG / 64);
+    const uint64_t j0 = job_begin(gd), j1 = job_stop(gd);
+    for (uint64_t job = j0 + (uint64_t)blockIdx.x * (kWG / 64) + (threadIdx.x >> 6); job < j1; job += nw) {
+        uint64_t key = 0x243F6A8885A308D3ull;
+        bool work = false, plain = false;
+        for (int sl = 0; sl < 2; ++sl) {
+            const uint64_t item = 2 * job + (uint64_t)sl;
+            uint64_t c = 0;
+            const bool act = job_slot<SRC_ARENA, true>(gd, unit_mask, io, P.cb, item, c);
+            const bool valid = item < gd.nitems;
+            uint64_t h = 0;
+            if (act) {
+                const uint64_t e = P.table[c];
+                if (entry_ok(e, P.arena_words)) {
+                    const uint32_t size = (uint32_t)(e & 0xFFFFull), words = (size + 3u) >> 2;
+                    const uint32_t *w = P.arena + (e >> 16);
+                    for (uint32_t i = (uint32_t)lane; i < words; i += 64) h += mix64(((uint64_t)i << 32) | w[i]);
+                    for (int o = 32; o >= 1; o >>= 1) h += __shfl_xor(h, o, 64);
+                    h = mix64(h ^ ((uint64_t)size << 40));
+                    work = true;
+                } else {
+                    plain = true;
+                }
+            }
+            const uint64_t tag = (c & opm) ^ ((uint64_t)(valid ? 1 : 0) << 62) ^ ((uint64_t)(act ? 1 : 0) << 63);
+            key = mix64(key ^ h) + mix64(tag + (uint64_t)sl);
+        }
+        if (lane != 0) continue;
+        uint32_t role = 0;
+        if (work && !plain) {
+            key &= cp.key_mask;
+            if (key == kEmptyKey) key ^= 1ull;
+            uint64_t slot = key & (cp.tsize - 1);
+            for (uint64_t probe = 0; probe < cp.tsize; ++probe) {
+                const uint64_t prev = atomicCAS((unsigned long long *)&cp.keys[slot], (unsigned long long)kEmptyKey,
+                                                (unsigned long long)key);
+                if (prev == kEmptyKey) {
+                    cp.owner[slot] = (uint32_t)job;
+                    break;
+                }
+                if (prev == key) {
+                    role = 1u + (uint32_t)slot;
+                    break;
+                }
+                slot = (slot + 1) & (cp.tsize - 1);
+            }
+        }
+        cp.role[job - j0] = role;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1559,6 +1748,45 @@ hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream
 {
     IOPtrs io = {};
     return launch_job<SRC_ARENA, DST_ARENA, true>(gd, P, io, grid, st, wpg, t0, t1);
+}
+
+template <int V>
+static void launch_list_v(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int list, int grid, hipStream_t st)
+{
+    if (list == 1)
+        hipLaunchKernelGGL((job_kernel<V, 2, SRC_ARENA, DST_ARENA, true, 1>), dim3(grid), dim3(256), 0, st, gd, P, io);
+    else
+        hipLaunchKernelGGL((job_kernel<V, 2, SRC_ARENA, DST_ARENA, true, 2>), dim3(grid), dim3(256), 0, st, gd, P, io);
+}
+
+hipError_t launch_gate_list(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, int list, int grid,
+                            hipStream_t st)
+{
+    if ((list != 1 && list != 2) || grid < 1 || grid > kMaxGrid / 2 || P.C % 128) return hipErrorInvalidValue;
+    IOPtrs io = {};
+    io.role = cp.role;
+    io.owner = cp.owner;
+    switch (P.C / 128) {
+    case 1: launch_list_v<1>(gd, P, io, list, grid, st); break;
+    case 2: launch_list_v<2>(gd, P, io, list, grid, st); break;
+    case 4: launch_list_v<4>(gd, P, io, list, grid, st); break;
+    case 8: launch_list_v<8>(gd, P, io, list, grid, st); break;
+    case 16: launch_list_v<16>(gd, P, io, list, grid, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cache_plan(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, hipStream_t st)
+{
+    const uint64_t jobs = job_stop(gd) - job_begin(gd);
+    if (cp.tsize < 2 * jobs || (cp.tsize & (cp.tsize - 1))) return hipErrorInvalidValue;
+    const uint64_t fb = std::min<uint64_t>((cp.tsize + kWG - 1) / kWG, 65535);
+    hipLaunchKernelGGL(fill_table_kernel, dim3((unsigned)fb), dim3(kWG), 0, st, cp.keys, cp.tsize, kEmptyKey,
+                       kEmptyKey);
+    const uint64_t pb = std::max<uint64_t>(1, std::min<uint64_t>((jobs + kWG / 64 - 1) / (kWG / 64), 65535));
+    hipLaunchKernelGGL(cache_plan_kernel, dim3((unsigned)pb), dim3(kWG), 0, st, gd, P, cp);
+    return hipGetLastError();
 }
 
 hipError_t launch_permute(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st)

@@ -34,6 +34,7 @@ constexpr int kScratchChunks = 64;
 constexpr int kMomGrid = 2048;
 constexpr int kMaxGraphs = 8;
 constexpr uint64_t kScanItems = 1024;
+constexpr uint32_t kCacheIdleGates = 32;   // cached gates in a row without a hit that switch the cache off
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -43,8 +44,9 @@ struct GraphEntry {
 };
 
 struct Layout {
-    size_t ds, table, undo, bsums, blevel, partials, wgp, scratch, cstats, feat, fn2, fsel, arena0, arena1,
-        arena_bytes, end;
+    size_t ds, table, undo, bsums, blevel, partials, wgp, scratch, cstats, feat, fn2, fsel, ckeys, cowner, crole,
+        arena0, arena1, arena_bytes, end;
+    uint64_t ctsize;   // block cache key slots (0: no cache)
 };
 
 // chunk statistics records held at once (blocks are processed in batches)
@@ -52,7 +54,7 @@ constexpr uint64_t kStatChunks = 65536;
 
 int chunk_log2_for(int bl) { return bl < 10 ? bl : 10; }
 
-Layout layout_for(int n, int bl, size_t pool_bytes)
+Layout layout_for(int n, int bl, size_t pool_bytes, bool cache)
 {
     const int cb = chunk_log2_for(bl);
     const int C = 2 << cb;
@@ -73,6 +75,11 @@ Layout layout_for(int n, int bl, size_t pool_bytes)
     L.feat = o; o = align256(o + 4 * kNIn * (size_t)nblocks);
     L.fn2 = o; o = align256(o + 8 * (size_t)nblocks);
     L.fsel = o; o = align256(o + (size_t)nblocks);
+    // block cache: key slots for twice the jobs of a gate (at most nchunks / 2 jobs)
+    L.ctsize = cache ? std::max<uint64_t>(64, nchunks) : 0;
+    L.ckeys = o; o = align256(o + 8 * (size_t)L.ctsize);
+    L.cowner = o; o = align256(o + 4 * (size_t)L.ctsize);
+    L.crole = o; o = align256(o + 4 * (size_t)(cache ? std::max<uint64_t>(1, nchunks / 2) : 0));
     L.end = o;
     size_t rest = pool_bytes > o ? pool_bytes - o : 0;
     L.arena_bytes = (rest / 2) & ~(size_t)255;
@@ -131,6 +138,11 @@ struct qcz_state {
     bool tuning = false;
     std::vector<hipEvent_t> events;   // QCZ_FLAG_TIMING: start/stop per gate of a batch
     std::vector<int> timed;           // per gate of the batch: 1 if its fused kernel was timed
+    // compressed block cache (QCZ_FLAG_CACHE)
+    bool cache_on = false;
+    uint64_t cache_key_mask = ~0ull;
+    uint32_t cache_idle = 0;          // consecutive cached gates without a hit
+    std::vector<uint8_t> cached;      // per gate of the batch: 1 if it ran through the cache
 };
 
 namespace {
@@ -352,9 +364,39 @@ size_t gates_that_fit(const qcz_state *s, const std::vector<GateDesc> &descs)
     return k;
 }
 
+// gates that run through the block cache: fused jobs over a whole gate at a
+// global level (per-block levels keep their own ledger per chunk)
+bool cache_gate(const qcz_state *s, const GateDesc &d)
+{
+    return s->cache_on && d.job_type != J_PERMUTE && !d.per_block && d.job_end == 0 && d.njobs >= 2;
+}
+
 qcz_status launch_one(qcz_state *s, const GateDesc &d, bool timing)
 {
     DevPtrs P = ptrs(s);
+    if (cache_gate(s, d)) {
+        // plan, leaders, followers: one gate over three launches, timed together
+        CachePtrs cp{};
+        cp.keys = (uint64_t *)(s->pool + s->lay.ckeys);
+        cp.owner = (uint32_t *)(s->pool + s->lay.cowner);
+        cp.role = (uint32_t *)(s->pool + s->lay.crole);
+        cp.tsize = 64;
+        while (cp.tsize < 2 * d.njobs) cp.tsize *= 2;
+        if (cp.tsize > s->lay.ctsize) return fail(s, QCZ_E_STATE, "block cache table too small");
+        cp.key_mask = s->cache_key_mask;
+        const int grid = std::min(grid_for(s, d), kMaxGrid / 2);
+        if (timing) HIPCHK(s, hipEventRecord(s->events[2 * d.seq], s->stream));
+        hipError_t e = launch_cache_plan(d, P, cp, s->stream);
+        if (e == hipSuccess) e = launch_gate_list(d, P, cp, 1, grid, s->stream);
+        if (e == hipSuccess) e = launch_gate_list(d, P, cp, 2, grid, s->stream);
+        if (e != hipSuccess) return fail(s, QCZ_E_DEVICE, std::string("cached gate launch: ") + hipGetErrorString(e));
+        if (timing) {
+            HIPCHK(s, hipEventRecord(s->events[2 * d.seq + 1], s->stream));
+            s->timed[(size_t)d.seq] = 1;
+        }
+        if ((size_t)d.seq < s->cached.size()) s->cached[(size_t)d.seq] = 1;
+        return QCZ_OK;
+    }
     const int grid = grid_for(s, d);
     const bool t = timing && d.job_type != J_PERMUTE;
     hipEvent_t t0 = t ? s->events[2 * d.seq] : nullptr, t1 = t ? s->events[2 * d.seq + 1] : nullptr;
@@ -376,6 +418,7 @@ qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
         }
         s->timed.assign(descs.size(), 0);
     }
+    s->cached.assign(descs.size(), 0);
     if (timing || !(s->cfg.flags & QCZ_FLAG_GRAPH) || s->stream == nullptr) {
         for (const auto &d : descs) {
             qcz_status st = launch_one(s, d, timing);
@@ -383,9 +426,10 @@ qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
         }
         return QCZ_OK;
     }
-    std::vector<uint8_t> key(descs.size() * sizeof(GateDesc) + sizeof(DevPtrs));
+    std::vector<uint8_t> key(descs.size() * sizeof(GateDesc) + sizeof(DevPtrs) + 1);
     DevPtrs P = ptrs(s);
     memcpy(key.data(), &P, sizeof(P));
+    key.back() = s->cache_on ? 1 : 0;   // the launches of a cached gate differ
     if (!descs.empty()) memcpy(key.data() + sizeof(P), descs.data(), descs.size() * sizeof(GateDesc));
     for (auto &g : s->graphs) {
         if (g.key == key) {
@@ -434,6 +478,13 @@ void commit_gate(qcz_state *s, const GateLog &lg, const GateDesc &d, int k)
         S.bytes_read += lg.rd;
         S.bytes_written += lg.wr;
         S.table_bytes += 24 * lg.reenc;
+        if (k < (int)s->cached.size() && s->cached[(size_t)k]) {
+            // Sec. 3.4: the cache is switched off when it keeps missing
+            S.cache_gates += 1;
+            S.cache_hits += lg.hits;
+            s->cache_idle = lg.hits ? 0 : s->cache_idle + 1;
+            if (s->cache_idle >= kCacheIdleGates) s->cache_on = false;
+        }
         if (k < (int)s->timed.size() && s->timed[(size_t)k]) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, s->events[2 * (size_t)k], s->events[2 * (size_t)k + 1]) == hipSuccess) {
@@ -641,6 +692,7 @@ qcz_status apply_in_ranges(qcz_state *s, const GateDesc &d)
     tot.live = s->live;
     tot.bump = s->bump;
     s->stats.range_gates += 1;
+    s->cached.clear();   // job ranges never run through the block cache
     commit_gate(s, tot, d, (int)s->timed.size());
     return QCZ_OK;
 }
@@ -791,7 +843,7 @@ size_t qcz_pool_bytes_min(const qcz_config *cfg)
 {
     if (!cfg || cfg->n_qubits < 6 || cfg->n_qubits > 40 || cfg->block_log2 < 6 || cfg->block_log2 > cfg->n_qubits)
         return 0;
-    Layout L = layout_for((int)cfg->n_qubits, (int)cfg->block_log2, 0);
+    Layout L = layout_for((int)cfg->n_qubits, (int)cfg->block_log2, 0, (cfg->flags & QCZ_FLAG_CACHE) != 0);
     const int cb = chunk_log2_for((int)cfg->block_log2);
     const uint64_t nchunks = 1ull << (cfg->n_qubits - cb);
     // two arenas, each holding the initial streams with room to spare
@@ -810,6 +862,7 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
     if (cfg->chunk_waves != 0 && cfg->chunk_waves != 2 && cfg->chunk_waves != 4 && cfg->chunk_waves != 8)
         return QCZ_E_INVAL;
     if (((uintptr_t)dev_pool & 255) != 0) return QCZ_E_INVAL;
+    if ((cfg->flags & QCZ_FLAG_CACHE) && (cfg->flags & QCZ_FLAG_AUTOTUNE)) return QCZ_E_INVAL;
     if (pool_bytes < qcz_pool_bytes_min(cfg)) return QCZ_E_NOMEM;
 
     qcz_state *s = new qcz_state();
@@ -822,7 +875,7 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
     s->nblocks = 1ull << (s->n - s->bl);
     s->pool = (uint8_t *)dev_pool;
     s->pool_bytes = pool_bytes;
-    s->lay = layout_for(s->n, s->bl, pool_bytes);
+    s->lay = layout_for(s->n, s->bl, pool_bytes, (cfg->flags & QCZ_FLAG_CACHE) != 0);
     s->ds = (DevState *)(s->pool + s->lay.ds);
     s->table = (uint64_t *)(s->pool + s->lay.table);
     s->undo = (uint64_t *)(s->pool + s->lay.undo);
@@ -837,6 +890,8 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
     s->chunk_waves = cfg->chunk_waves ? (int)cfg->chunk_waves : 2;
     while (s->chunk_waves > 2 && s->C < 64 * s->chunk_waves) s->chunk_waves /= 2;   // at least one value per thread
     s->level = cfg->mode == QCZ_MODE_FIXED ? cfg->level : 0;
+    s->cache_on = (cfg->flags & QCZ_FLAG_CACHE) && cfg->mode != QCZ_MODE_PERBLOCK;
+    s->cache_key_mask = (cfg->flags & QCZ_FLAG_CACHE_COLLIDE) ? 7ull : ~0ull;
 
     if (hip_stream) {
         s->stream = (hipStream_t)hip_stream;
@@ -1065,6 +1120,7 @@ qcz_status qcz_get_stats(qcz_state *s, qcz_stats_t *out)
     out->chunk_waves = (uint32_t)s->chunk_waves;
     out->grid = (uint32_t)s->grid_max;
     out->tuning = s->tuning ? 1u : 0u;
+    out->cache_on = s->cache_on ? 1u : 0u;
     return QCZ_OK;
 }
 

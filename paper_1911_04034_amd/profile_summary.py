@@ -21,7 +21,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "csrc", "qcz_kernels.hip")
-FUSED = "job_kernel<16, 2, 0, 0, true>"
+FUSED = "job_kernel<16, 2, 0, 0, true, 0>"
 
 
 def kernel_hash() -> str:

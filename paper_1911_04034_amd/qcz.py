@@ -20,6 +20,8 @@ FLAG_GRAPH = 1
 FLAG_TIMING = 2
 FLAG_AUTOTUNE = 4
 FLAG_RANGES = 8
+FLAG_CACHE = 16
+FLAG_CACHE_COLLIDE = 32
 STATUS = {0: "QCZ_OK", -1: "QCZ_E_INVAL", -2: "QCZ_E_NOMEM", -3: "QCZ_E_DEVICE", -4: "QCZ_E_FORMAT",
           -5: "QCZ_E_STATE"}
 
@@ -54,7 +56,8 @@ class Stats(ctypes.Structure):
                 ("table_bytes", ctypes.c_uint64), ("timed_launches", ctypes.c_uint64),
                 ("gate_kernel_ms", ctypes.c_double), ("chunk_waves", ctypes.c_uint32), ("grid", ctypes.c_uint32),
                 ("tuning", ctypes.c_uint32), ("stops", ctypes.c_uint32),
-                ("range_gates", ctypes.c_uint64)]
+                ("range_gates", ctypes.c_uint64), ("cache_gates", ctypes.c_uint64),
+                ("cache_hits", ctypes.c_uint64), ("cache_on", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 EXPORTED = [

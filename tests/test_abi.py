@@ -47,3 +47,20 @@ def test_host_only_calls():
     assert L.qcz_pool_bytes_min(ctypes.byref(cfg)) > 0
     bad = qcz.Config(3, 8, 0, 0, 0, 0, 0, 0, 0)
     assert L.qcz_pool_bytes_min(ctypes.byref(bad)) == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libqcz.so not built")
+def test_block_cache_pool_and_stats_layout():
+    """The block cache's key table (12 bytes per chunk) and role array (4
+    bytes per job) come out of the pool; the stats record ends with the
+    cache counters as the header lays them out."""
+    from paper_1911_04034_amd import qcz
+    L = qcz.load()
+    n, bl = 20, 12
+    plain = L.qcz_pool_bytes_min(ctypes.byref(qcz.Config(n, bl, 1, 1, 0, 0, 0, 0, 0)))
+    cached = L.qcz_pool_bytes_min(ctypes.byref(qcz.Config(n, bl, 1, 1, 0, qcz.FLAG_CACHE, 0, 0, 0)))
+    nchunks = 1 << (n - 10)
+    assert cached - plain >= 12 * nchunks + 4 * (nchunks // 2)
+    assert cached - plain <= 12 * nchunks + 4 * (nchunks // 2) + 3 * 256
+    assert qcz.Stats.cache_on.offset == qcz.Stats.cache_hits.offset + 8
+    assert ctypes.sizeof(qcz.Stats) == qcz.Stats.reserved.offset + 4

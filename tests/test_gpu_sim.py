@@ -205,15 +205,18 @@ def test_autotune_keeps_bytes_and_settles():
     assert_same_chunks(g, o, "after autotuning")
 
 
-def test_sampled_gates_full_size_grover24():
+@pytest.mark.parametrize("cache", [False, True])
+def test_sampled_gates_full_size_grover24(cache):
     """At the benchmark shape (24 qubits, 2^16-amplitude blocks) compare
     sampled gates: the oracle re-runs one unit of the blockwise loop on the
-    GPU's exported input chunks and must produce the GPU's output bytes."""
+    GPU's exported input chunks and must produce the GPU's output bytes.
+    With the block cache most chunks are copies of a leader job's output."""
     n, bl = 24, 16
     from paper_1911_04034_amd import qcz
     w = cc.grover_marked(n, 2)
     it = cc.grover_iteration(n, w)
-    g = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=1, pool_bytes=2 << 30, batch=128)
+    g = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=1, pool_bytes=2 << 30, batch=128,
+                  flags=qcz.FLAG_CACHE if cache else 0)
     g.apply(cc.grover_prefix(n))
     g.apply(it)
     rng = np.random.default_rng(5)
@@ -242,6 +245,9 @@ def test_sampled_gates_full_size_grover24():
                 assert g.export_chunk(c) == r0 and g.export_chunk(c1) == r1
     theta = math.asin(2.0 ** (-n / 2))
     assert abs(abs(g.read([w])[0]) - abs(math.sin(5 * theta))) < 1e-4
+    if cache:
+        st = g.stats()
+        assert st["cache_on"] == 1 and st["cache_hits"] > st["chunks_reencoded"] // 2
 
 
 def test_sampled_gates_full_size_qft24():
