@@ -4,6 +4,7 @@ Usage:
   python -m paper_1911_04034_amd.profile_summary stats  <kernel_stats.csv> <command> > profiles/X.txt
   python -m paper_1911_04034_amd.profile_summary traffic <fetch_dir> <write_dir> <copy_fetch_dir> \
          <copy_write_dir> <copy_bytes> <last_n_dispatches> <command> > profiles/Y.txt
+  python -m paper_1911_04034_amd.profile_summary counters <command> <name>=<dir> [<name>=<dir> ...] > profiles/Z.txt
 
 The traffic summary scales the per-dispatch FETCH_SIZE / WRITE_SIZE of the
 fused kernel by the ratio (known bytes / counter) that the same counters read
@@ -95,6 +96,35 @@ def traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, last, comm
     print("traffic_bytes_per_dispatch: %.1f" % (f * kf + w * kw))
 
 
+SQ = ["SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_VALU", "SQ_WAIT_ANY",
+      "SQ_WAVES", "SQ_WAVE_CYCLES"]
+
+
+def counters(command, *runs, waves_per_simd=3):
+    """Mean per dispatch of the SQ counters of the fused kernel, one block per
+    `name=dir` run, with the ratios derived from them."""
+    print("# rocprofv3 SQ counters of the fused gate kernel %s (mean per dispatch)" % FUSED)
+    print("# command: %s" % command)
+    print("# %d waves per SIMD: VALU busy per SIMD = %d * SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES" % (waves_per_simd,
+                                                                                               waves_per_simd))
+    print("# kernel source sha256[:16]: %s" % kernel_hash())
+    for run in runs:
+        name, d = run.split("=", 1)
+        v = {}
+        n = 0
+        for c in SQ:
+            v[c], n = per_dispatch(d, c, FUSED)
+        print()
+        print("workload %s (%d dispatches)" % (name, n))
+        for c in SQ:
+            print("  %-22s %.4g" % (c, v[c]))
+        print("  %-22s %.3f" % ("VALU busy per SIMD", waves_per_simd * v["SQ_ACTIVE_INST_VALU"] / v["SQ_WAVE_CYCLES"]))
+        print("  %-22s %.3f" % ("waiting / wave cycles", v["SQ_WAIT_ANY"] / v["SQ_WAVE_CYCLES"]))
+        print("  %-22s %.0f" % ("VALU instructions/wave", v["SQ_INSTS_VALU"] / v["SQ_WAVES"]))
+        print("  %-22s %.3f" % ("SALU / VALU", v["SQ_INSTS_SALU"] / v["SQ_INSTS_VALU"]))
+        print("  %-22s %.3f" % ("LDS / VALU", v["SQ_INSTS_LDS"] / v["SQ_INSTS_VALU"]))
+
+
 def read_traffic(path):
     """(bytes per dispatch, kernel hash) from a traffic summary, or (None, None)."""
     if not os.path.exists(path):
@@ -115,5 +145,7 @@ if __name__ == "__main__":
         stats(sys.argv[2], sys.argv[3], *(sys.argv[4:6]))
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:9])
+    elif sys.argv[1] == "counters":
+        counters(sys.argv[2], *sys.argv[3:])
     else:
         raise SystemExit(__doc__)
