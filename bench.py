@@ -381,7 +381,7 @@ def main():
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
-                    "kernel": ("block cache: plan + leader and follower job_kernel launches, per gate"
+                    "kernel": ("block cache: plan + leader job launch + follower copy kernel + remaining followers, per gate"
                                if args.cache else "job_kernel<16, ARENA, ARENA, gate> (fused decode-gate-encode)"),
                     "avg_launch_us": round(avg_ms * 1e3, 3), "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
                     "launches": timed}

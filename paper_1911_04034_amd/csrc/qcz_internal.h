@@ -120,6 +120,7 @@ struct IOPtrs {
     uint64_t *lsizes;           // per-level sizes: [block][kLevels] padded bytes (accumulated)
     const uint32_t *role;       // block cache, per job of the launch: 0 leader, else 1 + key slot
     const uint32_t *owner;      // block cache, per key slot: the leader job
+    const WgPart *cparts;       // block cache: per-workgroup sums of the followers' copy kernel
 };
 
 // Compressed block cache of one gate launch (Sec. 3.4, on the GPU): every job
@@ -128,10 +129,13 @@ struct IOPtrs {
 // follow: after an exact comparison of their streams with the leader's they
 // copy its output, or compute when the bytes differ.
 constexpr uint64_t kEmptyKey = ~0ull;
+constexpr uint32_t kRoleDone = ~0u;   // a follower copied by the copy kernel
+constexpr int kCopyGrid = 1024;       // workgroups of the followers' copy kernel
 struct CachePtrs {
     uint64_t *keys;       // [tsize], kEmptyKey when free
     uint32_t *owner;      // [tsize]
     uint32_t *role;       // [jobs of the launch]
+    WgPart *parts;        // [kCopyGrid] per-workgroup sums of the copy kernel
     uint64_t tsize;       // power of two, at least twice the jobs of the launch
     uint64_t key_mask;    // bits of the key kept (all but in tests that force collisions)
 };
@@ -157,10 +161,12 @@ __host__ __device__ inline uint32_t alloc_bytes(uint32_t size) { return (size + 
 // Host launchers (qcz_kernels.hip).
 hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st, int wpg,
                        hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
-// block cache: key the jobs (clears the key table first), then run the
-// leaders (list 1, no gate epilogue) and the followers (list 2, closes the
-// gate); both launches with the same grid, at most kMaxGrid / 2
+// block cache: key the jobs (clears the key table first), run the leaders
+// (list 1, no gate epilogue), copy the followers whose inputs match (one
+// wavefront per job), then run the remaining followers (list 2, closes the
+// gate); both job launches with the same grid, at most kMaxGrid / 2
 hipError_t launch_cache_plan(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, hipStream_t st);
+hipError_t launch_cache_copy(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, hipStream_t st);
 hipError_t launch_gate_list(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, int list, int grid,
                             hipStream_t st);
 hipError_t launch_permute(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);

@@ -984,7 +984,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     for (uint64_t job = job_begin(gd) + blockIdx.x; job < jstop; job += gridDim.x) {
         if (LIST != 0) {
             const uint32_t r = io.role[job - job_begin(gd)];
-            if (LIST == 1 ? r != 0u : r == 0u) continue;   // (uniform over the workgroup)
+            if (LIST == 1 ? r != 0u : (r == 0u || r == kRoleDone)) continue;   // (uniform over the workgroup)
         }
         const uint64_t item0 = 2 * job, item1 = 2 * job + 1;
         const bool valid0 = item0 < gd.nitems, valid1 = item1 < gd.nitems;
@@ -1416,6 +1416,15 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                     h += wp.hits;
                 }
             }
+            if (LIST == 2)   // the followers' copy kernel (kCopyGrid workgroups)
+                for (uint32_t g = (uint32_t)tid; g < (uint32_t)kCopyGrid; g += WGS) {
+                    const WgPart wq = io.cparts[g];
+                    d += wq.delta;
+                    r += wq.reenc;
+                    rd += wq.rd;
+                    wr += wq.wr;
+                    h += wq.hits;
+                }
             if (tid < kStripes) used = atomicAdd((unsigned long long *)&ds->stripe[tid][0], 0ull);
             for (int off = 32; off >= 1; off >>= 1) {
                 d += __shfl_down(d, off, 64);
@@ -1581,7 +1590,19 @@ __global__ __launch_bounds__(kWG) void cache_plan_kernel(GateDesc gd, DevPtrs P,
                 if (entry_ok(e, P.arena_words)) {
                     const uint32_t size = (uint32_t)(e & 0xFFFFull), words = (size + 3u) >> 2;
                     const uint32_t *w = P.arena + (e >> 16);
-                    for (uint32_t i = (uint32_t)lane; i < words; i += 64) h += mix64(((uint64_t)i << 32) | w[i]);
+                    for (uint32_t i0 = (uint32_t)lane; i0 < words; i0 += 8u * 64u) {   // eight loads in flight
+                        uint32_t v[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const uint32_t i = i0 + 64u * (uint32_t)u;
+                            v[u] = i < words ? w[i] : 0u;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const uint32_t i = i0 + 64u * (uint32_t)u;
+                            h += i < words ? mix64(((uint64_t)i << 32) | v[u]) : 0ull;
+                        }
+                    }
                     for (int o = 32; o >= 1; o >>= 1) h += __shfl_xor(h, o, 64);
                     h = mix64(h ^ ((uint64_t)size << 40));
                     work = true;
@@ -1613,6 +1634,113 @@ __global__ __launch_bounds__(kWG) void cache_plan_kernel(GateDesc gd, DevPtrs P,
             }
         }
         cp.role[job - j0] = role;
+    }
+}
+
+// Block cache followers, one wavefront per job: when both positions hold the
+// same streams as the leader job's inputs (byte comparison) and the gate reads
+// the same index bits, copy the leader's new streams (written by the leaders'
+// launch) and mark the job done; otherwise leave it to the followers' job
+// launch, which computes it.  Many jobs are in flight per CU, so the chain of
+// dependent loads of a follower is overlapped.  Per-workgroup sums go to
+// `parts` (always written, kCopyGrid workgroups), closed by that launch.
+__global__ __launch_bounds__(kWG) void cache_copy_kernel(GateDesc gd, DevPtrs P, CachePtrs cp, WgPart *parts)
+{
+    __shared__ uint64_t red[kWG / 64][5];
+    uint32_t unit_mask = 0;
+    for (int i = 0; i < 4; ++i) unit_mask |= unit_phase(gd.m[2 * i], gd.m[2 * i + 1]) ? (1u << i) : 0u;
+    const IOPtrs io = {};
+    const uint64_t opm = op_mask(gd, P.cb);
+    const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+    DevState *ds = P.ds;
+    const uint64_t nstr = ds->nstripes, sbase = ds->base, ssize = ds->stripe_size;
+    const int stripe = (int)(blockIdx.x % (uint32_t)nstr);
+    uint64_t a_d = 0, a_r = 0, a_rd = 0, a_wr = 0, a_h = 0;   // lane 0 of each wavefront
+    const uint64_t j0 = job_begin(gd), j1 = job_stop(gd);
+    const uint64_t nw = (uint64_t)gridDim.x * (kWG / 64);
+    const bool run = ds->stop == 0;
+    for (uint64_t job = j0 + (uint64_t)blockIdx.x * (kWG / 64) + (uint64_t)wv; run && job < j1; job += nw) {
+        const uint32_t role = cp.role[job - j0];
+        if (role == 0u) continue;
+        const uint64_t lj = cp.owner[role - 1u];
+        uint64_t c[2], mine[2], lnew[2];
+        bool act[2], valid[2], same = true;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const uint64_t item = 2 * job + (uint64_t)s, li = 2 * lj + (uint64_t)s;
+            uint64_t lc = 0;
+            act[s] = job_slot<SRC_ARENA, true>(gd, unit_mask, io, P.cb, item, c[s]);
+            const bool lact = job_slot<SRC_ARENA, true>(gd, unit_mask, io, P.cb, li, lc);
+            valid[s] = item < gd.nitems;
+            const bool lvalid = li < gd.nitems;
+            mine[s] = valid[s] ? P.table[c[s]] : 0ull;
+            const uint64_t lold = lvalid ? P.undo[li] : 0ull;
+            lnew[s] = act[s] ? P.table[lc] : 0ull;
+            bool ss = valid[s] == lvalid && act[s] == lact && (c[s] & opm) == (lc & opm);
+            if (ss && act[s])
+                ss = (mine[s] & 0xFFFFull) == (lold & 0xFFFFull) && entry_ok(mine[s], P.arena_words) &&
+                     entry_ok(lold, P.arena_words) && entry_ok(lnew[s], P.arena_words);
+            if (ss && act[s]) {
+                const uint32_t words = (uint32_t)(((mine[s] & 0xFFFFull) + 3ull) >> 2);
+                const uint32_t *pa = P.arena + (mine[s] >> 16), *pb = P.arena + (lold >> 16);
+                uint32_t diff = 0;
+                for (uint32_t w = (uint32_t)lane; w < words; w += 64) diff |= pa[w] ^ pb[w];
+                ss = !__any(diff != 0u);
+            }
+            same = same && ss;
+        }
+        if (!same) continue;   // computed by the followers' job launch
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const uint64_t item = 2 * job + (uint64_t)s;
+            if (!act[s]) {
+                if (valid[s] && lane == 0) P.undo[item] = mine[s];
+                continue;
+            }
+            const uint32_t nsize = (uint32_t)(lnew[s] & 0xFFFFull);
+            unsigned long long off = 0;
+            if (lane == 0)
+                off = atomicAdd((unsigned long long *)&ds->stripe[stripe][0], (unsigned long long)alloc_bytes(nsize));
+            off = __shfl(off, 0, 64);
+            const bool ok = off + alloc_bytes(nsize) <= ssize;
+            if (ok) {
+                const uint64_t dstw = (sbase + (uint64_t)stripe * ssize + off) >> 2, srcw = lnew[s] >> 16;
+                const uint32_t words = (nsize + 3u) >> 2;
+                if ((srcw & 3ull) == 0) {   // whole 16-byte units, zero past the leader's stream
+                    const u32x4 *s4 = reinterpret_cast<const u32x4 *>(P.arena + srcw);
+                    u32x4 *d4 = reinterpret_cast<u32x4 *>(P.arena + dstw);
+                    for (uint32_t w = (uint32_t)lane; w < (words + 3u) >> 2; w += 64) d4[w] = s4[w];
+                } else {
+                    for (uint32_t w = (uint32_t)lane; w < ((words + 3u) & ~3u); w += 64)
+                        P.arena[dstw + w] = w < words ? P.arena[srcw + w] : 0u;
+                }
+                if (lane == 0) {
+                    P.table[c[s]] = (dstw << 16) | (uint64_t)nsize;
+                    const uint64_t old_pad = ((mine[s] & 0xFFFFull) + 3ull) & ~3ull;
+                    const uint64_t new_pad = ((uint64_t)nsize + 3ull) & ~3ull;
+                    a_d += new_pad - old_pad;
+                    a_r += 1;
+                    a_rd += old_pad;
+                    a_wr += new_pad;
+                    a_h += 1;
+                }
+            } else if (lane == 0) {
+                atomicExch(&ds->fail, 1);
+            }
+            if (lane == 0) P.undo[item] = mine[s];
+        }
+        if (lane == 0) cp.role[job - j0] = kRoleDone;
+    }
+    if (lane == 0) {
+        red[wv][0] = a_d; red[wv][1] = a_r; red[wv][2] = a_rd; red[wv][3] = a_wr; red[wv][4] = a_h;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        WgPart wp = {};
+        for (int w = 0; w < kWG / 64; ++w) {
+            wp.delta += red[w][0]; wp.reenc += red[w][1]; wp.rd += red[w][2]; wp.wr += red[w][3]; wp.hits += red[w][4];
+        }
+        parts[blockIdx.x] = wp;
     }
 }
 
@@ -1766,6 +1894,7 @@ hipError_t launch_gate_list(const GateDesc &gd, const DevPtrs &P, const CachePtr
     IOPtrs io = {};
     io.role = cp.role;
     io.owner = cp.owner;
+    io.cparts = cp.parts;
     switch (P.C / 128) {
     case 1: launch_list_v<1>(gd, P, io, list, grid, st); break;
     case 2: launch_list_v<2>(gd, P, io, list, grid, st); break;
@@ -1774,6 +1903,12 @@ hipError_t launch_gate_list(const GateDesc &gd, const DevPtrs &P, const CachePtr
     case 16: launch_list_v<16>(gd, P, io, list, grid, st); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_cache_copy(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, hipStream_t st)
+{
+    hipLaunchKernelGGL(cache_copy_kernel, dim3(kCopyGrid), dim3(kWG), 0, st, gd, P, cp, cp.parts);
     return hipGetLastError();
 }
 

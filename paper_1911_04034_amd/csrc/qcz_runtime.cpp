@@ -45,7 +45,7 @@ struct GraphEntry {
 
 struct Layout {
     size_t ds, table, undo, bsums, blevel, partials, wgp, scratch, cstats, feat, fn2, fsel, ckeys, cowner, crole,
-        arena0, arena1, arena_bytes, end;
+        cparts, arena0, arena1, arena_bytes, end;
     uint64_t ctsize;   // block cache key slots (0: no cache)
 };
 
@@ -80,6 +80,7 @@ Layout layout_for(int n, int bl, size_t pool_bytes, bool cache)
     L.ckeys = o; o = align256(o + 8 * (size_t)L.ctsize);
     L.cowner = o; o = align256(o + 4 * (size_t)L.ctsize);
     L.crole = o; o = align256(o + 4 * (size_t)(cache ? std::max<uint64_t>(1, nchunks / 2) : 0));
+    L.cparts = o; o = align256(o + (cache ? sizeof(WgPart) * (size_t)kCopyGrid : 0));
     L.end = o;
     size_t rest = pool_bytes > o ? pool_bytes - o : 0;
     L.arena_bytes = (rest / 2) & ~(size_t)255;
@@ -375,11 +376,12 @@ qcz_status launch_one(qcz_state *s, const GateDesc &d, bool timing)
 {
     DevPtrs P = ptrs(s);
     if (cache_gate(s, d)) {
-        // plan, leaders, followers: one gate over three launches, timed together
+        // plan, leaders, follower copies, other followers: one gate over four launches, timed together
         CachePtrs cp{};
         cp.keys = (uint64_t *)(s->pool + s->lay.ckeys);
         cp.owner = (uint32_t *)(s->pool + s->lay.cowner);
         cp.role = (uint32_t *)(s->pool + s->lay.crole);
+        cp.parts = (WgPart *)(s->pool + s->lay.cparts);
         cp.tsize = 64;
         while (cp.tsize < 2 * d.njobs) cp.tsize *= 2;
         if (cp.tsize > s->lay.ctsize) return fail(s, QCZ_E_STATE, "block cache table too small");
@@ -388,6 +390,7 @@ qcz_status launch_one(qcz_state *s, const GateDesc &d, bool timing)
         if (timing) HIPCHK(s, hipEventRecord(s->events[2 * d.seq], s->stream));
         hipError_t e = launch_cache_plan(d, P, cp, s->stream);
         if (e == hipSuccess) e = launch_gate_list(d, P, cp, 1, grid, s->stream);
+        if (e == hipSuccess) e = launch_cache_copy(d, P, cp, s->stream);
         if (e == hipSuccess) e = launch_gate_list(d, P, cp, 2, grid, s->stream);
         if (e != hipSuccess) return fail(s, QCZ_E_DEVICE, std::string("cached gate launch: ") + hipGetErrorString(e));
         if (timing) {
