@@ -150,7 +150,7 @@ typedef struct {
     uint64_t range_gates;       /* gates run in job ranges because their new streams did not fit at once
                                    (not event-timed) */
     uint64_t cache_gates;       /* QCZ_FLAG_CACHE: gates run through the block cache (event timing, if on,
-                                   covers the cache's planning kernel and both job launches) */
+                                   covers the cache's planning and copy kernels and both job launches) */
     uint64_t cache_hits;        /* chunks whose new stream was copied from an identical job's */
     uint32_t cache_on;          /* 1 while the block cache is in use */
     uint32_t reserved;

@@ -135,6 +135,7 @@ struct CachePtrs {
     uint64_t *keys;       // [tsize], kEmptyKey when free
     uint32_t *owner;      // [tsize]
     uint32_t *role;       // [jobs of the launch]
+    uint64_t *jkey;       // [jobs of the launch] key of each job (kEmptyKey: leads without a match)
     WgPart *parts;        // [kCopyGrid] per-workgroup sums of the copy kernel
     uint64_t tsize;       // power of two, at least twice the jobs of the launch
     uint64_t key_mask;    // bits of the key kept (all but in tests that force collisions)
@@ -161,7 +162,8 @@ __host__ __device__ inline uint32_t alloc_bytes(uint32_t size) { return (size + 
 // Host launchers (qcz_kernels.hip).
 hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st, int wpg,
                        hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
-// block cache: key the jobs (clears the key table first), run the leaders
+// block cache: key the jobs (hash pass, which also clears the key table, then
+// a dedupe pass), run the leaders
 // (list 1, no gate epilogue), copy the followers whose inputs match (one
 // wavefront per job), then run the remaining followers (list 2, closes the
 // gate); both job launches with the same grid, at most kMaxGrid / 2

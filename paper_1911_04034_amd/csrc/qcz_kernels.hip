@@ -981,10 +981,19 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     double mom_re = 0.0, mom_im = 0.0, mom_n2 = 0.0;
 
     const uint64_t jstop = job_stop(gd);
-    for (uint64_t job = job_begin(gd) + blockIdx.x; job < jstop; job += gridDim.x) {
+    __shared__ uint32_t sh_role[LIST != 0 ? 256 : 1];
+    uint32_t kjob = 0;   // iterations of this workgroup's job loop
+    for (uint64_t job = job_begin(gd) + blockIdx.x; job < jstop; job += gridDim.x, ++kjob) {
+        uint32_t rjob = 0;
         if (LIST != 0) {
-            const uint32_t r = io.role[job - job_begin(gd)];
-            if (LIST == 1 ? r != 0u : (r == 0u || r == kRoleDone)) continue;   // (uniform over the workgroup)
+            if ((kjob & 255u) == 0u) {   // the roles of this workgroup's next 256 jobs, in one batch
+                lds_barrier();
+                const uint64_t jj = job + (uint64_t)tid * gridDim.x;
+                if (tid < 256) sh_role[tid] = jj < jstop ? io.role[jj - job_begin(gd)] : 0u;
+                lds_barrier();
+            }
+            rjob = sh_role[kjob & 255u];
+            if (LIST == 1 ? rjob != 0u : (rjob == 0u || rjob == kRoleDone)) continue;   // (uniform over the workgroup)
         }
         const uint64_t item0 = 2 * job, item1 = 2 * job + 1;
         const bool valid0 = item0 < gd.nitems, valid1 = item1 < gd.nitems;
@@ -1000,7 +1009,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
         // as the leader job's inputs (compared byte by byte) and the gate
         // reads the same index bits, the leader's new streams are the result
         if (LIST == 2) {
-            const uint64_t lj = io.owner[io.role[job - job_begin(gd)] - 1u];
+            const uint64_t lj = io.owner[rjob - 1u];
             const uint64_t li = 2 * lj + (uint64_t)s;
             uint64_t lc = 0;
             const bool lact = job_slot<SRC, GATE>(gd, unit_mask, io, P.cb, li, lc);
@@ -1561,14 +1570,16 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
-// Block cache (Sec. 3.4) of one gate launch: one wavefront per job hashes the
-// job's input streams (word values with their positions, and the size) and
-// the chunk-index bits the gate reads, then inserts the key into an
-// open-addressing table.  The job that inserts a key leads (role 0); a job
-// that finds its key follows the slot's owner (role 1 + slot).  Jobs with no
-// stream to re-encode, or with an entry outside the arena, lead.
-__global__ __launch_bounds__(kWG) void cache_plan_kernel(GateDesc gd, DevPtrs P, CachePtrs cp)
+// Block cache (Sec. 3.4) of one gate launch, first pass: one wavefront per
+// job hashes the job's input streams (word values with their positions, and
+// the size) and the chunk-index bits the gate reads into a 64-bit key.  Jobs
+// with no stream to re-encode, or with an entry outside the arena, get
+// kEmptyKey: they lead without looking for a match.
+__global__ __launch_bounds__(kWG) void cache_hash_kernel(GateDesc gd, DevPtrs P, CachePtrs cp)
 {
+    // clear the key table (read by the next kernel only)
+    for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < cp.tsize; i += (uint64_t)gridDim.x * kWG)
+        cp.keys[i] = kEmptyKey;
     uint32_t unit_mask = 0;
     for (int i = 0; i < 4; ++i) unit_mask |= unit_phase(gd.m[2 * i], gd.m[2 * i + 1]) ? (1u << i) : 0u;
     const IOPtrs io = {};
@@ -1614,27 +1625,66 @@ __global__ __launch_bounds__(kWG) void cache_plan_kernel(GateDesc gd, DevPtrs P,
             key = mix64(key ^ h) + mix64(tag + (uint64_t)sl);
         }
         if (lane != 0) continue;
-        uint32_t role = 0;
         if (work && !plain) {
             key &= cp.key_mask;
             if (key == kEmptyKey) key ^= 1ull;
-            uint64_t slot = key & (cp.tsize - 1);
-            for (uint64_t probe = 0; probe < cp.tsize; ++probe) {
-                const uint64_t prev = atomicCAS((unsigned long long *)&cp.keys[slot], (unsigned long long)kEmptyKey,
-                                                (unsigned long long)key);
-                if (prev == kEmptyKey) {
-                    cp.owner[slot] = (uint32_t)job;
-                    break;
-                }
-                if (prev == key) {
-                    role = 1u + (uint32_t)slot;
-                    break;
-                }
-                slot = (slot + 1) & (cp.tsize - 1);
-            }
+        } else {
+            key = kEmptyKey;
         }
-        cp.role[job - j0] = role;
+        cp.jkey[job - j0] = key;
     }
+}
+
+// Second pass, one thread per job: jobs of a workgroup meet in an LDS table
+// first, so that only one job per distinct key and workgroup inserts into the
+// global open-addressing table.  The job that inserts a key globally leads
+// (role 0); every other job with that key follows the slot's owner (role 1 +
+// slot).
+__global__ __launch_bounds__(kWG) void cache_dedupe_kernel(GateDesc gd, CachePtrs cp)
+{
+    __shared__ unsigned long long tkey[2 * kWG];
+    __shared__ uint32_t town[2 * kWG];
+    __shared__ uint32_t tslot[kWG];
+    const int t = (int)threadIdx.x;
+    tkey[t] = kEmptyKey;
+    tkey[t + kWG] = kEmptyKey;
+    __syncthreads();
+    const uint64_t j0 = job_begin(gd), j1 = job_stop(gd);
+    const uint64_t job = j0 + (uint64_t)blockIdx.x * kWG + (uint64_t)t;
+    const uint64_t key = job < j1 ? cp.jkey[job - j0] : kEmptyKey;
+    int h = -1;
+    if (key != kEmptyKey) {
+        int p = (int)((key >> 17) & (2 * kWG - 1));
+        for (int probe = 0; probe < 2 * kWG; ++probe) {
+            const unsigned long long prev = atomicCAS(&tkey[p], (unsigned long long)kEmptyKey, (unsigned long long)key);
+            if (prev == kEmptyKey) { town[p] = (uint32_t)t; h = p; break; }
+            if (prev == key) { h = p; break; }
+            p = (p + 1) & (2 * kWG - 1);
+        }
+    }
+    __syncthreads();
+    const int lead = h >= 0 ? (int)town[h] : t;
+    uint32_t role = 0;
+    if (h >= 0 && lead == t) {   // the workgroup's first job with this key: global insert
+        uint64_t slot = key & (cp.tsize - 1);
+        for (uint64_t probe = 0; probe < cp.tsize; ++probe) {
+            const uint64_t prev = atomicCAS((unsigned long long *)&cp.keys[slot], (unsigned long long)kEmptyKey,
+                                            (unsigned long long)key);
+            if (prev == kEmptyKey) {
+                cp.owner[slot] = (uint32_t)job;
+                break;
+            }
+            if (prev == key) {
+                role = 1u + (uint32_t)slot;
+                break;
+            }
+            slot = (slot + 1) & (cp.tsize - 1);
+        }
+        tslot[t] = (uint32_t)slot;
+    }
+    __syncthreads();
+    if (h >= 0 && lead != t) role = 1u + tslot[lead];
+    if (job < j1) cp.role[job - j0] = role;
 }
 
 // Block cache followers, one wavefront per job: when both positions hold the
@@ -1916,11 +1966,11 @@ hipError_t launch_cache_plan(const GateDesc &gd, const DevPtrs &P, const CachePt
 {
     const uint64_t jobs = job_stop(gd) - job_begin(gd);
     if (cp.tsize < 2 * jobs || (cp.tsize & (cp.tsize - 1))) return hipErrorInvalidValue;
-    const uint64_t fb = std::min<uint64_t>((cp.tsize + kWG - 1) / kWG, 65535);
-    hipLaunchKernelGGL(fill_table_kernel, dim3((unsigned)fb), dim3(kWG), 0, st, cp.keys, cp.tsize, kEmptyKey,
-                       kEmptyKey);
-    const uint64_t pb = std::max<uint64_t>(1, std::min<uint64_t>((jobs + kWG / 64 - 1) / (kWG / 64), 65535));
-    hipLaunchKernelGGL(cache_plan_kernel, dim3((unsigned)pb), dim3(kWG), 0, st, gd, P, cp);
+    const uint64_t hb = std::max<uint64_t>(1, std::min<uint64_t>((jobs + kWG / 64 - 1) / (kWG / 64), 65535));
+    hipLaunchKernelGGL(cache_hash_kernel, dim3((unsigned)hb), dim3(kWG), 0, st, gd, P, cp);
+    const uint64_t db = (jobs + kWG - 1) / kWG;
+    if (db > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(cache_dedupe_kernel, dim3((unsigned)std::max<uint64_t>(1, db)), dim3(kWG), 0, st, gd, cp);
     return hipGetLastError();
 }
 

@@ -45,7 +45,7 @@ struct GraphEntry {
 
 struct Layout {
     size_t ds, table, undo, bsums, blevel, partials, wgp, scratch, cstats, feat, fn2, fsel, ckeys, cowner, crole,
-        cparts, arena0, arena1, arena_bytes, end;
+        cparts, cjkey, arena0, arena1, arena_bytes, end;
     uint64_t ctsize;   // block cache key slots (0: no cache)
 };
 
@@ -81,6 +81,7 @@ Layout layout_for(int n, int bl, size_t pool_bytes, bool cache)
     L.cowner = o; o = align256(o + 4 * (size_t)L.ctsize);
     L.crole = o; o = align256(o + 4 * (size_t)(cache ? std::max<uint64_t>(1, nchunks / 2) : 0));
     L.cparts = o; o = align256(o + (cache ? sizeof(WgPart) * (size_t)kCopyGrid : 0));
+    L.cjkey = o; o = align256(o + 8 * (size_t)(cache ? std::max<uint64_t>(1, nchunks / 2) : 0));
     L.end = o;
     size_t rest = pool_bytes > o ? pool_bytes - o : 0;
     L.arena_bytes = (rest / 2) & ~(size_t)255;
@@ -382,6 +383,7 @@ qcz_status launch_one(qcz_state *s, const GateDesc &d, bool timing)
         cp.owner = (uint32_t *)(s->pool + s->lay.cowner);
         cp.role = (uint32_t *)(s->pool + s->lay.crole);
         cp.parts = (WgPart *)(s->pool + s->lay.cparts);
+        cp.jkey = (uint64_t *)(s->pool + s->lay.cjkey);
         cp.tsize = 64;
         while (cp.tsize < 2 * d.njobs) cp.tsize *= 2;
         if (cp.tsize > s->lay.ctsize) return fail(s, QCZ_E_STATE, "block cache table too small");

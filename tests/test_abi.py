@@ -51,8 +51,8 @@ def test_host_only_calls():
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libqcz.so not built")
 def test_block_cache_pool_and_stats_layout():
-    """The block cache's key table (12 bytes per chunk), role array (4 bytes
-    per job) and the copy kernel's 1024 per-workgroup sums (56 bytes each)
+    """The block cache's key table (12 bytes per chunk), role and key arrays
+    (4 + 8 bytes per job) and the copy kernel's 1024 per-workgroup sums (56 bytes each)
     come out of the pool; the stats record ends with the cache counters as
     the header lays them out."""
     from paper_1911_04034_amd import qcz
@@ -61,7 +61,7 @@ def test_block_cache_pool_and_stats_layout():
     plain = L.qcz_pool_bytes_min(ctypes.byref(qcz.Config(n, bl, 1, 1, 0, 0, 0, 0, 0)))
     cached = L.qcz_pool_bytes_min(ctypes.byref(qcz.Config(n, bl, 1, 1, 0, qcz.FLAG_CACHE, 0, 0, 0)))
     nchunks = 1 << (n - 10)
-    need = 12 * nchunks + 4 * (nchunks // 2) + 1024 * 56
-    assert need <= cached - plain <= need + 4 * 256
+    need = 12 * nchunks + 12 * (nchunks // 2) + 1024 * 56
+    assert need <= cached - plain <= need + 5 * 256
     assert qcz.Stats.cache_on.offset == qcz.Stats.cache_hits.offset + 8
     assert ctypes.sizeof(qcz.Stats) == qcz.Stats.reserved.offset + 4
