@@ -932,8 +932,9 @@ __device__ __forceinline__ uint64_t op_mask(const GateDesc &gd, int cb)
 }
 
 // LIST 0: every job of the launch.  With the block cache, LIST 1 runs the
-// leader jobs and leaves the gate open; LIST 2 runs the followers (copy on an
-// exact match, compute otherwise) and closes the gate over both launches.
+// leader jobs and leaves the gate open; LIST 2 computes the followers that the
+// copy kernel did not copy (their bytes differ from their leader's) and closes
+// the gate over the leaders' launch, the copy kernel and itself.
 template <int V, int WPG, int SRC, int DST, bool GATE, int LIST = 0>
 __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDesc gd, DevPtrs P, IOPtrs io)
 {
@@ -950,7 +951,6 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     // the gate's parameters: read in the gate phase from LDS, so that the job
     // loop does not hold them in scalar registers
     __shared__ double sh_m[8];
-    __shared__ uint64_t sh_hit[2];   // block cache: chunks copied, per slot
 
     DevState *ds = P.ds;
     if (DST == DST_ARENA && ds->stop) return;
@@ -975,8 +975,6 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     // written) live in LDS: only thread 0 of a slot updates them
     if (DST == DST_ARENA && lt == 0)
         for (int k = 0; k < 4; ++k) sh_acc[4 * s + k] = 0;
-    if (LIST == 2 && lt == 0) sh_hit[s] = 0;
-    const uint64_t opm = LIST == 2 ? op_mask(gd, P.cb) : 0ull;
     double acc_wd = 0.0, acc_lost = 0.0;   // per-block fidelity ledger terms
     double mom_re = 0.0, mom_im = 0.0, mom_n2 = 0.0;
 
@@ -1004,83 +1002,6 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
         const uint64_t c = s ? cc1 : cc0;
         const bool valid = s ? valid1 : valid0;
         const bool act = s ? act1 : act0;
-
-        // 0. block cache follower: when both positions hold the same streams
-        // as the leader job's inputs (compared byte by byte) and the gate
-        // reads the same index bits, the leader's new streams are the result
-        if (LIST == 2) {
-            const uint64_t lj = io.owner[rjob - 1u];
-            const uint64_t li = 2 * lj + (uint64_t)s;
-            uint64_t lc = 0;
-            const bool lact = job_slot<SRC, GATE>(gd, unit_mask, io, P.cb, li, lc);
-            const bool lvalid = li < gd.nitems;
-            const uint64_t mine = valid ? P.table[c] : 0ull;
-            const uint64_t lold = lvalid ? P.undo[li] : 0ull;   // written by the leaders' launch
-            bool same = valid == lvalid && act == lact && (c & opm) == (lc & opm);
-            if (same && act)
-                same = (mine & 0xFFFFull) == (lold & 0xFFFFull) && entry_ok(mine, P.arena_words) &&
-                       entry_ok(lold, P.arena_words);
-            if (same && act) {
-                const uint32_t words = (uint32_t)(((mine & 0xFFFFull) + 3ull) >> 2);
-                const uint32_t *pa = P.arena + (mine >> 16), *pb = P.arena + (lold >> 16);
-                uint32_t diff = 0;
-                for (uint32_t w = (uint32_t)lt; w < words; w += G) diff |= pa[w] ^ pb[w];
-                same = diff == 0u;
-            }
-            const bool wbad = __any(!same);
-            if ((tid & 63) == 0) slS[tid >> 6] = wbad ? 1u : 0u;
-            lds_barrier();
-            uint32_t bad = 0;
-#pragma unroll
-            for (int i = 0; i < WGS / 64; ++i) bad |= slS[i];
-            if (bad == 0u) {
-                const uint64_t lnew = act ? P.table[lc] : 0ull;
-                const uint32_t nsize = (uint32_t)(lnew & 0xFFFFull);
-                if (lt == 0) {
-                    uint64_t my_off = 0;
-                    int ok = 0;
-                    if (act) {
-                        const int stripe = (int)(blockIdx.x % (uint32_t)ds_nstripes);
-                        my_off = atomicAdd((unsigned long long *)&ds->stripe[stripe][0],
-                                           (unsigned long long)alloc_bytes(nsize));
-                        ok = (my_off + alloc_bytes(nsize) <= ds_ssize) ? 1 : 0;
-                        my_off += ds_base + (uint64_t)stripe * ds_ssize;
-                        if (!ok) atomicExch(&ds->fail, 1);
-                    }
-                    sh_off[s] = my_off;
-                    sh_ok[s] = ok;
-                }
-                lds_barrier();
-                const int ok = sh_ok[s];
-                if (ok) {
-                    const uint32_t words = (nsize + 3u) >> 2;
-                    const uint64_t srcw = lnew >> 16, dstw = sh_off[s] >> 2;
-                    if ((srcw & 3ull) == 0) {   // whole 16-byte units, zero past the leader's stream
-                        const u32x4 *s4 = reinterpret_cast<const u32x4 *>(P.arena + srcw);
-                        u32x4 *d4 = reinterpret_cast<u32x4 *>(P.arena + dstw);
-                        for (uint32_t w = lt; w < (words + 3u) >> 2; w += G) d4[w] = s4[w];
-                    } else {
-                        for (uint32_t w = lt; w < ((words + 3u) & ~3u); w += G)
-                            P.arena[dstw + w] = w < words ? P.arena[srcw + w] : 0u;
-                    }
-                }
-                if (lt == 0 && valid) {
-                    P.undo[item] = mine;
-                    if (ok) {
-                        P.table[c] = ((sh_off[s] >> 2) << 16) | (uint64_t)nsize;
-                        const uint64_t old_pad = ((mine & 0xFFFFull) + 3ull) & ~3ull;
-                        const uint64_t new_pad = ((uint64_t)nsize + 3ull) & ~3ull;
-                        sh_acc[4 * s] += new_pad - old_pad;
-                        sh_acc[4 * s + 1] += 1;
-                        sh_acc[4 * s + 2] += old_pad;
-                        sh_acc[4 * s + 3] += new_pad;
-                        sh_hit[s] += 1;
-                    }
-                }
-                lds_barrier();
-                continue;
-            }
-        }
 
         // 1. fetch
         uint64_t old_entry = 0;
@@ -1391,7 +1312,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             wp.lost = 0.0;
             if (gd.per_block)
                 for (int w = 0; w < WGS / 64; ++w) { wp.wd += sh_mom[w][0]; wp.lost += sh_mom[w][1]; }
-            wp.hits = LIST == 2 ? sh_hit[0] + sh_hit[1] : 0;
+            wp.hits = 0;
             if (LIST == 1) {
                 P.wgp[kMaxGrid / 2 + blockIdx.x] = wp;   // summed by the followers' launch
             } else {
@@ -1422,7 +1343,6 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                     r += wq.reenc;
                     rd += wq.rd;
                     wr += wq.wr;
-                    h += wp.hits;
                 }
             }
             if (LIST == 2)   // the followers' copy kernel (kCopyGrid workgroups)
