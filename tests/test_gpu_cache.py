@@ -130,3 +130,24 @@ def test_cache_flag_with_one_job_per_gate():
     o.apply(gates)
     assert_same_chunks(g, o, "after %d gates" % len(gates))
     assert g.stats()["cache_gates"] == 0
+
+
+def test_cache_with_graph_replay():
+    """Cached gates captured in HIP graphs (planning, leaders, copies, other
+    followers: kernels only, no memset nodes) and replayed: every replay of
+    the Grover iteration leaves the oracle's bytes, with eager readouts and
+    synchronisations between the replays."""
+    from paper_1911_04034_amd import qcz
+    n, bl = 14, 8
+    w = cc.grover_marked(n, 5)
+    it = cc.grover_iteration(n, w)
+    g, o = make(n, bl, oq.MODE_FIXED, 1, flags=qcz.FLAG_CACHE | qcz.FLAG_GRAPH, batch=len(it))
+    g.apply(cc.grover_prefix(n))
+    o.apply(cc.grover_prefix(n))
+    for k in range(4):
+        say("cache + graph grover14 iteration %d" % k)
+        g.apply(it)
+        o.apply(it)
+        assert_same_chunks(g, o, "after replay %d" % k)
+        assert abs(g.read([w])[0]) > 0.0
+    assert g.stats()["cache_hits"] > 0
