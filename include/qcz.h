@@ -217,6 +217,18 @@ qcz_status qcz_export_chunk(qcz_state *st, uint64_t chunk, void *host_buf, size_
  * checked; QCZ_E_FORMAT if it is not a valid stream header or too long. */
 qcz_status qcz_import_chunk(qcz_state *st, uint64_t chunk, const void *host_buf, size_t len);
 
+/* Checkpoint resume (Sec. 3.5): after every chunk of a state saved with
+ * qcz_export_chunk has been imported into a fresh state of the same
+ * configuration, restore the run's ledger from the qcz_footprint_t taken when
+ * the chunks were saved: level, gates applied, lossy steps, min / max
+ * compressed bytes and the fidelity lower bound.  The saved record is only
+ * read.  QCZ_E_INVAL if its qubit count / chunk count do not match the state
+ * or a field is out of range (level, bound outside (0, 1], min > max);
+ * QCZ_E_STATE if the imported streams' compressed bytes differ from the
+ * record's (not every chunk imported), or in QCZ_MODE_PERBLOCK (its ledger
+ * also tracks the stored squared norm, which the record does not carry). */
+qcz_status qcz_resume(qcz_state *st, const qcz_footprint_t *saved);
+
 /* Per-block levels (host array of 2^(n - block_log2) values 0..5) used by
  * QCZ_MODE_PERBLOCK; QCZ_E_STATE in other modes. */
 qcz_status qcz_set_block_levels(qcz_state *st, const uint8_t *levels);

@@ -1118,6 +1118,27 @@ qcz_status qcz_footprint(qcz_state *s, qcz_footprint_t *out)
     return QCZ_OK;
 }
 
+qcz_status qcz_resume(qcz_state *s, const qcz_footprint_t *f)
+{
+    if (!s || !f) return QCZ_E_INVAL;
+    if (f->raw_bytes != (1ull << (s->n + 4)) || f->nchunks != s->nchunks) return fail(s, QCZ_E_INVAL, "other shape");
+    if (f->level < 0 || f->level >= kLevels || !(f->fidelity_lower_bound > 0.0 && f->fidelity_lower_bound <= 1.0) ||
+        f->min_compressed > f->max_compressed || f->lossy_steps > f->gates_applied)
+        return fail(s, QCZ_E_INVAL, "saved ledger out of range");
+    if (s->cfg.mode == QCZ_MODE_PERBLOCK) return fail(s, QCZ_E_STATE, "per-block ledgers are not resumable");
+    if (s->cfg.mode == QCZ_MODE_FIXED && f->level != s->cfg.level) return fail(s, QCZ_E_INVAL, "other fixed level");
+    if (s->cfg.mode == QCZ_MODE_LOSSLESS && f->level != 0) return fail(s, QCZ_E_INVAL, "lossy level in lossless mode");
+    if (f->compressed_bytes != s->live) return fail(s, QCZ_E_STATE, "imported streams differ from the saved size");
+    s->level = f->level;
+    s->gates_applied = f->gates_applied;
+    s->lossy_steps = f->lossy_steps;
+    s->min_c = f->min_compressed;
+    s->max_c = f->max_compressed;
+    s->flb = f->fidelity_lower_bound;
+    clear_graphs(s);
+    return write_header(s);   // the device copy of the level
+}
+
 qcz_status qcz_get_stats(qcz_state *s, qcz_stats_t *out)
 {
     if (!s || !out) return QCZ_E_INVAL;

@@ -67,7 +67,7 @@ EXPORTED = [
     "qcz_encode_chunks", "qcz_decode_chunks", "qcz_get_stats", "qcz_reset_stats", "qcz_set_launch",
     "qcz_block_stats", "qcz_block_level_sizes", "qcz_label_levels", "qcz_project_levels", "qcz_mlp_forward",
     "qcz_mlp_workspace_bytes", "qcz_mlp_train_step", "qcz_select_levels", "qcz_set_selector", "qcz_copy_state",
-    "qcz_mixing_mask", "qcz_overlap",
+    "qcz_mixing_mask", "qcz_overlap", "qcz_resume",
 ]
 MLP_PARAMS = 5638
 N_FEATURES = 16
@@ -100,6 +100,7 @@ def load():
     L.qcz_sample.argtypes = [vp, u64, sz, vp]
     L.qcz_footprint.restype = i32
     L.qcz_footprint.argtypes = [vp, ctypes.POINTER(Footprint)]
+    L.qcz_resume.argtypes = [vp, ctypes.POINTER(Footprint)]
     L.qcz_export_chunk.restype = i32
     L.qcz_export_chunk.argtypes = [vp, u64, vp, sz, ctypes.POINTER(sz)]
     L.qcz_import_chunk.restype = i32
@@ -293,6 +294,36 @@ class State:
     def import_chunk(self, c: int, data: bytes):
         b = np.frombuffer(bytes(data), dtype=np.uint8).copy()
         self._check(self._lib.qcz_import_chunk(self._h, c, b.ctypes.data, b.size), "qcz_import_chunk")
+
+    # -- checkpoint / resume (Sec. 3.5) --------------------------------------
+    def save(self, path: str):
+        """Write the compressed chunks and the ledger to `path` (.npz: plain
+        arrays, loadable without pickle)."""
+        blobs = [self.export_chunk(c) for c in range(self.nchunks)]
+        sizes = np.array([len(b) for b in blobs], dtype=np.uint32)
+        fp = Footprint()
+        self._check(self._lib.qcz_footprint(self._h, ctypes.byref(fp)), "qcz_footprint")
+        cfg = np.array([self.cfg.n_qubits, self.cfg.block_log2, self.cfg.mode, self.cfg.level, self.cfg.budget_bytes,
+                        self.cfg.flags, self.cfg.batch, self.cfg.grid, self.cfg.chunk_waves], dtype=np.int64)
+        np.savez(path, config=cfg, sizes=sizes, streams=np.frombuffer(b"".join(blobs), dtype=np.uint8),
+                 footprint=np.frombuffer(bytes(fp), dtype=np.uint8))
+
+    @classmethod
+    def load(cls, path: str, pool_bytes: int | None = None, stream=None) -> "State":
+        """A new state holding the chunks and ledger saved by `save`."""
+        with np.load(path, allow_pickle=False) as z:
+            cfg, sizes, streams, fpb = z["config"], z["sizes"], z["streams"], z["footprint"]
+        n, bl, mode, level, budget, flags, batch, grid, waves = (int(v) for v in cfg)
+        st = cls(n, bl, mode=mode, level=level, budget=budget, pool_bytes=pool_bytes, flags=flags, batch=batch,
+                 grid=grid, stream=stream, chunk_waves=waves)
+        if sizes.size != st.nchunks or fpb.size != ctypes.sizeof(Footprint):
+            raise QczError(-1, "checkpoint does not match the configuration")
+        off = np.concatenate([[0], np.cumsum(sizes.astype(np.int64))])
+        for c in range(st.nchunks):
+            st.import_chunk(c, streams[off[c]:off[c + 1]].tobytes())
+        fp = Footprint.from_buffer_copy(fpb.tobytes())
+        st._check(st._lib.qcz_resume(st._h, ctypes.byref(fp)), "qcz_resume")
+        return st
 
     def chunk_sizes(self) -> np.ndarray:
         out = np.zeros(self.nchunks, dtype=np.uint32)
