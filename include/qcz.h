@@ -217,8 +217,23 @@ qcz_status qcz_export_chunk(qcz_state *st, uint64_t chunk, void *host_buf, size_
  * checked; QCZ_E_FORMAT if it is not a valid stream header or too long. */
 qcz_status qcz_import_chunk(qcz_state *st, uint64_t chunk, const void *host_buf, size_t len);
 
+/* Whole-state checkpoint image (Sec. 3.5), one copy each way.  Export:
+ * sizes (n_chunks values, host) gets every chunk's stream size and *total the
+ * image size, sum over chunks of the size rounded up to 16 bytes; with
+ * host_buf null nothing else happens (a size query), otherwise the state is
+ * first compacted (its streams packed in chunk order) and the image copied:
+ * chunk c's stream starts at the sum of the rounded sizes of chunks < c, and
+ * the bytes between a stream's end and its 16-byte boundary are zero.
+ * QCZ_E_INVAL if cap < *total.  Import: replace every chunk of `st` by the
+ * streams of such an image (len = its total, sizes as exported); the streams'
+ * headers are checked first (QCZ_E_FORMAT, state unchanged), QCZ_E_NOMEM if
+ * the image exceeds one arena.  The ledger is not part of the image: restore
+ * it with qcz_resume. */
+qcz_status qcz_export_state(qcz_state *st, void *host_buf, size_t cap, uint32_t *sizes, size_t *total);
+qcz_status qcz_import_state(qcz_state *st, const void *host_buf, size_t len, const uint32_t *sizes);
+
 /* Checkpoint resume (Sec. 3.5): after every chunk of a state saved with
- * qcz_export_chunk has been imported into a fresh state of the same
+ * qcz_export_state (or qcz_export_chunk) has been imported into a fresh state of the same
  * configuration, restore the run's ledger from the qcz_footprint_t taken when
  * the chunks were saved: level, gates applied, lossy steps, min / max
  * compressed bytes and the fidelity lower bound.  The saved record is only

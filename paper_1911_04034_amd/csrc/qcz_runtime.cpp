@@ -1118,6 +1118,66 @@ qcz_status qcz_footprint(qcz_state *s, qcz_footprint_t *out)
     return QCZ_OK;
 }
 
+qcz_status qcz_export_state(qcz_state *s, void *host_buf, size_t cap, uint32_t *sizes, size_t *total)
+{
+    if (!s || !sizes || !total) return QCZ_E_INVAL;
+    if (host_buf) {
+        qcz_status st = compact(s);   // streams packed in chunk order from the arena's start
+        if (st != QCZ_OK) return st;
+    }
+    std::vector<uint64_t> tab(s->nchunks);
+    HIPCHK(s, hipMemcpyAsync(tab.data(), s->table, 8 * s->nchunks, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    uint64_t tot = 0;
+    for (uint64_t c = 0; c < s->nchunks; ++c) {
+        sizes[c] = (uint32_t)(tab[c] & 0xFFFFull);
+        if (host_buf && (tab[c] >> 16) * 4 != tot) return fail(s, QCZ_E_STATE, "streams not packed after compaction");
+        tot += alloc_bytes(sizes[c]);
+    }
+    *total = (size_t)tot;
+    if (!host_buf) return QCZ_OK;
+    if (cap < tot) return fail(s, QCZ_E_INVAL, "buffer smaller than the image");
+    HIPCHK(s, hipMemcpyAsync(host_buf, s->arena[s->cur], tot, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    uint8_t *p = (uint8_t *)host_buf;
+    uint64_t off = 0;
+    for (uint64_t c = 0; c < s->nchunks; ++c) {   // compaction copies 4-byte words: clear the unit tails
+        memset(p + off + sizes[c], 0, alloc_bytes(sizes[c]) - sizes[c]);
+        off += alloc_bytes(sizes[c]);
+    }
+    return QCZ_OK;
+}
+
+qcz_status qcz_import_state(qcz_state *s, const void *host_buf, size_t len, const uint32_t *sizes)
+{
+    if (!s || !host_buf || !sizes) return QCZ_E_INVAL;
+    const uint8_t *p = (const uint8_t *)host_buf;
+    uint64_t off = 0, live = 0;
+    std::vector<uint64_t> tab(s->nchunks);
+    for (uint64_t c = 0; c < s->nchunks; ++c) {
+        const uint32_t sz = sizes[c];
+        if (sz < 4 || sz > chunk_cap_bytes(s->C) || off + alloc_bytes(sz) > len)
+            return fail(s, QCZ_E_FORMAT, "stream size out of range");
+        const uint32_t hdr = (uint32_t)p[off] | ((uint32_t)p[off + 1] << 8) | ((uint32_t)p[off + 2] << 16) |
+                             ((uint32_t)p[off + 3] << 24);
+        const uint32_t mode = hdr & 3u, lev = (hdr >> 2) & 7u;
+        if ((hdr >> 5) != 0 || lev >= (uint32_t)kLevels || mode > M_SPARSE || (mode == M_CONST2 && sz != 20))
+            return fail(s, QCZ_E_FORMAT, "bad stream header");
+        tab[c] = ((off / 4) << 16) | (uint64_t)sz;
+        off += alloc_bytes(sz);
+        live += (sz + 3u) & ~3u;
+    }
+    if (off != len) return fail(s, QCZ_E_FORMAT, "image length differs from the sizes");
+    if (len > s->lay.arena_bytes) return fail(s, QCZ_E_NOMEM, "image larger than one arena");
+    HIPCHK(s, hipMemcpyAsync(s->arena[s->cur], host_buf, len, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->table, tab.data(), 8 * s->nchunks, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    s->live = live;
+    s->min_c = s->max_c = live;
+    clear_graphs(s);
+    return reset_stripes(s, len);
+}
+
 qcz_status qcz_resume(qcz_state *s, const qcz_footprint_t *f)
 {
     if (!s || !f) return QCZ_E_INVAL;

@@ -67,7 +67,7 @@ EXPORTED = [
     "qcz_encode_chunks", "qcz_decode_chunks", "qcz_get_stats", "qcz_reset_stats", "qcz_set_launch",
     "qcz_block_stats", "qcz_block_level_sizes", "qcz_label_levels", "qcz_project_levels", "qcz_mlp_forward",
     "qcz_mlp_workspace_bytes", "qcz_mlp_train_step", "qcz_select_levels", "qcz_set_selector", "qcz_copy_state",
-    "qcz_mixing_mask", "qcz_overlap", "qcz_resume",
+    "qcz_mixing_mask", "qcz_overlap", "qcz_resume", "qcz_export_state", "qcz_import_state",
 ]
 MLP_PARAMS = 5638
 N_FEATURES = 16
@@ -101,6 +101,8 @@ def load():
     L.qcz_footprint.restype = i32
     L.qcz_footprint.argtypes = [vp, ctypes.POINTER(Footprint)]
     L.qcz_resume.argtypes = [vp, ctypes.POINTER(Footprint)]
+    L.qcz_export_state.argtypes = [vp, vp, sz, vp, ctypes.POINTER(sz)]
+    L.qcz_import_state.argtypes = [vp, vp, sz, vp]
     L.qcz_export_chunk.restype = i32
     L.qcz_export_chunk.argtypes = [vp, u64, vp, sz, ctypes.POINTER(sz)]
     L.qcz_import_chunk.restype = i32
@@ -296,17 +298,35 @@ class State:
         self._check(self._lib.qcz_import_chunk(self._h, c, b.ctypes.data, b.size), "qcz_import_chunk")
 
     # -- checkpoint / resume (Sec. 3.5) --------------------------------------
+    def export_state(self):
+        """(image, sizes): every chunk's stream in chunk order, each padded to
+        16 bytes, as one host array (the state is compacted first)."""
+        sizes = np.zeros(self.nchunks, dtype=np.uint32)
+        total = ctypes.c_size_t(0)
+        self._check(self._lib.qcz_export_state(self._h, None, 0, sizes.ctypes.data, ctypes.byref(total)),
+                    "qcz_export_state")
+        image = np.zeros(max(1, total.value), dtype=np.uint8)
+        self._check(self._lib.qcz_export_state(self._h, image.ctypes.data, image.size, sizes.ctypes.data,
+                                               ctypes.byref(total)), "qcz_export_state")
+        return image[:total.value], sizes
+
+    def import_state(self, image, sizes):
+        image = np.ascontiguousarray(image, dtype=np.uint8)
+        sizes = np.ascontiguousarray(sizes, dtype=np.uint32)
+        if sizes.size != self.nchunks:
+            raise QczError(-1, "one size per chunk expected")
+        self._check(self._lib.qcz_import_state(self._h, image.ctypes.data, image.size, sizes.ctypes.data),
+                    "qcz_import_state")
+
     def save(self, path: str):
         """Write the compressed chunks and the ledger to `path` (.npz: plain
         arrays, loadable without pickle)."""
-        blobs = [self.export_chunk(c) for c in range(self.nchunks)]
-        sizes = np.array([len(b) for b in blobs], dtype=np.uint32)
+        image, sizes = self.export_state()
         fp = Footprint()
         self._check(self._lib.qcz_footprint(self._h, ctypes.byref(fp)), "qcz_footprint")
         cfg = np.array([self.cfg.n_qubits, self.cfg.block_log2, self.cfg.mode, self.cfg.level, self.cfg.budget_bytes,
                         self.cfg.flags, self.cfg.batch, self.cfg.grid, self.cfg.chunk_waves], dtype=np.int64)
-        np.savez(path, config=cfg, sizes=sizes, streams=np.frombuffer(b"".join(blobs), dtype=np.uint8),
-                 footprint=np.frombuffer(bytes(fp), dtype=np.uint8))
+        np.savez(path, config=cfg, sizes=sizes, streams=image, footprint=np.frombuffer(bytes(fp), dtype=np.uint8))
 
     @classmethod
     def load(cls, path: str, pool_bytes: int | None = None, stream=None) -> "State":
@@ -318,9 +338,7 @@ class State:
                  grid=grid, stream=stream, chunk_waves=waves)
         if sizes.size != st.nchunks or fpb.size != ctypes.sizeof(Footprint):
             raise QczError(-1, "checkpoint does not match the configuration")
-        off = np.concatenate([[0], np.cumsum(sizes.astype(np.int64))])
-        for c in range(st.nchunks):
-            st.import_chunk(c, streams[off[c]:off[c + 1]].tobytes())
+        st.import_state(streams, sizes)
         fp = Footprint.from_buffer_copy(fpb.tobytes())
         st._check(st._lib.qcz_resume(st._h, ctypes.byref(fp)), "qcz_resume")
         return st

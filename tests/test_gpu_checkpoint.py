@@ -113,3 +113,65 @@ def a_as_oracle(a):
         def chunk(c):
             return a.export_chunk(c)
     return View
+
+
+def test_state_image_matches_chunk_exports():
+    """The one-copy image holds every chunk's stream at its 16-byte offset,
+    zero up to the boundary; importing it into a fresh state gives the same
+    chunks, and a malformed image is refused without touching the state."""
+    import numpy as np
+    from paper_1911_04034_amd import qcz
+    n, bl = 12, 8
+    s = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=2, pool_bytes=64 << 20)
+    s.apply(cc.concat([cc.grover_prefix(n), cc.random_circuit_small(n, depth=8, seed=2)]))
+    image, sizes = s.export_state()
+    off = 0
+    for c in range(s.nchunks):
+        blob = s.export_chunk(c)
+        assert len(blob) == sizes[c]
+        assert image[off:off + len(blob)].tobytes() == blob
+        unit = (len(blob) + 15) // 16 * 16
+        assert not image[off + len(blob):off + unit].any()
+        off += unit
+    assert off == image.size
+    t = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=2, pool_bytes=64 << 20)
+    before = [t.export_chunk(c) for c in range(t.nchunks)]
+    bad = image.copy()
+    bad[0:4] = 0xFF
+    with pytest.raises(qcz.QczError):
+        t.import_state(bad, sizes)
+    assert [t.export_chunk(c) for c in range(t.nchunks)] == before
+    t.import_state(image, sizes)
+    assert_same_chunks(t, a_as_oracle(s), "after the image import")
+    assert t.footprint()["compressed_bytes"] == s.footprint()["compressed_bytes"]
+
+
+def test_checkpoint_full_size_grover24(tmp_path):
+    """At the benchmark shape (16384 chunks) a checkpoint taken after one
+    Grover iteration reloads the same streams and ledger, and both states
+    continue identically."""
+    import time
+    import numpy as np
+    from paper_1911_04034_amd import qcz
+    n, bl = 24, 16
+    w = cc.grover_marked(n, 2)
+    it = cc.grover_iteration(n, w)
+    a = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=1, pool_bytes=2 << 30, batch=128)
+    a.apply(cc.grover_prefix(n))
+    a.apply(it)
+    path = str(tmp_path / "grover24.npz")
+    t0 = time.perf_counter()
+    a.save(path)
+    b = qcz.State.load(path, pool_bytes=2 << 30)
+    say("grover24 checkpoint save + load %.2f s" % (time.perf_counter() - t0))
+    assert np.array_equal(a.chunk_sizes(), b.chunk_sizes())
+    assert all(a.footprint()[k] == b.footprint()[k] for k in LEDGER)
+    rng = np.random.default_rng(3)
+    for c in rng.choice(a.nchunks, size=64, replace=False):
+        assert a.export_chunk(int(c)) == b.export_chunk(int(c))
+    a.apply(it)
+    b.apply(it)
+    assert np.array_equal(a.chunk_sizes(), b.chunk_sizes())
+    for c in rng.choice(a.nchunks, size=64, replace=False):
+        assert a.export_chunk(int(c)) == b.export_chunk(int(c))
+    assert all(a.footprint()[k] == b.footprint()[k] for k in LEDGER)
