@@ -370,11 +370,16 @@ def main():
 
     roofline = None
     traffic = None
+    valu_busy = None
     if args.workload == "grover24+qft24" and not args.cache:
         from paper_1911_04034_amd import profile_summary as ps
         t_bytes, t_hash = ps.read_traffic(os.path.join(ROOT, "profiles", "traffic_fused_kernel_grover24_qft24.txt"))
         if t_bytes is not None and t_hash == ps.kernel_hash():
             traffic = round(t_bytes, 1)
+        # what bounds the kernel: SQ counters of the same source (VALU issue per SIMD)
+        busy, b_hash = ps.read_valu_busy(os.path.join(ROOT, "profiles", "counters_fused_kernel_qft24_grover24.txt"))
+        if busy and b_hash == ps.kernel_hash():
+            valu_busy = busy
     if timed > 0:
         avg_ms = kms / timed
         bytes_per_launch = (rd + wr + tb) / launches if launches else 0.0
@@ -384,7 +389,7 @@ def main():
                     "kernel": ("block cache: plan + leader job launch + follower copy kernel + remaining followers, per gate"
                                if args.cache else "job_kernel<16, ARENA, ARENA, gate> (fused decode-gate-encode)"),
                     "avg_launch_us": round(avg_ms * 1e3, 3), "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
-                    "launches": timed}
+                    "launches": timed, "valu_busy_per_simd": valu_busy}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -125,6 +125,21 @@ def counters(command, *runs, waves_per_simd=3):
         print("  %-22s %.3f" % ("LDS / VALU", v["SQ_INSTS_LDS"] / v["SQ_INSTS_VALU"]))
 
 
+def read_valu_busy(path):
+    """({workload: VALU busy per SIMD}, kernel hash) from a counters summary, or ({}, None)."""
+    if not os.path.exists(path):
+        return {}, None
+    busy, h, cur = {}, None, None
+    for line in open(path):
+        if line.startswith("# kernel source sha256[:16]:"):
+            h = line.rsplit(":", 1)[1].strip()
+        elif line.startswith("workload "):
+            cur = line.split()[1]
+        elif cur and line.strip().startswith("VALU busy per SIMD"):
+            busy[cur] = float(line.split()[-1])
+    return busy, h
+
+
 def read_traffic(path):
     """(bytes per dispatch, kernel hash) from a traffic summary, or (None, None)."""
     if not os.path.exists(path):

@@ -65,3 +65,16 @@ def test_block_cache_pool_and_stats_layout():
     assert need <= cached - plain <= need + 5 * 256
     assert qcz.Stats.cache_on.offset == qcz.Stats.cache_hits.offset + 8
     assert ctypes.sizeof(qcz.Stats) == qcz.Stats.reserved.offset + 4
+
+
+def test_profile_summaries_parse():
+    """The bench reads its traffic and VALU-busy figures from the committed
+    rocprofv3 summaries, each tagged with the kernel source hash it was
+    taken with."""
+    from paper_1911_04034_amd import profile_summary as ps
+    prof = os.path.join(ROOT, "profiles")
+    t_bytes, t_hash = ps.read_traffic(os.path.join(prof, "traffic_fused_kernel_grover24_qft24.txt"))
+    busy, b_hash = ps.read_valu_busy(os.path.join(prof, "counters_fused_kernel_qft24_grover24.txt"))
+    assert t_bytes is not None and t_bytes > 0 and len(t_hash) == 16
+    assert set(busy) == {"qft24", "grover24"} and all(0.0 < v <= 1.0 for v in busy.values())
+    assert len(b_hash) == 16
