@@ -246,6 +246,8 @@ def main():
     ap.add_argument("--chunk-waves", type=int, default=0, help="wavefronts per chunk in the fused kernel (2, 4, 8)")
     ap.add_argument("--no-timing", action="store_true", help="launch from graphs instead of timing each kernel")
     ap.add_argument("--selector", action="store_true", help="qaoa34: also run the learned per-block selector")
+    ap.add_argument("--fuse", action="store_true",
+                    help="grover24/qft24: fuse runs of in-chunk single-qubit gates (a separate figure)")
     ap.add_argument("--cache", action="store_true",
                     help="grover24/qft24: run with the compressed block cache (a separate figure: each gate is "
                          "then a planning kernel plus two job launches, timed together)")
@@ -282,6 +284,8 @@ def main():
     flags = qcz.FLAG_GRAPH if args.no_timing else qcz.FLAG_TIMING
     if args.cache:
         flags |= qcz.FLAG_CACHE
+    if args.fuse:
+        flags |= qcz.FLAG_FUSE
     stream = torch.cuda.Stream()
 
     # --- inputs resident in HBM before timing -------------------------------
@@ -371,7 +375,7 @@ def main():
     roofline = None
     traffic = None
     valu_busy = None
-    if args.workload == "grover24+qft24" and not args.cache:
+    if args.workload == "grover24+qft24" and not args.cache and not args.fuse:
         from paper_1911_04034_amd import profile_summary as ps
         t_bytes, t_hash = ps.read_traffic(os.path.join(ROOT, "profiles", "traffic_fused_kernel_grover24_qft24.txt"))
         if t_bytes is not None and t_hash == ps.kernel_hash():
@@ -382,7 +386,7 @@ def main():
             valu_busy = busy
     if timed > 0:
         avg_ms = kms / timed
-        bytes_per_launch = (rd + wr + tb) / launches if launches else 0.0
+        bytes_per_launch = (rd + wr + tb) / timed   # per timed kernel (a fused run is one kernel)
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
@@ -412,6 +416,9 @@ def main():
         "compactions": compactions,
         "workloads": out_extra,
     }
+    if args.fuse:
+        line["config"]["fused_runs"] = True
+        line["roofline"]["kernel"] = "job_kernel fused runs of in-chunk gates + per-gate fused kernels"
     if args.cache:
         ch = sum(x["cache_hits"] for x in stats)
         line["config"]["block_cache"] = True

@@ -80,6 +80,15 @@ typedef enum {
                                Needs a larger pool (qcz_pool_bytes_min); not with QCZ_FLAG_AUTOTUNE. */
 #define QCZ_FLAG_CACHE_COLLIDE 32u /* test hook: keep 3 bits of the cache keys, so that different
                                       streams share keys and only the byte comparison separates them */
+#define QCZ_FLAG_FUSE 64u   /* gate-layer fusion, QCZ_MODE_FIXED / QCZ_MODE_LOSSLESS: consecutive single-qubit
+                               gates (U1, X) on in-chunk qubits with no control on a chunk-index qubit run as
+                               one pass per batch run (up to 32 gates): one decode, each gate followed by the
+                               truncation its re-encoding would apply (Sec. 3.7; none for a chunk holding a
+                               subnormal value), one encode.  Bytes, ledger and work counters (chunks and
+                               amplitudes per gate) equal the gate-by-gate run's; the stream bytes moved are
+                               counted once per pass, and min / max compressed bytes are sampled after each
+                               pass.  Direct launches only (not inside replayed graphs); not with
+                               QCZ_FLAG_AUTOTUNE; gates of the block cache are not fused. */
 
 typedef struct {
     uint32_t n_qubits;      /* 6 .. 40 */

@@ -121,7 +121,12 @@ struct IOPtrs {
     const uint32_t *role;       // block cache, per job of the launch: 0 leader, else 1 + key slot
     const uint32_t *owner;      // block cache, per key slot: the leader job
     const WgPart *cparts;       // block cache: per-workgroup sums of the followers' copy kernel
+    const GateDesc *run;        // fused run: the gates applied in one decode / encode pass
+    int32_t nrun;
 };
+
+// Gate-layer fusion: at most this many gates per fused pass.
+constexpr int kMaxRun = 32;
 
 // Compressed block cache of one gate launch (Sec. 3.4, on the GPU): every job
 // is keyed by a hash of its input streams and of the chunk-index bits the gate
@@ -169,6 +174,10 @@ hipError_t launch_gate(const GateDesc &gd, const DevPtrs &P, int grid, hipStream
 // gate); both job launches with the same grid, at most kMaxGrid / 2
 hipError_t launch_cache_plan(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, hipStream_t st);
 hipError_t launch_cache_copy(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, hipStream_t st);
+// a run of nrun in-chunk gates (device array `run`) in one pass over every
+// chunk; gd: the run's first gate (its enumeration and batch position)
+hipError_t launch_gate_run(const GateDesc &gd, const DevPtrs &P, const GateDesc *run, int nrun, int grid,
+                           hipStream_t st, hipEvent_t t0, hipEvent_t t1);
 hipError_t launch_gate_list(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, int list, int grid,
                             hipStream_t st);
 hipError_t launch_permute(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);

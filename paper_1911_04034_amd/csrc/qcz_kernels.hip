@@ -931,7 +931,9 @@ __device__ __forceinline__ uint64_t op_mask(const GateDesc &gd, int cb)
     return m;
 }
 
-// LIST 0: every job of the launch.  With the block cache, LIST 1 runs the
+// LIST 0: every job of the launch.  LIST 3: a fused run of in-chunk gates
+// (io.run), each followed by the truncation its re-encoding would apply, with
+// one decode before and one encode after.  With the block cache, LIST 1 runs the
 // leader jobs and leaves the gate open; LIST 2 computes the followers that the
 // copy kernel did not copy (their bytes differ from their leader's) and closes
 // the gate over the leaders' launch, the copy kernel and itself.
@@ -951,12 +953,15 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     // the gate's parameters: read in the gate phase from LDS, so that the job
     // loop does not hold them in scalar registers
     __shared__ double sh_m[8];
+    __shared__ double sh_rm[LIST == 3 ? kMaxRun : 1][8];   // fused run: the gates' matrices
+    __shared__ uint32_t sh_rsub[2][WGS / 64];              // fused run: subnormal flags, alternating per gate
 
     DevState *ds = P.ds;
     if (DST == DST_ARENA && ds->stop) return;
 
     const int tid = threadIdx.x, s = tid / G, lt = tid % G;
     if (GATE && tid < 8) sh_m[tid] = gd.m[tid];   // first read after the first job's fetch barrier
+    if (LIST == 3 && tid < 8 * io.nrun) sh_rm[tid >> 3][tid & 7] = io.run[tid >> 3].m[tid & 7];
     uint32_t unit_mask = 0;                        // phases equal to 1 (diagonal gates)
     if (GATE)
         for (int i = 0; i < 4; ++i) unit_mask |= unit_phase(gd.m[2 * i], gd.m[2 * i + 1]) ? (1u << i) : 0u;
@@ -979,11 +984,11 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     double mom_re = 0.0, mom_im = 0.0, mom_n2 = 0.0;
 
     const uint64_t jstop = job_stop(gd);
-    __shared__ uint32_t sh_role[LIST != 0 ? 256 : 1];
+    __shared__ uint32_t sh_role[(LIST == 1 || LIST == 2) ? 256 : 1];
     uint32_t kjob = 0;   // iterations of this workgroup's job loop
     for (uint64_t job = job_begin(gd) + blockIdx.x; job < jstop; job += gridDim.x, ++kjob) {
         uint32_t rjob = 0;
-        if (LIST != 0) {
+        if (LIST == 1 || LIST == 2) {
             if ((kjob & 255u) == 0u) {   // the roles of this workgroup's next 256 jobs, in one batch
                 lds_barrier();
                 const uint64_t jj = job + (uint64_t)tid * gridDim.x;
@@ -1044,16 +1049,57 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             double x[V];
 #pragma unroll
             for (int k = 0; k < V; ++k) x[k] = u2d(((uint64_t)th[k] << 32) | tl[k]);
-            // 3a. a gate each thread applies to its own values (no LDS pass)
-            if (GATE && gate_in_registers<V>(gd) && use)
+            if (LIST == 3) {
+                // 3r. the run: each gate (in registers or through LDS), then the
+                // truncation re-encoding would apply (none when the chunk holds
+                // a subnormal value), so the one encode below equals the last of
+                // the gate-by-gate encodes
+                const uint64_t base = (c << P.cb) | (uint64_t)(first / 2);
+                const uint32_t mh = sig_mask_hi(sig_bits(glevel));
+                for (int g = 0; g < io.nrun; ++g) {
+                    const GateDesc &rg = io.run[g];
+                    if (gate_in_registers<V>(rg)) {
+                        if (use) apply_gate_registers<V>(rg, sh_rm[g], x, base);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
+                        lds_barrier();
+                        apply_gate(rg, sh_rm[g], reinterpret_cast<double *>(buf[0]),
+                                   reinterpret_cast<double *>(buf[1]), cc0, cc1, use0, use1, P.cb, WGS);
+                        lds_barrier();
+#pragma unroll
+                        for (int k = 0; k < V; ++k) x[k] = vals[vpos(first + k)];
+                    }
+                    if (glevel > 0) {
+                        bool sub = false;
+#pragma unroll
+                        for (int k = 0; k < V; ++k) {
+                            const uint64_t u = d2u(x[k]);
+                            sub = sub || subnormal((uint32_t)(u >> 32), (uint32_t)u);
+                        }
+                        const bool wsub = __any(use && sub);
+                        if ((tid & 63) == 0) sh_rsub[g & 1][tid >> 6] = wsub ? 1u : 0u;
+                        lds_barrier();
+                        uint32_t gs = 0;
+#pragma unroll
+                        for (int i = 0; i < WPG; ++i) gs |= sh_rsub[g & 1][s * WPG + i];
+                        if (gs == 0) {
+#pragma unroll
+                            for (int k = 0; k < V; ++k) x[k] = u2d((uint64_t)((uint32_t)(d2u(x[k]) >> 32) & mh) << 32);
+                        }
+                    }
+                }
+            } else if (GATE && gate_in_registers<V>(gd) && use) {
+                // 3a. a gate each thread applies to its own values (no LDS pass)
                 apply_gate_registers<V>(gd, sh_m, x, (c << P.cb) | (uint64_t)(first / 2));
+            }
 #pragma unroll
             for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
             lds_barrier();
         }
 
         // 3. gate (pairs across threads or slots, in LDS)
-        if (GATE && !gate_in_registers<V>(gd)) {
+        if (GATE && LIST != 3 && !gate_in_registers<V>(gd)) {
             apply_gate(gd, sh_m, reinterpret_cast<double *>(buf[0]), reinterpret_cast<double *>(buf[1]), cc0, cc1, use0,
                        use1, P.cb, WGS);
             lds_barrier();
@@ -1855,6 +1901,35 @@ static void launch_list_v(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io
         hipLaunchKernelGGL((job_kernel<V, 2, SRC_ARENA, DST_ARENA, true, 1>), dim3(grid), dim3(256), 0, st, gd, P, io);
     else
         hipLaunchKernelGGL((job_kernel<V, 2, SRC_ARENA, DST_ARENA, true, 2>), dim3(grid), dim3(256), 0, st, gd, P, io);
+}
+
+template <int V>
+static void launch_run_v(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st,
+                         hipEvent_t t0, hipEvent_t t1)
+{
+    if (t0)
+        hipExtLaunchKernelGGL((job_kernel<V, 2, SRC_ARENA, DST_ARENA, true, 3>), dim3(grid), dim3(256), 0, st, t0, t1,
+                              0, gd, P, io);
+    else
+        hipLaunchKernelGGL((job_kernel<V, 2, SRC_ARENA, DST_ARENA, true, 3>), dim3(grid), dim3(256), 0, st, gd, P, io);
+}
+
+hipError_t launch_gate_run(const GateDesc &gd, const DevPtrs &P, const GateDesc *run, int nrun, int grid,
+                           hipStream_t st, hipEvent_t t0, hipEvent_t t1)
+{
+    if (nrun < 1 || nrun > kMaxRun || grid < 1 || P.C % 128) return hipErrorInvalidValue;
+    IOPtrs io = {};
+    io.run = run;
+    io.nrun = nrun;
+    switch (P.C / 128) {
+    case 1: launch_run_v<1>(gd, P, io, grid, st, t0, t1); break;
+    case 2: launch_run_v<2>(gd, P, io, grid, st, t0, t1); break;
+    case 4: launch_run_v<4>(gd, P, io, grid, st, t0, t1); break;
+    case 8: launch_run_v<8>(gd, P, io, grid, st, t0, t1); break;
+    case 16: launch_run_v<16>(gd, P, io, grid, st, t0, t1); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_gate_list(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, int list, int grid,

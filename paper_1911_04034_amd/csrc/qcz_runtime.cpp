@@ -45,7 +45,7 @@ struct GraphEntry {
 
 struct Layout {
     size_t ds, table, undo, bsums, blevel, partials, wgp, scratch, cstats, feat, fn2, fsel, ckeys, cowner, crole,
-        cparts, cjkey, arena0, arena1, arena_bytes, end;
+        cparts, cjkey, rundesc, arena0, arena1, arena_bytes, end;
     uint64_t ctsize;   // block cache key slots (0: no cache)
 };
 
@@ -54,7 +54,7 @@ constexpr uint64_t kStatChunks = 65536;
 
 int chunk_log2_for(int bl) { return bl < 10 ? bl : 10; }
 
-Layout layout_for(int n, int bl, size_t pool_bytes, bool cache)
+Layout layout_for(int n, int bl, size_t pool_bytes, bool cache, bool fuse)
 {
     const int cb = chunk_log2_for(bl);
     const int C = 2 << cb;
@@ -82,6 +82,7 @@ Layout layout_for(int n, int bl, size_t pool_bytes, bool cache)
     L.crole = o; o = align256(o + 4 * (size_t)(cache ? std::max<uint64_t>(1, nchunks / 2) : 0));
     L.cparts = o; o = align256(o + (cache ? sizeof(WgPart) * (size_t)kCopyGrid : 0));
     L.cjkey = o; o = align256(o + 8 * (size_t)(cache ? std::max<uint64_t>(1, nchunks / 2) : 0));
+    L.rundesc = o; o = align256(o + (fuse ? sizeof(GateDesc) * (size_t)kMaxBatch : 0));
     L.end = o;
     size_t rest = pool_bytes > o ? pool_bytes - o : 0;
     L.arena_bytes = (rest / 2) & ~(size_t)255;
@@ -145,6 +146,9 @@ struct qcz_state {
     uint64_t cache_key_mask = ~0ull;
     uint32_t cache_idle = 0;          // consecutive cached gates without a hit
     std::vector<uint8_t> cached;      // per gate of the batch: 1 if it ran through the cache
+    // gate-layer fusion (QCZ_FLAG_FUSE): per gate of the batch, the first and
+    // last gate of its fused run (-1: not in a run)
+    std::vector<int> run_first, run_last;
 };
 
 namespace {
@@ -412,6 +416,17 @@ qcz_status launch_one(qcz_state *s, const GateDesc &d, bool timing)
     return QCZ_OK;
 }
 
+// Gates a fused run may hold: in-chunk single-qubit gates with no control on
+// a chunk-index bit touch every chunk, in modes whose level does not depend on
+// the compressed size after each gate.
+bool fusable(const qcz_state *s, const GateDesc &d)
+{
+    return (s->cfg.flags & QCZ_FLAG_FUSE) && !s->cache_on && d.job_type == J_SINGLE &&
+           (d.kind == K_U1 || d.kind == K_X) && d.q < s->cb && (d.cm >> s->cb) == 0 && !d.per_block &&
+           d.job_end == 0 && d.nitems == s->nchunks &&
+           (s->cfg.mode == QCZ_MODE_FIXED || s->cfg.mode == QCZ_MODE_LOSSLESS);
+}
+
 qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
 {
     const bool timing = (s->cfg.flags & QCZ_FLAG_TIMING) != 0 || s->tuning;
@@ -424,11 +439,37 @@ qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
         s->timed.assign(descs.size(), 0);
     }
     s->cached.assign(descs.size(), 0);
+    s->run_first.assign(descs.size(), -1);
+    s->run_last.assign(descs.size(), -1);
     if (timing || !(s->cfg.flags & QCZ_FLAG_GRAPH) || s->stream == nullptr) {
-        for (const auto &d : descs) {
-            qcz_status st = launch_one(s, d, timing);
+        GateDesc *dev_descs = (GateDesc *)(s->pool + s->lay.rundesc);
+        bool uploaded = false;
+        for (size_t k = 0; k < descs.size();) {
+            size_t r = 0;
+            while (k + r < descs.size() && r < (size_t)kMaxRun && fusable(s, descs[k + r])) ++r;
+            if (r >= 2) {
+                if (!uploaded) {   // the batch's gate records, read by the fused runs
+                    HIPCHK(s, hipMemcpyAsync(dev_descs, descs.data(), descs.size() * sizeof(GateDesc),
+                                             hipMemcpyHostToDevice, s->stream));
+                    uploaded = true;
+                }
+                const GateDesc &d = descs[k];
+                hipEvent_t t0 = timing ? s->events[2 * d.seq] : nullptr, t1 = timing ? s->events[2 * d.seq + 1] : nullptr;
+                hipError_t e = launch_gate_run(d, ptrs(s), dev_descs + k, (int)r, grid_for(s, d), s->stream, t0, t1);
+                if (e != hipSuccess) return fail(s, QCZ_E_DEVICE, std::string("fused run launch: ") + hipGetErrorString(e));
+                if (timing) s->timed[k] = 1;
+                for (size_t j = k; j < k + r; ++j) {
+                    s->run_first[j] = (int)k;
+                    s->run_last[j] = (int)(k + r - 1);
+                }
+                k += r;
+                continue;
+            }
+            qcz_status st = launch_one(s, descs[k], timing);
             if (st != QCZ_OK) return st;
+            ++k;
         }
+        if (uploaded) HIPCHK(s, hipStreamSynchronize(s->stream));   // the host records may change after return
         return QCZ_OK;
     }
     std::vector<uint8_t> key(descs.size() * sizeof(GateDesc) + sizeof(DevPtrs) + 1);
@@ -468,7 +509,7 @@ qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
     return QCZ_OK;
 }
 
-void commit_gate(qcz_state *s, const GateLog &lg, const GateDesc &d, int k)
+void commit_gate(qcz_state *s, const GateLog &lg, const GateDesc &d, int k, bool tbl = true)
 {
     s->live = lg.live;
     s->bump = lg.bump;
@@ -482,7 +523,7 @@ void commit_gate(qcz_state *s, const GateLog &lg, const GateDesc &d, int k)
         S.amps_touched += lg.reenc * (uint64_t)(s->C / 2);
         S.bytes_read += lg.rd;
         S.bytes_written += lg.wr;
-        S.table_bytes += 24 * lg.reenc;
+        if (tbl) S.table_bytes += 24 * lg.reenc;
         if (k < (int)s->cached.size() && s->cached[(size_t)k]) {
             // Sec. 3.4: the cache is switched off when it keeps missing
             S.cache_gates += 1;
@@ -520,6 +561,23 @@ void commit_gate(qcz_state *s, const GateLog &lg, const GateDesc &d, int k)
     }
     s->min_c = std::min(s->min_c, s->live);
     s->max_c = std::max(s->max_c, s->live);
+}
+
+// Commit gate k of a batch from the device log.  A gate of a fused run takes
+// the run's log (one pass re-encoded every chunk once per gate of the run, in
+// effect): the chunks and live bytes after the run, its stream bytes and
+// table traffic counted once, on the run's last gate.
+void commit_logged(qcz_state *s, const DevState &h, const GateDesc &d, int k)
+{
+    const int f = k < (int)s->run_first.size() ? s->run_first[(size_t)k] : -1;
+    if (f < 0) {
+        commit_gate(s, h.log[k], d, k);
+        return;
+    }
+    GateLog lg = h.log[f];
+    const bool last = k == s->run_last[(size_t)k];
+    if (!last) lg.rd = lg.wr = 0;
+    commit_gate(s, lg, d, k, last);
 }
 
 // Move the autotuner to its next candidate; after kTuneRounds passes over
@@ -848,7 +906,8 @@ size_t qcz_pool_bytes_min(const qcz_config *cfg)
 {
     if (!cfg || cfg->n_qubits < 6 || cfg->n_qubits > 40 || cfg->block_log2 < 6 || cfg->block_log2 > cfg->n_qubits)
         return 0;
-    Layout L = layout_for((int)cfg->n_qubits, (int)cfg->block_log2, 0, (cfg->flags & QCZ_FLAG_CACHE) != 0);
+    Layout L = layout_for((int)cfg->n_qubits, (int)cfg->block_log2, 0, (cfg->flags & QCZ_FLAG_CACHE) != 0,
+                          (cfg->flags & QCZ_FLAG_FUSE) != 0);
     const int cb = chunk_log2_for((int)cfg->block_log2);
     const uint64_t nchunks = 1ull << (cfg->n_qubits - cb);
     // two arenas, each holding the initial streams with room to spare
@@ -867,7 +926,7 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
     if (cfg->chunk_waves != 0 && cfg->chunk_waves != 2 && cfg->chunk_waves != 4 && cfg->chunk_waves != 8)
         return QCZ_E_INVAL;
     if (((uintptr_t)dev_pool & 255) != 0) return QCZ_E_INVAL;
-    if ((cfg->flags & QCZ_FLAG_CACHE) && (cfg->flags & QCZ_FLAG_AUTOTUNE)) return QCZ_E_INVAL;
+    if ((cfg->flags & (QCZ_FLAG_CACHE | QCZ_FLAG_FUSE)) && (cfg->flags & QCZ_FLAG_AUTOTUNE)) return QCZ_E_INVAL;
     if (pool_bytes < qcz_pool_bytes_min(cfg)) return QCZ_E_NOMEM;
 
     qcz_state *s = new qcz_state();
@@ -880,7 +939,7 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
     s->nblocks = 1ull << (s->n - s->bl);
     s->pool = (uint8_t *)dev_pool;
     s->pool_bytes = pool_bytes;
-    s->lay = layout_for(s->n, s->bl, pool_bytes, (cfg->flags & QCZ_FLAG_CACHE) != 0);
+    s->lay = layout_for(s->n, s->bl, pool_bytes, (cfg->flags & QCZ_FLAG_CACHE) != 0, (cfg->flags & QCZ_FLAG_FUSE) != 0);
     s->ds = (DevState *)(s->pool + s->lay.ds);
     s->table = (uint64_t *)(s->pool + s->lay.table);
     s->undo = (uint64_t *)(s->pool + s->lay.undo);
@@ -1039,7 +1098,7 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
         const DevState &h = s->hds;
         for (int k = 0; k < kStripes; ++k) s->stripe_fill[k] = h.stripe[k][0];
         if (!h.stop) {
-            for (size_t k = 0; k < B; ++k) commit_gate(s, h.log[k], descs[k], (int)k);
+            for (size_t k = 0; k < B; ++k) commit_logged(s, h, descs[k], (int)k);
             idx += B;
             s->sel_since += B;
             if (applied) *applied = idx;
@@ -1049,7 +1108,7 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
         const int sseq = h.stop_seq;
         const int reason = h.stop_reason;
         s->stats.stops += 1;
-        for (int k = 0; k < sseq; ++k) commit_gate(s, h.log[k], descs[(size_t)k], k);
+        for (int k = 0; k < sseq; ++k) commit_logged(s, h, descs[(size_t)k], k);
         s->sel_since += (uint64_t)sseq;
         // undo the stopped gate
         const GateDesc &dstop = descs[(size_t)sseq];

@@ -22,6 +22,7 @@ FLAG_AUTOTUNE = 4
 FLAG_RANGES = 8
 FLAG_CACHE = 16
 FLAG_CACHE_COLLIDE = 32
+FLAG_FUSE = 64
 STATUS = {0: "QCZ_OK", -1: "QCZ_E_INVAL", -2: "QCZ_E_NOMEM", -3: "QCZ_E_DEVICE", -4: "QCZ_E_FORMAT",
           -5: "QCZ_E_STATE"}
 
