@@ -22,9 +22,11 @@ Prints one JSON line:
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -395,6 +397,31 @@ def main():
                     "avg_launch_us": round(avg_ms * 1e3, 3), "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
                     "launches": timed, "valu_busy_per_simd": valu_busy}
 
+    # The default run also reports the same workload with gate-layer fusion
+    # (same bytes and fidelities; a separate figure, the headline stays gate
+    # by gate).  It runs in a child process after this one's states are freed;
+    # profiling commands pass --no-cpu-baseline and skip it.
+    fused = None
+    if (not args.no_cpu_baseline and args.workload == "grover24+qft24" and not (args.fuse or args.cache)
+            and not args.no_timing):
+        grover = qft_states = None
+        gc.collect()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        log("fused-run figure: child process")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--fuse", "--no-cpu-baseline",
+                            "--steps", str(args.steps), "--warmup", str(args.warmup)],
+                           stdout=subprocess.PIPE, text=True, timeout=900)
+        lines = [x for x in r.stdout.splitlines() if x.startswith("{")]
+        if r.returncode == 0 and lines:
+            f = json.loads(lines[-1])
+            fused = {"value": f["value"], "unit": "GAmp/s", "ms_per_step": f["ms_per_step"],
+                     "fused_kernel_gamp_s": f["fused_kernel_gamp_s"], "kernels": f["roofline"]["launches"],
+                     "avg_kernel_us": f["roofline"]["avg_launch_us"], "fidelity_min": f["fidelity_min"],
+                     "command": "bench.py --fuse --steps %d --warmup %d" % (args.steps, args.warmup)}
+        else:
+            log("fused-run figure failed (status %d)" % r.returncode)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_seconds)
@@ -416,6 +443,8 @@ def main():
         "compactions": compactions,
         "workloads": out_extra,
     }
+    if fused is not None:
+        line["fused_runs"] = fused
     if args.fuse:
         line["config"]["fused_runs"] = True
         line["roofline"]["kernel"] = "job_kernel fused runs of in-chunk gates + per-gate fused kernels"
