@@ -132,7 +132,7 @@ def large_config(args, torch, cc, qcz):
         gates = cc.qaoa(n, 4, 3, 5)[0]
         level, mode = 2, qcz.MODE_FIXED
         pool = min(250 << 30, free - (12 << 30))
-    flags = qcz.FLAG_TIMING | qcz.FLAG_RANGES
+    flags = qcz.FLAG_TIMING | qcz.FLAG_RANGES | (qcz.FLAG_FUSE if args.fuse else 0)
     slice_len = 16 if args.workload == "qaoa34" else 64
     walls, stats, st, trace = [], [], None, []
     for p in range(args.warmup + args.steps):
@@ -207,6 +207,9 @@ def large_config(args, torch, cc, qcz):
         fid.update({"fidelity_raw": f_raw, "fidelity_norm": f_raw / nrm, "marked_probability": aw ** 2})
     avg_ms = kms / timed if timed else 0.0
     per_launch = byts / launches if launches else 0.0
+    if args.fuse:   # a fused run is one kernel for several gates
+        kernels = timed + sum(x["range_gates"] for x in stats)
+        per_launch = byts / kernels if kernels else 0.0
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     line = {
         "metric": METRIC, "value": round(amps / wall / 1e9, 4), "unit": "GAmp/s", "n_gpus": 1, "steps": args.steps,
@@ -214,7 +217,7 @@ def large_config(args, torch, cc, qcz):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "qubits": n, "block_amplitudes": 1 << bl,
                    "gates": int(len(gates)), "final_level": fp["level"], "budget_bytes": budget,
-                   "pool_bytes": int(pool), "parallelism": "single GPU"},
+                   "pool_bytes": int(pool), "parallelism": "single GPU", "fused_runs": bool(args.fuse)},
         "compression_ratio_min": round(fp["raw_bytes"] / (fp["max_compressed"] + fp["table_bytes"]), 3),
         "compression_ratio_final": round(fp["ratio"], 3),
         "peak_compressed_bytes": fp["max_compressed"],
