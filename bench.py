@@ -196,12 +196,15 @@ def large_config(args, torch, cc, qcz):
     wall = sum(walls)
     fid = {"fidelity_lower_bound": fp["fidelity_lower_bound"]}
     if args.workload == "grid30":
-        from paper_1911_04034_amd import reference as ref
-        log("dense fp64 reference run")
-        psi = ref.run(gates, n)
-        ov, n2 = ref.overlap_with_compressed(psi, st)
+        # the uncompressed fp64 reference: the same circuit in lossless mode (every stored value is the exact
+        # fp64 result of the gate arithmetic), compared through qcz_overlap (Eq. (9))
+        log("lossless fp64 reference run")
+        ex = qcz.State(n, bl, mode=qcz.MODE_LOSSLESS, pool_bytes=40 << 30, flags=qcz.FLAG_RANGES, batch=128)
+        ex.apply(gates)
+        ov = st.overlap(ex)
+        n2 = st.moments()[1]
         fid.update({"fidelity_raw": abs(ov), "fidelity_norm": abs(ov) / math.sqrt(n2)})
-        del psi
+        ex.close()
     elif args.workload == "grover34":
         f_raw, nrm, aw = grover_fidelity(st, n, w, 8)
         fid.update({"fidelity_raw": f_raw, "fidelity_norm": f_raw / nrm, "marked_probability": aw ** 2})

@@ -182,7 +182,12 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
  * number.  Records are validated first: QCZ_E_INVAL applies nothing. */
 qcz_status qcz_apply_gates(qcz_state *st, const qcz_gate *gates, size_t n_gates, size_t *applied);
 
-/* Amplitudes at the k indices idx[] into out_re_im[2k] (host). */
+/* Readout of the state the simulator holds (the amplitudes a_i of Sec. 2.1,
+ * Eq. (3), as decompressed from the stored chunks; a full-state simulator
+ * gives access to every amplitude at any point of the circuit, Sec. 2.2).  Amplitudes at the k indices idx[]
+ * (host, each < 2^n; QCZ_E_INVAL otherwise, nothing written) into
+ * out_re_im[2k] (host, re then im per index).  Decompression only: the state
+ * is not changed. */
 qcz_status qcz_read_amplitudes(qcz_state *st, const uint64_t *idx, size_t k, double *out_re_im);
 
 /* Decode chunks [first_chunk, first_chunk + n_chunks) into device memory
@@ -194,8 +199,11 @@ qcz_status qcz_decode_chunks_to(qcz_state *st, uint64_t first_chunk, uint64_t n_
  * configuration). */
 qcz_status qcz_moments(qcz_state *st, double out[3]);
 
-/* Draw `shots` basis indices (host out_idx) with probability
- * |a_i|^2 / sum |a|^2 without collapsing the state.  Shot k uses
+/* Measurement in the computational basis (Sec. 2.1: |a_i|^2 of Eq. (3) is the
+ * probability of outcome i, and they sum to 1, Eq. (4)), without collapsing
+ * the state.
+ * Draw `shots` basis indices (host out_idx) with probability
+ * |a_i|^2 / sum |a|^2.  Shot k uses
  * u_k = (SplitMix64 output k for state `seed`) >> 11, times 2^-53, and
  * t = u_k * (sum over chunks of their squared norms, in chunk order): the
  * chunk is the first whose running norm exceeds t, the amplitude the first
@@ -203,8 +211,10 @@ qcz_status qcz_moments(qcz_state *st, double out[3]);
  * nonzero one if rounding runs past the end).  QCZ_E_STATE for a zero state. */
 qcz_status qcz_sample(qcz_state *st, uint64_t seed, size_t shots, uint64_t *out_idx);
 
-/* <a|b> = sum_i conj(a_i) b_i over the decoded states (host outputs); a and
- * b have the same qubit count and chunk size.  Work runs on a's stream after
+/* Overlap of two compressed states, the quantity of the fidelity definition
+ * of Sec. 3.8, Eq. (9): <a|b> = sum_i conj(a_i) b_i over the decoded states
+ * (host outputs); a and b have the same qubit count and chunk size
+ * (QCZ_E_INVAL otherwise).  Work runs on a's stream after
  * b's stream is drained; a's and b's scratch areas are used. */
 qcz_status qcz_overlap(qcz_state *a, qcz_state *b, double *out_re, double *out_im);
 
@@ -236,8 +246,11 @@ qcz_status qcz_import_chunk(qcz_state *st, uint64_t chunk, const void *host_buf,
  * QCZ_E_INVAL if cap < *total.  Import: replace every chunk of `st` by the
  * streams of such an image (len = its total, sizes as exported); the streams'
  * headers are checked first (QCZ_E_FORMAT, state unchanged), QCZ_E_NOMEM if
- * the image exceeds one arena.  The ledger is not part of the image: restore
- * it with qcz_resume. */
+ * the image exceeds one arena.  The ledger is not part of the image: an import
+ * starts a fresh one (no gates applied, bound 1, the configuration's level;
+ * QCZ_MODE_PERBLOCK: the squared norm of the imported state) and makes a state
+ * left invalid by a failed ranged gate usable again; qcz_resume restores a
+ * saved ledger. */
 qcz_status qcz_export_state(qcz_state *st, void *host_buf, size_t cap, uint32_t *sizes, size_t *total);
 qcz_status qcz_import_state(qcz_state *st, const void *host_buf, size_t len, const uint32_t *sizes);
 

@@ -230,9 +230,386 @@ static size_t pack_body_read(const uint8_t *in, size_t avail, int N, int K, uint
     return codes_bytes + (size_t)((rpos + 7) / 8);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Entropy stage (the entropy-coding role of Zstd in Solution C, Sec. 4.2).  */
+/*                                                                            */
+/* A PACK or SPARSE body may carry its residuals entropy-coded; header bit 5  */
+/* (E) says so.  The residual of value i (its significant prefix after the    */
+/* L_i leading bytes it shares with the previous value) is cut into 4-bit     */
+/* lanes: lane j holds bits [64-4j-w_j, 64-4j) of the value, w_j =            */
+/* min(4, K-4j), j = 0 .. NN-1 with NN = ceil(K/4); value i codes the lanes   */
+/* j >= 2 L_i (the lanes of its shared bytes are copied from the previous     */
+/* value).  Each lane has its own code:                                       */
+/*   RAW   (0): the w_j-bit symbol as a field;                                */
+/*   CONST (1): every symbol of the lane is one value, stored once in the     */
+/*              table; nothing per value;                                     */
+/*   CODED (2): a canonical Huffman code (Huffman 1952) over the lane's        */
+/*              2^w_j symbols, code lengths limited to 8 bits.                */
+/* E body, after the codes area of the PACK / SPARSE body:                   */
+/*   u32 lane word: mode of lane j at bits 2j..2j+1 (0 for j >= NN);          */
+/*   table: a 4-bit-nibble sequence (nibble k at bits 4(k%2) of byte k/2):    */
+/*          for each lane in order, CONST: its symbol; CODED: the code length */
+/*          (0 = symbol absent) of each of its 2^w_j symbols; zero-padded to  */
+/*          a multiple of 4 bytes;                                            */
+/*   sub-stream lengths: ceil(C/16) fields of 12 bits, LSB first: field s is  */
+/*          the bit length of sub-stream s; zero-padded to 4 bytes;          */
+/*   bit stream, LSB first: sub-streams 0, 1, ... back to back; sub-stream s  */
+/*          holds the coded lanes of the stored values at chunk positions     */
+/*          16s .. 16s+15, value by value in position order, lanes in         */
+/*          increasing j.  A RAW symbol is a w_j-bit field; a CODED symbol is */
+/*          its canonical code written first bit first (bit-reversed into the */
+/*          LSB-first stream); zero-padded to a byte.                         */
+/* Lane choice (encoder), from the lane's n_j symbols and their counts:       */
+/*   RAW when n_j = 0; CONST when one distinct symbol and 4 < n_j w_j; CODED  */
+/*   when at least two distinct symbols, the most frequent one has at least   */
+/*   twice the uniform share (max count * 2^w_j >= 2 n_j) and                 */
+/*   4 * 2^w_j + sum(count * length) < n_j w_j; otherwise RAW.               */
+/* Chunk choice: CONST2 when it applies; else the smaller of PACK and SPARSE  */
+/* (PACK on a tie) as before; with the entropy stage enabled, that body is    */
+/* entropy-coded when the result is strictly smaller.                         */
+/* ------------------------------------------------------------------------- */
+#define OQ_HDR_ENT 0x20u
+#define OQ_ENC_ENTROPY 1    /* consider the entropy-coded body */
+#define OQ_ENC_FORCE_ENT 2  /* test hook: always entropy-code the PACK / SPARSE body */
+#define OQ_ENC_FORCE_CODED 4 /* test hook (with OQ_ENC_FORCE_ENT): every lane with two or more distinct
+                                symbols CODED, with one CONST, without the cost comparisons */
+#define OQ_HUFF_MAXLEN 8
+enum { OQ_LANE_RAW = 0, OQ_LANE_CONST = 1, OQ_LANE_CODED = 2 };
+
+static int nib_lanes(int K) { return (K + 3) / 4; }
+static int lane_width(int K, int j) { int w = K - 4 * j; return w < 4 ? w : 4; }
+static unsigned lane_symbol(uint64_t t, int K, int j)
+{
+    int w = lane_width(K, j);
+    return (unsigned)((t >> (64 - 4 * j - w)) & ((1u << w) - 1u));
+}
+
+/* Huffman code lengths (Huffman 1952) for the symbols with cnt > 0 (at least
+ * two of them).  Leaves in increasing (count, symbol) order; internal nodes in
+ * creation order form a second queue whose weights never decrease, so each
+ * step joins the two smallest heads, taking the leaf when a leaf and a node
+ * weigh the same.  A code length is the depth of the leaf.  Lengths above
+ * OQ_HUFF_MAXLEN are cut to it, then, while the Kraft sum exceeds 1, the
+ * longest code below the limit (fewest occurrences, then lowest symbol, on
+ * ties) is made one bit longer. */
+static void huff_lengths(const uint32_t *cnt, int nsym, uint8_t *len)
+{
+    int leaf[16], nl = 0;
+    for (int sy = 0; sy < nsym; ++sy) {
+        len[sy] = 0;
+        if (cnt[sy] > 0) leaf[nl++] = sy;
+    }
+    for (int a = 1; a < nl; ++a) {          /* insertion sort by (count, symbol) */
+        int v = leaf[a], b = a - 1;
+        while (b >= 0 && (cnt[leaf[b]] > cnt[v] || (cnt[leaf[b]] == cnt[v] && leaf[b] > v))) {
+            leaf[b + 1] = leaf[b];
+            --b;
+        }
+        leaf[b + 1] = v;
+    }
+    uint64_t w[32];
+    int parent[32], depth[32];
+    for (int i = 0; i < nl; ++i) w[i] = cnt[leaf[i]];
+    int nextleaf = 0, nextnode = nl, nn = nl;
+    while (nn < 2 * nl - 1) {
+        int pick[2];
+        for (int k = 0; k < 2; ++k) {
+            int take_leaf;
+            if (nextleaf < nl && nextnode < nn) take_leaf = w[nextleaf] <= w[nextnode];
+            else take_leaf = nextleaf < nl;
+            pick[k] = take_leaf ? nextleaf++ : nextnode++;
+        }
+        w[nn] = w[pick[0]] + w[pick[1]];
+        parent[pick[0]] = nn;
+        parent[pick[1]] = nn;
+        ++nn;
+    }
+    depth[nn - 1] = 0;
+    for (int i = nn - 2; i >= 0; --i) depth[i] = depth[parent[i]] + 1;
+    int maxl = 0;
+    for (int i = 0; i < nl; ++i) {
+        len[leaf[i]] = (uint8_t)depth[i];
+        if (depth[i] > maxl) maxl = depth[i];
+    }
+    if (maxl <= OQ_HUFF_MAXLEN) return;
+    for (int sy = 0; sy < nsym; ++sy)
+        if (len[sy] > OQ_HUFF_MAXLEN) len[sy] = OQ_HUFF_MAXLEN;
+    for (;;) {
+        uint32_t kraft = 0;   /* in units of 2^-8 */
+        for (int sy = 0; sy < nsym; ++sy)
+            if (len[sy]) kraft += 1u << (OQ_HUFF_MAXLEN - len[sy]);
+        if (kraft <= (1u << OQ_HUFF_MAXLEN)) break;
+        int best = -1;
+        for (int sy = 0; sy < nsym; ++sy) {
+            if (!len[sy] || len[sy] >= OQ_HUFF_MAXLEN) continue;
+            if (best < 0 || len[sy] > len[best] || (len[sy] == len[best] && cnt[sy] < cnt[best])) best = sy;
+        }
+        len[best] += 1;
+    }
+}
+
+/* Canonical codes for lengths len[] (0 = absent): symbols in increasing
+ * (length, symbol) order take consecutive codes, each shifted left by the
+ * growth of the length (the first takes 0). */
+static void canon_codes(const uint8_t *len, int nsym, uint32_t *code)
+{
+    uint32_t c = 0;
+    int prev = 0, first = 1;
+    for (int l = 1; l <= OQ_HUFF_MAXLEN; ++l)
+        for (int sy = 0; sy < nsym; ++sy) {
+            if (len[sy] != l) continue;
+            if (first) { c = 0; first = 0; }
+            else c = (c + 1) << (l - prev);
+            code[sy] = c;
+            prev = l;
+        }
+}
+
+static uint32_t bit_reverse(uint32_t v, int n)
+{
+    uint32_t r = 0;
+    for (int k = 0; k < n; ++k) r |= ((v >> k) & 1u) << (n - 1 - k);
+    return r;
+}
+
+typedef struct {
+    int mode;
+    unsigned csym;            /* CONST: the symbol */
+    uint8_t len[16];          /* CODED: code length per symbol */
+    uint32_t code[16];        /* CODED: canonical code per symbol */
+} oq_lane;
+
+/* Two-bit codes of the XOR chain over s[0..N) (the chain starts from 0). */
+static void chain_codes(const uint64_t *s, int N, int *L)
+{
+    uint64_t prev = 0;
+    for (int i = 0; i < N; ++i) {
+        L[i] = lead_bytes(s[i], prev);
+        prev = s[i];
+    }
+}
+
+/* Size of the entropy-coded body over s[0..N) (positions pos[] in a chunk of
+ * C values), and, when out is not NULL, its bytes. */
+static size_t sub_count(int C) { return (size_t)(C + 15) / 16; }
+static size_t sub_area(int C) { return 4 * ((12 * sub_count(C) + 31) / 32); }
+
+static size_t ent_body(const uint64_t *s, const int *pos, int N, int C, int K, int flags, uint8_t *out)
+{
+    int NN = nib_lanes(K);
+    int *L = (int *)malloc(sizeof(int) * (size_t)(N > 0 ? N : 1));
+    chain_codes(s, N, L);
+    uint32_t cnt[16][16];
+    uint32_t nj[16];
+    memset(cnt, 0, sizeof cnt);
+    memset(nj, 0, sizeof nj);
+    for (int i = 0; i < N; ++i)
+        for (int j = 2 * L[i]; j < NN; ++j) {
+            cnt[j][lane_symbol(s[i], K, j)] += 1;
+            nj[j] += 1;
+        }
+    oq_lane lane[16];
+    uint64_t bits = 0, nib = 0;
+    for (int j = 0; j < NN; ++j) {
+        int w = lane_width(K, j), nsym = 1 << w;
+        oq_lane *ln = &lane[j];
+        memset(ln, 0, sizeof *ln);
+        uint64_t raw = (uint64_t)nj[j] * (uint64_t)w;
+        int distinct = 0;
+        uint32_t mx = 0;
+        for (int sy = 0; sy < nsym; ++sy) {
+            if (cnt[j][sy]) { ++distinct; ln->csym = (unsigned)sy; }
+            if (cnt[j][sy] > mx) mx = cnt[j][sy];
+        }
+        ln->mode = OQ_LANE_RAW;
+        uint64_t cost = raw, tab = 0;
+        int forced = (flags & OQ_ENC_FORCE_CODED) != 0;
+        if (nj[j] > 0 && distinct == 1) {
+            if (4 < raw || forced) { ln->mode = OQ_LANE_CONST; cost = 0; tab = 1; }
+        } else if (distinct >= 2 && (forced || (uint64_t)mx * (uint64_t)nsym >= 2ull * nj[j])) {
+            huff_lengths(cnt[j], nsym, ln->len);
+            uint64_t coded = 4ull * (uint64_t)nsym;
+            for (int sy = 0; sy < nsym; ++sy) coded += (uint64_t)cnt[j][sy] * ln->len[sy];
+            if (coded < raw || forced) {
+                ln->mode = OQ_LANE_CODED;
+                canon_codes(ln->len, nsym, ln->code);
+                cost = coded - 4ull * (uint64_t)nsym;
+                tab = (uint64_t)nsym;
+            }
+        }
+        bits += cost;
+        nib += tab;
+    }
+    size_t codes_bytes = 4 * (size_t)((N + 15) / 16);
+    size_t tab_bytes = 4 * (size_t)((nib + 7) / 8);
+    size_t sub_bytes = sub_area(C);
+    size_t size = codes_bytes + 4 + tab_bytes + sub_bytes + (size_t)((bits + 7) / 8);
+    if (out) {
+        uint64_t p = 0;
+        for (int i = 0; i < N; ++i) put_bits(out, &p, (uint64_t)L[i], 2);
+        uint8_t *lw = out + codes_bytes;
+        uint32_t word = 0;
+        for (int j = 0; j < NN; ++j) word |= (uint32_t)lane[j].mode << (2 * j);
+        put_u32(lw, word);
+        uint8_t *tb = lw + 4;
+        uint64_t tp = 0;
+        for (int j = 0; j < NN; ++j) {
+            int nsym = 1 << lane_width(K, j);
+            if (lane[j].mode == OQ_LANE_CONST) put_bits(tb, &tp, lane[j].csym, 4);
+            else if (lane[j].mode == OQ_LANE_CODED)
+                for (int sy = 0; sy < nsym; ++sy) put_bits(tb, &tp, lane[j].len[sy], 4);
+        }
+        uint8_t *sl = tb + tab_bytes;
+        uint8_t *bs = sl + sub_bytes;
+        uint64_t bp = 0, lp = 0;
+        int i = 0;
+        for (int sub = 0; sub < (int)sub_count(C); ++sub) {
+            uint64_t start = bp;
+            while (i < N && pos[i] < 16 * (sub + 1)) {
+                for (int j = 2 * L[i]; j < NN; ++j) {
+                    unsigned sy = lane_symbol(s[i], K, j);
+                    if (lane[j].mode == OQ_LANE_RAW) put_bits(bs, &bp, sy, lane_width(K, j));
+                    else if (lane[j].mode == OQ_LANE_CODED)
+                        put_bits(bs, &bp, bit_reverse(lane[j].code[sy], lane[j].len[sy]), lane[j].len[sy]);
+                }
+                ++i;
+            }
+            put_bits(sl, &lp, bp - start, 12);
+        }
+    }
+    free(L);
+    return size;
+}
+
+/* Read an entropy-coded body of N values at positions pos[] of a chunk of C
+ * values; returns the bytes it occupies, 0 when malformed. */
+static size_t ent_body_read(const uint8_t *in, size_t avail, const int *pos, int N, int C, int K, uint64_t *s)
+{
+    int NN = nib_lanes(K);
+    size_t codes_bytes = 4 * (size_t)((N + 15) / 16);
+    if (codes_bytes + 4 > avail) return 0;
+    uint32_t word = get_u32(in + codes_bytes);
+    oq_lane lane[16];
+    size_t nib = 0;
+    for (int j = 0; j < 16; ++j) {
+        int m = (int)((word >> (2 * j)) & 3u);
+        if (j >= NN) { if (m) return 0; continue; }
+        if (m > OQ_LANE_CODED) return 0;
+        memset(&lane[j], 0, sizeof lane[j]);
+        lane[j].mode = m;
+        nib += m == OQ_LANE_CONST ? 1 : m == OQ_LANE_CODED ? (size_t)1 << lane_width(K, j) : 0;
+    }
+    size_t tab_bytes = 4 * ((nib + 7) / 8);
+    size_t sub_bytes = sub_area(C);
+    size_t head = codes_bytes + 4 + tab_bytes + sub_bytes;
+    if (head > avail) return 0;
+    const uint8_t *tb = in + codes_bytes + 4;
+    uint64_t tp = 0;
+    for (int j = 0; j < NN; ++j) {
+        int nsym = 1 << lane_width(K, j);
+        if (lane[j].mode == OQ_LANE_CONST) {
+            lane[j].csym = (unsigned)get_bits(tb, tp, 4);
+            tp += 4;
+            if (lane[j].csym >= (unsigned)nsym) return 0;
+        } else if (lane[j].mode == OQ_LANE_CODED) {
+            uint32_t kraft = 0;
+            for (int sy = 0; sy < nsym; ++sy) {
+                lane[j].len[sy] = (uint8_t)get_bits(tb, tp, 4);
+                tp += 4;
+                if (lane[j].len[sy] > OQ_HUFF_MAXLEN) return 0;
+                if (lane[j].len[sy]) kraft += 1u << (OQ_HUFF_MAXLEN - lane[j].len[sy]);
+            }
+            if (kraft == 0 || kraft > (1u << OQ_HUFF_MAXLEN)) return 0;
+            canon_codes(lane[j].len, nsym, lane[j].code);
+        }
+    }
+    const uint8_t *sl = in + codes_bytes + 4 + tab_bytes;
+    const uint8_t *bs = sl + sub_bytes;
+    size_t bs_avail = avail - head;
+    uint64_t bp = 0, prev = 0;
+    int i = 0;
+    for (int sub = 0; sub < (int)sub_count(C); ++sub) {
+        uint64_t want = get_bits(sl, 12 * (uint64_t)sub, 12), start = bp;
+        while (i < N && pos[i] < 16 * (sub + 1)) {
+            int Li = (int)get_bits(in, 2 * (uint64_t)i, 2);
+            uint64_t v = prev & top_mask(8 * Li);
+            for (int j = 2 * Li; j < NN; ++j) {
+                int w = lane_width(K, j);
+                unsigned sy;
+                if (lane[j].mode == OQ_LANE_RAW) {
+                    if ((bp + (uint64_t)w + 7) / 8 > bs_avail) return 0;
+                    sy = (unsigned)get_bits(bs, bp, w);
+                    bp += (uint64_t)w;
+                } else if (lane[j].mode == OQ_LANE_CONST) {
+                    sy = lane[j].csym;
+                } else {
+                    /* read the code first bit first until it names a symbol */
+                    uint32_t acc = 0;
+                    int l = 0, found = -1;
+                    while (found < 0) {
+                        if (l == OQ_HUFF_MAXLEN || (bp + 8) / 8 > bs_avail) return 0;
+                        acc = (acc << 1) | (uint32_t)get_bits(bs, bp, 1);
+                        ++bp;
+                        ++l;
+                        for (int t = 0; t < (1 << w); ++t)
+                            if (lane[j].len[t] == l && lane[j].code[t] == acc) { found = t; break; }
+                    }
+                    sy = (unsigned)found;
+                }
+                v |= (uint64_t)sy << (64 - 4 * j - w);
+            }
+            s[i] = v;
+            prev = v;
+            ++i;
+        }
+        if (bp - start != want) return 0;
+    }
+    if (i != N) return 0;
+    return head + (size_t)((bp + 7) / 8);
+}
+
+/* Exported for the pins of the code construction: lengths (0 for absent
+ * symbols) of at least two symbols with counts (nsym <= 16), and canonical
+ * codes for given lengths.  Return -1 on bad arguments. */
+int oq_huff_lengths(const uint32_t *cnt, int nsym, uint8_t *len)
+{
+    int present = 0;
+    if (nsym < 1 || nsym > 16) return -1;
+    for (int sy = 0; sy < nsym; ++sy) present += cnt[sy] > 0;
+    if (present < 2) return -1;
+    huff_lengths(cnt, nsym, len);
+    return 0;
+}
+
+int oq_canon_codes(const uint8_t *len, int nsym, uint32_t *code)
+{
+    if (nsym < 1 || nsym > 16) return -1;
+    for (int sy = 0; sy < nsym; ++sy) {
+        code[sy] = 0;
+        if (len[sy] > OQ_HUFF_MAXLEN) return -1;
+    }
+    canon_codes(len, nsym, code);
+    return 0;
+}
+
+/* Encode one chunk of C doubles at error level `level` with codec flags
+ * (OQ_ENC_*); returns its size.  `out` must hold oq_chunk_cap(C) bytes, or
+ * oq_chunk_cap_forced(C) with OQ_ENC_FORCE_ENT. */
+size_t oq_encode_chunk_ex(const double *x, int C, int level, int flags, uint8_t *out);
+
+size_t oq_chunk_cap_forced(int C)
+{
+    return 4 + 4 * (size_t)((C + 31) / 32) + 4 * (size_t)((C + 15) / 16) + 4 + 128 + sub_area(C) + 16 * (size_t)C;
+}
+
 /* Encode one chunk of C doubles at error level `level`; returns its size.
  * `out` must hold oq_chunk_cap(C) bytes. */
 size_t oq_encode_chunk(const double *x, int C, int level, uint8_t *out)
+{
+    return oq_encode_chunk_ex(x, C, level, 0, out);
+}
+
+size_t oq_encode_chunk_ex(const double *x, int C, int level, int flags, uint8_t *out)
 {
     if (C < 4 || (C & (C - 1)) != 0 || level < 0 || level >= OQ_NLEVELS) return 0;
     int lev = level;
@@ -244,32 +621,49 @@ size_t oq_encode_chunk(const double *x, int C, int level, uint8_t *out)
     uint64_t *nz = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)C);
     for (int i = 0; i < C; ++i) t[i] = oq_truncate_bits(dbits(x[i]), K);
 
-    memset(out, 0, oq_chunk_cap(C));
+    int force = (flags & OQ_ENC_FORCE_ENT) != 0;
+    int hooks = flags & OQ_ENC_FORCE_CODED;
+    memset(out, 0, force ? oq_chunk_cap_forced(C) : oq_chunk_cap(C));
     size_t size;
     int const2 = 1;
     for (int i = 0; i < C; ++i)
         if (t[i] != t[i & 1]) const2 = 0;
-    if (const2) {
+    if (const2 && !force) {
         put_u32(out, (uint32_t)(OQ_MODE_CONST2 | (lev << 2)));
         put_u64(out + 4, t[0]);
         put_u64(out + 12, t[1]);
         size = 20;
     } else {
         int nnz = 0;
-        for (int i = 0; i < C; ++i)
-            if (t[i] != 0) nz[nnz++] = t[i];
+        int *pos = (int *)malloc(sizeof(int) * (size_t)C);
+        int *allpos = (int *)malloc(sizeof(int) * (size_t)C);
+        for (int i = 0; i < C; ++i) {
+            allpos[i] = i;
+            if (t[i] != 0) { pos[nnz] = i; nz[nnz++] = t[i]; }
+        }
         size_t bitmap_bytes = 4 * (size_t)((C + 31) / 32);
         size_t pack_size = 4 + pack_body_size(t, C, K);
         size_t sparse_size = 4 + bitmap_bytes + pack_body_size(nz, nnz, K);
-        if (sparse_size < pack_size) {
-            put_u32(out, (uint32_t)(OQ_MODE_SPARSE | (lev << 2)));
+        int sparse = sparse_size < pack_size;
+        size_t base = sparse ? sparse_size : pack_size;
+        size_t lead = sparse ? 4 + bitmap_bytes : 4;
+        int ent = 0;
+        if (flags & (OQ_ENC_ENTROPY | OQ_ENC_FORCE_ENT)) {
+            size_t esize = lead + (sparse ? ent_body(nz, pos, nnz, C, K, hooks, NULL)
+                                          : ent_body(t, allpos, C, C, K, hooks, NULL));
+            ent = force || esize < base;
+        }
+        uint32_t hdr = (uint32_t)((sparse ? OQ_MODE_SPARSE : OQ_MODE_PACK) | (lev << 2)) | (ent ? OQ_HDR_ENT : 0u);
+        put_u32(out, hdr);
+        if (sparse) {
             uint64_t bpos = 0;
             for (int i = 0; i < C; ++i) put_bits(out + 4, &bpos, t[i] != 0, 1);
-            size = 4 + bitmap_bytes + pack_body_write(nz, nnz, K, out + 4 + bitmap_bytes);
-        } else {
-            put_u32(out, (uint32_t)(OQ_MODE_PACK | (lev << 2)));
-            size = 4 + pack_body_write(t, C, K, out + 4);
         }
+        if (ent) size = lead + (sparse ? ent_body(nz, pos, nnz, C, K, hooks, out + lead)
+                                       : ent_body(t, allpos, C, C, K, hooks, out + lead));
+        else size = lead + (sparse ? pack_body_write(nz, nnz, K, out + lead) : pack_body_write(t, C, K, out + lead));
+        free(pos);
+        free(allpos);
     }
     free(t);
     free(nz);
@@ -281,27 +675,31 @@ int oq_decode_chunk(const uint8_t *in, size_t len, int C, double *x)
 {
     if (C < 4 || (C & (C - 1)) != 0 || len < 4) return -1;
     uint32_t hdr = get_u32(in);
-    int mode = (int)(hdr & 3u), lev = (int)((hdr >> 2) & 7u);
-    if ((hdr >> 5) != 0 || lev >= OQ_NLEVELS) return -1;
+    int mode = (int)(hdr & 3u), lev = (int)((hdr >> 2) & 7u), ent = (hdr & OQ_HDR_ENT) != 0;
+    if ((hdr >> 6) != 0 || lev >= OQ_NLEVELS) return -1;
     int K = oq_sig_bits(lev);
     if (mode == OQ_MODE_CONST2) {
-        if (len != 20) return -1;
+        if (len != 20 || ent) return -1;
         uint64_t t0 = get_u64(in + 4), t1 = get_u64(in + 12);
         for (int i = 0; i < C; ++i) x[i] = bitsd((i & 1) ? t1 : t0);
         return 0;
     }
     uint64_t *s = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)C);
     int rc = 0;
+    int *pos = (int *)malloc(sizeof(int) * (size_t)C);
     if (mode == OQ_MODE_PACK) {
-        size_t used = pack_body_read(in + 4, len - 4, C, K, s);
+        for (int i = 0; i < C; ++i) pos[i] = i;
+        size_t used = ent ? ent_body_read(in + 4, len - 4, pos, C, C, K, s) : pack_body_read(in + 4, len - 4, C, K, s);
         if (used == 0 || used != len - 4) rc = -1;
         else for (int i = 0; i < C; ++i) x[i] = bitsd(s[i]);
     } else if (mode == OQ_MODE_SPARSE) {
         size_t bitmap_bytes = 4 * (size_t)((C + 31) / 32);
-        if (len < 4 + bitmap_bytes) { free(s); return -1; }
+        if (len < 4 + bitmap_bytes) { free(s); free(pos); return -1; }
         int nnz = 0;
-        for (int i = 0; i < C; ++i) nnz += (int)get_bits(in + 4, (uint64_t)i, 1);
-        size_t used = pack_body_read(in + 4 + bitmap_bytes, len - 4 - bitmap_bytes, nnz, K, s);
+        for (int i = 0; i < C; ++i)
+            if (get_bits(in + 4, (uint64_t)i, 1)) pos[nnz++] = i;
+        size_t used = ent ? ent_body_read(in + 4 + bitmap_bytes, len - 4 - bitmap_bytes, pos, nnz, C, K, s)
+                          : pack_body_read(in + 4 + bitmap_bytes, len - 4 - bitmap_bytes, nnz, K, s);
         if (used == 0 || used != len - 4 - bitmap_bytes) rc = -1;
         else {
             int k = 0;
@@ -312,6 +710,7 @@ int oq_decode_chunk(const uint8_t *in, size_t len, int C, double *x)
         rc = -1;
     }
     free(s);
+    free(pos);
     return rc;
 }
 
@@ -493,7 +892,7 @@ static double sum_sq(const double *x, int C)
  * single-chunk job pass in1 = NULL.  If n2 is not NULL, n2[k] receives the
  * squared norm of output chunk k after the update and before truncation, and
  * n2[2 + k] that of the values its new stream holds.  Returns 0 or -1. */
-static int gate_job_n2(const oq_gate *g, int cb, int C,
+static int gate_job_n2(const oq_gate *g, int cb, int C, int flags,
                        uint64_t c0, const uint8_t *in0, size_t len0, int level0, uint8_t *out0, size_t *olen0,
                        uint64_t c1, const uint8_t *in1, size_t len1, int level1, uint8_t *out1, size_t *olen1,
                        double *n2)
@@ -514,8 +913,8 @@ static int gate_job_n2(const oq_gate *g, int cb, int C,
             n2[0] = sum_sq(psi, C);
             n2[1] = two ? sum_sq(psi + C, C) : 0.0;
         }
-        *olen0 = oq_encode_chunk(psi, C, level0, out0);
-        if (two) *olen1 = oq_encode_chunk(psi + C, C, level1, out1);
+        *olen0 = oq_encode_chunk_ex(psi, C, level0, flags, out0);
+        if (two) *olen1 = oq_encode_chunk_ex(psi + C, C, level1, flags, out1);
         if (n2) {
             rc = oq_decode_chunk(out0, *olen0, C, psi);
             if (rc == 0 && two) rc = oq_decode_chunk(out1, *olen1, C, psi + C);
@@ -527,11 +926,19 @@ static int gate_job_n2(const oq_gate *g, int cb, int C,
     return rc;
 }
 
+int oq_gate_job_ex(const oq_gate *g, int cb, int C, int flags,
+                   uint64_t c0, const uint8_t *in0, size_t len0, int level0, uint8_t *out0, size_t *olen0,
+                   uint64_t c1, const uint8_t *in1, size_t len1, int level1, uint8_t *out1, size_t *olen1)
+{
+    return gate_job_n2(g, cb, C, flags, c0, in0, len0, level0, out0, olen0, c1, in1, len1, level1, out1, olen1,
+                       NULL);
+}
+
 int oq_gate_job(const oq_gate *g, int cb, int C,
                 uint64_t c0, const uint8_t *in0, size_t len0, int level0, uint8_t *out0, size_t *olen0,
                 uint64_t c1, const uint8_t *in1, size_t len1, int level1, uint8_t *out1, size_t *olen1)
 {
-    return gate_job_n2(g, cb, C, c0, in0, len0, level0, out0, olen0, c1, in1, len1, level1, out1, olen1, NULL);
+    return oq_gate_job_ex(g, cb, C, 0, c0, in0, len0, level0, out0, olen0, c1, in1, len1, level1, out1, olen1);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -552,6 +959,7 @@ typedef struct {
     double norm2;             /* per-block mode: squared norm of the stored state */
     uint64_t gates_applied, lossy_steps;
     uint64_t min_compressed, max_compressed;
+    int enc_flags;            /* OQ_ENC_ENTROPY: chunks may take the entropy-coded body */
     uint8_t *scratch_out[2];
 } oq_sim;
 
@@ -649,8 +1057,8 @@ static int sim_gate(oq_sim *s, const oq_gate *g, oq_undo *undo, uint64_t *nundo,
         }
         size_t o0 = 0, o1 = 0;
         if (role == OQ_JOB_SINGLE) {
-            if (gate_job_n2(g, s->cb, s->C, c, s->chunk[c], s->len[c], chunk_level(s, c), s->scratch_out[0], &o0,
-                            0, NULL, 0, 0, NULL, NULL, n2) != 0) return -1;
+            if (gate_job_n2(g, s->cb, s->C, s->enc_flags, c, s->chunk[c], s->len[c], chunk_level(s, c),
+                            s->scratch_out[0], &o0, 0, NULL, 0, 0, NULL, NULL, n2) != 0) return -1;
             *wd += oq_delta_tab[chunk_level(s, c)] * n2[0];
             *lost += n2[0] - n2[2];
             undo[(*nundo)++] = (oq_undo){c, s->chunk[c], s->len[c]};
@@ -660,8 +1068,9 @@ static int sim_gate(oq_sim *s, const oq_gate *g, oq_undo *undo, uint64_t *nundo,
             *reencoded += 1;
         } else { /* OQ_JOB_PAIR_LO */
             uint64_t c1 = c | (UINT64_C(1) << (g->target - s->cb));
-            if (gate_job_n2(g, s->cb, s->C, c, s->chunk[c], s->len[c], chunk_level(s, c), s->scratch_out[0], &o0,
-                            c1, s->chunk[c1], s->len[c1], chunk_level(s, c1), s->scratch_out[1], &o1, n2) != 0)
+            if (gate_job_n2(g, s->cb, s->C, s->enc_flags, c, s->chunk[c], s->len[c], chunk_level(s, c),
+                            s->scratch_out[0], &o0, c1, s->chunk[c1], s->len[c1], chunk_level(s, c1),
+                            s->scratch_out[1], &o1, n2) != 0)
                 return -1;
             *wd += oq_delta_tab[chunk_level(s, c)] * n2[0];
             *wd += oq_delta_tab[chunk_level(s, c1)] * n2[1];
@@ -781,6 +1190,10 @@ int oq_sim_set_chunk(oq_sim *s, uint64_t c, const uint8_t *in, size_t len)
     s->len[c] = (uint32_t)len;
     return 0;
 }
+
+/* Codec flags of later encodes (OQ_ENC_ENTROPY: the entropy-coded body is
+ * taken when it is smaller).  The initial state is the same either way. */
+void oq_sim_set_codec(oq_sim *s, int flags) { s->enc_flags = flags & OQ_ENC_ENTROPY; }
 
 int oq_sim_set_block_level(oq_sim *s, uint64_t b, int level)
 {

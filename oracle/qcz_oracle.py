@@ -64,6 +64,23 @@ def lib():
         L.oq_chunk_cap.argtypes = [ctypes.c_int]
         L.oq_encode_chunk.restype = ctypes.c_size_t
         L.oq_encode_chunk.argtypes = [dp, ctypes.c_int, ctypes.c_int, u8p]
+        L.oq_encode_chunk_ex.restype = ctypes.c_size_t
+        L.oq_encode_chunk_ex.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, u8p]
+        L.oq_chunk_cap_forced.restype = ctypes.c_size_t
+        L.oq_chunk_cap_forced.argtypes = [ctypes.c_int]
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.oq_huff_lengths.restype = ctypes.c_int
+        L.oq_huff_lengths.argtypes = [u32p, ctypes.c_int, u8p]
+        L.oq_canon_codes.restype = ctypes.c_int
+        L.oq_canon_codes.argtypes = [u8p, ctypes.c_int, u32p]
+        L.oq_gate_job_ex.restype = ctypes.c_int
+        L.oq_gate_job_ex.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_uint64, u8p, ctypes.c_size_t, ctypes.c_int, u8p,
+                                     ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.c_uint64, u8p, ctypes.c_size_t, ctypes.c_int, u8p,
+                                     ctypes.POINTER(ctypes.c_size_t)]
+        L.oq_sim_set_codec.restype = None
+        L.oq_sim_set_codec.argtypes = [vp, ctypes.c_int]
         L.oq_decode_chunk.restype = ctypes.c_int
         L.oq_decode_chunk.argtypes = [u8p, ctypes.c_size_t, ctypes.c_int, dp]
         L.oq_gate_size.restype = ctypes.c_size_t
@@ -153,14 +170,37 @@ def chunk_cap(C: int) -> int:
     return lib().oq_chunk_cap(C)
 
 
-def encode_chunk(x, level: int) -> bytes:
+ENC_ENTROPY = 1     # the encoder may take the entropy-coded body
+ENC_FORCE_ENT = 2   # test hook: always entropy-code the PACK / SPARSE body
+ENC_FORCE_CODED = 4 # test hook: every lane with two or more symbols CODED, one symbol CONST
+
+
+def encode_chunk(x, level: int, flags: int = 0) -> bytes:
     x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
     C = x.size
-    buf = np.zeros(chunk_cap(C), dtype=np.uint8)
-    n = lib().oq_encode_chunk(_dp(x), C, level, _u8(buf))
+    cap = lib().oq_chunk_cap_forced(C) if flags & ENC_FORCE_ENT else chunk_cap(C)
+    buf = np.zeros(cap, dtype=np.uint8)
+    n = lib().oq_encode_chunk_ex(_dp(x), C, level, flags, _u8(buf))
     if n == 0:
         raise ValueError("bad chunk size or level")
     return buf[:n].tobytes()
+
+
+def huff_lengths(counts) -> np.ndarray:
+    """Code lengths of the entropy stage's length-limited Huffman code."""
+    c = np.ascontiguousarray(np.asarray(counts, dtype=np.uint32))
+    out = np.zeros(c.size, dtype=np.uint8)
+    if lib().oq_huff_lengths(c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), c.size, _u8(out)) != 0:
+        raise ValueError("need 1..16 symbols, at least two present")
+    return out
+
+
+def canon_codes(lengths) -> np.ndarray:
+    ln = np.ascontiguousarray(np.asarray(lengths, dtype=np.uint8))
+    out = np.zeros(ln.size, dtype=np.uint32)
+    if lib().oq_canon_codes(_u8(ln), ln.size, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))) != 0:
+        raise ValueError("bad lengths")
+    return out
 
 
 def decode_chunk(data: bytes, C: int) -> np.ndarray:
@@ -196,8 +236,9 @@ def chunk_role(g, cb: int, c: int) -> int:
 
 
 def gate_job(g, cb: int, C: int, c0: int, in0: bytes, level0: int,
-             c1: int | None = None, in1: bytes | None = None, level1: int = 0):
-    """One unit of the blockwise loop on exported chunk bytes."""
+             c1: int | None = None, in1: bytes | None = None, level1: int = 0, flags: int = 0):
+    """One unit of the blockwise loop on exported chunk bytes (flags: codec
+    flags ENC_*)."""
     g = _gates(g)
     cap = chunk_cap(C)
     b0 = np.frombuffer(bytes(in0), dtype=np.uint8).copy()
@@ -205,15 +246,15 @@ def gate_job(g, cb: int, C: int, c0: int, in0: bytes, level0: int,
     n0 = ctypes.c_size_t(0)
     n1 = ctypes.c_size_t(0)
     if in1 is None:
-        rc = lib().oq_gate_job(g.ctypes.data, cb, C, c0, _u8(b0), b0.size, level0, _u8(o0), ctypes.byref(n0),
-                               0, None, 0, 0, None, None)
+        rc = lib().oq_gate_job_ex(g.ctypes.data, cb, C, flags, c0, _u8(b0), b0.size, level0, _u8(o0),
+                                  ctypes.byref(n0), 0, None, 0, 0, None, None)
         if rc != 0:
             raise ValueError("malformed chunk")
         return o0[:n0.value].tobytes()
     b1 = np.frombuffer(bytes(in1), dtype=np.uint8).copy()
     o1 = np.zeros(cap, dtype=np.uint8)
-    rc = lib().oq_gate_job(g.ctypes.data, cb, C, c0, _u8(b0), b0.size, level0, _u8(o0), ctypes.byref(n0),
-                           c1, _u8(b1), b1.size, level1, _u8(o1), ctypes.byref(n1))
+    rc = lib().oq_gate_job_ex(g.ctypes.data, cb, C, flags, c0, _u8(b0), b0.size, level0, _u8(o0),
+                              ctypes.byref(n0), c1, _u8(b1), b1.size, level1, _u8(o1), ctypes.byref(n1))
     if rc != 0:
         raise ValueError("malformed chunk")
     return o0[:n0.value].tobytes(), o1[:n1.value].tobytes()
@@ -226,11 +267,13 @@ class Sim:
     """Blockwise compressed simulator (Sec. 3.1/3.3) with the Sec. 3.7 rule."""
 
     def __init__(self, n: int, block_log2: int, mode: int = MODE_LOSSLESS,
-                 level: int = 0, budget: int = 0):
+                 level: int = 0, budget: int = 0, codec: int = 0):
         self.n, self.block_log2 = n, block_log2
         self._h = lib().oq_sim_create(n, block_log2, mode, level, budget)
         if not self._h:
             raise ValueError("bad simulator configuration")
+        if codec:
+            lib().oq_sim_set_codec(self._h, codec)   # ENC_ENTROPY: the entropy stage
         self.cb = lib().oq_sim_chunk_log2(self._h)
         self.C = 2 << self.cb
         self.nchunks = 1 << (n - self.cb)

@@ -1233,8 +1233,20 @@ qcz_status qcz_import_state(qcz_state *s, const void *host_buf, size_t len, cons
     HIPCHK(s, hipStreamSynchronize(s->stream));
     s->live = live;
     s->min_c = s->max_c = live;
+    // a fresh ledger at the configuration's level (qcz_resume restores a saved one); an
+    // import also replaces a state left invalid by a failed ranged gate
+    s->broken = false;
+    s->level = s->cfg.mode == QCZ_MODE_FIXED ? s->cfg.level : 0;
+    s->gates_applied = 0;
+    s->lossy_steps = 0;
+    s->flb = 1.0;
     clear_graphs(s);
-    return reset_stripes(s, len);
+    qcz_status st = reset_stripes(s, len);   // also writes the level to the device header
+    if (st != QCZ_OK || s->cfg.mode != QCZ_MODE_PERBLOCK) return st;
+    double mom[3];   // the per-block ledger divides by the stored state's squared norm
+    st = qcz_moments(s, mom);
+    if (st == QCZ_OK) s->norm2 = mom[2];
+    return st;
 }
 
 qcz_status qcz_resume(qcz_state *s, const qcz_footprint_t *f)

@@ -1,7 +1,7 @@
 """Uncompressed fp64 state-vector simulation with torch on the device, for
 measuring the fidelity of a compressed run (Eq. (9): |<psi_ideal|psi_sim>|).
 
-This is a measurement aid, not part of the compressed path: it holds the
+A test aid, not part of the compressed path (only tests import it): it holds the
 full 2^n complex128 vector (16 GiB at 30 qubits) and applies the same gate
 records with tensor views over the qubit dimensions.  Qubit q is bit q of
 the amplitude index, i.e. dimension n - 1 - q of the [2] * n view.

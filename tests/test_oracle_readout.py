@@ -56,3 +56,21 @@ def test_overlap_closed_forms():
     assert rr.overlap(a, 1j * a) == pytest.approx(1j)
     b = np.array([0, 0, 1, 0])
     assert rr.overlap(a, b) == 0
+
+
+def test_sampler_agrees_with_the_plain_global_inverse_cdf():
+    # The plain definition: index i with probability |a_i|^2 / sum |a|^2, drawn
+    # by inverting the running sum over the whole vector in index order.  The
+    # chunk-then-amplitude walk is the same inverse in exact arithmetic; only
+    # draws within rounding distance of a boundary may differ.
+    rng = np.random.default_rng(7)
+    n, apc, shots, seed = 12, 64, 4000, 99
+    psi = (rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)) * (rng.random(1 << n) < 0.7)
+    psi /= np.linalg.norm(psi)
+    got = rr.sample(psi, apc, seed, shots)
+    p = np.abs(psi) ** 2
+    cdf = np.cumsum(p)
+    u = np.array([(rr.splitmix64(seed, k) >> 11) * 2.0 ** -53 for k in range(shots)])
+    plain = np.minimum(np.searchsorted(cdf, u * cdf[-1], side="right"), (1 << n) - 1)
+    assert np.mean(got == plain) >= 0.999
+    assert np.all(p[got] > 0)

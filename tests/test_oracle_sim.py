@@ -186,3 +186,69 @@ def test_adaptive_rule_out_of_memory_keeps_last_committed_state():
     t = oq.Sim(n, bl, oq.MODE_ADAPTIVE, 0, budget)
     assert t.apply(gates[:k]) == k
     assert bits_equal(t.state(), s.state())
+
+
+def _replay_smallest_fitting_levels(n, bl, gates, budget):
+    """The adaptive rule re-derived from its definition (Sec. 3.7): gate k runs
+    at the smallest level >= the previous one whose result fits the budget.
+    Each candidate level is tried on a per-block simulator whose blocks all
+    hold that level (one uniform level = a fixed-level gate) and undone by
+    re-importing the chunks saved before the gate."""
+    s = oq.Sim(n, bl, oq.MODE_PERBLOCK, 0)
+    nblocks = 1 << (n - bl)
+    lev, levels = 0, []
+    for k in range(len(gates)):
+        saved = [s.chunk(c) for c in range(s.nchunks)]
+        while True:
+            for b in range(nblocks):
+                s.set_block_level(b, lev)
+            assert s.apply(gates[k:k + 1]) == 1
+            if s.footprint()["compressed_bytes"] <= budget:
+                break
+            for c, data in enumerate(saved):
+                s.set_chunk(c, data)
+            lev += 1
+            assert lev < oq.N_LEVELS
+        levels.append(lev)
+    return levels, s
+
+
+def test_adaptive_rule_takes_the_smallest_fitting_level_at_every_gate():
+    # a budget tight enough that some gates must relax more than one level at once
+    n, bl = 12, 8
+    gates = cc.random_circuit_small(n, depth=12, seed=24)
+    ref = oq.Sim(n, bl, oq.MODE_LOSSLESS)
+    peak = 0
+    for k in range(len(gates)):
+        ref.apply(gates[k:k + 1])
+        peak = max(peak, ref.footprint()["compressed_bytes"])
+    budget = int(0.3 * peak)
+    want, replay = _replay_smallest_fitting_levels(n, bl, gates, budget)
+    s = oq.Sim(n, bl, oq.MODE_ADAPTIVE, 0, budget)
+    got = []
+    for k in range(len(gates)):
+        assert s.apply(gates[k:k + 1]) == 1
+        got.append(s.footprint()["level"])
+    assert got == want
+    assert max(b - a for a, b in zip([0] + want, want)) >= 3   # gates that relaxed by several levels at once
+    assert bits_equal(s.state(), replay.state())
+    for c in range(s.nchunks):
+        assert s.chunk(c) == replay.chunk(c)
+
+
+def test_footprint_min_max_over_the_run():
+    # min / max compressed bytes equal the extremes of the sizes seen after
+    # every gate, counting the initial state
+    n, bl = 11, 7
+    gates = cc.random_circuit_small(n, depth=8, seed=24)
+    s = oq.Sim(n, bl, oq.MODE_FIXED, 2)
+    trace = [s.footprint()["compressed_bytes"]]
+    for k in range(len(gates)):
+        s.apply(gates[k:k + 1])
+        trace.append(s.footprint()["compressed_bytes"])
+    fp = s.footprint()
+    assert fp["min_compressed"] == min(trace) and fp["max_compressed"] == max(trace)
+    assert min(trace) < trace[0] < max(trace) or min(trace) == trace[0]
+    t = oq.Sim(n, bl, oq.MODE_FIXED, 2)
+    t.apply(gates)   # one call: the same extremes (tracked after each gate, not per call)
+    assert t.footprint()["min_compressed"] == min(trace) and t.footprint()["max_compressed"] == max(trace)

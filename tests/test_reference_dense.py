@@ -5,7 +5,7 @@ import torch
 
 from oracle import qcz_oracle as oq
 from paper_1911_04034_amd import circuits as cc
-from paper_1911_04034_amd import reference as ref
+import dense_ref as ref
 
 
 def test_reference_matches_oracle_dense_all_kinds():
