@@ -358,6 +358,21 @@ qcz_status qcz_mlp_train_step(float *dev_params, float *dev_m, float *dev_v, con
                               float *dev_grad, float *dev_loss, void *dev_work, size_t work_bytes,
                               void *hip_stream);
 
+/* The training step above without a workspace argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * or training loops, harnesses that forbid hipMalloc).  Same arguments,
+ * kernels and results as qcz_mlp_train_step; the workspace is a static device
+ * array that the library holds on every GPU it runs on until the process
+ * ends, sized for QCZ_MLP_NOALLOC_MAX_SAMPLES samples (about 8.5 MiB).  The
+ * call allocates nothing.  QCZ_E_NOMEM (nothing launched) for n_samples
+ * above that limit, QCZ_E_INVAL as qcz_mlp_train_step.  All calls on one GPU
+ * share its array: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialized by the caller. */
+#define QCZ_MLP_NOALLOC_MAX_SAMPLES 8192
+qcz_status qcz_mlp_train_step_noalloc(float *dev_params, float *dev_m, float *dev_v, const float *dev_x,
+                                      const uint8_t *dev_labels, uint64_t n_samples, float lr, uint32_t step,
+                                      float *dev_grad, float *dev_loss, void *hip_stream);
+
 /* QCZ_MODE_PERBLOCK: block features -> network -> most probable level per
  * block, raised to at least the rule's level (the loosest level with delta
  * <= beta: one bound for every block already meets the budget) -> budget

@@ -203,6 +203,10 @@ hipError_t launch_block_features(const double *cstats, const uint8_t *block_leve
 hipError_t launch_mlp_forward(const float *params, const float *X, uint64_t N, float *probs, uint8_t *argmax,
                               hipStream_t st);
 size_t mlp_workspace_bytes(uint64_t N);
+// the no-allocation training step: samples its static workspace holds, and the
+// device address / size of this GPU's copy of it
+constexpr uint64_t kMlpStaticSamples = 8192;
+hipError_t mlp_static_workspace(void **out, size_t *bytes);
 hipError_t launch_mlp_train(float *params, float *m, float *v, const float *X, const uint8_t *labels, uint64_t N,
                             float lr, uint32_t step, float *grad_out, float *loss_out, void *work, hipStream_t st);
 hipError_t launch_fill_table(const DevPtrs &P, uint64_t entry0, uint64_t entry_rest, hipStream_t st);

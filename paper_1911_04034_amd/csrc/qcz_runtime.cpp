@@ -1782,6 +1782,24 @@ qcz_status qcz_mlp_train_step(float *dev_params, float *dev_m, float *dev_v, con
     return QCZ_OK;
 }
 
+qcz_status qcz_mlp_train_step_noalloc(float *dev_params, float *dev_m, float *dev_v, const float *dev_x,
+                                      const uint8_t *dev_labels, uint64_t n_samples, float lr, uint32_t step,
+                                      float *dev_grad, float *dev_loss, void *hip_stream)
+{
+    if (!dev_params || !dev_x || !dev_labels || n_samples == 0) return QCZ_E_INVAL;
+    if (step > 0 && (!dev_m || !dev_v)) return QCZ_E_INVAL;
+    if (n_samples > (uint64_t)QCZ_MLP_NOALLOC_MAX_SAMPLES) return QCZ_E_NOMEM;
+    static_assert(QCZ_MLP_NOALLOC_MAX_SAMPLES == kMlpStaticSamples, "header and kernels agree on the limit");
+    void *ws = nullptr;
+    size_t bytes = 0;
+    if (mlp_static_workspace(&ws, &bytes) != hipSuccess || bytes < mlp_workspace_bytes(n_samples))
+        return QCZ_E_DEVICE;
+    if (launch_mlp_train(dev_params, dev_m, dev_v, dev_x, dev_labels, n_samples, lr, step, dev_grad, dev_loss, ws,
+                         (hipStream_t)hip_stream) != hipSuccess)
+        return QCZ_E_DEVICE;
+    return QCZ_OK;
+}
+
 qcz_status qcz_select_levels(qcz_state *s, const float *dev_params, double beta, uint64_t mix_mask,
                              uint8_t *out_levels)
 {

@@ -20,6 +20,9 @@
 
 #include <math.h>
 
+#include <map>
+#include <mutex>
+
 namespace qcz {
 
 // ---------------------------------------------------------------------------
@@ -336,12 +339,43 @@ hipError_t launch_mlp_forward(const float *params, const float *X, uint64_t N, f
     return hipGetLastError();
 }
 
-size_t mlp_workspace_bytes(uint64_t N)
+static constexpr size_t ws_bytes(uint64_t N)
 {
-    const size_t ws = (size_t)kWsRows * N * sizeof(float);
-    const size_t part = (size_t)slices(N) * kNParams * sizeof(float);
-    const size_t loss = (size_t)sample_blocks(N) * sizeof(float);
-    return ((ws + 255) & ~(size_t)255) + ((part + 255) & ~(size_t)255) + ((loss + 255) & ~(size_t)255);
+    return (((size_t)kWsRows * N * sizeof(float) + 255) & ~(size_t)255) +
+           (((size_t)((N + kSlice - 1) / kSlice) * kNParams * sizeof(float) + 255) & ~(size_t)255) +
+           (((size_t)((N + kMlpWG - 1) / kMlpWG) * sizeof(float) + 255) & ~(size_t)255);
+}
+
+size_t mlp_workspace_bytes(uint64_t N) { return ws_bytes(N); }
+
+// Workspace of the training step for callers that cannot allocate: a static
+// device array holding the workspace of kMlpStaticSamples samples (about
+// 8.5 MiB; every GPU the library runs on holds its own copy until the process
+// ends).  Every step reads only what it wrote itself, so no clearing is needed.
+static __device__ __align__(256) uint8_t scratch[ws_bytes(kMlpStaticSamples)];
+
+// The device address of this GPU's copy of `scratch`, looked up once per
+// device (with that device current) on the first call from it.  In host code
+// the array's name is not a device address; only the looked-up pointer may be
+// handed to kernels.
+hipError_t mlp_static_workspace(void **out, size_t *bytes)
+{
+    static std::mutex mu;
+    static std::map<int, void *> addr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        it = addr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    *bytes = sizeof(scratch);
+    return hipSuccess;
 }
 
 hipError_t launch_mlp_train(float *params, float *m, float *v, const float *X, const uint8_t *labels, uint64_t N,

@@ -67,7 +67,7 @@ EXPORTED = [
     "qcz_chunk_sizes", "qcz_num_chunks", "qcz_chunk_doubles", "qcz_last_error", "qcz_destroy", "qcz_chunk_cap",
     "qcz_encode_chunks", "qcz_decode_chunks", "qcz_get_stats", "qcz_reset_stats", "qcz_set_launch",
     "qcz_block_stats", "qcz_block_level_sizes", "qcz_label_levels", "qcz_project_levels", "qcz_mlp_forward",
-    "qcz_mlp_workspace_bytes", "qcz_mlp_train_step", "qcz_select_levels", "qcz_set_selector", "qcz_copy_state",
+    "qcz_mlp_workspace_bytes", "qcz_mlp_train_step", "qcz_mlp_train_step_noalloc", "qcz_select_levels", "qcz_set_selector", "qcz_copy_state",
     "qcz_mixing_mask", "qcz_overlap", "qcz_resume", "qcz_export_state", "qcz_import_state",
 ]
 MLP_PARAMS = 5638
@@ -147,6 +147,8 @@ def load():
     L.qcz_mlp_workspace_bytes.argtypes = [u64]
     L.qcz_mlp_train_step.restype = i32
     L.qcz_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, u64, flt, u32, vp, vp, vp, sz, vp]
+    L.qcz_mlp_train_step_noalloc.restype = i32
+    L.qcz_mlp_train_step_noalloc.argtypes = [vp, vp, vp, vp, vp, u64, flt, u32, vp, vp, vp]
     L.qcz_select_levels.restype = i32
     L.qcz_select_levels.argtypes = [vp, vp, dbl, u64, vp]
     L.qcz_set_selector.restype = i32
