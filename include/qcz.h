@@ -90,6 +90,14 @@ typedef enum {
                                pass.  Direct launches only (not inside replayed graphs); not with
                                QCZ_FLAG_AUTOTUNE; gates of the block cache are not fused. */
 
+#define QCZ_FLAG_ENTROPY 128u /* the entropy-coding stage (Sec. 4.2: Solution C's lossless stage ends in an
+                               entropy coder): a PACK or SPARSE chunk may carry its residuals in 4-bit lanes,
+                               each stored raw, as one constant or by a canonical Huffman code of at most 8
+                               bits, in sub-streams of 16 positions (header bit 5), whenever that is smaller.
+                               Lossless: decoded values are those of the run without it.  Needs
+                               block_log2 >= 10 (2048-double chunks) and two wavefronts per chunk; not with
+                               QCZ_FLAG_CACHE or QCZ_FLAG_AUTOTUNE. */
+
 typedef struct {
     uint32_t n_qubits;      /* 6 .. 40 */
     uint32_t block_log2;    /* log2 amplitudes per block, 6 .. n_qubits */
@@ -407,11 +415,15 @@ size_t qcz_chunk_cap(uint32_t C);
 /* Encode n_chunks chunks of C doubles (device, contiguous) at `level` into
  * device slots of slot_bytes bytes each (slot_bytes >= qcz_chunk_cap(C),
  * multiple of 4); stream sizes go to dev_sizes (device, n_chunks u32).
- * C is a power of two in 128 .. 2048. */
-qcz_status qcz_encode_chunks(const void *dev_in, uint32_t C, uint64_t n_chunks, int level, void *dev_slots,
-                             size_t slot_bytes, uint32_t *dev_sizes, void *hip_stream);
+ * C is a power of two in 128 .. 2048.  codec_flags: QCZ_CODEC_ENTROPY lets
+ * a chunk take the entropy-coded body (C = 2048 only); other bits:
+ * QCZ_E_INVAL. */
+#define QCZ_CODEC_ENTROPY 1u
+qcz_status qcz_encode_chunks(const void *dev_in, uint32_t C, uint64_t n_chunks, int level, uint32_t codec_flags,
+                             void *dev_slots, size_t slot_bytes, uint32_t *dev_sizes, void *hip_stream);
 
-/* Decode n_chunks streams from device slots into C doubles each (device). */
+/* Decode n_chunks streams from device slots into C doubles each (device);
+ * streams with and without the entropy stage. */
 qcz_status qcz_decode_chunks(const void *dev_slots, size_t slot_bytes, const uint32_t *dev_sizes, uint32_t C,
                              uint64_t n_chunks, void *dev_out, void *hip_stream);
 

@@ -41,6 +41,9 @@ struct GateDesc {
     int32_t block_shift;            // log2(chunks per block)
     int32_t fixed_level;            // >= 0: codec kernels encode at this level
     uint64_t job0, job_end;         // jobs [job0, job_end) of this launch (job_end 0: all njobs)
+    int32_t entropy;                // the encoder may take the entropy-coded body (header bit 5); its
+                                    // kernels decode such streams too (C = 2048, two wavefronts per chunk)
+    int32_t pad_;
 };
 
 // the jobs one launch of a gate runs

@@ -293,16 +293,269 @@ __device__ __forceinline__ void gscan_enc(uint32_t bad, uint32_t rp, uint32_t cn
 }
 
 // ---------------------------------------------------------------------------
+// entropy stage (header bit 5): the residual of a value (its bits after the
+// leading bytes it shares with the previous value) is cut into 4-bit lanes;
+// lane j covers bits [64-4j-w_j, 64-4j) of the value, w_j = min(4, K-4j),
+// j < NN = ceil(K/4), and value i codes the lanes j >= 2 L_i.  Each lane is
+// RAW (the w_j-bit symbol), CONST (one symbol, stored once) or CODED by a
+// canonical Huffman code of at most 8 bits.  Sub-stream s holds the codes of
+// positions 16s .. 16s+15; a 12-bit field per sub-stream gives its length.
+// Kernels with the stage run C = 2048 doubles with two wavefronts per chunk,
+// so thread lt owns positions 16 lt .. 16 lt + 15: exactly sub-stream lt.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kHdrEnt = 0x20u;
+constexpr int kEntMaxLen = 8;
+constexpr int kEntSlotWords = 1024;   // per slot: decode tables (16 lanes x 256 bytes) or encode tables
+enum { LANE_RAW = 0, LANE_CONST = 1, LANE_CODED = 2 };
+// per slot in the entropy area: encode table (u16 per lane and symbol: code,
+// bit-reversed, | length << 8) and lane records (4 words per lane)
+constexpr int kEntRecWord0 = 128;
+
+__device__ __forceinline__ int ent_lanes(int K) { return (K + 3) >> 2; }
+__device__ __forceinline__ int ent_width(int K, int j)
+{
+    const int w = K - 4 * j;
+    return w < 4 ? w : 4;
+}
+// lane j of a value (high word h, low word l)
+__device__ __forceinline__ uint32_t ent_sym(uint32_t h, uint32_t l, int K, int j)
+{
+    const int w = ent_width(K, j);
+    return j < 8 ? __builtin_amdgcn_ubfe(h, (uint32_t)(32 - 4 * j - w), (uint32_t)w)
+                 : __builtin_amdgcn_ubfe(l, (uint32_t)(60 - 4 * j), 4u);
+}
+// table nibbles of a lane in mode m
+__device__ __forceinline__ uint32_t ent_nibs(uint32_t m, int w) { return m == LANE_CONST ? 1u : m == LANE_CODED ? (1u << w) : 0u; }
+// nibble k of a 64-bit word of sixteen 4-bit fields
+__device__ __forceinline__ uint32_t nib64(uint64_t v, int k) { return (uint32_t)(v >> (4 * k)) & 15u; }
+
+// one 4-bit field per bit of a 16-bit mask
+__device__ __forceinline__ uint64_t spread16(uint32_t m)
+{
+    uint64_t x = m & 0xFFFFu;
+    x = (x | (x << 24)) & 0x000000FF000000FFull;
+    x = (x | (x << 12)) & 0x000F000F000F000Full;
+    x = (x | (x << 6)) & 0x0303030303030303ull;
+    x = (x | (x << 3)) & 0x1111111111111111ull;
+    return x;
+}
+
+template <int N>
+__device__ __forceinline__ void cswap(uint32_t (&k)[N], int a, int b)
+{
+    const uint32_t lo = min(k[a], k[b]), hi = max(k[a], k[b]);
+    k[a] = lo;
+    k[b] = hi;
+}
+
+// Code lengths of the lane's Huffman code (two or more symbols present; the
+// counts are those of symbols 0..15).  Leaves in increasing (count, symbol)
+// order (a bitonic sorting network on count << 4 | symbol), internal nodes
+// in creation order as a second queue; each step joins the two lightest heads,
+// the leaf first on equal weights.  Queue entries are weight << 16 | the mask
+// of the leaves below (by sorted position) and live in this thread's LDS
+// scratch q[32]; every merge adds one to the depth of the leaves below it.
+// Lengths above 8 are cut to 8, then the longest code below 8 (fewest
+// occurrences, then lowest symbol) grows by one bit while the Kraft sum
+// exceeds 1.  Returns 16 four-bit lengths, symbol s at bits 4s.
+__device__ uint64_t ent_huff_lengths(const uint32_t (&c)[16], uint32_t *q)
+{
+    uint32_t key[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) key[s] = c[s] ? (c[s] << 4) | (uint32_t)s : ~0u;
+#pragma unroll
+    for (int size = 2; size <= 16; size <<= 1)
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int jx = i ^ stride;
+                if (jx > i) {
+                    if ((i & size) == 0) cswap(key, i, jx);
+                    else cswap(key, jx, i);
+                }
+            }
+    int nl = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        nl += key[i] != ~0u ? 1 : 0;
+        q[i] = key[i] != ~0u ? ((key[i] >> 4) << 16) | (1u << i) : ~0u;
+    }
+    uint32_t *node = q + 16;
+    int h1 = 0, h2 = 0, nn = 0;
+    uint64_t depth = 0;
+    for (int it = 0; it < nl - 1; ++it) {
+        const uint32_t lw0 = h1 < nl ? q[h1] : ~0u, lw1 = h1 + 1 < nl ? q[h1 + 1] : ~0u;
+        const uint32_t nw0 = h2 < nn ? node[h2] : ~0u, nw1 = h2 + 1 < nn ? node[h2 + 1] : ~0u;
+        const bool t1 = (lw0 >> 16) <= (nw0 >> 16);
+        const uint32_t a = t1 ? lw0 : nw0;
+        const uint32_t lh = t1 ? lw1 : lw0, nh = t1 ? nw0 : nw1;
+        const bool t2 = (lh >> 16) <= (nh >> 16);
+        const uint32_t bb = t2 ? lh : nh;
+        h1 += (t1 ? 1 : 0) + (t2 ? 1 : 0);
+        h2 += (t1 ? 0 : 1) + (t2 ? 0 : 1);
+        const uint32_t m = (a | bb) & 0xFFFFu;
+        node[nn++] = (((a >> 16) + (bb >> 16)) << 16) | m;
+        depth += spread16(m);
+    }
+    uint64_t len = 0;
+    uint32_t maxl = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t d = nib64(depth, i);
+        if (i < nl) len |= (uint64_t)d << (4 * (key[i] & 15u));
+        maxl = (i < nl && d > maxl) ? d : maxl;
+    }
+    if (maxl > (uint32_t)kEntMaxLen) {
+        uint32_t kraft = 0;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            uint32_t l = nib64(len, s);
+            if (l > (uint32_t)kEntMaxLen) {
+                len = (len & ~(15ull << (4 * s))) | ((uint64_t)kEntMaxLen << (4 * s));
+                l = kEntMaxLen;
+            }
+            kraft += l ? (1u << (kEntMaxLen - l)) : 0u;
+        }
+        while (kraft > (1u << kEntMaxLen)) {
+            int best = -1;
+            uint32_t bl = 0, bc = 0;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const uint32_t l = nib64(len, s);
+                const bool ok = l != 0 && l < (uint32_t)kEntMaxLen;
+                const bool better = best < 0 || l > bl || (l == bl && c[s] < bc);
+                if (ok && better) { best = s; bl = l; bc = c[s]; }
+            }
+            len += 1ull << (4 * best);
+            kraft -= 1u << (kEntMaxLen - bl - 1);
+        }
+    }
+    return len;
+}
+
+// Canonical code of symbol s (length l > 0) among the lengths `len`: symbols
+// in increasing (length, symbol) order take consecutive codes, i.e. the code
+// is the sum of 2^(8 - length) over the symbols before s, shifted down by
+// 8 - l.
+__device__ __forceinline__ uint32_t ent_canon_code(uint64_t len, int s, uint32_t l)
+{
+    uint32_t start = 0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const uint32_t lt = nib64(len, t);
+        const bool before = lt != 0 && (lt < l || (lt == l && t < s));
+        start += before ? (1u << (kEntMaxLen - lt)) : 0u;
+    }
+    return start >> (kEntMaxLen - l);
+}
+
+// bit-reversed l-bit code (the code's first bit at the lowest position)
+__device__ __forceinline__ uint32_t ent_rev(uint32_t code, uint32_t l)
+{
+    return l ? (__builtin_bitreverse32(code) >> (32u - l)) : 0u;
+}
+
+// Build lane j of the encoder's code from the slot's histogram hist[4][16][16]
+// (four copies, summed): choose RAW / CONST / CODED by the format's rule, write
+// the lane's encode table enc[16 * j + s] (u16: bit-reversed code | length << 8)
+// and its record rec[4 j ..]: mode | symbol << 4 | table nibbles << 8, coded
+// bits, lengths (low, high word).
+__device__ __noinline__ void ent_build_lane(const uint32_t *hist, uint32_t *q, int K, int j, uint16_t *enc, uint32_t *rec)
+{
+    uint32_t c[16];
+    uint32_t n = 0, distinct = 0, mx = 0, csym = 0;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        c[s] = hist[(0 * 16 + j) * 16 + s] + hist[(1 * 16 + j) * 16 + s] + hist[(2 * 16 + j) * 16 + s] +
+               hist[(3 * 16 + j) * 16 + s];
+        n += c[s];
+        distinct += c[s] ? 1u : 0u;
+        mx = c[s] > mx ? c[s] : mx;
+        csym = c[s] ? (uint32_t)s : csym;
+    }
+    const int w = ent_width(K, j);
+    const uint32_t nsym = 1u << w, raw = n * (uint32_t)w;
+    uint32_t mode = LANE_RAW, cost = raw;
+    uint64_t len = 0;
+    if (n > 0 && distinct == 1) {
+        if (4u < raw) { mode = LANE_CONST; cost = 0; }
+    } else if (distinct >= 2 && mx * nsym >= 2u * n) {
+        len = ent_huff_lengths(c, q);
+        uint32_t coded = 4u * nsym;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) coded += c[s] * nib64(len, s);
+        if (coded < raw) { mode = LANE_CODED; cost = coded - 4u * nsym; }
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        uint32_t e = 0;
+        if (mode == LANE_RAW) e = (uint32_t)s | ((uint32_t)w << 8);
+        else if (mode == LANE_CODED) {
+            const uint32_t l = nib64(len, s);
+            e = l ? (ent_rev(ent_canon_code(len, s, l), l) | (l << 8)) : 0u;
+        }
+        enc[16 * j + s] = (uint16_t)e;
+    }
+    rec[4 * j] = mode | (csym << 4) | (ent_nibs(mode, w) << 8);
+    rec[4 * j + 1] = cost;
+    rec[4 * j + 2] = mode == LANE_CODED ? (uint32_t)len : 0u;
+    rec[4 * j + 3] = mode == LANE_CODED ? (uint32_t)(len >> 32) : 0u;
+}
+
+// Decode tables of an entropy-coded stream: tab[256 j + x] = symbol | length
+// << 4 for the next eight bits x of the stream (RAW: the low w bits; CONST:
+// the symbol, length 0; CODED: the symbol whose bit-reversed code is x's low
+// bits).  The caller has cleared tab (entries of a malformed stream may stay
+// 0: a symbol 0 of length 0).  Thread lt fills the entries of (lane, symbol)
+// pairs lt, lt + G, ...  tw0: first word of the table area; laneword: the
+// stream's lane word.
+template <int G>
+__device__ void ent_fill_tables(const uint32_t *b, int tw0, uint32_t laneword, int K, uint8_t *tab, int lt)
+{
+    const int NN = ent_lanes(K);
+    for (int p = lt; p < NN * 16; p += G) {
+        const int j = p >> 4, s = p & 15;
+        const int w = ent_width(K, j);
+        const uint32_t mode = (laneword >> (2 * j)) & 3u;
+        uint32_t off = 0;   // nibble offset of lane j in the table area
+        for (int i = 0; i < j; ++i) off += ent_nibs((laneword >> (2 * i)) & 3u, ent_width(K, i));
+        uint8_t *t = tab + 256 * j;
+        if (mode == LANE_RAW) {
+            if (s < (1 << w))
+                for (int x = s; x < 256; x += 1 << w) t[x] = (uint8_t)(s | (w << 4));
+        } else if (mode == LANE_CONST) {
+            const uint32_t csym = __builtin_amdgcn_ubfe(b[clampw(tw0 + (int)(off >> 3))], 4u * (off & 7u), 4u);
+            for (int x = 16 * s; x < 16 * s + 16; ++x) t[x] = (uint8_t)csym;
+        } else if (mode == LANE_CODED && s < (1 << w)) {
+            // the lane's 2^w lengths: nibbles off .. off + 2^w - 1
+            const int wi = clampn<3>(tw0 + (int)(off >> 3));
+            const uint32_t sh = 4u * (off & 7u);
+            const uint64_t lo = ((uint64_t)b[wi + 1] << 32) | b[wi];
+            uint64_t len = (lo >> sh) | (sh ? ((uint64_t)b[wi + 2] << (64 - sh)) : 0ull);
+            if (w < 4) len &= (1ull << (4 << w)) - 1ull;
+            const uint32_t l = nib64(len, s);
+            if (l == 0 || l > (uint32_t)kEntMaxLen) continue;
+            const uint32_t r = ent_rev(ent_canon_code(len, s, l), l);
+            for (uint32_t x = r; x < 256u; x += 1u << l) t[x] = (uint8_t)(s | (l << 4));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // decode: the chunk staged in b[] -> the V values this thread owns
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int codes_word0(int mode, int C) { return mode == M_SPARSE ? 1 + ((C + 31) >> 5) : 1; }
 
 // `hdr` is the stream header (an inactive slot passes a CONST2 header and
-// active = false); `any_sparse` is workgroup-uniform.
-template <int V, int WPG>
+// active = false); `any_sparse` and `any_ent` (a slot holds an entropy-coded
+// stream) are workgroup-uniform; etab is the slot's decode-table area.
+template <int V, int WPG, bool ENT = false>
 __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool any_sparse, int C, int lt,
-                             uint32_t *slotA, uint32_t *slotB, uint32_t *slotC, uint32_t (&th)[V], uint32_t (&tl)[V])
+                             uint32_t *slotA, uint32_t *slotB, uint32_t *slotC, uint32_t (&th)[V], uint32_t (&tl)[V],
+                             bool any_ent = false, uint8_t *etab = nullptr)
 {
+    static_assert(!ENT || V == 16, "the entropy stage runs one sub-stream of 16 values per thread");
     const int mode = (int)(hdr & 3u);
     int lev = (int)((hdr >> 2) & 7u);
     if (lev >= kLevels) lev = 0;
@@ -341,6 +594,29 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
         Lpos = (V >= 16) ? cw : (cw & ((1u << (2 * V)) - 1u));
         rsum = resid_total(Lpos, K, (uint32_t)V);
     }
+    // entropy-coded stream: decode tables of its lanes, and my sub-stream's
+    // bit length (field lt of the length area) in place of the residual total
+    const bool my_ent = ENT && active && (hdr & kHdrEnt) != 0 && mode != M_CONST2;
+    int bw0 = 0;   // first word of the entropy-coded bit stream
+    if (ENT && any_ent) {
+        const int NN = ent_lanes(K);
+        const uint32_t lw = my_ent ? b[clampw(res_w0)] : 0u;
+        uint32_t *tw = reinterpret_cast<uint32_t *>(etab);
+        if (my_ent)
+            for (int i = lt; i < 64 * NN; i += 64 * WPG) tw[i] = 0u;
+        lds_barrier();
+        if (my_ent) ent_fill_tables<64 * WPG>(b, res_w0 + 1, lw, K, etab, lt);
+        lds_barrier();
+        if (my_ent) {
+            uint32_t nib = 0;
+            for (int j = 0; j < NN; ++j) nib += ent_nibs((lw >> (2 * j)) & 3u, ent_width(K, j));
+            const int sw0 = res_w0 + 1 + (int)((nib + 7u) >> 3);
+            const uint32_t bit = 12u * (uint32_t)lt;
+            const int wi = clampn<2>(sw0 + (int)(bit >> 5));
+            rsum = fshr(b[wi + 1], b[wi], bit & 31u) & 0xFFFu;
+            bw0 = sw0 + ((12 * (C / 16) + 31) >> 5);
+        }
+    }
     uint32_t o, rtot;
     gscan_add<WPG>(rsum, slotB, o, rtot);
 
@@ -348,7 +624,42 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
     // as last defined by one of my stored values (a value with L shared
     // leading bytes defines the 3 - L after them) and the smallest such L
     uint32_t cbytes = 0, cmin = 3;
-    if (K < 64) {
+    if (ENT && my_ent) {
+        // my sub-stream: for each stored value the lanes 2L .. NN-1, each an
+        // eight-bit table lookup on a bit window refilled a word at a time
+        const int NN = ent_lanes(K);
+        const int wi = bw0 + (int)(o >> 5);
+        const uint32_t sh = o & 31u;
+        uint64_t win = (((uint64_t)b[clampw(wi + 1)] << 32) | b[clampw(wi)]) >> sh;
+        int avail = 64 - (int)sh;
+        int nextw = wi + 2;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const uint32_t st = (stored >> k) & 1u;
+            const uint32_t L = (Lpos >> (2 * k)) & 3u;
+            uint32_t vh = 0, vl = 0;
+            const int j0 = st ? 2 * (int)L : NN;
+            for (int j = j0; j < NN; ++j) {
+                if (avail < 8) {
+                    win |= (uint64_t)b[clampw(nextw)] << avail;
+                    ++nextw;
+                    avail += 32;
+                }
+                const uint32_t e = etab[256 * j + (uint32_t)(win & 255u)];
+                const uint32_t sym = e & 15u, l = e >> 4;
+                win >>= l;
+                avail -= (int)l;
+                if (j < 8) vh |= sym << (32 - 4 * j - ent_width(K, j));
+                else vl |= sym << (60 - 4 * j);
+            }
+            th[k] = vh;
+            tl[k] = vl;
+            const uint32_t Ls = st ? L : 3u;
+            const uint32_t own = (~0u >> (8u * Ls)) & 0xFFFFFF00u;
+            cbytes = (own & vh) | (~own & cbytes);
+            cmin = Ls < cmin ? Ls : cmin;
+        }
+    } else if (K < 64) {
         const uint32_t up = (uint32_t)(32 - K);
         // residual width of each code, one byte apiece
         const uint32_t rtab = resid_bits(K, 0) | (resid_bits(K, 1) << 8) | (resid_bits(K, 2) << 16) |
@@ -453,16 +764,101 @@ struct EncPlan {
     uint32_t c0h, c0l, c1h, c1l;  // values 0 and 1 (CONST2)
     int mode, lev, K;
     uint32_t size;
+    bool ent;               // the body's residuals are entropy-coded
+    uint32_t ent_off;       // bit offset of my sub-stream in the entropy-coded bit stream
+    uint32_t ent_bits;      // its length
+    uint32_t laneword;      // lane modes (2 bits per lane)
 };
+
+// the stored values a thread codes (PACK: all, SPARSE: the nonzero ones) and
+// their two-bit codes (PACK: by position, SPARSE: in rank order)
+template <int V>
+__device__ __forceinline__ void ent_values(const EncPlan<V> &e, uint32_t &mask, uint32_t &codes, bool &sparse)
+{
+    const uint32_t vmask = (V >= 32) ? ~0u : ((1u << V) - 1u);
+    sparse = e.mode == M_SPARSE;
+    mask = e.mode == M_CONST2 ? 0u : (sparse ? e.nzm : vmask);
+    codes = sparse ? e.scodes : e.codes;
+}
+
+// Entropy stage of the plan (ENT kernels, ent_on uniform over the launch).
+// The entropy helpers are called, not inlined (ent_plan, ent_emit,
+// ent_build_lane): inlined into the job kernel at three workgroups per CU,
+// the plan came out wrong (tests/test_gpu_entropy.py), called it is exact
+// and its registers stay out of the kernel's allocation.
+// lane histograms (four copies, by lane & 3, in the slot's buffer b, free
+// once the plan's scans have passed), one builder thread per lane, the size
+// of the entropy-coded body from the lanes' costs, and each thread's bit
+// offset.  Contains barriers: every thread calls it.
+template <int V, int WPG>
+__device__ __noinline__ void ent_plan(EncPlan<V> &e, int C, int lt, uint32_t *b, uint32_t *ent, uint32_t *slot)
+{
+    constexpr int G = 64 * WPG;
+    const int K = e.K, NN = ent_lanes(K);
+    uint32_t mask, codes;
+    bool sparse;
+    ent_values<V>(e, mask, codes, sparse);
+    uint32_t *hist = b;
+    for (int i = lt; i < 1024; i += G) hist[i] = 0u;
+    lds_barrier();
+    const uint32_t rep = threadIdx.x & 3u;
+    {
+        uint32_t j2 = 0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const bool on = ((mask >> k) & 1u) != 0;
+            const uint32_t L = __builtin_amdgcn_ubfe(codes, sparse ? (j2 & 31u) : 2u * k, 2u);
+            j2 += on ? 2u : 0u;
+            for (int j = on ? 2 * (int)L : NN; j < NN; ++j)
+                atomicAdd(&hist[(rep * 16u + (uint32_t)j) * 16u + ent_sym(e.th[k], e.tl[k], K, j)], 1u);
+        }
+    }
+    lds_barrier();
+    uint16_t *enc = reinterpret_cast<uint16_t *>(ent);
+    uint32_t *rec = ent + kEntRecWord0;
+    if (lt < NN) ent_build_lane(hist, b + 1024 + 32 * lt, K, lt, enc, rec);
+    lds_barrier();
+    uint32_t bits = 0, nibs = 0, lw = 0;
+    for (int j = 0; j < NN; ++j) {
+        const uint32_t r0 = rec[4 * j];
+        bits += rec[4 * j + 1];
+        nibs += r0 >> 8;
+        lw |= (r0 & 3u) << (2 * j);
+    }
+    const uint32_t N = sparse ? e.nnz : (uint32_t)C;
+    const uint32_t lead = sparse ? 4u + 4u * (uint32_t)((C + 31) / 32) : 4u;
+    const uint32_t esize = lead + 4u * ((N + 15u) / 16u) + 4u + 4u * ((nibs + 7u) / 8u) +
+                           4u * ((12u * (uint32_t)(C / 16) + 31u) / 32u) + (bits + 7u) / 8u;
+    const bool take = e.mode != M_CONST2 && esize < e.size;
+    uint32_t mine = 0;
+    if (take) {
+        uint32_t j2 = 0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const bool on = ((mask >> k) & 1u) != 0;
+            const uint32_t L = __builtin_amdgcn_ubfe(codes, sparse ? (j2 & 31u) : 2u * k, 2u);
+            j2 += on ? 2u : 0u;
+            for (int j = on ? 2 * (int)L : NN; j < NN; ++j)
+                mine += (uint32_t)enc[16 * j + ent_sym(e.th[k], e.tl[k], K, j)] >> 8;
+        }
+    }
+    uint32_t tot;
+    gscan_add<WPG>(mine, slot, e.ent_off, tot);
+    e.ent = take;
+    e.ent_bits = mine;
+    e.laneword = lw;
+    if (take) e.size = esize;
+}
 
 // Plan the stream of one chunk.  x: my values (hi, lo); xprev_hi: high word of
 // the value before mine; x0/x1: values 0 and 1 of the chunk.  `sub` is the
 // group's subnormal flag.  Contains barriers: every thread calls it; the plan
 // of a group with no chunk (stale values) is computed and ignored.
-template <int V, int WPG>
+template <int V, int WPG, bool ENT = false>
 __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], uint32_t xprev_hi, uint64_t x0,
                             uint64_t x1, int lev_req, bool sub, int C, int lt, uint32_t *slotB,
-                            uint32_t *slotC, EncPlan<V> &e)
+                            uint32_t *slotC, EncPlan<V> &e, bool ent_on = false, uint32_t *b = nullptr,
+                            uint32_t *ent = nullptr, uint32_t *slotD = nullptr)
 {
     const int first = lt * V;
     const int lev = sub ? 0 : lev_req;  // a chunk with a subnormal is kept lossless
@@ -543,6 +939,9 @@ __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], ui
     if (const2) { e.mode = M_CONST2; e.size = 20; }
     else if (need_me && sparse_size < pack_size) { e.mode = M_SPARSE; e.size = sparse_size; }
     else { e.mode = M_PACK; e.size = pack_size; }
+    e.ent = false;
+    e.ent_off = e.ent_bits = e.laneword = 0;
+    if (ENT && ent_on) ent_plan<V, WPG>(e, C, lt, b, ent, slotD);
 }
 
 // OR an r-bit field (r <= 32) into the word stream at bit offset o
@@ -618,12 +1017,79 @@ __device__ __forceinline__ void emit_residuals(uint32_t *b, int base, uint32_t o
     }
 }
 
+// OR a field of r <= 64 bits into the word stream at bit offset o
+__device__ __forceinline__ void or_field(uint32_t *b, int base, uint32_t o, uint64_t v, uint32_t r)
+{
+    if (r == 0) return;
+    const uint32_t sh = o & 31u;
+    const int wi = base + (int)(o >> 5);
+    const uint64_t lo = v << sh;
+    atomicOr(&b[clampw(wi)], (uint32_t)lo);
+    if ((uint32_t)(lo >> 32)) atomicOr(&b[clampw(wi + 1)], (uint32_t)(lo >> 32));
+    if (sh + r > 64u) atomicOr(&b[clampw(wi + 2)], (uint32_t)(v >> (64u - sh)));
+}
+
+// entropy-coded body after the codes area (word ew0): lane word, table
+// nibbles (lane builders), my sub-stream's length field and my codes
+template <int V>
+__device__ __noinline__ void ent_emit(uint32_t *b, const EncPlan<V> &e, int C, int lt, int ew0, const uint32_t *ent)
+{
+    const int K = e.K, NN = ent_lanes(K);
+    const uint16_t *enc = reinterpret_cast<const uint16_t *>(ent);
+    const uint32_t *rec = ent + kEntRecWord0;
+    uint32_t nibs = 0, off = 0;
+    for (int j = 0; j < NN; ++j) {
+        const uint32_t n = rec[4 * j] >> 8;
+        off += j < lt ? n : 0u;
+        nibs += n;
+    }
+    if (lt == 0) b[ew0] = e.laneword;
+    if (lt < NN) {
+        const uint32_t r0 = rec[4 * lt];
+        const uint32_t n = r0 >> 8;
+        const uint64_t v = (r0 & 3u) == LANE_CONST ? (uint64_t)((r0 >> 4) & 15u)
+                                                    : (((uint64_t)rec[4 * lt + 3] << 32) | rec[4 * lt + 2]);
+        or_field(b, ew0 + 1, 4u * off, v, 4u * n);
+    }
+    const int sw0 = ew0 + 1 + (int)((nibs + 7u) >> 3);
+    or_field(b, sw0, 12u * (uint32_t)lt, e.ent_bits, 12u);
+    const int bw0 = sw0 + ((12 * (C / 16) + 31) >> 5);
+    uint32_t mask, codes;
+    bool sparse;
+    ent_values<V>(e, mask, codes, sparse);
+    uint64_t acc = 0;
+    uint32_t nb = e.ent_off & 31u;
+    int wi = bw0 + (int)(e.ent_off >> 5);
+    bool first = true;
+    uint32_t j2 = 0;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const bool on = ((mask >> k) & 1u) != 0;
+        const uint32_t L = __builtin_amdgcn_ubfe(codes, sparse ? (j2 & 31u) : 2u * k, 2u);
+        j2 += on ? 2u : 0u;
+        for (int j = on ? 2 * (int)L : NN; j < NN; ++j) {
+            const uint32_t x = enc[16 * j + ent_sym(e.th[k], e.tl[k], K, j)];
+            acc |= (uint64_t)(x & 0xFFu) << nb;
+            nb += x >> 8;
+            if (nb >= 32u) {
+                if (first) atomicOr(&b[clampw(wi)], (uint32_t)acc);
+                else b[clampw(wi)] = (uint32_t)acc;
+                first = false;
+                ++wi;
+                acc >>= 32;
+                nb -= 32u;
+            }
+        }
+    }
+    if (nb > 0u) atomicOr(&b[clampw(wi)], (uint32_t)acc);
+}
+
 // write the planned stream into b[] (already zeroed); no barriers inside
 template <int V>
-__device__ void encode_emit(uint32_t *b, const EncPlan<V> &e, int C, int lt)
+__device__ void encode_emit(uint32_t *b, const EncPlan<V> &e, int C, int lt, const uint32_t *ent = nullptr)
 {
     const int first = lt * V;
-    if (lt == 0) b[0] = (uint32_t)e.mode | ((uint32_t)e.lev << 2);
+    if (lt == 0) b[0] = (uint32_t)e.mode | ((uint32_t)e.lev << 2) | (e.ent ? kHdrEnt : 0u);
     if (e.mode == M_CONST2) {
         if (lt == 0) {
             b[1] = e.c0l; b[2] = e.c0h;
@@ -636,7 +1102,8 @@ __device__ void encode_emit(uint32_t *b, const EncPlan<V> &e, int C, int lt)
         const uint32_t bit = 2u * (uint32_t)first;
         if (V == 16) b[1 + (bit >> 5)] = e.codes;
         else atomicOr(&b[1 + (bit >> 5)], e.codes << (bit & 31));
-        emit_residuals<V>(b, 1 + C / 16, e.pack_off, e, vmask, e.codes, false);
+        if (e.ent) ent_emit<V>(b, e, C, lt, 1 + C / 16, ent);
+        else emit_residuals<V>(b, 1 + C / 16, e.pack_off, e, vmask, e.codes, false);
     } else {  // M_SPARSE
         if (e.nzm) atomicOr(&b[1 + (first >> 5)], e.nzm << (first & 31));
         const int cw0 = 1 + ((C + 31) >> 5);
@@ -648,7 +1115,8 @@ __device__ void encode_emit(uint32_t *b, const EncPlan<V> &e, int C, int lt)
             if ((uint32_t)v) atomicOr(&b[clampw(wi)], (uint32_t)v);
             if ((uint32_t)(v >> 32)) atomicOr(&b[clampw(wi + 1)], (uint32_t)(v >> 32));
         }
-        emit_residuals<V>(b, cw0 + (int)((e.nnz + 15u) >> 4), e.sp_off, e, e.nzm, e.scodes, true);
+        if (e.ent) ent_emit<V>(b, e, C, lt, cw0 + (int)((e.nnz + 15u) >> 4), ent);
+        else emit_residuals<V>(b, cw0 + (int)((e.nnz + 15u) >> 4), e.sp_off, e, e.nzm, e.scodes, true);
     }
 }
 
@@ -937,7 +1405,7 @@ __device__ __forceinline__ uint64_t op_mask(const GateDesc &gd, int cb)
 // leader jobs and leaves the gate open; LIST 2 computes the followers that the
 // copy kernel did not copy (their bytes differ from their leader's) and closes
 // the gate over the leaders' launch, the copy kernel and itself.
-template <int V, int WPG, int SRC, int DST, bool GATE, int LIST = 0>
+template <int V, int WPG, int SRC, int DST, bool GATE, int LIST = 0, bool ENT = false>
 __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDesc gd, DevPtrs P, IOPtrs io)
 {
     constexpr int G = 64 * WPG;   // threads per chunk slot
@@ -955,6 +1423,8 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     __shared__ double sh_m[8];
     __shared__ double sh_rm[LIST == 3 ? kMaxRun : 1][8];   // fused run: the gates' matrices
     __shared__ uint32_t sh_rsub[2][WGS / 64];              // fused run: subnormal flags, alternating per gate
+    // entropy stage, per slot: decode tables while decoding, encode tables and lane records while encoding
+    __shared__ __align__(16) uint32_t sh_ent[ENT ? 2 : 1][ENT ? kEntSlotWords : 1];
 
     DevState *ds = P.ds;
     if (DST == DST_ARENA && ds->stop) return;
@@ -970,7 +1440,10 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     double *vals = reinterpret_cast<double *>(b);
     const int first = lt * V;
     // LDS slots of the scans (per call site)
-    uint32_t *slA = sh, *slB = sh + 16, *slC = sh + 32, *slE = sh + 48, *slF = sh + 176, *slS = sh + 192;
+    uint32_t *slA = sh, *slB = sh + 16, *slC = sh + 32, *slE = sh + 48, *slF = sh + 176, *slS = sh + 192,
+             *slD = sh + 224;
+    uint32_t *ent = sh_ent[ENT ? s : 0];
+    const bool ent_on = ENT && gd.entropy != 0;
     const int glevel = (DST == DST_ARENA || DST == DST_SLOTS) && gd.fixed_level < 0 && !gd.per_block ? ds->level : 0;
     const uint64_t ds_nstripes = DST == DST_ARENA ? ds->nstripes : 1;
     const uint64_t ds_base = DST == DST_ARENA ? ds->base : 0;           // fixed while a gate runs
@@ -1043,8 +1516,10 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             const uint32_t hdr1 = use1 ? buf[1][0] : (uint32_t)M_CONST2;
             my_hdr = s ? hdr1 : hdr0;
             const bool any_sparse = (hdr0 & 3u) == M_SPARSE || (hdr1 & 3u) == M_SPARSE;
+            const bool any_ent = ENT && ((hdr0 | hdr1) & kHdrEnt) != 0;
             uint32_t th[V], tl[V];
-            decode_group<V, WPG>(b, s ? hdr1 : hdr0, use, any_sparse, C, lt, slA, slB, slC, th, tl);
+            decode_group<V, WPG, ENT>(b, s ? hdr1 : hdr0, use, any_sparse, C, lt, slA, slB, slC, th, tl, any_ent,
+                                      reinterpret_cast<uint8_t *>(ent));
             lds_barrier();
             double x[V];
 #pragma unroll
@@ -1200,7 +1675,8 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             for (int i = 0; i < WPG; ++i) gs |= slS[s * WPG + i];
             for (int lev = 0; lev < kLevels; ++lev) {
                 EncPlan<V> e;
-                encode_plan<V, WPG>(xh, xl, xprev_hi, x0, x1, lev, gs != 0, C, lt, slE, slF, e);
+                encode_plan<V, WPG, ENT>(xh, xl, xprev_hi, x0, x1, lev, gs != 0, C, lt, slE, slF, e, ent_on, b, ent,
+                                         slD);
                 if (lt == 0 && use)
                     atomicAdd((unsigned long long *)&io.lsizes[(c >> gd.block_shift) * kLevels + lev],
                               (unsigned long long)((e.size + 3u) & ~3u));
@@ -1243,7 +1719,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                 }
             }
             EncPlan<V> e;
-            encode_plan<V, WPG>(xh, xl, xprev_hi, x0, x1, lev_req, gsub, C, lt, slE, slF, e);
+            encode_plan<V, WPG, ENT>(xh, xl, xprev_hi, x0, x1, lev_req, gsub, C, lt, slE, slF, e, ent_on, b, ent, slD);
             if (DST == DST_ARENA && gd.per_block && enc) {
                 double post = 0.0;
 #pragma unroll
@@ -1268,7 +1744,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                 for (uint32_t w = lt; w < (words + 3u) >> 2; w += G) b4[w] = make_uint4(0u, 0u, 0u, 0u);
             }
             lds_barrier();
-            if (enc) encode_emit<V>(b, e, C, lt);
+            if (enc) encode_emit<V>(b, e, C, lt, ent);
             if (lt == 0) {
                 int ok = 0;
                 if (enc) {
@@ -1842,15 +2318,16 @@ __global__ __launch_bounds__(kWG) void compact_copy_kernel(DevPtrs P, uint32_t *
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-template <int V, int WPG, int SRC, int DST, bool GATE>
+template <int V, int WPG, int SRC, int DST, bool GATE, bool ENT = false>
 static void launch_vw(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st,
                       hipEvent_t t0, hipEvent_t t1)
 {
     if (t0) {  // events attached to the dispatch itself: they time exactly this kernel
-        hipExtLaunchKernelGGL((job_kernel<V, WPG, SRC, DST, GATE>), dim3(grid), dim3(128 * WPG), 0, st, t0, t1, 0, gd,
-                              P, io);
+        hipExtLaunchKernelGGL((job_kernel<V, WPG, SRC, DST, GATE, 0, ENT>), dim3(grid), dim3(128 * WPG), 0, st, t0, t1,
+                              0, gd, P, io);
     } else {
-        hipLaunchKernelGGL((job_kernel<V, WPG, SRC, DST, GATE>), dim3(grid), dim3(128 * WPG), 0, st, gd, P, io);
+        hipLaunchKernelGGL((job_kernel<V, WPG, SRC, DST, GATE, 0, ENT>), dim3(grid), dim3(128 * WPG), 0, st, gd, P,
+                           io);
     }
 }
 
@@ -1864,6 +2341,11 @@ static hipError_t launch_job(const GateDesc &gd, const DevPtrs &P, const IOPtrs 
     const int threads = 64 * wpg;
     if (P.C % threads) return hipErrorInvalidValue;
     const int V = P.C / threads;
+    if (gd.entropy) {   // the entropy stage: 2048-double chunks, two wavefronts per chunk
+        if (V != 16 || wpg != 2) return hipErrorInvalidValue;
+        launch_vw<16, 2, SRC, DST, GATE, true>(gd, P, io, grid, st, t0, t1);
+        return hipGetLastError();
+    }
     const int key = wpg * 100 + V;
     switch (key) {
     case 201: launch_vw<1, 2, SRC, DST, GATE>(gd, P, io, grid, st, t0, t1); break;
@@ -1903,15 +2385,16 @@ static void launch_list_v(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io
         hipLaunchKernelGGL((job_kernel<V, 2, SRC_ARENA, DST_ARENA, true, 2>), dim3(grid), dim3(256), 0, st, gd, P, io);
 }
 
-template <int V>
+template <int V, bool ENT = false>
 static void launch_run_v(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st,
                          hipEvent_t t0, hipEvent_t t1)
 {
     if (t0)
-        hipExtLaunchKernelGGL((job_kernel<V, 2, SRC_ARENA, DST_ARENA, true, 3>), dim3(grid), dim3(256), 0, st, t0, t1,
-                              0, gd, P, io);
+        hipExtLaunchKernelGGL((job_kernel<V, 2, SRC_ARENA, DST_ARENA, true, 3, ENT>), dim3(grid), dim3(256), 0, st, t0,
+                              t1, 0, gd, P, io);
     else
-        hipLaunchKernelGGL((job_kernel<V, 2, SRC_ARENA, DST_ARENA, true, 3>), dim3(grid), dim3(256), 0, st, gd, P, io);
+        hipLaunchKernelGGL((job_kernel<V, 2, SRC_ARENA, DST_ARENA, true, 3, ENT>), dim3(grid), dim3(256), 0, st, gd, P,
+                           io);
 }
 
 hipError_t launch_gate_run(const GateDesc &gd, const DevPtrs &P, const GateDesc *run, int nrun, int grid,
@@ -1921,6 +2404,11 @@ hipError_t launch_gate_run(const GateDesc &gd, const DevPtrs &P, const GateDesc 
     IOPtrs io = {};
     io.run = run;
     io.nrun = nrun;
+    if (gd.entropy) {
+        if (P.C != kCMax) return hipErrorInvalidValue;
+        launch_run_v<16, true>(gd, P, io, grid, st, t0, t1);
+        return hipGetLastError();
+    }
     switch (P.C / 128) {
     case 1: launch_run_v<1>(gd, P, io, grid, st, t0, t1); break;
     case 2: launch_run_v<2>(gd, P, io, grid, st, t0, t1); break;
@@ -1935,7 +2423,8 @@ hipError_t launch_gate_run(const GateDesc &gd, const DevPtrs &P, const GateDesc 
 hipError_t launch_gate_list(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, int list, int grid,
                             hipStream_t st)
 {
-    if ((list != 1 && list != 2) || grid < 1 || grid > kMaxGrid / 2 || P.C % 128) return hipErrorInvalidValue;
+    if ((list != 1 && list != 2) || grid < 1 || grid > kMaxGrid / 2 || P.C % 128 || gd.entropy)
+        return hipErrorInvalidValue;
     IOPtrs io = {};
     io.role = cp.role;
     io.owner = cp.owner;

@@ -183,6 +183,19 @@ DevPtrs ptrs(const qcz_state *s)
 
 int popcount64(uint64_t x) { return __builtin_popcountll(x); }
 
+// the state's encoder may take the entropy-coded body; its kernels decode it
+int ent_state(const qcz_state *s) { return (s->cfg.flags & QCZ_FLAG_ENTROPY) ? 1 : 0; }
+
+// A stream header: mode, level, and the entropy bit (only where the state
+// may hold entropy-coded streams, and never on a CONST2 stream).
+bool header_ok(const qcz_state *s, uint32_t hdr, size_t len)
+{
+    const uint32_t mode = hdr & 3u, lev = (hdr >> 2) & 7u, ent = (hdr >> 5) & 1u;
+    if ((hdr >> 6) != 0 || lev >= (uint32_t)kLevels || mode > M_SPARSE) return false;
+    if (ent && (!ent_state(s) || mode == M_CONST2)) return false;
+    return mode != M_CONST2 || len == 20;
+}
+
 bool is_unit(double re, double im) { return re == 1.0 && im == 0.0; }
 
 qcz_status check_gate(const qcz_state *s, const qcz_gate &g)
@@ -225,6 +238,7 @@ GateDesc lower_gate(const qcz_state *s, const qcz_gate &g, int seq)
     d.per_block = s->cfg.mode == QCZ_MODE_PERBLOCK ? 1 : 0;
     d.block_shift = s->bl - s->cb;
     d.fixed_level = -1;
+    d.entropy = ent_state(s);
     const uint64_t cm_hi = g.control_mask >> s->cb;
     const uint64_t cm_lo = g.control_mask & ((1ull << s->cb) - 1);
     if ((g.kind == K_U1 || g.kind == K_X) && (int)g.target >= s->cb) {
@@ -615,6 +629,7 @@ qcz_status single_kernel_chunks(qcz_state *s, GateDesc &d, uint64_t nitems, uint
     d.nitems = nitems;
     d.njobs = (nitems + 1) / 2;
     d.fixed_level = -1;
+    d.entropy = ent_state(s);
     int bits = 0;
     while ((1ull << bits) < nitems) ++bits;
     d.nchunk_bits = bits;
@@ -927,6 +942,10 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
         return QCZ_E_INVAL;
     if (((uintptr_t)dev_pool & 255) != 0) return QCZ_E_INVAL;
     if ((cfg->flags & (QCZ_FLAG_CACHE | QCZ_FLAG_FUSE)) && (cfg->flags & QCZ_FLAG_AUTOTUNE)) return QCZ_E_INVAL;
+    if ((cfg->flags & QCZ_FLAG_ENTROPY) &&
+        (cfg->block_log2 < 10 || (cfg->flags & (QCZ_FLAG_CACHE | QCZ_FLAG_AUTOTUNE)) ||
+         (cfg->chunk_waves != 0 && cfg->chunk_waves != 2)))
+        return QCZ_E_INVAL;
     if (pool_bytes < qcz_pool_bytes_min(cfg)) return QCZ_E_NOMEM;
 
     qcz_state *s = new qcz_state();
@@ -1000,7 +1019,8 @@ qcz_status qcz_create(const qcz_config *cfg, void *dev_pool, size_t pool_bytes, 
     init[0] = 1.0;
     if (hipMemcpyAsync(raw, init.data(), init.size() * 8, hipMemcpyHostToDevice, s->stream) != hipSuccess)
         return bail(QCZ_E_DEVICE);
-    if (qcz_encode_chunks(raw, (uint32_t)s->C, 2, 0, slots, slot, sizes, s->stream) != QCZ_OK) return bail(QCZ_E_DEVICE);
+    if (qcz_encode_chunks(raw, (uint32_t)s->C, 2, 0, 0, slots, slot, sizes, s->stream) != QCZ_OK)
+        return bail(QCZ_E_DEVICE);
     uint32_t hsz[2] = {0, 0};
     if (hipMemcpyAsync(hsz, sizes, 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess) return bail(QCZ_E_DEVICE);
     if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(QCZ_E_DEVICE);
@@ -1219,9 +1239,7 @@ qcz_status qcz_import_state(qcz_state *s, const void *host_buf, size_t len, cons
             return fail(s, QCZ_E_FORMAT, "stream size out of range");
         const uint32_t hdr = (uint32_t)p[off] | ((uint32_t)p[off + 1] << 8) | ((uint32_t)p[off + 2] << 16) |
                              ((uint32_t)p[off + 3] << 24);
-        const uint32_t mode = hdr & 3u, lev = (hdr >> 2) & 7u;
-        if ((hdr >> 5) != 0 || lev >= (uint32_t)kLevels || mode > M_SPARSE || (mode == M_CONST2 && sz != 20))
-            return fail(s, QCZ_E_FORMAT, "bad stream header");
+        if (!header_ok(s, hdr, sz)) return fail(s, QCZ_E_FORMAT, "bad stream header");
         tab[c] = ((off / 4) << 16) | (uint64_t)sz;
         off += alloc_bytes(sz);
         live += (sz + 3u) & ~3u;
@@ -1285,7 +1303,8 @@ qcz_status qcz_set_launch(qcz_state *s, uint32_t chunk_waves, uint32_t grid)
 {
     if (!s) return QCZ_E_INVAL;
     if (chunk_waves) {
-        if ((chunk_waves != 2 && chunk_waves != 4 && chunk_waves != 8) || s->C % (64 * (int)chunk_waves) != 0)
+        if ((chunk_waves != 2 && chunk_waves != 4 && chunk_waves != 8) || s->C % (64 * (int)chunk_waves) != 0 ||
+            (ent_state(s) && chunk_waves != 2))
             return fail(s, QCZ_E_INVAL, "unsupported chunk_waves");
         s->chunk_waves = (int)chunk_waves;
     }
@@ -1498,6 +1517,7 @@ qcz_status qcz_overlap(qcz_state *a, qcz_state *b, double *out_re, double *out_i
         const uint64_t m = std::min<uint64_t>(kScratchChunks, a->nchunks - c0);
         GateDesc d{};
         single_kernel_chunks(a, d, m, 0);
+        d.entropy = ent_state(a) | ent_state(b);   // entropy kernels decode both kinds of stream
         IOPtrs io{};
         io.first = c0;
         io.raw_out = ra;
@@ -1539,9 +1559,7 @@ qcz_status qcz_import_chunk(qcz_state *s, uint64_t chunk, const void *host_buf, 
     if (len < 4 || len > chunk_cap_bytes(s->C)) return fail(s, QCZ_E_FORMAT, "stream length out of range");
     const uint8_t *p = (const uint8_t *)host_buf;
     const uint32_t hdr = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
-    const uint32_t mode = hdr & 3u, lev = (hdr >> 2) & 7u;
-    if ((hdr >> 5) != 0 || lev >= (uint32_t)kLevels || mode > M_SPARSE || (mode == M_CONST2 && len != 20))
-        return fail(s, QCZ_E_FORMAT, "bad stream header");
+    if (!header_ok(s, hdr, len)) return fail(s, QCZ_E_FORMAT, "bad stream header");
     const uint64_t pad = (len + 3) & ~(size_t)3;   // ledger size
     const uint64_t room_needed = alloc_bytes((uint32_t)len);   // arena allocation (16-byte units)
     auto emptiest = [&]() {
@@ -1589,11 +1607,13 @@ qcz_status qcz_chunk_sizes(qcz_state *s, uint32_t *out_sizes)
     return QCZ_OK;
 }
 
-qcz_status qcz_encode_chunks(const void *dev_in, uint32_t C, uint64_t n_chunks, int level, void *dev_slots,
-                             size_t slot_bytes, uint32_t *dev_sizes, void *hip_stream)
+qcz_status qcz_encode_chunks(const void *dev_in, uint32_t C, uint64_t n_chunks, int level, uint32_t codec_flags,
+                             void *dev_slots, size_t slot_bytes, uint32_t *dev_sizes, void *hip_stream)
 {
     if (!dev_in || !dev_slots || !dev_sizes) return QCZ_E_INVAL;
     if (C < (uint32_t)kCMin || C > (uint32_t)kCMax || (C & (C - 1)) || level < 0 || level >= kLevels) return QCZ_E_INVAL;
+    if ((codec_flags & ~QCZ_CODEC_ENTROPY) || ((codec_flags & QCZ_CODEC_ENTROPY) && C != (uint32_t)kCMax))
+        return QCZ_E_INVAL;
     if (slot_bytes < chunk_cap_bytes((int)C) || (slot_bytes & 3)) return QCZ_E_INVAL;
     if (n_chunks == 0) return QCZ_OK;
     GateDesc d{};
@@ -1604,6 +1624,7 @@ qcz_status qcz_encode_chunks(const void *dev_in, uint32_t C, uint64_t n_chunks, 
     while ((1ull << bits) < n_chunks) ++bits;
     d.nchunk_bits = bits;
     d.fixed_level = level;
+    d.entropy = (codec_flags & QCZ_CODEC_ENTROPY) ? 1 : 0;
     DevPtrs P{};
     P.C = (int)C;
     int cb = 0;
@@ -1634,6 +1655,7 @@ qcz_status qcz_decode_chunks(const void *dev_slots, size_t slot_bytes, const uin
     while ((1ull << bits) < n_chunks) ++bits;
     d.nchunk_bits = bits;
     d.fixed_level = 0;
+    d.entropy = C == (uint32_t)kCMax ? 1 : 0;   // those kernels decode streams with and without the entropy stage
     DevPtrs P{};
     P.C = (int)C;
     IOPtrs io{};

@@ -23,6 +23,8 @@ FLAG_RANGES = 8
 FLAG_CACHE = 16
 FLAG_CACHE_COLLIDE = 32
 FLAG_FUSE = 64
+FLAG_ENTROPY = 128
+CODEC_ENTROPY = 1
 STATUS = {0: "QCZ_OK", -1: "QCZ_E_INVAL", -2: "QCZ_E_NOMEM", -3: "QCZ_E_DEVICE", -4: "QCZ_E_FORMAT",
           -5: "QCZ_E_STATE"}
 
@@ -123,7 +125,7 @@ def load():
     L.qcz_chunk_cap.restype = sz
     L.qcz_chunk_cap.argtypes = [u32]
     L.qcz_encode_chunks.restype = i32
-    L.qcz_encode_chunks.argtypes = [vp, u32, u64, i32, vp, sz, vp, vp]
+    L.qcz_encode_chunks.argtypes = [vp, u32, u64, i32, u32, vp, sz, vp, vp]
     L.qcz_decode_chunks.restype = i32
     L.qcz_decode_chunks.argtypes = [vp, sz, vp, u32, u64, vp, vp]
     L.qcz_get_stats.restype = i32
@@ -408,8 +410,9 @@ class State:
 
 
 # -- codec entry points -----------------------------------------------------
-def encode_chunks(x, level: int, stream=None):
-    """x: cuda float64 tensor [n, C].  Returns (slots uint8 [n, slot], sizes)."""
+def encode_chunks(x, level: int, stream=None, codec_flags: int = 0):
+    """x: cuda float64 tensor [n, C].  Returns (slots uint8 [n, slot], sizes).
+    codec_flags: CODEC_ENTROPY lets chunks take the entropy-coded body."""
     torch = _torch()
     L = load()
     n, C = x.shape
@@ -417,8 +420,8 @@ def encode_chunks(x, level: int, stream=None):
     slots = torch.zeros((n, slot), dtype=torch.uint8, device=x.device)
     sizes = torch.zeros(n, dtype=torch.int32, device=x.device)
     st = stream if stream is not None else torch.cuda.current_stream()
-    rc = L.qcz_encode_chunks(x.contiguous().data_ptr(), C, n, level, slots.data_ptr(), slot, sizes.data_ptr(),
-                             st.cuda_stream)
+    rc = L.qcz_encode_chunks(x.contiguous().data_ptr(), C, n, level, codec_flags, slots.data_ptr(), slot,
+                             sizes.data_ptr(), st.cuda_stream)
     if rc != 0:
         raise QczError(rc, "qcz_encode_chunks")
     st.synchronize()
