@@ -256,6 +256,8 @@ def main():
     ap.add_argument("--selector", action="store_true", help="qaoa34: also run the learned per-block selector")
     ap.add_argument("--fuse", action="store_true",
                     help="grover24/qft24: fuse runs of in-chunk single-qubit gates (a separate figure)")
+    ap.add_argument("--entropy", action="store_true",
+                    help="the entropy-coding stage (per-lane Huffman codes of the residuals, QCZ_FLAG_ENTROPY)")
     ap.add_argument("--cache", action="store_true",
                     help="grover24/qft24: run with the compressed block cache (a separate figure: each gate is "
                          "then a planning kernel plus two job launches, timed together)")
@@ -294,6 +296,8 @@ def main():
         flags |= qcz.FLAG_CACHE
     if args.fuse:
         flags |= qcz.FLAG_FUSE
+    if args.entropy:
+        flags |= qcz.FLAG_ENTROPY
     stream = torch.cuda.Stream()
 
     # --- inputs resident in HBM before timing -------------------------------

@@ -487,13 +487,36 @@ __device__ __noinline__ void ent_build_lane(const uint32_t *hist, uint32_t *q, i
         for (int s = 0; s < 16; ++s) coded += c[s] * nib64(len, s);
         if (coded < raw) { mode = LANE_CODED; cost = coded - 4u * nsym; }
     }
+    // canonical codes: the first code of each length follows from the number
+    // of codes per length (8-bit fields, length l at bits 8(l-1)); symbols of
+    // one length then take consecutive codes in symbol order
+    uint64_t nx = 0;
+    if (mode == LANE_CODED) {
+        uint64_t cnt = 0;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const uint32_t l = nib64(len, s);
+            cnt += l ? (1ull << (8u * (l - 1u))) : 0ull;
+        }
+        uint32_t code = 0;
+#pragma unroll
+        for (int l = 1; l <= kEntMaxLen; ++l) {
+            if (l > 1) code = (code + (uint32_t)((cnt >> (8 * (l - 2))) & 0xFFu)) << 1;
+            nx |= (uint64_t)(code & 0xFFu) << (8 * (l - 1));
+        }
+    }
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
         uint32_t e = 0;
         if (mode == LANE_RAW) e = (uint32_t)s | ((uint32_t)w << 8);
         else if (mode == LANE_CODED) {
             const uint32_t l = nib64(len, s);
-            e = l ? (ent_rev(ent_canon_code(len, s, l), l) | (l << 8)) : 0u;
+            if (l) {
+                const uint32_t sh = 8u * (l - 1u);
+                const uint32_t code = (uint32_t)(nx >> sh) & 0xFFu;
+                nx += 1ull << sh;
+                e = ent_rev(code, l) | (l << 8);
+            }
         }
         enc[16 * j + s] = (uint16_t)e;
     }
