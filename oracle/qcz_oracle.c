@@ -899,6 +899,9 @@ static int gate_job_n2(const oq_gate *g, int cb, int C, int flags,
 {
     uint64_t ca = (uint64_t)C / 2;
     int two = in1 != NULL;
+    /* a pair job exactly for U1 / X gates whose target indexes chunks */
+    int pair_gate = (g->kind == OQ_U1 || g->kind == OQ_X) && (int)g->target >= cb;
+    if (pair_gate != two || (two && (c1 ^ c0) != (UINT64_C(1) << (g->target - cb)))) return -1;
     double *psi = (double *)malloc(sizeof(double) * (size_t)C * (two ? 2 : 1));
     int rc = oq_decode_chunk(in0, len0, C, psi);
     if (rc == 0 && two) rc = oq_decode_chunk(in1, len1, C, psi + C);
