@@ -1,23 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the fused compressed gate-apply path on one MI355X.
 
-Workload (default "grover24+qft24"): a 24-qubit Grover search with a seeded
-marked index and floor(pi/4 * 2^12) = 3216 iterations, and a 24-qubit QFT of
-a seeded basis state; complex128 amplitudes, 2^16-amplitude blocks (chunks of
-1024 amplitudes), error bound 1e-5 on every gate.  Synthetic circuits from
-paper_1911_04034_amd.circuits; inputs are created in HBM before timing.
-
-One step = one pass of the whole workload: the full QFT-24 circuit on a fresh
-state plus --grover-iters Grover iterations continuing the Grover state
-(--grover-iters 0 spreads the full 3216-iteration search over the passes).
+Default workload "qaoa34": the largest configuration that one GPU holds, a
+34-qubit QAOA circuit (H on every qubit, p = 4 layers of Rzz on a seeded
+3-regular graph and Rx mixers; 374 gates) on complex128 amplitudes, 2^20-
+amplitude blocks (chunks of 1024 amplitudes), error bound 1e-4 on every gate,
+256 GiB uncompressed.  The circuit is one continuing run cut into
+warmup + steps windows of consecutive gates; a step is one window.  Inputs
+(gate list, compressed state) are in HBM before timing.  Other workloads:
+grover24+qft24 (the 24-qubit pair), grid30, grover34.
 
 Prints one JSON line:
   value      = amplitudes through the fused kernel (touched chunks) per second
                of the timed region, in GAmp/s;
   roofline   = the fused kernel's algorithmic bytes (compressed streams read +
                written + 24 table/undo bytes per chunk) over its event-timed
-               average duration, against 8 TB/s;
-  cpu_baseline = the CPU oracle on a bounded sample of the same workload.
+               duration, against 8 TB/s, with the counter-measured traffic and
+               VALU-busy fraction when the profiles match the kernel source;
+  cpu_baseline = the CPU oracle on chunks exported from the same state, one
+               core and all host cores.
 """
 from __future__ import annotations
 
@@ -73,36 +74,76 @@ def qft_fidelity(st, n, x_in):
     return abs(ov), nrm
 
 
-def cpu_baseline(budget_s: float):
-    """The C oracle on a bounded sample: QFT-24 from its input state, gate by
-    gate, until the time budget is spent; returns amplitude-gates per second
-    over the touched chunks."""
+def _cpu_worker(job):
+    """One worker of the CPU leg: gate jobs of the oracle over exported chunks
+    until its share of the budget is spent; returns (amplitudes, seconds)."""
     from oracle import qcz_oracle as oq
-    from paper_1911_04034_amd import circuits as cc
-    n, bl, level = 24, 16, 1
-    gates = cc.qft(n, cc.qft_input(n, 2))
-    sim = oq.Sim(n, bl, oq.MODE_FIXED, level)
-    cb = sim.cb
-    ca = 1 << cb
-    # skip ahead cheaply over the X prefix and into the dense part of the circuit:
-    # the sample is the first gates whose chunks are no longer almost all zero
-    t_all = 0.0
-    amps = 0
-    k = 0
-    used = 0
-    while k < len(gates) and t_all < budget_s:
-        g = gates[k:k + 1]
-        touched = sum(1 for c in range(0, sim.nchunks) if oq.chunk_role(g, cb, c) in (1, 2, 3))
+    gates, chunks, cb, C, level, flags, budget = job
+    amps, t_all, k = 0, 0.0, 0
+    while t_all < budget:
+        g, c0, b0, c1, b1 = chunks[k % len(chunks)]
+        gate = gates[g:g + 1]
         t0 = time.perf_counter()
-        sim.apply(g)
-        dt = time.perf_counter() - t0
-        t_all += dt
-        amps += touched * ca
-        used += 1
+        if c1 is None:
+            oq.gate_job(gate, cb, C, c0, b0, level, flags=flags)
+            amps += C // 2
+        else:
+            oq.gate_job(gate, cb, C, c0, b0, level, c1, b1, level, flags=flags)
+            amps += C
+        t_all += time.perf_counter() - t0
         k += 1
-    return {"value": amps / t_all / 1e9 if t_all > 0 else 0.0, "unit": "GAmp/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d gates of QFT-24 (2^16-amplitude blocks, bound 1e-5) through the single-threaded "
-                      "C oracle, %.1f s" % (used, t_all)}
+    return amps, t_all
+
+
+def cpu_baseline(st, gates, level, budget_s: float, entropy: bool = False, desc: str = ""):
+    """The C oracle on a bounded sample of the same workload: chunks exported
+    from the GPU state where the timed region ended (each gate's input chunks,
+    as the blockwise loop reads them), pushed through the oracle's decode ->
+    gate -> encode (Sec. 3.1/3.3) for the workload's own gates.  First single-
+    threaded, then one process per host core; GAmp/s over the amplitudes of
+    the re-encoded chunks."""
+    import multiprocessing as mp
+    from oracle import qcz_oracle as oq
+    cb, C = st.cb, st.C
+    flags = oq.ENC_ENTROPY if entropy else 0
+    rng = np.random.default_rng(7)
+    sample = []
+    for gi in range(len(gates)):
+        g = gates[gi:gi + 1]
+        q = int(g["target"][0])
+        kind = int(g["kind"][0])
+        for c in rng.choice(st.nchunks, size=4, replace=False):
+            c = int(c)
+            if kind in (0, 3) and q >= cb:
+                c0 = c & ~(1 << (q - cb))
+                c1 = c0 | (1 << (q - cb))
+                sample.append((gi, c0, st.export_chunk(c0), c1, st.export_chunk(c1)))
+            else:
+                sample.append((gi, c, st.export_chunk(c), None, None))
+    half = budget_s / 2
+    a1, t1 = _cpu_worker((gates, sample, cb, C, level, flags, half))
+    cores = os.cpu_count() or 1
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    cores = min(cores, int(os.environ.get("QCZ_CPU_WORKERS", "16")))   # the host's CPU share for one GPU
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_cpu_worker, [(gates, sample[i::cores] or sample, cb, C, level, flags, half)
+                                     for i in range(cores)])
+    wall = time.perf_counter() - t0
+    amps = sum(a for a, _ in res)
+    model = ""
+    try:
+        model = next(x.split(":", 1)[1].strip() for x in open("/proc/cpuinfo") if x.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return {"value": amps / wall / 1e9, "unit": "GAmp/s", "cores": cores, "kind": "oracle",
+            "single_core": a1 / t1 / 1e9, "cpu_model": model, "nproc": os.cpu_count(),
+            "sample": "%s: %d chunk jobs (input chunks of the workload's gates, exported from the GPU state at the "
+                      "end of the timed region) through the C oracle's decode -> gate -> encode, %.1f s on one core "
+                      "then %.1f s wall on %d processes" % (desc, len(sample), t1, wall, cores)}
 
 
 LARGE = {
@@ -116,12 +157,14 @@ LARGE = {
 
 
 def large_config(args, torch, cc, qcz):
-    """One of the large configurations: every step runs the whole circuit on a
-    fresh compressed state (inputs: the gate list and the |0> state, both in
-    HBM before timing); fidelity is measured after the timed region."""
+    """A large configuration as one continuing run: the circuit is cut into
+    warmup + steps windows of consecutive gates; the warmup windows run first,
+    the timed steps are the rest (inputs: the gate list and the compressed
+    state, both in HBM before timing).  Fidelity after the timed region."""
     n, bl, desc = LARGE[args.workload]
     free, _total = torch.cuda.mem_get_info()
     budget = 0
+    w = None
     if args.workload == "grid30":
         gates, level, mode, pool = cc.grid_rcs(5, 6, 20, 3), 2, qcz.MODE_FIXED, 40 << 30
     elif args.workload == "grover34":
@@ -132,68 +175,35 @@ def large_config(args, torch, cc, qcz):
         gates = cc.qaoa(n, 4, 3, 5)[0]
         level, mode = 2, qcz.MODE_FIXED
         pool = min(250 << 30, free - (12 << 30))
-    flags = qcz.FLAG_TIMING | qcz.FLAG_RANGES | (qcz.FLAG_FUSE if args.fuse else 0)
-    slice_len = 16 if args.workload == "qaoa34" else 64
-    walls, stats, st, trace = [], [], None, []
-    for p in range(args.warmup + args.steps):
-        st = None
-        torch.cuda.empty_cache()
-        st = qcz.State(n, bl, mode=mode, level=level, budget=budget, pool_bytes=pool, flags=flags, batch=128)
-        torch.cuda.synchronize()
+    if args.gates:
+        gates = gates[:args.gates]
+    flags = qcz.FLAG_TIMING | qcz.FLAG_RANGES | (qcz.FLAG_FUSE if args.fuse else 0) | \
+        (qcz.FLAG_ENTROPY if args.entropy else 0)
+    passes = args.warmup + args.steps
+    win = -(-len(gates) // passes)
+    windows = [gates[k:k + win] for k in range(0, len(gates), win)]
+    st = qcz.State(n, bl, mode=mode, level=level, budget=budget, pool_bytes=pool, flags=flags, batch=128)
+    trace = [st.footprint()["compressed_bytes"]]
+    walls = []
+    t_all = None
+    for p, wg in enumerate(windows):
+        if p == args.warmup:
+            torch.cuda.synchronize()
+            st.reset_stats()
+            c0 = st.footprint()["compactions"]
+            t_all = time.perf_counter()
         t0 = time.perf_counter()
-        trace = []
-        for k in range(0, len(gates), slice_len):
-            st.apply(gates[k:k + slice_len])
-            fp = st.footprint()
-            trace.append(fp["compressed_bytes"])
-            log("%s pass %d: %d/%d gates, level %d, compressed %.2f GB" % (
-                args.workload, p, min(k + slice_len, len(gates)), len(gates), fp["level"],
-                fp["compressed_bytes"] / 1e9))
+        st.apply(wg)
         torch.cuda.synchronize()
-        if p >= args.warmup:
-            walls.append(time.perf_counter() - t0)
-            stats.append(st.stats())
+        walls.append(time.perf_counter() - t0)
+        fp = st.footprint()
+        trace.append(fp["compressed_bytes"])
+        log("%s window %d/%d (%d gates): level %d, compressed %.2f GB, %.2f s" % (
+            args.workload, p + 1, len(windows), len(wg), fp["level"], fp["compressed_bytes"] / 1e9, walls[-1]))
+    wall = time.perf_counter() - t_all if t_all is not None else 0.0
+    stats = st.stats()
     fp = st.footprint()
-    selector = None
-    if args.workload == "qaoa34" and args.selector:
-        # the learned per-block levels at the rule's per-step budget (1e-4), trained on
-        # the device from teacher traces of small circuits (12-13 qubits)
-        from paper_1911_04034_amd import selector as sel
-        train = [(cc.biased_local(12, 6, 8, 1), 12, 6), (cc.biased_local(13, 7, 8, 2), 13, 7),
-                 (cc.biased_local(13, 6, 8, 3), 13, 6), (cc.grover(12, 12, 11)[0], 12, 6),
-                 (cc.random_circuit_small(12, 12, 13), 12, 6), (cc.qft(12, cc.qft_input(12, 14)), 12, 6),
-                 (cc.qaoa(12, 3, 3, 15)[0], 12, 6)]
-        log("selector: teacher traces and training")
-        X, y = sel.training_set(train, (1e-5, 1e-4, 1e-3), 16)
-        params, losses = sel.train(X, y, steps=1500, lr=3e-3, seed=0)
-        acc = sel.accuracy(params, X, y)
-        st = None
-        torch.cuda.empty_cache()
-        st2 = qcz.State(n, bl, mode=qcz.MODE_PERBLOCK, level=0, pool_bytes=pool, batch=128, flags=qcz.FLAG_RANGES)
-        st2.set_selector(params, 1e-4, 16)
-        t0 = time.perf_counter()
-        strace = []
-        for k in range(0, len(gates), 16):
-            st2.apply(gates[k:k + 16])
-            f2 = st2.footprint()
-            strace.append(f2["compressed_bytes"])
-            log("qaoa34 selector: %d/%d gates, compressed %.2f GB" % (min(k + 16, len(gates)), len(gates),
-                                                                      f2["compressed_bytes"] / 1e9))
-        torch.cuda.synchronize()
-        f2 = st2.footprint()
-        selector = {"train_samples": int(X.shape[0]), "train_loss": [round(losses[0], 4), round(losses[-1], 4)],
-                    "train_accuracy": round(acc, 4), "wall_s": round(time.perf_counter() - t0, 2),
-                    "mean_compressed_bytes": float(np.mean(strace)), "peak_compressed_bytes": f2["max_compressed"],
-                    "fidelity_lower_bound": f2["fidelity_lower_bound"],
-                    "rule_mean_compressed_bytes": float(np.mean(trace)),
-                    "gain_mean_bytes": round(float(np.mean(trace)) / float(np.mean(strace)), 4)}
-        st = st2
-    amps = sum(x["amps_touched"] for x in stats)
-    kms = sum(x["gate_kernel_ms"] for x in stats)
-    timed = sum(x["timed_launches"] for x in stats)
-    launches = sum(x["gate_launches"] for x in stats)
-    byts = sum(x["bytes_read"] + x["bytes_written"] + x["table_bytes"] for x in stats)
-    wall = sum(walls)
+    timed_steps = len(windows) - args.warmup
     fid = {"fidelity_lower_bound": fp["fidelity_lower_bound"]}
     if args.workload == "grid30":
         # the uncompressed fp64 reference: the same circuit in lossless mode (every stored value is the exact
@@ -205,36 +215,96 @@ def large_config(args, torch, cc, qcz):
         n2 = st.moments()[1]
         fid.update({"fidelity_raw": abs(ov), "fidelity_norm": abs(ov) / math.sqrt(n2)})
         ex.close()
-    elif args.workload == "grover34":
+    elif args.workload == "grover34" and not args.gates:
         f_raw, nrm, aw = grover_fidelity(st, n, w, 8)
         fid.update({"fidelity_raw": f_raw, "fidelity_norm": f_raw / nrm, "marked_probability": aw ** 2})
+    amps = stats["amps_touched"]
+    kms = stats["gate_kernel_ms"]
+    timed = stats["timed_launches"]
+    byts = stats["bytes_read"] + stats["bytes_written"] + stats["table_bytes"]
     avg_ms = kms / timed if timed else 0.0
-    per_launch = byts / launches if launches else 0.0
-    if args.fuse:   # a fused run is one kernel for several gates
-        kernels = timed + sum(x["range_gates"] for x in stats)
-        per_launch = byts / kernels if kernels else 0.0
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    per_launch = byts / timed if timed else 0.0
+    achieved = byts / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    traffic = alu = None
+    from paper_1911_04034_amd import profile_summary as ps
+    tag = args.workload + ("_entropy" if args.entropy else "")
+    t_bytes, t_hash = ps.read_traffic(os.path.join(ROOT, "profiles", "traffic_fused_kernel_%s.txt" % tag))
+    if t_bytes is not None and t_hash == ps.kernel_hash():
+        traffic = round(t_bytes, 1)
+    busy, b_hash = ps.read_valu_busy(os.path.join(ROOT, "profiles", "counters_fused_kernel_%s.txt" % tag))
+    if busy and b_hash == ps.kernel_hash():
+        alu = busy.get(tag)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
+                "alu_frac": alu,
+                "kernel": "job_kernel<16, 2, ARENA, ARENA, gate%s> (fused decode-gate-encode)" % (
+                    ", entropy" if args.entropy else ""),
+                "avg_launch_us": round(avg_ms * 1e3, 3), "algorithmic_bytes_per_launch": round(per_launch, 1),
+                "launches": timed, "range_launches": stats["range_launches"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        cpu = cpu_baseline(st, windows[-1], level, args.cpu_seconds, args.entropy,
+                           "%d-qubit %s state after gate %d, its last %d gates" % (n, args.workload, len(gates),
+                                                                                  len(windows[-1])))
     line = {
-        "metric": METRIC, "value": round(amps / wall / 1e9, 4), "unit": "GAmp/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(wall / max(1, args.steps) * 1e3, 3), "higher_is_better": True,
+        "metric": METRIC, "value": round(amps / wall / 1e9, 4) if wall > 0 else 0.0, "unit": "GAmp/s", "n_gpus": 1,
+        "steps": timed_steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / max(1, timed_steps) * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "qubits": n, "block_amplitudes": 1 << bl,
-                   "gates": int(len(gates)), "final_level": fp["level"], "budget_bytes": budget,
-                   "pool_bytes": int(pool), "parallelism": "single GPU", "fused_runs": bool(args.fuse)},
+                   "bound": [0.0, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1][level], "gates": int(len(gates)),
+                   "gates_per_step": win, "final_level": fp["level"], "pool_bytes": int(pool),
+                   "entropy_stage": bool(args.entropy), "parallelism": "single GPU"},
         "compression_ratio_min": round(fp["raw_bytes"] / (fp["max_compressed"] + fp["table_bytes"]), 3),
         "compression_ratio_final": round(fp["ratio"], 3),
         "peak_compressed_bytes": fp["max_compressed"],
         "fidelity": fid,
-        "mean_compressed_bytes": float(np.mean(trace)) if trace else None,
-        "selector": selector,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
-                     "kernel": "job_kernel<16, ARENA, ARENA, gate> (fused decode-gate-encode)",
-                     "avg_launch_us": round(avg_ms * 1e3, 3), "algorithmic_bytes_per_launch": round(per_launch, 1),
-                     "launches": timed},
-        "cpu_baseline": None,
+        "logical_gamp_s": round(sum(len(wg) for wg in windows[args.warmup:]) * (1 << n) / wall / 1e9, 3)
+        if wall > 0 else None,
+        "fused_kernel_gamp_s": round(amps / (kms * 1e-3) / 1e9, 3) if kms > 0 else None,
+        "kernel_share_of_wall": round(kms * 1e-3 / wall, 4) if wall > 0 else None,
+        "compactions": fp["compactions"] - c0 if t_all is not None else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
     }
+    if args.workload == "qaoa34" and args.selector:
+        line["selector"] = selector_run(args, torch, cc, qcz, n, bl, gates, pool, trace, st)
     print(json.dumps(line), flush=True)
+
+
+def selector_run(args, torch, cc, qcz, n, bl, gates, pool, trace, st):
+    """The learned per-block levels at the rule's per-step budget (1e-4),
+    trained on the device from teacher traces of small circuits."""
+    from paper_1911_04034_amd import selector as sel
+    train = [(cc.biased_local(12, 6, 8, 1), 12, 6), (cc.biased_local(13, 7, 8, 2), 13, 7),
+             (cc.biased_local(13, 6, 8, 3), 13, 6), (cc.grover(12, 12, 11)[0], 12, 6),
+             (cc.random_circuit_small(12, 12, 13), 12, 6), (cc.qft(12, cc.qft_input(12, 14)), 12, 6),
+             (cc.qaoa(12, 3, 3, 15)[0], 12, 6)]
+    log("selector: teacher traces and training")
+    X, y = sel.training_set(train, (1e-5, 1e-4, 1e-3), 16)
+    params, losses = sel.train(X, y, steps=1500, lr=3e-3, seed=0)
+    acc = sel.accuracy(params, X, y)
+    st.close()
+    torch.cuda.empty_cache()
+    st2 = qcz.State(n, bl, mode=qcz.MODE_PERBLOCK, level=0, pool_bytes=pool, batch=128, flags=qcz.FLAG_RANGES)
+    st2.set_selector(params, 1e-4, 16)
+    t0 = time.perf_counter()
+    strace = []
+    for k in range(0, len(gates), 16):
+        st2.apply(gates[k:k + 16])
+        f2 = st2.footprint()
+        strace.append(f2["compressed_bytes"])
+        log("qaoa34 selector: %d/%d gates, compressed %.2f GB" % (min(k + 16, len(gates)), len(gates),
+                                                                  f2["compressed_bytes"] / 1e9))
+    torch.cuda.synchronize()
+    f2 = st2.footprint()
+    return {"train_samples": int(X.shape[0]), "train_loss": [round(losses[0], 4), round(losses[-1], 4)],
+            "train_accuracy": round(acc, 4), "wall_s": round(time.perf_counter() - t0, 2),
+            "mean_compressed_bytes": float(np.mean(strace)), "peak_compressed_bytes": f2["max_compressed"],
+            "fidelity_lower_bound": f2["fidelity_lower_bound"],
+            "rule_mean_compressed_bytes": float(np.mean(trace)),
+            "gain_mean_bytes": round(float(np.mean(trace)) / float(np.mean(strace)), 4)}
 
 
 def main():
@@ -242,14 +312,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="grover24+qft24",
+    ap.add_argument("--workload", default="qaoa34",
                     choices=["grover24+qft24", "grover24", "qft24"] + sorted(LARGE))
     ap.add_argument("--grover-iters", type=int, default=32,
                     help="Grover iterations per step (0: spread the full 3216 over warmup+steps)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=24.0,
+                    help="CPU leg: half on one core, half on all host cores")
+    ap.add_argument("--gates", type=int, default=0, help="large configurations: only the first GATES gates "
+                    "(profiling runs)")
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--chunk-waves", type=int, default=0, help="wavefronts per chunk in the fused kernel (2, 4, 8)")
     ap.add_argument("--no-timing", action="store_true", help="launch from graphs instead of timing each kernel")
@@ -434,7 +507,13 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.cpu_seconds)
+        # dense chunks: the QFT state at the end of the timed region, with the circuit's last 40 gates
+        qs = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=level, pool_bytes=4 << 30,
+                       flags=qcz.FLAG_ENTROPY if args.entropy else 0)
+        qs.apply(qft_gates)
+        cpu = cpu_baseline(qs, qft_gates[-40:], level, args.cpu_seconds, args.entropy,
+                           "24-qubit QFT state (bound 1e-5) and the QFT's last 40 gates")
+        qs.close()
 
     line = {
         "metric": METRIC, "value": round(value, 4), "unit": "GAmp/s", "n_gpus": 1, "steps": args.steps,

@@ -164,13 +164,14 @@ typedef struct {
     uint32_t grid;              /* launch shape in use: workgroups per fused launch */
     uint32_t tuning;            /* 1 while the autotuner is still measuring */
     uint32_t stops;             /* batches stopped on the device (budget or arena full) and rolled back */
-    uint64_t range_gates;       /* gates run in job ranges because their new streams did not fit at once
-                                   (not event-timed) */
+    uint64_t range_gates;       /* gates run in job ranges because their new streams did not fit at once */
     uint64_t cache_gates;       /* QCZ_FLAG_CACHE: gates run through the block cache (event timing, if on,
                                    covers the cache's planning and copy kernels and both job launches) */
     uint64_t cache_hits;        /* chunks whose new stream was copied from an identical job's */
     uint32_t cache_on;          /* 1 while the block cache is in use */
     uint32_t reserved;
+    uint64_t range_launches;    /* fused kernels of gates run in job ranges (QCZ_FLAG_TIMING: event-timed and
+                                   counted in timed_launches / gate_kernel_ms) */
 } qcz_stats_t;
 
 /* Bytes of device pool needed for a configuration (state |0..0> plus

@@ -723,11 +723,29 @@ qcz_status apply_in_ranges(qcz_state *s, const GateDesc &d)
         r.job0 = j;
         r.job_end = j + L;
         const uint64_t live0 = s->live, bump0 = s->bump;
-        qcz_status st = launch_one(s, r, false);
+        // with QCZ_FLAG_TIMING each range launch is timed like a whole gate
+        const bool timing = (s->cfg.flags & QCZ_FLAG_TIMING) != 0;
+        if (timing) {
+            while (s->events.size() < 2) {
+                hipEvent_t ev;
+                HIPCHK(s, hipEventCreate(&ev));
+                s->events.push_back(ev);
+            }
+            s->timed.assign(1, 0);
+        }
+        qcz_status st = launch_one(s, r, timing);
         if (st != QCZ_OK) return st;
         HIPCHK(s, hipMemcpyAsync(&s->hds, s->ds, offsetof(DevState, log) + sizeof(GateLog), hipMemcpyDeviceToHost,
                                  s->stream));
         HIPCHK(s, hipStreamSynchronize(s->stream));
+        if (timing && s->timed[0]) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, s->events[0], s->events[1]) == hipSuccess) {
+                s->stats.timed_launches += 1;
+                s->stats.gate_kernel_ms += ms;
+                s->stats.range_launches += 1;
+            }
+        }
         const DevState &h = s->hds;
         for (int k = 0; k < kStripes; ++k) s->stripe_fill[k] = h.stripe[k][0];
         if (!h.stop) {
@@ -771,7 +789,8 @@ qcz_status apply_in_ranges(qcz_state *s, const GateDesc &d)
     tot.bump = s->bump;
     s->stats.range_gates += 1;
     s->cached.clear();   // job ranges never run through the block cache
-    commit_gate(s, tot, d, (int)s->timed.size());
+    s->timed.clear();    // (the ranges' kernel time is already counted)
+    commit_gate(s, tot, d, 0);
     return QCZ_OK;
 }
 

@@ -1,28 +1,15 @@
-"""Summarise rocprofv3 CSV output for the fused gate kernel.
-
-Usage:
-  python -m paper_1911_04034_amd.profile_summary stats  <kernel_stats.csv> <command> > profiles/X.txt
-  python -m paper_1911_04034_amd.profile_summary traffic <fetch_dir> <write_dir> <copy_fetch_dir> \
-         <copy_write_dir> <copy_bytes> <last_n_dispatches> <command> > profiles/Y.txt
-  python -m paper_1911_04034_amd.profile_summary counters <command> <name>=<dir> [<name>=<dir> ...] > profiles/Z.txt
-
-The traffic summary scales the per-dispatch FETCH_SIZE / WRITE_SIZE of the
-fused kernel by the ratio (known bytes / counter) that the same counters read
-for a plain device copy, and records a hash of the kernel source so readers
-can tell whether the counters still describe the current kernel.
-"""
+"""Readers of the rocprofv3 summaries under profiles/ that the benchmark
+reports beside its own timing (counter-measured traffic and VALU-busy
+fraction of the fused kernel), and the hash of the device code that tells
+whether a summary still describes the current kernels.  The summaries are
+written by profile_summary.py at the repository root."""
 from __future__ import annotations
 
-import csv
-import glob
 import hashlib
 import os
-import statistics
-import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "csrc", "qcz_kernels.hip")
-FUSED = "job_kernel<16, 2, 0, 0, true, 0>"
 
 
 def kernel_hash() -> str:
@@ -30,99 +17,6 @@ def kernel_hash() -> str:
     src = open(KERNEL_SRC, "rb").read()
     cut = src.find(b"// host launchers")
     return hashlib.sha256(src[:cut] if cut > 0 else src).hexdigest()[:16]
-
-
-def _counter_rows(d):
-    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
-    rows = []
-    for f in files:
-        rows += list(csv.DictReader(open(f)))
-    return rows
-
-
-def per_dispatch(d, counter, name_part, last=0):
-    """Mean over dispatches of `counter` (summed over its dimensions) for kernels matching name_part;
-    with last > 0 only the last `last` dispatches (the benchmark's timed region) count."""
-    acc = {}
-    for r in _counter_rows(d):
-        if r["Counter_Name"] != counter or name_part not in r["Kernel_Name"]:
-            continue
-        key = int(r["Dispatch_Id"])
-        acc.setdefault(key, 0.0)
-        acc[key] += float(r["Counter_Value"])
-    vals = [acc[k] for k in sorted(acc)]
-    if last > 0:
-        vals = vals[-last:]
-    return (statistics.mean(vals) if vals else float("nan")), len(vals)
-
-
-def stats(path, command, trace=None, last=0):
-    rows = list(csv.DictReader(open(path)))
-    if trace:
-        tr = [r for r in csv.DictReader(open(trace)) if FUSED in r["Kernel_Name"]]
-        tr.sort(key=lambda r: int(r["Start_Timestamp"]))
-        d = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in tr][-int(last):]
-        print("# fused kernel, last %d dispatches (the timed region): mean %.1f ns" % (len(d), statistics.mean(d)))
-    print("# rocprofv3 --kernel-trace --stats summary")
-    print("# command: %s" % command)
-    print("# kernel source sha256[:16]: %s" % kernel_hash())
-    print("%-70s %8s %14s %12s %8s" % ("kernel", "calls", "total_ns", "avg_ns", "pct"))
-    for r in rows[:15]:
-        print("%-70s %8s %14s %12.1f %8.2f" % (r["Name"][:70], r["Calls"], r["TotalDurationNs"],
-                                              float(r["AverageNs"]), float(r["Percentage"])))
-
-
-def traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, last, command):
-    copy_bytes = float(copy_bytes)
-    last = int(last)
-    cf, _ = per_dispatch(cfetch_dir, "FETCH_SIZE", "copyBuffer")
-    cw, _ = per_dispatch(cwrite_dir, "WRITE_SIZE", "copyBuffer")
-    f, nf = per_dispatch(fetch_dir, "FETCH_SIZE", FUSED, last)
-    w, nw = per_dispatch(write_dir, "WRITE_SIZE", FUSED, last)
-    kf = copy_bytes / cf if cf else float("nan")
-    kw = copy_bytes / cw if cw else float("nan")
-    print("# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, fused gate kernel %s" % FUSED)
-    print("# command: %s" % command)
-    print("kernel_source_sha256_16: %s" % kernel_hash())
-    print("copy_bytes: %d" % copy_bytes)
-    print("copy_fetch_counter: %.4f" % cf)
-    print("copy_write_counter: %.4f" % cw)
-    print("fetch_scale_bytes_per_unit: %.4f" % kf)
-    print("write_scale_bytes_per_unit: %.4f" % kw)
-    print("dispatches_fetch: %d" % nf)
-    print("dispatches_write: %d" % nw)
-    print("fetch_counter_per_dispatch: %.4f" % f)
-    print("write_counter_per_dispatch: %.4f" % w)
-    print("traffic_bytes_per_dispatch: %.1f" % (f * kf + w * kw))
-
-
-SQ = ["SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_VALU", "SQ_WAIT_ANY",
-      "SQ_WAVES", "SQ_WAVE_CYCLES"]
-
-
-def counters(command, *runs, waves_per_simd=3):
-    """Mean per dispatch of the SQ counters of the fused kernel, one block per
-    `name=dir` run, with the ratios derived from them."""
-    print("# rocprofv3 SQ counters of the fused gate kernel %s (mean per dispatch)" % FUSED)
-    print("# command: %s" % command)
-    print("# %d waves per SIMD: VALU busy per SIMD = %d * SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES" % (waves_per_simd,
-                                                                                               waves_per_simd))
-    print("# kernel source sha256[:16]: %s" % kernel_hash())
-    for run in runs:
-        name, d = run.split("=", 1)
-        v = {}
-        n = 0
-        for c in SQ:
-            v[c], n = per_dispatch(d, c, FUSED)
-        print()
-        print("workload %s (%d dispatches)" % (name, n))
-        for c in SQ:
-            print("  %-22s %.4g" % (c, v[c]))
-        print("  %-22s %.3f" % ("VALU busy per SIMD", waves_per_simd * v["SQ_ACTIVE_INST_VALU"] / v["SQ_WAVE_CYCLES"]))
-        print("  %-22s %.3f" % ("waiting / wave cycles", v["SQ_WAIT_ANY"] / v["SQ_WAVE_CYCLES"]))
-        print("  %-22s %.0f" % ("VALU instructions/wave", v["SQ_INSTS_VALU"] / v["SQ_WAVES"]))
-        print("  %-22s %.3f" % ("SALU / VALU", v["SQ_INSTS_SALU"] / v["SQ_INSTS_VALU"]))
-        print("  %-22s %.3f" % ("LDS / VALU", v["SQ_INSTS_LDS"] / v["SQ_INSTS_VALU"]))
 
 
 def read_valu_busy(path):
@@ -153,14 +47,3 @@ def read_traffic(path):
         return float(vals["traffic_bytes_per_dispatch"]), vals["kernel_source_sha256_16"]
     except (KeyError, ValueError):
         return None, None
-
-
-if __name__ == "__main__":
-    if sys.argv[1] == "stats":
-        stats(sys.argv[2], sys.argv[3], *(sys.argv[4:6]))
-    elif sys.argv[1] == "traffic":
-        traffic(*sys.argv[2:9])
-    elif sys.argv[1] == "counters":
-        counters(sys.argv[2], *sys.argv[3:])
-    else:
-        raise SystemExit(__doc__)

@@ -60,7 +60,8 @@ class Stats(ctypes.Structure):
                 ("gate_kernel_ms", ctypes.c_double), ("chunk_waves", ctypes.c_uint32), ("grid", ctypes.c_uint32),
                 ("tuning", ctypes.c_uint32), ("stops", ctypes.c_uint32),
                 ("range_gates", ctypes.c_uint64), ("cache_gates", ctypes.c_uint64),
-                ("cache_hits", ctypes.c_uint64), ("cache_on", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("cache_hits", ctypes.c_uint64), ("cache_on", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("range_launches", ctypes.c_uint64)]
 
 
 EXPORTED = [
