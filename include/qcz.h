@@ -65,7 +65,10 @@ typedef enum {
                                 (wavefronts per chunk x workgroups per CU), time each shape with events and
                                 keep the fastest per recompressed chunk; results do not depend on the shape */
 #define QCZ_FLAG_RANGES 8u  /* modes without a size budget: a gate whose new streams do not fit beside the
-                               live ones even after compaction runs in job ranges, each committed before the
+                               live ones even after compaction, nor as a sweep into the other arena (a gate
+                               that does not fit beside the live streams is first tried as one launch writing
+                               every chunk into the other, empty arena; that needs no flag and keeps the
+                               state at the last committed gate when it stops), runs in job ranges, each committed before the
                                next, so the arena only needs the live state plus one range.  The price: a
                                gate that still runs out of arena midway cannot be undone (its replaced
                                streams are gone); the call returns QCZ_E_NOMEM and the state is invalid
@@ -172,6 +175,9 @@ typedef struct {
     uint32_t reserved;
     uint64_t range_launches;    /* fused kernels of gates run in job ranges (QCZ_FLAG_TIMING: event-timed and
                                    counted in timed_launches / gate_kernel_ms) */
+    uint64_t sweep_gates;       /* gates run as sweeps: their new streams did not fit beside the live ones,
+                                   so one launch wrote every chunk into the other arena (the chunks the gate
+                                   leaves unchanged copied as they are) and the arenas swapped roles */
 } qcz_stats_t;
 
 /* Bytes of device pool needed for a configuration (state |0..0> plus

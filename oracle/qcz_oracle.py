@@ -270,6 +270,7 @@ class Sim:
                  level: int = 0, budget: int = 0, codec: int = 0):
         self.n, self.block_log2 = n, block_log2
         self._h = lib().oq_sim_create(n, block_log2, mode, level, budget)
+        self._destroy = lib().oq_sim_destroy   # held: module globals may be gone when __del__ runs at exit
         if not self._h:
             raise ValueError("bad simulator configuration")
         if codec:
@@ -279,8 +280,8 @@ class Sim:
         self.nchunks = 1 << (n - self.cb)
 
     def close(self):
-        if self._h:
-            lib().oq_sim_destroy(self._h)
+        if getattr(self, "_h", None):
+            self._destroy(self._h)
             self._h = None
 
     def __del__(self):

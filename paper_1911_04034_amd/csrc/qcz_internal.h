@@ -43,7 +43,10 @@ struct GateDesc {
     uint64_t job0, job_end;         // jobs [job0, job_end) of this launch (job_end 0: all njobs)
     int32_t entropy;                // the encoder may take the entropy-coded body (header bit 5); its
                                     // kernels decode such streams too (C = 2048, two wavefronts per chunk)
-    int32_t pad_;
+    int32_t sweep;                  // every chunk is enumerated and lands in the other arena (DevPtrs::out):
+                                    // chunks the gate leaves unchanged are copied there as they are
+    uint64_t act_mask, act_val;     // a sweep acts on chunk c only if (c & act_mask) == act_val (the
+                                    // control bits its plain enumeration would have held fixed)
 };
 
 // the jobs one launch of a gate runs
@@ -96,6 +99,8 @@ struct WgPart {
 // Pointers of one state, passed by value to every kernel.
 struct DevPtrs {
     uint32_t *arena;            // current arena, word addressed
+    uint32_t *out;              // where gate kernels write new streams: the current arena, or the
+                                // other one for a sweep
     uint64_t arena_words;
     uint64_t *table;            // per chunk: (offset in words << 16) | size in bytes
     uint64_t *undo;             // per enumerated position: previous table entry

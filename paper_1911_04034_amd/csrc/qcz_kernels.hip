@@ -1221,7 +1221,8 @@ __device__ __forceinline__ bool job_slot(const GateDesc &gd, uint32_t unit_mask,
     const bool valid = item < gd.nitems;
     if (SRC == SRC_ARENA && !GATE && io.list) c = valid ? io.list[item] : 0;
     else c = valid ? item_chunk(gd, item) + io.first : 0;
-    return valid && !(GATE && gd.check_phase && !diag_touches(gd, unit_mask, c, cb));
+    return valid && !(GATE && gd.check_phase && !diag_touches(gd, unit_mask, c, cb)) &&
+           !(GATE && (c & gd.act_mask) != gd.act_val);
 }
 
 // validity of a table entry's stream: in the arena, within a staging buffer
@@ -1517,7 +1518,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                 if ((off & 3ull) == 0) stage_units<G>(b, P.arena + off, words, lt);
                 else stage_words<G>(b, P.arena + off, words, lt);
             }
-            if (act && !ok_src && lt == 0 && ds) atomicExch(&ds->corrupt, 1);
+            if ((act || (GATE && gd.sweep && valid)) && !ok_src && lt == 0 && ds) atomicExch(&ds->corrupt, 1);
         } else if (SRC == SRC_SLOTS) {
             const uint32_t size = valid ? io.sizes_in[item] : 0u;
             const uint32_t words = (size + 3u) >> 2;
@@ -1753,12 +1754,16 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                 acc_wd += level_delta(lev_req) * pre;
                 acc_lost += pre - post;
             }
+            // a sweep moves every chunk to the other arena: one the gate leaves
+            // unchanged (skipped by its controls or its phases) is copied as it is
+            const bool carry = DST == DST_ARENA && GATE && gd.sweep && valid && !act && ok_src;
+            const uint32_t new_size = enc ? e.size : (uint32_t)(old_entry & 0xFFFFull);
             // claim arena space now; the returned offset is first needed after
             // the stream has been assembled in LDS, which hides the atomic
             uint64_t my_off = 0;
             const int stripe = (int)(blockIdx.x % (uint32_t)ds_nstripes);
-            if (lt == 0 && enc && DST == DST_ARENA)
-                my_off = atomicAdd((unsigned long long *)&ds->stripe[stripe][0], (unsigned long long)alloc_bytes(e.size));
+            if (lt == 0 && (enc || carry) && DST == DST_ARENA)
+                my_off = atomicAdd((unsigned long long *)&ds->stripe[stripe][0], (unsigned long long)alloc_bytes(new_size));
             // no barrier before clearing b[]: every read of the decoded values
             // (and of the other slot's buffer) precedes the plan's last barrier
             const uint32_t words = (e.size + 3u) >> 2;
@@ -1770,9 +1775,9 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             if (enc) encode_emit<V>(b, e, C, lt, ent);
             if (lt == 0) {
                 int ok = 0;
-                if (enc) {
+                if (enc || carry) {
                     if (DST == DST_ARENA) {
-                        ok = (my_off + alloc_bytes(e.size) <= ds_ssize) ? 1 : 0;
+                        ok = (my_off + alloc_bytes(new_size) <= ds_ssize) ? 1 : 0;
                         my_off += ds_base + (uint64_t)stripe * ds_ssize;
                         if (!ok) atomicExch(&ds->fail, 1);
                     } else {
@@ -1785,10 +1790,16 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             lds_barrier();
             const int ok = sh_ok[s];
             if (ok) {
-                if (DST == DST_ARENA) {
+                if (DST == DST_ARENA && carry) {
+                    // the old stream, word by word (a compacted stream may start at any
+                    // word), with its last 16-byte unit's tail cleared
+                    const uint64_t offw = sh_off[s] >> 2, srcw = old_entry >> 16;
+                    const uint32_t cw = (new_size + 3u) >> 2, units = (cw + 3u) >> 2;
+                    for (uint32_t w = lt; w < 4u * units; w += G) P.out[offw + w] = w < cw ? P.arena[srcw + w] : 0u;
+                } else if (DST == DST_ARENA) {
                     // whole 16-byte units: the allocation holds them and b[] is zero past the stream
                     const uint64_t offw = sh_off[s] >> 2;
-                    u32x4 *dst4 = reinterpret_cast<u32x4 *>(P.arena + offw);
+                    u32x4 *dst4 = reinterpret_cast<u32x4 *>(P.out + offw);
                     const u32x4 *b4 = reinterpret_cast<const u32x4 *>(b);
                     for (uint32_t w = lt; w < (words + 3u) >> 2; w += G) dst4[w] = b4[w];
                 } else {
@@ -1798,11 +1809,16 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             if (lt == 0 && valid) {
                 if (DST == DST_ARENA) {
                     P.undo[item] = old_entry;
-                    if (ok) {
+                    const uint64_t old_pad = ((old_entry & 0xFFFFull) + 3ull) & ~3ull;
+                    const uint64_t new_pad = ((uint64_t)e.size + 3ull) & ~3ull;
+                    // the size change counts also where the allocation failed: the
+                    // gate's logged size is then its true one, which the budget
+                    // test takes before the full arena
+                    if (enc) sh_acc[4 * s] += new_pad - old_pad;   // two's complement: a signed delta
+                    if (ok && carry) {
+                        P.table[c] = ((sh_off[s] >> 2) << 16) | (uint64_t)new_size;
+                    } else if (ok) {
                         P.table[c] = ((sh_off[s] >> 2) << 16) | (uint64_t)e.size;
-                        const uint64_t old_pad = ((old_entry & 0xFFFFull) + 3ull) & ~3ull;
-                        const uint64_t new_pad = ((uint64_t)e.size + 3ull) & ~3ull;
-                        sh_acc[4 * s] += new_pad - old_pad;   // two's complement: the sum is a signed delta
                         sh_acc[4 * s + 1] += 1;
                         sh_acc[4 * s + 2] += old_pad;
                         sh_acc[4 * s + 3] += new_pad;
@@ -1949,9 +1965,10 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             const int fail = atomicExch(&ds->fail, 0);
             const int corrupt = atomicExch(&ds->corrupt, 0);
             int reason = STOP_NONE;
+            // over the budget first: Sec. 3.7 relaxes the level whatever the arena holds
             if (corrupt) reason = STOP_CORRUPT;
-            else if (fail) reason = STOP_ARENA;
             else if (ds->budget && live > ds->budget) reason = STOP_BUDGET;
+            else if (fail) reason = STOP_ARENA;
             if (reason != STOP_NONE) {
                 ds->stop_reason = reason;
                 ds->stop_seq = gd.seq;

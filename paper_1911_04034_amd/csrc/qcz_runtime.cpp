@@ -169,6 +169,7 @@ DevPtrs ptrs(const qcz_state *s)
 {
     DevPtrs P{};
     P.arena = s->arena[s->cur];
+    P.out = P.arena;
     P.arena_words = s->lay.arena_bytes / 4;
     P.table = s->table;
     P.undo = s->undo;
@@ -794,6 +795,126 @@ qcz_status apply_in_ranges(qcz_state *s, const GateDesc &d)
     return QCZ_OK;
 }
 
+// Sweep: a gate (or a fused run of in-chunk gates) whose new streams do not
+// fit beside the live ones runs as one launch that writes every chunk into
+// the other arena, the chunks it leaves unchanged copied there as they are.
+// The current arena is only read, so a stop (budget or full arena) is undone
+// by restoring the table entries, and a success swaps the arenas' roles: the
+// compaction comes with the gate, where job ranges would compact several
+// times per gate.  The sweep's enumeration covers every chunk; the control
+// bits the plain enumeration holds fixed become the act mask.
+bool sweepable(const qcz_state *s, const GateDesc &d)
+{
+    (void)s;
+    return d.job_type != J_PERMUTE && d.nitems > 0 && d.job_end == 0;
+}
+
+GateDesc sweep_desc(const GateDesc &d)
+{
+    GateDesc r = d;
+    r.sweep = 1;
+    r.act_mask = d.fixed_mask & ~d.pair_bit;
+    r.act_val = d.fixed_val & r.act_mask;
+    r.fixed_mask = d.fixed_mask & d.pair_bit;   // 0 for jobs inside chunks
+    r.fixed_val = 0;
+    const int nfree = d.nchunk_bits - popcount64(r.fixed_mask);
+    if (d.job_type == J_PAIR) {
+        r.njobs = 1ull << nfree;
+        r.nitems = 2 * r.njobs;
+    } else {
+        r.nitems = 1ull << nfree;
+        r.njobs = (r.nitems + 1) / 2;
+    }
+    return r;
+}
+
+// the state, a sixteenth for growth and the 16-byte allocation units, in an
+// empty arena less a thirty-second for unevenly filled stripes
+bool sweep_may_fit(const qcz_state *s)
+{
+    const uint64_t need = s->live + s->live / 16 + 16 * s->nchunks;
+    return need <= s->lay.arena_bytes - s->lay.arena_bytes / 32;
+}
+
+// Run descs[0 .. r) as a sweep (r > 1: a fused run).  *reason: STOP_NONE when
+// committed, else why the device stopped it (the state is then unchanged).
+qcz_status apply_sweep(qcz_state *s, const GateDesc *descs, size_t r, int *reason)
+{
+    *reason = STOP_NONE;
+    const uint64_t base0 = s->base, ssize0 = s->stripe_size, live0 = s->live, bump0 = s->bump;
+    const int ns0 = s->nstripes;
+    uint64_t fill0[kStripes];
+    for (int k = 0; k < kStripes; ++k) fill0[k] = s->stripe_fill[k];
+    const int other = 1 - s->cur;
+    // stripes over the whole other arena (the header describes the arena written to)
+    qcz_status st = reset_stripes(s, 0);
+    if (st != QCZ_OK) return st;
+    GateDesc d = sweep_desc(descs[0]);
+    d.seq = 0;
+    DevPtrs P = ptrs(s);
+    P.out = s->arena[other];
+    const bool timing = (s->cfg.flags & QCZ_FLAG_TIMING) != 0;
+    if (timing)
+        while (s->events.size() < 2) {
+            hipEvent_t ev;
+            HIPCHK(s, hipEventCreate(&ev));
+            s->events.push_back(ev);
+        }
+    hipEvent_t t0 = timing ? s->events[0] : nullptr, t1 = timing ? s->events[1] : nullptr;
+    const int grid = grid_for(s, d);
+    hipError_t e;
+    if (r > 1) {
+        GateDesc *dev_descs = (GateDesc *)(s->pool + s->lay.rundesc);
+        HIPCHK(s, hipMemcpyAsync(dev_descs, descs, r * sizeof(GateDesc), hipMemcpyHostToDevice, s->stream));
+        e = launch_gate_run(d, P, dev_descs, (int)r, grid, s->stream, t0, t1);
+    } else {
+        e = launch_gate(d, P, grid, s->stream, s->chunk_waves, t0, t1);
+    }
+    if (e != hipSuccess) return fail(s, QCZ_E_DEVICE, std::string("sweep launch: ") + hipGetErrorString(e));
+    HIPCHK(s, hipMemcpyAsync(&s->hds, s->ds, offsetof(DevState, log) + sizeof(GateLog), hipMemcpyDeviceToHost,
+                             s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    const DevState &h = s->hds;
+    if (!h.stop) {
+        s->cur = other;
+        for (int k = 0; k < kStripes; ++k) s->stripe_fill[k] = h.stripe[k][0];
+        if (timing) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, s->events[0], s->events[1]) == hipSuccess) {
+                s->stats.timed_launches += 1;
+                s->stats.gate_kernel_ms += ms;
+            }
+        }
+        // a fused run commits like one of launch_batch: every gate takes the
+        // run's log, its stream bytes and table traffic counted on the last
+        s->timed.clear();
+        s->cached.clear();
+        for (size_t k = 0; k < r; ++k) {
+            GateLog lg = h.log[0];
+            if (k + 1 < r) lg.rd = lg.wr = 0;
+            commit_gate(s, lg, descs[k], (int)k, k + 1 == r);
+        }
+        s->stats.sweep_gates += r;
+        return QCZ_OK;
+    }
+    *reason = h.stop_reason;
+    s->stats.stops += 1;
+    const int rg = (int)std::max<uint64_t>(1, std::min<uint64_t>((launch_items(d) + kWG - 1) / kWG, 65535));
+    HIPCHK(s, launch_rollback(d, P, rg, s->stream));
+    // the current arena's allocator as it was
+    s->base = base0;
+    s->stripe_size = ssize0;
+    s->nstripes = ns0;
+    s->live = live0;
+    s->bump = bump0;
+    for (int k = 0; k < kStripes; ++k) {
+        s->stripe_fill[k] = fill0[k];
+        s->hds.stripe[k][0] = fill0[k];
+    }
+    HIPCHK(s, hipMemcpyAsync(&s->ds->stripe, &s->hds.stripe, sizeof(s->hds.stripe), hipMemcpyHostToDevice, s->stream));
+    return write_header(s);
+}
+
 // Blocks grouped by coset id b & ~mask: cosets in increasing id, members in
 // block order, and the weight of each coset summed in block order.
 struct Cosets {
@@ -1085,6 +1206,8 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
             return fail(s, QCZ_E_INVAL, "malformed gate record " + std::to_string(k));
     size_t idx = 0;
     int compacted_for = -1;  // gate index a compaction was made for
+    int swept_out = -1;      // gate index whose sweep ran out of arena
+    int sweep_for = -1;      // gate index that did not fit after a compaction: sweep it
     std::vector<GateDesc> descs;
     while (idx < n_gates) {
         size_t B = std::min<size_t>((size_t)s->batch, n_gates - idx);
@@ -1106,6 +1229,36 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
         }
         descs.clear();
         for (size_t k = 0; k < B; ++k) descs.push_back(lower_gate(s, gates[idx + k], (int)k));
+        // A gate that does not fit beside the live streams sweeps into the
+        // other arena when the state fits there (with the in-chunk gates
+        // fused after it, under QCZ_FLAG_FUSE); a sweep the device stopped
+        // for arena room falls back to compaction and job ranges below.
+        if ((gates_that_fit(s, descs) == 0 || sweep_for == (int)idx) && sweepable(s, descs[0]) &&
+            swept_out != (int)idx && sweep_may_fit(s)) {
+            size_t r = 1;
+            if (fusable(s, descs[0]))
+                while (r < descs.size() && r < (size_t)kMaxRun && fusable(s, descs[r])) ++r;
+            int reason = STOP_NONE;
+            qcz_status st = apply_sweep(s, descs.data(), r, &reason);
+            if (st != QCZ_OK) return st;
+            if (reason == STOP_NONE) {
+                idx += r;
+                s->sel_since += r;
+                if (applied) *applied = idx;
+                continue;
+            }
+            if (reason == STOP_BUDGET) {
+                if (s->level >= kLevels - 1)
+                    return fail(s, QCZ_E_NOMEM, "compressed state exceeds the budget at the loosest level");
+                s->level += 1;   // Sec. 3.7: relax the bound and redo the gate
+                st = write_header(s);
+                if (st != QCZ_OK) return st;
+                continue;
+            }
+            if (reason != STOP_ARENA) return fail(s, QCZ_E_FORMAT, "a chunk table entry points outside the arena");
+            swept_out = (int)idx;
+            continue;
+        }
         // Compact before a batch that is not expected to fit, so that a full
         // stripe seldom stops a batch midway (a stop costs a rollback and the
         // relaunch of the rest); if it still does not fit, launch the part
@@ -1171,7 +1324,12 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
             st = write_header(s);
             if (st != QCZ_OK) return st;
             if (compacted_for == (int)idx) {
-                // the gate's new streams do not fit beside the live ones even after compaction
+                // the gate's new streams do not fit beside the live ones even after
+                // compaction: a sweep into the other arena, else job ranges
+                if (swept_out != (int)idx && sweepable(s, dstop) && sweep_may_fit(s)) {
+                    sweep_for = (int)idx;
+                    continue;
+                }
                 if (!ranges_allowed(s) || dstop.job_type == J_PERMUTE || dstop.njobs < 2)
                     return fail(s, QCZ_E_NOMEM, "arena too small for one gate after compaction");
                 st = apply_in_ranges(s, dstop);

@@ -61,7 +61,7 @@ class Stats(ctypes.Structure):
                 ("tuning", ctypes.c_uint32), ("stops", ctypes.c_uint32),
                 ("range_gates", ctypes.c_uint64), ("cache_gates", ctypes.c_uint64),
                 ("cache_hits", ctypes.c_uint64), ("cache_on", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("range_launches", ctypes.c_uint64)]
+                ("range_launches", ctypes.c_uint64), ("sweep_gates", ctypes.c_uint64)]
 
 
 EXPORTED = [

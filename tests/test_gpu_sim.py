@@ -290,9 +290,10 @@ def test_sampled_gates_full_size_qft24():
 
 
 def test_gates_split_into_job_ranges_when_arena_is_short():
-    """An arena of about 1.5x the largest state cannot hold a full-state gate's
-    new streams next to the old ones; such gates run in job ranges with
-    compaction between them, and the bytes stay the oracle's."""
+    """An arena a sixty-fourth above the largest state holds neither a
+    full-state gate's new streams next to the old ones nor, near the peak, a
+    sweep into the other arena; such gates run in job ranges with compaction
+    between them, and the bytes stay the oracle's."""
     import ctypes
     from paper_1911_04034_amd import qcz
     n, bl = 14, 8
@@ -303,7 +304,7 @@ def test_gates_split_into_job_ranges_when_arena_is_short():
     cfg = qcz.Config(n, bl, 0, 0, 0, 0, 0, 0, 0)
     pmin = qcz.load().qcz_pool_bytes_min(ctypes.byref(cfg))
     nchunks = 1 << (n - 8)
-    arena = int(1.5 * peak) + (64 << 10)
+    arena = peak + peak // 64 + (16 << 10)
     pool = pmin + 2 * (arena - (64 << 10) - 64 * nchunks)
     g = qcz.State(n, bl, mode=qcz.MODE_LOSSLESS, pool_bytes=pool, batch=16, flags=qcz.FLAG_RANGES)
     say("job ranges: peak %d arena %d" % (peak, arena))
@@ -313,10 +314,11 @@ def test_gates_split_into_job_ranges_when_arena_is_short():
     assert g.footprint()["compressed_bytes"] == o.footprint()["compressed_bytes"]
 
 
-def test_underestimated_gate_falls_back_to_job_ranges():
+def test_underestimated_gate_falls_back_to_a_sweep_or_job_ranges():
     """From a state of two-constant chunks one gate makes every chunk dense:
-    the planner's estimate is far too low, the whole gate stops twice on a
-    full arena, and the gate then runs in job ranges; bytes stay the oracle's."""
+    the planner's estimate is far too low, the whole gate stops on a full
+    arena, and the gate then runs as a sweep into the other arena (or in job
+    ranges, should the sweep not fit); bytes stay the oracle's."""
     import ctypes
     from paper_1911_04034_amd import qcz
     n, bl = 14, 8
@@ -333,5 +335,5 @@ def test_underestimated_gate_falls_back_to_job_ranges():
     say("range fallback: peak %d arena %d" % (peak, arena))
     assert g.apply(gates) == len(gates)
     st = g.stats()
-    assert st["range_gates"] > 0
+    assert st["stops"] >= 1 and st["sweep_gates"] + st["range_gates"] > 0
     assert_same_chunks(g, o, "after the fallback")
