@@ -134,7 +134,7 @@ struct IOPtrs {
 };
 
 // Gate-layer fusion: at most this many gates per fused pass.
-constexpr int kMaxRun = 32;
+constexpr int kMaxRun = 64;
 
 // Compressed block cache of one gate launch (Sec. 3.4, on the GPU): every job
 // is keyed by a hash of its input streams and of the chunk-index bits the gate

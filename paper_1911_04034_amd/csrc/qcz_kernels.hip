@@ -1304,6 +1304,19 @@ __device__ void apply_gate(const GateDesc &gd, const double *m, double *v0, doub
     }
 }
 
+// whether gate rg of a fused run re-encodes chunk c: the chunk is in its
+// enumeration (controls on chunk-index qubits, a diagonal's fixed half) and,
+// for a diagonal gate, some phase reachable in the chunk is not 1 (the gate's
+// record is read from global memory: uniform, scalar loads)
+__device__ __forceinline__ bool run_touches(const GateDesc &rg, uint64_t c, int cb)
+{
+    if ((c & rg.fixed_mask) != rg.fixed_val) return false;
+    if (!rg.check_phase) return true;
+    uint32_t um = 0;
+    for (int i = 0; i < 4; ++i) um |= unit_phase(rg.m[2 * i], rg.m[2 * i + 1]) ? (1u << i) : 0u;
+    return diag_touches(rg, um, c, cb);
+}
+
 // A single-chunk gate that each thread can apply to its own V values: diagonal
 // phases, multi-controlled Z, and U1 / X whose target pairs lie inside a
 // thread's V/2 amplitudes (2^(q+1) <= V/2).  Same arithmetic as apply_gate.
@@ -1446,7 +1459,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     // loop does not hold them in scalar registers
     __shared__ double sh_m[8];
     __shared__ double sh_rm[LIST == 3 ? kMaxRun : 1][8];   // fused run: the gates' matrices
-    __shared__ uint32_t sh_rsub[2][WGS / 64];              // fused run: subnormal flags, alternating per gate
+    __shared__ uint32_t sh_rsub[2][WGS / 64];              // fused run: subnormal flags, alternating per truncation
     // entropy stage, per slot: decode tables while decoding, encode tables and lane records while encoding
     __shared__ __align__(16) uint32_t sh_ent[ENT ? 2 : 1][ENT ? kEntSlotWords : 1];
 
@@ -1455,7 +1468,8 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
 
     const int tid = threadIdx.x, s = tid / G, lt = tid % G;
     if (GATE && tid < 8) sh_m[tid] = gd.m[tid];   // first read after the first job's fetch barrier
-    if (LIST == 3 && tid < 8 * io.nrun) sh_rm[tid >> 3][tid & 7] = io.run[tid >> 3].m[tid & 7];
+    if (LIST == 3)
+        for (int i = tid; i < 8 * io.nrun; i += WGS) sh_rm[i >> 3][i & 7] = io.run[i >> 3].m[i & 7];
     uint32_t unit_mask = 0;                        // phases equal to 1 (diagonal gates)
     if (GATE)
         for (int i = 0; i < 4; ++i) unit_mask |= unit_phase(gd.m[2 * i], gd.m[2 * i + 1]) ? (1u << i) : 0u;
@@ -1498,8 +1512,18 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
         const uint64_t item0 = 2 * job, item1 = 2 * job + 1;
         const bool valid0 = item0 < gd.nitems, valid1 = item1 < gd.nitems;
         uint64_t cc0 = 0, cc1 = 0;
-        const bool act0 = job_slot<SRC, GATE>(gd, unit_mask, io, P.cb, item0, cc0);
-        const bool act1 = job_slot<SRC, GATE>(gd, unit_mask, io, P.cb, item1, cc1);
+        bool act0 = job_slot<SRC, GATE>(gd, unit_mask, io, P.cb, item0, cc0);
+        bool act1 = job_slot<SRC, GATE>(gd, unit_mask, io, P.cb, item1, cc1);
+        if (LIST == 3) {
+            // a fused run enumerates every chunk; it re-encodes those some gate touches
+            bool t0 = false, t1 = false;
+            for (int g = 0; g < io.nrun; ++g) {
+                t0 = t0 || run_touches(io.run[g], cc0, P.cb);
+                t1 = t1 || run_touches(io.run[g], cc1, P.cb);
+            }
+            act0 = act0 && t0;
+            act1 = act1 && t1;
+        }
         const uint64_t item = s ? item1 : item0;
         const uint64_t c = s ? cc1 : cc0;
         const bool valid = s ? valid1 : valid0;
@@ -1555,34 +1579,40 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                 // the gate-by-gate encodes
                 const uint64_t base = (c << P.cb) | (uint64_t)(first / 2);
                 const uint32_t mh = sig_mask_hi(sig_bits(glevel));
+                int ntr = 0;
                 for (int g = 0; g < io.nrun; ++g) {
                     const GateDesc &rg = io.run[g];
+                    // a chunk the gate does not touch skips it and its truncation,
+                    // as it would keep its stream gate by gate
+                    const bool tg0 = use0 && run_touches(rg, cc0, P.cb), tg1 = use1 && run_touches(rg, cc1, P.cb);
+                    const bool tg = s ? tg1 : tg0;
                     if (gate_in_registers<V>(rg)) {
-                        if (use) apply_gate_registers<V>(rg, sh_rm[g], x, base);
+                        if (tg) apply_gate_registers<V>(rg, sh_rm[g], x, base);
                     } else {
 #pragma unroll
                         for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
                         lds_barrier();
                         apply_gate(rg, sh_rm[g], reinterpret_cast<double *>(buf[0]),
-                                   reinterpret_cast<double *>(buf[1]), cc0, cc1, use0, use1, P.cb, WGS);
+                                   reinterpret_cast<double *>(buf[1]), cc0, cc1, tg0, tg1, P.cb, WGS);
                         lds_barrier();
 #pragma unroll
                         for (int k = 0; k < V; ++k) x[k] = vals[vpos(first + k)];
                     }
-                    if (glevel > 0) {
+                    if (glevel > 0 && (tg0 || tg1)) {
                         bool sub = false;
 #pragma unroll
                         for (int k = 0; k < V; ++k) {
                             const uint64_t u = d2u(x[k]);
                             sub = sub || subnormal((uint32_t)(u >> 32), (uint32_t)u);
                         }
-                        const bool wsub = __any(use && sub);
-                        if ((tid & 63) == 0) sh_rsub[g & 1][tid >> 6] = wsub ? 1u : 0u;
+                        const bool wsub = __any(tg && sub);
+                        if ((tid & 63) == 0) sh_rsub[ntr & 1][tid >> 6] = wsub ? 1u : 0u;
                         lds_barrier();
                         uint32_t gs = 0;
 #pragma unroll
-                        for (int i = 0; i < WPG; ++i) gs |= sh_rsub[g & 1][s * WPG + i];
-                        if (gs == 0) {
+                        for (int i = 0; i < WPG; ++i) gs |= sh_rsub[ntr & 1][s * WPG + i];
+                        ++ntr;   // flags alternate per truncation step: a barrier separates reuses
+                        if (gs == 0 && tg) {
 #pragma unroll
                             for (int k = 0; k < V; ++k) x[k] = u2d((uint64_t)((uint32_t)(d2u(x[k]) >> 32) & mh) << 32);
                         }

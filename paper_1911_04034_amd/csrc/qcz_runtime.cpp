@@ -431,15 +431,30 @@ qcz_status launch_one(qcz_state *s, const GateDesc &d, bool timing)
     return QCZ_OK;
 }
 
-// Gates a fused run may hold: in-chunk single-qubit gates with no control on
-// a chunk-index bit touch every chunk, in modes whose level does not depend on
-// the compressed size after each gate.
+// Gates a fused run may hold: every gate whose jobs lie inside single chunks
+// (in-chunk targets of any kind, diagonal gates and multi-controlled Z on any
+// qubits, with any controls), in modes whose level does not depend on the
+// compressed size after each gate.  The run enumerates every chunk; each
+// chunk takes, in order, the gates whose own enumeration and phases touch it,
+// each followed by the truncation its re-encoding would apply, and is
+// re-encoded once if any gate touched it.  Every such gate touches some
+// chunk, so the ledger's per-gate lossy steps are those of the gates one by one.
 bool fusable(const qcz_state *s, const GateDesc &d)
 {
-    return (s->cfg.flags & QCZ_FLAG_FUSE) && !s->cache_on && d.job_type == J_SINGLE &&
-           (d.kind == K_U1 || d.kind == K_X) && d.q < s->cb && (d.cm >> s->cb) == 0 && !d.per_block &&
-           d.job_end == 0 && d.nitems == s->nchunks &&
-           (s->cfg.mode == QCZ_MODE_FIXED || s->cfg.mode == QCZ_MODE_LOSSLESS);
+    return (s->cfg.flags & QCZ_FLAG_FUSE) && !s->cache_on && d.job_type == J_SINGLE && d.nitems > 0 &&
+           !d.per_block && d.job_end == 0 && (s->cfg.mode == QCZ_MODE_FIXED || s->cfg.mode == QCZ_MODE_LOSSLESS);
+}
+
+// the launch record of a fused run: its first gate over every chunk
+GateDesc run_launch(const qcz_state *s, const GateDesc &first)
+{
+    GateDesc r = first;
+    r.fixed_mask = r.fixed_val = 0;
+    r.check_phase = 0;
+    r.act_mask = r.act_val = 0;
+    r.nitems = s->nchunks;
+    r.njobs = (s->nchunks + 1) / 2;
+    return r;
 }
 
 qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
@@ -468,7 +483,7 @@ qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
                                              hipMemcpyHostToDevice, s->stream));
                     uploaded = true;
                 }
-                const GateDesc &d = descs[k];
+                const GateDesc d = run_launch(s, descs[k]);
                 hipEvent_t t0 = timing ? s->events[2 * d.seq] : nullptr, t1 = timing ? s->events[2 * d.seq + 1] : nullptr;
                 hipError_t e = launch_gate_run(d, ptrs(s), dev_descs + k, (int)r, grid_for(s, d), s->stream, t0, t1);
                 if (e != hipSuccess) return fail(s, QCZ_E_DEVICE, std::string("fused run launch: ") + hipGetErrorString(e));
@@ -849,7 +864,7 @@ qcz_status apply_sweep(qcz_state *s, const GateDesc *descs, size_t r, int *reaso
     // stripes over the whole other arena (the header describes the arena written to)
     qcz_status st = reset_stripes(s, 0);
     if (st != QCZ_OK) return st;
-    GateDesc d = sweep_desc(descs[0]);
+    GateDesc d = sweep_desc(r > 1 ? run_launch(s, descs[0]) : descs[0]);
     d.seq = 0;
     DevPtrs P = ptrs(s);
     P.out = s->arena[other];
@@ -1302,8 +1317,11 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
         s->stats.stops += 1;
         for (int k = 0; k < sseq; ++k) commit_logged(s, h, descs[(size_t)k], k);
         s->sel_since += (uint64_t)sseq;
-        // undo the stopped gate
-        const GateDesc &dstop = descs[(size_t)sseq];
+        // undo the stopped gate (a fused run's undo log covers every chunk)
+        const bool run_stop = sseq < (int)s->run_first.size() && s->run_first[(size_t)sseq] == sseq &&
+                              s->run_last[(size_t)sseq] > sseq;
+        const GateDesc &gstop = descs[(size_t)sseq];
+        const GateDesc dstop = run_stop ? run_launch(s, gstop) : gstop;
         DevPtrs P = ptrs(s);
         const uint64_t work = dstop.job_type == J_PERMUTE ? dstop.njobs : launch_items(dstop);
         const int rg = (int)std::max<uint64_t>(1, std::min<uint64_t>((work + kWG - 1) / kWG, 65535));
@@ -1326,13 +1344,13 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
             if (compacted_for == (int)idx) {
                 // the gate's new streams do not fit beside the live ones even after
                 // compaction: a sweep into the other arena, else job ranges
-                if (swept_out != (int)idx && sweepable(s, dstop) && sweep_may_fit(s)) {
+                if (swept_out != (int)idx && sweepable(s, gstop) && sweep_may_fit(s)) {
                     sweep_for = (int)idx;
                     continue;
                 }
-                if (!ranges_allowed(s) || dstop.job_type == J_PERMUTE || dstop.njobs < 2)
+                if (!ranges_allowed(s) || gstop.job_type == J_PERMUTE || gstop.njobs < 2)
                     return fail(s, QCZ_E_NOMEM, "arena too small for one gate after compaction");
-                st = apply_in_ranges(s, dstop);
+                st = apply_in_ranges(s, gstop);
                 if (st != QCZ_OK) return st;
                 idx += 1;
                 s->sel_since += 1;
