@@ -4,10 +4,12 @@
 Default workload "qaoa34": the largest configuration that one GPU holds, a
 34-qubit QAOA circuit (H on every qubit, p = 4 layers of Rzz on a seeded
 3-regular graph and Rx mixers; 374 gates) on complex128 amplitudes, 2^20-
-amplitude blocks (chunks of 1024 amplitudes), error bound 1e-4 on every gate,
+amplitude blocks (chunks of 1024 amplitudes), error bound 1e-5 on every gate,
 256 GiB uncompressed.  The circuit is one continuing run cut into
 warmup + steps windows of consecutive gates; a step is one window.  Inputs
-(gate list, compressed state) are in HBM before timing.  Other workloads:
+(gate list, compressed state) are in HBM before timing.  Gates whose jobs
+lie inside single chunks run fused (one pass per run), and a gate that does
+not fit beside the live streams sweeps into the other arena.  Other workloads:
 grover24+qft24 (the 24-qubit pair), grid30, grover34.
 
 Prints one JSON line:
@@ -150,9 +152,9 @@ LARGE = {
     # name: (qubits, block_log2, description)
     "grid30": (30, 20, "30-qubit 5x6-grid random circuit, depth 20, {sqrtX, sqrtY, T} + CZ patterns, bound 1e-4"),
     "grover34": (34, 20, "34-qubit Grover, 8 iterations, bound 1e-5 (256 GiB uncompressed)"),
-    "qaoa34": (34, 20, "34-qubit QAOA, p=4 on a seeded 3-regular graph, bound 1e-4 for every block (the rule); "
-                       "with --selector also the learned per-block levels at the same per-step budget "
-                       "(256 GiB uncompressed)"),
+    "qaoa34": (34, 20, "34-qubit QAOA, p=4 on a seeded 3-regular graph, bound 1e-5 on every gate (Eq. (11) "
+                       "fidelity lower bound >= 0.99 over the 374 gates); with --selector also the learned "
+                       "per-block levels (256 GiB uncompressed)"),
 }
 
 
@@ -173,11 +175,13 @@ def large_config(args, torch, cc, qcz):
         level, mode, pool = 1, qcz.MODE_FIXED, min(250 << 30, free - (12 << 30))
     else:
         gates = cc.qaoa(n, 4, 3, 5)[0]
-        level, mode = 2, qcz.MODE_FIXED
+        level, mode = 1, qcz.MODE_FIXED
         pool = min(250 << 30, free - (12 << 30))
+    if args.level >= 0:
+        level = args.level
     if args.gates:
         gates = gates[:args.gates]
-    flags = qcz.FLAG_TIMING | qcz.FLAG_RANGES | (qcz.FLAG_FUSE if args.fuse else 0) | \
+    flags = qcz.FLAG_TIMING | qcz.FLAG_RANGES | (0 if args.no_fuse else qcz.FLAG_FUSE) | \
         (qcz.FLAG_ENTROPY if args.entropy else 0)
     passes = args.warmup + args.steps
     win = -(-len(gates) // passes)
@@ -240,7 +244,7 @@ def large_config(args, torch, cc, qcz):
                 "kernel": "job_kernel<16, 2, ARENA, ARENA, gate%s> (fused decode-gate-encode)" % (
                     ", entropy" if args.entropy else ""),
                 "avg_launch_us": round(avg_ms * 1e3, 3), "algorithmic_bytes_per_launch": round(per_launch, 1),
-                "launches": timed, "range_launches": stats["range_launches"]}
+                "launches": timed, "range_launches": stats["range_launches"], "sweep_gates": stats["sweep_gates"]}
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -255,7 +259,8 @@ def large_config(args, torch, cc, qcz):
         "config": {"workload": args.workload, "description": desc, "qubits": n, "block_amplitudes": 1 << bl,
                    "bound": [0.0, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1][level], "gates": int(len(gates)),
                    "gates_per_step": win, "final_level": fp["level"], "pool_bytes": int(pool),
-                   "entropy_stage": bool(args.entropy), "parallelism": "single GPU"},
+                   "entropy_stage": bool(args.entropy), "fused_runs": not args.no_fuse,
+                   "parallelism": "single GPU"},
         "compression_ratio_min": round(fp["raw_bytes"] / (fp["max_compressed"] + fp["table_bytes"]), 3),
         "compression_ratio_final": round(fp["ratio"], 3),
         "peak_compressed_bytes": fp["max_compressed"],
@@ -269,13 +274,44 @@ def large_config(args, torch, cc, qcz):
         "cpu_baseline": cpu,
     }
     if args.workload == "qaoa34" and args.selector:
-        line["selector"] = selector_run(args, torch, cc, qcz, n, bl, gates, pool, trace, st)
+        line["selector"] = selector_run(args, torch, cc, qcz, n, bl, gates, pool, trace, st,
+                                        [0.0, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1][level])
+    if args.workload == "qaoa34" and not args.gates and args.fidelity_qubits:
+        st.close()   # (also after the selector run, which closed it: closing twice is harmless)
+        torch.cuda.empty_cache()
+        line["fidelity"]["same_generator"] = qaoa_fidelity(qcz, cc, args.fidelity_qubits, bl, level, flags)
     print(json.dumps(line), flush=True)
 
 
-def selector_run(args, torch, cc, qcz, n, bl, gates, pool, trace, st):
-    """The learned per-block levels at the rule's per-step budget (1e-4),
-    trained on the device from teacher traces of small circuits."""
+def qaoa_fidelity(qcz, cc, n, bl, level, flags):
+    """End-to-end fidelity of the compressed run against uncompressed fp64 on
+    the same QAOA generator at n qubits: the reference is the lossless run
+    (every stored value the exact fp64 result of the gate arithmetic),
+    compared through qcz_overlap (Eq. (9))."""
+    gates = cc.qaoa(n, 4, 3, 5)[0]
+    log("fidelity: %d-qubit QAOA, lossless reference and level %d" % (n, level))
+    ex = qcz.State(n, bl, mode=qcz.MODE_LOSSLESS, pool_bytes=48 << 30, flags=qcz.FLAG_FUSE | qcz.FLAG_RANGES,
+                   batch=128)
+    ex.apply(gates)
+    lo = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=level, pool_bytes=24 << 30,
+                   flags=(flags & ~qcz.FLAG_TIMING) | qcz.FLAG_RANGES, batch=128)
+    lo.apply(gates)
+    ov = lo.overlap(ex)
+    n2_lo, n2_ex = lo.moments()[1], ex.moments()[1]
+    fp = lo.footprint()
+    out = {"qubits": n, "gates": int(len(gates)), "fidelity_raw": abs(ov),
+           "fidelity_norm": abs(ov) / math.sqrt(n2_lo * n2_ex), "fidelity_lower_bound": fp["fidelity_lower_bound"],
+           "compression_ratio_final": round(fp["ratio"], 3),
+           "compression_ratio_lossless": round(ex.footprint()["ratio"], 3)}
+    ex.close()
+    lo.close()
+    return out
+
+
+def selector_run(args, torch, cc, qcz, n, bl, gates, pool, trace, st, beta):
+    """The learned per-block levels at the rule's per-step budget (the bound
+    of the run's level), trained on the device from teacher traces of small
+    circuits."""
     from paper_1911_04034_amd import selector as sel
     train = [(cc.biased_local(12, 6, 8, 1), 12, 6), (cc.biased_local(13, 7, 8, 2), 13, 7),
              (cc.biased_local(13, 6, 8, 3), 13, 6), (cc.grover(12, 12, 11)[0], 12, 6),
@@ -288,7 +324,7 @@ def selector_run(args, torch, cc, qcz, n, bl, gates, pool, trace, st):
     st.close()
     torch.cuda.empty_cache()
     st2 = qcz.State(n, bl, mode=qcz.MODE_PERBLOCK, level=0, pool_bytes=pool, batch=128, flags=qcz.FLAG_RANGES)
-    st2.set_selector(params, 1e-4, 16)
+    st2.set_selector(params, beta, 16)
     t0 = time.perf_counter()
     strace = []
     for k in range(0, len(gates), 16):
@@ -328,7 +364,14 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="launch from graphs instead of timing each kernel")
     ap.add_argument("--selector", action="store_true", help="qaoa34: also run the learned per-block selector")
     ap.add_argument("--fuse", action="store_true",
-                    help="grover24/qft24: fuse runs of in-chunk single-qubit gates (a separate figure)")
+                    help="grover24/qft24: fuse runs of gates whose jobs lie inside single chunks (a separate figure)")
+    ap.add_argument("--level", type=int, default=-1,
+                    help="large configurations: error-bound level (0 lossless, 1..5: 1e-5 .. 1e-1)")
+    ap.add_argument("--fidelity-qubits", type=int, default=30,
+                    help="qaoa34: also measure the fidelity against lossless fp64 on the same generator at this "
+                         "many qubits (0: skip)")
+    ap.add_argument("--no-fuse", action="store_true",
+                    help="large configurations: one pass per gate instead of fused runs (QCZ_FLAG_FUSE)")
     ap.add_argument("--entropy", action="store_true",
                     help="the entropy-coding stage (per-lane Huffman codes of the residuals, QCZ_FLAG_ENTROPY)")
     ap.add_argument("--cache", action="store_true",
