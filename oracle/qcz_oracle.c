@@ -276,6 +276,21 @@ static size_t pack_body_read(const uint8_t *in, size_t avail, int N, int K, uint
 #define OQ_HUFF_MAXLEN 8
 enum { OQ_LANE_RAW = 0, OQ_LANE_CONST = 1, OQ_LANE_CODED = 2 };
 
+/* ------------------------------------------------------------------------- */
+/* Solution D of Sec. 4.2: the real and imaginary parts are separated before  */
+/* the Solution C steps.  Header bit 6 (R) marks a PACK or SPARSE stream      */
+/* whose values are stored in the order re a_0, re a_1, ..., re a_{A-1},      */
+/* im a_0, ..., im a_{A-1} (A = C/2 amplitudes) instead of interleaved; every */
+/* step after the reordering (XOR chain, truncation, codes, bitmap, entropy   */
+/* stage) runs on that sequence unchanged.  CONST2 is defined on amplitudes   */
+/* and never carries R.                                                       */
+/* ------------------------------------------------------------------------- */
+#define OQ_HDR_RSH 0x40u
+#define OQ_ENC_RESHUFFLE 8  /* store PACK / SPARSE values re parts first, then im parts (Solution D) */
+
+/* stored position j -> interleaved position */
+static int rsh_pos(int j, int C) { return j < C / 2 ? 2 * j : 2 * (j - C / 2) + 1; }
+
 static int nib_lanes(int K) { return (K + 3) / 4; }
 static int lane_width(int K, int j) { int w = K - 4 * j; return w < 4 ? w : 4; }
 static unsigned lane_symbol(uint64_t t, int K, int j)
@@ -634,6 +649,13 @@ size_t oq_encode_chunk_ex(const double *x, int C, int level, int flags, uint8_t 
         put_u64(out + 12, t[1]);
         size = 20;
     } else {
+        int rsh = (flags & OQ_ENC_RESHUFFLE) != 0;
+        if (rsh) {   /* Solution D: the values in stored order */
+            uint64_t *u = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)C);
+            for (int j = 0; j < C; ++j) u[j] = t[rsh_pos(j, C)];
+            memcpy(t, u, sizeof(uint64_t) * (size_t)C);
+            free(u);
+        }
         int nnz = 0;
         int *pos = (int *)malloc(sizeof(int) * (size_t)C);
         int *allpos = (int *)malloc(sizeof(int) * (size_t)C);
@@ -653,7 +675,8 @@ size_t oq_encode_chunk_ex(const double *x, int C, int level, int flags, uint8_t 
                                           : ent_body(t, allpos, C, C, K, hooks, NULL));
             ent = force || esize < base;
         }
-        uint32_t hdr = (uint32_t)((sparse ? OQ_MODE_SPARSE : OQ_MODE_PACK) | (lev << 2)) | (ent ? OQ_HDR_ENT : 0u);
+        uint32_t hdr = (uint32_t)((sparse ? OQ_MODE_SPARSE : OQ_MODE_PACK) | (lev << 2)) | (ent ? OQ_HDR_ENT : 0u) |
+                       (rsh ? OQ_HDR_RSH : 0u);
         put_u32(out, hdr);
         if (sparse) {
             uint64_t bpos = 0;
@@ -676,10 +699,11 @@ int oq_decode_chunk(const uint8_t *in, size_t len, int C, double *x)
     if (C < 4 || (C & (C - 1)) != 0 || len < 4) return -1;
     uint32_t hdr = get_u32(in);
     int mode = (int)(hdr & 3u), lev = (int)((hdr >> 2) & 7u), ent = (hdr & OQ_HDR_ENT) != 0;
-    if ((hdr >> 6) != 0 || lev >= OQ_NLEVELS) return -1;
+    int rsh = (hdr & OQ_HDR_RSH) != 0;
+    if ((hdr >> 7) != 0 || lev >= OQ_NLEVELS) return -1;
     int K = oq_sig_bits(lev);
     if (mode == OQ_MODE_CONST2) {
-        if (len != 20 || ent) return -1;
+        if (len != 20 || ent || rsh) return -1;
         uint64_t t0 = get_u64(in + 4), t1 = get_u64(in + 12);
         for (int i = 0; i < C; ++i) x[i] = bitsd((i & 1) ? t1 : t0);
         return 0;
@@ -708,6 +732,12 @@ int oq_decode_chunk(const uint8_t *in, size_t len, int C, double *x)
         }
     } else {
         rc = -1;
+    }
+    if (rc == 0 && rsh) {   /* back to interleaved order */
+        double *u = (double *)malloc(sizeof(double) * (size_t)C);
+        for (int j = 0; j < C; ++j) u[rsh_pos(j, C)] = x[j];
+        memcpy(x, u, sizeof(double) * (size_t)C);
+        free(u);
     }
     free(s);
     free(pos);
@@ -962,7 +992,8 @@ typedef struct {
     double norm2;             /* per-block mode: squared norm of the stored state */
     uint64_t gates_applied, lossy_steps;
     uint64_t min_compressed, max_compressed;
-    int enc_flags;            /* OQ_ENC_ENTROPY: chunks may take the entropy-coded body */
+    int enc_flags;            /* OQ_ENC_ENTROPY: chunks may take the entropy-coded body;
+                                 OQ_ENC_RESHUFFLE: Solution D value order */
     uint8_t *scratch_out[2];
 } oq_sim;
 
@@ -1196,7 +1227,7 @@ int oq_sim_set_chunk(oq_sim *s, uint64_t c, const uint8_t *in, size_t len)
 
 /* Codec flags of later encodes (OQ_ENC_ENTROPY: the entropy-coded body is
  * taken when it is smaller).  The initial state is the same either way. */
-void oq_sim_set_codec(oq_sim *s, int flags) { s->enc_flags = flags & OQ_ENC_ENTROPY; }
+void oq_sim_set_codec(oq_sim *s, int flags) { s->enc_flags = flags & (OQ_ENC_ENTROPY | OQ_ENC_RESHUFFLE); }
 
 int oq_sim_set_block_level(oq_sim *s, uint64_t b, int level)
 {

@@ -173,6 +173,7 @@ def chunk_cap(C: int) -> int:
 ENC_ENTROPY = 1     # the encoder may take the entropy-coded body
 ENC_FORCE_ENT = 2   # test hook: always entropy-code the PACK / SPARSE body
 ENC_FORCE_CODED = 4 # test hook: every lane with two or more symbols CODED, one symbol CONST
+ENC_RESHUFFLE = 8   # Solution D: PACK / SPARSE values stored re parts first, then im parts (header bit 6)
 
 
 def encode_chunk(x, level: int, flags: int = 0) -> bytes:
@@ -274,7 +275,7 @@ class Sim:
         if not self._h:
             raise ValueError("bad simulator configuration")
         if codec:
-            lib().oq_sim_set_codec(self._h, codec)   # ENC_ENTROPY: the entropy stage
+            lib().oq_sim_set_codec(self._h, codec)   # ENC_ENTROPY / ENC_RESHUFFLE for later encodes
         self.cb = lib().oq_sim_chunk_log2(self._h)
         self.C = 2 << self.cb
         self.nchunks = 1 << (n - self.cb)
