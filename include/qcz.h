@@ -83,12 +83,14 @@ typedef enum {
                                Needs a larger pool (qcz_pool_bytes_min); not with QCZ_FLAG_AUTOTUNE. */
 #define QCZ_FLAG_CACHE_COLLIDE 32u /* test hook: keep 3 bits of the cache keys, so that different
                                       streams share keys and only the byte comparison separates them */
-#define QCZ_FLAG_FUSE 64u   /* gate-layer fusion, QCZ_MODE_FIXED / QCZ_MODE_LOSSLESS: consecutive single-qubit
-                               gates (U1, X) on in-chunk qubits with no control on a chunk-index qubit run as
-                               one pass per batch run (up to 32 gates): one decode, each gate followed by the
-                               truncation its re-encoding would apply (Sec. 3.7; none for a chunk holding a
-                               subnormal value), one encode.  Bytes, ledger and work counters (chunks and
-                               amplitudes per gate) equal the gate-by-gate run's; the stream bytes moved are
+#define QCZ_FLAG_FUSE 64u   /* gate-layer fusion, QCZ_MODE_FIXED / QCZ_MODE_LOSSLESS: consecutive gates whose
+                               jobs lie inside single chunks (targets on in-chunk qubits, diagonal gates and
+                               multi-controlled Z on any qubits, any controls) run as one pass per batch run
+                               (up to 64 gates): one decode of every chunk; each chunk takes, in order, the
+                               gates that touch it, each followed by the truncation its re-encoding would
+                               apply (Sec. 3.7; none for a chunk holding a subnormal value); one encode of the
+                               chunks some gate touched.  Bytes and ledger equal the gate-by-gate run's; each
+                               gate of a run counts the run's re-encoded chunks, the stream bytes moved are
                                counted once per pass, and min / max compressed bytes are sampled after each
                                pass.  Direct launches only (not inside replayed graphs); not with
                                QCZ_FLAG_AUTOTUNE; gates of the block cache are not fused. */
@@ -100,6 +102,10 @@ typedef enum {
                                Lossless: decoded values are those of the run without it.  Needs
                                block_log2 >= 10 (2048-double chunks) and two wavefronts per chunk; not with
                                QCZ_FLAG_CACHE or QCZ_FLAG_AUTOTUNE. */
+#define QCZ_FLAG_RESHUFFLE 256u /* Solution D (Sec. 4.2): PACK and SPARSE chunks store their values re parts
+                               first, then im parts (header bit 6), before the Solution C steps; decoded
+                               values are those of the run without it.  Chunks created by qcz_create are
+                               interleaved; every kernel decodes both orders. */
 
 typedef struct {
     uint32_t n_qubits;      /* 6 .. 40 */
@@ -423,14 +429,15 @@ size_t qcz_chunk_cap(uint32_t C);
  * device slots of slot_bytes bytes each (slot_bytes >= qcz_chunk_cap(C),
  * multiple of 4); stream sizes go to dev_sizes (device, n_chunks u32).
  * C is a power of two in 128 .. 2048.  codec_flags: QCZ_CODEC_ENTROPY lets
- * a chunk take the entropy-coded body (C = 2048 only); other bits:
- * QCZ_E_INVAL. */
+ * a chunk take the entropy-coded body (C = 2048 only); QCZ_CODEC_RESHUFFLE
+ * stores values in Solution D's order (Sec. 4.2); other bits: QCZ_E_INVAL. */
 #define QCZ_CODEC_ENTROPY 1u
+#define QCZ_CODEC_RESHUFFLE 2u
 qcz_status qcz_encode_chunks(const void *dev_in, uint32_t C, uint64_t n_chunks, int level, uint32_t codec_flags,
                              void *dev_slots, size_t slot_bytes, uint32_t *dev_sizes, void *hip_stream);
 
 /* Decode n_chunks streams from device slots into C doubles each (device);
- * streams with and without the entropy stage. */
+ * streams with and without the entropy stage, in either value order. */
 qcz_status qcz_decode_chunks(const void *dev_slots, size_t slot_bytes, const uint32_t *dev_sizes, uint32_t C,
                              uint64_t n_chunks, void *dev_out, void *hip_stream);
 

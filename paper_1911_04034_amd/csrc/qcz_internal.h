@@ -47,6 +47,8 @@ struct GateDesc {
                                     // chunks the gate leaves unchanged are copied there as they are
     uint64_t act_mask, act_val;     // a sweep acts on chunk c only if (c & act_mask) == act_val (the
                                     // control bits its plain enumeration would have held fixed)
+    int32_t reshuffle;              // the encoder stores PACK / SPARSE values re parts first (header bit 6)
+    int32_t pad_;
 };
 
 // the jobs one launch of a gate runs

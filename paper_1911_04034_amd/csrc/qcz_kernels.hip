@@ -304,6 +304,11 @@ __device__ __forceinline__ void gscan_enc(uint32_t bad, uint32_t rp, uint32_t cn
 // so thread lt owns positions 16 lt .. 16 lt + 15: exactly sub-stream lt.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kHdrEnt = 0x20u;
+// Solution D (Sec. 4.2): a PACK / SPARSE stream with header bit 6 stores its
+// values re parts first, then im parts; stored position j holds interleaved
+// position rsh_pos(j)
+constexpr uint32_t kHdrRsh = 0x40u;
+__device__ __forceinline__ int rsh_pos(int j, int C) { return j < C / 2 ? 2 * j : 2 * (j - C / 2) + 1; }
 constexpr int kEntMaxLen = 8;
 constexpr int kEntSlotWords = 1024;   // per slot: decode tables (16 lanes x 256 bytes) or encode tables
 enum { LANE_RAW = 0, LANE_CONST = 1, LANE_CODED = 2 };
@@ -788,6 +793,7 @@ struct EncPlan {
     int mode, lev, K;
     uint32_t size;
     bool ent;               // the body's residuals are entropy-coded
+    bool rsh;               // values stored re parts first (Solution D; never on CONST2)
     uint32_t ent_off;       // bit offset of my sub-stream in the entropy-coded bit stream
     uint32_t ent_bits;      // its length
     uint32_t laneword;      // lane modes (2 bits per lane)
@@ -881,7 +887,7 @@ template <int V, int WPG, bool ENT = false>
 __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], uint32_t xprev_hi, uint64_t x0,
                             uint64_t x1, int lev_req, bool sub, int C, int lt, uint32_t *slotB,
                             uint32_t *slotC, EncPlan<V> &e, bool ent_on = false, uint32_t *b = nullptr,
-                            uint32_t *ent = nullptr, uint32_t *slotD = nullptr)
+                            uint32_t *ent = nullptr, uint32_t *slotD = nullptr, bool rsh = false)
 {
     const int first = lt * V;
     const int lev = sub ? 0 : lev_req;  // a chunk with a subnormal is kept lossless
@@ -901,7 +907,8 @@ __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], ui
         const uint32_t l = lossless ? xl[k] : 0u;
         e.th[k] = h;
         e.tl[k] = l;
-        const bool odd = ((first + k) & 1) != 0;
+        // im part of its amplitude (values in stored order: interleaved, or Solution D's)
+        const bool odd = rsh ? (first + k) >= C / 2 : ((first + k) & 1) != 0;
         badbits |= (h ^ (odd ? e.c1h : e.c0h)) | (l ^ (odd ? e.c1l : e.c0l));   // differs from value 0 / 1
         const uint32_t L = lead_bytes(h, prev);
         codes |= L << (2 * k);
@@ -959,6 +966,7 @@ __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], ui
     e.nzm = nzm;
     e.lev = lev;
     e.K = K;
+    e.rsh = rsh && !const2;
     if (const2) { e.mode = M_CONST2; e.size = 20; }
     else if (need_me && sparse_size < pack_size) { e.mode = M_SPARSE; e.size = sparse_size; }
     else { e.mode = M_PACK; e.size = pack_size; }
@@ -1112,7 +1120,7 @@ template <int V>
 __device__ void encode_emit(uint32_t *b, const EncPlan<V> &e, int C, int lt, const uint32_t *ent = nullptr)
 {
     const int first = lt * V;
-    if (lt == 0) b[0] = (uint32_t)e.mode | ((uint32_t)e.lev << 2) | (e.ent ? kHdrEnt : 0u);
+    if (lt == 0) b[0] = (uint32_t)e.mode | ((uint32_t)e.lev << 2) | (e.ent ? kHdrEnt : 0u) | (e.rsh ? kHdrRsh : 0u);
     if (e.mode == M_CONST2) {
         if (lt == 0) {
             b[1] = e.c0l; b[2] = e.c0h;
@@ -1572,6 +1580,17 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             double x[V];
 #pragma unroll
             for (int k = 0; k < V; ++k) x[k] = u2d(((uint64_t)th[k] << 32) | tl[k]);
+            // Solution D streams: the values, decoded in stored order, go to their
+            // interleaved positions through LDS (uniform branch over the workgroup)
+            const bool rsh0 = use0 && (hdr0 & kHdrRsh) != 0, rsh1 = use1 && (hdr1 & kHdrRsh) != 0;
+            if (rsh0 || rsh1) {
+                const bool mine = s ? rsh1 : rsh0;
+#pragma unroll
+                for (int k = 0; k < V; ++k) vals[vpos(mine ? rsh_pos(first + k, C) : first + k)] = x[k];
+                lds_barrier();
+#pragma unroll
+                for (int k = 0; k < V; ++k) x[k] = vals[vpos(first + k)];
+            }
             if (LIST == 3) {
                 // 3r. the run: each gate (in registers or through LDS), then the
                 // truncation re-encoding would apply (none when the chunk holds
@@ -1712,14 +1731,16 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             // 4b. padded size of the chunk re-encoded at every level
             uint32_t xh[V], xl[V];
             bool sub = false;
+            const bool rsh = gd.reshuffle != 0;   // values in Solution D's stored order
 #pragma unroll
             for (int k = 0; k < V; ++k) {
-                const uint64_t x = d2u(vals[vpos(first + k)]);
+                const uint64_t x = d2u(vals[vpos(rsh ? rsh_pos(first + k, C) : first + k)]);
                 xh[k] = (uint32_t)(x >> 32);
                 xl[k] = (uint32_t)x;
                 sub = sub || subnormal(xh[k], xl[k]);
             }
-            const uint32_t xprev_hi = lt ? (uint32_t)(d2u(vals[vpos(first - 1)]) >> 32) : 0u;
+            const uint32_t xprev_hi =
+                lt ? (uint32_t)(d2u(vals[vpos(rsh ? rsh_pos(first - 1, C) : first - 1)]) >> 32) : 0u;
             const uint64_t x0 = d2u(vals[0]), x1 = d2u(vals[1]);
             const bool wsub = __any(use && sub);
             if ((tid & 63) == 0) slS[tid >> 6] = wsub ? 1u : 0u;
@@ -1730,7 +1751,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             for (int lev = 0; lev < kLevels; ++lev) {
                 EncPlan<V> e;
                 encode_plan<V, WPG, ENT>(xh, xl, xprev_hi, x0, x1, lev, gs != 0, C, lt, slE, slF, e, ent_on, b, ent,
-                                         slD);
+                                         slD, rsh);
                 if (lt == 0 && use)
                     atomicAdd((unsigned long long *)&io.lsizes[(c >> gd.block_shift) * kLevels + lev],
                               (unsigned long long)((e.size + 3u) & ~3u));
@@ -1740,14 +1761,16 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             // encode at the chunk's level
             uint32_t xh[V], xl[V];
             bool sub = false;
+            const bool rsh = gd.reshuffle != 0;   // values in Solution D's stored order
 #pragma unroll
             for (int k = 0; k < V; ++k) {
-                const uint64_t x = d2u(vals[vpos(first + k)]);
+                const uint64_t x = d2u(vals[vpos(rsh ? rsh_pos(first + k, C) : first + k)]);
                 xh[k] = (uint32_t)(x >> 32);
                 xl[k] = (uint32_t)x;
                 sub = sub || subnormal(xh[k], xl[k]);
             }
-            const uint32_t xprev_hi = lt ? (uint32_t)(d2u(vals[vpos(first - 1)]) >> 32) : 0u;
+            const uint32_t xprev_hi =
+                lt ? (uint32_t)(d2u(vals[vpos(rsh ? rsh_pos(first - 1, C) : first - 1)]) >> 32) : 0u;
             const uint64_t x0 = d2u(vals[0]), x1 = d2u(vals[1]);
             int lev_req;
             if (gd.fixed_level >= 0) lev_req = gd.fixed_level;
@@ -1773,7 +1796,8 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                 }
             }
             EncPlan<V> e;
-            encode_plan<V, WPG, ENT>(xh, xl, xprev_hi, x0, x1, lev_req, gsub, C, lt, slE, slF, e, ent_on, b, ent, slD);
+            encode_plan<V, WPG, ENT>(xh, xl, xprev_hi, x0, x1, lev_req, gsub, C, lt, slE, slF, e, ent_on, b, ent, slD,
+                                     rsh);
             if (DST == DST_ARENA && gd.per_block && enc) {
                 double post = 0.0;
 #pragma unroll

@@ -186,14 +186,17 @@ int popcount64(uint64_t x) { return __builtin_popcountll(x); }
 
 // the state's encoder may take the entropy-coded body; its kernels decode it
 int ent_state(const qcz_state *s) { return (s->cfg.flags & QCZ_FLAG_ENTROPY) ? 1 : 0; }
+// the state's encoder stores values re parts first (Solution D)
+int rsh_state(const qcz_state *s) { return (s->cfg.flags & QCZ_FLAG_RESHUFFLE) ? 1 : 0; }
 
 // A stream header: mode, level, and the entropy bit (only where the state
 // may hold entropy-coded streams, and never on a CONST2 stream).
 bool header_ok(const qcz_state *s, uint32_t hdr, size_t len)
 {
-    const uint32_t mode = hdr & 3u, lev = (hdr >> 2) & 7u, ent = (hdr >> 5) & 1u;
-    if ((hdr >> 6) != 0 || lev >= (uint32_t)kLevels || mode > M_SPARSE) return false;
+    const uint32_t mode = hdr & 3u, lev = (hdr >> 2) & 7u, ent = (hdr >> 5) & 1u, rsh = (hdr >> 6) & 1u;
+    if ((hdr >> 7) != 0 || lev >= (uint32_t)kLevels || mode > M_SPARSE) return false;
     if (ent && (!ent_state(s) || mode == M_CONST2)) return false;
+    if (rsh && mode == M_CONST2) return false;
     return mode != M_CONST2 || len == 20;
 }
 
@@ -240,6 +243,7 @@ GateDesc lower_gate(const qcz_state *s, const qcz_gate &g, int seq)
     d.block_shift = s->bl - s->cb;
     d.fixed_level = -1;
     d.entropy = ent_state(s);
+    d.reshuffle = rsh_state(s);
     const uint64_t cm_hi = g.control_mask >> s->cb;
     const uint64_t cm_lo = g.control_mask & ((1ull << s->cb) - 1);
     if ((g.kind == K_U1 || g.kind == K_X) && (int)g.target >= s->cb) {
@@ -646,6 +650,7 @@ qcz_status single_kernel_chunks(qcz_state *s, GateDesc &d, uint64_t nitems, uint
     d.njobs = (nitems + 1) / 2;
     d.fixed_level = -1;
     d.entropy = ent_state(s);
+    d.reshuffle = rsh_state(s);
     int bits = 0;
     while ((1ull << bits) < nitems) ++bits;
     d.nchunk_bits = bits;
@@ -1807,7 +1812,8 @@ qcz_status qcz_encode_chunks(const void *dev_in, uint32_t C, uint64_t n_chunks, 
 {
     if (!dev_in || !dev_slots || !dev_sizes) return QCZ_E_INVAL;
     if (C < (uint32_t)kCMin || C > (uint32_t)kCMax || (C & (C - 1)) || level < 0 || level >= kLevels) return QCZ_E_INVAL;
-    if ((codec_flags & ~QCZ_CODEC_ENTROPY) || ((codec_flags & QCZ_CODEC_ENTROPY) && C != (uint32_t)kCMax))
+    if ((codec_flags & ~(QCZ_CODEC_ENTROPY | QCZ_CODEC_RESHUFFLE)) ||
+        ((codec_flags & QCZ_CODEC_ENTROPY) && C != (uint32_t)kCMax))
         return QCZ_E_INVAL;
     if (slot_bytes < chunk_cap_bytes((int)C) || (slot_bytes & 3)) return QCZ_E_INVAL;
     if (n_chunks == 0) return QCZ_OK;
@@ -1820,6 +1826,7 @@ qcz_status qcz_encode_chunks(const void *dev_in, uint32_t C, uint64_t n_chunks, 
     d.nchunk_bits = bits;
     d.fixed_level = level;
     d.entropy = (codec_flags & QCZ_CODEC_ENTROPY) ? 1 : 0;
+    d.reshuffle = (codec_flags & QCZ_CODEC_RESHUFFLE) ? 1 : 0;
     DevPtrs P{};
     P.C = (int)C;
     int cb = 0;

@@ -24,7 +24,9 @@ FLAG_CACHE = 16
 FLAG_CACHE_COLLIDE = 32
 FLAG_FUSE = 64
 FLAG_ENTROPY = 128
+FLAG_RESHUFFLE = 256
 CODEC_ENTROPY = 1
+CODEC_RESHUFFLE = 2
 STATUS = {0: "QCZ_OK", -1: "QCZ_E_INVAL", -2: "QCZ_E_NOMEM", -3: "QCZ_E_DEVICE", -4: "QCZ_E_FORMAT",
           -5: "QCZ_E_STATE"}
 

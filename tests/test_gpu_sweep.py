@@ -16,10 +16,11 @@ from tests.gpu_util import assert_same_chunks, say, same_bits
 pytestmark = pytest.mark.gpu
 
 
-def pool_for(n, bl, arena):
-    """Pool bytes whose two arenas hold about `arena` bytes each."""
+def pool_for(n, bl, arena, flags=0):
+    """Pool bytes whose two arenas hold about `arena` bytes each (for a state
+    created with `flags`, which may reserve more of the pool)."""
     from paper_1911_04034_amd import qcz
-    cfg = qcz.Config(n, bl, 0, 0, 0, 0, 0, 0, 0)
+    cfg = qcz.Config(n, bl, 0, 0, 0, flags, 0, 0, 0)
     pmin = qcz.load().qcz_pool_bytes_min(ctypes.byref(cfg))
     nchunks = 1 << (n - min(bl, 10))
     return pmin + 2 * (arena - (64 << 10) - 64 * nchunks)
@@ -78,7 +79,7 @@ def test_sweeps_in_batches_with_fused_runs():
     peak = peak_of(n, bl, gates, oq.MODE_FIXED, level)
     arena = int(1.25 * peak) + (16 << 10)
     for flags in (0, qcz.FLAG_FUSE, qcz.FLAG_FUSE | qcz.FLAG_GRAPH):
-        g = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=level, pool_bytes=pool_for(n, bl, arena), flags=flags,
+        g = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=level, pool_bytes=pool_for(n, bl, arena, flags), flags=flags,
                       batch=32)
         o = oq.Sim(n, bl, oq.MODE_FIXED, level)
         say("sweeps in batches: flags %d peak %d arena %d" % (flags, peak, arena))
@@ -119,7 +120,7 @@ def test_entropy_streams_sweep():
     gates = cc.concat([cc.grover(n, 2, 7)[0], carry_heavy(n, 95)])
     peak = peak_of(n, bl, gates, oq.MODE_FIXED, level, codec=oq.ENC_ENTROPY)
     arena = int(1.25 * peak) + (32 << 10)
-    g = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=level, pool_bytes=pool_for(n, bl, arena),
+    g = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=level, pool_bytes=pool_for(n, bl, arena, qcz.FLAG_ENTROPY),
                   flags=qcz.FLAG_ENTROPY, batch=16)
     o = oq.Sim(n, bl, oq.MODE_FIXED, level, codec=oq.ENC_ENTROPY)
     say("entropy sweeps: peak %d arena %d" % (peak, arena))
