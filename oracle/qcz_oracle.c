@@ -693,11 +693,323 @@ size_t oq_encode_chunk_ex(const double *x, int C, int level, int flags, uint8_t 
     return size;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Solution B of Sec. 4.2 (prediction-based, complex-aware): every value is   */
+/* quantized in the logarithmic domain, predicted from the previous value of  */
+/* the same part (real parts from real parts, imaginary from imaginary), and  */
+/* the quantization codes (16,384 bins) are Huffman coded.                     */
+/*                                                                            */
+/* Log transform: the IEEE-754 bit pattern of |x|, read as an integer v (the  */
+/* bits without the sign), grows like 2^52 log2|x| (a piecewise-linear        */
+/* logarithm); one step of v changes |x| by at most a factor 1 + 2^-52.  The  */
+/* sign travels as one bit beside the code.  Quantization at level l:         */
+/* k = floor((v + W/2) / W) with bin                                          */
+/* width W = 2^w, w = 52 - t_l, t = 16, 13, 9, 6, 3 for 1e-5 .. 1e-1 (the     */
+/* largest t with 2^-(t+1) <= epsilon); the value is rebuilt from k W, which  */
+/* is within W/2 steps of v: relative error at most 2^-(t+1) <= epsilon.      */
+/* Prediction (Lorenzo in one dimension, on the quantized integers): the code */
+/* of value j is k_j - k_p, p the previous value of its part that was not     */
+/* zero (k_p = 0 before the first).  Quantizing before predicting makes every */
+/* code depend on the input values only (the dual quantization of GPU         */
+/* prediction compressors), with the same bound as predicting from rebuilt    */
+/* values.  Symbols: 0 escape (the value stored verbatim: a first value, a    */
+/* code outside the bins, a subnormal, inf or NaN, or k W beyond the finite   */
+/* range), 1 an exact zero, 2 + (code + 8190) for codes in [-8190, 8191];    */
+/* every symbol but the escape is followed by the value's sign bit.           */
+/* Lossy levels only (level 0 has no bins).                                   */
+/*                                                                            */
+/* Stream (mode 3 in the header, bits 5 and 6 zero), coding order re a_0 ..  */
+/* re a_{A-1}, im a_0 .. im a_{A-1}, in sub-streams of 32 symbols:            */
+/*   u32 header; u16 count of symbols per code length 1..16;                  */
+/*   u16 bit length of each of the C/32 sub-streams;                          */
+/*   u16 symbols in canonical order (length, then symbol), zero-padded to a   */
+/*   4-byte boundary; the codes (canonical, first bit first into an LSB-first */
+/*   bit stream, each but an escape's followed by the sign bit, sub-streams   */
+/*   back to back), zero-padded to 4 bytes; u64 escaped values in coding      */
+/*   order.                                                                   */
+/* Code lengths: Huffman over the symbols present (leaves in (count, symbol)  */
+/* order, two queues, the leaf first on equal weights); a lone symbol takes   */
+/* length 1.  With C <= 2048 values no length exceeds 16 (a depth-17 leaf     */
+/* needs a total weight of at least the Fibonacci number F(19) = 4181).       */
+/* ------------------------------------------------------------------------- */
+#define OQ_MODE_PRED 3
+#define OQ_PRED_NSYM 16384
+#define OQ_PRED_MAXLEN 16
+#define OQ_PRED_SUB 32
+
+static const int oq_pred_t[OQ_NLEVELS] = {0, 16, 13, 9, 6, 3};
+
+int oq_pred_width(int level) { return (level >= 1 && level < OQ_NLEVELS) ? 52 - oq_pred_t[level] : -1; }
+
+static int64_t pred_v(uint64_t b) { return (int64_t)(b & 0x7FFFFFFFFFFFFFFFull); }
+
+/* floor((v + W/2) / W) */
+static int64_t pred_k(int64_t v, int w) { return (v + ((int64_t)1 << (w - 1))) >> w; }
+
+/* a value quantizes when it is a nonzero normal double whose rebuilt value
+ * k W is finite */
+static int pred_quantizable(uint64_t b, int w)
+{
+    uint64_t e = (b >> 52) & 0x7FF;
+    if (e == 0 || e == 0x7FF) return 0;
+    uint64_t m = (uint64_t)pred_k(pred_v(b), w) << w;
+    return ((m >> 52) & 0x7FF) != 0x7FF && (m >> 63) == 0;
+}
+
+/* Symbols of one chunk in coding order; returns the number of escapes. */
+int oq_pred_symbols(const double *x, int C, int level, uint16_t *sym)
+{
+    int w = oq_pred_width(level), A = C / 2, nesc = 0;
+    if (w < 0) return -1;
+    for (int part = 0; part < 2; ++part) {
+        int64_t kp = 0;
+        int have = 0;   /* a previous value of the part that was not zero */
+        for (int a = 0; a < A; ++a) {
+            uint64_t b = dbits(x[2 * a + part]);
+            int j = part * A + a;
+            if ((b << 1) == 0) { sym[j] = 1; continue; }          /* +-0: the prediction goes on from k_p */
+            int64_t k = pred_k(pred_v(b), w);
+            int64_t d = k - kp;
+            if (have && pred_quantizable(b, w) && d >= -8190 && d <= 8191) sym[j] = (uint16_t)(2 + (d + 8190));
+            else { sym[j] = 0; ++nesc; }
+            kp = k;   /* (an escaped value's k is taken from the value itself) */
+            have = 1;
+        }
+    }
+    return nesc;
+}
+
+typedef struct { uint32_t cnt; int sym; } oq_leaf;
+
+static int leaf_cmp(const void *pa, const void *pb)
+{
+    const oq_leaf *a = (const oq_leaf *)pa, *b = (const oq_leaf *)pb;
+    if (a->cnt != b->cnt) return a->cnt < b->cnt ? -1 : 1;
+    return a->sym < b->sym ? -1 : (a->sym > b->sym);
+}
+
+/* Huffman code lengths of the symbols with cnt > 0 (cnt over nsym symbols);
+ * returns the longest length, or -1 with no symbol present. */
+int oq_pred_huff_lengths(const uint32_t *cnt, int nsym, uint8_t *len)
+{
+    int nl = 0;
+    for (int sy = 0; sy < nsym; ++sy) { len[sy] = 0; nl += cnt[sy] > 0; }
+    if (nl == 0) return -1;
+    oq_leaf *lv = (oq_leaf *)malloc(sizeof(oq_leaf) * (size_t)nl);
+    nl = 0;
+    for (int sy = 0; sy < nsym; ++sy)
+        if (cnt[sy]) { lv[nl].cnt = cnt[sy]; lv[nl].sym = sy; ++nl; }
+    qsort(lv, (size_t)nl, sizeof(oq_leaf), leaf_cmp);
+    if (nl == 1) { len[lv[0].sym] = 1; free(lv); return 1; }
+    uint64_t *wt = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(2 * nl));
+    int *parent = (int *)malloc(sizeof(int) * (size_t)(2 * nl));
+    int *depth = (int *)malloc(sizeof(int) * (size_t)(2 * nl));
+    for (int i = 0; i < nl; ++i) wt[i] = lv[i].cnt;
+    int nextleaf = 0, nextnode = nl, nn = nl;
+    while (nn < 2 * nl - 1) {
+        int pick[2];
+        for (int q = 0; q < 2; ++q) {
+            int take_leaf;
+            if (nextleaf < nl && nextnode < nn) take_leaf = wt[nextleaf] <= wt[nextnode];
+            else take_leaf = nextleaf < nl;
+            pick[q] = take_leaf ? nextleaf++ : nextnode++;
+        }
+        wt[nn] = wt[pick[0]] + wt[pick[1]];
+        parent[pick[0]] = parent[pick[1]] = nn;
+        ++nn;
+    }
+    depth[nn - 1] = 0;
+    for (int i = nn - 2; i >= 0; --i) depth[i] = depth[parent[i]] + 1;
+    int maxl = 0;
+    for (int i = 0; i < nl; ++i) {
+        len[lv[i].sym] = (uint8_t)depth[i];
+        if (depth[i] > maxl) maxl = depth[i];
+    }
+    free(lv); free(wt); free(parent); free(depth);
+    return maxl;
+}
+
+/* Canonical codes of lengths len[] (0: absent), lengths up to 16. */
+static void pred_canon(const uint8_t *len, int nsym, uint32_t *code)
+{
+    uint32_t c = 0;
+    int prev = 0, first = 1;
+    for (int l = 1; l <= OQ_PRED_MAXLEN; ++l)
+        for (int sy = 0; sy < nsym; ++sy) {
+            if (len[sy] != l) continue;
+            if (first) { c = 0; first = 0; }
+            else c = (c + 1) << (l - prev);
+            code[sy] = c;
+            prev = l;
+        }
+}
+
+static size_t pad4s(size_t x) { return (x + 3) & ~(size_t)3; }
+
+size_t oq_pred_cap(int C)
+{
+    return 4 + 2 * OQ_PRED_MAXLEN + 2 * (size_t)(C / OQ_PRED_SUB) + pad4s(2 * (size_t)C) +
+           4 * (size_t)((C * (OQ_PRED_MAXLEN + 1) + 31) / 32) + 8 * (size_t)C;
+}
+
+/* Encode one chunk with Solution B at lossy level 1..5; returns its size
+ * (0 for a bad size or level).  `out` holds oq_pred_cap(C) bytes. */
+size_t oq_encode_pred(const double *x, int C, int level, uint8_t *out)
+{
+    if (C < 64 || (C & (C - 1)) != 0 || oq_pred_width(level) < 0) return 0;
+    int A = C / 2, NS = C / OQ_PRED_SUB;
+    uint16_t *sym = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)C);
+    int nesc = oq_pred_symbols(x, C, level, sym);
+    uint32_t *cnt = (uint32_t *)calloc(OQ_PRED_NSYM, sizeof(uint32_t));
+    uint8_t *len = (uint8_t *)malloc(OQ_PRED_NSYM);
+    uint32_t *code = (uint32_t *)calloc(OQ_PRED_NSYM, sizeof(uint32_t));
+    for (int j = 0; j < C; ++j) cnt[sym[j]] += 1;
+    oq_pred_huff_lengths(cnt, OQ_PRED_NSYM, len);
+    pred_canon(len, OQ_PRED_NSYM, code);
+    memset(out, 0, oq_pred_cap(C));
+    put_u32(out, (uint32_t)(OQ_MODE_PRED | (level << 2)));
+    size_t o = 4;
+    int nsym = 0;
+    for (int l = 1; l <= OQ_PRED_MAXLEN; ++l) {
+        int c = 0;
+        for (int sy = 0; sy < OQ_PRED_NSYM; ++sy) c += len[sy] == l;
+        out[o] = (uint8_t)c; out[o + 1] = (uint8_t)(c >> 8);
+        o += 2;
+        nsym += c;
+    }
+    size_t sub_o = o;
+    o += 2 * (size_t)NS;
+    for (int l = 1; l <= OQ_PRED_MAXLEN; ++l)
+        for (int sy = 0; sy < OQ_PRED_NSYM; ++sy)
+            if (len[sy] == l) { out[o] = (uint8_t)sy; out[o + 1] = (uint8_t)(sy >> 8); o += 2; }
+    o = pad4s(o);
+    uint64_t bpos = 0;
+    for (int i = 0; i < NS; ++i) {
+        uint64_t b0 = bpos;
+        for (int j = i * OQ_PRED_SUB; j < (i + 1) * OQ_PRED_SUB; ++j) {
+            int l = len[sym[j]];
+            put_bits(out + o, &bpos, bit_reverse(code[sym[j]], l), l);   /* first code bit at the lowest position */
+            if (sym[j] != 0) {
+                int a = j < A ? j : j - A, part = j < A ? 0 : 1;
+                put_bits(out + o, &bpos, dbits(x[2 * a + part]) >> 63, 1);
+            }
+        }
+        uint32_t sl = (uint32_t)(bpos - b0);
+        out[sub_o + 2 * i] = (uint8_t)sl; out[sub_o + 2 * i + 1] = (uint8_t)(sl >> 8);
+    }
+    o += 4 * (size_t)((bpos + 31) / 32);
+    for (int j = 0; j < C; ++j)
+        if (sym[j] == 0) {
+            int a = j < A ? j : j - A, part = j < A ? 0 : 1;
+            put_u64(out + o, dbits(x[2 * a + part]));
+            o += 8;
+        }
+    (void)nesc;
+    (void)nsym;
+    free(sym); free(cnt); free(len); free(code);
+    return o;
+}
+
+/* Decode a Solution B stream; 0 on success, -1 when malformed. */
+static int decode_pred(const uint8_t *in, size_t len, int C, double *x)
+{
+    uint32_t hdr = get_u32(in);
+    int level = (int)((hdr >> 2) & 7u), w = oq_pred_width(level);
+    if ((hdr & 3u) != OQ_MODE_PRED || (hdr >> 5) != 0 || w < 0 || C < 64) return -1;
+    int A = C / 2, NS = C / OQ_PRED_SUB;
+    size_t o = 4;
+    int cntl[OQ_PRED_MAXLEN + 1], nsym = 0;
+    if (len < o + 2 * OQ_PRED_MAXLEN + 2 * (size_t)NS) return -1;
+    uint64_t kraft = 0;   /* in units of 2^-16 */
+    for (int l = 1; l <= OQ_PRED_MAXLEN; ++l) {
+        cntl[l] = in[o] | (in[o + 1] << 8);
+        o += 2;
+        nsym += cntl[l];
+        kraft += (uint64_t)cntl[l] << (OQ_PRED_MAXLEN - l);
+    }
+    if (nsym < 1 || nsym > C || kraft > (1u << OQ_PRED_MAXLEN)) return -1;
+    size_t sub_o = o;
+    uint64_t total = 0;
+    for (int i = 0; i < NS; ++i) total += (uint64_t)(in[sub_o + 2 * i] | (in[sub_o + 2 * i + 1] << 8));
+    o += 2 * (size_t)NS;
+    if (len < pad4s(o + 2 * (size_t)nsym)) return -1;
+    uint8_t *sgn = (uint8_t *)malloc((size_t)C);
+    uint16_t *syms = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)nsym);
+    for (int i = 0; i < nsym; ++i) {
+        syms[i] = (uint16_t)(in[o + 2 * i] | (in[o + 2 * i + 1] << 8));
+        if (syms[i] >= OQ_PRED_NSYM) { free(syms); free(sgn); return -1; }
+    }
+    o = pad4s(o + 2 * (size_t)nsym);
+    size_t bits_o = o;
+    o += 4 * (size_t)((total + 31) / 32);
+    if (len < o) { free(syms); free(sgn); return -1; }
+    /* canonical decoding: first code and first symbol index per length */
+    uint32_t firstc[OQ_PRED_MAXLEN + 2];
+    int firsti[OQ_PRED_MAXLEN + 2];
+    uint32_t c = 0;
+    int idx = 0;
+    for (int l = 1; l <= OQ_PRED_MAXLEN; ++l) {
+        firstc[l] = c;
+        firsti[l] = idx;
+        c = (c + (uint32_t)cntl[l]) << 1;
+        idx += cntl[l];
+    }
+    uint16_t *sym = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)C);
+    uint64_t bpos = 0;
+    int rc = 0;
+    for (int i = 0; i < NS && !rc; ++i) {
+        uint64_t end = bpos + (uint64_t)(in[sub_o + 2 * i] | (in[sub_o + 2 * i + 1] << 8));
+        for (int j = i * OQ_PRED_SUB; j < (i + 1) * OQ_PRED_SUB && !rc; ++j) {
+            uint32_t v = 0;
+            int l = 0, found = 0;
+            while (!found && l < OQ_PRED_MAXLEN && bpos < end) {
+                v = (v << 1) | (uint32_t)get_bits(in + bits_o, bpos++, 1);
+                ++l;
+                if (cntl[l] && v >= firstc[l] && v - firstc[l] < (uint32_t)cntl[l]) {
+                    sym[j] = syms[firsti[l] + (int)(v - firstc[l])];
+                    found = 1;
+                }
+            }
+            if (!found) rc = -1;
+            else if (sym[j] != 0) {
+                if (bpos >= end) rc = -1;
+                else sgn[j] = (uint8_t)get_bits(in + bits_o, bpos++, 1);
+            }
+        }
+        if (!rc && bpos != end) rc = -1;
+    }
+    int64_t kp[2] = {0, 0};
+    for (int j = 0; j < C && !rc; ++j) {
+        int part = j < A ? 0 : 1, a = j < A ? j : j - A;
+        uint64_t b;
+        if (sym[j] == 1) { x[2 * a + part] = bitsd((uint64_t)sgn[j] << 63); continue; }
+        if (sym[j] == 0) {
+            if (o + 8 > len) { rc = -1; break; }
+            b = get_u64(in + o);
+            o += 8;
+            kp[part] = pred_k(pred_v(b), w);
+        } else {
+            kp[part] += (int64_t)sym[j] - 2 - 8190;
+            int64_t lim = (int64_t)1 << (63 - w);
+            if (kp[part] >= lim) { rc = -1; break; }   /* beyond any finite value */
+            if (kp[part] <= 0) { rc = -1; break; }
+            b = ((uint64_t)kp[part] << w) | ((uint64_t)sgn[j] << 63);
+        }
+        x[2 * a + part] = bitsd(b);
+    }
+    if (!rc && o != len) rc = -1;
+    free(syms);
+    free(sym);
+    free(sgn);
+    return rc;
+}
+
 /* Decode one chunk; returns 0 on success, -1 on a malformed stream. */
 int oq_decode_chunk(const uint8_t *in, size_t len, int C, double *x)
 {
     if (C < 4 || (C & (C - 1)) != 0 || len < 4) return -1;
     uint32_t hdr = get_u32(in);
+    if ((hdr & 3u) == OQ_MODE_PRED) return decode_pred(in, len, C, x);
     int mode = (int)(hdr & 3u), lev = (int)((hdr >> 2) & 7u), ent = (hdr & OQ_HDR_ENT) != 0;
     int rsh = (hdr & OQ_HDR_RSH) != 0;
     if ((hdr >> 7) != 0 || lev >= OQ_NLEVELS) return -1;

@@ -79,6 +79,16 @@ def lib():
                                      ctypes.POINTER(ctypes.c_size_t),
                                      ctypes.c_uint64, u8p, ctypes.c_size_t, ctypes.c_int, u8p,
                                      ctypes.POINTER(ctypes.c_size_t)]
+        L.oq_encode_pred.restype = ctypes.c_size_t
+        L.oq_encode_pred.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+        L.oq_pred_cap.restype = ctypes.c_size_t
+        L.oq_pred_cap.argtypes = [ctypes.c_int]
+        L.oq_pred_symbols.restype = ctypes.c_int
+        L.oq_pred_symbols.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+        L.oq_pred_huff_lengths.restype = ctypes.c_int
+        L.oq_pred_huff_lengths.argtypes = [vp, ctypes.c_int, vp]
+        L.oq_pred_width.restype = ctypes.c_int
+        L.oq_pred_width.argtypes = [ctypes.c_int]
         L.oq_sim_set_codec.restype = None
         L.oq_sim_set_codec.argtypes = [vp, ctypes.c_int]
         L.oq_decode_chunk.restype = ctypes.c_int
@@ -185,6 +195,39 @@ def encode_chunk(x, level: int, flags: int = 0) -> bytes:
     if n == 0:
         raise ValueError("bad chunk size or level")
     return buf[:n].tobytes()
+
+
+def encode_pred(x, level: int) -> bytes:
+    """Solution B (Sec. 4.2): log-domain quantization, per-part prediction,
+    16,384 bins, Huffman codes; lossy levels 1..5."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    buf = np.zeros(lib().oq_pred_cap(x.size), dtype=np.uint8)
+    n = lib().oq_encode_pred(_dp(x), x.size, level, _u8(buf))
+    if n == 0:
+        raise ValueError("bad chunk size or level")
+    return buf[:n].tobytes()
+
+
+def pred_symbols(x, level: int):
+    """Solution B's symbols in coding order (re parts, then im parts) and
+    the number of escapes."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    sym = np.zeros(x.size, dtype=np.uint16)
+    nesc = lib().oq_pred_symbols(_dp(x), x.size, level, sym.ctypes.data)
+    if nesc < 0:
+        raise ValueError("bad level")
+    return sym, nesc
+
+
+def pred_huff_lengths(counts) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(counts, dtype=np.uint32))
+    out = np.zeros(c.size, dtype=np.uint8)
+    lib().oq_pred_huff_lengths(c.ctypes.data, c.size, _u8(out))
+    return out
+
+
+def pred_width(level: int) -> int:
+    return lib().oq_pred_width(level)
 
 
 def huff_lengths(counts) -> np.ndarray:
