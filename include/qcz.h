@@ -433,11 +433,23 @@ size_t qcz_chunk_cap(uint32_t C);
  * stores values in Solution D's order (Sec. 4.2); other bits: QCZ_E_INVAL. */
 #define QCZ_CODEC_ENTROPY 1u
 #define QCZ_CODEC_RESHUFFLE 2u
+/* Solution B (Sec. 4.2), alone (no other codec bit), lossy levels 1..5, C >= 256: each value quantized
+ * in the log domain (the bit pattern of |x| read as an integer; bin width 2^(52-t), t = 16, 13, 9, 6, 3
+ * for 1e-5 .. 1e-1), predicted from the previous nonzero value of its part (real parts, then imaginary
+ * parts), 16,384 symbols (escape, zero, codes -8190 .. 8191) Huffman coded with the sign bit beside each
+ * code; header mode 3.  Slots hold qcz_chunk_cap_codec(C, QCZ_CODEC_PREDICT) bytes; a chunk whose
+ * stream would not fit its slot gets size 0. */
+#define QCZ_CODEC_PREDICT 4u
+/* Bytes a slot needs for the streams of a codec (0 for a bad C or flags). */
+size_t qcz_chunk_cap_codec(uint32_t C, uint32_t codec_flags);
 qcz_status qcz_encode_chunks(const void *dev_in, uint32_t C, uint64_t n_chunks, int level, uint32_t codec_flags,
                              void *dev_slots, size_t slot_bytes, uint32_t *dev_sizes, void *hip_stream);
 
 /* Decode n_chunks streams from device slots into C doubles each (device);
- * streams with and without the entropy stage, in either value order. */
+ * streams with and without the entropy stage, in either value order, and
+ * Solution B streams (C >= 256).  Streams must be well formed (as the
+ * encoders write them): a malformed Solution B stream decodes to unspecified
+ * values, without access outside its slot. */
 qcz_status qcz_decode_chunks(const void *dev_slots, size_t slot_bytes, const uint32_t *dev_sizes, uint32_t C,
                              uint64_t n_chunks, void *dev_out, void *hip_stream);
 

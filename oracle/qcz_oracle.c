@@ -741,10 +741,10 @@ static const int oq_pred_t[OQ_NLEVELS] = {0, 16, 13, 9, 6, 3};
 
 int oq_pred_width(int level) { return (level >= 1 && level < OQ_NLEVELS) ? 52 - oq_pred_t[level] : -1; }
 
-static int64_t pred_v(uint64_t b) { return (int64_t)(b & 0x7FFFFFFFFFFFFFFFull); }
+static uint64_t pred_v(uint64_t b) { return b & 0x7FFFFFFFFFFFFFFFull; }
 
-/* floor((v + W/2) / W) */
-static int64_t pred_k(int64_t v, int w) { return (v + ((int64_t)1 << (w - 1))) >> w; }
+/* floor((v + W/2) / W), v < 2^63 (no overflow in 64 unsigned bits) */
+static int64_t pred_k(uint64_t v, int w) { return (int64_t)((v + ((uint64_t)1 << (w - 1))) >> w); }
 
 /* a value quantizes when it is a nonzero normal double whose rebuilt value
  * k W is finite */

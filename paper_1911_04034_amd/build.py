@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqcz.so")
 SOURCES = [os.path.join(CSRC, "qcz_kernels.hip"), os.path.join(CSRC, "qcz_select.hip"),
-           os.path.join(CSRC, "qcz_runtime.cpp")]
+           os.path.join(CSRC, "qcz_pred.hip"), os.path.join(CSRC, "qcz_runtime.cpp")]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

@@ -220,6 +220,15 @@ hipError_t mlp_static_workspace(void **out, size_t *bytes);
 hipError_t launch_mlp_train(float *params, float *m, float *v, const float *X, const uint8_t *labels, uint64_t N,
                             float lr, uint32_t step, float *grad_out, float *loss_out, void *work, hipStream_t st);
 hipError_t launch_fill_table(const DevPtrs &P, uint64_t entry0, uint64_t entry_rest, hipStream_t st);
+
+// Solution B codec (qcz_pred.hip): C = 256 .. 2048, lossy levels; encoded
+// sizes above the slot are reported as 0; the decoder writes only the
+// chunks whose header has mode 3 (the job kernel's slot decoder skips them)
+hipError_t launch_pred_encode(const double *in, int C, int level, uint64_t nchunks, uint32_t *slots,
+                              uint64_t slot_words, uint32_t *sizes, hipStream_t st);
+hipError_t launch_pred_decode(const uint32_t *slots, uint64_t slot_words, const uint32_t *sizes, int C,
+                              uint64_t nchunks, double *out, hipStream_t st);
+size_t pred_cap_bytes(int C);
 hipError_t launch_compact(const DevPtrs &P, uint32_t *dst_arena, uint64_t *scratch, uint64_t *block_sums,
                           uint64_t nblocks_scan, hipStream_t st);
 

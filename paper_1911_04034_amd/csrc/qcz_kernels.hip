@@ -1562,7 +1562,9 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
         }
         if (lt == 0) sh_src_ok[s] = ok_src ? 1 : 0;
         lds_barrier();
-        const bool use0 = act0 && sh_src_ok[0] != 0, use1 = act1 && sh_src_ok[1] != 0;
+        // (slot streams of Solution B, header mode 3, are decoded by their own kernel)
+        const bool use0 = act0 && sh_src_ok[0] != 0 && (SRC != SRC_SLOTS || (buf[0][0] & 3u) != 3u);
+        const bool use1 = act1 && sh_src_ok[1] != 0 && (SRC != SRC_SLOTS || (buf[1][0] & 3u) != 3u);
         const bool use = s ? use1 : use0;
 
         // 2. decode

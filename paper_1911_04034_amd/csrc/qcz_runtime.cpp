@@ -1812,6 +1812,14 @@ qcz_status qcz_encode_chunks(const void *dev_in, uint32_t C, uint64_t n_chunks, 
 {
     if (!dev_in || !dev_slots || !dev_sizes) return QCZ_E_INVAL;
     if (C < (uint32_t)kCMin || C > (uint32_t)kCMax || (C & (C - 1)) || level < 0 || level >= kLevels) return QCZ_E_INVAL;
+    if (codec_flags == QCZ_CODEC_PREDICT) {
+        if (C < 256 || level < 1 || slot_bytes < pred_cap_bytes((int)C) || (slot_bytes & 3)) return QCZ_E_INVAL;
+        if (n_chunks == 0) return QCZ_OK;
+        return launch_pred_encode((const double *)dev_in, (int)C, level, n_chunks, (uint32_t *)dev_slots, slot_bytes / 4,
+                                  dev_sizes, (hipStream_t)hip_stream) == hipSuccess
+                   ? QCZ_OK
+                   : QCZ_E_DEVICE;
+    }
     if ((codec_flags & ~(QCZ_CODEC_ENTROPY | QCZ_CODEC_RESHUFFLE)) ||
         ((codec_flags & QCZ_CODEC_ENTROPY) && C != (uint32_t)kCMax))
         return QCZ_E_INVAL;
@@ -1867,7 +1875,18 @@ qcz_status qcz_decode_chunks(const void *dev_slots, size_t slot_bytes, const uin
     io.raw_out = (double *)dev_out;
     const int grid = (int)std::min<uint64_t>(d.njobs, 4096);
     if (launch_decode_slots(d, P, io, grid, (hipStream_t)hip_stream) != hipSuccess) return QCZ_E_DEVICE;
+    if (C >= 256 && launch_pred_decode((const uint32_t *)dev_slots, slot_bytes / 4, dev_sizes, (int)C, n_chunks,
+                                       (double *)dev_out, (hipStream_t)hip_stream) != hipSuccess)
+        return QCZ_E_DEVICE;
     return QCZ_OK;
+}
+
+size_t qcz_chunk_cap_codec(uint32_t C, uint32_t codec_flags)
+{
+    if (C < (uint32_t)kCMin || C > (uint32_t)kCMax || (C & (C - 1))) return 0;
+    if (codec_flags == QCZ_CODEC_PREDICT) return C >= 256 ? pred_cap_bytes((int)C) : 0;
+    if (codec_flags & ~(QCZ_CODEC_ENTROPY | QCZ_CODEC_RESHUFFLE)) return 0;
+    return chunk_cap_bytes((int)C);
 }
 
 // ---------------------------------------------------------------------------

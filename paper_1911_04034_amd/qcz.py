@@ -27,6 +27,7 @@ FLAG_ENTROPY = 128
 FLAG_RESHUFFLE = 256
 CODEC_ENTROPY = 1
 CODEC_RESHUFFLE = 2
+CODEC_PREDICT = 4
 STATUS = {0: "QCZ_OK", -1: "QCZ_E_INVAL", -2: "QCZ_E_NOMEM", -3: "QCZ_E_DEVICE", -4: "QCZ_E_FORMAT",
           -5: "QCZ_E_STATE"}
 
@@ -70,6 +71,7 @@ EXPORTED = [
     "qcz_pool_bytes_min", "qcz_create", "qcz_apply_gates", "qcz_read_amplitudes", "qcz_decode_chunks_to",
     "qcz_moments", "qcz_sample", "qcz_footprint", "qcz_export_chunk", "qcz_import_chunk", "qcz_set_block_levels",
     "qcz_chunk_sizes", "qcz_num_chunks", "qcz_chunk_doubles", "qcz_last_error", "qcz_destroy", "qcz_chunk_cap",
+    "qcz_chunk_cap_codec",
     "qcz_encode_chunks", "qcz_decode_chunks", "qcz_get_stats", "qcz_reset_stats", "qcz_set_launch",
     "qcz_block_stats", "qcz_block_level_sizes", "qcz_label_levels", "qcz_project_levels", "qcz_mlp_forward",
     "qcz_mlp_workspace_bytes", "qcz_mlp_train_step", "qcz_mlp_train_step_noalloc", "qcz_select_levels", "qcz_set_selector", "qcz_copy_state",
@@ -127,6 +129,8 @@ def load():
     L.qcz_destroy.argtypes = [vp]
     L.qcz_chunk_cap.restype = sz
     L.qcz_chunk_cap.argtypes = [u32]
+    L.qcz_chunk_cap_codec.restype = sz
+    L.qcz_chunk_cap_codec.argtypes = [u32, u32]
     L.qcz_encode_chunks.restype = i32
     L.qcz_encode_chunks.argtypes = [vp, u32, u64, i32, u32, vp, sz, vp, vp]
     L.qcz_decode_chunks.restype = i32
@@ -415,11 +419,16 @@ class State:
 # -- codec entry points -----------------------------------------------------
 def encode_chunks(x, level: int, stream=None, codec_flags: int = 0):
     """x: cuda float64 tensor [n, C].  Returns (slots uint8 [n, slot], sizes).
-    codec_flags: CODEC_ENTROPY lets chunks take the entropy-coded body."""
+    codec_flags: CODEC_ENTROPY lets chunks take the entropy-coded body,
+    CODEC_RESHUFFLE stores Solution D's order, CODEC_PREDICT (alone) encodes
+    with Solution B."""
     torch = _torch()
     L = load()
     n, C = x.shape
-    slot = (chunk_cap(C) + 3) & ~3
+    cap = L.qcz_chunk_cap_codec(C, codec_flags)
+    if cap == 0:
+        raise QczError(-1, "qcz_chunk_cap_codec")
+    slot = (cap + 3) & ~3
     slots = torch.zeros((n, slot), dtype=torch.uint8, device=x.device)
     sizes = torch.zeros(n, dtype=torch.int32, device=x.device)
     st = stream if stream is not None else torch.cuda.current_stream()
