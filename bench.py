@@ -245,6 +245,9 @@ def large_config(args, torch, cc, qcz):
                     ", entropy" if args.entropy else ""),
                 "avg_launch_us": round(avg_ms * 1e3, 3), "algorithmic_bytes_per_launch": round(per_launch, 1),
                 "launches": timed, "range_launches": stats["range_launches"], "sweep_gates": stats["sweep_gates"]}
+    codecs = None
+    if not args.gates:
+        codecs = codec_comparison(torch, qcz, st, max(1, level))
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -272,6 +275,7 @@ def large_config(args, torch, cc, qcz):
         "compactions": fp["compactions"] - c0 if t_all is not None else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "codec_comparison": codecs,
     }
     if args.workload == "qaoa34" and args.selector:
         line["selector"] = selector_run(args, torch, cc, qcz, n, bl, gates, pool, trace, st,
@@ -281,6 +285,56 @@ def large_config(args, torch, cc, qcz):
         torch.cuda.empty_cache()
         line["fidelity"]["same_generator"] = qaoa_fidelity(qcz, cc, args.fidelity_qubits, bl, level, flags)
     print(json.dumps(line), flush=True)
+
+
+def codec_comparison(torch, qcz, st, level, nchunks=65536):
+    """The paper's comparison of its lossy solutions (Sec. 4.2) on the final
+    state: a contiguous sample of chunks from the middle of the state, decoded
+    once, then encoded at the run's bound with Solution C (the state's codec),
+    Solution C with the entropy stage, Solution D (re/im separated, with and
+    without the entropy stage) and Solution B (log-domain prediction, 16,384
+    bins, Huffman).  Compression ratio = raw bytes / stream bytes (4-byte
+    padded); rates in GB/s of raw input through the encoder and the decoder
+    (device timing of one call each, after one warm call)."""
+    n = min(nchunks, st.nchunks)
+    first = (st.nchunks - n) // 2
+    C = st.C
+    raw = torch.empty(n * C, dtype=torch.float64, device="cuda")
+    st.decode_to(first, n, raw)
+    raw = raw.view(n, C)
+    out = {"sample": "%d chunks of %d amplitudes from the middle of the final state, bound %g" % (
+        n, C // 2, [0.0, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1][level])}
+    variants = {"C": 0, "C+entropy": qcz.CODEC_ENTROPY, "D": qcz.CODEC_RESHUFFLE,
+                "D+entropy": qcz.CODEC_RESHUFFLE | qcz.CODEC_ENTROPY, "B": qcz.CODEC_PREDICT}
+    for name, flags in variants.items():
+        try:
+            qcz.encode_chunks(raw, level, codec_flags=flags)
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record()
+            slots, sizes = qcz.encode_chunks(raw, level, codec_flags=flags)
+            t1.record()
+            torch.cuda.synchronize()
+            enc_ms = t0.elapsed_time(t1)
+            qcz.decode_chunks(slots, sizes, C)
+            t0.record()
+            dec = qcz.decode_chunks(slots, sizes, C)
+            t1.record()
+            torch.cuda.synchronize()
+            dec_ms = t0.elapsed_time(t1)
+            stream = int(((sizes.to(torch.int64) + 3) // 4 * 4).sum().item())
+            ok = bool((sizes > 0).all().item())
+            err = torch.abs(dec - raw) <= [0.0, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1][level] * torch.abs(raw)
+            out[name] = {"compression_ratio": round(raw.numel() * 8 / stream, 3),
+                         "encode_gbs": round(raw.numel() * 8 / (enc_ms * 1e-3) / 1e9, 1),
+                         "decode_gbs": round(raw.numel() * 8 / (dec_ms * 1e-3) / 1e9, 1),
+                         "bound_held": bool(err.all().item()) and ok}
+            del slots, sizes, dec
+        except Exception as e:   # (a codec that rejects the chunk size)
+            out[name] = {"error": str(e)}
+    del raw
+    torch.cuda.empty_cache()
+    log("codec comparison: %s" % json.dumps(out))
+    return out
 
 
 def qaoa_fidelity(qcz, cc, n, bl, level, flags):
