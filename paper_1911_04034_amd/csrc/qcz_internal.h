@@ -21,7 +21,7 @@ constexpr int kMaxGrid = 8192;      // workgroups per gate launch
 constexpr uint32_t kMaxChunkBytes = 4 + 4 * (kCMax / 16) + 8 * kCMax;   // 16900
 
 enum GateKind { K_U1 = 0, K_DIAG1 = 1, K_DIAG2 = 2, K_X = 3, K_MCZ = 4 };
-enum JobType { J_SINGLE = 0, J_PAIR = 1, J_PERMUTE = 2 };
+enum JobType { J_SINGLE = 0, J_PAIR = 1, J_PERMUTE = 2, J_GROUP = 3 };
 enum StopReason { STOP_NONE = 0, STOP_BUDGET = 1, STOP_ARENA = 2, STOP_CORRUPT = 3 };
 enum ChunkMode { M_PACK = 0, M_CONST2 = 1, M_SPARSE = 2 };
 
@@ -49,6 +49,7 @@ struct GateDesc {
                                     // control bits its plain enumeration would have held fixed)
     int32_t reshuffle;              // the encoder stores PACK / SPARSE values re parts first (header bit 6)
     int32_t pad_;
+    uint64_t pair_bit2;             // GROUP: the second chunk-index bit of the four-chunk groups
 };
 
 // the jobs one launch of a gate runs
@@ -190,6 +191,10 @@ hipError_t launch_gate_run(const GateDesc &gd, const DevPtrs &P, const GateDesc 
                            hipStream_t st, hipEvent_t t0, hipEvent_t t1);
 hipError_t launch_gate_list(const GateDesc &gd, const DevPtrs &P, const CachePtrs &cp, int list, int grid,
                             hipStream_t st);
+// a run of nrun chunk-pair gates on the two chunk-index bits of gd (J_GROUP:
+// pair_bit, pair_bit2) in one pass over groups of four chunks (C = 2048)
+hipError_t launch_group_run(const GateDesc &gd, const DevPtrs &P, const GateDesc *run, int nrun, int grid,
+                            hipStream_t st, hipEvent_t t0, hipEvent_t t1);
 hipError_t launch_permute(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);
 hipError_t launch_rollback(const GateDesc &gd, const DevPtrs &P, int grid, hipStream_t st);
 hipError_t launch_encode_raw(const GateDesc &gd, const DevPtrs &P, const IOPtrs &io, int grid, hipStream_t st);

@@ -1213,6 +1213,10 @@ __device__ __forceinline__ uint64_t deposit(const GateDesc &gd, uint64_t k)
 // chunk id of enumerated position `item`
 __device__ __forceinline__ uint64_t item_chunk(const GateDesc &gd, uint64_t item)
 {
+    if (gd.job_type == J_GROUP) {
+        uint64_t c = deposit(gd, item >> 2);
+        return c | ((item & 1ull) ? gd.pair_bit : 0ull) | ((item & 2ull) ? gd.pair_bit2 : 0ull);
+    }
     if (gd.job_type == J_PAIR) {
         uint64_t c = deposit(gd, item >> 1);
         return (item & 1ull) ? (c | gd.pair_bit) : c;
@@ -2036,6 +2040,356 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     }
 }
 
+// ---------------------------------------------------------------------------
+// chunk-group runs
+// ---------------------------------------------------------------------------
+// A run of chunk-pair gates (Sec. 3.3's pair update) whose targets are two
+// chunk-index bits B1 = gd.pair_bit and B2 = gd.pair_bit2: a job is the group
+// of four chunks base | {0, B1, B2, B1|B2}.  The two slots of the workgroup
+// fetch and decode them in two rounds into four LDS buffers; each gate of the
+// run updates the pairs it joins across the buffers, followed by the
+// truncation its re-encoding would apply to the chunks it touched (none for a
+// chunk holding a subnormal value); the two slots encode the four chunks in
+// two rounds.  A chunk that no gate of the run touches keeps its stream (or is
+// copied as it is in a sweep).  Bytes equal the gate-by-gate method's.
+// C = 2048 only (V = 16, two wavefronts per chunk); not with the entropy stage.
+__device__ __forceinline__ bool group_gate_touches(const GateDesc &rg, uint64_t c, int cb)
+{
+    return ((c << cb) & rg.cm & ~(((uint64_t)1 << cb) - 1)) == (rg.cm & ~(((uint64_t)1 << cb) - 1));
+}
+
+template <int V>
+__global__ __launch_bounds__(256, 2) void group_kernel(GateDesc gd, DevPtrs P, IOPtrs io)
+{
+    constexpr int WPG = 2;
+    constexpr int G = 64 * WPG;
+    constexpr int WGS = 2 * G;
+    __shared__ __align__(16) uint32_t buf[4][kBufWords];
+    __shared__ uint32_t sh[256];
+    __shared__ uint64_t sh_off[2];
+    __shared__ int sh_ok[2];
+    __shared__ int sh_src_ok[4];
+    __shared__ uint64_t sh_acc[8];
+    __shared__ double sh_rm[kMaxRun][8];
+    __shared__ uint32_t sh_sub[2][4];
+
+    DevState *ds = P.ds;
+    if (ds->stop) return;
+    const int tid = threadIdx.x, s = tid / G, lt = tid % G;
+    for (int i = tid; i < 8 * io.nrun; i += WGS) sh_rm[i >> 3][i & 7] = io.run[i >> 3].m[i & 7];
+    const int C = P.C, cb = P.cb, ca = C / 2;
+    const int first = lt * V;
+    uint32_t *slA = sh, *slB = sh + 16, *slC = sh + 32, *slE = sh + 48, *slF = sh + 176, *slS = sh + 192;
+    const int glevel = ds->level;
+    const uint64_t ds_nstripes = ds->nstripes, ds_base = ds->base, ds_ssize = ds->stripe_size;
+    const uint32_t mh = sig_mask_hi(sig_bits(glevel));
+    if (lt == 0)
+        for (int k = 0; k < 4; ++k) sh_acc[4 * s + k] = 0;
+    int ntr = 0;   // truncation steps so far (alternating flag sets)
+    lds_barrier();   // (the run's matrices)
+
+    for (uint64_t job = job_begin(gd) + blockIdx.x; job < job_stop(gd); job += gridDim.x) {
+        // the group's chunks and which of them some gate of the run touches
+        uint64_t cg[4];
+        bool tg[4];
+        const uint64_t base = deposit(gd, job);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            cg[g] = base | ((g & 1) ? gd.pair_bit : 0ull) | ((g & 2) ? gd.pair_bit2 : 0ull);
+            bool t = false;
+            for (int r = 0; r < io.nrun; ++r) t = t || group_gate_touches(io.run[r], cg[g], cb);
+            tg[g] = t;
+        }
+        uint64_t old_entry[2] = {0, 0};
+        bool ok_src_r[2] = {true, true};
+
+        // 1. two rounds of fetch and decode
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int gi = 2 * r + s;
+            uint32_t *b = buf[gi];
+            double *vals = reinterpret_cast<double *>(b);
+            const uint64_t c = cg[gi];
+            const bool act = tg[gi];
+            const uint64_t e = P.table[c];
+            old_entry[r] = e;
+            const uint32_t size = (uint32_t)(e & 0xFFFFull);
+            const uint64_t off = e >> 16;
+            const uint32_t words = (size + 3u) >> 2;
+            const bool ok_src = entry_ok(e, P.arena_words);
+            ok_src_r[r] = ok_src;
+            if (act && ok_src) {
+                if ((off & 3ull) == 0) stage_units<G>(b, P.arena + off, words, lt);
+                else stage_words<G>(b, P.arena + off, words, lt);
+            }
+            if ((act || gd.sweep) && !ok_src && lt == 0) atomicExch(&ds->corrupt, 1);
+            if (lt == 0) sh_src_ok[gi] = ok_src ? 1 : 0;
+            lds_barrier();
+            const bool use0 = tg[2 * r] && sh_src_ok[2 * r] != 0, use1 = tg[2 * r + 1] && sh_src_ok[2 * r + 1] != 0;
+            const bool use = s ? use1 : use0;
+            const uint32_t hdr0 = use0 ? buf[2 * r][0] : (uint32_t)M_CONST2;
+            const uint32_t hdr1 = use1 ? buf[2 * r + 1][0] : (uint32_t)M_CONST2;
+            const bool any_sparse = (hdr0 & 3u) == M_SPARSE || (hdr1 & 3u) == M_SPARSE;
+            uint32_t th[V], tl[V];
+            decode_group<V, WPG, false>(b, s ? hdr1 : hdr0, use, any_sparse, C, lt, slA, slB, slC, th, tl);
+            lds_barrier();
+            double x[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) x[k] = u2d(((uint64_t)th[k] << 32) | tl[k]);
+            const bool rsh0 = use0 && (hdr0 & kHdrRsh) != 0, rsh1 = use1 && (hdr1 & kHdrRsh) != 0;
+            if (rsh0 || rsh1) {
+                const bool mine = s ? rsh1 : rsh0;
+#pragma unroll
+                for (int k = 0; k < V; ++k) vals[vpos(mine ? rsh_pos(first + k, C) : first + k)] = x[k];
+                lds_barrier();
+#pragma unroll
+                for (int k = 0; k < V; ++k) x[k] = vals[vpos(first + k)];
+            }
+#pragma unroll
+            for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
+            lds_barrier();
+        }
+
+        // 2. the run: each gate on the pairs it joins, then its truncation
+        for (int r = 0; r < io.nrun; ++r) {
+            const GateDesc &rg = io.run[r];
+            const int bitsel = rg.pair_bit == gd.pair_bit ? 1 : 2;   // group index bit of the target
+            const uint32_t cm_lo = (uint32_t)(rg.cm & (uint64_t)(ca - 1));
+            // pair q (0, 1): group indices p0 < p1 differing in bitsel
+            bool pact[2];
+            int pg0[2], pg1[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int other = bitsel == 1 ? 2 : 1;
+                pg0[q] = q ? other : 0;
+                pg1[q] = pg0[q] | bitsel;
+                pact[q] = tg[pg0[q]] && tg[pg1[q]] && sh_src_ok[pg0[q]] && sh_src_ok[pg1[q]] &&
+                          group_gate_touches(rg, cg[pg0[q]], cb);
+            }
+            {
+                const int q = tid >> 7;
+                if (pact[q]) {
+                    double *v0 = reinterpret_cast<double *>(buf[pg0[q]]);
+                    double *v1 = reinterpret_cast<double *>(buf[pg1[q]]);
+                    const double u0r = sh_rm[r][0], u0i = sh_rm[r][1], u1r = sh_rm[r][2], u1i = sh_rm[r][3];
+                    const double u2r = sh_rm[r][4], u2i = sh_rm[r][5], u3r = sh_rm[r][6], u3i = sh_rm[r][7];
+                    for (int k = tid & 127; k < ca; k += 128) {
+                        if (((uint32_t)k & cm_lo) != cm_lo) continue;
+                        const int p = vpos(2 * k);
+                        const double ar = v0[p], ai = v0[p + 1], br = v1[p], bi = v1[p + 1];
+                        if (rg.kind == K_X) {
+                            v0[p] = br; v0[p + 1] = bi; v1[p] = ar; v1[p + 1] = ai;
+                        } else {
+                            double yr, yi, zr, zi;
+                            lin2(u0r, u0i, u1r, u1i, ar, ai, br, bi, yr, yi);
+                            lin2(u2r, u2i, u3r, u3i, ar, ai, br, bi, zr, zi);
+                            v0[p] = yr; v0[p + 1] = yi; v1[p] = zr; v1[p + 1] = zi;
+                        }
+                    }
+                }
+            }
+            lds_barrier();
+            if (glevel > 0 && (pact[0] || pact[1])) {
+                // per touched chunk: a subnormal value anywhere keeps it untruncated
+                uint32_t *flags = sh_sub[ntr & 1];
+                if (tid < 4) flags[tid] = 0u;
+                lds_barrier();
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const bool touched = (pact[0] && (g == pg0[0] || g == pg1[0])) ||
+                                         (pact[1] && (g == pg0[1] || g == pg1[1]));
+                    if (!touched) continue;
+                    const double *v = reinterpret_cast<const double *>(buf[g]);
+                    bool sub = false;
+                    for (int i = tid; i < C; i += WGS) {
+                        const uint64_t u = d2u(v[vpos(i)]);
+                        sub = sub || subnormal((uint32_t)(u >> 32), (uint32_t)u);
+                    }
+                    if (__any(sub) && (tid & 63) == 0) atomicOr(&flags[g], 1u);
+                }
+                lds_barrier();
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const bool touched = (pact[0] && (g == pg0[0] || g == pg1[0])) ||
+                                         (pact[1] && (g == pg0[1] || g == pg1[1]));
+                    if (!touched || flags[g]) continue;
+                    double *v = reinterpret_cast<double *>(buf[g]);
+                    for (int i = tid; i < C; i += WGS) {
+                        const int p = vpos(i);
+                        v[p] = u2d((uint64_t)((uint32_t)(d2u(v[p]) >> 32) & mh) << 32);
+                    }
+                }
+                ++ntr;
+                lds_barrier();
+            }
+        }
+
+        // 3. two rounds of encode, claim and copy-out
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int gi = 2 * r + s;
+            uint32_t *b = buf[gi];
+            const double *vals = reinterpret_cast<const double *>(b);
+            const uint64_t c = cg[gi];
+            const uint64_t item = 4 * job + (uint64_t)gi;
+            const bool use = tg[gi] && sh_src_ok[gi] != 0;
+            const bool carry = gd.sweep && !tg[gi] && ok_src_r[r];
+            uint32_t xh[V], xl[V];
+            bool sub = false;
+            const bool rsh = gd.reshuffle != 0;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const uint64_t x = d2u(vals[vpos(rsh ? rsh_pos(first + k, C) : first + k)]);
+                xh[k] = (uint32_t)(x >> 32);
+                xl[k] = (uint32_t)x;
+                sub = sub || subnormal(xh[k], xl[k]);
+            }
+            const uint32_t xprev_hi =
+                lt ? (uint32_t)(d2u(vals[vpos(rsh ? rsh_pos(first - 1, C) : first - 1)]) >> 32) : 0u;
+            const uint64_t x0 = d2u(vals[0]), x1 = d2u(vals[1]);
+            const bool wsub = __any(use && sub);
+            if ((tid & 63) == 0) slS[tid >> 6] = wsub ? 1u : 0u;
+            lds_barrier();
+            uint32_t gs = 0;
+#pragma unroll
+            for (int i = 0; i < WPG; ++i) gs |= slS[s * WPG + i];
+            EncPlan<V> e;
+            encode_plan<V, WPG, false>(xh, xl, xprev_hi, x0, x1, glevel, gs != 0, C, lt, slE, slF, e, false, nullptr,
+                                       nullptr, nullptr, rsh);
+            const uint32_t new_size = use ? e.size : (uint32_t)(old_entry[r] & 0xFFFFull);
+            uint64_t my_off = 0;
+            const int stripe = (int)(blockIdx.x % (uint32_t)ds_nstripes);
+            if (lt == 0 && (use || carry))
+                my_off = atomicAdd((unsigned long long *)&ds->stripe[stripe][0], (unsigned long long)alloc_bytes(new_size));
+            const uint32_t words = (e.size + 3u) >> 2;
+            if (use) {
+                uint4 *b4 = reinterpret_cast<uint4 *>(b);
+                for (uint32_t w = lt; w < (words + 3u) >> 2; w += G) b4[w] = make_uint4(0u, 0u, 0u, 0u);
+            }
+            lds_barrier();
+            if (use) encode_emit<V>(b, e, C, lt);
+            if (lt == 0) {
+                int ok = 0;
+                if (use || carry) {
+                    ok = (my_off + alloc_bytes(new_size) <= ds_ssize) ? 1 : 0;
+                    my_off += ds_base + (uint64_t)stripe * ds_ssize;
+                    if (!ok) atomicExch(&ds->fail, 1);
+                }
+                sh_off[s] = my_off;
+                sh_ok[s] = ok;
+            }
+            lds_barrier();
+            const int ok = sh_ok[s];
+            if (ok && carry) {
+                const uint64_t offw = sh_off[s] >> 2, srcw = old_entry[r] >> 16;
+                const uint32_t cw = (new_size + 3u) >> 2, units = (cw + 3u) >> 2;
+                for (uint32_t w = lt; w < 4u * units; w += G) P.out[offw + w] = w < cw ? P.arena[srcw + w] : 0u;
+            } else if (ok) {
+                const uint64_t offw = sh_off[s] >> 2;
+                u32x4 *dst4 = reinterpret_cast<u32x4 *>(P.out + offw);
+                const u32x4 *b4 = reinterpret_cast<const u32x4 *>(b);
+                for (uint32_t w = lt; w < (words + 3u) >> 2; w += G) dst4[w] = b4[w];
+            }
+            if (lt == 0) {
+                P.undo[item] = old_entry[r];
+                const uint64_t old_pad = ((old_entry[r] & 0xFFFFull) + 3ull) & ~3ull;
+                const uint64_t new_pad = ((uint64_t)e.size + 3ull) & ~3ull;
+                if (use) sh_acc[4 * s] += new_pad - old_pad;   // (also where the claim failed)
+                if (ok && carry) {
+                    P.table[c] = ((sh_off[s] >> 2) << 16) | (uint64_t)new_size;
+                } else if (ok) {
+                    P.table[c] = ((sh_off[s] >> 2) << 16) | (uint64_t)e.size;
+                    sh_acc[4 * s + 1] += 1;
+                    sh_acc[4 * s + 2] += old_pad;
+                    sh_acc[4 * s + 3] += new_pad;
+                }
+            }
+            lds_barrier();
+        }
+    }
+
+    // per-workgroup totals; the last workgroup closes the run
+    if (tid == 0) {
+        WgPart wp;
+        wp.delta = sh_acc[0] + sh_acc[4];
+        wp.reenc = sh_acc[1] + sh_acc[5];
+        wp.rd = sh_acc[2] + sh_acc[6];
+        wp.wr = sh_acc[3] + sh_acc[7];
+        wp.wd = 0.0;
+        wp.lost = 0.0;
+        wp.hits = 0;
+        P.wgp[blockIdx.x] = wp;
+        __threadfence();
+        const uint32_t prev = atomicAdd(&ds->done, 1u);
+        sh_ok[0] = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    lds_barrier();
+    if (sh_ok[0]) {
+        __threadfence();
+        uint64_t d = 0, rr = 0, rd = 0, wr = 0, used = 0;
+        for (uint32_t g = (uint32_t)tid; g < gridDim.x; g += WGS) {
+            const WgPart wp = P.wgp[g];
+            d += wp.delta;
+            rr += wp.reenc;
+            rd += wp.rd;
+            wr += wp.wr;
+        }
+        if (tid < kStripes) used = atomicAdd((unsigned long long *)&ds->stripe[tid][0], 0ull);
+        for (int off = 32; off >= 1; off >>= 1) {
+            d += __shfl_down(d, off, 64);
+            rr += __shfl_down(rr, off, 64);
+            rd += __shfl_down(rd, off, 64);
+            wr += __shfl_down(wr, off, 64);
+            used += __shfl_down(used, off, 64);
+        }
+        uint64_t *red = reinterpret_cast<uint64_t *>(buf[0]);
+        if ((tid & 63) == 0) {
+            red[5 * (tid >> 6)] = d;
+            red[5 * (tid >> 6) + 1] = rr;
+            red[5 * (tid >> 6) + 2] = rd;
+            red[5 * (tid >> 6) + 3] = wr;
+            red[5 * (tid >> 6) + 4] = used;
+        }
+    }
+    lds_barrier();
+    if (tid == 0 && sh_ok[0]) {
+        const uint64_t *red = reinterpret_cast<const uint64_t *>(buf[0]);
+        uint64_t d = 0, rr = 0, rd = 0, wr = 0, used = 0;
+        for (int w = 0; w < WGS / 64; ++w) {
+            d += red[5 * w];
+            rr += red[5 * w + 1];
+            rd += red[5 * w + 2];
+            wr += red[5 * w + 3];
+            used += red[5 * w + 4];
+        }
+        const uint64_t live = ds->live + d;
+        ds->live = live;
+        GateLog lg;
+        lg.live = live;
+        lg.bump = ds->base + used;
+        lg.reenc = rr;
+        lg.rd = rd;
+        lg.wr = wr;
+        lg.wd = 0.0;
+        lg.lost = 0.0;
+        lg.hits = 0;
+        ds->log[gd.seq] = lg;
+        const int fail = atomicExch(&ds->fail, 0);
+        const int corrupt = atomicExch(&ds->corrupt, 0);
+        int reason = STOP_NONE;
+        if (corrupt) reason = STOP_CORRUPT;
+        else if (ds->budget && live > ds->budget) reason = STOP_BUDGET;
+        else if (fail) reason = STOP_ARENA;
+        if (reason != STOP_NONE) {
+            ds->stop_reason = reason;
+            ds->stop_seq = gd.seq;
+            __threadfence();
+            ds->stop = 1;
+        }
+        atomicExch(&ds->done, 0u);
+    }
+}
+
 // X on chunk-index bits with no control inside the chunk: exchange table
 // entries (the streams themselves are unchanged and exact).
 __global__ __launch_bounds__(kWG) void permute_kernel(GateDesc gd, DevPtrs P)
@@ -2513,6 +2867,21 @@ hipError_t launch_gate_run(const GateDesc &gd, const DevPtrs &P, const GateDesc 
     case 16: launch_run_v<16>(gd, P, io, grid, st, t0, t1); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_group_run(const GateDesc &gd, const DevPtrs &P, const GateDesc *run, int nrun, int grid,
+                            hipStream_t st, hipEvent_t t0, hipEvent_t t1)
+{
+    if (nrun < 1 || nrun > kMaxRun || grid < 1 || P.C != kCMax || gd.job_type != J_GROUP || gd.entropy)
+        return hipErrorInvalidValue;
+    IOPtrs io = {};
+    io.run = run;
+    io.nrun = nrun;
+    if (t0)
+        hipExtLaunchKernelGGL(group_kernel<16>, dim3(grid), dim3(256), 0, st, t0, t1, 0, gd, P, io);
+    else
+        hipLaunchKernelGGL(group_kernel<16>, dim3(grid), dim3(256), 0, st, gd, P, io);
     return hipGetLastError();
 }
 

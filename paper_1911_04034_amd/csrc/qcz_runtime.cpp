@@ -149,6 +149,7 @@ struct qcz_state {
     // gate-layer fusion (QCZ_FLAG_FUSE): per gate of the batch, the first and
     // last gate of its fused run (-1: not in a run)
     std::vector<int> run_first, run_last;
+    std::vector<GateDesc> run_desc;   // per batch position: the launch record of the run starting there
 };
 
 namespace {
@@ -461,6 +462,64 @@ GateDesc run_launch(const qcz_state *s, const GateDesc &first)
     return r;
 }
 
+// Gates a chunk-group run may hold: U1 / X whose target is a chunk-index bit
+// (pair jobs, any controls), in the modes of fused runs, on 2048-double chunks
+// without the entropy stage.  A run takes consecutive such gates on at most two
+// distinct target bits; each job then holds the four chunks those bits join.
+bool pairable(const qcz_state *s, const GateDesc &d)
+{
+    return (s->cfg.flags & QCZ_FLAG_FUSE) && !s->cache_on && d.job_type == J_PAIR && (d.kind == K_U1 || d.kind == K_X) &&
+           !d.per_block && d.job_end == 0 && !ent_state(s) && s->C == kCMax && (s->n - s->cb) >= 2 &&
+           (s->cfg.mode == QCZ_MODE_FIXED || s->cfg.mode == QCZ_MODE_LOSSLESS);
+}
+
+// Length of the run starting at descs[k] and its launch record: 0 (a lone
+// gate), a fused run of single-chunk gates (kind 1, at least two gates) or a
+// chunk-group run (kind 2, at least two gates).
+size_t run_at(const qcz_state *s, const GateDesc *descs, size_t n, size_t k, GateDesc &launch, int &kind)
+{
+    kind = 0;
+    size_t r = 0;
+    while (k + r < n && r < (size_t)kMaxRun && fusable(s, descs[k + r])) ++r;
+    if (r >= 2) {
+        kind = 1;
+        launch = run_launch(s, descs[k]);
+        return r;
+    }
+    uint64_t b1 = 0, b2 = 0;
+    r = 0;
+    while (k + r < n && r < (size_t)kMaxRun && pairable(s, descs[k + r])) {
+        const uint64_t pb = descs[k + r].pair_bit;
+        if (b1 == 0) b1 = pb;
+        else if (pb != b1 && b2 == 0) b2 = pb;
+        else if (pb != b1 && pb != b2) break;
+        ++r;
+    }
+    if (r < 2) return 0;
+    if (b2 == 0)   // one target bit: the lowest other chunk-index bit completes the groups
+        for (int bit = 0; bit < s->n - s->cb; ++bit)
+            if ((1ull << bit) != b1) { b2 = 1ull << bit; break; }
+    kind = 2;
+    launch = descs[k];
+    launch.job_type = J_GROUP;
+    launch.pair_bit = b1;
+    launch.pair_bit2 = b2;
+    launch.fixed_mask = b1 | b2;
+    launch.fixed_val = 0;
+    launch.check_phase = 0;
+    launch.act_mask = launch.act_val = 0;
+    launch.nitems = s->nchunks;
+    launch.njobs = s->nchunks / 4;
+    return r;
+}
+
+// chunk-group workgroups hold four chunks (two per CU fit its LDS): one resident round
+int group_grid(const qcz_state *s, const GateDesc &d)
+{
+    const int g = std::max(1, s->grid_max * 2 / 3);
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(d.njobs, (uint64_t)g));
+}
+
 qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
 {
     const bool timing = (s->cfg.flags & QCZ_FLAG_TIMING) != 0 || s->tuning;
@@ -475,22 +534,27 @@ qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
     s->cached.assign(descs.size(), 0);
     s->run_first.assign(descs.size(), -1);
     s->run_last.assign(descs.size(), -1);
+    s->run_desc.assign(descs.size(), GateDesc{});
     if (timing || !(s->cfg.flags & QCZ_FLAG_GRAPH) || s->stream == nullptr) {
         GateDesc *dev_descs = (GateDesc *)(s->pool + s->lay.rundesc);
         bool uploaded = false;
         for (size_t k = 0; k < descs.size();) {
-            size_t r = 0;
-            while (k + r < descs.size() && r < (size_t)kMaxRun && fusable(s, descs[k + r])) ++r;
-            if (r >= 2) {
+            GateDesc d;
+            int kind = 0;
+            const size_t r = run_at(s, descs.data(), descs.size(), k, d, kind);
+            if (kind != 0) {
                 if (!uploaded) {   // the batch's gate records, read by the fused runs
                     HIPCHK(s, hipMemcpyAsync(dev_descs, descs.data(), descs.size() * sizeof(GateDesc),
                                              hipMemcpyHostToDevice, s->stream));
                     uploaded = true;
                 }
-                const GateDesc d = run_launch(s, descs[k]);
                 hipEvent_t t0 = timing ? s->events[2 * d.seq] : nullptr, t1 = timing ? s->events[2 * d.seq + 1] : nullptr;
-                hipError_t e = launch_gate_run(d, ptrs(s), dev_descs + k, (int)r, grid_for(s, d), s->stream, t0, t1);
+                hipError_t e = kind == 1
+                                   ? launch_gate_run(d, ptrs(s), dev_descs + k, (int)r, grid_for(s, d), s->stream, t0, t1)
+                                   : launch_group_run(d, ptrs(s), dev_descs + k, (int)r, group_grid(s, d), s->stream,
+                                                      t0, t1);
                 if (e != hipSuccess) return fail(s, QCZ_E_DEVICE, std::string("fused run launch: ") + hipGetErrorString(e));
+                s->run_desc[k] = d;
                 if (timing) s->timed[k] = 1;
                 for (size_t j = k; j < k + r; ++j) {
                     s->run_first[j] = (int)k;
@@ -856,9 +920,10 @@ bool sweep_may_fit(const qcz_state *s)
     return need <= s->lay.arena_bytes - s->lay.arena_bytes / 32;
 }
 
-// Run descs[0 .. r) as a sweep (r > 1: a fused run).  *reason: STOP_NONE when
-// committed, else why the device stopped it (the state is then unchanged).
-qcz_status apply_sweep(qcz_state *s, const GateDesc *descs, size_t r, int *reason)
+// Run descs[0 .. r) as a sweep (kind 1: a fused run, kind 2: a chunk-group
+// run, launched from `launch`).  *reason: STOP_NONE when committed, else why
+// the device stopped it (the state is then unchanged).
+qcz_status apply_sweep(qcz_state *s, const GateDesc *descs, size_t r, int kind, const GateDesc &launch, int *reason)
 {
     *reason = STOP_NONE;
     const uint64_t base0 = s->base, ssize0 = s->stripe_size, live0 = s->live, bump0 = s->bump;
@@ -869,7 +934,9 @@ qcz_status apply_sweep(qcz_state *s, const GateDesc *descs, size_t r, int *reaso
     // stripes over the whole other arena (the header describes the arena written to)
     qcz_status st = reset_stripes(s, 0);
     if (st != QCZ_OK) return st;
-    GateDesc d = sweep_desc(r > 1 ? run_launch(s, descs[0]) : descs[0]);
+    GateDesc d = launch;
+    if (kind == 2) d.sweep = 1;   // (its enumeration covers every chunk already)
+    else d = sweep_desc(launch);
     d.seq = 0;
     DevPtrs P = ptrs(s);
     P.out = s->arena[other];
@@ -881,12 +948,13 @@ qcz_status apply_sweep(qcz_state *s, const GateDesc *descs, size_t r, int *reaso
             s->events.push_back(ev);
         }
     hipEvent_t t0 = timing ? s->events[0] : nullptr, t1 = timing ? s->events[1] : nullptr;
-    const int grid = grid_for(s, d);
+    const int grid = kind == 2 ? group_grid(s, d) : grid_for(s, d);
     hipError_t e;
-    if (r > 1) {
+    if (kind != 0) {
         GateDesc *dev_descs = (GateDesc *)(s->pool + s->lay.rundesc);
         HIPCHK(s, hipMemcpyAsync(dev_descs, descs, r * sizeof(GateDesc), hipMemcpyHostToDevice, s->stream));
-        e = launch_gate_run(d, P, dev_descs, (int)r, grid, s->stream, t0, t1);
+        e = kind == 1 ? launch_gate_run(d, P, dev_descs, (int)r, grid, s->stream, t0, t1)
+                      : launch_group_run(d, P, dev_descs, (int)r, grid, s->stream, t0, t1);
     } else {
         e = launch_gate(d, P, grid, s->stream, s->chunk_waves, t0, t1);
     }
@@ -1255,11 +1323,15 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
         // for arena room falls back to compaction and job ranges below.
         if ((gates_that_fit(s, descs) == 0 || sweep_for == (int)idx) && sweepable(s, descs[0]) &&
             swept_out != (int)idx && sweep_may_fit(s)) {
-            size_t r = 1;
-            if (fusable(s, descs[0]))
-                while (r < descs.size() && r < (size_t)kMaxRun && fusable(s, descs[r])) ++r;
+            GateDesc launch;
+            int kind = 0;
+            size_t r = run_at(s, descs.data(), descs.size(), 0, launch, kind);
+            if (kind == 0) {
+                r = 1;
+                launch = descs[0];
+            }
             int reason = STOP_NONE;
-            qcz_status st = apply_sweep(s, descs.data(), r, &reason);
+            qcz_status st = apply_sweep(s, descs.data(), r, kind, launch, &reason);
             if (st != QCZ_OK) return st;
             if (reason == STOP_NONE) {
                 idx += r;
@@ -1326,7 +1398,7 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
         const bool run_stop = sseq < (int)s->run_first.size() && s->run_first[(size_t)sseq] == sseq &&
                               s->run_last[(size_t)sseq] > sseq;
         const GateDesc &gstop = descs[(size_t)sseq];
-        const GateDesc dstop = run_stop ? run_launch(s, gstop) : gstop;
+        const GateDesc dstop = run_stop ? s->run_desc[(size_t)sseq] : gstop;
         DevPtrs P = ptrs(s);
         const uint64_t work = dstop.job_type == J_PERMUTE ? dstop.njobs : launch_items(dstop);
         const int rg = (int)std::max<uint64_t>(1, std::min<uint64_t>((work + kWG - 1) / kWG, 65535));

@@ -129,3 +129,90 @@ def test_fuse_rejected_with_autotune():
     from paper_1911_04034_amd import qcz
     with pytest.raises(qcz.QczError):
         qcz.State(10, 8, mode=qcz.MODE_FIXED, level=1, pool_bytes=16 << 20, flags=qcz.FLAG_FUSE | qcz.FLAG_AUTOTUNE)
+
+
+def group_heavy(n, seed):
+    """Runs of chunk-pair gates on chunk-index qubits (n - 4 .. n - 1 with
+    2^10-amplitude chunks): Hadamard and Rx layers, pair gates with controls on
+    chunk-index and in-chunk qubits, X with in-chunk controls, between random
+    gates of every kind."""
+    import numpy as np
+    hi = list(range(10, n))
+    parts = [cc.concat([cc.h(q) for q in range(n)]), cc.random_unitary_gates(n, 12, seed)]
+    for k in range(3):
+        parts.append(cc.concat([cc.rx(q, 0.3 + 0.2 * k + 0.01 * q) for q in hi]))
+        parts.append(cc.concat([cc.u1(hi[0], np.array([[0, 1j], [1j, 0]]), controls=(hi[1],)),
+                                cc.u1(hi[1], np.array([[1, 1], [1, -1]]) / np.sqrt(2), controls=(3,)),
+                                cc.x(hi[0], controls=(5,)), cc.h(hi[1]), cc.h(hi[0]),
+                                cc.u1(hi[2], np.array([[np.cos(0.4), -np.sin(0.4)], [np.sin(0.4), np.cos(0.4)]]),
+                                      controls=(hi[0], 2)), cc.h(hi[3])]))
+        parts.append(cc.random_unitary_gates(n, 10, seed + 1 + k))
+        parts.append(cc.concat([cc.rzz(hi[0], hi[2], 0.7), cc.rzz(1, hi[3], 0.2)]))
+    return cc.concat(parts)
+
+
+@pytest.mark.parametrize("level", [0, 1, 3])
+def test_chunk_group_runs_match_oracle(level):
+    """Runs of chunk-pair gates on two chunk-index qubits in one pass over
+    groups of four chunks: bytes equal the oracle's (gate by gate) after every
+    batch, and to the plain GPU run's."""
+    from paper_1911_04034_amd import qcz
+    n, bl = 14, 10
+    gates = group_heavy(n, 60 + level)
+    mode = oq.MODE_LOSSLESS if level == 0 else oq.MODE_FIXED
+    g, o = make(n, bl, mode, level, batch=64)
+    p = qcz.State(n, bl, mode=mode, level=level, pool_bytes=64 << 20, batch=64)
+    say("chunk-group runs level=%d (%d gates)" % (level, len(gates)))
+    for k in range(0, len(gates), 24):
+        part = gates[k:k + 24]
+        for s_ in (g, o, p):
+            s_.apply(part)
+        assert_same_chunks(g, o, "after gate %d" % (k + len(part) - 1))
+    fg, fo, fp = g.footprint(), o.footprint(), p.footprint()
+    assert fg["lossy_steps"] == fo["lossy_steps"] == fp["lossy_steps"]
+    assert fg["fidelity_lower_bound"] == fo["fidelity_lower_bound"]
+    assert g.stats()["gate_launches"] == p.stats()["gate_launches"]
+
+
+def test_chunk_group_runs_qaoa_and_grover_sweeps():
+    """QAOA-16 and Grover-15 with fused runs in an arena that a full-state
+    gate only fits as a sweep: chunk-group runs also sweep into the other
+    arena; bytes equal the oracle's."""
+    import ctypes
+    from paper_1911_04034_amd import qcz
+    for n, gates in ((16, cc.qaoa(16, 2, 3, 17)[0]), (15, cc.grover(15, 2, 19)[0])):
+        bl, level = 10, 1
+        o = oq.Sim(n, bl, oq.MODE_FIXED, level)
+        peak = 0
+        for k in range(len(gates)):
+            o.apply(gates[k:k + 1])
+            peak = max(peak, o.footprint()["compressed_bytes"])
+        cfg = qcz.Config(n, bl, 0, 0, 0, qcz.FLAG_FUSE, 0, 0, 0)
+        pmin = qcz.load().qcz_pool_bytes_min(ctypes.byref(cfg))
+        arena = int(1.25 * peak) + (32 << 10)
+        pool = pmin + 2 * (arena - (64 << 10) - 64 * (1 << (n - 10)))
+        g, o = make(n, bl, oq.MODE_FIXED, level, batch=96, pool_bytes=pool)
+        say("chunk-group sweeps n=%d: peak %d arena %d" % (n, peak, arena))
+        for k in range(0, len(gates), 40):
+            part = gates[k:k + 40]
+            assert g.apply(part) == len(part) and o.apply(part) == len(part)
+            assert_same_chunks(g, o, "n=%d after gate %d" % (n, k + len(part) - 1))
+        assert g.stats()["sweep_gates"] > 0
+
+
+def test_chunk_group_run_exhausting_the_arena_is_undone():
+    """A chunk-group run that overflows the arena stops and is undone over all
+    four chunks of every group; the call fails with NOMEM and the state is the
+    oracle's after the gates that completed."""
+    import ctypes
+    from paper_1911_04034_amd import qcz
+    n, bl = 14, 10
+    gates = cc.concat([cc.h(3), cc.h(7)] + [cc.concat([cc.h(q) for q in range(10, 14)]),
+                                            cc.random_unitary_gates(n, 40, 71)])
+    pmin = qcz.load().qcz_pool_bytes_min(ctypes.byref(qcz.Config(n, bl, 0, 0, 0, qcz.FLAG_FUSE, 0, 0, 0)))
+    g, o = make(n, bl, oq.MODE_LOSSLESS, 0, pool_bytes=pmin, batch=16)
+    rc, applied = g.try_apply(gates)
+    say("chunk-group arena exhaustion: rc=%d applied=%d" % (rc, applied))
+    assert rc == -2 and 0 < applied < len(gates)
+    o.apply(gates[:applied])
+    assert_same_chunks(g, o, "after arena NOMEM")
