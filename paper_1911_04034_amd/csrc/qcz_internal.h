@@ -52,7 +52,8 @@ struct GateDesc {
     uint64_t pair_bit2;             // GROUP: the second chunk-index bit of the four-chunk groups
 };
 
-// the jobs one launch of a gate runs
+// the jobs one launch of a gate runs, and the enumerated chunk positions per job
+__host__ __device__ inline uint64_t items_per_job(const GateDesc &d) { return d.job_type == J_GROUP ? 4 : 2; }
 __host__ __device__ inline uint64_t job_begin(const GateDesc &d) { return d.job_end ? d.job0 : 0; }
 __host__ __device__ inline uint64_t job_stop(const GateDesc &d) { return d.job_end ? d.job_end : d.njobs; }
 

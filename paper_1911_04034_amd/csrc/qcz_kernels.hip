@@ -2440,9 +2440,10 @@ __global__ __launch_bounds__(kWG) void rollback_kernel(GateDesc gd, DevPtrs P)
         }
         return;
     }
-    // the items of jobs [job_begin, job_stop): 2 job .. 2 job + 1
-    const uint64_t it0 = 2 * job_begin(gd);
-    const uint64_t it1 = 2 * job_stop(gd) < gd.nitems ? 2 * job_stop(gd) : gd.nitems;
+    // the items of jobs [job_begin, job_stop): two per job (four in chunk groups)
+    const uint64_t ipj = items_per_job(gd);
+    const uint64_t it0 = ipj * job_begin(gd);
+    const uint64_t it1 = ipj * job_stop(gd) < gd.nitems ? ipj * job_stop(gd) : gd.nitems;
     for (uint64_t it = it0 + (uint64_t)blockIdx.x * kWG + threadIdx.x; it < it1; it += stride)
         P.table[item_chunk(gd, it)] = P.undo[it];
 }

@@ -294,7 +294,8 @@ int grid_for(const qcz_state *s, const GateDesc &d)
 // enumerated chunk positions a launch covers (two per job)
 uint64_t launch_items(const GateDesc &d)
 {
-    const uint64_t i0 = 2 * job_begin(d), i1 = std::min<uint64_t>(2 * job_stop(d), d.nitems);
+    const uint64_t ipj = items_per_job(d);
+    const uint64_t i0 = ipj * job_begin(d), i1 = std::min<uint64_t>(ipj * job_stop(d), d.nitems);
     return i1 > i0 ? i1 - i0 : 0;
 }
 

@@ -216,3 +216,37 @@ def test_chunk_group_run_exhausting_the_arena_is_undone():
     assert rc == -2 and 0 < applied < len(gates)
     o.apply(gates[:applied])
     assert_same_chunks(g, o, "after arena NOMEM")
+
+
+def test_chunk_group_run_stopped_midway_restores_every_chunk():
+    """Regression: a chunk-group run that runs out of arena (as a sweep and
+    in place) is rolled back over all four chunks of every group, so the
+    call fails with the state exactly at the gate before the run.  Two dense
+    chunks (0 and 8 of sixteen, in the first and third group), then Rx on
+    two chunk-index qubits makes their groups dense: more than either arena
+    holds."""
+    import ctypes
+    import math
+    import numpy as np
+    from paper_1911_04034_amd import qcz
+    n, bl = 14, 10
+    rot = [cc.u1(q, np.array([[math.cos(0.3 * q + 0.1), -math.sin(0.3 * q + 0.1)],
+                              [math.sin(0.3 * q + 0.1), math.cos(0.3 * q + 0.1)]])) for q in range(10)]
+    before = cc.concat([cc.h(13)] + rot + [cc.t(q) for q in range(10)])
+    run = cc.concat([cc.rx(10, 0.7), cc.rx(11, 1.1)])
+    o = oq.Sim(n, bl, oq.MODE_LOSSLESS)
+    o.apply(before)
+    live = o.footprint()["compressed_bytes"]
+    cfg = qcz.Config(n, bl, 0, 0, 0, qcz.FLAG_FUSE, 0, 0, 0)
+    pmin = qcz.load().qcz_pool_bytes_min(ctypes.byref(cfg))
+    arena = int(1.8 * live)
+    pool = pmin + 2 * (arena - (64 << 10) - 64 * (1 << (n - 10)))
+    g = qcz.State(n, bl, mode=qcz.MODE_LOSSLESS, pool_bytes=pool, batch=64, flags=qcz.FLAG_FUSE)
+    assert g.apply(before) == len(before)
+    assert_same_chunks(g, o, "before the run")
+    say("group run stopped midway: live %d arena %d" % (live, arena))
+    rc, applied = g.try_apply(run)
+    assert rc == -2 and applied == 0
+    assert g.stats()["stops"] >= 1
+    assert_same_chunks(g, o, "after the rolled-back run")
+    assert g.footprint()["compressed_bytes"] == live
