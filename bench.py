@@ -8,8 +8,10 @@ amplitude blocks (chunks of 1024 amplitudes), error bound 1e-5 on every gate,
 256 GiB uncompressed.  The circuit is one continuing run cut into
 warmup + steps windows of consecutive gates; a step is one window.  Inputs
 (gate list, compressed state) are in HBM before timing.  Gates whose jobs
-lie inside single chunks run fused (one pass per run), and a gate that does
-not fit beside the live streams sweeps into the other arena.  Other workloads:
+lie inside single chunks run fused (one pass per run), chunk-pair gates on
+two chunk-index qubits run as one pass over groups of four chunks, a gate
+that does not fit beside the live streams sweeps into the other arena, and
+the windows are cut at the boundaries of those passes.  Other workloads:
 grover24+qft24 (the 24-qubit pair), grid30, grover34.
 
 Prints one JSON line:
@@ -182,10 +184,14 @@ def large_config(args, torch, cc, qcz):
     if args.gates:
         gates = gates[:args.gates]
     flags = qcz.FLAG_TIMING | qcz.FLAG_RANGES | (0 if args.no_fuse else qcz.FLAG_FUSE) | \
-        (qcz.FLAG_ENTROPY if args.entropy else 0)
+        (qcz.FLAG_ENTROPY if args.entropy else 0) | (0 if args.no_groups else qcz.FLAG_GROUPS)
     passes = args.warmup + args.steps
-    win = -(-len(gates) // passes)
-    windows = [gates[k:k + win] for k in range(0, len(gates), win)]
+    if args.no_fuse:
+        win = -(-len(gates) // passes)
+        windows = [gates[k:k + win] for k in range(0, len(gates), win)]
+    else:
+        windows = pass_windows(gates, min(bl, 10), passes, not args.no_groups and not args.entropy)
+    win = max(len(w) for w in windows)
     st = qcz.State(n, bl, mode=mode, level=level, budget=budget, pool_bytes=pool, flags=flags, batch=128)
     trace = [st.footprint()["compressed_bytes"]]
     walls = []
@@ -225,26 +231,36 @@ def large_config(args, torch, cc, qcz):
     amps = stats["amps_touched"]
     kms = stats["gate_kernel_ms"]
     timed = stats["timed_launches"]
-    byts = stats["bytes_read"] + stats["bytes_written"] + stats["table_bytes"]
-    avg_ms = kms / timed if timed else 0.0
-    per_launch = byts / timed if timed else 0.0
-    achieved = byts / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
-    traffic = alu = None
     from paper_1911_04034_amd import profile_summary as ps
-    tag = args.workload + ("_entropy" if args.entropy else "")
-    t_bytes, t_hash = ps.read_traffic(os.path.join(ROOT, "profiles", "traffic_fused_kernel_%s.txt" % tag))
-    if t_bytes is not None and t_hash == ps.kernel_hash():
-        traffic = round(t_bytes, 1)
-    busy, b_hash = ps.read_valu_busy(os.path.join(ROOT, "profiles", "counters_fused_kernel_%s.txt" % tag))
-    if busy and b_hash == ps.kernel_hash():
-        alu = busy.get(tag)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
-                "alu_frac": alu,
-                "kernel": "job_kernel<16, 2, ARENA, ARENA, gate%s> (fused decode-gate-encode)" % (
-                    ", entropy" if args.entropy else ""),
-                "avg_launch_us": round(avg_ms * 1e3, 3), "algorithmic_bytes_per_launch": round(per_launch, 1),
-                "launches": timed, "range_launches": stats["range_launches"], "sweep_gates": stats["sweep_gates"]}
+    suffix = "_entropy" if args.entropy else ""
+    kinds = {0: ("job_kernel", "job_kernel<16, 2, ARENA, ARENA, gate%s>: one gate per pass" % suffix.replace("_", ", ")),
+             1: ("run_kernel", "job_kernel<16, 2, ARENA, ARENA, gate, run%s>: a fused run of single-chunk gates per pass"
+                 % suffix.replace("_", ", ")),
+             2: ("group_kernel", "group_kernel<16>: a run of chunk-pair gates on two chunk-index qubits per pass")}
+    per = []
+    for i, (tag, name) in kinds.items():
+        L, ms, B = stats["kind_launches"][i], stats["kind_kernel_ms"][i], stats["kind_bytes"][i]
+        if L == 0 or ms <= 0:
+            continue
+        t_bytes, t_hash = ps.read_traffic(os.path.join(ROOT, "profiles", "traffic_%s_%s%s.txt" % (tag, args.workload,
+                                                                                              suffix)))
+        busy, b_hash = ps.read_valu_busy(os.path.join(ROOT, "profiles", "counters_%s_%s%s.txt" % (tag, args.workload,
+                                                                                              suffix)))
+        achieved = B / (ms * 1e-3) / 1e9
+        per.append({"kernel": name, "launches": L, "kernel_ms": round(ms, 1), "share_of_kernel_time": round(ms / kms, 4),
+                    "avg_launch_us": round(ms / L * 1e3, 3), "algorithmic_bytes_per_launch": round(B / L, 1),
+                    "achieved": round(achieved, 3), "frac": round(achieved / HBM_PEAK_GBS, 6),
+                    "traffic": round(t_bytes, 1) if t_bytes is not None and t_hash == ps.kernel_hash() else None,
+                    "alu_frac": busy.get(args.workload + suffix) if busy and b_hash == ps.kernel_hash() else None})
+    dom = max(per, key=lambda k: k["kernel_ms"]) if per else {"kernel": None, "achieved": 0.0, "frac": 0.0,
+                                                                "traffic": None, "alu_frac": None,
+                                                                "avg_launch_us": 0.0,
+                                                                "algorithmic_bytes_per_launch": 0.0, "launches": 0}
+    roofline = {"bound": "hbm", "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dom["frac"], "traffic": dom["traffic"], "alu_frac": dom["alu_frac"], "kernel": dom["kernel"],
+                "avg_launch_us": dom["avg_launch_us"], "algorithmic_bytes_per_launch": dom["algorithmic_bytes_per_launch"],
+                "launches": dom["launches"], "all_launches": timed, "range_launches": stats["range_launches"],
+                "sweep_gates": stats["sweep_gates"], "kernels": per}
     codecs = None
     if not args.gates:
         codecs = codec_comparison(torch, qcz, st, max(1, level))
@@ -263,6 +279,7 @@ def large_config(args, torch, cc, qcz):
                    "bound": [0.0, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1][level], "gates": int(len(gates)),
                    "gates_per_step": win, "final_level": fp["level"], "pool_bytes": int(pool),
                    "entropy_stage": bool(args.entropy), "fused_runs": not args.no_fuse,
+                   "chunk_group_runs": not (args.no_groups or args.no_fuse or args.entropy),
                    "parallelism": "single GPU"},
         "compression_ratio_min": round(fp["raw_bytes"] / (fp["max_compressed"] + fp["table_bytes"]), 3),
         "compression_ratio_final": round(fp["ratio"], 3),
@@ -285,6 +302,45 @@ def large_config(args, torch, cc, qcz):
         torch.cuda.empty_cache()
         line["fidelity"]["same_generator"] = qaoa_fidelity(qcz, cc, args.fidelity_qubits, bl, level, flags)
     print(json.dumps(line), flush=True)
+
+
+def pass_windows(gates, cb, nwin, groups, max_run=64):
+    """Cut the gate list into nwin consecutive windows at the boundaries of
+    the passes the library forms with fused runs (gates whose jobs lie inside
+    single chunks: one pass per run of up to 64; chunk-pair gates: one pass
+    each, or per run on at most two target qubits with chunk-group runs), so
+    that no step splits a pass; windows hold near-equal numbers of passes."""
+    U1, DIAG1, DIAG2, X, MCZ = 0, 1, 2, 3, 4
+    lo = (1 << cb) - 1
+    passes, cur, kind, bits = [], [], None, set()
+    for i in range(len(gates)):
+        g = gates[i]
+        k, t, cm = int(g["kind"]), int(g["target"]), int(g["control_mask"])
+        if k in (DIAG1, DIAG2, MCZ) or t < cb:
+            c = "single"
+        elif k == X and (cm & lo) == 0:
+            c = "permute"
+        else:
+            c = "pair"
+        joins = (c == kind and len(cur) < max_run and
+                 (c == "single" or (c == "pair" and groups and len(bits | {t}) <= 2)))
+        if not joins and cur:
+            passes.append(cur)
+            cur, bits = [], set()
+        cur.append(i)
+        kind = c
+        if c == "pair":
+            bits.add(t)
+    if cur:
+        passes.append(cur)
+    nwin = max(1, min(nwin, len(passes)))
+    out, start = [], 0
+    for w in range(nwin):
+        end = round((w + 1) * len(passes) / nwin)
+        idx = [i for p in passes[start:end] for i in p]
+        out.append(gates[idx[0]:idx[-1] + 1])
+        start = end
+    return out
 
 
 def codec_comparison(torch, qcz, st, level, nchunks=65536):
@@ -424,6 +480,9 @@ def main():
     ap.add_argument("--fidelity-qubits", type=int, default=30,
                     help="qaoa34: also measure the fidelity against lossless fp64 on the same generator at this "
                          "many qubits (0: skip)")
+    ap.add_argument("--no-groups", action="store_true",
+                    help="large configurations: chunk-pair gates one pass each instead of chunk-group runs on two "
+                         "chunk-index qubits (QCZ_FLAG_GROUPS)")
     ap.add_argument("--no-fuse", action="store_true",
                     help="large configurations: one pass per gate instead of fused runs (QCZ_FLAG_FUSE)")
     ap.add_argument("--entropy", action="store_true",

@@ -102,6 +102,14 @@ typedef enum {
                                Lossless: decoded values are those of the run without it.  Needs
                                block_log2 >= 10 (2048-double chunks) and two wavefronts per chunk; not with
                                QCZ_FLAG_CACHE or QCZ_FLAG_AUTOTUNE. */
+#define QCZ_FLAG_GROUPS 512u /* with QCZ_FLAG_FUSE: consecutive U1 / X gates whose targets are chunk-index qubits
+                               (chunk-pair jobs, any controls) on at most two distinct target bits run as one
+                               pass over groups of the four chunks those bits join (up to 64 gates): each chunk
+                               decoded and encoded once, each gate followed by the truncation its re-encoding
+                               would apply to the chunks it touched.  Same bytes and ledger as gate by gate.
+                               2048-double chunks, not with QCZ_FLAG_ENTROPY.  The pass holds four chunks in
+                               LDS (two workgroups per CU instead of three), so it pays where pair passes
+                               dominate and the state is small; measure before enabling. */
 #define QCZ_FLAG_RESHUFFLE 256u /* Solution D (Sec. 4.2): PACK and SPARSE chunks store their values re parts
                                first, then im parts (header bit 6), before the Solution C steps; decoded
                                values are those of the run without it.  Chunks created by qcz_create are
@@ -184,6 +192,12 @@ typedef struct {
     uint64_t sweep_gates;       /* gates run as sweeps: their new streams did not fit beside the live ones,
                                    so one launch wrote every chunk into the other arena (the chunks the gate
                                    leaves unchanged copied as they are) and the arenas swapped roles */
+    /* the same counters by kind of pass, [0] one gate, [1] a fused run of single-chunk gates (QCZ_FLAG_FUSE),
+       [2] a chunk-group run (QCZ_FLAG_GROUPS): event-timed launches and their time (QCZ_FLAG_TIMING), and
+       the stream bytes read and written plus table bytes of the committed passes */
+    uint64_t kind_launches[3];
+    double kind_kernel_ms[3];
+    uint64_t kind_bytes[3];
 } qcz_stats_t;
 
 /* Bytes of device pool needed for a configuration (state |0..0> plus

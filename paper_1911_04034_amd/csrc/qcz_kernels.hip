@@ -2103,28 +2103,34 @@ __global__ __launch_bounds__(256, 2) void group_kernel(GateDesc gd, DevPtrs P, I
         uint64_t old_entry[2] = {0, 0};
         bool ok_src_r[2] = {true, true};
 
-        // 1. two rounds of fetch and decode
+        // 1. fetch the four streams (each slot stages two, all loads in flight
+        //    together), then decode them in two rounds
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int gi = 2 * r + s;
+            const uint64_t e = P.table[cg[gi]];
+            old_entry[r] = e;
+            ok_src_r[r] = entry_ok(e, P.arena_words);
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int gi = 2 * r + s;
+            const uint64_t e = old_entry[r];
+            const uint32_t words = ((uint32_t)(e & 0xFFFFull) + 3u) >> 2;
+            const uint64_t off = e >> 16;
+            if (tg[gi] && ok_src_r[r]) {
+                if ((off & 3ull) == 0) stage_units<G>(buf[gi], P.arena + off, words, lt);
+                else stage_words<G>(buf[gi], P.arena + off, words, lt);
+            }
+            if ((tg[gi] || gd.sweep) && !ok_src_r[r] && lt == 0) atomicExch(&ds->corrupt, 1);
+            if (lt == 0) sh_src_ok[gi] = ok_src_r[r] ? 1 : 0;
+        }
+        lds_barrier();
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int gi = 2 * r + s;
             uint32_t *b = buf[gi];
             double *vals = reinterpret_cast<double *>(b);
-            const uint64_t c = cg[gi];
-            const bool act = tg[gi];
-            const uint64_t e = P.table[c];
-            old_entry[r] = e;
-            const uint32_t size = (uint32_t)(e & 0xFFFFull);
-            const uint64_t off = e >> 16;
-            const uint32_t words = (size + 3u) >> 2;
-            const bool ok_src = entry_ok(e, P.arena_words);
-            ok_src_r[r] = ok_src;
-            if (act && ok_src) {
-                if ((off & 3ull) == 0) stage_units<G>(b, P.arena + off, words, lt);
-                else stage_words<G>(b, P.arena + off, words, lt);
-            }
-            if ((act || gd.sweep) && !ok_src && lt == 0) atomicExch(&ds->corrupt, 1);
-            if (lt == 0) sh_src_ok[gi] = ok_src ? 1 : 0;
-            lds_barrier();
             const bool use0 = tg[2 * r] && sh_src_ok[2 * r] != 0, use1 = tg[2 * r + 1] && sh_src_ok[2 * r + 1] != 0;
             const bool use = s ? use1 : use0;
             const uint32_t hdr0 = use0 ? buf[2 * r][0] : (uint32_t)M_CONST2;

@@ -469,7 +469,8 @@ GateDesc run_launch(const qcz_state *s, const GateDesc &first)
 // distinct target bits; each job then holds the four chunks those bits join.
 bool pairable(const qcz_state *s, const GateDesc &d)
 {
-    return (s->cfg.flags & QCZ_FLAG_FUSE) && !s->cache_on && d.job_type == J_PAIR && (d.kind == K_U1 || d.kind == K_X) &&
+    return (s->cfg.flags & QCZ_FLAG_FUSE) && (s->cfg.flags & QCZ_FLAG_GROUPS) && !s->cache_on && d.job_type == J_PAIR &&
+           (d.kind == K_U1 || d.kind == K_X) &&
            !d.per_block && d.job_end == 0 && !ent_state(s) && s->C == kCMax && (s->n - s->cb) >= 2 &&
            (s->cfg.mode == QCZ_MODE_FIXED || s->cfg.mode == QCZ_MODE_LOSSLESS);
 }
@@ -608,7 +609,8 @@ qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
     return QCZ_OK;
 }
 
-void commit_gate(qcz_state *s, const GateLog &lg, const GateDesc &d, int k, bool tbl = true)
+// kind: 0 a one-gate pass, 1 a fused run, 2 a chunk-group run (per-kind counters)
+void commit_gate(qcz_state *s, const GateLog &lg, const GateDesc &d, int k, bool tbl = true, int kind = 0)
 {
     s->live = lg.live;
     s->bump = lg.bump;
@@ -623,6 +625,7 @@ void commit_gate(qcz_state *s, const GateLog &lg, const GateDesc &d, int k, bool
         S.bytes_read += lg.rd;
         S.bytes_written += lg.wr;
         if (tbl) S.table_bytes += 24 * lg.reenc;
+        S.kind_bytes[kind] += lg.rd + lg.wr + (tbl ? 24 * lg.reenc : 0);
         if (k < (int)s->cached.size() && s->cached[(size_t)k]) {
             // Sec. 3.4: the cache is switched off when it keeps missing
             S.cache_gates += 1;
@@ -636,6 +639,8 @@ void commit_gate(qcz_state *s, const GateLog &lg, const GateDesc &d, int k, bool
                 if (s->cfg.flags & QCZ_FLAG_TIMING) {
                     S.timed_launches += 1;
                     S.gate_kernel_ms += ms;
+                    S.kind_launches[kind] += 1;
+                    S.kind_kernel_ms[kind] += ms;
                 }
                 if (s->tuning) {
                     auto &c = s->cands[(size_t)s->tune_next];
@@ -676,7 +681,7 @@ void commit_logged(qcz_state *s, const DevState &h, const GateDesc &d, int k)
     GateLog lg = h.log[f];
     const bool last = k == s->run_last[(size_t)k];
     if (!last) lg.rd = lg.wr = 0;
-    commit_gate(s, lg, d, k, last);
+    commit_gate(s, lg, d, k, last, s->run_desc[(size_t)f].job_type == J_GROUP ? 2 : 1);
 }
 
 // Move the autotuner to its next candidate; after kTuneRounds passes over
@@ -830,6 +835,8 @@ qcz_status apply_in_ranges(qcz_state *s, const GateDesc &d)
                 s->stats.timed_launches += 1;
                 s->stats.gate_kernel_ms += ms;
                 s->stats.range_launches += 1;
+                s->stats.kind_launches[0] += 1;
+                s->stats.kind_kernel_ms[0] += ms;
             }
         }
         const DevState &h = s->hds;
@@ -972,6 +979,8 @@ qcz_status apply_sweep(qcz_state *s, const GateDesc *descs, size_t r, int kind, 
             if (hipEventElapsedTime(&ms, s->events[0], s->events[1]) == hipSuccess) {
                 s->stats.timed_launches += 1;
                 s->stats.gate_kernel_ms += ms;
+                s->stats.kind_launches[kind] += 1;
+                s->stats.kind_kernel_ms[kind] += ms;
             }
         }
         // a fused run commits like one of launch_batch: every gate takes the
@@ -981,7 +990,7 @@ qcz_status apply_sweep(qcz_state *s, const GateDesc *descs, size_t r, int kind, 
         for (size_t k = 0; k < r; ++k) {
             GateLog lg = h.log[0];
             if (k + 1 < r) lg.rd = lg.wr = 0;
-            commit_gate(s, lg, descs[k], (int)k, k + 1 == r);
+            commit_gate(s, lg, descs[k], (int)k, k + 1 == r, kind);
         }
         s->stats.sweep_gates += r;
         return QCZ_OK;

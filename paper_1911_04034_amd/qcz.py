@@ -25,6 +25,7 @@ FLAG_CACHE_COLLIDE = 32
 FLAG_FUSE = 64
 FLAG_ENTROPY = 128
 FLAG_RESHUFFLE = 256
+FLAG_GROUPS = 512
 CODEC_ENTROPY = 1
 CODEC_RESHUFFLE = 2
 CODEC_PREDICT = 4
@@ -64,7 +65,9 @@ class Stats(ctypes.Structure):
                 ("tuning", ctypes.c_uint32), ("stops", ctypes.c_uint32),
                 ("range_gates", ctypes.c_uint64), ("cache_gates", ctypes.c_uint64),
                 ("cache_hits", ctypes.c_uint64), ("cache_on", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("range_launches", ctypes.c_uint64), ("sweep_gates", ctypes.c_uint64)]
+                ("range_launches", ctypes.c_uint64), ("sweep_gates", ctypes.c_uint64),
+                ("kind_launches", ctypes.c_uint64 * 3), ("kind_kernel_ms", ctypes.c_double * 3),
+                ("kind_bytes", ctypes.c_uint64 * 3)]
 
 
 EXPORTED = [
@@ -289,7 +292,11 @@ class State:
     def stats(self) -> dict:
         st = Stats()
         self._check(self._lib.qcz_get_stats(self._h, ctypes.byref(st)), "qcz_get_stats")
-        return {k: getattr(st, k) for k, _ in Stats._fields_}
+        out = {}
+        for k, _ in Stats._fields_:
+            v = getattr(st, k)
+            out[k] = list(v) if k.startswith("kind_") else v
+        return out
 
     def reset_stats(self):
         self._check(self._lib.qcz_reset_stats(self._h), "qcz_reset_stats")

@@ -3,13 +3,14 @@
 text files kept under profiles/ (the benchmark reads two of them back).
 
 Usage:
-  python profile_summary.py stats <kernel_stats.csv> <command> [<kernel_trace.csv> <last_n>] > profiles/X.txt
+  python profile_summary.py stats <kernel_stats.csv> <command> [<kernel_trace.csv> <last_n> [<kernel>]] > profiles/X.txt
   python profile_summary.py traffic <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir> <copy_bytes> \\
          <last_n_dispatches> <command> [<kernel>] > profiles/Y.txt
   python profile_summary.py counters <command> <kernel> <name>=<dir> [<name>=<dir> ...] > profiles/Z.txt
 
-<kernel> picks the dispatches by name: "plain" (job_kernel<16, 2, 0, 0, true, 0, false>, the default) or
-"entropy" (job_kernel<16, 2, 0, 0, true, 0, true>).  The traffic summary scales the per-dispatch FETCH_SIZE /
+<kernel> picks the dispatches by name: "plain" (job_kernel<16, 2, 0, 0, true, 0, false>: one gate per pass,
+the default), "entropy" (the same with the entropy stage), "run" (job_kernel<16, 2, 0, 0, true, 3, false>: a
+fused run of single-chunk gates) or "group" (group_kernel<16>: a chunk-group run).  The traffic summary scales the per-dispatch FETCH_SIZE /
 WRITE_SIZE of the kernel by the bytes per counter unit that the same counters read for a plain device copy;
 every summary records the hash of the device code it was taken with.
 """
@@ -23,7 +24,8 @@ import sys
 
 from paper_1911_04034_amd.profile_summary import kernel_hash
 
-KERNELS = {"plain": "job_kernel<16, 2, 0, 0, true, 0, false>", "entropy": "job_kernel<16, 2, 0, 0, true, 0, true>"}
+KERNELS = {"plain": "job_kernel<16, 2, 0, 0, true, 0, false>", "entropy": "job_kernel<16, 2, 0, 0, true, 0, true>",
+           "run": "job_kernel<16, 2, 0, 0, true, 3, false>", "group": "group_kernel<16>"}
 
 
 def _counter_rows(d):
@@ -54,7 +56,8 @@ def stats(path, command, trace=None, last=0, kernel="plain"):
         tr = [r for r in csv.DictReader(open(trace)) if KERNELS[kernel] in r["Kernel_Name"]]
         tr.sort(key=lambda r: int(r["Start_Timestamp"]))
         d = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in tr][-int(last):]
-        print("# fused kernel, last %d dispatches (the timed region): mean %.1f ns" % (len(d), statistics.mean(d)))
+        print("# %s, last %d dispatches (the timed region): mean %.1f ns" % (KERNELS[kernel], len(d),
+                                                                          statistics.mean(d)))
     print("# rocprofv3 --kernel-trace --stats summary")
     print("# command: %s" % command)
     print("# kernel source sha256[:16]: %s" % kernel_hash())
@@ -122,7 +125,7 @@ if __name__ == "__main__":
     if len(sys.argv) < 2:
         raise SystemExit(__doc__)
     if sys.argv[1] == "stats":
-        stats(sys.argv[2], sys.argv[3], *sys.argv[4:7])
+        stats(sys.argv[2], sys.argv[3], *sys.argv[4:8])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:10])
     elif sys.argv[1] == "counters":

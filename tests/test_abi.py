@@ -64,8 +64,8 @@ def test_block_cache_pool_and_stats_layout():
     need = 12 * nchunks + 12 * (nchunks // 2) + 1024 * 56
     assert need <= cached - plain <= need + 5 * 256
     assert qcz.Stats.cache_on.offset == qcz.Stats.cache_hits.offset + 8
-    assert ctypes.sizeof(qcz.Stats) == qcz.Stats.sweep_gates.offset + 8 == qcz.Stats.range_launches.offset + 16 \
-        == qcz.Stats.reserved.offset + 20
+    assert ctypes.sizeof(qcz.Stats) == qcz.Stats.kind_bytes.offset + 24 == qcz.Stats.sweep_gates.offset + 80 \
+        == qcz.Stats.range_launches.offset + 88 == qcz.Stats.reserved.offset + 92
 
 
 def test_profile_summaries_parse():

@@ -160,7 +160,7 @@ def test_chunk_group_runs_match_oracle(level):
     n, bl = 14, 10
     gates = group_heavy(n, 60 + level)
     mode = oq.MODE_LOSSLESS if level == 0 else oq.MODE_FIXED
-    g, o = make(n, bl, mode, level, batch=64)
+    g, o = make(n, bl, mode, level, batch=64, flags=qcz.FLAG_FUSE | qcz.FLAG_GROUPS)
     p = qcz.State(n, bl, mode=mode, level=level, pool_bytes=64 << 20, batch=64)
     say("chunk-group runs level=%d (%d gates)" % (level, len(gates)))
     for k in range(0, len(gates), 24):
@@ -187,11 +187,11 @@ def test_chunk_group_runs_qaoa_and_grover_sweeps():
         for k in range(len(gates)):
             o.apply(gates[k:k + 1])
             peak = max(peak, o.footprint()["compressed_bytes"])
-        cfg = qcz.Config(n, bl, 0, 0, 0, qcz.FLAG_FUSE, 0, 0, 0)
+        cfg = qcz.Config(n, bl, 0, 0, 0, qcz.FLAG_FUSE | qcz.FLAG_GROUPS, 0, 0, 0)
         pmin = qcz.load().qcz_pool_bytes_min(ctypes.byref(cfg))
         arena = int(1.25 * peak) + (32 << 10)
         pool = pmin + 2 * (arena - (64 << 10) - 64 * (1 << (n - 10)))
-        g, o = make(n, bl, oq.MODE_FIXED, level, batch=96, pool_bytes=pool)
+        g, o = make(n, bl, oq.MODE_FIXED, level, batch=96, pool_bytes=pool, flags=qcz.FLAG_FUSE | qcz.FLAG_GROUPS)
         say("chunk-group sweeps n=%d: peak %d arena %d" % (n, peak, arena))
         for k in range(0, len(gates), 40):
             part = gates[k:k + 40]
@@ -209,8 +209,9 @@ def test_chunk_group_run_exhausting_the_arena_is_undone():
     n, bl = 14, 10
     gates = cc.concat([cc.h(3), cc.h(7)] + [cc.concat([cc.h(q) for q in range(10, 14)]),
                                             cc.random_unitary_gates(n, 40, 71)])
-    pmin = qcz.load().qcz_pool_bytes_min(ctypes.byref(qcz.Config(n, bl, 0, 0, 0, qcz.FLAG_FUSE, 0, 0, 0)))
-    g, o = make(n, bl, oq.MODE_LOSSLESS, 0, pool_bytes=pmin, batch=16)
+    flags = qcz.FLAG_FUSE | qcz.FLAG_GROUPS
+    pmin = qcz.load().qcz_pool_bytes_min(ctypes.byref(qcz.Config(n, bl, 0, 0, 0, flags, 0, 0, 0)))
+    g, o = make(n, bl, oq.MODE_LOSSLESS, 0, pool_bytes=pmin, batch=16, flags=flags)
     rc, applied = g.try_apply(gates)
     say("chunk-group arena exhaustion: rc=%d applied=%d" % (rc, applied))
     assert rc == -2 and 0 < applied < len(gates)
@@ -237,11 +238,12 @@ def test_chunk_group_run_stopped_midway_restores_every_chunk():
     o = oq.Sim(n, bl, oq.MODE_LOSSLESS)
     o.apply(before)
     live = o.footprint()["compressed_bytes"]
-    cfg = qcz.Config(n, bl, 0, 0, 0, qcz.FLAG_FUSE, 0, 0, 0)
+    flags = qcz.FLAG_FUSE | qcz.FLAG_GROUPS
+    cfg = qcz.Config(n, bl, 0, 0, 0, flags, 0, 0, 0)
     pmin = qcz.load().qcz_pool_bytes_min(ctypes.byref(cfg))
     arena = int(1.8 * live)
     pool = pmin + 2 * (arena - (64 << 10) - 64 * (1 << (n - 10)))
-    g = qcz.State(n, bl, mode=qcz.MODE_LOSSLESS, pool_bytes=pool, batch=64, flags=qcz.FLAG_FUSE)
+    g = qcz.State(n, bl, mode=qcz.MODE_LOSSLESS, pool_bytes=pool, batch=64, flags=flags)
     assert g.apply(before) == len(before)
     assert_same_chunks(g, o, "before the run")
     say("group run stopped midway: live %d arena %d" % (live, arena))
