@@ -96,10 +96,14 @@ SQ = ["SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES", "SQ_INSTS_LDS", "SQ_INSTS_SALU", 
       "SQ_WAVES", "SQ_WAVE_CYCLES"]
 
 
-def counters(command, kernel, *runs, waves_per_simd=3):
+WAVES_PER_SIMD = {"group": 2}   # resident waves per SIMD (two workgroups of four waves per CU); others three
+
+
+def counters(command, kernel, *runs):
     """Mean per dispatch of the SQ counters of the fused kernel, one block per
     `name=dir` run, with the ratios derived from them."""
     name = KERNELS[kernel]
+    waves_per_simd = WAVES_PER_SIMD.get(kernel, 3)
     print("# rocprofv3 SQ counters of the fused gate kernel %s (mean per dispatch)" % name)
     print("# command: %s" % command)
     print("# %d waves per SIMD: VALU busy per SIMD = %d * SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES" % (waves_per_simd,
