@@ -83,6 +83,9 @@ __device__ __forceinline__ bool subnormal(uint32_t h, uint32_t l)
     return ((h >> 20) & 0x7FFu) == 0 && ((h & 0xFFFFFu) | l) != 0;
 }
 
+// the same test on a double (one class comparison: positive or negative subnormal)
+__device__ __forceinline__ bool is_subnormal(double x) { return __builtin_isfpclass(x, 0x0090); }
+
 __device__ __forceinline__ int clampw(int i) { return i < kBufWords - 1 ? i : kBufWords - 1; }
 // first of N consecutive words read together (one ds_read2 for N = 2)
 template <int N>
@@ -1181,7 +1184,8 @@ __device__ __forceinline__ void phase_of(const double *m, int idx, double &pr, d
 
 // a diagonal gate leaves chunk c alone when every phase reachable in it is 1
 // unit_mask: bit idx set when phase idx is 1 (computed once per launch)
-__device__ bool diag_touches(const GateDesc &gd, uint32_t unit_mask, uint64_t c, int cb)
+template <class D>
+__device__ bool diag_touches(const D &gd, uint32_t unit_mask, uint64_t c, int cb)
 {
     const int nidx = gd.kind == K_DIAG1 ? 2 : 4;
 #pragma unroll
@@ -1245,7 +1249,9 @@ __device__ __forceinline__ bool entry_ok(uint64_t entry, uint64_t arena_words)
     return words <= (uint32_t)(kBufWords - 8) && (entry >> 16) + words <= arena_words && size >= 4;
 }
 
-__device__ void apply_gate(const GateDesc &gd, const double *m, double *v0, double *v1, uint64_t c0, uint64_t c1,
+// D: a GateDesc, or a fused run's RunRec (the fields kind, q, q2, cm, job_type)
+template <class D>
+__device__ void apply_gate(const D &gd, const double *m, double *v0, double *v1, uint64_t c0, uint64_t c1,
                            bool a0, bool a1, int cb, int nthreads)
 {
     const int tid = threadIdx.x;
@@ -1316,24 +1322,48 @@ __device__ void apply_gate(const GateDesc &gd, const double *m, double *v0, doub
     }
 }
 
+// A fused run's gate as the run loop reads it, copied to LDS once per launch:
+// the kernel writes global memory, so reads of the run's records there inside
+// the job loop would be vector loads, each waited for on its own.
+struct RunRec {
+    uint64_t cm;                     // control mask over amplitude-index bits
+    uint64_t fixed_mask, fixed_val;  // chunk-index bits held fixed by the gate's enumeration
+    int32_t kind, q, q2, job_type;
+    int32_t check_phase;             // diagonal: chunks whose reachable phases are all 1 are not touched
+    uint32_t unit;                   // bit i: phase i is 1
+};
+
+__device__ __forceinline__ RunRec run_rec(const GateDesc &d)
+{
+    RunRec r;
+    r.cm = d.cm;
+    r.fixed_mask = d.fixed_mask;
+    r.fixed_val = d.fixed_val;
+    r.kind = d.kind;
+    r.q = d.q;
+    r.q2 = d.q2;
+    r.job_type = d.job_type;
+    r.check_phase = d.check_phase;
+    r.unit = 0;
+    for (int i = 0; i < 4; ++i) r.unit |= unit_phase(d.m[2 * i], d.m[2 * i + 1]) ? (1u << i) : 0u;
+    return r;
+}
+
 // whether gate rg of a fused run re-encodes chunk c: the chunk is in its
 // enumeration (controls on chunk-index qubits, a diagonal's fixed half) and,
-// for a diagonal gate, some phase reachable in the chunk is not 1 (the gate's
-// record is read from global memory: uniform, scalar loads)
-__device__ __forceinline__ bool run_touches(const GateDesc &rg, uint64_t c, int cb)
+// for a diagonal gate, some phase reachable in the chunk is not 1
+__device__ __forceinline__ bool run_touches(const RunRec &rg, uint64_t c, int cb)
 {
     if ((c & rg.fixed_mask) != rg.fixed_val) return false;
     if (!rg.check_phase) return true;
-    uint32_t um = 0;
-    for (int i = 0; i < 4; ++i) um |= unit_phase(rg.m[2 * i], rg.m[2 * i + 1]) ? (1u << i) : 0u;
-    return diag_touches(rg, um, c, cb);
+    return diag_touches(rg, rg.unit, c, cb);
 }
 
 // A single-chunk gate that each thread can apply to its own V values: diagonal
 // phases, multi-controlled Z, and U1 / X whose target pairs lie inside a
 // thread's V/2 amplitudes (2^(q+1) <= V/2).  Same arithmetic as apply_gate.
-template <int V>
-__device__ __forceinline__ bool gate_in_registers(const GateDesc &gd)
+template <int V, class D>
+__device__ __forceinline__ bool gate_in_registers(const D &gd)
 {
     if (gd.job_type != J_SINGLE || (V & 1)) return false;
     if (gd.kind == K_DIAG1 || gd.kind == K_DIAG2 || gd.kind == K_MCZ) return true;
@@ -1350,7 +1380,8 @@ struct RegSplit {
     static constexpr int LB = A >= 8 ? 3 : A >= 4 ? 2 : A >= 2 ? 1 : 0;   // log2(A)
     bool mine;       // my high bits satisfy the high controls
     uint32_t cm_lo;  // controls among the low bits
-    __device__ __forceinline__ RegSplit(const GateDesc &gd, uint64_t base)
+    template <class D>
+    __device__ __forceinline__ RegSplit(const D &gd, uint64_t base)
     {
         const uint64_t hi_mask = ~(uint64_t)(A - 1);
         mine = (base & gd.cm & hi_mask) == (gd.cm & hi_mask);
@@ -1358,8 +1389,8 @@ struct RegSplit {
     }
 };
 
-template <int V, int Q>
-__device__ __forceinline__ void pairs_in_registers(const GateDesc &gd, const double *m, double (&x)[V],
+template <int V, int Q, class D>
+__device__ __forceinline__ void pairs_in_registers(const D &gd, const double *m, double (&x)[V],
                                                    const RegSplit<V> &sp)
 {
 #pragma unroll
@@ -1380,8 +1411,8 @@ __device__ __forceinline__ void pairs_in_registers(const GateDesc &gd, const dou
 }
 
 // x: my V values (amplitudes base .. base + V/2 - 1 of the state)
-template <int V>
-__device__ __forceinline__ void apply_gate_registers(const GateDesc &gd, const double *m, double (&x)[V], uint64_t base)
+template <int V, class D>
+__device__ __forceinline__ void apply_gate_registers(const D &gd, const double *m, double (&x)[V], uint64_t base)
 {
     const RegSplit<V> sp(gd, base);
     if (!sp.mine) return;
@@ -1472,6 +1503,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     __shared__ double sh_m[8];
     __shared__ double sh_rm[LIST == 3 ? kMaxRun : 1][8];   // fused run: the gates' matrices
     __shared__ uint32_t sh_rsub[2][WGS / 64];              // fused run: subnormal flags, alternating per truncation
+    __shared__ RunRec sh_rr[LIST == 3 ? kMaxRun : 1];      // fused run: the gates' records
     // entropy stage, per slot: decode tables while decoding, encode tables and lane records while encoding
     __shared__ __align__(16) uint32_t sh_ent[ENT ? 2 : 1][ENT ? kEntSlotWords : 1];
 
@@ -1480,8 +1512,11 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
 
     const int tid = threadIdx.x, s = tid / G, lt = tid % G;
     if (GATE && tid < 8) sh_m[tid] = gd.m[tid];   // first read after the first job's fetch barrier
-    if (LIST == 3)
+    if (LIST == 3) {
         for (int i = tid; i < 8 * io.nrun; i += WGS) sh_rm[i >> 3][i & 7] = io.run[i >> 3].m[i & 7];
+        for (int g = tid; g < io.nrun; g += WGS) sh_rr[g] = run_rec(io.run[g]);
+        lds_barrier();   // the records are read before the first job's fetch barrier
+    }
     uint32_t unit_mask = 0;                        // phases equal to 1 (diagonal gates)
     if (GATE)
         for (int i = 0; i < 4; ++i) unit_mask |= unit_phase(gd.m[2 * i], gd.m[2 * i + 1]) ? (1u << i) : 0u;
@@ -1526,130 +1561,155 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
         uint64_t cc0 = 0, cc1 = 0;
         bool act0 = job_slot<SRC, GATE>(gd, unit_mask, io, P.cb, item0, cc0);
         bool act1 = job_slot<SRC, GATE>(gd, unit_mask, io, P.cb, item1, cc1);
+        uint64_t tm0 = 0, tm1 = 0;   // fused run: bit g set when gate g touches the slot's chunk
         if (LIST == 3) {
             // a fused run enumerates every chunk; it re-encodes those some gate touches
-            bool t0 = false, t1 = false;
             for (int g = 0; g < io.nrun; ++g) {
-                t0 = t0 || run_touches(io.run[g], cc0, P.cb);
-                t1 = t1 || run_touches(io.run[g], cc1, P.cb);
+                tm0 |= run_touches(sh_rr[g], cc0, P.cb) ? (1ull << g) : 0ull;
+                tm1 |= run_touches(sh_rr[g], cc1, P.cb) ? (1ull << g) : 0ull;
             }
-            act0 = act0 && t0;
-            act1 = act1 && t1;
+            act0 = act0 && tm0 != 0;
+            act1 = act1 && tm1 != 0;
         }
         const uint64_t item = s ? item1 : item0;
         const uint64_t c = s ? cc1 : cc0;
         const bool valid = s ? valid1 : valid0;
         const bool act = s ? act1 : act0;
 
-        // 1. fetch
+        // 1-3. fetch, decode and (fused runs) the run's gates; a fused run
+        // takes a second attempt when its first one met a subnormal value
         uint64_t old_entry = 0;
-        bool ok_src = true;
-        if (SRC == SRC_ARENA) {
-            if (valid) old_entry = P.table[c];
-            const uint32_t size = (uint32_t)(old_entry & 0xFFFFull);
-            const uint64_t off = old_entry >> 16;
-            const uint32_t words = (size + 3u) >> 2;
-            ok_src = entry_ok(old_entry, P.arena_words);
-            if (act && ok_src) {
-                if ((off & 3ull) == 0) stage_units<G>(b, P.arena + off, words, lt);
-                else stage_words<G>(b, P.arena + off, words, lt);
-            }
-            if ((act || (GATE && gd.sweep && valid)) && !ok_src && lt == 0 && ds) atomicExch(&ds->corrupt, 1);
-        } else if (SRC == SRC_SLOTS) {
-            const uint32_t size = valid ? io.sizes_in[item] : 0u;
-            const uint32_t words = (size + 3u) >> 2;
-            ok_src = words <= (uint32_t)(kBufWords - 8) && words <= io.slot_words && size >= 4;
-            if (act && ok_src) stage_words<G>(b, io.slots_in + item * io.slot_words, words, lt);
-        } else {  // SRC_RAW
-            if (act)
-                for (int w = lt; w < C; w += G) vals[vpos(w)] = io.raw_in[item * (uint64_t)C + w];
-        }
-        if (lt == 0) sh_src_ok[s] = ok_src ? 1 : 0;
-        lds_barrier();
-        // (slot streams of Solution B, header mode 3, are decoded by their own kernel)
-        const bool use0 = act0 && sh_src_ok[0] != 0 && (SRC != SRC_SLOTS || (buf[0][0] & 3u) != 3u);
-        const bool use1 = act1 && sh_src_ok[1] != 0 && (SRC != SRC_SLOTS || (buf[1][0] & 3u) != 3u);
-        const bool use = s ? use1 : use0;
-
-        // 2. decode
+        bool ok_src = true, use0 = false, use1 = false, use = false;
         uint32_t my_hdr = 0;
-        if (SRC != SRC_RAW) {
-            const uint32_t hdr0 = use0 ? buf[0][0] : (uint32_t)M_CONST2;
-            const uint32_t hdr1 = use1 ? buf[1][0] : (uint32_t)M_CONST2;
-            my_hdr = s ? hdr1 : hdr0;
-            const bool any_sparse = (hdr0 & 3u) == M_SPARSE || (hdr1 & 3u) == M_SPARSE;
-            const bool any_ent = ENT && ((hdr0 | hdr1) & kHdrEnt) != 0;
-            uint32_t th[V], tl[V];
-            decode_group<V, WPG, ENT>(b, s ? hdr1 : hdr0, use, any_sparse, C, lt, slA, slB, slC, th, tl, any_ent,
-                                      reinterpret_cast<uint8_t *>(ent));
-            lds_barrier();
-            double x[V];
-#pragma unroll
-            for (int k = 0; k < V; ++k) x[k] = u2d(((uint64_t)th[k] << 32) | tl[k]);
-            // Solution D streams: the values, decoded in stored order, go to their
-            // interleaved positions through LDS (uniform branch over the workgroup)
-            const bool rsh0 = use0 && (hdr0 & kHdrRsh) != 0, rsh1 = use1 && (hdr1 & kHdrRsh) != 0;
-            if (rsh0 || rsh1) {
-                const bool mine = s ? rsh1 : rsh0;
-#pragma unroll
-                for (int k = 0; k < V; ++k) vals[vpos(mine ? rsh_pos(first + k, C) : first + k)] = x[k];
-                lds_barrier();
-#pragma unroll
-                for (int k = 0; k < V; ++k) x[k] = vals[vpos(first + k)];
-            }
-            if (LIST == 3) {
-                // 3r. the run: each gate (in registers or through LDS), then the
-                // truncation re-encoding would apply (none when the chunk holds
-                // a subnormal value), so the one encode below equals the last of
-                // the gate-by-gate encodes
-                const uint64_t base = (c << P.cb) | (uint64_t)(first / 2);
-                const uint32_t mh = sig_mask_hi(sig_bits(glevel));
-                int ntr = 0;
-                for (int g = 0; g < io.nrun; ++g) {
-                    const GateDesc &rg = io.run[g];
-                    // a chunk the gate does not touch skips it and its truncation,
-                    // as it would keep its stream gate by gate
-                    const bool tg0 = use0 && run_touches(rg, cc0, P.cb), tg1 = use1 && run_touches(rg, cc1, P.cb);
-                    const bool tg = s ? tg1 : tg0;
-                    if (gate_in_registers<V>(rg)) {
-                        if (tg) apply_gate_registers<V>(rg, sh_rm[g], x, base);
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
-                        lds_barrier();
-                        apply_gate(rg, sh_rm[g], reinterpret_cast<double *>(buf[0]),
-                                   reinterpret_cast<double *>(buf[1]), cc0, cc1, tg0, tg1, P.cb, WGS);
-                        lds_barrier();
-#pragma unroll
-                        for (int k = 0; k < V; ++k) x[k] = vals[vpos(first + k)];
-                    }
-                    if (glevel > 0 && (tg0 || tg1)) {
-                        bool sub = false;
-#pragma unroll
-                        for (int k = 0; k < V; ++k) {
-                            const uint64_t u = d2u(x[k]);
-                            sub = sub || subnormal((uint32_t)(u >> 32), (uint32_t)u);
-                        }
-                        const bool wsub = __any(tg && sub);
-                        if ((tid & 63) == 0) sh_rsub[ntr & 1][tid >> 6] = wsub ? 1u : 0u;
-                        lds_barrier();
-                        uint32_t gs = 0;
-#pragma unroll
-                        for (int i = 0; i < WPG; ++i) gs |= sh_rsub[ntr & 1][s * WPG + i];
-                        ++ntr;   // flags alternate per truncation step: a barrier separates reuses
-                        if (gs == 0 && tg) {
-#pragma unroll
-                            for (int k = 0; k < V; ++k) x[k] = u2d((uint64_t)((uint32_t)(d2u(x[k]) >> 32) & mh) << 32);
-                        }
-                    }
+        for (bool careful = false;; careful = true) {
+            // 1. fetch
+            old_entry = 0;
+            ok_src = true;
+            if (SRC == SRC_ARENA) {
+                if (valid) old_entry = P.table[c];
+                const uint32_t size = (uint32_t)(old_entry & 0xFFFFull);
+                const uint64_t off = old_entry >> 16;
+                const uint32_t words = (size + 3u) >> 2;
+                ok_src = entry_ok(old_entry, P.arena_words);
+                if (act && ok_src) {
+                    if ((off & 3ull) == 0) stage_units<G>(b, P.arena + off, words, lt);
+                    else stage_words<G>(b, P.arena + off, words, lt);
                 }
-            } else if (GATE && gate_in_registers<V>(gd) && use) {
-                // 3a. a gate each thread applies to its own values (no LDS pass)
-                apply_gate_registers<V>(gd, sh_m, x, (c << P.cb) | (uint64_t)(first / 2));
+                if ((act || (GATE && gd.sweep && valid)) && !ok_src && lt == 0 && ds) atomicExch(&ds->corrupt, 1);
+            } else if (SRC == SRC_SLOTS) {
+                const uint32_t size = valid ? io.sizes_in[item] : 0u;
+                const uint32_t words = (size + 3u) >> 2;
+                ok_src = words <= (uint32_t)(kBufWords - 8) && words <= io.slot_words && size >= 4;
+                if (act && ok_src) stage_words<G>(b, io.slots_in + item * io.slot_words, words, lt);
+            } else {  // SRC_RAW
+                if (act)
+                    for (int w = lt; w < C; w += G) vals[vpos(w)] = io.raw_in[item * (uint64_t)C + w];
             }
-#pragma unroll
-            for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
+            if (lt == 0) sh_src_ok[s] = ok_src ? 1 : 0;
             lds_barrier();
+            // (slot streams of Solution B, header mode 3, are decoded by their own kernel)
+            use0 = act0 && sh_src_ok[0] != 0 && (SRC != SRC_SLOTS || (buf[0][0] & 3u) != 3u);
+            use1 = act1 && sh_src_ok[1] != 0 && (SRC != SRC_SLOTS || (buf[1][0] & 3u) != 3u);
+            use = s ? use1 : use0;
+
+            // 2. decode
+            my_hdr = 0;
+            if (SRC != SRC_RAW) {
+                const uint32_t hdr0 = use0 ? buf[0][0] : (uint32_t)M_CONST2;
+                const uint32_t hdr1 = use1 ? buf[1][0] : (uint32_t)M_CONST2;
+                my_hdr = s ? hdr1 : hdr0;
+                const bool any_sparse = (hdr0 & 3u) == M_SPARSE || (hdr1 & 3u) == M_SPARSE;
+                const bool any_ent = ENT && ((hdr0 | hdr1) & kHdrEnt) != 0;
+                uint32_t th[V], tl[V];
+                decode_group<V, WPG, ENT>(b, s ? hdr1 : hdr0, use, any_sparse, C, lt, slA, slB, slC, th, tl, any_ent,
+                                          reinterpret_cast<uint8_t *>(ent));
+                lds_barrier();
+                double x[V];
+#pragma unroll
+                for (int k = 0; k < V; ++k) x[k] = u2d(((uint64_t)th[k] << 32) | tl[k]);
+                // Solution D streams: the values, decoded in stored order, go to their
+                // interleaved positions through LDS (uniform branch over the workgroup)
+                const bool rsh0 = use0 && (hdr0 & kHdrRsh) != 0, rsh1 = use1 && (hdr1 & kHdrRsh) != 0;
+                if (rsh0 || rsh1) {
+                    const bool mine = s ? rsh1 : rsh0;
+#pragma unroll
+                    for (int k = 0; k < V; ++k) vals[vpos(mine ? rsh_pos(first + k, C) : first + k)] = x[k];
+                    lds_barrier();
+#pragma unroll
+                    for (int k = 0; k < V; ++k) x[k] = vals[vpos(first + k)];
+                }
+                if (LIST == 3) {
+                    // 3r. the run: each gate (in registers or through LDS), then the
+                    // truncation re-encoding would apply, none when the chunk holds a
+                    // subnormal value, so that the one encode below equals the last
+                    // of the gate-by-gate encodes.  The first attempt truncates after
+                    // every gate and notes whether a touched value came out
+                    // subnormal; if one did in either slot, both chunks are fetched
+                    // and run again, this time deciding over the whole chunk after
+                    // each gate (a barrier per gate).
+                    const uint64_t base = (c << P.cb) | (uint64_t)(first / 2);
+                    const uint32_t mh = sig_mask_hi(sig_bits(glevel));
+                    bool seen = false;   // a touched value of mine came out subnormal
+                    int ntr = 0;
+                    for (int g = 0; g < io.nrun; ++g) {
+                        const RunRec &rg = sh_rr[g];
+                        // a chunk the gate does not touch skips it and its truncation,
+                        // as it would keep its stream gate by gate
+                        const bool tg0 = use0 && ((tm0 >> g) & 1ull) != 0, tg1 = use1 && ((tm1 >> g) & 1ull) != 0;
+                        const bool tg = s ? tg1 : tg0;
+                        if (gate_in_registers<V>(rg)) {
+                            if (tg) apply_gate_registers<V>(rg, sh_rm[g], x, base);
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
+                            lds_barrier();
+                            apply_gate(rg, sh_rm[g], reinterpret_cast<double *>(buf[0]),
+                                       reinterpret_cast<double *>(buf[1]), cc0, cc1, tg0, tg1, P.cb, WGS);
+                            lds_barrier();
+#pragma unroll
+                            for (int k = 0; k < V; ++k) x[k] = vals[vpos(first + k)];
+                        }
+                        if (glevel > 0 && (tg0 || tg1)) {
+                            bool sub = false;
+#pragma unroll
+                            for (int k = 0; k < V; ++k) sub = sub || is_subnormal(x[k]);
+                            uint32_t gs = 0;
+                            if (careful) {
+                                const bool wsub = __any(tg && sub);
+                                if ((tid & 63) == 0) sh_rsub[ntr & 1][tid >> 6] = wsub ? 1u : 0u;
+                                lds_barrier();
+#pragma unroll
+                                for (int i = 0; i < WPG; ++i) gs |= sh_rsub[ntr & 1][s * WPG + i];
+                                ++ntr;   // flags alternate per truncation step: a barrier separates reuses
+                            } else {
+                                seen = seen || (tg && sub);
+                            }
+                            if (gs == 0 && tg) {
+#pragma unroll
+                                for (int k = 0; k < V; ++k) x[k] = u2d((uint64_t)((uint32_t)(d2u(x[k]) >> 32) & mh) << 32);
+                            }
+                        }
+                    }
+                    if (!careful && glevel > 0) {
+                        // (sh_rsub is next written after the fetch barrier of the
+                        // second attempt or of a later job)
+                        const bool wsub = __any(seen);
+                        if ((tid & 63) == 0) sh_rsub[0][tid >> 6] = wsub ? 1u : 0u;
+                        lds_barrier();
+                        uint32_t any = 0;
+#pragma unroll
+                        for (int i = 0; i < WGS / 64; ++i) any |= sh_rsub[0][i];
+                        if (any != 0) continue;   // (uniform over the workgroup)
+                    }
+                } else if (GATE && gate_in_registers<V>(gd) && use) {
+                    // 3a. a gate each thread applies to its own values (no LDS pass)
+                    apply_gate_registers<V>(gd, sh_m, x, (c << P.cb) | (uint64_t)(first / 2));
+                }
+#pragma unroll
+                for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
+                lds_barrier();
+            }
+            break;
         }
 
         // 3. gate (pairs across threads or slots, in LDS)
@@ -2053,9 +2113,9 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
 // two rounds.  A chunk that no gate of the run touches keeps its stream (or is
 // copied as it is in a sweep).  Bytes equal the gate-by-gate method's.
 // C = 2048 only (V = 16, two wavefronts per chunk); not with the entropy stage.
-__device__ __forceinline__ bool group_gate_touches(const GateDesc &rg, uint64_t c, int cb)
+__device__ __forceinline__ bool group_gate_touches(uint64_t cm, uint64_t c, int cb)
 {
-    return ((c << cb) & rg.cm & ~(((uint64_t)1 << cb) - 1)) == (rg.cm & ~(((uint64_t)1 << cb) - 1));
+    return ((c << cb) & cm & ~(((uint64_t)1 << cb) - 1)) == (cm & ~(((uint64_t)1 << cb) - 1));
 }
 
 template <int V>
@@ -2072,11 +2132,20 @@ __global__ __launch_bounds__(256, 2) void group_kernel(GateDesc gd, DevPtrs P, I
     __shared__ uint64_t sh_acc[8];
     __shared__ double sh_rm[kMaxRun][8];
     __shared__ uint32_t sh_sub[2][4];
+    // the run's gates as the job loop reads them: control mask, and kind |
+    // group index bit of the target << 8 (read from LDS: global reads inside
+    // the job loop would be vector loads, each waited for on its own)
+    __shared__ uint64_t sh_gcm[kMaxRun];
+    __shared__ int32_t sh_gk[kMaxRun];
 
     DevState *ds = P.ds;
     if (ds->stop) return;
     const int tid = threadIdx.x, s = tid / G, lt = tid % G;
     for (int i = tid; i < 8 * io.nrun; i += WGS) sh_rm[i >> 3][i & 7] = io.run[i >> 3].m[i & 7];
+    for (int r = tid; r < io.nrun; r += WGS) {
+        sh_gcm[r] = io.run[r].cm;
+        sh_gk[r] = io.run[r].kind | ((io.run[r].pair_bit == gd.pair_bit ? 1 : 2) << 8);
+    }
     const int C = P.C, cb = P.cb, ca = C / 2;
     const int first = lt * V;
     uint32_t *slA = sh, *slB = sh + 16, *slC = sh + 32, *slE = sh + 48, *slF = sh + 176, *slS = sh + 192;
@@ -2086,7 +2155,7 @@ __global__ __launch_bounds__(256, 2) void group_kernel(GateDesc gd, DevPtrs P, I
     if (lt == 0)
         for (int k = 0; k < 4; ++k) sh_acc[4 * s + k] = 0;
     int ntr = 0;   // truncation steps so far (alternating flag sets)
-    lds_barrier();   // (the run's matrices)
+    lds_barrier();   // (the run's matrices and records)
 
     for (uint64_t job = job_begin(gd) + blockIdx.x; job < job_stop(gd); job += gridDim.x) {
         // the group's chunks and which of them some gate of the run touches
@@ -2097,137 +2166,169 @@ __global__ __launch_bounds__(256, 2) void group_kernel(GateDesc gd, DevPtrs P, I
         for (int g = 0; g < 4; ++g) {
             cg[g] = base | ((g & 1) ? gd.pair_bit : 0ull) | ((g & 2) ? gd.pair_bit2 : 0ull);
             bool t = false;
-            for (int r = 0; r < io.nrun; ++r) t = t || group_gate_touches(io.run[r], cg[g], cb);
+            for (int r = 0; r < io.nrun; ++r) t = t || group_gate_touches(sh_gcm[r], cg[g], cb);
             tg[g] = t;
         }
+        // 1-2. fetch, decode and run; a second attempt when the first one met
+        //      a subnormal value
         uint64_t old_entry[2] = {0, 0};
         bool ok_src_r[2] = {true, true};
-
-        // 1. fetch the four streams (each slot stages two, all loads in flight
-        //    together), then decode them in two rounds
+        for (bool careful = false;; careful = true) {
+            // 1. fetch the four streams (each slot stages two, all loads in flight
+            //    together), then decode them in two rounds
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int gi = 2 * r + s;
-            const uint64_t e = P.table[cg[gi]];
-            old_entry[r] = e;
-            ok_src_r[r] = entry_ok(e, P.arena_words);
-        }
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int gi = 2 * r + s;
-            const uint64_t e = old_entry[r];
-            const uint32_t words = ((uint32_t)(e & 0xFFFFull) + 3u) >> 2;
-            const uint64_t off = e >> 16;
-            if (tg[gi] && ok_src_r[r]) {
-                if ((off & 3ull) == 0) stage_units<G>(buf[gi], P.arena + off, words, lt);
-                else stage_words<G>(buf[gi], P.arena + off, words, lt);
+            for (int r = 0; r < 2; ++r) {
+                const int gi = 2 * r + s;
+                const uint64_t e = P.table[cg[gi]];
+                old_entry[r] = e;
+                ok_src_r[r] = entry_ok(e, P.arena_words);
             }
-            if ((tg[gi] || gd.sweep) && !ok_src_r[r] && lt == 0) atomicExch(&ds->corrupt, 1);
-            if (lt == 0) sh_src_ok[gi] = ok_src_r[r] ? 1 : 0;
-        }
-        lds_barrier();
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int gi = 2 * r + s;
-            uint32_t *b = buf[gi];
-            double *vals = reinterpret_cast<double *>(b);
-            const bool use0 = tg[2 * r] && sh_src_ok[2 * r] != 0, use1 = tg[2 * r + 1] && sh_src_ok[2 * r + 1] != 0;
-            const bool use = s ? use1 : use0;
-            const uint32_t hdr0 = use0 ? buf[2 * r][0] : (uint32_t)M_CONST2;
-            const uint32_t hdr1 = use1 ? buf[2 * r + 1][0] : (uint32_t)M_CONST2;
-            const bool any_sparse = (hdr0 & 3u) == M_SPARSE || (hdr1 & 3u) == M_SPARSE;
-            uint32_t th[V], tl[V];
-            decode_group<V, WPG, false>(b, s ? hdr1 : hdr0, use, any_sparse, C, lt, slA, slB, slC, th, tl);
+            for (int r = 0; r < 2; ++r) {
+                const int gi = 2 * r + s;
+                const uint64_t e = old_entry[r];
+                const uint32_t words = ((uint32_t)(e & 0xFFFFull) + 3u) >> 2;
+                const uint64_t off = e >> 16;
+                if (tg[gi] && ok_src_r[r]) {
+                    if ((off & 3ull) == 0) stage_units<G>(buf[gi], P.arena + off, words, lt);
+                    else stage_words<G>(buf[gi], P.arena + off, words, lt);
+                }
+                if ((tg[gi] || gd.sweep) && !ok_src_r[r] && lt == 0) atomicExch(&ds->corrupt, 1);
+                if (lt == 0) sh_src_ok[gi] = ok_src_r[r] ? 1 : 0;
+            }
             lds_barrier();
-            double x[V];
 #pragma unroll
-            for (int k = 0; k < V; ++k) x[k] = u2d(((uint64_t)th[k] << 32) | tl[k]);
-            const bool rsh0 = use0 && (hdr0 & kHdrRsh) != 0, rsh1 = use1 && (hdr1 & kHdrRsh) != 0;
-            if (rsh0 || rsh1) {
-                const bool mine = s ? rsh1 : rsh0;
-#pragma unroll
-                for (int k = 0; k < V; ++k) vals[vpos(mine ? rsh_pos(first + k, C) : first + k)] = x[k];
+            for (int r = 0; r < 2; ++r) {
+                const int gi = 2 * r + s;
+                uint32_t *b = buf[gi];
+                double *vals = reinterpret_cast<double *>(b);
+                const bool use0 = tg[2 * r] && sh_src_ok[2 * r] != 0, use1 = tg[2 * r + 1] && sh_src_ok[2 * r + 1] != 0;
+                const bool use = s ? use1 : use0;
+                const uint32_t hdr0 = use0 ? buf[2 * r][0] : (uint32_t)M_CONST2;
+                const uint32_t hdr1 = use1 ? buf[2 * r + 1][0] : (uint32_t)M_CONST2;
+                const bool any_sparse = (hdr0 & 3u) == M_SPARSE || (hdr1 & 3u) == M_SPARSE;
+                uint32_t th[V], tl[V];
+                decode_group<V, WPG, false>(b, s ? hdr1 : hdr0, use, any_sparse, C, lt, slA, slB, slC, th, tl);
                 lds_barrier();
+                double x[V];
 #pragma unroll
-                for (int k = 0; k < V; ++k) x[k] = vals[vpos(first + k)];
+                for (int k = 0; k < V; ++k) x[k] = u2d(((uint64_t)th[k] << 32) | tl[k]);
+                const bool rsh0 = use0 && (hdr0 & kHdrRsh) != 0, rsh1 = use1 && (hdr1 & kHdrRsh) != 0;
+                if (rsh0 || rsh1) {
+                    const bool mine = s ? rsh1 : rsh0;
+#pragma unroll
+                    for (int k = 0; k < V; ++k) vals[vpos(mine ? rsh_pos(first + k, C) : first + k)] = x[k];
+                    lds_barrier();
+#pragma unroll
+                    for (int k = 0; k < V; ++k) x[k] = vals[vpos(first + k)];
+                }
+#pragma unroll
+                for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
+                lds_barrier();
             }
-#pragma unroll
-            for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
-            lds_barrier();
-        }
 
-        // 2. the run: each gate on the pairs it joins, then its truncation
-        for (int r = 0; r < io.nrun; ++r) {
-            const GateDesc &rg = io.run[r];
-            const int bitsel = rg.pair_bit == gd.pair_bit ? 1 : 2;   // group index bit of the target
-            const uint32_t cm_lo = (uint32_t)(rg.cm & (uint64_t)(ca - 1));
-            // pair q (0, 1): group indices p0 < p1 differing in bitsel
-            bool pact[2];
-            int pg0[2], pg1[2];
+            // 2. the run: each gate on the pairs it joins, then its truncation,
+            //    none for a chunk holding a subnormal value.  The first attempt
+            //    truncates each value as the gate writes it and notes whether a
+            //    touched value came out subnormal; if one did, the group is
+            //    fetched and run again, deciding over each whole chunk after
+            //    every gate.
+            const bool inline_trunc = !careful && glevel > 0;
+            bool seen = false;   // a value I truncated came out subnormal
+            for (int r = 0; r < io.nrun; ++r) {
+                const uint64_t rcm = sh_gcm[r];
+                const int rkind = sh_gk[r] & 0xFF, bitsel = sh_gk[r] >> 8;   // group index bit of the target
+                const uint32_t cm_lo = (uint32_t)(rcm & (uint64_t)(ca - 1));
+                // pair q (0, 1): group indices p0 < p1 differing in bitsel
+                bool pact[2];
+                int pg0[2], pg1[2];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int other = bitsel == 1 ? 2 : 1;
-                pg0[q] = q ? other : 0;
-                pg1[q] = pg0[q] | bitsel;
-                pact[q] = tg[pg0[q]] && tg[pg1[q]] && sh_src_ok[pg0[q]] && sh_src_ok[pg1[q]] &&
-                          group_gate_touches(rg, cg[pg0[q]], cb);
-            }
-            {
-                const int q = tid >> 7;
-                if (pact[q]) {
-                    double *v0 = reinterpret_cast<double *>(buf[pg0[q]]);
-                    double *v1 = reinterpret_cast<double *>(buf[pg1[q]]);
-                    const double u0r = sh_rm[r][0], u0i = sh_rm[r][1], u1r = sh_rm[r][2], u1i = sh_rm[r][3];
-                    const double u2r = sh_rm[r][4], u2i = sh_rm[r][5], u3r = sh_rm[r][6], u3i = sh_rm[r][7];
-                    for (int k = tid & 127; k < ca; k += 128) {
-                        if (((uint32_t)k & cm_lo) != cm_lo) continue;
-                        const int p = vpos(2 * k);
-                        const double ar = v0[p], ai = v0[p + 1], br = v1[p], bi = v1[p + 1];
-                        if (rg.kind == K_X) {
-                            v0[p] = br; v0[p + 1] = bi; v1[p] = ar; v1[p + 1] = ai;
-                        } else {
-                            double yr, yi, zr, zi;
-                            lin2(u0r, u0i, u1r, u1i, ar, ai, br, bi, yr, yi);
-                            lin2(u2r, u2i, u3r, u3i, ar, ai, br, bi, zr, zi);
-                            v0[p] = yr; v0[p + 1] = yi; v1[p] = zr; v1[p + 1] = zi;
+                for (int q = 0; q < 2; ++q) {
+                    const int other = bitsel == 1 ? 2 : 1;
+                    pg0[q] = q ? other : 0;
+                    pg1[q] = pg0[q] | bitsel;
+                    pact[q] = tg[pg0[q]] && tg[pg1[q]] && sh_src_ok[pg0[q]] && sh_src_ok[pg1[q]] &&
+                              group_gate_touches(rcm, cg[pg0[q]], cb);
+                }
+                {
+                    const int q = tid >> 7;
+                    if (pact[q]) {
+                        double *v0 = reinterpret_cast<double *>(buf[pg0[q]]);
+                        double *v1 = reinterpret_cast<double *>(buf[pg1[q]]);
+                        const double u0r = sh_rm[r][0], u0i = sh_rm[r][1], u1r = sh_rm[r][2], u1i = sh_rm[r][3];
+                        const double u2r = sh_rm[r][4], u2i = sh_rm[r][5], u3r = sh_rm[r][6], u3i = sh_rm[r][7];
+                        for (int k = tid & 127; k < ca; k += 128) {
+                            const bool on = ((uint32_t)k & cm_lo) == cm_lo;
+                            if (!on && !inline_trunc) continue;
+                            const int p = vpos(2 * k);
+                            double ar = v0[p], ai = v0[p + 1], br = v1[p], bi = v1[p + 1];
+                            if (on) {
+                                if (rkind == K_X) {
+                                    const double tr = ar, ti = ai;
+                                    ar = br; ai = bi; br = tr; bi = ti;
+                                } else {
+                                    double yr, yi, zr, zi;
+                                    lin2(u0r, u0i, u1r, u1i, ar, ai, br, bi, yr, yi);
+                                    lin2(u2r, u2i, u3r, u3i, ar, ai, br, bi, zr, zi);
+                                    ar = yr; ai = yi; br = zr; bi = zi;
+                                }
+                            }
+                            if (inline_trunc) {
+                                seen = seen || is_subnormal(ar) || is_subnormal(ai) || is_subnormal(br) || is_subnormal(bi);
+                                ar = u2d((uint64_t)((uint32_t)(d2u(ar) >> 32) & mh) << 32);
+                                ai = u2d((uint64_t)((uint32_t)(d2u(ai) >> 32) & mh) << 32);
+                                br = u2d((uint64_t)((uint32_t)(d2u(br) >> 32) & mh) << 32);
+                                bi = u2d((uint64_t)((uint32_t)(d2u(bi) >> 32) & mh) << 32);
+                            }
+                            v0[p] = ar; v0[p + 1] = ai; v1[p] = br; v1[p + 1] = bi;
                         }
                     }
                 }
-            }
-            lds_barrier();
-            if (glevel > 0 && (pact[0] || pact[1])) {
-                // per touched chunk: a subnormal value anywhere keeps it untruncated
-                uint32_t *flags = sh_sub[ntr & 1];
-                if (tid < 4) flags[tid] = 0u;
                 lds_barrier();
+                if (careful && glevel > 0 && (pact[0] || pact[1])) {
+                    // per touched chunk: a subnormal value anywhere keeps it untruncated
+                    uint32_t *flags = sh_sub[ntr & 1];
+                    if (tid < 4) flags[tid] = 0u;
+                    lds_barrier();
 #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const bool touched = (pact[0] && (g == pg0[0] || g == pg1[0])) ||
-                                         (pact[1] && (g == pg0[1] || g == pg1[1]));
-                    if (!touched) continue;
-                    const double *v = reinterpret_cast<const double *>(buf[g]);
-                    bool sub = false;
-                    for (int i = tid; i < C; i += WGS) {
-                        const uint64_t u = d2u(v[vpos(i)]);
-                        sub = sub || subnormal((uint32_t)(u >> 32), (uint32_t)u);
+                    for (int g = 0; g < 4; ++g) {
+                        const bool touched = (pact[0] && (g == pg0[0] || g == pg1[0])) ||
+                                             (pact[1] && (g == pg0[1] || g == pg1[1]));
+                        if (!touched) continue;
+                        const double *v = reinterpret_cast<const double *>(buf[g]);
+                        bool sub = false;
+                        for (int i = tid; i < C; i += WGS) {
+                            const uint64_t u = d2u(v[vpos(i)]);
+                            sub = sub || subnormal((uint32_t)(u >> 32), (uint32_t)u);
+                        }
+                        if (__any(sub) && (tid & 63) == 0) atomicOr(&flags[g], 1u);
                     }
-                    if (__any(sub) && (tid & 63) == 0) atomicOr(&flags[g], 1u);
-                }
-                lds_barrier();
+                    lds_barrier();
 #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const bool touched = (pact[0] && (g == pg0[0] || g == pg1[0])) ||
-                                         (pact[1] && (g == pg0[1] || g == pg1[1]));
-                    if (!touched || flags[g]) continue;
-                    double *v = reinterpret_cast<double *>(buf[g]);
-                    for (int i = tid; i < C; i += WGS) {
-                        const int p = vpos(i);
-                        v[p] = u2d((uint64_t)((uint32_t)(d2u(v[p]) >> 32) & mh) << 32);
+                    for (int g = 0; g < 4; ++g) {
+                        const bool touched = (pact[0] && (g == pg0[0] || g == pg1[0])) ||
+                                             (pact[1] && (g == pg0[1] || g == pg1[1]));
+                        if (!touched || flags[g]) continue;
+                        double *v = reinterpret_cast<double *>(buf[g]);
+                        for (int i = tid; i < C; i += WGS) {
+                            const int p = vpos(i);
+                            v[p] = u2d((uint64_t)((uint32_t)(d2u(v[p]) >> 32) & mh) << 32);
+                        }
                     }
+                    ++ntr;
+                    lds_barrier();
                 }
-                ++ntr;
-                lds_barrier();
             }
+            if (inline_trunc) {
+                // (sh_sub is next written after the fetch barrier of the second
+                // attempt or of a later job)
+                const bool wsub = __any(seen);
+                if ((tid & 63) == 0) sh_sub[0][tid >> 6] = wsub ? 1u : 0u;
+                lds_barrier();
+                const uint32_t any = sh_sub[0][0] | sh_sub[0][1] | sh_sub[0][2] | sh_sub[0][3];
+                if (any != 0) continue;   // (uniform over the workgroup)
+            }
+            break;
         }
 
         // 3. two rounds of encode, claim and copy-out

@@ -252,3 +252,48 @@ def test_chunk_group_run_stopped_midway_restores_every_chunk():
     assert g.stats()["stops"] >= 1
     assert_same_chunks(g, o, "after the rolled-back run")
     assert g.footprint()["compressed_bytes"] == live
+
+
+def subnormal_runs(n):
+    """Gates that drive some values of a chunk into the subnormal range in
+    the middle of a run and bring them back later in the same run: a diagonal
+    phase of magnitude 2^-1020 on an in-chunk qubit (every chunk, and with a
+    control on a chunk-index qubit only half of them), then its inverse; a
+    chunk-pair gate whose first row is scaled by 2^-1020, then a Hadamard on
+    the same chunk-index qubit that mixes the small values with normal ones.
+    Gate by gate, a chunk holding a subnormal value is stored lossless, so a
+    run must decide per gate whether to truncate."""
+    import numpy as np
+    tiny, huge = 2.0 ** -1020, 2.0 ** 1020
+    hi = list(range(10, n))
+    shrink = np.array([[tiny, tiny], [1.0, -1.0]]) / np.sqrt(2)
+    layer = cc.concat([cc.rz(0, 0.3), cc.diag1(4, 1.0, tiny), cc.rz(1, 0.5), cc.rx(2, 0.2), cc.rx(5, 0.4),
+                       cc.diag1(4, 1.0, huge), cc.rz(3, 0.1), cc.rx(6, 0.3),
+                       cc.diag1(3, 1.0, tiny, controls=(hi[1],)), cc.rx(7, 0.6), cc.diag1(3, 1.0, huge, controls=(hi[1],)),
+                       cc.h(hi[0]), cc.h(hi[1]), cc.u1(hi[0], shrink), cc.rx(hi[1], 0.3), cc.h(hi[0]), cc.h(hi[1]),
+                       cc.u1(hi[1], shrink, controls=(2,)), cc.h(hi[1]), cc.rx(hi[0], 0.5)])
+    return cc.concat([cc.grover_prefix(n), cc.random_unitary_gates(n, 8, 71), layer, cc.random_unitary_gates(n, 8, 72),
+                      layer])
+
+
+@pytest.mark.parametrize("level", [1, 3])
+@pytest.mark.parametrize("groups", [False, True])
+def test_runs_with_subnormal_values_midway(level, groups):
+    """Fused runs and chunk-group runs in which values turn subnormal and back
+    within the run: the bytes after every batch are the oracle's (which
+    re-encodes gate by gate and leaves such chunks untruncated)."""
+    from paper_1911_04034_amd import qcz
+    n, bl = 13, 10
+    gates = subnormal_runs(n)
+    flags = qcz.FLAG_FUSE | (qcz.FLAG_GROUPS if groups else 0)
+    g, o = make(n, bl, oq.MODE_FIXED, level, batch=64, flags=flags)
+    say("runs with subnormal values level=%d groups=%d (%d gates)" % (level, groups, len(gates)))
+    for k in range(0, len(gates), 20):
+        part = gates[k:k + 20]
+        assert g.apply(part) == len(part) and o.apply(part) == len(part)
+        assert_same_chunks(g, o, "after gate %d" % (k + len(part) - 1))
+    fg, fo = g.footprint(), o.footprint()
+    assert fg["lossy_steps"] == fo["lossy_steps"]
+    assert fg["compressed_bytes"] == fo["compressed_bytes"]
+    if groups:
+        assert g.stats()["kind_bytes"][2] > 0   # chunk-group runs formed
