@@ -1325,6 +1325,7 @@ __device__ void apply_gate(const D &gd, const double *m, double *v0, double *v1,
 // A fused run's gate as the run loop reads it, copied to LDS once per launch:
 // the kernel writes global memory, so reads of the run's records there inside
 // the job loop would be vector loads, each waited for on its own.
+static_assert(kMaxRun <= 64, "a run's touch masks are wavefront ballots: one lane per gate");
 struct RunRec {
     uint64_t cm;                     // control mask over amplitude-index bits
     uint64_t fixed_mask, fixed_val;  // chunk-index bits held fixed by the gate's enumeration
@@ -1347,6 +1348,30 @@ __device__ __forceinline__ RunRec run_rec(const GateDesc &d)
     r.unit = 0;
     for (int i = 0; i < 4; ++i) r.unit |= unit_phase(d.m[2 * i], d.m[2 * i + 1]) ? (1u << i) : 0u;
     return r;
+}
+
+// wave-uniform values read from LDS: held in scalar registers, so that tests
+// and branches on them are scalar instructions instead of per-lane masks
+__device__ __forceinline__ uint32_t uni32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int32_t uni32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v)
+{
+    return ((uint64_t)uni32((uint32_t)(v >> 32)) << 32) | uni32((uint32_t)v);
+}
+
+__device__ __forceinline__ RunRec uniform_rec(const RunRec &r)
+{
+    RunRec u;
+    u.cm = uni64(r.cm);
+    u.fixed_mask = uni64(r.fixed_mask);
+    u.fixed_val = uni64(r.fixed_val);
+    u.kind = uni32(r.kind);
+    u.q = uni32(r.q);
+    u.q2 = uni32(r.q2);
+    u.job_type = uni32(r.job_type);
+    u.check_phase = uni32(r.check_phase);
+    u.unit = uni32(r.unit);
+    return u;
 }
 
 // whether gate rg of a fused run re-encodes chunk c: the chunk is in its
@@ -1563,11 +1588,13 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
         bool act1 = job_slot<SRC, GATE>(gd, unit_mask, io, P.cb, item1, cc1);
         uint64_t tm0 = 0, tm1 = 0;   // fused run: bit g set when gate g touches the slot's chunk
         if (LIST == 3) {
-            // a fused run enumerates every chunk; it re-encodes those some gate touches
-            for (int g = 0; g < io.nrun; ++g) {
-                tm0 |= run_touches(sh_rr[g], cc0, P.cb) ? (1ull << g) : 0ull;
-                tm1 |= run_touches(sh_rr[g], cc1, P.cb) ? (1ull << g) : 0ull;
-            }
+            // a fused run enumerates every chunk; it re-encodes those some gate
+            // touches.  Lane g of every wavefront tests gate g (at most 64 gates
+            // per run), and the ballots give each wavefront both masks.
+            const int ln = tid & 63;
+            const bool in_run = ln < io.nrun;
+            tm0 = __ballot(in_run && run_touches(sh_rr[in_run ? ln : 0], cc0, P.cb));
+            tm1 = __ballot(in_run && run_touches(sh_rr[in_run ? ln : 0], cc1, P.cb));
             act0 = act0 && tm0 != 0;
             act1 = act1 && tm1 != 0;
         }
@@ -1652,7 +1679,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                     bool seen = false;   // a touched value of mine came out subnormal
                     int ntr = 0;
                     for (int g = 0; g < io.nrun; ++g) {
-                        const RunRec &rg = sh_rr[g];
+                        const RunRec rg = uniform_rec(sh_rr[g]);
                         // a chunk the gate does not touch skips it and its truncation,
                         // as it would keep its stream gate by gate
                         const bool tg0 = use0 && ((tm0 >> g) & 1ull) != 0, tg1 = use1 && ((tm1 >> g) & 1ull) != 0;
@@ -2162,12 +2189,14 @@ __global__ __launch_bounds__(256, 2) void group_kernel(GateDesc gd, DevPtrs P, I
         uint64_t cg[4];
         bool tg[4];
         const uint64_t base = deposit(gd, job);
+        // (lane r of every wavefront tests gate r: at most 64 gates per run)
+        const int ln = tid & 63;
+        const bool in_run = ln < io.nrun;
+        const uint64_t lcm = sh_gcm[in_run ? ln : 0];
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             cg[g] = base | ((g & 1) ? gd.pair_bit : 0ull) | ((g & 2) ? gd.pair_bit2 : 0ull);
-            bool t = false;
-            for (int r = 0; r < io.nrun; ++r) t = t || group_gate_touches(sh_gcm[r], cg[g], cb);
-            tg[g] = t;
+            tg[g] = __ballot(in_run && group_gate_touches(lcm, cg[g], cb)) != 0;
         }
         // 1-2. fetch, decode and run; a second attempt when the first one met
         //      a subnormal value
@@ -2236,8 +2265,9 @@ __global__ __launch_bounds__(256, 2) void group_kernel(GateDesc gd, DevPtrs P, I
             const bool inline_trunc = !careful && glevel > 0;
             bool seen = false;   // a value I truncated came out subnormal
             for (int r = 0; r < io.nrun; ++r) {
-                const uint64_t rcm = sh_gcm[r];
-                const int rkind = sh_gk[r] & 0xFF, bitsel = sh_gk[r] >> 8;   // group index bit of the target
+                const uint64_t rcm = uni64(sh_gcm[r]);
+                const int32_t rk = uni32(sh_gk[r]);
+                const int rkind = rk & 0xFF, bitsel = rk >> 8;   // group index bit of the target
                 const uint32_t cm_lo = (uint32_t)(rcm & (uint64_t)(ca - 1));
                 // pair q (0, 1): group indices p0 < p1 differing in bitsel
                 bool pact[2];

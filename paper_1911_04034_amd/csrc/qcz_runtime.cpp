@@ -376,21 +376,6 @@ uint64_t stripe_share(const qcz_state *s, const GateDesc &d)
     return (items * per * groups + g - 1) / g;
 }
 
-// Number of leading gates of `descs` whose expected allocations fit in the
-// room the fullest stripe has left.
-size_t gates_that_fit(const qcz_state *s, const std::vector<GateDesc> &descs)
-{
-    const uint64_t fill = max_stripe_fill(s);
-    const uint64_t room = s->stripe_size > fill ? s->stripe_size - fill : 0;
-    uint64_t acc = 0;
-    size_t k = 0;
-    for (; k < descs.size(); ++k) {
-        acc += stripe_share(s, descs[k]);
-        if (acc > room) break;
-    }
-    return k;
-}
-
 // gates that run through the block cache: fused jobs over a whole gate at a
 // global level (per-block levels keep their own ledger per chunk)
 bool cache_gate(const qcz_state *s, const GateDesc &d)
@@ -520,6 +505,31 @@ int group_grid(const qcz_state *s, const GateDesc &d)
 {
     const int g = std::max(1, s->grid_max * 2 / 3);
     return (int)std::max<uint64_t>(1, std::min<uint64_t>(d.njobs, (uint64_t)g));
+}
+
+// Number of leading gates of `descs` whose expected allocations fit in the
+// room the fullest stripe has left.  Gates that the batch launches as one
+// fused or chunk-group run allocate once per chunk for the whole run, so a
+// run is counted once; a run that does not fit ends the count before it.
+size_t gates_that_fit(const qcz_state *s, const std::vector<GateDesc> &descs)
+{
+    const uint64_t fill = max_stripe_fill(s);
+    const uint64_t room = s->stripe_size > fill ? s->stripe_size - fill : 0;
+    uint64_t acc = 0;
+    size_t k = 0;
+    while (k < descs.size()) {
+        GateDesc launch;
+        int kind = 0;
+        size_t r = run_at(s, descs.data(), descs.size(), k, launch, kind);
+        if (kind == 0) {
+            r = 1;
+            launch = descs[k];
+        }
+        acc += stripe_share(s, launch);
+        if (acc > room) break;
+        k += r;
+    }
+    return k;
 }
 
 qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)

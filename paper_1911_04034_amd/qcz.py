@@ -87,10 +87,16 @@ _lib = None
 
 
 def load():
-    """Load libqcz.so (built in-tree by __graft_entry__.build())."""
+    """Load libqcz.so (built in-tree by __graft_entry__.build()).
+
+    torch is imported first: torch brings its own HIP runtime, and libqcz.so
+    must bind to that same runtime (loaded first, the system one would be a
+    second runtime in the process, with which torch's device memory and
+    streams cannot be used)."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401  (see above)
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libqcz.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
     L = ctypes.CDLL(LIB_PATH)
