@@ -1608,6 +1608,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
         uint64_t old_entry = 0;
         bool ok_src = true, use0 = false, use1 = false, use = false;
         uint32_t my_hdr = 0;
+        bool verified = false;   // a fused run's truncation steps found no subnormal value
         for (bool careful = false;; careful = true) {
             // 1. fetch
             old_entry = 0;
@@ -1727,6 +1728,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
 #pragma unroll
                         for (int i = 0; i < WGS / 64; ++i) any |= sh_rsub[0][i];
                         if (any != 0) continue;   // (uniform over the workgroup)
+                        verified = true;
                     }
                 } else if (GATE && gate_in_registers<V>(gd) && use) {
                     // 3a. a gate each thread applies to its own values (no LDS pass)
@@ -1870,13 +1872,17 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             else if (gd.per_block) lev_req = P.block_level[c >> gd.block_shift];
             else lev_req = glevel;
             const bool enc = use;
-            // subnormal flag of the group (wave ballots meet in LDS)
-            const bool wsub = __any(enc && sub);
-            if ((tid & 63) == 0) slS[tid >> 6] = wsub ? 1u : 0u;
-            lds_barrier();
+            // subnormal flag of the group (wave ballots meet in LDS); not needed
+            // at level 0, nor after a fused run whose truncation steps tested
+            // every touched chunk and found none (uniform over the workgroup)
             uint32_t gs = 0;
+            if (!verified && !(gd.fixed_level < 0 && !gd.per_block && glevel == 0)) {
+                const bool wsub = __any(enc && sub);
+                if ((tid & 63) == 0) slS[tid >> 6] = wsub ? 1u : 0u;
+                lds_barrier();
 #pragma unroll
-            for (int i = 0; i < WPG; ++i) gs |= slS[s * WPG + i];
+                for (int i = 0; i < WPG; ++i) gs |= slS[s * WPG + i];
+            }
             const bool gsub = gs != 0;
             // Sec. 3.8 per chunk (per-block levels): delta(level) * |v|^2 before
             // truncation, and the squared norm the truncation removes
@@ -2145,12 +2151,15 @@ __device__ __forceinline__ bool group_gate_touches(uint64_t cm, uint64_t c, int 
     return ((c << cb) & cm & ~(((uint64_t)1 << cb) - 1)) == (cm & ~(((uint64_t)1 << cb) - 1));
 }
 
+// V values per thread: a chunk slot is kCMax / V threads, the workgroup two slots
 template <int V>
-__global__ __launch_bounds__(256, 2) void group_kernel(GateDesc gd, DevPtrs P, IOPtrs io)
+__global__ __launch_bounds__(2 * kCMax / V, 2) void group_kernel(GateDesc gd, DevPtrs P, IOPtrs io)
 {
-    constexpr int WPG = 2;
-    constexpr int G = 64 * WPG;
+    constexpr int G = kCMax / V;       // threads per chunk slot
+    constexpr int WPG = G / 64;        // wavefronts per slot
     constexpr int WGS = 2 * G;
+    constexpr int NW = WGS / 64;       // wavefronts per workgroup
+    static_assert(NW >= 4, "sh_sub also holds one flag per chunk of the group");
     __shared__ __align__(16) uint32_t buf[4][kBufWords];
     __shared__ uint32_t sh[256];
     __shared__ uint64_t sh_off[2];
@@ -2158,7 +2167,7 @@ __global__ __launch_bounds__(256, 2) void group_kernel(GateDesc gd, DevPtrs P, I
     __shared__ int sh_src_ok[4];
     __shared__ uint64_t sh_acc[8];
     __shared__ double sh_rm[kMaxRun][8];
-    __shared__ uint32_t sh_sub[2][4];
+    __shared__ uint32_t sh_sub[2][NW];
     // the run's gates as the job loop reads them: control mask, and kind |
     // group index bit of the target << 8 (read from LDS: global reads inside
     // the job loop would be vector loads, each waited for on its own)
@@ -2202,6 +2211,7 @@ __global__ __launch_bounds__(256, 2) void group_kernel(GateDesc gd, DevPtrs P, I
         //      a subnormal value
         uint64_t old_entry[2] = {0, 0};
         bool ok_src_r[2] = {true, true};
+        bool verified = false;   // the run's truncation steps found no subnormal value
         for (bool careful = false;; careful = true) {
             // 1. fetch the four streams (each slot stages two, all loads in flight
             //    together), then decode them in two rounds
@@ -2281,13 +2291,13 @@ __global__ __launch_bounds__(256, 2) void group_kernel(GateDesc gd, DevPtrs P, I
                               group_gate_touches(rcm, cg[pg0[q]], cb);
                 }
                 {
-                    const int q = tid >> 7;
+                    const int q = tid / G;   // the slot's threads take pair q
                     if (pact[q]) {
                         double *v0 = reinterpret_cast<double *>(buf[pg0[q]]);
                         double *v1 = reinterpret_cast<double *>(buf[pg1[q]]);
                         const double u0r = sh_rm[r][0], u0i = sh_rm[r][1], u1r = sh_rm[r][2], u1i = sh_rm[r][3];
                         const double u2r = sh_rm[r][4], u2i = sh_rm[r][5], u3r = sh_rm[r][6], u3i = sh_rm[r][7];
-                        for (int k = tid & 127; k < ca; k += 128) {
+                        for (int k = tid % G; k < ca; k += G) {
                             const bool on = ((uint32_t)k & cm_lo) == cm_lo;
                             if (!on && !inline_trunc) continue;
                             const int p = vpos(2 * k);
@@ -2355,8 +2365,11 @@ __global__ __launch_bounds__(256, 2) void group_kernel(GateDesc gd, DevPtrs P, I
                 const bool wsub = __any(seen);
                 if ((tid & 63) == 0) sh_sub[0][tid >> 6] = wsub ? 1u : 0u;
                 lds_barrier();
-                const uint32_t any = sh_sub[0][0] | sh_sub[0][1] | sh_sub[0][2] | sh_sub[0][3];
+                uint32_t any = 0;
+#pragma unroll
+                for (int i = 0; i < NW; ++i) any |= sh_sub[0][i];
                 if (any != 0) continue;   // (uniform over the workgroup)
+                verified = true;
             }
             break;
         }
@@ -2384,12 +2397,16 @@ __global__ __launch_bounds__(256, 2) void group_kernel(GateDesc gd, DevPtrs P, I
             const uint32_t xprev_hi =
                 lt ? (uint32_t)(d2u(vals[vpos(rsh ? rsh_pos(first - 1, C) : first - 1)]) >> 32) : 0u;
             const uint64_t x0 = d2u(vals[0]), x1 = d2u(vals[1]);
-            const bool wsub = __any(use && sub);
-            if ((tid & 63) == 0) slS[tid >> 6] = wsub ? 1u : 0u;
-            lds_barrier();
+            // subnormal flag of the chunk: not needed at level 0, nor when the
+            // run's truncation steps tested every touched chunk and found none
             uint32_t gs = 0;
+            if (!verified && glevel > 0) {
+                const bool wsub = __any(use && sub);
+                if ((tid & 63) == 0) slS[tid >> 6] = wsub ? 1u : 0u;
+                lds_barrier();
 #pragma unroll
-            for (int i = 0; i < WPG; ++i) gs |= slS[s * WPG + i];
+                for (int i = 0; i < WPG; ++i) gs |= slS[s * WPG + i];
+            }
             EncPlan<V> e;
             encode_plan<V, WPG, false>(xh, xl, xprev_hi, x0, x1, glevel, gs != 0, C, lt, slE, slF, e, false, nullptr,
                                        nullptr, nullptr, rsh);
