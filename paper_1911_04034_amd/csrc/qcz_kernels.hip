@@ -1487,6 +1487,17 @@ __device__ __forceinline__ void apply_gate_registers(const D &gd, const double *
     }
 }
 
+// A diagonal gate without controls whose phase is the same for all of a
+// thread's amplitudes (its qubits above the thread's low index bits): in a
+// fused run such gates take a loop of their own (see the job kernel).
+template <int V>
+__device__ __forceinline__ bool thread_phase_diag(const RunRec &rg)
+{
+    constexpr int LB = RegSplit<V>::LB;
+    return (V & 1) == 0 && V >= 2 && rg.job_type == J_SINGLE && (rg.kind == K_DIAG1 || rg.kind == K_DIAG2) &&
+           rg.cm == 0 && rg.q >= LB && (rg.kind == K_DIAG1 || rg.q2 >= LB);
+}
+
 // ---------------------------------------------------------------------------
 // the job kernel
 // ---------------------------------------------------------------------------
@@ -1537,10 +1548,13 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
 
     const int tid = threadIdx.x, s = tid / G, lt = tid % G;
     if (GATE && tid < 8) sh_m[tid] = gd.m[tid];   // first read after the first job's fetch barrier
+    uint64_t fastm = 0;   // fused run: bit g set when gate g has one phase per thread (thread_phase_diag)
     if (LIST == 3) {
         for (int i = tid; i < 8 * io.nrun; i += WGS) sh_rm[i >> 3][i & 7] = io.run[i >> 3].m[i & 7];
         for (int g = tid; g < io.nrun; g += WGS) sh_rr[g] = run_rec(io.run[g]);
         lds_barrier();   // the records are read before the first job's fetch barrier
+        const int ln = tid & 63;
+        fastm = __ballot(ln < io.nrun && thread_phase_diag<V>(sh_rr[ln < io.nrun ? ln : 0]));
     }
     uint32_t unit_mask = 0;                        // phases equal to 1 (diagonal gates)
     if (GATE)
@@ -1679,7 +1693,41 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                     const uint32_t mh = sig_mask_hi(sig_bits(glevel));
                     bool seen = false;   // a touched value of mine came out subnormal
                     int ntr = 0;
-                    for (int g = 0; g < io.nrun; ++g) {
+                    // (a wavefront lies in one slot: its slot's mask and chunk state are wave-uniform)
+                    const uint64_t tm_w = uni64(s ? tm1 : tm0);
+                    const bool use_w = uni32((uint32_t)(s ? use1 : use0)) != 0;
+                    for (int g = 0; g < io.nrun;) {
+                        if (!careful && glevel > 0 && ((fastm >> g) & 1ull) != 0) {
+                            // consecutive diagonal gates with one phase per thread: the
+                            // ones that touch my chunk, each with the update, the
+                            // subnormal test and the truncation in one pass over my
+                            // values (a loop of their own, without per-gate branches)
+                            const uint64_t rest = ~(fastm >> g);
+                            const int e = rest != 0 ? g + __builtin_ctzll(rest) : 64;   // end of the segment
+                            const uint64_t seg = e - g >= 64 ? ~0ull : ((1ull << (e - g)) - 1ull);
+                            uint64_t todo = use_w ? (tm_w >> g) & seg : 0ull;
+                            const uint64_t m64 = (uint64_t)mh << 32;   // the truncation as one mask
+                            while (todo != 0) {
+                                const int k = g + __builtin_ctzll(todo);
+                                todo &= todo - 1ull;
+                                const RunRec rk = uniform_rec(sh_rr[k]);
+                                uint32_t ihi = (uint32_t)(base >> rk.q) & 1u;
+                                if (rk.kind == K_DIAG2) ihi |= ((uint32_t)(base >> rk.q2) & 1u) << 1;
+                                double pr, pi;
+                                phase_of(sh_rm[k], (int)ihi, pr, pi);
+#pragma unroll
+                                for (int a = 0; a < V / 2; ++a) {
+                                    double yr, yi;
+                                    dmul(pr, pi, x[2 * a], x[2 * a + 1], yr, yi);
+                                    seen |= is_subnormal(yr);
+                                    seen |= is_subnormal(yi);
+                                    x[2 * a] = u2d(d2u(yr) & m64);
+                                    x[2 * a + 1] = u2d(d2u(yi) & m64);
+                                }
+                            }
+                            g = e;
+                            continue;
+                        }
                         const RunRec rg = uniform_rec(sh_rr[g]);
                         // a chunk the gate does not touch skips it and its truncation,
                         // as it would keep its stream gate by gate
@@ -1717,6 +1765,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                                 for (int k = 0; k < V; ++k) x[k] = u2d((uint64_t)((uint32_t)(d2u(x[k]) >> 32) & mh) << 32);
                             }
                         }
+                        ++g;
                     }
                     if (!careful && glevel > 0) {
                         // (sh_rsub is next written after the fetch barrier of the
