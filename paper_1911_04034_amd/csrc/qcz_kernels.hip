@@ -312,6 +312,47 @@ constexpr uint32_t kHdrEnt = 0x20u;
 // position rsh_pos(j)
 constexpr uint32_t kHdrRsh = 0x40u;
 __device__ __forceinline__ int rsh_pos(int j, int C) { return j < C / 2 ? 2 * j : 2 * (j - C / 2) + 1; }
+
+// The LDS copy of a chunk holds its values interleaved at vpos(i).  A thread's
+// values in stored order (Solution D's when rsh) as (hi, lo) words, and whether
+// one is subnormal; the two orders are separate loops (a uniform branch), so
+// that the plain one reads at fixed offsets from the thread's first value.
+template <int V>
+__device__ __forceinline__ void load_stored(const double *vals, int first, int C, bool rsh, uint32_t (&xh)[V],
+                                            uint32_t (&xl)[V], bool &sub)
+{
+    if (rsh) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const uint64_t x = (uint64_t)__double_as_longlong(vals[vpos(rsh_pos(first + k, C))]);
+            xh[k] = (uint32_t)(x >> 32);
+            xl[k] = (uint32_t)x;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const uint64_t x = (uint64_t)__double_as_longlong(vals[vpos(first + k)]);
+            xh[k] = (uint32_t)(x >> 32);
+            xl[k] = (uint32_t)x;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < V; ++k) sub = sub || subnormal(xh[k], xl[k]);
+}
+
+// Values decoded in Solution D's stored order move to their interleaved
+// positions (mine), or stay (plain streams), through the LDS copy.
+template <int V>
+__device__ __forceinline__ void store_interleaved(double *vals, int first, int C, bool mine, const double (&x)[V])
+{
+    if (mine) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) vals[vpos(rsh_pos(first + k, C))] = x[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
+    }
+}
 constexpr int kEntMaxLen = 8;
 constexpr int kEntSlotWords = 1024;   // per slot: decode tables (16 lanes x 256 bytes) or encode tables
 enum { LANE_RAW = 0, LANE_CONST = 1, LANE_CODED = 2 };
@@ -1674,8 +1715,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                 const bool rsh0 = use0 && (hdr0 & kHdrRsh) != 0, rsh1 = use1 && (hdr1 & kHdrRsh) != 0;
                 if (rsh0 || rsh1) {
                     const bool mine = s ? rsh1 : rsh0;
-#pragma unroll
-                    for (int k = 0; k < V; ++k) vals[vpos(mine ? rsh_pos(first + k, C) : first + k)] = x[k];
+                    store_interleaved<V>(vals, first, C, mine, x);
                     lds_barrier();
 #pragma unroll
                     for (int k = 0; k < V; ++k) x[k] = vals[vpos(first + k)];
@@ -1876,13 +1916,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             uint32_t xh[V], xl[V];
             bool sub = false;
             const bool rsh = gd.reshuffle != 0;   // values in Solution D's stored order
-#pragma unroll
-            for (int k = 0; k < V; ++k) {
-                const uint64_t x = d2u(vals[vpos(rsh ? rsh_pos(first + k, C) : first + k)]);
-                xh[k] = (uint32_t)(x >> 32);
-                xl[k] = (uint32_t)x;
-                sub = sub || subnormal(xh[k], xl[k]);
-            }
+            load_stored<V>(vals, first, C, rsh, xh, xl, sub);
             const uint32_t xprev_hi =
                 lt ? (uint32_t)(d2u(vals[vpos(rsh ? rsh_pos(first - 1, C) : first - 1)]) >> 32) : 0u;
             const uint64_t x0 = d2u(vals[0]), x1 = d2u(vals[1]);
@@ -1906,13 +1940,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
             uint32_t xh[V], xl[V];
             bool sub = false;
             const bool rsh = gd.reshuffle != 0;   // values in Solution D's stored order
-#pragma unroll
-            for (int k = 0; k < V; ++k) {
-                const uint64_t x = d2u(vals[vpos(rsh ? rsh_pos(first + k, C) : first + k)]);
-                xh[k] = (uint32_t)(x >> 32);
-                xl[k] = (uint32_t)x;
-                sub = sub || subnormal(xh[k], xl[k]);
-            }
+            load_stored<V>(vals, first, C, rsh, xh, xl, sub);
             const uint32_t xprev_hi =
                 lt ? (uint32_t)(d2u(vals[vpos(rsh ? rsh_pos(first - 1, C) : first - 1)]) >> 32) : 0u;
             const uint64_t x0 = d2u(vals[0]), x1 = d2u(vals[1]);
