@@ -622,6 +622,49 @@ __device__ __forceinline__ int codes_word0(int mode, int C) { return mode == M_S
 // `hdr` is the stream header (an inactive slot passes a CONST2 header and
 // active = false); `any_sparse` and `any_ent` (a slot holds an entropy-coded
 // stream) are workgroup-uniform; etab is the slot's decode-table area.
+// The residual fields of a thread's values (K < 64), from bit ob of the
+// residual area bw: rd marks the values whose fields are read (stored and
+// inside the buffer); each value gets its K-bit prefix bits below the shared
+// leading bytes, and cbytes / cmin collect the carry-out of the leading-byte
+// scan.  ALL: every value is read (a PACK stream), without per-value tests.
+template <int V, bool ALL>
+__device__ __forceinline__ void unpack_residuals(const uint32_t *bw, uint32_t ob, uint32_t rd, uint32_t stored,
+                                                 uint32_t Lpos, uint32_t rtab, uint32_t up, uint32_t (&th)[V],
+                                                 uint32_t (&tl)[V], uint32_t &cbytes, uint32_t &cmin)
+{
+    // four values at a time: their word pairs are read before any is used,
+    // so one LDS round trip serves four values
+    constexpr int U = V < 4 ? V : 4;
+#pragma unroll
+    for (int k0 = 0; k0 < V; k0 += U) {
+        uint32_t lo[U], hi[U], sh[U], rr[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int k = k0 + j;
+            const uint32_t L = (Lpos >> (2 * k)) & 3u;
+            rr[j] = (ALL || ((rd >> k) & 1u)) ? __builtin_amdgcn_ubfe(rtab, 8u * L, 8u) : 0u;
+            const uint32_t wi = ob >> 5;
+            lo[j] = bw[wi];
+            hi[j] = bw[wi + 1];
+            sh[j] = ob & 31u;
+            ob += rr[j];
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int k = k0 + j;
+            const uint32_t L = (Lpos >> (2 * k)) & 3u;
+            // lossy levels keep at most 29 bits, so rr < 32
+            const uint32_t p = (fshr(hi[j], lo[j], sh[j]) & ((1u << rr[j]) - 1u)) << up;
+            th[k] = p;
+            tl[k] = 0u;
+            const uint32_t Ls = (ALL || ((stored >> k) & 1u)) ? L : 3u;
+            const uint32_t own = (~0u >> (8u * Ls)) & 0xFFFFFF00u;
+            cbytes = (own & p) | (~own & cbytes);
+            cmin = Ls < cmin ? Ls : cmin;
+        }
+    }
+}
+
 template <int V, int WPG, bool ENT = false>
 __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool any_sparse, int C, int lt,
                              uint32_t *slotA, uint32_t *slotB, uint32_t *slotC, uint32_t (&th)[V], uint32_t (&tl)[V],
@@ -740,40 +783,11 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
         // stream keeps them inside the buffer, a corrupt one reads empty fields
         const bool fits = res_w0 + (int)((o + rsum) >> 5) <= kBufWords - 2;
         const uint32_t rd = fits ? stored : 0u;
-        uint32_t ob = fits ? o : 0u;
-        const uint32_t *bw = b + res_w0;
-        // four values at a time: their word pairs are read before any is used,
-        // so one LDS round trip serves four values
-        constexpr int U = V < 4 ? V : 4;
-#pragma unroll
-        for (int k0 = 0; k0 < V; k0 += U) {
-            uint32_t lo[U], hi[U], sh[U], rr[U];
-#pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int k = k0 + j;
-                const uint32_t L = (Lpos >> (2 * k)) & 3u;
-                rr[j] = ((rd >> k) & 1u) ? __builtin_amdgcn_ubfe(rtab, 8u * L, 8u) : 0u;
-                const uint32_t wi = ob >> 5;
-                lo[j] = bw[wi];
-                hi[j] = bw[wi + 1];
-                sh[j] = ob & 31u;
-                ob += rr[j];
-            }
-#pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int k = k0 + j;
-                const uint32_t st = (stored >> k) & 1u;
-                const uint32_t L = (Lpos >> (2 * k)) & 3u;
-                // lossy levels keep at most 29 bits, so rr < 32
-                const uint32_t p = (fshr(hi[j], lo[j], sh[j]) & ((1u << rr[j]) - 1u)) << up;
-                th[k] = p;
-                tl[k] = 0u;
-                const uint32_t Ls = st ? L : 3u;
-                const uint32_t own = (~0u >> (8u * Ls)) & 0xFFFFFF00u;
-                cbytes = (own & p) | (~own & cbytes);
-                cmin = Ls < cmin ? Ls : cmin;
-            }
-        }
+        const uint32_t ob = fits ? o : 0u;
+        if (rd == vmask)   // every value stored and inside the buffer (PACK)
+            unpack_residuals<V, true>(b + res_w0, ob, rd, stored, Lpos, rtab, up, th, tl, cbytes, cmin);
+        else
+            unpack_residuals<V, false>(b + res_w0, ob, rd, stored, Lpos, rtab, up, th, tl, cbytes, cmin);
     } else {
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -1041,24 +1055,25 @@ __device__ __forceinline__ void or_bits64(uint32_t *b, int base, uint32_t o, uin
 }
 
 // residual field of a value: the low r bits of its K-bit significant prefix
-template <int V>
+// (SPARSE a template argument: the PACK instance tests nothing per value)
+template <int V, bool SPARSE>
 __device__ __forceinline__ void emit_residuals(uint32_t *b, int base, uint32_t o, const EncPlan<V> &e,
-                                               uint32_t mask, uint32_t codes, bool sparse)
+                                               uint32_t mask, uint32_t codes)
 {
+    constexpr bool sparse = SPARSE;
     const int K = e.K;
     uint32_t j2 = 0;   // two bits per code of the values emitted so far (SPARSE: rank order)
     if (K < 64) {
         // a thread's fields are contiguous: assemble them in a 64-bit
-        // accumulator and write whole words; only the first word (shared with
-        // the thread before) and the last partial one (shared with the thread
-        // after) need an atomic OR
+        // accumulator and OR each word into the zeroed stream as it fills (the
+        // first word is shared with the thread before, the last partial one
+        // with the thread after; the others are mine alone)
         // (the planned size bounds every word index: no clamping)
         const uint32_t rtab = resid_bits(K, 0) | (resid_bits(K, 1) << 8) | (resid_bits(K, 2) << 16) |
                               (resid_bits(K, 3) << 24);
         uint64_t acc = 0;
         uint32_t nb = o & 31u;
         int wi = base + (int)(o >> 5);
-        bool first = true;
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             const bool on = ((mask >> k) & 1u) != 0;
@@ -1068,9 +1083,7 @@ __device__ __forceinline__ void emit_residuals(uint32_t *b, int base, uint32_t o
             acc |= (uint64_t)__builtin_amdgcn_ubfe(e.th[k], (uint32_t)(32 - K), r) << nb;   // r bits from bit 32 - K
             nb += r;
             if (nb >= 32u) {
-                if (first) atomicOr(&b[wi], (uint32_t)acc);
-                else b[wi] = (uint32_t)acc;
-                first = false;
+                atomicOr(&b[wi], (uint32_t)acc);
                 ++wi;
                 acc >>= 32;
                 nb -= 32u;
@@ -1178,7 +1191,7 @@ __device__ void encode_emit(uint32_t *b, const EncPlan<V> &e, int C, int lt, con
         if (V == 16) b[1 + (bit >> 5)] = e.codes;
         else atomicOr(&b[1 + (bit >> 5)], e.codes << (bit & 31));
         if (e.ent) ent_emit<V>(b, e, C, lt, 1 + C / 16, ent);
-        else emit_residuals<V>(b, 1 + C / 16, e.pack_off, e, vmask, e.codes, false);
+        else emit_residuals<V, false>(b, 1 + C / 16, e.pack_off, e, vmask, e.codes);
     } else {  // M_SPARSE
         if (e.nzm) atomicOr(&b[1 + (first >> 5)], e.nzm << (first & 31));
         const int cw0 = 1 + ((C + 31) >> 5);
@@ -1191,7 +1204,7 @@ __device__ void encode_emit(uint32_t *b, const EncPlan<V> &e, int C, int lt, con
             if ((uint32_t)(v >> 32)) atomicOr(&b[clampw(wi + 1)], (uint32_t)(v >> 32));
         }
         if (e.ent) ent_emit<V>(b, e, C, lt, cw0 + (int)((e.nnz + 15u) >> 4), ent);
-        else emit_residuals<V>(b, cw0 + (int)((e.nnz + 15u) >> 4), e.sp_off, e, e.nzm, e.scodes, true);
+        else emit_residuals<V, true>(b, cw0 + (int)((e.nnz + 15u) >> 4), e.sp_off, e, e.nzm, e.scodes);
     }
 }
 
