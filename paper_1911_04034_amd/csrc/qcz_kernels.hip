@@ -820,6 +820,14 @@ __device__ void decode_group(const uint32_t *b, uint32_t hdr, bool active, bool 
             th[k] = odd ? c1h : c0h;
             tl[k] = odd ? c1l : c0l;
         }
+    } else if (stored == vmask) {
+        // every value stored (PACK): each one is the previous value for the next
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const uint32_t mine = ~0u >> (8u * ((Lpos >> (2 * k)) & 3u));
+            prev = (mine & th[k]) | (~mine & prev);
+            th[k] = prev;
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -959,15 +967,21 @@ __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], ui
 
     uint32_t badbits = 0, nzm = 0, codes = 0, lf = 0, lv = 0;
     uint32_t prev = xprev_hi & mh;
+    // CONST2 test: value k of mine is compared with value 0 (a real part) or
+    // value 1 (an imaginary part).  Interleaved, that follows the parity of its
+    // position; in Solution D's order a thread's values all lie in one half, so
+    // both references are that half's
+    const uint32_t half_h = first >= C / 2 ? e.c1h : e.c0h, half_l = first >= C / 2 ? e.c1l : e.c0l;
+    const uint32_t re_h = rsh ? half_h : e.c0h, re_l = rsh ? half_l : e.c0l;
+    const uint32_t im_h = rsh ? half_h : e.c1h, im_l = rsh ? half_l : e.c1l;
 #pragma unroll
     for (int k = 0; k < V; ++k) {
         const uint32_t h = xh[k] & mh;
         const uint32_t l = lossless ? xl[k] : 0u;
         e.th[k] = h;
         e.tl[k] = l;
-        // im part of its amplitude (values in stored order: interleaved, or Solution D's)
-        const bool odd = rsh ? (first + k) >= C / 2 : ((first + k) & 1) != 0;
-        badbits |= (h ^ (odd ? e.c1h : e.c0h)) | (l ^ (odd ? e.c1l : e.c0l));   // differs from value 0 / 1
+        const bool odd = ((first + k) & 1) != 0;
+        badbits |= (h ^ (odd ? im_h : re_h)) | (l ^ (odd ? im_l : re_l));   // differs from value 0 / 1
         const uint32_t L = lead_bytes(h, prev);
         codes |= L << (2 * k);
         prev = h;
