@@ -9,7 +9,7 @@ amplitude blocks (chunks of 1024 amplitudes), error bound 1e-5 on every gate,
 warmup + steps windows of consecutive gates; a step is one window.  Inputs
 (gate list, compressed state) are in HBM before timing.  Gates whose jobs
 lie inside single chunks run fused (one pass per run), chunk-pair gates on
-two chunk-index qubits run as one pass over groups of four chunks, a gate
+up to three chunk-index qubits run as one pass over groups of eight chunks, a gate
 that does not fit beside the live streams sweeps into the other arena, and
 the windows are cut at the boundaries of those passes.  Other workloads:
 grover24+qft24 (the 24-qubit pair), grid30, grover34.
@@ -190,7 +190,9 @@ def large_config(args, torch, cc, qcz):
         win = -(-len(gates) // passes)
         windows = [gates[k:k + win] for k in range(0, len(gates), win)]
     else:
-        windows = pass_windows(gates, min(bl, 10), passes, not args.no_groups and not args.entropy)
+        cb = min(bl, 10)
+        windows = pass_windows(gates, cb, passes, not args.no_groups and not args.entropy,
+                               group_bits=3 if n - cb >= 3 else 2)
     win = max(len(w) for w in windows)
     st = qcz.State(n, bl, mode=mode, level=level, budget=budget, pool_bytes=pool, flags=flags, batch=128)
     trace = [st.footprint()["compressed_bytes"]]
@@ -236,7 +238,7 @@ def large_config(args, torch, cc, qcz):
     kinds = {0: ("job_kernel", "job_kernel<16, 2, ARENA, ARENA, gate%s>: one gate per pass" % suffix.replace("_", ", ")),
              1: ("run_kernel", "job_kernel<16, 2, ARENA, ARENA, gate, run%s>: a fused run of single-chunk gates per pass"
                  % suffix.replace("_", ", ")),
-             2: ("group_kernel", "group_kernel<16>: a run of chunk-pair gates on two chunk-index qubits per pass")}
+             2: ("group_kernel", "group_kernel<16, NB>: a run of chunk-pair gates on up to three chunk-index qubits per pass")}
     per = []
     for i, (tag, name) in kinds.items():
         L, ms, B = stats["kind_launches"][i], stats["kind_kernel_ms"][i], stats["kind_bytes"][i]
@@ -304,12 +306,13 @@ def large_config(args, torch, cc, qcz):
     print(json.dumps(line), flush=True)
 
 
-def pass_windows(gates, cb, nwin, groups, max_run=64):
+def pass_windows(gates, cb, nwin, groups, max_run=64, group_bits=3):
     """Cut the gate list into nwin consecutive windows at the boundaries of
     the passes the library forms with fused runs (gates whose jobs lie inside
     single chunks: one pass per run of up to 64; chunk-pair gates: one pass
-    each, or per run on at most two target qubits with chunk-group runs), so
-    that no step splits a pass; windows hold near-equal numbers of passes."""
+    each, or per run on at most group_bits target qubits with chunk-group
+    runs), so that no step splits a pass; windows hold near-equal numbers of
+    passes."""
     U1, DIAG1, DIAG2, X, MCZ = 0, 1, 2, 3, 4
     lo = (1 << cb) - 1
     passes, cur, kind, bits = [], [], None, set()
@@ -323,7 +326,7 @@ def pass_windows(gates, cb, nwin, groups, max_run=64):
         else:
             c = "pair"
         joins = (c == kind and len(cur) < max_run and
-                 (c == "single" or (c == "pair" and groups and len(bits | {t}) <= 2)))
+                 (c == "single" or (c == "pair" and groups and len(bits | {t}) <= group_bits)))
         if not joins and cur:
             passes.append(cur)
             cur, bits = [], set()

@@ -103,13 +103,14 @@ typedef enum {
                                block_log2 >= 10 (2048-double chunks) and two wavefronts per chunk; not with
                                QCZ_FLAG_CACHE or QCZ_FLAG_AUTOTUNE. */
 #define QCZ_FLAG_GROUPS 512u /* with QCZ_FLAG_FUSE: consecutive U1 / X gates whose targets are chunk-index qubits
-                               (chunk-pair jobs, any controls) on at most two distinct target bits run as one
-                               pass over groups of the four chunks those bits join (up to 64 gates): each chunk
-                               decoded and encoded once, each gate followed by the truncation its re-encoding
-                               would apply to the chunks it touched.  Same bytes and ledger as gate by gate.
-                               2048-double chunks, not with QCZ_FLAG_ENTROPY.  The pass holds four chunks in
-                               LDS (two workgroups per CU instead of three), so it pays where pair passes
-                               dominate and the state is small; measure before enabling. */
+                               (chunk-pair jobs, any controls) on at most three distinct target bits (two when
+                               the state has only two chunk-index bits) run as one pass over groups of the
+                               eight (four) chunks those bits join (up to 64 gates): each chunk decoded and
+                               encoded once, each gate followed by the truncation its re-encoding would apply
+                               to the chunks it touched.  Same bytes and ledger as gate by gate.  2048-double
+                               chunks, not with QCZ_FLAG_ENTROPY.  The pass holds its chunks in LDS (one or two
+                               workgroups per CU instead of three), so it pays where pair passes dominate;
+                               measure before enabling. */
 #define QCZ_FLAG_RESHUFFLE 256u /* Solution D (Sec. 4.2): PACK and SPARSE chunks store their values re parts
                                first, then im parts (header bit 6), before the Solution C steps; decoded
                                values are those of the run without it.  Chunks created by qcz_create are

@@ -49,11 +49,15 @@ struct GateDesc {
                                     // control bits its plain enumeration would have held fixed)
     int32_t reshuffle;              // the encoder stores PACK / SPARSE values re parts first (header bit 6)
     int32_t pad_;
-    uint64_t pair_bit2;             // GROUP: the second chunk-index bit of the four-chunk groups
+    uint64_t pair_bit2;             // GROUP: the second chunk-index bit of the groups
+    uint64_t pair_bit3;             // GROUP: the third chunk-index bit (eight-chunk groups), or 0
 };
 
 // the jobs one launch of a gate runs, and the enumerated chunk positions per job
-__host__ __device__ inline uint64_t items_per_job(const GateDesc &d) { return d.job_type == J_GROUP ? 4 : 2; }
+__host__ __device__ inline uint64_t items_per_job(const GateDesc &d)
+{
+    return d.job_type == J_GROUP ? (d.pair_bit3 ? 8 : 4) : 2;
+}
 __host__ __device__ inline uint64_t job_begin(const GateDesc &d) { return d.job_end ? d.job0 : 0; }
 __host__ __device__ inline uint64_t job_stop(const GateDesc &d) { return d.job_end ? d.job_end : d.njobs; }
 

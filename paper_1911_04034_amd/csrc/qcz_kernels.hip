@@ -999,17 +999,23 @@ __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], ui
     const uint32_t RP = tot[1], NNZ = tot[2];
     e.nnz = NNZ;
     // SPARSE can only win when the chunk has zeros; with none its body equals
-    // PACK's plus the bitmap.  The decision must be uniform over the workgroup.
+    // PACK's plus the bitmap.  The decision must be uniform over the workgroup:
+    // the scan runs when any slot (WPG wavefronts each) needs it.
     const int w = threadIdx.x >> 6;
-    const int og0 = (w < WPG) ? WPG : 0;   // first wavefront of the other slot's group
-    uint32_t other_bad = 0, other_nnz = 0;
+    const int g0 = w - (w % WPG);   // my slot's first wavefront
+    const int nw = (int)(blockDim.x >> 6);
+    bool need_other = false;
+    for (int o0 = 0; o0 < nw; o0 += WPG) {
+        if (o0 == g0) continue;
+        uint32_t other_bad = 0, other_nnz = 0;
 #pragma unroll
-    for (int i = 0; i < WPG; ++i) {
-        other_bad += slotB[8 * (og0 + i)];
-        other_nnz += slotB[8 * (og0 + i) + 2];
+        for (int i = 0; i < WPG; ++i) {
+            other_bad += slotB[8 * (o0 + i)];
+            other_nnz += slotB[8 * (o0 + i) + 2];
+        }
+        need_other = need_other || (other_bad != 0 && other_nnz < (uint32_t)C);
     }
     const bool need_me = !const2 && NNZ < (uint32_t)C;
-    const bool need_other = other_bad != 0 && other_nnz < (uint32_t)C;
     uint32_t RS = 0;
     e.scodes = 0;
     e.sp_off = 0;
@@ -1286,8 +1292,9 @@ __device__ __forceinline__ uint64_t deposit(const GateDesc &gd, uint64_t k)
 __device__ __forceinline__ uint64_t item_chunk(const GateDesc &gd, uint64_t item)
 {
     if (gd.job_type == J_GROUP) {
-        uint64_t c = deposit(gd, item >> 2);
-        return c | ((item & 1ull) ? gd.pair_bit : 0ull) | ((item & 2ull) ? gd.pair_bit2 : 0ull);
+        uint64_t c = deposit(gd, item >> (gd.pair_bit3 ? 3 : 2));
+        return c | ((item & 1ull) ? gd.pair_bit : 0ull) | ((item & 2ull) ? gd.pair_bit2 : 0ull) |
+               ((gd.pair_bit3 && (item & 4ull)) ? gd.pair_bit3 : 0ull);
     }
     if (gd.job_type == J_PAIR) {
         uint64_t c = deposit(gd, item >> 1);
@@ -2255,21 +2262,25 @@ __device__ __forceinline__ bool group_gate_touches(uint64_t cm, uint64_t c, int 
     return ((c << cb) & cm & ~(((uint64_t)1 << cb) - 1)) == (cm & ~(((uint64_t)1 << cb) - 1));
 }
 
-// V values per thread: a chunk slot is kCMax / V threads, the workgroup two slots
-template <int V>
-__global__ __launch_bounds__(2 * kCMax / V, 2) void group_kernel(GateDesc gd, DevPtrs P, IOPtrs io)
+// V values per thread: a chunk slot is kCMax / V threads.  NB chunk-index bits
+// per group (2 or 3): 2^NB chunks, 2^(NB-1) slots, each slot taking two of them.
+template <int V, int NB>
+__global__ __launch_bounds__((1 << (NB - 1)) * kCMax / V, NB == 2 ? 2 : 1) void group_kernel(GateDesc gd, DevPtrs P,
+                                                                                             IOPtrs io)
 {
+    constexpr int NG = 1 << NB;        // chunks per group
+    constexpr int NS = NG / 2;         // slots
     constexpr int G = kCMax / V;       // threads per chunk slot
     constexpr int WPG = G / 64;        // wavefronts per slot
-    constexpr int WGS = 2 * G;
+    constexpr int WGS = NS * G;
     constexpr int NW = WGS / 64;       // wavefronts per workgroup
-    static_assert(NW >= 4, "sh_sub also holds one flag per chunk of the group");
-    __shared__ __align__(16) uint32_t buf[4][kBufWords];
+    static_assert(NW >= NG, "sh_sub also holds one flag per chunk of the group");
+    __shared__ __align__(16) uint32_t buf[NG][kBufWords];
     __shared__ uint32_t sh[256];
-    __shared__ uint64_t sh_off[2];
-    __shared__ int sh_ok[2];
-    __shared__ int sh_src_ok[4];
-    __shared__ uint64_t sh_acc[8];
+    __shared__ uint64_t sh_off[NS];
+    __shared__ int sh_ok[NS];
+    __shared__ int sh_src_ok[NG];
+    __shared__ uint64_t sh_acc[4 * NS];
     __shared__ double sh_rm[kMaxRun][8];
     __shared__ uint32_t sh_sub[2][NW];
     // the run's gates as the job loop reads them: control mask, and kind |
@@ -2284,7 +2295,8 @@ __global__ __launch_bounds__(2 * kCMax / V, 2) void group_kernel(GateDesc gd, De
     for (int i = tid; i < 8 * io.nrun; i += WGS) sh_rm[i >> 3][i & 7] = io.run[i >> 3].m[i & 7];
     for (int r = tid; r < io.nrun; r += WGS) {
         sh_gcm[r] = io.run[r].cm;
-        sh_gk[r] = io.run[r].kind | ((io.run[r].pair_bit == gd.pair_bit ? 1 : 2) << 8);
+        const uint64_t pb = io.run[r].pair_bit;
+        sh_gk[r] = io.run[r].kind | ((pb == gd.pair_bit ? 1 : pb == gd.pair_bit2 ? 2 : 4) << 8);
     }
     const int C = P.C, cb = P.cb, ca = C / 2;
     const int first = lt * V;
@@ -2299,16 +2311,17 @@ __global__ __launch_bounds__(2 * kCMax / V, 2) void group_kernel(GateDesc gd, De
 
     for (uint64_t job = job_begin(gd) + blockIdx.x; job < job_stop(gd); job += gridDim.x) {
         // the group's chunks and which of them some gate of the run touches
-        uint64_t cg[4];
-        bool tg[4];
+        uint64_t cg[NG];
+        bool tg[NG];
         const uint64_t base = deposit(gd, job);
         // (lane r of every wavefront tests gate r: at most 64 gates per run)
         const int ln = tid & 63;
         const bool in_run = ln < io.nrun;
         const uint64_t lcm = sh_gcm[in_run ? ln : 0];
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            cg[g] = base | ((g & 1) ? gd.pair_bit : 0ull) | ((g & 2) ? gd.pair_bit2 : 0ull);
+        for (int g = 0; g < NG; ++g) {
+            cg[g] = base | ((g & 1) ? gd.pair_bit : 0ull) | ((g & 2) ? gd.pair_bit2 : 0ull) |
+                    ((g & 4) ? gd.pair_bit3 : 0ull);
             tg[g] = __ballot(in_run && group_gate_touches(lcm, cg[g], cb)) != 0;
         }
         // 1-2. fetch, decode and run; a second attempt when the first one met
@@ -2317,18 +2330,18 @@ __global__ __launch_bounds__(2 * kCMax / V, 2) void group_kernel(GateDesc gd, De
         bool ok_src_r[2] = {true, true};
         bool verified = false;   // the run's truncation steps found no subnormal value
         for (bool careful = false;; careful = true) {
-            // 1. fetch the four streams (each slot stages two, all loads in flight
-            //    together), then decode them in two rounds
+            // 1. fetch the group's streams (each slot stages two, all loads in
+            //    flight together), then decode them in two rounds
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                const int gi = 2 * r + s;
+                const int gi = NS * r + s;
                 const uint64_t e = P.table[cg[gi]];
                 old_entry[r] = e;
                 ok_src_r[r] = entry_ok(e, P.arena_words);
             }
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                const int gi = 2 * r + s;
+                const int gi = NS * r + s;
                 const uint64_t e = old_entry[r];
                 const uint32_t words = ((uint32_t)(e & 0xFFFFull) + 3u) >> 2;
                 const uint64_t off = e >> 16;
@@ -2342,23 +2355,33 @@ __global__ __launch_bounds__(2 * kCMax / V, 2) void group_kernel(GateDesc gd, De
             lds_barrier();
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                const int gi = 2 * r + s;
+                const int gi = NS * r + s;
                 uint32_t *b = buf[gi];
                 double *vals = reinterpret_cast<double *>(b);
-                const bool use0 = tg[2 * r] && sh_src_ok[2 * r] != 0, use1 = tg[2 * r + 1] && sh_src_ok[2 * r + 1] != 0;
-                const bool use = s ? use1 : use0;
-                const uint32_t hdr0 = use0 ? buf[2 * r][0] : (uint32_t)M_CONST2;
-                const uint32_t hdr1 = use1 ? buf[2 * r + 1][0] : (uint32_t)M_CONST2;
-                const bool any_sparse = (hdr0 & 3u) == M_SPARSE || (hdr1 & 3u) == M_SPARSE;
+                // the round's streams: mine, and whether any slot holds a SPARSE
+                // or a Solution D stream (branches with barriers: uniform)
+                bool use = false, any_sparse = false, any_rsh = false;
+                uint32_t my_hdr = (uint32_t)M_CONST2;
+#pragma unroll
+                for (int j = 0; j < NS; ++j) {
+                    const int gj = NS * r + j;
+                    const bool uj = tg[gj] && sh_src_ok[gj] != 0;
+                    const uint32_t hj = uj ? buf[gj][0] : (uint32_t)M_CONST2;
+                    any_sparse = any_sparse || (hj & 3u) == M_SPARSE;
+                    any_rsh = any_rsh || (uj && (hj & kHdrRsh) != 0);
+                    if (j == s) {
+                        use = uj;
+                        my_hdr = hj;
+                    }
+                }
                 uint32_t th[V], tl[V];
-                decode_group<V, WPG, false>(b, s ? hdr1 : hdr0, use, any_sparse, C, lt, slA, slB, slC, th, tl);
+                decode_group<V, WPG, false>(b, my_hdr, use, any_sparse, C, lt, slA, slB, slC, th, tl);
                 lds_barrier();
                 double x[V];
 #pragma unroll
                 for (int k = 0; k < V; ++k) x[k] = u2d(((uint64_t)th[k] << 32) | tl[k]);
-                const bool rsh0 = use0 && (hdr0 & kHdrRsh) != 0, rsh1 = use1 && (hdr1 & kHdrRsh) != 0;
-                if (rsh0 || rsh1) {
-                    const bool mine = s ? rsh1 : rsh0;
+                if (any_rsh) {
+                    const bool mine = use && (my_hdr & kHdrRsh) != 0;
 #pragma unroll
                     for (int k = 0; k < V; ++k) vals[vpos(mine ? rsh_pos(first + k, C) : first + k)] = x[k];
                     lds_barrier();
@@ -2383,16 +2406,19 @@ __global__ __launch_bounds__(2 * kCMax / V, 2) void group_kernel(GateDesc gd, De
                 const int32_t rk = uni32(sh_gk[r]);
                 const int rkind = rk & 0xFF, bitsel = rk >> 8;   // group index bit of the target
                 const uint32_t cm_lo = (uint32_t)(rcm & (uint64_t)(ca - 1));
-                // pair q (0, 1): group indices p0 < p1 differing in bitsel
-                bool pact[2];
-                int pg0[2], pg1[2];
+                // pair q (0 .. NS-1): group indices p0 < p1 differing in bitsel,
+                // p0 the q-th index with that bit clear
+                const int bpos = bitsel == 1 ? 0 : bitsel == 2 ? 1 : 2;
+                bool pact[NS];
+                int pg0[NS], pg1[NS];
+                bool any_pact = false;
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const int other = bitsel == 1 ? 2 : 1;
-                    pg0[q] = q ? other : 0;
+                for (int q = 0; q < NS; ++q) {
+                    pg0[q] = ((q >> bpos) << (bpos + 1)) | (q & (bitsel - 1));
                     pg1[q] = pg0[q] | bitsel;
                     pact[q] = tg[pg0[q]] && tg[pg1[q]] && sh_src_ok[pg0[q]] && sh_src_ok[pg1[q]] &&
                               group_gate_touches(rcm, cg[pg0[q]], cb);
+                    any_pact = any_pact || pact[q];
                 }
                 {
                     const int q = tid / G;   // the slot's threads take pair q
@@ -2429,15 +2455,16 @@ __global__ __launch_bounds__(2 * kCMax / V, 2) void group_kernel(GateDesc gd, De
                     }
                 }
                 lds_barrier();
-                if (careful && glevel > 0 && (pact[0] || pact[1])) {
+                if (careful && glevel > 0 && any_pact) {
                     // per touched chunk: a subnormal value anywhere keeps it untruncated
                     uint32_t *flags = sh_sub[ntr & 1];
-                    if (tid < 4) flags[tid] = 0u;
+                    if (tid < NG) flags[tid] = 0u;
                     lds_barrier();
 #pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        const bool touched = (pact[0] && (g == pg0[0] || g == pg1[0])) ||
-                                             (pact[1] && (g == pg0[1] || g == pg1[1]));
+                    for (int g = 0; g < NG; ++g) {
+                        bool touched = false;
+#pragma unroll
+                        for (int q = 0; q < NS; ++q) touched = touched || (pact[q] && (g == pg0[q] || g == pg1[q]));
                         if (!touched) continue;
                         const double *v = reinterpret_cast<const double *>(buf[g]);
                         bool sub = false;
@@ -2449,9 +2476,10 @@ __global__ __launch_bounds__(2 * kCMax / V, 2) void group_kernel(GateDesc gd, De
                     }
                     lds_barrier();
 #pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        const bool touched = (pact[0] && (g == pg0[0] || g == pg1[0])) ||
-                                             (pact[1] && (g == pg0[1] || g == pg1[1]));
+                    for (int g = 0; g < NG; ++g) {
+                        bool touched = false;
+#pragma unroll
+                        for (int q = 0; q < NS; ++q) touched = touched || (pact[q] && (g == pg0[q] || g == pg1[q]));
                         if (!touched || flags[g]) continue;
                         double *v = reinterpret_cast<double *>(buf[g]);
                         for (int i = tid; i < C; i += WGS) {
@@ -2481,11 +2509,11 @@ __global__ __launch_bounds__(2 * kCMax / V, 2) void group_kernel(GateDesc gd, De
         // 3. two rounds of encode, claim and copy-out
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-            const int gi = 2 * r + s;
+            const int gi = NS * r + s;
             uint32_t *b = buf[gi];
             const double *vals = reinterpret_cast<const double *>(b);
             const uint64_t c = cg[gi];
-            const uint64_t item = 4 * job + (uint64_t)gi;
+            const uint64_t item = (uint64_t)NG * job + (uint64_t)gi;
             const bool use = tg[gi] && sh_src_ok[gi] != 0;
             const bool carry = gd.sweep && !tg[gi] && ok_src_r[r];
             uint32_t xh[V], xl[V];
@@ -2569,10 +2597,13 @@ __global__ __launch_bounds__(2 * kCMax / V, 2) void group_kernel(GateDesc gd, De
     // per-workgroup totals; the last workgroup closes the run
     if (tid == 0) {
         WgPart wp;
-        wp.delta = sh_acc[0] + sh_acc[4];
-        wp.reenc = sh_acc[1] + sh_acc[5];
-        wp.rd = sh_acc[2] + sh_acc[6];
-        wp.wr = sh_acc[3] + sh_acc[7];
+        wp.delta = wp.reenc = wp.rd = wp.wr = 0;
+        for (int j = 0; j < NS; ++j) {
+            wp.delta += sh_acc[4 * j];
+            wp.reenc += sh_acc[4 * j + 1];
+            wp.rd += sh_acc[4 * j + 2];
+            wp.wr += sh_acc[4 * j + 3];
+        }
         wp.wd = 0.0;
         wp.lost = 0.0;
         wp.hits = 0;
@@ -3137,10 +3168,18 @@ hipError_t launch_group_run(const GateDesc &gd, const DevPtrs &P, const GateDesc
     IOPtrs io = {};
     io.run = run;
     io.nrun = nrun;
-    if (t0)
-        hipExtLaunchKernelGGL(group_kernel<16>, dim3(grid), dim3(256), 0, st, t0, t1, 0, gd, P, io);
-    else
-        hipLaunchKernelGGL(group_kernel<16>, dim3(grid), dim3(256), 0, st, gd, P, io);
+    // two chunk-index bits: 256 threads, two workgroups per CU; three: 512, one
+    if (gd.pair_bit3) {
+        if (t0)
+            hipExtLaunchKernelGGL((group_kernel<16, 3>), dim3(grid), dim3(512), 0, st, t0, t1, 0, gd, P, io);
+        else
+            hipLaunchKernelGGL((group_kernel<16, 3>), dim3(grid), dim3(512), 0, st, gd, P, io);
+    } else {
+        if (t0)
+            hipExtLaunchKernelGGL((group_kernel<16, 2>), dim3(grid), dim3(256), 0, st, t0, t1, 0, gd, P, io);
+        else
+            hipLaunchKernelGGL((group_kernel<16, 2>), dim3(grid), dim3(256), 0, st, gd, P, io);
+    }
     return hipGetLastError();
 }
 

@@ -473,37 +473,46 @@ size_t run_at(const qcz_state *s, const GateDesc *descs, size_t n, size_t k, Gat
         launch = run_launch(s, descs[k]);
         return r;
     }
-    uint64_t b1 = 0, b2 = 0;
+    // target bits of the run: up to three distinct ones (eight-chunk groups)
+    // when the state has that many chunk-index bits, else two
+    const int maxbits = (s->n - s->cb) >= 3 ? 3 : 2;
+    uint64_t bits[3] = {0, 0, 0};
+    int nb = 0;
     r = 0;
     while (k + r < n && r < (size_t)kMaxRun && pairable(s, descs[k + r])) {
         const uint64_t pb = descs[k + r].pair_bit;
-        if (b1 == 0) b1 = pb;
-        else if (pb != b1 && b2 == 0) b2 = pb;
-        else if (pb != b1 && pb != b2) break;
+        bool known = false;
+        for (int i = 0; i < nb; ++i) known = known || bits[i] == pb;
+        if (!known) {
+            if (nb == maxbits) break;
+            bits[nb++] = pb;
+        }
         ++r;
     }
     if (r < 2) return 0;
-    if (b2 == 0)   // one target bit: the lowest other chunk-index bit completes the groups
+    if (nb == 1)   // one target bit: the lowest other chunk-index bit completes the groups
         for (int bit = 0; bit < s->n - s->cb; ++bit)
-            if ((1ull << bit) != b1) { b2 = 1ull << bit; break; }
+            if ((1ull << bit) != bits[0]) { bits[nb++] = 1ull << bit; break; }
     kind = 2;
     launch = descs[k];
     launch.job_type = J_GROUP;
-    launch.pair_bit = b1;
-    launch.pair_bit2 = b2;
-    launch.fixed_mask = b1 | b2;
+    launch.pair_bit = bits[0];
+    launch.pair_bit2 = bits[1];
+    launch.pair_bit3 = nb == 3 ? bits[2] : 0;
+    launch.fixed_mask = bits[0] | bits[1] | launch.pair_bit3;
     launch.fixed_val = 0;
     launch.check_phase = 0;
     launch.act_mask = launch.act_val = 0;
     launch.nitems = s->nchunks;
-    launch.njobs = s->nchunks / 4;
+    launch.njobs = s->nchunks / items_per_job(launch);
     return r;
 }
 
-// chunk-group workgroups hold four chunks (two per CU fit its LDS): one resident round
+// chunk-group workgroups: four chunks (two workgroups per CU fit its LDS) or
+// eight (one per CU); one resident round
 int group_grid(const qcz_state *s, const GateDesc &d)
 {
-    const int g = std::max(1, s->grid_max * 2 / 3);
+    const int g = std::max(1, d.pair_bit3 ? s->grid_max / 3 : s->grid_max * 2 / 3);
     return (int)std::max<uint64_t>(1, std::min<uint64_t>(d.njobs, (uint64_t)g));
 }
 

@@ -10,7 +10,8 @@ Usage:
 
 <kernel> picks the dispatches by name: "plain" (job_kernel<16, 2, 0, 0, true, 0, false>: one gate per pass,
 the default), "entropy" (the same with the entropy stage), "run" (job_kernel<16, 2, 0, 0, true, 3, false>: a
-fused run of single-chunk gates) or "group" (group_kernel<16>: a chunk-group run).  The traffic summary scales the per-dispatch FETCH_SIZE /
+fused run of single-chunk gates), "group" (group_kernel<16, 3>: a chunk-group run over eight chunks) or
+"group4" (group_kernel<16, 2>: over four chunks).  The traffic summary scales the per-dispatch FETCH_SIZE /
 WRITE_SIZE of the kernel by the bytes per counter unit that the same counters read for a plain device copy;
 every summary records the hash of the device code it was taken with.
 """
@@ -25,7 +26,7 @@ import sys
 from paper_1911_04034_amd.profile_summary import kernel_hash
 
 KERNELS = {"plain": "job_kernel<16, 2, 0, 0, true, 0, false>", "entropy": "job_kernel<16, 2, 0, 0, true, 0, true>",
-           "run": "job_kernel<16, 2, 0, 0, true, 3, false>", "group": "group_kernel<16>"}
+           "run": "job_kernel<16, 2, 0, 0, true, 3, false>", "group": "group_kernel<16, 3>", "group4": "group_kernel<16, 2>"}
 
 
 def _counter_rows(d):
@@ -96,7 +97,7 @@ SQ = ["SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES", "SQ_INSTS_LDS", "SQ_INSTS_SALU", 
       "SQ_WAVES", "SQ_WAVE_CYCLES"]
 
 
-WAVES_PER_SIMD = {"group": 2}   # resident waves per SIMD (two workgroups of four waves per CU); others three
+WAVES_PER_SIMD = {"group": 2, "group4": 2}   # resident waves per SIMD (eight waves per CU); others three
 
 
 def counters(command, kernel, *runs):

@@ -219,13 +219,14 @@ def test_chunk_group_run_exhausting_the_arena_is_undone():
     assert_same_chunks(g, o, "after arena NOMEM")
 
 
-def test_chunk_group_run_stopped_midway_restores_every_chunk():
+@pytest.mark.parametrize("targets", [(10, 11), (10, 11, 12)])
+def test_chunk_group_run_stopped_midway_restores_every_chunk(targets):
     """Regression: a chunk-group run that runs out of arena (as a sweep and
-    in place) is rolled back over all four chunks of every group, so the
-    call fails with the state exactly at the gate before the run.  Two dense
-    chunks (0 and 8 of sixteen, in the first and third group), then Rx on
-    two chunk-index qubits makes their groups dense: more than either arena
-    holds."""
+    in place) is rolled back over all chunks of every group (four with two
+    target qubits, eight with three), so the call fails with the state
+    exactly at the gate before the run.  Two dense chunks (0 and 8 of
+    sixteen, in different groups), then Rx on the chunk-index qubits makes
+    their groups dense: more than either arena holds."""
     import ctypes
     import math
     import numpy as np
@@ -234,7 +235,7 @@ def test_chunk_group_run_stopped_midway_restores_every_chunk():
     rot = [cc.u1(q, np.array([[math.cos(0.3 * q + 0.1), -math.sin(0.3 * q + 0.1)],
                               [math.sin(0.3 * q + 0.1), math.cos(0.3 * q + 0.1)]])) for q in range(10)]
     before = cc.concat([cc.h(13)] + rot + [cc.t(q) for q in range(10)])
-    run = cc.concat([cc.rx(10, 0.7), cc.rx(11, 1.1)])
+    run = cc.concat([cc.rx(q, 0.7 + 0.4 * i) for i, q in enumerate(targets)])
     o = oq.Sim(n, bl, oq.MODE_LOSSLESS)
     o.apply(before)
     live = o.footprint()["compressed_bytes"]
@@ -246,7 +247,7 @@ def test_chunk_group_run_stopped_midway_restores_every_chunk():
     g = qcz.State(n, bl, mode=qcz.MODE_LOSSLESS, pool_bytes=pool, batch=64, flags=flags)
     assert g.apply(before) == len(before)
     assert_same_chunks(g, o, "before the run")
-    say("group run stopped midway: live %d arena %d" % (live, arena))
+    say("group run on %s stopped midway: live %d arena %d" % (targets, live, arena))
     rc, applied = g.try_apply(run)
     assert rc == -2 and applied == 0
     assert g.stats()["stops"] >= 1
@@ -260,20 +261,27 @@ def subnormal_runs(n):
     phase of magnitude 2^-1020 on an in-chunk qubit (every chunk, and with a
     control on a chunk-index qubit only half of them), then its inverse; a
     chunk-pair gate whose first row is scaled by 2^-1020, then a Hadamard on
-    the same chunk-index qubit that mixes the small values with normal ones.
+    the same chunk-index qubit that mixes the small values with normal ones
+    (in runs on two chunk-index qubits, then on three).
     Gate by gate, a chunk holding a subnormal value is stored lossless, so a
     run must decide per gate whether to truncate."""
     import numpy as np
     tiny, huge = 2.0 ** -1020, 2.0 ** 1020
     hi = list(range(10, n))
     shrink = np.array([[tiny, tiny], [1.0, -1.0]]) / np.sqrt(2)
-    layer = cc.concat([cc.rz(0, 0.3), cc.diag1(4, 1.0, tiny), cc.rz(1, 0.5), cc.rx(2, 0.2), cc.rx(5, 0.4),
-                       cc.diag1(4, 1.0, huge), cc.rz(3, 0.1), cc.rx(6, 0.3),
-                       cc.diag1(3, 1.0, tiny, controls=(hi[1],)), cc.rx(7, 0.6), cc.diag1(3, 1.0, huge, controls=(hi[1],)),
-                       cc.h(hi[0]), cc.h(hi[1]), cc.u1(hi[0], shrink), cc.rx(hi[1], 0.3), cc.h(hi[0]), cc.h(hi[1]),
-                       cc.u1(hi[1], shrink, controls=(2,)), cc.h(hi[1]), cc.rx(hi[0], 0.5)])
-    return cc.concat([cc.grover_prefix(n), cc.random_unitary_gates(n, 8, 71), layer, cc.random_unitary_gates(n, 8, 72),
-                      layer])
+
+    def layer(third):
+        # the chunk-pair segment targets two chunk-index qubits, or three
+        extra = [cc.rx(hi[2], 0.2)] if third else []
+        return cc.concat([cc.rz(0, 0.3), cc.diag1(4, 1.0, tiny), cc.rz(1, 0.5), cc.rx(2, 0.2), cc.rx(5, 0.4),
+                          cc.diag1(4, 1.0, huge), cc.rz(3, 0.1), cc.rx(6, 0.3),
+                          cc.diag1(3, 1.0, tiny, controls=(hi[1],)), cc.rx(7, 0.6),
+                          cc.diag1(3, 1.0, huge, controls=(hi[1],)),
+                          cc.h(hi[0]), cc.h(hi[1]), cc.u1(hi[0], shrink), cc.rx(hi[1], 0.3)] + extra +
+                         [cc.h(hi[0]), cc.h(hi[1]), cc.u1(hi[1], shrink, controls=(2,)), cc.h(hi[1]),
+                          cc.rx(hi[0], 0.5)])
+    return cc.concat([cc.grover_prefix(n), cc.random_unitary_gates(n, 8, 71), layer(False),
+                      cc.random_unitary_gates(n, 8, 72), layer(True)])
 
 
 @pytest.mark.parametrize("level", [1, 3])
