@@ -131,6 +131,36 @@ __device__ __forceinline__ void stage_units(uint32_t *dst, const uint32_t *src, 
     }
 }
 
+// Two streams at once (each as in stage_units, `on` selecting which are
+// copied): the loads of both are in flight together, one HBM round trip for
+// streams of up to 4 G units.
+template <int G>
+__device__ __forceinline__ void stage_units2(uint32_t *dst0, const uint32_t *src0, uint32_t words0, bool on0,
+                                             uint32_t *dst1, const uint32_t *src1, uint32_t words1, bool on1, int lt)
+{
+    const uint32_t units0 = on0 ? (words0 + 3u) >> 2 : 0u, units1 = on1 ? (words1 + 3u) >> 2 : 0u;
+    const uint32_t units = units0 > units1 ? units0 : units1;
+    const u32x4 *a4 = reinterpret_cast<const u32x4 *>(src0);
+    const u32x4 *b4 = reinterpret_cast<const u32x4 *>(src1);
+    u32x4 *c4 = reinterpret_cast<u32x4 *>(dst0);
+    u32x4 *d4 = reinterpret_cast<u32x4 *>(dst1);
+    for (uint32_t base = (uint32_t)lt; base < units; base += 4u * G) {
+        u32x4 v[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t w = base + (uint32_t)u * G;
+            v[u] = (w < units0) ? __builtin_nontemporal_load(a4 + w) : u32x4{0u, 0u, 0u, 0u};
+            y[u] = (w < units1) ? __builtin_nontemporal_load(b4 + w) : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t w = base + (uint32_t)u * G;
+            if (w < units0) c4[w] = v[u];
+            if (w < units1) d4[w] = y[u];
+        }
+    }
+}
+
 // Workgroup barrier that orders LDS only: pending global stores and loads
 // are not waited for (no thread of the workgroup reads them back).
 __device__ __forceinline__ void lds_barrier()
@@ -2308,6 +2338,10 @@ __global__ __launch_bounds__((1 << (NB - 1)) * kCMax / V, NB == 2 ? 2 : 1) void 
         for (int k = 0; k < 4; ++k) sh_acc[4 * s + k] = 0;
     int ntr = 0;   // truncation steps so far (alternating flag sets)
     lds_barrier();   // (the run's matrices and records)
+    // the table entries of my two chunks of the next group, read while the
+    // current group is decoded (no other workgroup writes them in this launch)
+    uint64_t next_entry[2] = {0, 0};
+    bool have_next = false;
 
     for (uint64_t job = job_begin(gd) + blockIdx.x; job < job_stop(gd); job += gridDim.x) {
         // the group's chunks and which of them some gate of the run touches
@@ -2335,22 +2369,43 @@ __global__ __launch_bounds__((1 << (NB - 1)) * kCMax / V, NB == 2 ? 2 : 1) void 
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int gi = NS * r + s;
-                const uint64_t e = P.table[cg[gi]];
+                const uint64_t e = (have_next && !careful) ? next_entry[r] : P.table[cg[gi]];
                 old_entry[r] = e;
                 ok_src_r[r] = entry_ok(e, P.arena_words);
+            }
+            {
+                // both streams' loads in flight together (16-byte aligned ones)
+                const uint64_t e0 = old_entry[0], e1 = old_entry[1];
+                const bool on0 = tg[s] && ok_src_r[0], on1 = tg[NS + s] && ok_src_r[1];
+                const uint32_t w0 = ((uint32_t)(e0 & 0xFFFFull) + 3u) >> 2, w1 = ((uint32_t)(e1 & 0xFFFFull) + 3u) >> 2;
+                const uint64_t off0 = e0 >> 16, off1 = e1 >> 16;
+                if (((off0 | off1) & 3ull) == 0) {
+                    stage_units2<G>(buf[s], P.arena + off0, w0, on0, buf[NS + s], P.arena + off1, w1, on1, lt);
+                } else {
+                    if (on0) stage_words<G>(buf[s], P.arena + off0, w0, lt);
+                    if (on1) stage_words<G>(buf[NS + s], P.arena + off1, w1, lt);
+                }
             }
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int gi = NS * r + s;
-                const uint64_t e = old_entry[r];
-                const uint32_t words = ((uint32_t)(e & 0xFFFFull) + 3u) >> 2;
-                const uint64_t off = e >> 16;
-                if (tg[gi] && ok_src_r[r]) {
-                    if ((off & 3ull) == 0) stage_units<G>(buf[gi], P.arena + off, words, lt);
-                    else stage_words<G>(buf[gi], P.arena + off, words, lt);
-                }
                 if ((tg[gi] || gd.sweep) && !ok_src_r[r] && lt == 0) atomicExch(&ds->corrupt, 1);
                 if (lt == 0) sh_src_ok[gi] = ok_src_r[r] ? 1 : 0;
+            }
+            if (!careful) {
+                // the next group's entries (their loads complete during the decode)
+                const uint64_t nj = job + gridDim.x;
+                have_next = nj < job_stop(gd);
+                if (have_next) {
+                    const uint64_t nbase = deposit(gd, nj);
+#pragma unroll
+                    for (int r = 0; r < 2; ++r) {
+                        const int gi = NS * r + s;
+                        const uint64_t c = nbase | ((gi & 1) ? gd.pair_bit : 0ull) | ((gi & 2) ? gd.pair_bit2 : 0ull) |
+                                           ((gi & 4) ? gd.pair_bit3 : 0ull);
+                        next_entry[r] = P.table[c];
+                    }
+                }
             }
             lds_barrier();
 #pragma unroll
