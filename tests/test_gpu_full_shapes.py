@@ -14,7 +14,9 @@ GPU's exported input chunks and must produce the GPU's output bytes:
 * Gate-layer fusion and the entropy stage at 24 qubits: bytes equal to the
   plain run, and to the oracle on sampled jobs.
 * QAOA-34 (256 GiB uncompressed, bound 1e-5, fused runs and sweeps), when the
-  GPU has the memory: sampled jobs of every 10th gate.
+  GPU has the memory: sampled jobs of every 10th gate; and with chunk-group
+  runs (the benchmark's path), sampled groups of eight chunks of three runs
+  against the oracle applying the runs' gates one by one.
 """
 import math
 
@@ -253,6 +255,65 @@ def test_qaoa34_sampled_gates():
     say("qaoa34: compressed %.2f GB, ratio %.3f, F_lb %.6f, sweeps %d" % (
         fp["compressed_bytes"] / 1e9, fp["ratio"], fp["fidelity_lower_bound"], g.stats()["sweep_gates"]))
     assert checked >= 3 * (len(gates) // 10) - 5
+    assert fp["fidelity_lower_bound"] >= 0.99
+    g.close()
+    torch.cuda.empty_cache()
+
+
+def test_qaoa34_chunk_group_runs_sampled():
+    """The benchmark's path at full shape: QAOA-34 with fused runs and
+    chunk-group runs.  For three of the first layer's runs of chunk-index
+    mixers on three qubits (one pass over groups of eight chunks), the oracle
+    applies the run's gates one by one, pair job by pair job, to the exported
+    input chunks of sampled groups and must produce the GPU's output bytes."""
+    import torch
+    from paper_1911_04034_amd import qcz
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < (250 << 30) + (8 << 30):
+        pytest.skip("needs about 258 GiB of free device memory (found %.1f GiB)" % (free / 2 ** 30))
+    n, bl, level = 34, 20, 1
+    gates = cc.qaoa(n, 4, 3, 5)[0]
+    g = qcz.State(n, bl, mode=qcz.MODE_FIXED, level=level, pool_bytes=250 << 30, batch=128,
+                  flags=qcz.FLAG_FUSE | qcz.FLAG_RANGES | qcz.FLAG_GROUPS)
+    cb, C = g.cb, g.C
+    first_pair = n + 51 + 10                     # H layer, the layer's Rzz, the in-chunk mixers
+    assert all(int(gates[first_pair + i]["target"]) == cb + i for i in range(24))
+    assert g.apply(gates[:first_pair]) == first_pair
+    rng = np.random.default_rng(3434)
+    checked = 0
+    k = first_pair
+    for seg in range(8):
+        run = gates[k:k + 3]
+        bits = [1 << (int(r["target"]) - cb) for r in run]
+        groups = []
+        if seg in (0, 3, 7):
+            for c in rng.integers(0, g.nchunks, size=3):
+                base = int(c) & ~(bits[0] | bits[1] | bits[2])
+                members = [base | (bits[0] if j & 1 else 0) | (bits[1] if j & 2 else 0) | (bits[2] if j & 4 else 0)
+                           for j in range(8)]
+                groups.append((members, {m: g.export_chunk(m) for m in members}))
+        say("qaoa34 chunk-group run %d (targets %s), %d sampled groups" % (seg, [int(r["target"]) for r in run],
+                                                                           len(groups)))
+        assert g.apply(run) == 3
+        for members, cur in groups:
+            for gi in range(3):
+                gate = run[gi:gi + 1]
+                for m in members:
+                    if m & bits[gi]:
+                        continue
+                    r0, r1 = oq.gate_job(gate, cb, C, m, cur[m], level, m | bits[gi], cur[m | bits[gi]], level)
+                    cur[m], cur[m | bits[gi]] = r0, r1
+            for m in members:
+                assert g.export_chunk(m) == cur[m], (seg, m)
+            checked += 1
+        k += 3
+    assert checked == 9
+    assert g.stats()["kind_bytes"][2] > 0           # the mixers ran as chunk-group runs
+    assert g.apply(gates[k:]) == len(gates) - k
+    fp = g.footprint()
+    say("qaoa34 with chunk-group runs: compressed %.2f GB, F_lb %.6f" % (fp["compressed_bytes"] / 1e9,
+                                                                          fp["fidelity_lower_bound"]))
     assert fp["fidelity_lower_bound"] >= 0.99
     g.close()
     torch.cuda.empty_cache()
