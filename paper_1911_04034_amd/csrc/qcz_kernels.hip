@@ -1592,15 +1592,14 @@ __device__ __forceinline__ void apply_gate_registers(const D &gd, const double *
     }
 }
 
-// A diagonal gate without controls whose phase is the same for all of a
-// thread's amplitudes (its qubits above the thread's low index bits): in a
-// fused run such gates take a loop of their own (see the job kernel).
+// A diagonal gate without controls: in a fused run such gates take a loop of
+// their own (see the job kernel), one phase per thread when its qubits lie
+// above the thread's low index bits, else one per amplitude.
 template <int V>
 __device__ __forceinline__ bool thread_phase_diag(const RunRec &rg)
 {
-    constexpr int LB = RegSplit<V>::LB;
     return (V & 1) == 0 && V >= 2 && rg.job_type == J_SINGLE && (rg.kind == K_DIAG1 || rg.kind == K_DIAG2) &&
-           rg.cm == 0 && rg.q >= LB && (rg.kind == K_DIAG1 || rg.q2 >= LB);
+           rg.cm == 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1653,7 +1652,7 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
 
     const int tid = threadIdx.x, s = tid / G, lt = tid % G;
     if (GATE && tid < 8) sh_m[tid] = gd.m[tid];   // first read after the first job's fetch barrier
-    uint64_t fastm = 0;   // fused run: bit g set when gate g has one phase per thread (thread_phase_diag)
+    uint64_t fastm = 0;   // fused run: bit g set when gate g is an uncontrolled diagonal gate (thread_phase_diag)
     if (LIST == 3) {
         for (int i = tid; i < 8 * io.nrun; i += WGS) sh_rm[i >> 3][i & 7] = io.run[i >> 3].m[i & 7];
         for (int g = tid; g < io.nrun; g += WGS) sh_rr[g] = run_rec(io.run[g]);
@@ -1802,10 +1801,10 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                     const bool use_w = uni32((uint32_t)(s ? use1 : use0)) != 0;
                     for (int g = 0; g < io.nrun;) {
                         if (!careful && glevel > 0 && ((fastm >> g) & 1ull) != 0) {
-                            // consecutive diagonal gates with one phase per thread: the
-                            // ones that touch my chunk, each with the update, the
-                            // subnormal test and the truncation in one pass over my
-                            // values (a loop of their own, without per-gate branches)
+                            // consecutive uncontrolled diagonal gates: the ones that
+                            // touch my chunk, each with the update, the subnormal test
+                            // and the truncation in one pass over my values (a loop of
+                            // their own, without branches on the gate kind)
                             const uint64_t rest = ~(fastm >> g);
                             const int e = rest != 0 ? g + __builtin_ctzll(rest) : 64;   // end of the segment
                             const uint64_t seg = e - g >= 64 ? ~0ull : ((1ull << (e - g)) - 1ull);
@@ -1815,18 +1814,37 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                                 const int k = g + __builtin_ctzll(todo);
                                 todo &= todo - 1ull;
                                 const RunRec rk = uniform_rec(sh_rr[k]);
+                                // phase index bits from my high index bits (the low ones of
+                                // base are 0), then per amplitude those of a low qubit
                                 uint32_t ihi = (uint32_t)(base >> rk.q) & 1u;
                                 if (rk.kind == K_DIAG2) ihi |= ((uint32_t)(base >> rk.q2) & 1u) << 1;
-                                double pr, pi;
-                                phase_of(sh_rm[k], (int)ihi, pr, pi);
+                                constexpr int LB = RegSplit<V>::LB;
+                                const int ql = rk.q < LB ? rk.q : LB;
+                                const int q2l = (rk.kind == K_DIAG2 && rk.q2 < LB) ? rk.q2 : LB;
+                                if (ql == LB && q2l == LB) {
+                                    double pr, pi;
+                                    phase_of(sh_rm[k], (int)ihi, pr, pi);
 #pragma unroll
-                                for (int a = 0; a < V / 2; ++a) {
-                                    double yr, yi;
-                                    dmul(pr, pi, x[2 * a], x[2 * a + 1], yr, yi);
-                                    seen |= is_subnormal(yr);
-                                    seen |= is_subnormal(yi);
-                                    x[2 * a] = u2d(d2u(yr) & m64);
-                                    x[2 * a + 1] = u2d(d2u(yi) & m64);
+                                    for (int a = 0; a < V / 2; ++a) {
+                                        double yr, yi;
+                                        dmul(pr, pi, x[2 * a], x[2 * a + 1], yr, yi);
+                                        seen |= is_subnormal(yr);
+                                        seen |= is_subnormal(yi);
+                                        x[2 * a] = u2d(d2u(yr) & m64);
+                                        x[2 * a + 1] = u2d(d2u(yi) & m64);
+                                    }
+                                } else {
+#pragma unroll
+                                    for (int a = 0; a < V / 2; ++a) {
+                                        const uint32_t idx = ihi | (((uint32_t)a >> ql) & 1u) | ((((uint32_t)a >> q2l) & 1u) << 1);
+                                        double pr, pi, yr, yi;
+                                        phase_of(sh_rm[k], (int)idx, pr, pi);
+                                        dmul(pr, pi, x[2 * a], x[2 * a + 1], yr, yi);
+                                        seen |= is_subnormal(yr);
+                                        seen |= is_subnormal(yi);
+                                        x[2 * a] = u2d(d2u(yr) & m64);
+                                        x[2 * a + 1] = u2d(d2u(yi) & m64);
+                                    }
                                 }
                             }
                             g = e;
