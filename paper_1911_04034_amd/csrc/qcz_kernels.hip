@@ -1602,6 +1602,54 @@ __device__ __forceinline__ bool thread_phase_diag(const RunRec &rg)
            rg.cm == 0;
 }
 
+// An uncontrolled U1 / X on an in-chunk qubit whose pairs span threads: in a
+// fused run consecutive such gates are applied in LDS one after another
+// (see the job kernel).
+template <int V>
+__device__ __forceinline__ bool lds_pair_gate(const RunRec &rg)
+{
+    return rg.job_type == J_SINGLE && (rg.kind == K_U1 || rg.kind == K_X) && rg.cm == 0 && !gate_in_registers<V>(rg);
+}
+
+// One such gate on the slots' chunks in LDS (apply_gate's pair update), each
+// value tested for a subnormal result and truncated as it is written; a slot
+// whose chunk the gate does not touch (t0 / t1 false) is left alone.
+__device__ __forceinline__ void lds_pairs_truncated(const RunRec &rg, const double *m, double *v0, double *v1, bool t0,
+                                                    bool t1, int cb, int nthreads, uint64_t m64, bool &seen)
+{
+    const int tid = threadIdx.x;
+    const int units = (1 << cb) / 2;
+    const int q = rg.q;
+    const double u0r = m[0], u0i = m[1], u1r = m[2], u1i = m[3], u2r = m[4], u2i = m[5], u3r = m[6], u3i = m[7];
+    for (int s = 0; s < 2; ++s) {
+        if (!(s ? t1 : t0)) continue;
+        double *v = s ? v1 : v0;
+        for (int u = tid; u < units; u += nthreads) {
+            const int k0 = ((u >> q) << (q + 1)) | (u & ((1 << q) - 1));
+            const int k1 = k0 | (1 << q);
+            const int p0 = vpos(2 * k0), p1 = vpos(2 * k1);
+            double ar = v[p0], ai = v[p0 + 1], br = v[p1], bi = v[p1 + 1];
+            if (rg.kind == K_X) {
+                const double tr = ar, ti = ai;
+                ar = br; ai = bi; br = tr; bi = ti;
+            } else {
+                double yr, yi, zr, zi;
+                lin2(u0r, u0i, u1r, u1i, ar, ai, br, bi, yr, yi);
+                lin2(u2r, u2i, u3r, u3i, ar, ai, br, bi, zr, zi);
+                ar = yr; ai = yi; br = zr; bi = zi;
+            }
+            seen |= is_subnormal(ar);
+            seen |= is_subnormal(ai);
+            seen |= is_subnormal(br);
+            seen |= is_subnormal(bi);
+            v[p0] = u2d(d2u(ar) & m64);
+            v[p0 + 1] = u2d(d2u(ai) & m64);
+            v[p1] = u2d(d2u(br) & m64);
+            v[p1 + 1] = u2d(d2u(bi) & m64);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // the job kernel
 // ---------------------------------------------------------------------------
@@ -1653,12 +1701,14 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
     const int tid = threadIdx.x, s = tid / G, lt = tid % G;
     if (GATE && tid < 8) sh_m[tid] = gd.m[tid];   // first read after the first job's fetch barrier
     uint64_t fastm = 0;   // fused run: bit g set when gate g is an uncontrolled diagonal gate (thread_phase_diag)
+    uint64_t ldsm = 0;    // fused run: bit g set when gate g is an LDS pair gate (lds_pair_gate)
     if (LIST == 3) {
         for (int i = tid; i < 8 * io.nrun; i += WGS) sh_rm[i >> 3][i & 7] = io.run[i >> 3].m[i & 7];
         for (int g = tid; g < io.nrun; g += WGS) sh_rr[g] = run_rec(io.run[g]);
         lds_barrier();   // the records are read before the first job's fetch barrier
         const int ln = tid & 63;
         fastm = __ballot(ln < io.nrun && thread_phase_diag<V>(sh_rr[ln < io.nrun ? ln : 0]));
+        ldsm = __ballot(ln < io.nrun && lds_pair_gate<V>(sh_rr[ln < io.nrun ? ln : 0]));
     }
     uint32_t unit_mask = 0;                        // phases equal to 1 (diagonal gates)
     if (GATE)
@@ -1848,6 +1898,28 @@ __global__ __launch_bounds__(128 * WPG, WPG == 2 ? 3 : 1) void job_kernel(GateDe
                                 }
                             }
                             g = e;
+                            continue;
+                        }
+                        if (!careful && glevel > 0 && ((ldsm >> g) & 1ull) != 0 && ((ldsm >> g) & 2ull) != 0) {
+                            // two or more consecutive LDS pair gates: my values go to LDS
+                            // once, each gate updates, tests and truncates the pairs of
+                            // the chunks it touches, and they come back at the end
+                            const uint64_t rest = ~(ldsm >> g);
+                            const int e = rest != 0 ? g + __builtin_ctzll(rest) : 64;   // end of the segment
+                            const uint64_t m64 = (uint64_t)mh << 32;
+#pragma unroll
+                            for (int k = 0; k < V; ++k) vals[vpos(first + k)] = x[k];
+                            for (; g < e; ++g) {
+                                lds_barrier();
+                                const RunRec rj = uniform_rec(sh_rr[g]);
+                                lds_pairs_truncated(rj, sh_rm[g], reinterpret_cast<double *>(buf[0]),
+                                                    reinterpret_cast<double *>(buf[1]),
+                                                    use0 && ((tm0 >> g) & 1ull) != 0, use1 && ((tm1 >> g) & 1ull) != 0,
+                                                    P.cb, WGS, m64, seen);
+                            }
+                            lds_barrier();
+#pragma unroll
+                            for (int k = 0; k < V; ++k) x[k] = vals[vpos(first + k)];
                             continue;
                         }
                         const RunRec rg = uniform_rec(sh_rr[g]);

@@ -274,7 +274,7 @@ def subnormal_runs(n):
         # the chunk-pair segment targets two chunk-index qubits, or three
         extra = [cc.rx(hi[2], 0.2)] if third else []
         return cc.concat([cc.rz(0, 0.3), cc.diag1(4, 1.0, tiny), cc.rz(1, 0.5), cc.rx(2, 0.2), cc.rx(5, 0.4),
-                          cc.diag1(4, 1.0, huge), cc.rz(3, 0.1), cc.rx(6, 0.3),
+                          cc.rx(8, 0.25), cc.diag1(4, 1.0, huge), cc.rz(3, 0.1), cc.rx(6, 0.3),
                           cc.diag1(3, 1.0, tiny, controls=(hi[1],)), cc.rx(7, 0.6),
                           cc.diag1(3, 1.0, huge, controls=(hi[1],)),
                           cc.h(hi[0]), cc.h(hi[1]), cc.u1(hi[0], shrink), cc.rx(hi[1], 0.3)] + extra +
