@@ -541,6 +541,26 @@ size_t gates_that_fit(const qcz_state *s, const std::vector<GateDesc> &descs)
     return k;
 }
 
+// Leading gates of `descs` up to and including the first fused or chunk-group
+// run.  A run re-encodes every chunk, and the arena estimates of a batch rest
+// on the mean stream size before it: a run that turns a near-constant state
+// dense (the first layer after Hadamards) would leave the next launch's
+// estimate far too low, its appends would stop on a full arena, and the
+// rollback, compaction and relaunch would cost more than a pass.  So a run
+// ends its batch, and the next batch is planned from the sizes it left.
+size_t through_first_run(const qcz_state *s, const std::vector<GateDesc> &descs)
+{
+    size_t k = 0;
+    while (k < descs.size()) {
+        GateDesc launch;
+        int kind = 0;
+        const size_t r = run_at(s, descs.data(), descs.size(), k, launch, kind);
+        if (kind != 0) return k + r;
+        k += 1;
+    }
+    return k;
+}
+
 qcz_status launch_batch(qcz_state *s, const std::vector<GateDesc> &descs)
 {
     const bool timing = (s->cfg.flags & QCZ_FLAG_TIMING) != 0 || s->tuning;
@@ -1346,6 +1366,8 @@ qcz_status qcz_apply_gates(qcz_state *s, const qcz_gate *gates, size_t n_gates, 
         }
         descs.clear();
         for (size_t k = 0; k < B; ++k) descs.push_back(lower_gate(s, gates[idx + k], (int)k));
+        B = through_first_run(s, descs);
+        descs.resize(B);
         // A gate that does not fit beside the live streams sweeps into the
         // other arena when the state fits there (with the in-chunk gates
         // fused after it, under QCZ_FLAG_FUSE); a sweep the device stopped
