@@ -200,6 +200,36 @@ def test_chunk_group_runs_qaoa_and_grover_sweeps():
         assert g.stats()["sweep_gates"] > 0
 
 
+def test_run_that_densifies_the_state_ends_its_batch():
+    """Regression: after the Hadamard layer the QAOA state is near-constant,
+    and the first layer's run makes it dense.  The chunk-group pass behind it
+    in the same call is planned from the sizes the run left, so it sweeps into
+    the other arena instead of stopping on a full one (no stop, no
+    compaction); bytes equal the oracle's."""
+    import ctypes
+    from paper_1911_04034_amd import qcz
+    n, bl, level = 16, 10, 1
+    gates, edges = cc.qaoa(n, 1, 3, 23)
+    hadamards = gates[:n]
+    layer = gates[n:n + len(edges) + 13]   # Rzz on every edge, Rx on qubits 0 .. 12
+    o = oq.Sim(n, bl, oq.MODE_FIXED, level)
+    o.apply(hadamards)
+    o.apply(layer[:len(edges) + 10])
+    dense = o.footprint()["compressed_bytes"]
+    cfg = qcz.Config(n, bl, 0, 0, 0, qcz.FLAG_FUSE | qcz.FLAG_GROUPS, 0, 0, 0)
+    pmin = qcz.load().qcz_pool_bytes_min(ctypes.byref(cfg))
+    arena = int(1.25 * dense) + (32 << 10)
+    pool = pmin + 2 * (arena - (64 << 10) - 64 * (1 << (n - 10)))
+    g, o = make(n, bl, oq.MODE_FIXED, level, batch=96, pool_bytes=pool, flags=qcz.FLAG_FUSE | qcz.FLAG_GROUPS)
+    say("densifying run: dense %d arena %d" % (dense, arena))
+    assert g.apply(hadamards) == n and o.apply(hadamards) == n
+    assert g.apply(layer) == len(layer) and o.apply(layer) == len(layer)
+    assert_same_chunks(g, o, "after the first layer")
+    st = g.stats()
+    assert st["stops"] == 0 and g.footprint()["compactions"] == 0
+    assert st["sweep_gates"] >= 3 and st["kind_bytes"][2] > 0
+
+
 def test_chunk_group_run_exhausting_the_arena_is_undone():
     """A chunk-group run that overflows the arena stops and is undone over all
     four chunks of every group; the call fails with NOMEM and the state is the
