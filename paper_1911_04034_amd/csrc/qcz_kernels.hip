@@ -979,6 +979,34 @@ __device__ __noinline__ void ent_plan(EncPlan<V> &e, int C, int lt, uint32_t *b,
 // the value before mine; x0/x1: values 0 and 1 of the chunk.  `sub` is the
 // group's subnormal flag.  Contains barriers: every thread calls it; the plan
 // of a group with no chunk (stale values) is computed and ignored.
+// The per-value part of the plan: truncated words, CONST2 test bits, codes,
+// nonzero positions and the last nonzero high word.  LOSSLESS is a template
+// argument so that the lossy instance (low words all zero, as are the CONST2
+// references' low words) spends no instructions on low words.
+template <int V, bool LOSSLESS>
+__device__ __forceinline__ void plan_values(const uint32_t (&xh)[V], const uint32_t (&xl)[V], uint32_t mh,
+                                            uint32_t prev, int first, uint32_t re_h, uint32_t re_l, uint32_t im_h,
+                                            uint32_t im_l, EncPlan<V> &e, uint32_t &badbits, uint32_t &codes,
+                                            uint32_t &nzm, uint32_t &lv)
+{
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const uint32_t h = xh[k] & mh;
+        const uint32_t l = LOSSLESS ? xl[k] : 0u;
+        e.th[k] = h;
+        e.tl[k] = l;
+        const bool odd = ((first + k) & 1) != 0;
+        const uint32_t dh = h ^ (odd ? im_h : re_h);   // differs from value 0 / 1
+        badbits |= LOSSLESS ? (dh | (l ^ (odd ? im_l : re_l))) : dh;
+        const uint32_t L = lead_bytes(h, prev);
+        codes |= L << (2 * k);
+        prev = h;
+        const bool nz = (LOSSLESS ? (h | l) : h) != 0;
+        nzm |= nz ? (1u << k) : 0u;
+        lv = nz ? h : lv;
+    }
+}
+
 template <int V, int WPG, bool ENT = false>
 __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], uint32_t xprev_hi, uint64_t x0,
                             uint64_t x1, int lev_req, bool sub, int C, int lt, uint32_t *slotB,
@@ -1004,21 +1032,10 @@ __device__ void encode_plan(const uint32_t (&xh)[V], const uint32_t (&xl)[V], ui
     const uint32_t half_h = first >= C / 2 ? e.c1h : e.c0h, half_l = first >= C / 2 ? e.c1l : e.c0l;
     const uint32_t re_h = rsh ? half_h : e.c0h, re_l = rsh ? half_l : e.c0l;
     const uint32_t im_h = rsh ? half_h : e.c1h, im_l = rsh ? half_l : e.c1l;
-#pragma unroll
-    for (int k = 0; k < V; ++k) {
-        const uint32_t h = xh[k] & mh;
-        const uint32_t l = lossless ? xl[k] : 0u;
-        e.th[k] = h;
-        e.tl[k] = l;
-        const bool odd = ((first + k) & 1) != 0;
-        badbits |= (h ^ (odd ? im_h : re_h)) | (l ^ (odd ? im_l : re_l));   // differs from value 0 / 1
-        const uint32_t L = lead_bytes(h, prev);
-        codes |= L << (2 * k);
-        prev = h;
-        const bool nz = (h | l) != 0;
-        nzm |= nz ? (1u << k) : 0u;
-        lv = nz ? h : lv;
-    }
+    if (lossless)
+        plan_values<V, true>(xh, xl, mh, prev, first, re_h, re_l, im_h, im_l, e, badbits, codes, nzm, lv);
+    else
+        plan_values<V, false>(xh, xl, mh, prev, first, re_h, re_l, im_h, im_l, e, badbits, codes, nzm, lv);
     const uint32_t cnt = __popc(nzm);
     lf = nzm ? 1u : 0u;
     const uint32_t bad = badbits ? 1u : 0u;
